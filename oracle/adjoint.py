@@ -1,0 +1,170 @@
+"""Active-set identification, polish and implicit-differentiation VJP
+(Algorithm 2; Sec. "Backward Pass"; Appendix "Backward Pass: Sensitivities
+Computation").
+
+For the QP  min 1/2 x'Px + q'x  s.t.  Cx = c, lo <= Gx <= hi  at a solution
+(x, y_f, y_g) with active rows A (lower L, upper U), the active-set KKT map is
+
+    F(w, theta) = [ H x + q + C'y_f + G_A'y_A ;  C x - c ;  G_A x - b_A ]
+
+with b_A = lo on L rows and hi on U rows.  The VJP of a loss with gradient
+dL/dx solves  K eta = (dL/dx, 0, 0),  K = [[H, C', G_A'], [C, 0, 0], [G_A, 0, 0]]
+(eq. bwd:noslack_kkt_matrix; K is symmetric so its transpose is itself) and
+returns  dL/dtheta = -(dF/dtheta)' eta  (eq. loss_gradient):
+
+    dL/dq      = -eta_x
+    dL/dc      = +eta_f          (so dL/dx_init = eta_f on the initial rows)
+    dL/dD_t[i,i] = -eta_x[t,i] * x[t,i]
+    dL/dlo_i   = +eta_A,i on lower-active rows, 0 elsewhere
+    dL/dhi_i   = +eta_A,i on upper-active rows, 0 elsewhere
+
+Soft rows: an L1 row whose slack is nonzero has the fixed multiplier
+-gamma1 sign(xi) and drops out of the system; an L1 row with xi = 0 is treated
+as a hard row.  L2-slack rows (eq. bwd:slack_reduced_system) are not handled
+here and raise.
+
+Parity: the dense direct solve is the definition; pinned by central finite
+differences of polished solutions and by the closed-form LQR gradient
+(tests/test_oracle_adjoint.py).  The regularised refinement variant is pinned
+against the dense solve.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .qp import HARD, SOFT_L1, SOFT_L2, StageQP
+
+
+def active_set(qp: StageQP, x, y_g, xi=None, eps_g=None, eps_solve=1e-4):
+    """Lower/upper active masks by the rule of Appendix "Active constraints
+    identification": the dual sign decides; closeness to a bound only when the
+    dual is ambiguous (|y| < eps_g).  eps_g = 10 eps_solve max(1, ||y_g||_inf)
+    for the dual test; the proximity test uses eps_g max(1, |bound|).
+    Rows whose L1 slack is nonzero are returned in neither mask.
+    """
+    _, _, G, _, _, lo, hi = qp.matrices()
+    g = G @ x
+    y_g = np.asarray(y_g, float)
+    if eps_g is None:
+        eps_g = 10.0 * eps_solve * max(1.0, float(np.max(np.abs(y_g))) if y_g.size else 1.0)
+    amb = np.abs(y_g) < eps_g
+    lower = (y_g < -eps_g) | (amb & (g - lo <= eps_g * np.maximum(1.0, np.abs(lo))))
+    upper = (y_g > eps_g) | (amb & (hi - g <= eps_g * np.maximum(1.0, np.abs(hi))))
+    both = lower & upper
+    lower = lower & ~(both & (y_g > 0))
+    upper = upper & ~(both & ~(y_g > 0))
+    kind = qp.soft_rows()
+    if xi is not None:
+        drop = (kind == SOFT_L1) & (np.asarray(xi) != 0.0)
+        lower &= ~drop
+        upper &= ~drop
+    if np.any(kind == SOFT_L2):
+        raise NotImplementedError("L2-slack rows need the reduced slack adjoint system")
+    return lower, upper
+
+
+def _kkt(qp: StageQP, lower, upper, H=None):
+    P, C, G, q, c, lo, hi = qp.matrices()
+    H = P if H is None else H
+    act = lower | upper
+    GA = G[np.flatnonzero(act)]
+    K = sp.bmat([[H, C.T, GA.T], [C, None, None], [GA, None, None]], format="csc")
+    bA = np.where(lower, lo, hi)[act]
+    return K, P, C, G, q, c, GA, bA, act
+
+
+def polish(qp: StageQP, x, y_g, xi=None, eps_solve=1e-4, tol=1e-9):
+    """Solve the equality-constrained KKT system on the identified active set
+    and certify it: primal feasibility, dual signs and (by construction)
+    complementarity.  Returns (ok, sol) with sol = dict(x, y_f, y_g, z_g, xi).
+    Soft L1 rows with nonzero slack keep the multiplier -gamma1 sign(xi).
+    """
+    lower, upper = active_set(qp, x, y_g, xi=xi, eps_solve=eps_solve)
+    K, P, C, G, q, c, GA, bA, act = _kkt(qp, lower, upper)
+    nv, ne = qp.nvar, qp.neq
+    kind = qp.soft_rows()
+    fixed = np.zeros(qp.nineq)
+    if xi is not None:
+        sel = (kind == SOFT_L1) & (np.asarray(xi) != 0.0)
+        fixed[sel] = -qp.gamma1 * np.sign(np.asarray(xi)[sel])
+    rhs = np.concatenate([-q - G.T @ fixed, c, bA])
+    sol = spla.spsolve(K, rhs)
+    xs = sol[:nv]
+    yf = sol[nv:nv + ne]
+    yg = fixed.copy()
+    yg[act] = sol[nv + ne:]
+    g = G @ xs
+    lo, hi = qp.lo.reshape(-1), qp.hi.reshape(-1)
+    xis = np.zeros(qp.nineq)
+    if xi is not None:
+        sel = (kind == SOFT_L1) & (np.asarray(xi) != 0.0)
+        xis[sel] = np.clip(g[sel], lo[sel], hi[sel]) - g[sel]
+    gx = g + xis
+    feas = np.all(gx >= lo - tol * np.maximum(1, np.abs(lo))) and np.all(gx <= hi + tol * np.maximum(1, np.abs(hi)))
+    signs = np.all(yg[lower] <= tol) and np.all(yg[upper] >= -tol)
+    ok = bool(feas and signs and np.all(np.isfinite(sol)))
+    return ok, {"x": xs, "y_f": yf, "y_g": yg, "z_g": g, "xi": xis, "lower": lower, "upper": upper}
+
+
+def adjoint_dense(qp: StageQP, x, dL_dx, lower, upper, H=None):
+    """eta = K^{-1} (dL/dx, 0, 0) by a direct sparse LU (the definition)."""
+    K, *_ , act = _kkt(qp, lower, upper, H)
+    nv, ne = qp.nvar, qp.neq
+    rhs = np.concatenate([dL_dx, np.zeros(ne + int(act.sum()))])
+    eta = spla.spsolve(K, rhs)
+    eta_g = np.zeros(qp.nineq)
+    eta_g[act] = eta[nv + ne:]
+    return eta[:nv], eta[nv:nv + ne], eta_g
+
+
+def adjoint_refined(qp: StageQP, x, dL_dx, lower, upper, sigma_b=1e-9, rho_b=1e6, sweeps=4, H=None):
+    """Same eta by iterative refinement on K with the regularised matrix
+    K_reg = [[H + sigma_b I, J'], [J, -rho_b^{-1} I]], J = [C; G_A]:
+    e <- e + K_reg^{-1} (r - K e).  Each K_reg solve is one Schur step
+    (H + sigma_b I + rho_b J'J) e_x = r_x + rho_b J' r_y, e_y = rho_b (J e_x - r_y).
+    Written with dense NumPy algebra (the oracle's plain form of the GPU scheme).
+    """
+    P, C, G, q, c, lo, hi = qp.matrices()
+    H = P if H is None else H
+    act = lower | upper
+    J = sp.vstack([C, G[np.flatnonzero(act)]]).tocsr()
+    nv = qp.nvar
+    Hd = H.toarray()
+    Jd = J.toarray()
+    S = Hd + sigma_b * np.eye(nv) + rho_b * Jd.T @ Jd
+    Lc = np.linalg.cholesky(S)
+
+    def kreg_solve(rx, ry):
+        ex = np.linalg.solve(Lc.T, np.linalg.solve(Lc, rx + rho_b * Jd.T @ ry))
+        ey = rho_b * (Jd @ ex - ry)
+        return ex, ey
+
+    rx0 = np.asarray(dL_dx, float)
+    ry0 = np.zeros(Jd.shape[0])
+    ex, ey = kreg_solve(rx0, ry0)
+    for _ in range(sweeps - 1):
+        rx = rx0 - (Hd @ ex + Jd.T @ ey)
+        ry = ry0 - Jd @ ex
+        dx, dy = kreg_solve(rx, ry)
+        ex, ey = ex + dx, ey + dy
+    ne = qp.neq
+    eta_g = np.zeros(qp.nineq)
+    eta_g[act] = ey[ne:]
+    return ex, ey[:ne], eta_g
+
+
+def qp_vjp(qp: StageQP, x, eta_x, eta_f, eta_g, lower, upper):
+    """Map eta to gradients of the QP data (eq. loss_gradient)."""
+    n = qp.n
+    xs = np.asarray(x).reshape(qp.N + 1, n)
+    ex = np.asarray(eta_x).reshape(qp.N + 1, n)
+    return {
+        "d_q": -ex,
+        "d_c": np.asarray(eta_f).copy(),
+        "d_x_init": np.asarray(eta_f)[: qp.nx].copy(),
+        "d_Ddiag": -ex * xs,
+        "d_lo": np.where(lower, eta_g, 0.0).reshape(qp.N + 1, qp.ng),
+        "d_hi": np.where(upper, eta_g, 0.0).reshape(qp.N + 1, qp.ng),
+    }
