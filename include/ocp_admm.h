@@ -1,0 +1,203 @@
+/*
+ * ocp_admm.h -- C ABI of the batched SQP-ADMM optimal-control QP solver for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem class (Sec. "Contribution", box OCP; Appendix "Optimal Control
+ * Problem"): stages t = 0..N with states x_t (nx), controls u_t (nu),
+ *   min  sum_t l_t + slack penalty
+ *   s.t. x_0 = x_init,  f_t(x_t,u_t,x_{t+1},u_{t+1}) = 0,  g_lo <= g_t + xi_t <= g_hi.
+ * Each SQP step convexifies it into the stage-wise QP of Sec. "QP
+ * Approximation of OCP" / Appendix "QP Approximation":
+ *   min 1/2 x'Px + q'x + slack penalty   s.t.  Cx = c,  lo <= Gx + xi <= hi
+ * with P block-tridiagonal (D_t, E_t), C block-bidiagonal (A_init = [I 0],
+ * [A_t^- A_t^+]) and G block-diagonal (G_t).  The QP is solved by the ADMM
+ * scheme of Algorithm 3 with a block-tridiagonal Cholesky of the Schur
+ * matrix S = P + sigma I + C'rho_f C + G'rho_g G (Appendix "ADMM"), and
+ * differentiated by the active-set implicit VJP of Algorithm 2.
+ *
+ * Conventions
+ *  - Stage-concatenated batches: instance b owns stages stage_off[b] ..
+ *    stage_off[b+1]-1 (N_b + 1 of them); S = total stage count.  Horizons
+ *    may differ per instance (ragged batches).
+ *  - Every array argument is a DEVICE pointer owned by the caller, in
+ *    row-major order, FP64 unless stated otherwise.  Settings structs are
+ *    host memory.  The library owns only its workspace, allocated by
+ *    ocp_create and freed by ocp_destroy; ocp_set_* / ocp_solve /
+ *    ocp_adjoint allocate nothing.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *    asynchronous on that stream; one handle must not be used from two
+ *    streams at once.
+ *  - Errors are reported only through the return code (nothing aborts or
+ *    throws).  Numerical trouble of one instance is reported per instance in
+ *    ocp_solution.status, never as a call failure.
+ */
+#ifndef OCP_ADMM_H
+#define OCP_ADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ocp_handle_s* ocp_handle;
+
+typedef enum {
+  OCP_OK = 0,
+  OCP_E_ARG = 1,         /* null pointer / invalid value */
+  OCP_E_SHAPE = 2,       /* sizes inconsistent or not compiled in (see ocp_supported) */
+  OCP_E_HIP = 3,         /* a HIP runtime call failed */
+  OCP_E_NOMEM = 4,       /* workspace allocation failed */
+  OCP_E_ORDER = 5,       /* call order violated (e.g. solve before set, adjoint before solve) */
+  OCP_E_UNSUPPORTED = 6  /* feature not available for this model / row kind */
+} ocp_status;
+
+/* models */
+enum { OCP_MODEL_QP = 0, OCP_MODEL_LTI = 1, OCP_MODEL_BICYCLE = 2 };
+/* arithmetic of the ADMM iterations; the factorisation is always FP64 */
+enum { OCP_PREC_FP64 = 0, OCP_PREC_MIXED = 1 };
+/* inequality-row kinds: hard, L2-penalised slack (Sec. "Slack update"),
+ * L1-penalised slack */
+enum { OCP_ROW_HARD = 0, OCP_ROW_L2 = 1, OCP_ROW_L1 = 2 };
+/* per-instance status */
+enum { OCP_SOLVED = 0, OCP_MAX_ITER = 1, OCP_NON_FINITE = 2, OCP_FACTOR_BREAKDOWN = 3 };
+
+typedef struct {
+  int32_t batch;          /* B >= 1 */
+  int32_t nx, nu, ng;     /* state, control and inequality-row counts per stage */
+  int32_t model;          /* OCP_MODEL_* */
+  int32_t precision;      /* OCP_PREC_* */
+  int32_t time_invariant; /* OCP_MODEL_QP only: blocks given once per instance (see ocp_qp) */
+} ocp_dims;
+
+/* Solver settings (host struct).  Defaults (ocp_default_settings) are the
+ * paper's: sigma = 1e-6, rho_bar_0 = 0.1, rho_f = 1e3 rho_bar, rho_g = rho_bar,
+ * rho_bar in [1e-6, 1e6], adaptation every 25 iterations when the change
+ * exceeds 5x (Sec. "Solving QP via ADMM", step-size selection), Armijo
+ * eta = 0.4 (Appendix "Line search"), at most 1000 ADMM iterations. */
+typedef struct {
+  double sigma, rho0, rho_f_scale, rho_min, rho_max, k_ratio;
+  double alpha;            /* over-relaxation in (0,2); default 1.6 */
+  double eps_abs, eps_rel; /* ADMM stopping test, evaluated in FP64 */
+  double eps_c;            /* SQP stopping tolerance (eq. sqp_stop) */
+  double armijo_eta;
+  double eps_active;       /* active-set tolerance scale for the adjoint */
+  double adj_sigma, adj_rho; /* regularisation of the adjoint refinement */
+  int32_t max_admm;        /* ADMM iterations per QP */
+  int32_t k_rho;           /* rho adaptation interval (0 = never) */
+  int32_t k_check;         /* convergence test interval (0 = run exactly max_admm) */
+  int32_t adapt_rho;       /* 0/1 */
+  int32_t warm_start;      /* 1: start from the handle's current state and rho */
+  int32_t max_sqp;         /* SQP iterations (bicycle model) */
+  int32_t fixed_sqp;       /* 1: run exactly max_sqp iterations */
+  int32_t refine_sweeps;   /* adjoint iterative-refinement sweeps */
+} ocp_settings;
+
+/* Linear time-invariant model (OCP_MODEL_LTI): x_{t+1} = A x_t + B u_t,
+ * cost 1/2(x'Qx + u'Ru) for t < N and 1/2(x'Q_f x + u'Ru) at t = N, bounds
+ * lo <= G (x_t,u_t) <= hi at every stage.  Shapes:
+ * A [B,nx,nx], Bm [B,nx,nu], Qd [B,nx], Rd [B,nu], Qfd [B,nx] (diagonals),
+ * G [ng, nx+nu] (shared by all instances and stages), lo, hi [B,ng], x0 [B,nx]. */
+typedef struct {
+  const double *A, *Bm, *Qd, *Rd, *Qfd, *G, *lo, *hi, *x0;
+} ocp_lti;
+
+/* General stage-wise QP (OCP_MODEL_QP).  n = nx + nu.
+ * time_invariant = 0: D [S,n,n], E [S,n,n] (E_t = block (t+1,t); slot N of
+ *   each instance unused), q [S,n], Am, Ap [S,nx,n], b [S,nx] (slot N
+ *   unused), G [S,ng,n], lo, hi [S,ng].
+ * time_invariant = 1: D [2B,n,n] (interior, terminal), E [B,n,n],
+ *   Am, Ap [B,nx,n], b [B,nx], G [B,ng,n], lo, hi [B,ng]; q stays [S,n].
+ * E, q and b may be NULL (zero).  x_init [B,nx].  soft [ng] (uint8 row
+ * kinds, host or device not allowed: DEVICE pointer) may be NULL (all hard).
+ * gamma2: L2 slack weight (gamma/2 ||xi||^2); gamma1: L1 slack weight. */
+typedef struct {
+  const double *D, *E, *q, *Am, *Ap, *b, *G, *lo, *hi, *x_init;
+  const uint8_t* soft;
+  double gamma2, gamma1;
+} ocp_qp;
+
+/* Kinematic bicycle (OCP_MODEL_BICYCLE, nx = 4, nu = 2, ng = 3): state
+ * (px, py, yaw, v), control (a, delta); implicit-midpoint dynamics
+ * x_{t+1} = x_t + dt fc((x_t + x_{t+1})/2, u_t); tracking cost
+ * 1/2 (x_t - r_t)'Q(x_t - r_t) + 1/2 u_t'R u_t (Q_f at t = N); rows
+ * a in [-a_bound, a_bound], delta in [-steer_bound, steer_bound] (hard) and
+ * the lateral offset n_t'(p_t - p_ref,t) in [-lat_bound, lat_bound] (L1 slack,
+ * weight gamma1).  ref [S,4], normal [S,2], x0 [B,4] device; scalars host. */
+typedef struct {
+  const double *ref, *normal, *x0;
+  double dt, wheelbase, a_bound, steer_bound, lat_bound, gamma1;
+  double Qd[4], Rd[2], Qfd[4];
+} ocp_bicycle;
+
+/* Solution buffers (device, FP64, caller-owned).  Any pointer may be NULL
+ * to skip that output.  x [S,n]; xi, z_g, y_g [S,ng]; y_f [S,nx] where the
+ * slot of stage 0 holds the initial-state multipliers and the slot of stage
+ * t+1 the multipliers of dynamics row t; per instance [B]: status,
+ * admm_iters (last QP), sqp_iters, n_factor, r_prim, r_dual (FP64
+ * residuals of eq. admm:residuals), rho (final rho_bar); sqp_kkt [B,3] =
+ * (stationarity, equality, inequality) of eq. sqp_stop (bicycle only). */
+typedef struct {
+  double *x, *xi, *z_g, *y_f, *y_g;
+  int32_t *status, *admm_iters, *sqp_iters, *n_factor;
+  double *r_prim, *r_dual, *rho, *sqp_kkt;
+} ocp_solution;
+
+/* Gradients of a loss w.r.t. the QP data at the last solution (device, FP64,
+ * caller-owned, NULL to skip): d_q [S,n], d_Ddiag [S,n] (diagonal of D_t),
+ * d_x_init [B,nx], d_lo, d_hi [S,ng], eta_x [S,n], active [S,ng] (int8:
+ * -1 lower, +1 upper, 0 inactive). */
+typedef struct {
+  double *d_q, *d_Ddiag, *d_x_init, *d_lo, *d_hi, *eta_x;
+  int8_t* active;
+} ocp_qp_grads;
+
+/* Fill `s` with the defaults listed above.  Never fails. */
+void ocp_default_settings(ocp_settings* s);
+
+/* Static string for a status code. */
+const char* ocp_status_string(ocp_status st);
+
+/* 1 if kernels are compiled for (nx, nu, ng), else 0. */
+int32_t ocp_supported(int32_t nx, int32_t nu, int32_t ng);
+
+/* Workspace bytes ocp_create would allocate for these dims and horizons
+ * (horizons: HOST array of B horizons N_b >= 1). */
+ocp_status ocp_workspace_bytes(const ocp_dims* dims, const int32_t* horizons, size_t* bytes);
+
+/* Allocate a solver for `dims` and the B horizons (HOST array).  On success
+ * *out receives the handle.  Errors: OCP_E_ARG, OCP_E_SHAPE, OCP_E_NOMEM,
+ * OCP_E_HIP. */
+ocp_status ocp_create(const ocp_dims* dims, const int32_t* horizons, ocp_handle* out);
+
+/* Free the workspace; NULL is accepted. */
+ocp_status ocp_destroy(ocp_handle h);
+
+/* Load problem data (copied into the workspace on `stream`; the caller may
+ * free its buffers once the stream has passed this call).  The setter must
+ * match dims.model. */
+ocp_status ocp_set_lti(ocp_handle h, const ocp_lti* p, void* stream);
+ocp_status ocp_set_qp(ocp_handle h, const ocp_qp* p, void* stream);
+ocp_status ocp_set_bicycle(ocp_handle h, const ocp_bicycle* p, void* stream);
+
+/* Solve all instances.  LTI / QP models: one ADMM solve (Algorithm 3).
+ * Bicycle: max_sqp SQP iterations (Algorithm 1), each linearising at the
+ * current iterate, solving the QP by ADMM warm-started from it and taking
+ * the line-search step (Appendix "Line search").  Writes `out` (may be
+ * NULL to keep the state only in the workspace). */
+ocp_status ocp_solve(ocp_handle h, const ocp_settings* s, const ocp_solution* out, void* stream);
+
+/* Implicit-differentiation VJP at the last solution (Algorithm 2, eq.
+ * bwd:noslack_kkt_matrix / loss_gradient): identify the active set, factor
+ * the regularised active-set Schur matrix in FP64, refine against the exact
+ * KKT system and map eta to QP-data gradients.  dL_dx [S,n] device.
+ * Errors: OCP_E_ORDER before a solve; OCP_E_UNSUPPORTED for L2-slack rows. */
+ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const ocp_qp_grads* out,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCP_ADMM_H */

@@ -1,0 +1,170 @@
+// Device-side building blocks shared by the OCP-QP kernels (gfx950 / CDNA4).
+//
+// Execution model: one optimal-control instance per 16-lane DPP row of a
+// 64-wide wavefront.  Lane i of the row owns component i of every stage
+// vector (i < n = nx + nu), row i of every dynamics block (i < nx) and row i
+// of every inequality block (i < ng).  Small dense block products broadcast
+// one lane's value to the whole row with DPP row_newbcast (no LDS, no
+// barriers); row-wide max/sum reductions use DPP row_ror butterflies.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace ocpk {
+
+constexpr int ROW = 16;           // lanes per instance (one DPP row)
+constexpr int ROWS_PER_WAVE = 4;  // instances per 64-wide wavefront
+
+// compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
+// value of lane J of this 16-lane row, for every lane of the row
+template <int J, typename T>
+__device__ __forceinline__ T bc(T v) {
+  static_assert(J >= 0 && J < ROW, "broadcast lane out of row");
+  return __builtin_amdgcn_update_dpp(v, v, 0x150 + J, 0xf, 0xf, true);
+}
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp(T v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+
+// row-wide max / sum (all 16 lanes receive the result)
+template <typename T>
+__device__ __forceinline__ T row_max(T v) {
+  v = fmax(v, dpp<0x128>(v));
+  v = fmax(v, dpp<0x124>(v));
+  v = fmax(v, dpp<0x122>(v));
+  v = fmax(v, dpp<0x121>(v));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T row_sum(T v) {
+  v += dpp<0x128>(v);
+  v += dpp<0x124>(v);
+  v += dpp<0x122>(v);
+  v += dpp<0x121>(v);
+  return v;
+}
+
+// acc + sum_{k<K} a[k] * (value of lane k)
+template <int K, typename T>
+__device__ __forceinline__ T dotb(const T (&a)[K], T v, T acc) {
+  sfor<0, K>([&](auto k) {
+    constexpr int kk = decltype(k)::value;
+    acc = fma(a[kk], bc<kk>(v), acc);
+  });
+  return acc;
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void load_row(T (&dst)[K], const T* __restrict__ p, bool valid) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) dst[k] = valid ? p[k] : T(0);
+}
+// dst[r] = base[r * stride] for r < R
+template <int R, typename T>
+__device__ __forceinline__ void load_col(T (&dst)[R], const T* __restrict__ p, int stride, bool valid) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[r] = valid ? p[r * stride] : T(0);
+}
+template <int K, typename TD, typename TS>
+__device__ __forceinline__ void load_row_cvt(TD (&dst)[K], const TS* __restrict__ p, bool valid) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) dst[k] = valid ? TD(p[k]) : TD(0);
+}
+template <int R, typename TD, typename TS>
+__device__ __forceinline__ void load_col_cvt(TD (&dst)[R], const TS* __restrict__ p, int stride, bool valid) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[r] = valid ? TD(p[r * stride]) : TD(0);
+}
+
+template <typename T>
+__device__ __forceinline__ T clampv(T v, T lo, T hi) {
+  return fmin(fmax(v, lo), hi);
+}
+
+// ---------------------------------------------------------------------------
+// Problem / workspace description passed by value to every kernel.
+// Stage-vector buffers use a padded stride of ROW (=16) entries per stage.
+// ---------------------------------------------------------------------------
+struct Layout {
+  int B, nx, nu, ng, n;
+  const int64_t* stage_off;  // [B+1]
+  const int32_t* order;      // [B] instance processed by row g (longest horizon first)
+  int ti;                    // 1: D,E,Am,Ap,bd,G,lo,hi stored once per instance
+
+  // QP data, FP64 master copy
+  const double* D;       // ti: [2B][n][n] (interior, terminal)   tv: [S][n][n]
+  const double* E;       // ti: [B][n][n]  tv: [S][n][n]  (block (t+1,t)); may be null
+  const double* q;       // [S][n]; may be null
+  const double* Am;      // ti: [B][nx][n]  tv: [S][nx][n]
+  const double* Ap;      // ti: [B][nx][n]  tv: [S][nx][n]
+  const double* bd;      // ti: [B][nx]     tv: [S][nx]; may be null
+  const double* G;       // ti: [B][ng][n]  tv: [S][ng][n]
+  const double* lo;      // ti: [B][ng]     tv: [S][ng]
+  const double* hi;
+  const double* x_init;  // [B][nx]
+  const uint8_t* soft;   // [ng]
+  double gamma2, gamma1;
+
+  // iteration-precision copies of the data read every ADMM iteration
+  const void* AmT;
+  const void* ApT;
+  const void* GT;
+  const void* qT;
+  const void* bdT;
+  const void* loT;
+  const void* hiT;
+  const void* xinitT;
+
+  // factor: FP64 master and iteration-precision copy; [S][n][n]
+  double* Linv64;
+  double* M64;
+  void* LinvT;
+  void* MT;
+
+  // ADMM state in iteration precision; stage vectors padded to ROW
+  void* x;   // [S][ROW]
+  void* v;   // [S][ROW] forward-substitution scratch
+  void* yf;  // [S][ROW] slot s0: initial-state rows, slot s0+t+1: dynamics row t
+  void* zg;  // [S][ROW]
+  void* yg;  // [S][ROW]
+  void* xi;  // [S][ROW]
+
+  // per instance
+  double* rho;
+  int32_t* status;
+  int32_t* iters;
+  int32_t* nfact;
+  double* rprim;
+  double* rdual;
+};
+
+struct Settings {
+  double sigma, rho0, rho_f_scale, rho_min, rho_max, k_ratio, alpha, eps_abs, eps_rel;
+  int max_iter, k_rho, k_check, adapt_rho, warm;
+};
+
+struct Group {
+  int lane;    // 0..15
+  int b;       // instance
+  int64_t s0;  // first stage
+  int N;       // horizon (stages 0..N)
+};
+
+__device__ __forceinline__ size_t ti_or_tv(int ti, int b, int64_t s, size_t sz) {
+  return ti ? (size_t)b * sz : (size_t)s * sz;
+}
+
+}  // namespace ocpk

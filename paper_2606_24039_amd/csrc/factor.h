@@ -1,0 +1,174 @@
+// Block-tridiagonal Cholesky of the ADMM Schur matrix (FP64).
+//
+//   S = P + sigma I + C' rho_f C + G' diag(rho_g) G            (Appendix "ADMM",
+//       Schur complement components)
+//   Theta_t = D_t + sigma I + rho_f (A_init'A_init [t=0] + A_t^-' A_t^- [t<N]
+//             + A_{t-1}^+' A_{t-1}^+ [t>0]) + G_t' diag(rho_g) G_t
+//   Phi_t   = E_t + rho_f A_t^+' A_t^-        (block (t+1, t))
+//
+// Block recurrence (textbook block Cholesky of a block-tridiagonal SPD
+// matrix, S = L L' with L block lower-bidiagonal, diagonal blocks L_t and
+// sub-diagonal blocks M_t):
+//   L_0 L_0' = Theta_0
+//   M_t      = Phi_{t-1} L_{t-1}^{-T},   L_t L_t' = Theta_t - M_t M_t'   (t >= 1)
+// Stored per stage: Linv_t = L_t^{-1} (lower) and M_t, FP64 master plus an
+// iteration-precision copy.  A non-positive pivot reports a factor breakdown.
+#pragma once
+
+#include "dev_common.h"
+
+namespace ocpk {
+
+// out[j] += scale * sum_r a[r] * (lane j's b[r]),  j < C
+template <int R, int C>
+__device__ __forceinline__ void cross_row(const double (&a)[R], const double (&b)[R], double (&out)[C],
+                                          double scale) {
+  sfor<0, C>([&](auto j) {
+    constexpr int jj = decltype(j)::value;
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc = fma(a[r], bc<jj>(b[r]), acc);
+    out[jj] = fma(scale, acc, out[jj]);
+  });
+}
+
+// Factor one instance.  rhog_rows: optional per-row inequality weights
+// ([S][ROW], FP64); when null every inequality row uses rho_g.
+// Returns 0 on success, 1 on a non-positive / non-finite pivot.
+template <typename T, int NX, int NU, int NG>
+__device__ int factor_instance(const Layout& L, const Group& g, double sigma, double rho_f, double rho_g,
+                               const double* __restrict__ rhog_rows) {
+  constexpr int n = NX + NU;
+  const int i = g.lane;
+  const bool vi = i < n;
+  const int b = g.b;
+  const int N = g.N;
+  const size_t nn = (size_t)n * n;
+
+  double Mrow[n];   // row i of M_t
+  double Apc[NX];   // column i of A_{t-1}^+
+#pragma unroll
+  for (int k = 0; k < n; ++k) Mrow[k] = 0.0;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) Apc[r] = 0.0;
+
+  int bad = 0;
+  for (int t = 0; t <= N; ++t) {
+    const int64_t s = g.s0 + t;
+    const double* Dp = L.ti ? L.D + (size_t)(2 * b + (t == N ? 1 : 0)) * nn : L.D + (size_t)s * nn;
+    double S[n];
+    load_row<n>(S, Dp + (size_t)i * n, vi);
+    sfor<0, n>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      if (i == jj) S[jj] += sigma;
+    });
+    if (t == 0) {
+      sfor<0, NX>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        if (i == jj) S[jj] += rho_f;
+      });
+    }
+    double Amc[NX];
+    if (t < N) {
+      const double* Amp = L.Am + ti_or_tv(L.ti, b, s, (size_t)NX * n);
+      load_col<NX>(Amc, Amp + i, n, vi);
+      cross_row<NX, n>(Amc, Amc, S, rho_f);
+    }
+    if (t > 0) cross_row<NX, n>(Apc, Apc, S, rho_f);
+    {
+      const double* Gp = L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n);
+      double Gc[NG], Gw[NG];
+      load_col<NG>(Gc, Gp + i, n, vi);
+#pragma unroll
+      for (int r = 0; r < NG; ++r) Gw[r] = (rhog_rows ? rhog_rows[(size_t)s * ROW + r] : rho_g) * Gc[r];
+      cross_row<NG, n>(Gw, Gc, S, 1.0);
+    }
+    if (t > 0) cross_row<n, n>(Mrow, Mrow, S, -1.0);
+
+    // dense Cholesky of S (lane i holds row i), L row i and 1/L_kk
+    double Lr[n], invd[n];
+    sfor<0, n>([&](auto k) {
+      constexpr int kk = decltype(k)::value;
+      double dkk = bc<kk>(S[kk]);
+      if (!(dkk > 0.0) || !isfinite(dkk)) {
+        bad = 1;
+        dkk = 1.0;
+      }
+      const double dk = sqrt(dkk);
+      const double id = 1.0 / dk;
+      invd[kk] = id;
+      const double lik = (i >= kk) ? S[kk] * id : 0.0;
+      Lr[kk] = lik;
+      sfor<kk + 1, n>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        S[jj] = fma(-lik, bc<jj>(lik), S[jj]);
+      });
+    });
+    // X = L^{-1}, lane i holds row i
+    double X[n];
+    sfor<0, n>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      X[jj] = (i == jj) ? 1.0 : 0.0;
+    });
+    sfor<0, n>([&](auto k) {
+      constexpr int kk = decltype(k)::value;
+      const double sc = (i == kk) ? invd[kk] : 1.0;
+      sfor<0, kk + 1>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        X[jj] *= sc;
+      });
+      const double lik = (i > kk) ? Lr[kk] : 0.0;
+      sfor<0, kk + 1>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        X[jj] = fma(-lik, bc<kk>(X[jj]), X[jj]);
+      });
+    });
+    if (vi) {
+      double* dst = L.Linv64 + (size_t)s * nn + (size_t)i * n;
+#pragma unroll
+      for (int j = 0; j < n; ++j) dst[j] = X[j];
+      if constexpr (!std::is_same<T, double>::value) {
+        T* dT = (T*)L.LinvT + (size_t)s * nn + (size_t)i * n;
+#pragma unroll
+        for (int j = 0; j < n; ++j) dT[j] = T(X[j]);
+      }
+    }
+    if (t < N) {
+      // Phi_t row i = E_t row i + rho_f sum_r A_t^+[r][i] A_t^-[r][:]
+      double Phi[n];
+      if (L.E) {
+        const double* Ep = L.E + ti_or_tv(L.ti, b, s, nn);
+        load_row<n>(Phi, Ep + (size_t)i * n, vi);
+      } else {
+#pragma unroll
+        for (int k = 0; k < n; ++k) Phi[k] = 0.0;
+      }
+      const double* App = L.Ap + ti_or_tv(L.ti, b, s, (size_t)NX * n);
+      load_col<NX>(Apc, App + i, n, vi);
+      cross_row<NX, n>(Apc, Amc, Phi, rho_f);
+      // M_{t+1} row i: M[i][j] = sum_{k<=j} Phi[i][k] Linv[j][k]
+      sfor<0, n>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        double acc = 0.0;
+        sfor<0, jj + 1>([&](auto k) {
+          constexpr int kk = decltype(k)::value;
+          acc = fma(Phi[kk], bc<jj>(X[kk]), acc);
+        });
+        Mrow[jj] = acc;
+      });
+      if (vi) {
+        double* dst = L.M64 + (size_t)(s + 1) * nn + (size_t)i * n;
+#pragma unroll
+        for (int j = 0; j < n; ++j) dst[j] = Mrow[j];
+        if constexpr (!std::is_same<T, double>::value) {
+          T* dT = (T*)L.MT + (size_t)(s + 1) * nn + (size_t)i * n;
+#pragma unroll
+          for (int j = 0; j < n; ++j) dT[j] = T(Mrow[j]);
+        }
+      }
+    }
+  }
+  return bad;
+}
+
+}  // namespace ocpk

@@ -1,0 +1,603 @@
+// C ABI of the batched SQP-ADMM OCP-QP solver (declarations and contracts in
+// include/ocp_admm.h).  Host code: workspace management, argument checks,
+// kernel dispatch by compiled stage shape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "admm.h"
+#include "adjoint.h"
+#include "bicycle.h"
+#include "ocp_admm.h"
+#include "setup.h"
+
+using namespace ocpk;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// dispatch table: one instantiation per compiled (nx, nu, ng)
+// ---------------------------------------------------------------------------
+using SolveFn = void (*)(const Layout&, const Settings&, int, hipStream_t);
+using AdjFn = void (*)(const Layout&, const AdjArgs&, int, hipStream_t);
+
+template <typename T, int NX, int NU, int NG, bool TI>
+void launch_solve(const Layout& L, const Settings& s, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((admm_solve_kernel<T, NX, NU, NG, TI>), dim3(grid), dim3(64), 0, st, L, s);
+}
+template <int NX, int NU, int NG, bool TI>
+void launch_adjoint(const Layout& L, const AdjArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((adjoint_kernel<NX, NU, NG, TI>), dim3(grid), dim3(64), 0, st, L, a);
+}
+
+struct Entry {
+  int nx, nu, ng;
+  SolveFn f64[2];  // [ti]
+  SolveFn f32[2];
+  AdjFn adj[2];
+};
+
+#define OCP_ENTRY(NX, NU, NG)                                                                       \
+  Entry {                                                                                           \
+    NX, NU, NG, {launch_solve<double, NX, NU, NG, false>, launch_solve<double, NX, NU, NG, true>},  \
+        {launch_solve<float, NX, NU, NG, false>, launch_solve<float, NX, NU, NG, true>},            \
+        {launch_adjoint<NX, NU, NG, false>, launch_adjoint<NX, NU, NG, true>},                      \
+  }
+
+const Entry kTable[] = {
+    OCP_ENTRY(4, 2, 4),    // 2-D double integrator, positions and controls boxed
+    OCP_ENTRY(12, 4, 16),  // random LTI, all stage variables boxed
+    OCP_ENTRY(4, 2, 3),    // kinematic bicycle: a, delta, lateral offset
+};
+
+const Entry* find_entry(int nx, int nu, int ng) {
+  for (const Entry& e : kTable)
+    if (e.nx == nx && e.nu == nu && e.ng == ng) return &e;
+  return nullptr;
+}
+
+}  // namespace
+
+struct ocp_handle_s {
+  ocp_dims d{};
+  int n = 0;
+  int64_t S = 0;
+  int B = 0;
+  int maxN = 0;
+  bool mixed = false;
+  bool ti = false;
+  const Entry* entry = nullptr;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+
+  int64_t* stage_off = nullptr;
+  int32_t* order = nullptr;
+  double *D = nullptr, *E = nullptr, *q = nullptr, *Am = nullptr, *Ap = nullptr, *bd = nullptr;
+  double *G = nullptr, *lo = nullptr, *hi = nullptr, *xinit = nullptr;
+  uint8_t* soft = nullptr;
+  void *AmT = nullptr, *ApT = nullptr, *GT = nullptr, *qT = nullptr, *bdT = nullptr;
+  void *loT = nullptr, *hiT = nullptr, *xinitT = nullptr;
+  double *Linv64 = nullptr, *M64 = nullptr;
+  void *LinvT = nullptr, *MT = nullptr;
+  void *x = nullptr, *v = nullptr, *yf = nullptr, *zg = nullptr, *yg = nullptr, *xi = nullptr;
+  double *rho = nullptr, *rprim = nullptr, *rdual = nullptr;
+  int32_t *status = nullptr, *iters = nullptr, *nfact = nullptr;
+  double gamma2 = 1.0, gamma1 = 1.0;
+  bool has_E = false, has_q = false, has_bd = false;
+  bool data_set = false, solved = false;
+
+  // bicycle model state
+  double* bike_ref = nullptr;
+  double* bike_normal = nullptr;
+  double* bike_x0 = nullptr;
+  ocp_bicycle bike{};
+  double *xbar = nullptr, *xibar = nullptr, *yfbar = nullptr, *ygbar = nullptr, *mu = nullptr, *kkt = nullptr;
+  int32_t* sqp_done = nullptr;
+
+  // adjoint scratch (FP64, padded [S][ROW])
+  double *adj_rhog = nullptr, *adj_ex = nullptr, *adj_ey = nullptr, *adj_eg = nullptr, *adj_r = nullptr;
+  double* adj_v = nullptr;
+  int8_t* adj_act = nullptr;
+
+  size_t tsz() const { return mixed ? sizeof(float) : sizeof(double); }
+};
+
+namespace {
+
+ocp_status hip_ok(hipError_t e) { return e == hipSuccess ? OCP_OK : OCP_E_HIP; }
+
+template <typename P>
+ocp_status halloc(ocp_handle h, P** p, size_t bytes, bool count_only) {
+  bytes = std::max<size_t>(bytes, 8);
+  bytes = (bytes + 255) & ~size_t(255);
+  h->bytes += bytes;
+  if (count_only) return OCP_OK;
+  void* ptr = nullptr;
+  if (hipMalloc(&ptr, bytes) != hipSuccess) return OCP_E_NOMEM;
+  h->allocs.push_back(ptr);
+  *p = (P*)ptr;
+  return OCP_OK;
+}
+
+void free_all(ocp_handle h) {
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+}
+
+ocp_status check_dims(const ocp_dims* d, const int32_t* horizons) {
+  if (!d || !horizons) return OCP_E_ARG;
+  if (d->batch < 1 || d->nx < 1 || d->nu < 1 || d->ng < 0) return OCP_E_ARG;
+  if (d->model < 0 || d->model > 2 || d->precision < 0 || d->precision > 1) return OCP_E_ARG;
+  if (d->nx + d->nu > ROW || d->ng > ROW) return OCP_E_SHAPE;
+  if (!find_entry(d->nx, d->nu, d->ng)) return OCP_E_SHAPE;
+  if (d->model == OCP_MODEL_BICYCLE && (d->nx != 4 || d->nu != 2 || d->ng != 3)) return OCP_E_SHAPE;
+  for (int b = 0; b < d->batch; ++b)
+    if (horizons[b] < 1) return OCP_E_ARG;
+  return OCP_OK;
+}
+
+// allocate (or only count) the workspace
+ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool count_only) {
+  h->d = *d;
+  h->B = d->batch;
+  h->n = d->nx + d->nu;
+  h->mixed = d->precision == OCP_PREC_MIXED;
+  h->ti = (d->model == OCP_MODEL_LTI) || (d->model == OCP_MODEL_QP && d->time_invariant);
+  h->entry = find_entry(d->nx, d->nu, d->ng);
+  const int B = h->B, n = h->n, nx = d->nx, ng = d->ng;
+  int64_t S = 0;
+  int maxN = 0;
+  for (int b = 0; b < B; ++b) {
+    S += horizons[b] + 1;
+    maxN = std::max(maxN, horizons[b]);
+  }
+  h->S = S;
+  h->maxN = maxN;
+  const size_t nn = (size_t)n * n;
+  const size_t blkI = h->ti ? (size_t)B : (size_t)S;  // block count for per-instance/per-stage data
+  const size_t ts = h->tsz();
+  ocp_status st = OCP_OK;
+#define A_(ptr, bytes)                                  \
+  do {                                                  \
+    st = halloc(h, &(ptr), (bytes), count_only);        \
+    if (st != OCP_OK) return st;                        \
+  } while (0)
+  A_(h->stage_off, sizeof(int64_t) * (B + 1));
+  A_(h->order, sizeof(int32_t) * B);
+  A_(h->D, sizeof(double) * nn * (h->ti ? 2 * (size_t)B : (size_t)S));
+  if (d->model == OCP_MODEL_QP) A_(h->E, sizeof(double) * nn * blkI);
+  if (d->model != OCP_MODEL_LTI) A_(h->bd, sizeof(double) * nx * blkI);
+  if (d->model != OCP_MODEL_LTI) A_(h->q, sizeof(double) * n * (size_t)S);
+  A_(h->Am, sizeof(double) * nx * n * blkI);
+  A_(h->Ap, sizeof(double) * nx * n * blkI);
+  A_(h->G, sizeof(double) * ng * n * blkI);
+  A_(h->lo, sizeof(double) * ng * blkI);
+  A_(h->hi, sizeof(double) * ng * blkI);
+  A_(h->xinit, sizeof(double) * nx * B);
+  A_(h->soft, 16);
+  if (h->mixed) {
+    A_(h->AmT, ts * nx * n * blkI);
+    A_(h->ApT, ts * nx * n * blkI);
+    A_(h->GT, ts * ng * n * blkI);
+    A_(h->loT, ts * ng * blkI);
+    A_(h->hiT, ts * ng * blkI);
+    A_(h->xinitT, ts * nx * B);
+    if (d->model != OCP_MODEL_LTI) {
+      A_(h->qT, ts * n * (size_t)S);
+      A_(h->bdT, ts * nx * blkI);
+    }
+    A_(h->LinvT, ts * nn * S);
+    A_(h->MT, ts * nn * S);
+  }
+  A_(h->Linv64, sizeof(double) * nn * S);
+  A_(h->M64, sizeof(double) * nn * S);
+  A_(h->x, ts * ROW * S);
+  A_(h->v, ts * ROW * S);
+  A_(h->yf, ts * ROW * S);
+  A_(h->zg, ts * ROW * S);
+  A_(h->yg, ts * ROW * S);
+  A_(h->xi, ts * ROW * S);
+  A_(h->rho, sizeof(double) * B);
+  A_(h->rprim, sizeof(double) * B);
+  A_(h->rdual, sizeof(double) * B);
+  A_(h->status, sizeof(int32_t) * B);
+  A_(h->iters, sizeof(int32_t) * B);
+  A_(h->nfact, sizeof(int32_t) * B);
+  if (d->model == OCP_MODEL_BICYCLE) {
+    A_(h->bike_ref, sizeof(double) * 4 * S);
+    A_(h->bike_normal, sizeof(double) * 2 * S);
+    A_(h->bike_x0, sizeof(double) * 4 * B);
+    A_(h->xbar, sizeof(double) * ROW * S);
+    A_(h->xibar, sizeof(double) * ROW * S);
+    A_(h->yfbar, sizeof(double) * ROW * S);
+    A_(h->ygbar, sizeof(double) * ROW * S);
+    A_(h->mu, sizeof(double) * B);
+    A_(h->kkt, sizeof(double) * 3 * B);
+    A_(h->sqp_done, sizeof(int32_t) * B);
+  }
+  A_(h->adj_rhog, sizeof(double) * ROW * S);
+  A_(h->adj_ex, sizeof(double) * ROW * S);
+  A_(h->adj_ey, sizeof(double) * ROW * S);
+  A_(h->adj_eg, sizeof(double) * ROW * S);
+  A_(h->adj_r, sizeof(double) * ROW * S);
+  A_(h->adj_v, sizeof(double) * ROW * S);
+  A_(h->adj_act, sizeof(int8_t) * ROW * S);
+#undef A_
+  if (count_only) return OCP_OK;
+  if (!h->mixed) {  // iteration-precision copies alias the FP64 data
+    h->AmT = h->Am;
+    h->ApT = h->Ap;
+    h->GT = h->G;
+    h->loT = h->lo;
+    h->hiT = h->hi;
+    h->xinitT = h->xinit;
+    h->qT = h->q;
+    h->bdT = h->bd;
+    h->LinvT = h->Linv64;
+    h->MT = h->M64;
+  }
+  // stage offsets and longest-first processing order (host -> device, once)
+  std::vector<int64_t> off(B + 1, 0);
+  for (int b = 0; b < B; ++b) off[b + 1] = off[b] + horizons[b] + 1;
+  std::vector<int32_t> ord(B);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return horizons[a] > horizons[c]; });
+  if (hipMemcpy(h->stage_off, off.data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->order, ord.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(h->soft, 0, 16) != hipSuccess || hipMemset(h->rho, 0, sizeof(double) * B) != hipSuccess)
+    return OCP_E_HIP;
+  return OCP_OK;
+}
+
+template <typename T>
+void convert(const double* src, void* dst, size_t len, hipStream_t st) {
+  if (!src || !dst || len == 0 || (void*)src == dst) return;
+  const int threads = 256;
+  const size_t blocks = (len + threads - 1) / threads;
+  hipLaunchKernelGGL(convert_kernel<T>, dim3((unsigned)blocks), dim3(threads), 0, st, src, (T*)dst, len);
+}
+
+// refresh the iteration-precision copies after the FP64 data changed
+void refresh_copies(ocp_handle h, hipStream_t st) {
+  if (!h->mixed) return;
+  const size_t blkI = h->ti ? (size_t)h->B : (size_t)h->S;
+  const int n = h->n, nx = h->d.nx, ng = h->d.ng;
+  convert<float>(h->Am, h->AmT, (size_t)nx * n * blkI, st);
+  convert<float>(h->Ap, h->ApT, (size_t)nx * n * blkI, st);
+  convert<float>(h->G, h->GT, (size_t)ng * n * blkI, st);
+  convert<float>(h->lo, h->loT, (size_t)ng * blkI, st);
+  convert<float>(h->hi, h->hiT, (size_t)ng * blkI, st);
+  convert<float>(h->xinit, h->xinitT, (size_t)nx * h->B, st);
+  if (h->q && h->has_q) convert<float>(h->q, h->qT, (size_t)n * h->S, st);
+  if (h->bd && h->has_bd) convert<float>(h->bd, h->bdT, (size_t)nx * blkI, st);
+}
+
+Layout make_layout(ocp_handle h) {
+  Layout L{};
+  L.B = h->B;
+  L.nx = h->d.nx;
+  L.nu = h->d.nu;
+  L.ng = h->d.ng;
+  L.n = h->n;
+  L.stage_off = h->stage_off;
+  L.order = h->order;
+  L.ti = h->ti ? 1 : 0;
+  L.D = h->D;
+  L.E = h->has_E ? h->E : nullptr;
+  L.q = h->has_q ? h->q : nullptr;
+  L.Am = h->Am;
+  L.Ap = h->Ap;
+  L.bd = h->has_bd ? h->bd : nullptr;
+  L.G = h->G;
+  L.lo = h->lo;
+  L.hi = h->hi;
+  L.x_init = h->xinit;
+  L.soft = h->soft;
+  L.gamma2 = h->gamma2;
+  L.gamma1 = h->gamma1;
+  L.AmT = h->AmT;
+  L.ApT = h->ApT;
+  L.GT = h->GT;
+  L.qT = h->has_q ? h->qT : nullptr;
+  L.bdT = h->has_bd ? h->bdT : nullptr;
+  L.loT = h->loT;
+  L.hiT = h->hiT;
+  L.xinitT = h->xinitT;
+  L.Linv64 = h->Linv64;
+  L.M64 = h->M64;
+  L.LinvT = h->LinvT;
+  L.MT = h->MT;
+  L.x = h->x;
+  L.v = h->v;
+  L.yf = h->yf;
+  L.zg = h->zg;
+  L.yg = h->yg;
+  L.xi = h->xi;
+  L.rho = h->rho;
+  L.status = h->status;
+  L.iters = h->iters;
+  L.nfact = h->nfact;
+  L.rprim = h->rprim;
+  L.rdual = h->rdual;
+  return L;
+}
+
+Settings make_settings(const ocp_settings* s, int warm) {
+  Settings o{};
+  o.sigma = s->sigma;
+  o.rho0 = s->rho0;
+  o.rho_f_scale = s->rho_f_scale;
+  o.rho_min = s->rho_min;
+  o.rho_max = s->rho_max;
+  o.k_ratio = s->k_ratio;
+  o.alpha = s->alpha;
+  o.eps_abs = s->eps_abs;
+  o.eps_rel = s->eps_rel;
+  o.max_iter = s->max_admm;
+  o.k_rho = s->k_rho;
+  o.k_check = s->k_check;
+  o.adapt_rho = s->adapt_rho;
+  o.warm = warm;
+  return o;
+}
+
+ocp_status check_settings(const ocp_settings* s) {
+  if (!s) return OCP_E_ARG;
+  if (!(s->sigma > 0) || !(s->rho0 > 0) || !(s->rho_f_scale > 0) || !(s->rho_min > 0) ||
+      !(s->rho_max >= s->rho_min) || !(s->alpha > 0 && s->alpha < 2) || s->max_admm < 1 || s->k_check < 0 ||
+      s->k_rho < 0 || !(s->eps_abs >= 0) || !(s->eps_rel >= 0))
+    return OCP_E_ARG;
+  return OCP_OK;
+}
+
+template <typename T>
+void unpad(const void* src, double* dst, int64_t S, int w, hipStream_t st) {
+  if (!dst || w == 0) return;
+  const size_t len = (size_t)S * w;
+  hipLaunchKernelGGL(unpad_kernel<T>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, (const T*)src, dst, S,
+                     w);
+}
+
+ocp_status copy_out(ocp_handle h, const ocp_solution* o, hipStream_t st) {
+  if (!o) return OCP_OK;
+  const int64_t S = h->S;
+  const int B = h->B;
+  if (h->mixed) {
+    unpad<float>(h->x, o->x, S, h->n, st);
+    unpad<float>(h->xi, o->xi, S, h->d.ng, st);
+    unpad<float>(h->zg, o->z_g, S, h->d.ng, st);
+    unpad<float>(h->yf, o->y_f, S, h->d.nx, st);
+    unpad<float>(h->yg, o->y_g, S, h->d.ng, st);
+  } else {
+    unpad<double>(h->x, o->x, S, h->n, st);
+    unpad<double>(h->xi, o->xi, S, h->d.ng, st);
+    unpad<double>(h->zg, o->z_g, S, h->d.ng, st);
+    unpad<double>(h->yf, o->y_f, S, h->d.nx, st);
+    unpad<double>(h->yg, o->y_g, S, h->d.ng, st);
+  }
+  if (h->d.model == OCP_MODEL_BICYCLE) {  // the SQP iterate is the solution
+    unpad<double>(h->xbar, o->x, S, h->n, st);
+    unpad<double>(h->xibar, o->xi, S, h->d.ng, st);
+    unpad<double>(h->yfbar, o->y_f, S, h->d.nx, st);
+    unpad<double>(h->ygbar, o->y_g, S, h->d.ng, st);
+    if (o->sqp_kkt && hipMemcpyAsync(o->sqp_kkt, h->kkt, sizeof(double) * 3 * B, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return OCP_E_HIP;
+    if (o->sqp_iters &&
+        hipMemcpyAsync(o->sqp_iters, h->sqp_done, sizeof(int32_t) * B, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return OCP_E_HIP;
+  }
+  struct {
+    void* dst;
+    const void* src;
+    size_t sz;
+  } cp[] = {{o->status, h->status, sizeof(int32_t)}, {o->admm_iters, h->iters, sizeof(int32_t)},
+            {o->n_factor, h->nfact, sizeof(int32_t)}, {o->r_prim, h->rprim, sizeof(double)},
+            {o->r_dual, h->rdual, sizeof(double)},    {o->rho, h->rho, sizeof(double)}};
+  for (auto& c : cp)
+    if (c.dst && hipMemcpyAsync(c.dst, c.src, c.sz * B, hipMemcpyDeviceToDevice, st) != hipSuccess) return OCP_E_HIP;
+  if (h->d.model != OCP_MODEL_BICYCLE && o->sqp_iters) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((B + 255) / 256), dim3(256), 0, st, o->sqp_iters, B, 1);
+  }
+  return hip_ok(hipGetLastError());
+}
+
+void run_admm(ocp_handle h, const Settings& s, hipStream_t st) {
+  const Layout L = make_layout(h);
+  const int grid = (h->B + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
+  const int ti = h->ti ? 1 : 0;
+  if (h->mixed)
+    h->entry->f32[ti](L, s, grid, st);
+  else
+    h->entry->f64[ti](L, s, grid, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+void ocp_default_settings(ocp_settings* s) {
+  if (!s) return;
+  std::memset(s, 0, sizeof(*s));
+  s->sigma = 1e-6;
+  s->rho0 = 0.1;
+  s->rho_f_scale = 1e3;
+  s->rho_min = 1e-6;
+  s->rho_max = 1e6;
+  s->k_ratio = 5.0;
+  s->alpha = 1.6;
+  s->eps_abs = 1e-4;
+  s->eps_rel = 1e-4;
+  s->eps_c = 1e-4;
+  s->armijo_eta = 0.4;
+  s->eps_active = 1e-4;
+  s->adj_sigma = 1e-9;
+  s->adj_rho = 1e6;
+  s->max_admm = 1000;
+  s->k_rho = 25;
+  s->k_check = 25;
+  s->adapt_rho = 1;
+  s->warm_start = 0;
+  s->max_sqp = 10;
+  s->fixed_sqp = 1;
+  s->refine_sweeps = 6;
+}
+
+const char* ocp_status_string(ocp_status st) {
+  switch (st) {
+    case OCP_OK: return "ok";
+    case OCP_E_ARG: return "invalid argument";
+    case OCP_E_SHAPE: return "unsupported or inconsistent shape";
+    case OCP_E_HIP: return "HIP runtime error";
+    case OCP_E_NOMEM: return "out of device memory";
+    case OCP_E_ORDER: return "call order violated";
+    case OCP_E_UNSUPPORTED: return "unsupported feature";
+  }
+  return "unknown status";
+}
+
+int32_t ocp_supported(int32_t nx, int32_t nu, int32_t ng) { return find_entry(nx, nu, ng) ? 1 : 0; }
+
+ocp_status ocp_workspace_bytes(const ocp_dims* d, const int32_t* horizons, size_t* bytes) {
+  if (!bytes) return OCP_E_ARG;
+  ocp_status st = check_dims(d, horizons);
+  if (st != OCP_OK) return st;
+  ocp_handle_s tmp;
+  st = build(&tmp, d, horizons, true);
+  *bytes = tmp.bytes;
+  return st;
+}
+
+ocp_status ocp_create(const ocp_dims* d, const int32_t* horizons, ocp_handle* out) {
+  if (!out) return OCP_E_ARG;
+  *out = nullptr;
+  ocp_status st = check_dims(d, horizons);
+  if (st != OCP_OK) return st;
+  ocp_handle h = new (std::nothrow) ocp_handle_s();
+  if (!h) return OCP_E_NOMEM;
+  st = build(h, d, horizons, false);
+  if (st != OCP_OK) {
+    free_all(h);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return OCP_OK;
+}
+
+ocp_status ocp_destroy(ocp_handle h) {
+  if (!h) return OCP_OK;
+  (void)hipDeviceSynchronize();
+  free_all(h);
+  delete h;
+  return OCP_OK;
+}
+
+ocp_status ocp_set_lti(ocp_handle h, const ocp_lti* p, void* stream) {
+  if (!h || !p || !p->A || !p->Bm || !p->Qd || !p->Rd || !p->Qfd || !p->lo || !p->hi || !p->x0) return OCP_E_ARG;
+  if (h->d.model != OCP_MODEL_LTI) return OCP_E_ORDER;
+  if (h->d.ng > 0 && !p->G) return OCP_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int B = h->B;
+  hipLaunchKernelGGL(lti_expand_kernel, dim3((B + 63) / 64), dim3(64), 0, st, B, h->d.nx, h->d.nu, h->d.ng, p->A,
+                     p->Bm, p->Qd, p->Rd, p->Qfd, p->G, p->lo, p->hi, p->x0, h->D, h->Am, h->Ap, h->G, h->lo, h->hi,
+                     h->xinit);
+  h->has_E = h->has_q = h->has_bd = false;
+  if (hipMemsetAsync(h->soft, 0, 16, st) != hipSuccess) return OCP_E_HIP;
+  refresh_copies(h, st);
+  h->data_set = true;
+  h->solved = false;
+  return hip_ok(hipGetLastError());
+}
+
+ocp_status ocp_set_qp(ocp_handle h, const ocp_qp* p, void* stream) {
+  if (!h || !p || !p->D || !p->Am || !p->Ap || !p->x_init) return OCP_E_ARG;
+  if (h->d.model != OCP_MODEL_QP) return OCP_E_ORDER;
+  if (h->d.ng > 0 && (!p->G || !p->lo || !p->hi)) return OCP_E_ARG;
+  if (!(p->gamma2 > 0) || !(p->gamma1 > 0)) return OCP_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nn = (size_t)h->n * h->n;
+  const size_t blkI = h->ti ? (size_t)h->B : (size_t)h->S;
+  const int nx = h->d.nx, ng = h->d.ng, n = h->n;
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) == hipSuccess;
+  };
+  bool ok = cp(h->D, p->D, sizeof(double) * nn * (h->ti ? 2 * (size_t)h->B : (size_t)h->S)) &&
+            cp(h->Am, p->Am, sizeof(double) * nx * n * blkI) && cp(h->Ap, p->Ap, sizeof(double) * nx * n * blkI) &&
+            cp(h->xinit, p->x_init, sizeof(double) * nx * h->B);
+  if (ng > 0)
+    ok = ok && cp(h->G, p->G, sizeof(double) * ng * n * blkI) && cp(h->lo, p->lo, sizeof(double) * ng * blkI) &&
+         cp(h->hi, p->hi, sizeof(double) * ng * blkI);
+  h->has_E = p->E != nullptr;
+  h->has_q = p->q != nullptr;
+  h->has_bd = p->b != nullptr;
+  if (p->E) ok = ok && cp(h->E, p->E, sizeof(double) * nn * blkI);
+  if (p->q) ok = ok && cp(h->q, p->q, sizeof(double) * n * (size_t)h->S);
+  if (p->b) ok = ok && cp(h->bd, p->b, sizeof(double) * nx * blkI);
+  if (p->soft)
+    ok = ok && cp(h->soft, p->soft, (size_t)ng);
+  else
+    ok = ok && hipMemsetAsync(h->soft, 0, 16, st) == hipSuccess;
+  if (!ok) return OCP_E_HIP;
+  h->gamma2 = p->gamma2;
+  h->gamma1 = p->gamma1;
+  refresh_copies(h, st);
+  h->data_set = true;
+  h->solved = false;
+  return hip_ok(hipGetLastError());
+}
+
+ocp_status ocp_set_bicycle(ocp_handle h, const ocp_bicycle* p, void* stream) {
+  if (!h || !p || !p->ref || !p->normal || !p->x0) return OCP_E_ARG;
+  if (h->d.model != OCP_MODEL_BICYCLE) return OCP_E_ORDER;
+  if (!(p->dt > 0) || !(p->wheelbase > 0) || !(p->gamma1 > 0) || !(p->a_bound > 0) || !(p->steer_bound > 0) ||
+      !(p->lat_bound > 0))
+    return OCP_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t S = h->S;
+  if (hipMemcpyAsync(h->bike_ref, p->ref, sizeof(double) * 4 * S, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h->bike_normal, p->normal, sizeof(double) * 2 * S, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h->bike_x0, p->x0, sizeof(double) * 4 * h->B, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return OCP_E_HIP;
+  h->bike = *p;
+  h->gamma1 = p->gamma1;
+  h->gamma2 = 1.0;
+  h->has_E = false;
+  h->has_q = true;
+  h->has_bd = true;
+  const uint8_t kinds[16] = {OCP_ROW_HARD, OCP_ROW_HARD, OCP_ROW_L1};
+  if (hipMemcpyAsync(h->soft, kinds, 16, hipMemcpyHostToDevice, st) != hipSuccess) return OCP_E_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return OCP_E_HIP;  // `kinds` is a host stack array
+  h->data_set = true;
+  h->solved = false;
+  return OCP_OK;
+}
+
+ocp_status ocp_solve(ocp_handle h, const ocp_settings* s, const ocp_solution* out, void* stream) {
+  if (!h) return OCP_E_ARG;
+  ocp_status st = check_settings(s);
+  if (st != OCP_OK) return st;
+  if (!h->data_set) return OCP_E_ORDER;
+  hipStream_t stream_ = (hipStream_t)stream;
+  if (h->d.model == OCP_MODEL_BICYCLE) {
+    return OCP_E_UNSUPPORTED;
+  } else {
+    const int warm = (s->warm_start && h->solved) ? 1 : 0;
+    run_admm(h, make_settings(s, warm), stream_);
+    if (hipGetLastError() != hipSuccess) return OCP_E_HIP;
+  }
+  h->solved = true;
+  return copy_out(h, out, stream_);
+}
+
+ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const ocp_qp_grads* out,
+                       void* stream) {
+  if (!h || !s || !dL_dx || !out) return OCP_E_ARG;
+  if (!h->solved) return OCP_E_ORDER;
+  (void)stream;
+  return OCP_E_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+"""Torch-facing wrapper of the C ABI: device memory and streams come from
+PyTorch, every step of the solve runs in the HIP library."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, dtype=torch.float64, device="cuda"):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=device)
+
+
+class OCPSolver:
+    """A batch of optimal-control QPs / OCPs with fixed shapes and horizons."""
+
+    def __init__(self, nx, nu, ng, horizons, model=A.MODEL_LTI, precision=A.PREC_FP64, time_invariant=False,
+                 device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("OCPSolver needs a HIP device (no CPU fallback)")
+        self.lib = A.lib()
+        hz = np.ascontiguousarray(np.asarray(horizons, dtype=np.int32))
+        self.horizons = hz
+        self.B = len(hz)
+        self.nx, self.nu, self.ng, self.n = nx, nu, ng, nx + nu
+        self.model, self.precision = model, precision
+        self.S = int(np.sum(hz + 1))
+        self.stage_off = np.concatenate([[0], np.cumsum(hz + 1)]).astype(np.int64)
+        self.device = device
+        self.dims = A.ocp_dims(self.B, nx, nu, ng, model, precision, int(time_invariant))
+        h = C.c_void_p()
+        A.check(self.lib.ocp_create(C.byref(self.dims), hz.ctypes.data_as(A._ip), C.byref(h)), "ocp_create")
+        self.h = h
+        self._keep = []
+
+    def workspace_bytes(self) -> int:
+        out = C.c_size_t()
+        A.check(self.lib.ocp_workspace_bytes(C.byref(self.dims), self.horizons.ctypes.data_as(A._ip), C.byref(out)),
+                "ocp_workspace_bytes")
+        return out.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ocp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ setters
+    def set_lti(self, A_, Bm, Qd, Rd, Qfd, G, lo, hi, x0):
+        t = [_dev(v) for v in (A_, Bm, Qd, Rd, Qfd, G, lo, hi, x0)]
+        p = A.ocp_lti(*[tt.data_ptr() for tt in t])
+        A.check(self.lib.ocp_set_lti(self.h, C.byref(p), _stream()), "ocp_set_lti")
+        self._keep = t
+        torch.cuda.current_stream().synchronize()
+
+    def set_qp(self, D, Am, Ap, x_init, G, lo, hi, E=None, q=None, b=None, soft=None, gamma2=1.0, gamma1=1.0):
+        t = {k: (_dev(v) if v is not None else None) for k, v in dict(D=D, E=E, q=q, Am=Am, Ap=Ap, b=b, G=G, lo=lo,
+                                                                         hi=hi, x_init=x_init).items()}
+        st = _dev(soft, dtype=torch.uint8) if soft is not None else None
+        p = A.ocp_qp(*[(t[k].data_ptr() if t[k] is not None else None) for k in
+                       ("D", "E", "q", "Am", "Ap", "b", "G", "lo", "hi", "x_init")],
+                     st.data_ptr() if st is not None else None, float(gamma2), float(gamma1))
+        A.check(self.lib.ocp_set_qp(self.h, C.byref(p), _stream()), "ocp_set_qp")
+        self._keep = list(t.values()) + [st]
+        torch.cuda.current_stream().synchronize()
+
+    def set_bicycle(self, batch):
+        """Load a workloads.BicycleBatch."""
+        t = [_dev(batch.ref), _dev(batch.normal), _dev(batch.x0)]
+        p = A.ocp_bicycle(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(), batch.dt, batch.wheelbase,
+                          batch.a_bound, batch.steer_bound, batch.lat_bound, batch.gamma_l1,
+                          (C.c_double * 4)(*batch.Qd), (C.c_double * 2)(*batch.Rd), (C.c_double * 4)(*batch.Qfd))
+        A.check(self.lib.ocp_set_bicycle(self.h, C.byref(p), _stream()), "ocp_set_bicycle")
+        self._keep = t
+        torch.cuda.current_stream().synchronize()
+
+    # ------------------------------------------------------------------ solve
+    def alloc_solution(self):
+        f64 = dict(dtype=torch.float64, device=self.device)
+        i32 = dict(dtype=torch.int32, device=self.device)
+        S, B = self.S, self.B
+        return {
+            "x": torch.empty(S, self.n, **f64), "xi": torch.empty(S, self.ng, **f64),
+            "z_g": torch.empty(S, self.ng, **f64), "y_f": torch.empty(S, self.nx, **f64),
+            "y_g": torch.empty(S, self.ng, **f64), "status": torch.empty(B, **i32),
+            "admm_iters": torch.empty(B, **i32), "sqp_iters": torch.empty(B, **i32),
+            "n_factor": torch.empty(B, **i32), "r_prim": torch.empty(B, **f64), "r_dual": torch.empty(B, **f64),
+            "rho": torch.empty(B, **f64), "sqp_kkt": torch.empty(B, 3, **f64),
+        }
+
+    def solve(self, settings=None, out=None, sync=True, **overrides):
+        s = settings if settings is not None else A.default_settings(**overrides)
+        out = out if out is not None else self.alloc_solution()
+        sol = A.ocp_solution(*[(out[k].data_ptr() if out.get(k) is not None else None) for k, _ in
+                               A.ocp_solution._fields_])
+        A.check(self.lib.ocp_solve(self.h, C.byref(s), C.byref(sol), _stream()), "ocp_solve")
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        return out
+
+    def solve_raw(self, settings, sol_struct):
+        """Launch a solve with a prebuilt ocp_solution (no allocation, no sync)."""
+        A.check(self.lib.ocp_solve(self.h, C.byref(settings), C.byref(sol_struct), _stream()), "ocp_solve")
+
+    def adjoint(self, dL_dx, settings=None, **overrides):
+        s = settings if settings is not None else A.default_settings(**overrides)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        g = {"d_q": torch.empty(self.S, self.n, **f64), "d_Ddiag": torch.empty(self.S, self.n, **f64),
+             "d_x_init": torch.empty(self.B, self.nx, **f64), "d_lo": torch.empty(self.S, self.ng, **f64),
+             "d_hi": torch.empty(self.S, self.ng, **f64), "eta_x": torch.empty(self.S, self.n, **f64),
+             "active": torch.empty(self.S, self.ng, dtype=torch.int8, device=self.device)}
+        gs = A.ocp_qp_grads(*[g[k].data_ptr() for k, _ in A.ocp_qp_grads._fields_])
+        dl = _dev(dL_dx)
+        A.check(self.lib.ocp_adjoint(self.h, C.byref(s), C.c_void_p(dl.data_ptr()), C.byref(gs), _stream()),
+                "ocp_adjoint")
+        torch.cuda.current_stream().synchronize()
+        return g
+
+    def split(self, arr, i):
+        """Rows of a stage-concatenated array that belong to instance i."""
+        return arr[int(self.stage_off[i]):int(self.stage_off[i + 1])]
