@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark: gated QP solves/s of the batched ADMM OCP-QP path on one MI355X.
+
+One step = one pass of the hot path over the batch: for every instance the
+FP64 block factorisation, the ADMM iterations (FP32 over the FP64 factor, or
+plain FP64), the rho adaptations with their refactorisations and the FP64
+stopping test; and, once the adjoint is available, the implicit-gradient
+solve ("+grad").  An instance counts as solved only if its FP64-evaluated
+residuals pass the stopping test at eps_abs = eps_rel = 1e-4.
+
+Prints ONE JSON line (rank 0).  Details go to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X vector FP32 (published)
+PEAK_FP64 = 78.6   # TFLOP/s, MI355X vector FP64 (published)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# algorithmic work per unit ("Measurement")
+# ---------------------------------------------------------------------------
+def lti_flops_per_stage(nx, nu, ng):
+    """(FP32-path flops per stage per ADMM iteration, FP64 flops per stage per
+    factorisation) for the LTI layout A^- = [A B] dense, A^+ = [-I 0], G a
+    0/1 selection with ng rows."""
+    n = nx + nu
+    nnz = nx * n + nx + ng
+    f_eta = 2 * nnz + 6 * (nx + ng + n)
+    f_sub = 2 * (2 * n * n + n * (n + 1))
+    f_az = 2 * nnz
+    f_elem = 12 * ng + 6 * nx + 4 * n
+    f_it = f_eta + f_sub + f_az + f_elem
+    f_fac = 2 * nx * n * n + 2 * nx * n + n ** 3 + n ** 3 / 3 + n ** 3 / 3 + n ** 3
+    return f_it, f_fac
+
+
+def make_workload(name):
+    from workloads import random_lti
+
+    if name == "c2":
+        b = random_lti(1024, N=50, nx=12, nu=4, seed=2)
+        desc = ("batched linear MPC: 1024 random LTI instances, nx=12, nu=4, N=50, "
+                "A=I+0.1G (spectral radius of G 1.05), x in [-10,10], u in [-1,1]")
+        return b, desc
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(batch, sample, settings_kw):
+    """The FP64 oracle on the host cores, one instance per task."""
+    import multiprocessing as mp
+
+    global _CPU_BATCH
+    _CPU_BATCH = batch
+    cores = min(len(os.sched_getaffinity(0)), 16, sample)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores, initializer=_worker_init) as pool:
+        res = pool.map(_oracle_one, [(i, settings_kw) for i in range(sample)])
+    wall = time.perf_counter() - t0
+    solved = sum(1 for ok, _ in res if ok)
+    iters = sum(it for _, it in res)
+    return {"value": solved / wall, "unit": "QP solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {sample} of {batch.batch} instances, FP64 NumPy/SciPy oracle, eps 1e-4",
+            "solved": solved, "wall_s": round(wall, 3), "admm_iters_per_s": iters / wall}
+
+
+def _worker_init():
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+
+
+_CPU_BATCH = None
+
+
+def _oracle_one(args):
+    i, kw = args
+    batch = _CPU_BATCH
+    from oracle.admm import ADMMSettings, admm_solve
+    from oracle.qp import lti_batch_qp
+
+    r = admm_solve(lti_batch_qp(batch, i), ADMMSettings(**kw))
+    return r.status == 0, r.iters
+
+
+def run_gpu(batch, precision, steps, warmup, settings_kw):
+    import torch
+
+    from paper_2606_24039_amd import _abi as A
+    from paper_2606_24039_amd.solver import OCPSolver
+
+    hz = np.full(batch.batch, batch.N)
+    s = OCPSolver(batch.nx, batch.nu, batch.ng, hz, model=A.MODEL_LTI, precision=precision)
+    s.set_lti(batch.A, batch.B, batch.Qd, batch.Rd, batch.Qfd, batch.G, batch.lo, batch.hi, batch.x0)
+    st = A.default_settings(**settings_kw)
+    out = s.alloc_solution()
+    sol = s.solution_struct(out)
+    stream = torch.cuda.current_stream()
+
+    def step(ev0=None, ev1=None):
+        if ev0 is not None:
+            ev0.record(stream)
+        s.solve_raw(st, None)  # exactly one kernel: the persistent ADMM solve
+        if ev1 is not None:
+            ev1.record(stream)
+        A.check(s.lib.ocp_get_solution(s.h, A.C.byref(sol), A.C.c_void_p(stream.cuda_stream)), "get_solution")
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(*evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    status = out["status"].cpu().numpy()
+    iters = out["admm_iters"].cpu().numpy()
+    nfact = out["n_factor"].cpu().numpy()
+    solved = int((status == 0).sum())
+    res = {"wall_s": wall, "ms_per_step": wall / steps * 1e3, "kernel_ms": kern_ms, "solved": solved,
+           "batch": batch.batch, "iters_mean": float(iters.mean()), "iters_sum": int(iters.sum()),
+           "nfact_sum": int(nfact.sum()), "status_counts": {int(k): int(v) for k, v in
+                                                           zip(*np.unique(status, return_counts=True))}}
+    s.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--cpu-sample", type=int, default=96, help="instances timed on the oracle (0 = skip)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the batched solve has no "
+                                   "cross-GPU exchange; run one process per GPU on disjoint instance shards"}))
+        sys.exit(2)
+
+    batch, desc = make_workload(args.workload)
+    settings_kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_admm=1000, k_check=25, k_rho=25)
+    f_it, f_fac = lti_flops_per_stage(batch.nx, batch.nu, batch.ng)
+    stages = batch.N + 1
+
+    log(f"[bench] workload: {desc}")
+    mixed = run_gpu(batch, 1, args.steps, args.warmup, settings_kw)
+    log(f"[bench] mixed: {json.dumps(mixed)}")
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_gpu(batch, 0, max(3, args.steps // 4), 1, settings_kw)
+        log(f"[bench] fp64: {json.dumps(fp64)}")
+
+    value = mixed["solved"] / (mixed["ms_per_step"] * 1e-3)
+    # roofline of the dominant kernel (the persistent ADMM solve), per launch
+    F32 = mixed["iters_sum"] * stages * f_it
+    F64 = mixed["nfact_sum"] * stages * f_fac
+    t = mixed["kernel_ms"] * 1e-3
+    achieved = (F32 + F64 * PEAK_FP32 / PEAK_FP64) / t / 1e12  # FP32-equivalent TFLOP/s
+    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32, 6), "traffic": None,
+            "kernel": "admm_solve_kernel<float,12,4,16,TI>", "kernel_ms": round(mixed["kernel_ms"], 4),
+            "flops_fp32_per_launch": F32, "flops_fp64_per_launch": F64,
+            "note": "FP64 flops weighted by the FP32/FP64 peak ratio"}
+    out = {
+        "metric": "QP solves/s at 1e-4 KKT residual, FP32+grad vs plain FP64, 1 MI355X",
+        "value": round(value, 2), "unit": "QP solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(mixed["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": desc, "batch": batch.batch, "horizon": batch.N, "nx": batch.nx, "nu": batch.nu,
+                   "ng": batch.ng, "precision": "fp32 ADMM iterations, fp64 factorisation and gate",
+                   "eps": 1e-4, "grad": False, "parallelism": "single GPU, one instance per 16-lane row"},
+        "admm_iters_per_s": round(mixed["iters_sum"] / (mixed["ms_per_step"] * 1e-3), 1),
+        "solved_fraction": mixed["solved"] / batch.batch,
+        "roofline": roof,
+    }
+    if fp64 is not None:
+        out["fp64"] = {"value": round(fp64["solved"] / (fp64["ms_per_step"] * 1e-3), 2),
+                       "ms_per_step": round(fp64["ms_per_step"], 4), "kernel_ms": round(fp64["kernel_ms"], 4),
+                       "solved_fraction": fp64["solved"] / batch.batch, "iters_mean": fp64["iters_mean"]}
+        out["speedup_vs_fp64"] = round(value / max(out["fp64"]["value"], 1e-9), 3)
+    if args.cpu_sample > 0:
+        cb_kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_iter=1000, k_check=25, k_rho=25)
+        out["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_sample, batch.batch), cb_kw)
+        log(f"[bench] cpu: {json.dumps(out['cpu_baseline'])}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

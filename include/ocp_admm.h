@@ -110,7 +110,7 @@ typedef struct {
  * time_invariant = 1: D [2B,n,n] (interior, terminal), E [B,n,n],
  *   Am, Ap [B,nx,n], b [B,nx], G [B,ng,n], lo, hi [B,ng]; q stays [S,n].
  * E, q and b may be NULL (zero).  x_init [B,nx].  soft [ng] (uint8 row
- * kinds, host or device not allowed: DEVICE pointer) may be NULL (all hard).
+ * kinds, DEVICE pointer) may be NULL (all rows hard).
  * gamma2: L2 slack weight (gamma/2 ||xi||^2); gamma1: L1 slack weight. */
 typedef struct {
   const double *D, *E, *q, *Am, *Ap, *b, *G, *lo, *hi, *x_init;
@@ -187,6 +187,10 @@ ocp_status ocp_set_bicycle(ocp_handle h, const ocp_bicycle* p, void* stream);
  * the line-search step (Appendix "Line search").  Writes `out` (may be
  * NULL to keep the state only in the workspace). */
 ocp_status ocp_solve(ocp_handle h, const ocp_settings* s, const ocp_solution* out, void* stream);
+
+/* Copy the handle's current solution (last ocp_solve) into `out` without
+ * solving again.  Errors: OCP_E_ORDER before a solve. */
+ocp_status ocp_get_solution(ocp_handle h, const ocp_solution* out, void* stream);
 
 /* Implicit-differentiation VJP at the last solution (Algorithm 2, eq.
  * bwd:noslack_kkt_matrix / loss_gradient): identify the active set, factor

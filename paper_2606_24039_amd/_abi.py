@@ -69,6 +69,7 @@ SIGNATURES = [
     ("ocp_set_qp", C.c_int, [C.c_void_p, C.POINTER(ocp_qp), C.c_void_p]),
     ("ocp_set_bicycle", C.c_int, [C.c_void_p, C.POINTER(ocp_bicycle), C.c_void_p]),
     ("ocp_solve", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.POINTER(ocp_solution), C.c_void_p]),
+    ("ocp_get_solution", C.c_int, [C.c_void_p, C.POINTER(ocp_solution), C.c_void_p]),
     ("ocp_adjoint", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_void_p, C.POINTER(ocp_qp_grads),
                               C.c_void_p]),
 ]

@@ -592,6 +592,12 @@ ocp_status ocp_solve(ocp_handle h, const ocp_settings* s, const ocp_solution* ou
   return copy_out(h, out, stream_);
 }
 
+ocp_status ocp_get_solution(ocp_handle h, const ocp_solution* out, void* stream) {
+  if (!h || !out) return OCP_E_ARG;
+  if (!h->solved) return OCP_E_ORDER;
+  return copy_out(h, out, (hipStream_t)stream);
+}
+
 ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const ocp_qp_grads* out,
                        void* stream) {
   if (!h || !s || !dL_dx || !out) return OCP_E_ARG;

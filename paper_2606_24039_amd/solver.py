@@ -116,9 +116,22 @@ class OCPSolver:
             torch.cuda.current_stream().synchronize()
         return out
 
+    def solution_struct(self, out):
+        return A.ocp_solution(*[(out[k].data_ptr() if out.get(k) is not None else None) for k, _ in
+                                A.ocp_solution._fields_])
+
+    def get_solution(self, out=None, sync=True):
+        out = out if out is not None else self.alloc_solution()
+        sol = self.solution_struct(out)
+        A.check(self.lib.ocp_get_solution(self.h, C.byref(sol), _stream()), "ocp_get_solution")
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        return out
+
     def solve_raw(self, settings, sol_struct):
         """Launch a solve with a prebuilt ocp_solution (no allocation, no sync)."""
-        A.check(self.lib.ocp_solve(self.h, C.byref(settings), C.byref(sol_struct), _stream()), "ocp_solve")
+        A.check(self.lib.ocp_solve(self.h, C.byref(settings), C.byref(sol_struct) if sol_struct is not None else None,
+                                   _stream()), "ocp_solve")
 
     def adjoint(self, dL_dx, settings=None, **overrides):
         s = settings if settings is not None else A.default_settings(**overrides)
