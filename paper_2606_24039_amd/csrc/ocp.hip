@@ -28,23 +28,25 @@ template <typename T, int NX, int NU, int NG, bool TI>
 void launch_solve(const Layout& L, const Settings& s, int grid, hipStream_t st) {
   hipLaunchKernelGGL((admm_solve_kernel<T, NX, NU, NG, TI>), dim3(grid), dim3(64), 0, st, L, s);
 }
-template <int NX, int NU, int NG, bool TI>
+template <typename T, int NX, int NU, int NG, bool TI>
 void launch_adjoint(const Layout& L, const AdjArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((adjoint_kernel<NX, NU, NG, TI>), dim3(grid), dim3(64), 0, st, L, a);
+  hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG, TI>), dim3(grid), dim3(64), 0, st, L, a);
 }
 
 struct Entry {
   int nx, nu, ng;
   SolveFn f64[2];  // [ti]
   SolveFn f32[2];
-  AdjFn adj[2];
+  AdjFn adj64[2];
+  AdjFn adj32[2];
 };
 
 #define OCP_ENTRY(NX, NU, NG)                                                                       \
   Entry {                                                                                           \
     NX, NU, NG, {launch_solve<double, NX, NU, NG, false>, launch_solve<double, NX, NU, NG, true>},  \
         {launch_solve<float, NX, NU, NG, false>, launch_solve<float, NX, NU, NG, true>},            \
-        {launch_adjoint<NX, NU, NG, false>, launch_adjoint<NX, NU, NG, true>},                      \
+        {launch_adjoint<double, NX, NU, NG, false>, launch_adjoint<double, NX, NU, NG, true>},      \
+        {launch_adjoint<float, NX, NU, NG, false>, launch_adjoint<float, NX, NU, NG, true>},        \
   }
 
 const Entry kTable[] = {
@@ -99,7 +101,8 @@ struct ocp_handle_s {
 
   // adjoint scratch (FP64, padded [S][ROW])
   double *adj_rhog = nullptr, *adj_ex = nullptr, *adj_ey = nullptr, *adj_eg = nullptr, *adj_r = nullptr;
-  double* adj_v = nullptr;
+  double *adj_v = nullptr, *adj_rg = nullptr;
+  uint8_t soft_host[16] = {0};
   int8_t* adj_act = nullptr;
 
   size_t tsz() const { return mixed ? sizeof(float) : sizeof(double); }
@@ -224,6 +227,7 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   A_(h->adj_eg, sizeof(double) * ROW * S);
   A_(h->adj_r, sizeof(double) * ROW * S);
   A_(h->adj_v, sizeof(double) * ROW * S);
+  A_(h->adj_rg, sizeof(double) * ROW * S);
   A_(h->adj_act, sizeof(int8_t) * ROW * S);
 #undef A_
   if (count_only) return OCP_OK;
@@ -505,6 +509,7 @@ ocp_status ocp_set_lti(ocp_handle h, const ocp_lti* p, void* stream) {
                      p->Bm, p->Qd, p->Rd, p->Qfd, p->G, p->lo, p->hi, p->x0, h->D, h->Am, h->Ap, h->G, h->lo, h->hi,
                      h->xinit);
   h->has_E = h->has_q = h->has_bd = false;
+  std::memset(h->soft_host, 0, sizeof(h->soft_host));
   if (hipMemsetAsync(h->soft, 0, 16, st) != hipSuccess) return OCP_E_HIP;
   refresh_copies(h, st);
   h->data_set = true;
@@ -536,10 +541,16 @@ ocp_status ocp_set_qp(ocp_handle h, const ocp_qp* p, void* stream) {
   if (p->E) ok = ok && cp(h->E, p->E, sizeof(double) * nn * blkI);
   if (p->q) ok = ok && cp(h->q, p->q, sizeof(double) * n * (size_t)h->S);
   if (p->b) ok = ok && cp(h->bd, p->b, sizeof(double) * nx * blkI);
-  if (p->soft)
-    ok = ok && cp(h->soft, p->soft, (size_t)ng);
-  else
+  std::memset(h->soft_host, 0, sizeof(h->soft_host));
+  if (p->soft) {
+    ok = ok && cp(h->soft, p->soft, (size_t)ng) &&
+         hipMemcpyAsync(h->soft_host, p->soft, (size_t)ng, hipMemcpyDeviceToHost, st) == hipSuccess &&
+         hipStreamSynchronize(st) == hipSuccess;
+    for (int r = 0; r < ng && ok; ++r)
+      if (h->soft_host[r] > OCP_ROW_L1) return OCP_E_ARG;
+  } else {
     ok = ok && hipMemsetAsync(h->soft, 0, 16, st) == hipSuccess;
+  }
   if (!ok) return OCP_E_HIP;
   h->gamma2 = p->gamma2;
   h->gamma1 = p->gamma1;
@@ -568,6 +579,7 @@ ocp_status ocp_set_bicycle(ocp_handle h, const ocp_bicycle* p, void* stream) {
   h->has_q = true;
   h->has_bd = true;
   const uint8_t kinds[16] = {OCP_ROW_HARD, OCP_ROW_HARD, OCP_ROW_L1};
+  std::memcpy(h->soft_host, kinds, sizeof(kinds));
   if (hipMemcpyAsync(h->soft, kinds, 16, hipMemcpyHostToDevice, st) != hipSuccess) return OCP_E_HIP;
   if (hipStreamSynchronize(st) != hipSuccess) return OCP_E_HIP;  // `kinds` is a host stack array
   h->data_set = true;
@@ -602,8 +614,40 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
                        void* stream) {
   if (!h || !s || !dL_dx || !out) return OCP_E_ARG;
   if (!h->solved) return OCP_E_ORDER;
-  (void)stream;
-  return OCP_E_UNSUPPORTED;
+  for (int r = 0; r < h->d.ng; ++r)
+    if (h->soft_host[r] == OCP_ROW_L2) return OCP_E_UNSUPPORTED;
+  if (!(s->adj_sigma > 0) || !(s->adj_rho > 0) || !(s->eps_active > 0) || s->refine_sweeps < 1) return OCP_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  AdjArgs a{};
+  a.dLdx = dL_dx;
+  a.sigma_b = s->adj_sigma;
+  a.rho_b = s->adj_rho;
+  a.eps_active = s->eps_active;
+  a.sweeps = s->refine_sweeps;
+  a.w = h->adj_rhog;
+  a.ex = h->adj_ex;
+  a.ef = h->adj_ey;
+  a.eg = h->adj_eg;
+  a.rf = h->adj_r;
+  a.rg = h->adj_rg;
+  a.v = h->adj_v;
+  a.act = h->adj_act;
+  a.d_q = out->d_q;
+  a.d_Ddiag = out->d_Ddiag;
+  a.d_x_init = out->d_x_init;
+  a.d_lo = out->d_lo;
+  a.d_hi = out->d_hi;
+  a.eta_x = out->eta_x;
+  a.active = out->active;
+  Layout L = make_layout(h);
+  const int grid = (h->B + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
+  const int ti = h->ti ? 1 : 0;
+  if (h->mixed)
+    h->entry->adj32[ti](L, a, grid, st);
+  else
+    h->entry->adj64[ti](L, a, grid, st);
+  // the factor now holds the adjoint system: the next solve refactors from scratch
+  return hip_ok(hipGetLastError());
 }
 
 }  // extern "C"
