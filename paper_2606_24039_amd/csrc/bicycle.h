@@ -1,12 +1,413 @@
-// Kinematic-bicycle SQP kernels.
+// Kinematic-bicycle SQP kernels (Algorithm 1): convexification of the OCP at
+// the current iterate (Appendix "QP Approximation"), backtracking line search
+// on the L1 merit (Appendix "Line search") and the stopping quantities of
+// eq. sqp_stop.
+//
+// Model: state (px, py, yaw, v), control (a, delta), wheelbase Lw,
+//   fc(x, u) = (v cos yaw, v sin yaw, v tan(delta) / Lw, a),
+// implicit midpoint with zero-order hold on u:
+//   f_t = x_t + dt fc((x_t + x_{t+1}) / 2, u_t) - x_{t+1},
+//   A_t^- = [I + dt/2 Jx, dt Ju],  A_t^+ = [-I + dt/2 Jx, 0]  (at the midpoint).
+// Cost 1/2 (x_t - r_t)'Q(x_t - r_t) + 1/2 u_t'R u_t (Q_f at t = N); in the
+// absolute-coordinate QP q_t = grad l_t(xbar_t) - D_t xbar_t = -D_t (r_t, 0).
+// Rows g_t = (a_t, delta_t, n_t'(p_t - p_ref,t)): a, delta hard, lateral L1.
 #pragma once
+
 #include "admm.h"
+
 namespace ocpk {
-struct BikeArgs {
-  int dummy;
-};
+
 __global__ void fill_i32_kernel(int32_t* p, int n, int v) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = v;
 }
+
+struct BikeArgs {
+  const double* ref;     // [S][4]
+  const double* normal;  // [S][2]
+  const double* x0;      // [B][4]
+  const int32_t* stage_inst;  // [S] instance of each global stage
+  double dt, Lw, a_b, d_b, lat_b, gamma1;
+  double Qd[4], Rd[2], Qfd[4];
+  // SQP state (FP64, padded [S][ROW])
+  double* xbar;
+  double* xibar;
+  double* yfbar;
+  double* ygbar;
+  double* mu;       // [B] merit penalty
+  double* kkt;      // [B][3]
+  int32_t* done;    // [B] SQP iterations taken
+  int32_t* frozen;  // [B] 1 once converged (only when not running a fixed count)
+  double eps_c, armijo_eta;
+  int fixed;
+};
+
+struct BikeDeriv {
+  double f[4];
+  double Jx[4][4];
+  double Ju[4][2];
+};
+
+__device__ __forceinline__ void bike_fc(const double* x, const double* u, double Lw, double* out) {
+  out[0] = x[3] * cos(x[2]);
+  out[1] = x[3] * sin(x[2]);
+  out[2] = x[3] * tan(u[1]) / Lw;
+  out[3] = u[0];
+}
+
+// midpoint residual f_t and its Jacobian blocks at (xt, ut, xn)
+__device__ __forceinline__ void bike_midpoint(const double* xt, const double* ut, const double* xn, double dt,
+                                              double Lw, double* f, double (*Am)[6], double (*Ap)[6]) {
+  double m[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) m[k] = 0.5 * (xt[k] + xn[k]);
+  const double c = cos(m[2]), s = sin(m[2]), tn = tan(ut[1]), cd = cos(ut[1]);
+  const double fc[4] = {m[3] * c, m[3] * s, m[3] * tn / Lw, ut[0]};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) f[k] = xt[k] + dt * fc[k] - xn[k];
+  if (!Am) return;
+  double Jx[4][4] = {{0, 0, -m[3] * s, c}, {0, 0, m[3] * c, s}, {0, 0, 0, tn / Lw}, {0, 0, 0, 0}};
+  double Ju[4][2] = {{0, 0}, {0, 0}, {0, m[3] / (Lw * cd * cd)}, {1, 0}};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Am[r][k] = (r == k ? 1.0 : 0.0) + 0.5 * dt * Jx[r][k];
+      Ap[r][k] = (r == k ? -1.0 : 0.0) + 0.5 * dt * Jx[r][k];
+    }
+    Am[r][4] = dt * Ju[r][0];
+    Am[r][5] = dt * Ju[r][1];
+    Ap[r][4] = 0.0;
+    Ap[r][5] = 0.0;
+  }
+}
+
+// SQP initial guess: the reference with zero controls.
+__global__ void bike_init_kernel(Layout L, BikeArgs a, double rho0) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < (int64_t)L.B) {
+    a.mu[s] = 0.0;
+    a.done[s] = 0;
+    a.frozen[s] = 0;
+    L.rho[s] = rho0;
+  }
+  const int64_t S = L.stage_off[L.B];
+  if (s >= S) return;
+#pragma unroll
+  for (int k = 0; k < ROW; ++k) {
+    a.xbar[s * ROW + k] = (k < 4) ? a.ref[s * 4 + k] : 0.0;
+    a.xibar[s * ROW + k] = 0.0;
+    a.yfbar[s * ROW + k] = 0.0;
+    a.ygbar[s * ROW + k] = 0.0;
+  }
+}
+
+// Convexify at xbar (one thread per global stage) and warm-start the ADMM
+// state from the SQP iterate: x = xbar, y = ybar, z_g = G xbar.
+template <typename T>
+__global__ void bike_linearize_kernel(Layout L, BikeArgs a) {
+  const int64_t S = L.stage_off[L.B];
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const int b = a.stage_inst[s];
+  const int64_t s0 = L.stage_off[b];
+  const int t = (int)(s - s0);
+  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+  const double* xb = a.xbar + s * ROW;
+  double* D = const_cast<double*>(L.D) + s * 36;
+  double* q = const_cast<double*>(L.q) + s * 6;
+  const double* Wq = (t == N) ? a.Qfd : a.Qd;
+#pragma unroll
+  for (int k = 0; k < 36; ++k) D[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    D[k * 6 + k] = Wq[k];
+    q[k] = -Wq[k] * a.ref[s * 4 + k];
+  }
+  D[4 * 6 + 4] = a.Rd[0];
+  D[5 * 6 + 5] = a.Rd[1];
+  q[4] = q[5] = 0.0;
+  double* Am = const_cast<double*>(L.Am) + s * 24;
+  double* Ap = const_cast<double*>(L.Ap) + s * 24;
+  double* bd = const_cast<double*>(L.bd) + s * 4;
+  if (t < N) {
+    const double* xn = a.xbar + (s + 1) * ROW;
+    double f[4], Ml[4][6], Mr[4][6];
+    bike_midpoint(xb, xb + 4, xn, a.dt, a.Lw, f, Ml, Mr);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double acc = -f[r];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        Am[r * 6 + k] = Ml[r][k];
+        Ap[r * 6 + k] = Mr[r][k];
+        acc += Ml[r][k] * xb[k] + Mr[r][k] * xn[k];
+      }
+      bd[r] = acc;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) Am[k] = Ap[k] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bd[r] = 0.0;
+  }
+  double* G = const_cast<double*>(L.G) + s * 18;
+  double* lo = const_cast<double*>(L.lo) + s * 3;
+  double* hi = const_cast<double*>(L.hi) + s * 3;
+  const double nx_ = a.normal[s * 2], ny_ = a.normal[s * 2 + 1];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) G[k] = 0.0;
+  G[0 * 6 + 4] = 1.0;
+  G[1 * 6 + 5] = 1.0;
+  G[2 * 6 + 0] = nx_;
+  G[2 * 6 + 1] = ny_;
+  const double np = nx_ * a.ref[s * 4] + ny_ * a.ref[s * 4 + 1];
+  lo[0] = -a.a_b;
+  hi[0] = a.a_b;
+  lo[1] = -a.d_b;
+  hi[1] = a.d_b;
+  lo[2] = -a.lat_b + np;
+  hi[2] = a.lat_b + np;
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) const_cast<double*>(L.x_init)[(size_t)b * 4 + k] = a.x0[(size_t)b * 4 + k];
+  }
+  // iteration-precision copies
+  if constexpr (!std::is_same<T, double>::value) {
+    T* AmT = (T*)L.AmT + s * 24;
+    T* ApT = (T*)L.ApT + s * 24;
+    T* GT = (T*)L.GT + s * 18;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+      AmT[k] = T(Am[k]);
+      ApT[k] = T(Ap[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 18; ++k) GT[k] = T(G[k]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ((T*)L.qT)[s * 6 + k] = T(q[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ((T*)L.bdT)[s * 4 + k] = T(bd[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ((T*)L.loT)[s * 3 + k] = T(lo[k]);
+      ((T*)L.hiT)[s * 3 + k] = T(hi[k]);
+    }
+    if (t == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ((T*)L.xinitT)[(size_t)b * 4 + k] = T(a.x0[(size_t)b * 4 + k]);
+    }
+  }
+  // warm start of the ADMM state
+  T* X = (T*)L.x + s * ROW;
+  T* YF = (T*)L.yf + s * ROW;
+  T* YG = (T*)L.yg + s * ROW;
+  T* ZG = (T*)L.zg + s * ROW;
+  T* XI = (T*)L.xi + s * ROW;
+#pragma unroll
+  for (int k = 0; k < ROW; ++k) {
+    X[k] = T(xb[k]);
+    YF[k] = T(a.yfbar[s * ROW + k]);
+    YG[k] = T(a.ygbar[s * ROW + k]);
+    XI[k] = T(0);
+    ZG[k] = T(0);
+  }
+  ZG[0] = T(xb[4]);
+  ZG[1] = T(xb[5]);
+  ZG[2] = T(nx_ * xb[0] + ny_ * xb[1]);
+}
+
+// Per-stage pieces of the merit at z = xbar + alpha (x* - xbar).
+struct MeritPart {
+  double cost, viol;
+};
+
+__device__ __forceinline__ void bike_point(const BikeArgs& a, const double* xb, const double* dx, double al,
+                                           double* z) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) z[k] = xb[k] + al * dx[k];
+}
+
+// Line search and SQP bookkeeping for one instance per 16-lane row.  Lane i
+// handles the stages t = i, i+16, ...; per-candidate sums use row reductions.
+template <typename T>
+__global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs a) {
+  constexpr int NA = 8;  // alpha in {1, 1/2, ..., 1/128}
+  const int lane = threadIdx.x & (ROW - 1);
+  const int slot = blockIdx.x * ROWS_PER_WAVE + (threadIdx.x >> 4);
+  if (slot >= L.B) return;
+  const int b = L.order ? L.order[slot] : slot;
+  if (a.frozen[b]) return;
+  const int64_t s0 = L.stage_off[b];
+  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+  const T* XS = (const T*)L.x;
+  const T* XIS = (const T*)L.xi;
+  const T* YFS = (const T*)L.yf;
+  const T* YGS = (const T*)L.yg;
+  const double* x0 = a.x0 + (size_t)b * 4;
+
+  double cost[NA + 1], viol[NA + 1];
+#pragma unroll
+  for (int j = 0; j <= NA; ++j) cost[j] = viol[j] = 0.0;
+  double gdir = 0.0;
+  for (int t = lane; t <= N; t += ROW) {
+    const int64_t s = s0 + t;
+    double xb[6], dx[6], xbn[6], dxn[6];
+    const double xib = a.xibar[s * ROW + 2];
+    const double dxi = double(XIS[s * ROW + 2]) - xib;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      xb[k] = a.xbar[s * ROW + k];
+      dx[k] = double(XS[s * ROW + k]) - xb[k];
+    }
+    if (t < N) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        xbn[k] = a.xbar[(s + 1) * ROW + k];
+        dxn[k] = double(XS[(s + 1) * ROW + k]) - xbn[k];
+      }
+    }
+    const double* W = (t == N) ? a.Qfd : a.Qd;
+    const double* r = a.ref + s * 4;
+    const double nx_ = a.normal[s * 2], ny_ = a.normal[s * 2 + 1];
+    const double gconst = -(nx_ * r[0] + ny_ * r[1]);
+    // directional derivative of cost + slack penalty at xbar
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gdir += W[k] * (xb[k] - r[k]) * dx[k];
+    gdir += a.Rd[0] * xb[4] * dx[4] + a.Rd[1] * xb[5] * dx[5];
+    gdir += a.gamma1 * ((xib != 0.0) ? (xib > 0 ? dxi : -dxi) : fabs(dxi));
+#pragma unroll
+    for (int j = 0; j <= NA; ++j) {
+      const double al = (j == 0) ? 0.0 : ldexp(1.0, -(j - 1));
+      double z[6], zn[6];
+      bike_point(a, xb, dx, al, z);
+      const double xi = xib + al * dxi;
+      double c = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c += 0.5 * W[k] * (z[k] - r[k]) * (z[k] - r[k]);
+      c += 0.5 * (a.Rd[0] * z[4] * z[4] + a.Rd[1] * z[5] * z[5]) + a.gamma1 * fabs(xi);
+      double v = 0.0;
+      if (t < N) {
+        bike_point(a, xbn, dxn, al, zn);
+        double f[4];
+        bike_midpoint(z, z + 4, zn, a.dt, a.Lw, f, nullptr, nullptr);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v += fabs(f[k]);
+      }
+      if (t == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v += fabs(z[k] - x0[k]);
+      }
+      const double g0 = z[4], g1 = z[5], g2 = nx_ * z[0] + ny_ * z[1] + gconst + xi;
+      v += fmax(g0 - a.a_b, 0.0) + fmax(-a.a_b - g0, 0.0) + fmax(g1 - a.d_b, 0.0) + fmax(-a.d_b - g1, 0.0) +
+           fmax(g2 - a.lat_b, 0.0) + fmax(-a.lat_b - g2, 0.0);
+      cost[j] += c;
+      viol[j] += v;
+    }
+  }
+  gdir = row_sum(gdir);
+#pragma unroll
+  for (int j = 0; j <= NA; ++j) {
+    cost[j] = row_sum(cost[j]);
+    viol[j] = row_sum(viol[j]);
+  }
+  const double mu = fmax(fmax(a.mu[b], fabs(gdir) / (0.5 * fmax(viol[0], a.eps_c))), 1.0);
+  const double dmu = gdir - mu * viol[0];
+  const double phi0 = cost[0] + mu * viol[0];
+  double alpha = -1.0;
+#pragma unroll
+  for (int j = 1; j <= NA; ++j) {
+    const double al = ldexp(1.0, -(j - 1));
+    const double ph = cost[j] + mu * viol[j];
+    if (alpha < 0.0 && isfinite(ph) && ph <= phi0 + a.armijo_eta * al * dmu) alpha = al;
+  }
+  if (alpha < 0.0) {  // fallback: the finite candidate with the smallest merit (ties: larger alpha)
+    double best = INFINITY;
+    alpha = 0.0;
+#pragma unroll
+    for (int j = 1; j <= NA; ++j) {
+      const double ph = cost[j] + mu * viol[j];
+      if (isfinite(ph) && ph < best) {
+        best = ph;
+        alpha = ldexp(1.0, -(j - 1));
+      }
+    }
+  }
+  // take the step (lane k updates component k of every stage)
+  for (int t = 0; t <= N; ++t) {
+    const int64_t s = s0 + t;
+    const size_t sv = (size_t)s * ROW + lane;
+    if (lane < 6) a.xbar[sv] += alpha * (double(XS[sv]) - a.xbar[sv]);
+    if (lane < 3) {
+      a.xibar[sv] += alpha * (double(XIS[sv]) - a.xibar[sv]);
+      a.ygbar[sv] += alpha * (double(YGS[sv]) - a.ygbar[sv]);
+    }
+    if (lane < 4) a.yfbar[sv] += alpha * (double(YFS[sv]) - a.yfbar[sv]);
+  }
+  // stopping quantities (eq. sqp_stop) at the new iterate
+  double st = 0.0, fe = 0.0, gi = 0.0;
+  for (int t = lane; t <= N; t += ROW) {
+    const int64_t s = s0 + t;
+    const double* xb = a.xbar + s * ROW;
+    const double* W = (t == N) ? a.Qfd : a.Qd;
+    const double* r = a.ref + s * 4;
+    double grad[6];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) grad[k] = W[k] * (xb[k] - r[k]);
+    grad[4] = a.Rd[0] * xb[4];
+    grad[5] = a.Rd[1] * xb[5];
+    const double* yg = a.ygbar + s * ROW;
+    const double nx_ = a.normal[s * 2], ny_ = a.normal[s * 2 + 1];
+    grad[4] += yg[0];
+    grad[5] += yg[1];
+    grad[0] += nx_ * yg[2];
+    grad[1] += ny_ * yg[2];
+    double f[4], Ml[4][6], Mr[4][6];
+    if (t < N) {  // dynamics row t: A_t^-' y
+      const double* yf = a.yfbar + (s + 1) * ROW;
+      bike_midpoint(xb, xb + 4, xb + ROW, a.dt, a.Lw, f, Ml, Mr);
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) grad[k] += Ml[rr][k] * yf[rr];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) fe = fmax(fe, fabs(f[k]));
+    }
+    if (t > 0) {  // dynamics row t-1: A_{t-1}^+' y
+      const double* yf = a.yfbar + s * ROW;
+      const double* xp = xb - ROW;
+      bike_midpoint(xp, xp + 4, xb, a.dt, a.Lw, f, Ml, Mr);
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) grad[k] += Mr[rr][k] * yf[rr];
+    } else {
+      const double* yf = a.yfbar + s * ROW;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        grad[k] += yf[k];
+        fe = fmax(fe, fabs(xb[k] - x0[k]));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) st = fmax(st, fabs(grad[k]));
+    const double xi = a.xibar[s * ROW + 2];
+    const double g0 = xb[4], g1 = xb[5], g2 = nx_ * (xb[0] - r[0]) + ny_ * (xb[1] - r[1]) + xi;
+    gi = fmax(gi, fmax(fmax(g0 - a.a_b, -a.a_b - g0), 0.0));
+    gi = fmax(gi, fmax(fmax(g1 - a.d_b, -a.d_b - g1), 0.0));
+    gi = fmax(gi, fmax(fmax(g2 - a.lat_b, -a.lat_b - g2), 0.0));
+  }
+  st = row_max(st);
+  fe = row_max(fe);
+  gi = row_max(gi);
+  if (lane == 0) {
+    a.mu[b] = mu;
+    a.kkt[(size_t)b * 3 + 0] = st;
+    a.kkt[(size_t)b * 3 + 1] = fe;
+    a.kkt[(size_t)b * 3 + 2] = gi;
+    a.done[b] += 1;
+    if (!a.fixed && st <= a.eps_c && fe <= a.eps_c && gi <= a.eps_c) a.frozen[b] = 1;
+  }
+}
+
 }  // namespace ocpk

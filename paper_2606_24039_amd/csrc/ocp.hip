@@ -98,6 +98,8 @@ struct ocp_handle_s {
   ocp_bicycle bike{};
   double *xbar = nullptr, *xibar = nullptr, *yfbar = nullptr, *ygbar = nullptr, *mu = nullptr, *kkt = nullptr;
   int32_t* sqp_done = nullptr;
+  int32_t* sqp_frozen = nullptr;
+  int32_t* stage_inst = nullptr;
 
   // adjoint scratch (FP64, padded [S][ROW])
   double *adj_rhog = nullptr, *adj_ex = nullptr, *adj_ey = nullptr, *adj_eg = nullptr, *adj_r = nullptr;
@@ -220,6 +222,8 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
     A_(h->mu, sizeof(double) * B);
     A_(h->kkt, sizeof(double) * 3 * B);
     A_(h->sqp_done, sizeof(int32_t) * B);
+    A_(h->sqp_frozen, sizeof(int32_t) * B);
+    A_(h->stage_inst, sizeof(int32_t) * S);
   }
   A_(h->adj_rhog, sizeof(double) * ROW * S);
   A_(h->adj_ex, sizeof(double) * ROW * S);
@@ -249,6 +253,13 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   std::vector<int32_t> ord(B);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return horizons[a] > horizons[c]; });
+  if (h->stage_inst) {
+    std::vector<int32_t> si((size_t)S);
+    for (int b = 0; b < B; ++b)
+      for (int64_t k = off[b]; k < off[b + 1]; ++k) si[(size_t)k] = b;
+    if (hipMemcpy(h->stage_inst, si.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice) != hipSuccess)
+      return OCP_E_HIP;
+  }
   if (hipMemcpy(h->stage_off, off.data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->order, ord.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(h->soft, 0, 16) != hipSuccess || hipMemset(h->rho, 0, sizeof(double) * B) != hipSuccess)
@@ -416,6 +427,65 @@ void run_admm(ocp_handle h, const Settings& s, hipStream_t st) {
     h->entry->f32[ti](L, s, grid, st);
   else
     h->entry->f64[ti](L, s, grid, st);
+}
+
+BikeArgs make_bike(ocp_handle h, const ocp_settings* s) {
+  BikeArgs a{};
+  a.ref = h->bike_ref;
+  a.normal = h->bike_normal;
+  a.x0 = h->bike_x0;
+  a.stage_inst = h->stage_inst;
+  a.dt = h->bike.dt;
+  a.Lw = h->bike.wheelbase;
+  a.a_b = h->bike.a_bound;
+  a.d_b = h->bike.steer_bound;
+  a.lat_b = h->bike.lat_bound;
+  a.gamma1 = h->bike.gamma1;
+  for (int k = 0; k < 4; ++k) {
+    a.Qd[k] = h->bike.Qd[k];
+    a.Qfd[k] = h->bike.Qfd[k];
+  }
+  a.Rd[0] = h->bike.Rd[0];
+  a.Rd[1] = h->bike.Rd[1];
+  a.xbar = h->xbar;
+  a.xibar = h->xibar;
+  a.yfbar = h->yfbar;
+  a.ygbar = h->ygbar;
+  a.mu = h->mu;
+  a.kkt = h->kkt;
+  a.done = h->sqp_done;
+  a.frozen = h->sqp_frozen;
+  a.eps_c = s->eps_c;
+  a.armijo_eta = s->armijo_eta;
+  a.fixed = s->fixed_sqp;
+  return a;
+}
+
+// Algorithm 1 on every instance: linearise at the iterate, solve the QP by
+// ADMM warm-started from it, take the line-search step.
+ocp_status bicycle_sqp(ocp_handle h, const ocp_settings* s, hipStream_t st) {
+  if (s->max_sqp < 1 || !(s->eps_c > 0) || !(s->armijo_eta > 0 && s->armijo_eta < 1)) return OCP_E_ARG;
+  const BikeArgs a = make_bike(h, s);
+  const Layout L = make_layout(h);
+  const int64_t S = h->S;
+  const unsigned gs = (unsigned)((std::max<int64_t>(S, h->B) + 255) / 256);
+  const int grid = (h->B + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
+  if (!(s->warm_start && h->solved)) hipLaunchKernelGGL(bike_init_kernel, dim3(gs), dim3(256), 0, st, L, a, s->rho0);
+  const Settings ad = make_settings(s, 1);
+  for (int k = 0; k < s->max_sqp; ++k) {
+    if (h->mixed) {
+      hipLaunchKernelGGL(bike_linearize_kernel<float>, dim3(gs), dim3(256), 0, st, L, a);
+    } else {
+      hipLaunchKernelGGL(bike_linearize_kernel<double>, dim3(gs), dim3(256), 0, st, L, a);
+    }
+    run_admm(h, ad, st);
+    if (h->mixed) {
+      hipLaunchKernelGGL(bike_linesearch_kernel<float>, dim3(grid), dim3(64), 0, st, L, a);
+    } else {
+      hipLaunchKernelGGL(bike_linesearch_kernel<double>, dim3(grid), dim3(64), 0, st, L, a);
+    }
+  }
+  return hip_ok(hipGetLastError());
 }
 
 }  // namespace
@@ -594,7 +664,8 @@ ocp_status ocp_solve(ocp_handle h, const ocp_settings* s, const ocp_solution* ou
   if (!h->data_set) return OCP_E_ORDER;
   hipStream_t stream_ = (hipStream_t)stream;
   if (h->d.model == OCP_MODEL_BICYCLE) {
-    return OCP_E_UNSUPPORTED;
+    st = bicycle_sqp(h, s, stream_);
+    if (st != OCP_OK) return st;
   } else {
     const int warm = (s->warm_start && h->solved) ? 1 : 0;
     run_admm(h, make_settings(s, warm), stream_);
