@@ -13,6 +13,8 @@
 
 #include <type_traits>
 
+#include "dpp_dot.h"
+
 namespace ocpk {
 
 constexpr int ROW = 16;           // lanes per instance (one DPP row)
@@ -57,14 +59,24 @@ __device__ __forceinline__ T row_sum(T v) {
   return v;
 }
 
-// acc + sum_{k<K} a[k] * (value of lane k)
+// acc + sum_{k<K} a[k] * (value of lane k): one inline-assembly block of K
+// DPP-sourced FMAs (dpp_dot.h)
 template <int K, typename T>
 __device__ __forceinline__ T dotb(const T (&a)[K], T v, T acc) {
-  sfor<0, K>([&](auto k) {
-    constexpr int kk = decltype(k)::value;
-    acc = fma(a[kk], bc<kk>(v), acc);
-  });
-  return acc;
+  return dotb_asm<K>(a, v, acc);
+}
+
+// value of lane `src` (0..15) of this 16-lane row (ds_bpermute)
+__device__ __forceinline__ float row_gather(float v, int src) {
+  const int addr = ((int)(threadIdx.x & ~(ROW - 1)) + src) << 2;
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double row_gather(double v, int src) {
+  const int addr = ((int)(threadIdx.x & ~(ROW - 1)) + src) << 2;
+  const long long u = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(u & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(u >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
 template <int K, typename T>
@@ -133,6 +145,11 @@ struct Layout {
   double* M64;
   void* LinvT;
   void* MT;
+  void* LinvTr;  // iteration-precision transposes: row i = column i of Linv_t / M_t
+  void* MTr;
+  // structure of time-invariant LTI data: G rows are unit selectors
+  int8_t gsel[16];  // variable selected by inequality row r
+  int8_t ginv[16];  // inequality row selecting variable i, or -1
 
   // ADMM state in iteration precision; stage vectors padded to ROW
   void* x;   // [S][ROW]
@@ -149,6 +166,7 @@ struct Layout {
   int32_t* nfact;
   double* rprim;
   double* rdual;
+  unsigned init_blocks;  // grid of the per-entry init kernels
 };
 
 struct Settings {

@@ -26,8 +26,7 @@ __device__ __forceinline__ void cross_row(const double (&a)[R], const double (&b
   sfor<0, C>([&](auto j) {
     constexpr int jj = decltype(j)::value;
     double acc = 0.0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc = fma(a[r], bc<jj>(b[r]), acc);
+    DotC<R, double>::template f<jj>(acc, b, a);
     out[jj] = fma(scale, acc, out[jj]);
   });
 }
@@ -132,6 +131,11 @@ __device__ int factor_instance(const Layout& L, const Group& g, double sigma, do
 #pragma unroll
         for (int j = 0; j < n; ++j) dT[j] = T(X[j]);
       }
+      if (L.LinvTr) {  // transpose: lane i writes column i
+        T* dT = (T*)L.LinvTr + (size_t)s * nn + i;
+#pragma unroll
+        for (int j = 0; j < n; ++j) dT[(size_t)j * n] = T(X[j]);
+      }
     }
     if (t < N) {
       // Phi_t row i = E_t row i + rho_f sum_r A_t^+[r][i] A_t^-[r][:]
@@ -149,11 +153,13 @@ __device__ int factor_instance(const Layout& L, const Group& g, double sigma, do
       // M_{t+1} row i: M[i][j] = sum_{k<=j} Phi[i][k] Linv[j][k]
       sfor<0, n>([&](auto j) {
         constexpr int jj = decltype(j)::value;
-        double acc = 0.0;
-        sfor<0, jj + 1>([&](auto k) {
-          constexpr int kk = decltype(k)::value;
-          acc = fma(Phi[kk], bc<jj>(X[kk]), acc);
-        });
+        double acc = 0.0, xs[jj + 1], ps[jj + 1];
+#pragma unroll
+        for (int k = 0; k <= jj; ++k) {
+          xs[k] = X[k];
+          ps[k] = Phi[k];
+        }
+        DotC<jj + 1, double>::template f<jj>(acc, xs, ps);
         Mrow[jj] = acc;
       });
       if (vi) {
@@ -164,6 +170,11 @@ __device__ int factor_instance(const Layout& L, const Group& g, double sigma, do
           T* dT = (T*)L.MT + (size_t)(s + 1) * nn + (size_t)i * n;
 #pragma unroll
           for (int j = 0; j < n; ++j) dT[j] = T(Mrow[j]);
+        }
+        if (L.MTr) {
+          T* dT = (T*)L.MTr + (size_t)(s + 1) * nn + i;
+#pragma unroll
+          for (int j = 0; j < n; ++j) dT[(size_t)j * n] = T(Mrow[j]);
         }
       }
     }

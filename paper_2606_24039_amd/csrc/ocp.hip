@@ -21,30 +21,60 @@ namespace {
 // ---------------------------------------------------------------------------
 // dispatch table: one instantiation per compiled (nx, nu, ng)
 // ---------------------------------------------------------------------------
-using SolveFn = void (*)(const Layout&, const Settings&, int, hipStream_t);
+using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, int, hipStream_t);
 using AdjFn = void (*)(const Layout&, const AdjArgs&, int, hipStream_t);
 
-template <typename T, int NX, int NU, int NG, bool TI>
-void launch_solve(const Layout& L, const Settings& s, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((admm_solve_kernel<T, NX, NU, NG, TI>), dim3(grid), dim3(64), 0, st, L, s);
+// One ADMM solve: init and factorisation, then up to each boundary (the next
+// multiple of k_check or k_rho, or the cap) the iterations, the FP64 check
+// and, after a rho change, the refactorisation of the instances concerned.
+template <typename T, int NX, int NU, int NG, typename ST>
+void launch_solve(const Layout& L, const Settings& s, int32_t* need, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((admm_init_kernel<T>), dim3(L.init_blocks), dim3(256), 0, st, L, s, need);
+  hipLaunchKernelGGL((admm_factor_kernel<T, NX, NU, NG>), dim3(grid), dim3(64), 0, st, L, s, need);
+  const bool adapt_on = s.adapt_rho && s.k_rho > 0;
+  int k = 0;
+  while (k < s.max_iter) {
+    int nb = s.max_iter;
+    if (s.k_check > 0) nb = std::min(nb, (k / s.k_check + 1) * s.k_check);
+    if (adapt_on) nb = std::min(nb, (k / s.k_rho + 1) * s.k_rho);
+    hipLaunchKernelGGL((admm_iter_kernel<T, NX, NU, NG, ST>), dim3(grid), dim3(64), 0, st, L, s, nb);
+    const int check = (s.k_check > 0 && nb % s.k_check == 0) ? 1 : 0;
+    const int adapt = (adapt_on && nb % s.k_rho == 0 && nb < s.max_iter) ? 1 : 0;
+    const int last = (nb == s.max_iter) ? 1 : 0;
+    if (check || adapt || last)
+      hipLaunchKernelGGL((admm_check_kernel<T, NX, NU, NG>), dim3(grid), dim3(64), 0, st, L, s, need, check, adapt,
+                         last);
+    if (adapt) hipLaunchKernelGGL((admm_factor_kernel<T, NX, NU, NG>), dim3(grid), dim3(64), 0, st, L, s, need);
+    k = nb;
+  }
 }
+
 template <typename T, int NX, int NU, int NG, bool TI>
 void launch_adjoint(const Layout& L, const AdjArgs& a, int grid, hipStream_t st) {
   hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG, TI>), dim3(grid), dim3(64), 0, st, L, a);
 }
 
+// structure variants of the iteration kernel
+enum { VAR_TV = 0, VAR_TI = 1, VAR_LTI_BOX = 2 };
+using StTV = Structure<false, false, false>;
+using StTI = Structure<true, false, false>;
+using StBox = Structure<true, true, true>;
+
 struct Entry {
   int nx, nu, ng;
-  SolveFn f64[2];  // [ti]
-  SolveFn f32[2];
+  SolveFn f64[3];  // [variant]
+  SolveFn f32[3];
   AdjFn adj64[2];
   AdjFn adj32[2];
 };
 
 #define OCP_ENTRY(NX, NU, NG)                                                                       \
   Entry {                                                                                           \
-    NX, NU, NG, {launch_solve<double, NX, NU, NG, false>, launch_solve<double, NX, NU, NG, true>},  \
-        {launch_solve<float, NX, NU, NG, false>, launch_solve<float, NX, NU, NG, true>},            \
+    NX, NU, NG,                                                                                     \
+        {launch_solve<double, NX, NU, NG, StTV>, launch_solve<double, NX, NU, NG, StTI>,            \
+         launch_solve<double, NX, NU, NG, StBox>},                                                  \
+        {launch_solve<float, NX, NU, NG, StTV>, launch_solve<float, NX, NU, NG, StTI>,              \
+         launch_solve<float, NX, NU, NG, StBox>},                                                   \
         {launch_adjoint<double, NX, NU, NG, false>, launch_adjoint<double, NX, NU, NG, true>},      \
         {launch_adjoint<float, NX, NU, NG, false>, launch_adjoint<float, NX, NU, NG, true>},        \
   }
@@ -83,10 +113,12 @@ struct ocp_handle_s {
   void *AmT = nullptr, *ApT = nullptr, *GT = nullptr, *qT = nullptr, *bdT = nullptr;
   void *loT = nullptr, *hiT = nullptr, *xinitT = nullptr;
   double *Linv64 = nullptr, *M64 = nullptr;
-  void *LinvT = nullptr, *MT = nullptr;
+  void *LinvT = nullptr, *MT = nullptr, *LinvTr = nullptr, *MTr = nullptr;
+  int variant = 0;
+  int8_t gsel[16] = {0}, ginv[16] = {0};
   void *x = nullptr, *v = nullptr, *yf = nullptr, *zg = nullptr, *yg = nullptr, *xi = nullptr;
   double *rho = nullptr, *rprim = nullptr, *rdual = nullptr;
-  int32_t *status = nullptr, *iters = nullptr, *nfact = nullptr;
+  int32_t *status = nullptr, *iters = nullptr, *nfact = nullptr, *need = nullptr;
   double gamma2 = 1.0, gamma1 = 1.0;
   bool has_E = false, has_q = false, has_bd = false;
   bool data_set = false, solved = false;
@@ -199,6 +231,8 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   }
   A_(h->Linv64, sizeof(double) * nn * S);
   A_(h->M64, sizeof(double) * nn * S);
+  A_(h->LinvTr, ts * nn * S);
+  A_(h->MTr, ts * nn * S);
   A_(h->x, ts * ROW * S);
   A_(h->v, ts * ROW * S);
   A_(h->yf, ts * ROW * S);
@@ -211,6 +245,7 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   A_(h->status, sizeof(int32_t) * B);
   A_(h->iters, sizeof(int32_t) * B);
   A_(h->nfact, sizeof(int32_t) * B);
+  A_(h->need, sizeof(int32_t) * B);
   if (d->model == OCP_MODEL_BICYCLE) {
     A_(h->bike_ref, sizeof(double) * 4 * S);
     A_(h->bike_normal, sizeof(double) * 2 * S);
@@ -325,6 +360,12 @@ Layout make_layout(ocp_handle h) {
   L.M64 = h->M64;
   L.LinvT = h->LinvT;
   L.MT = h->MT;
+  L.LinvTr = h->LinvTr;
+  L.MTr = h->MTr;
+  for (int k = 0; k < 16; ++k) {
+    L.gsel[k] = h->gsel[k];
+    L.ginv[k] = h->ginv[k];
+  }
   L.x = h->x;
   L.v = h->v;
   L.yf = h->yf;
@@ -337,6 +378,7 @@ Layout make_layout(ocp_handle h) {
   L.nfact = h->nfact;
   L.rprim = h->rprim;
   L.rdual = h->rdual;
+  L.init_blocks = (unsigned)((std::max<int64_t>(h->S * ROW, h->B) + 255) / 256);
   return L;
 }
 
@@ -423,10 +465,11 @@ void run_admm(ocp_handle h, const Settings& s, hipStream_t st) {
   const Layout L = make_layout(h);
   const int grid = (h->B + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
   const int ti = h->ti ? 1 : 0;
+  const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (ti ? VAR_TI : VAR_TV);
   if (h->mixed)
-    h->entry->f32[ti](L, s, grid, st);
+    h->entry->f32[var](L, s, h->need, grid, st);
   else
-    h->entry->f64[ti](L, s, grid, st);
+    h->entry->f64[var](L, s, h->need, grid, st);
 }
 
 BikeArgs make_bike(ocp_handle h, const ocp_settings* s) {
@@ -579,6 +622,29 @@ ocp_status ocp_set_lti(ocp_handle h, const ocp_lti* p, void* stream) {
                      p->Bm, p->Qd, p->Rd, p->Qfd, p->G, p->lo, p->hi, p->x0, h->D, h->Am, h->Ap, h->G, h->lo, h->hi,
                      h->xinit);
   h->has_E = h->has_q = h->has_bd = false;
+  // a G whose rows each select one distinct variable takes the box-bound kernel variant
+  {
+    const int ng = h->d.ng, n = h->n;
+    std::vector<double> Gh((size_t)std::max(ng, 1) * n, 0.0);
+    if (ng > 0 && (hipMemcpyAsync(Gh.data(), p->G, sizeof(double) * ng * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                   hipStreamSynchronize(st) != hipSuccess))
+      return OCP_E_HIP;
+    bool sel = true;
+    int8_t gs[16], gi[16];
+    for (int k = 0; k < 16; ++k) gs[k] = 0, gi[k] = -1;
+    for (int r = 0; r < ng && sel; ++r) {
+      int hit = -1, cnt = 0;
+      for (int c = 0; c < n; ++c) {
+        if (Gh[(size_t)r * n + c] == 1.0) hit = c, ++cnt;
+        else if (Gh[(size_t)r * n + c] != 0.0) cnt = 99;
+      }
+      if (cnt != 1 || gi[hit] != -1) sel = false;
+      else gs[r] = (int8_t)hit, gi[hit] = (int8_t)r;
+    }
+    h->variant = sel ? VAR_LTI_BOX : VAR_TI;
+    std::memcpy(h->gsel, gs, 16);
+    std::memcpy(h->ginv, gi, 16);
+  }
   std::memset(h->soft_host, 0, sizeof(h->soft_host));
   if (hipMemsetAsync(h->soft, 0, 16, st) != hipSuccess) return OCP_E_HIP;
   refresh_copies(h, st);
@@ -624,6 +690,7 @@ ocp_status ocp_set_qp(ocp_handle h, const ocp_qp* p, void* stream) {
   if (!ok) return OCP_E_HIP;
   h->gamma2 = p->gamma2;
   h->gamma1 = p->gamma1;
+  h->variant = h->ti ? VAR_TI : VAR_TV;
   refresh_copies(h, st);
   h->data_set = true;
   h->solved = false;
@@ -643,6 +710,7 @@ ocp_status ocp_set_bicycle(ocp_handle h, const ocp_bicycle* p, void* stream) {
       hipMemcpyAsync(h->bike_x0, p->x0, sizeof(double) * 4 * h->B, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return OCP_E_HIP;
   h->bike = *p;
+  h->variant = VAR_TV;
   h->gamma1 = p->gamma1;
   h->gamma2 = 1.0;
   h->has_E = false;
@@ -711,6 +779,8 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   a.eta_x = out->eta_x;
   a.active = out->active;
   Layout L = make_layout(h);
+  L.LinvTr = nullptr;  // the adjoint factor needs no iteration-precision copies
+  L.MTr = nullptr;
   const int grid = (h->B + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
   const int ti = h->ti ? 1 : 0;
   if (h->mixed)
