@@ -99,7 +99,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   }
 
   // ---- 2. factor H + sigma_b I + rho_b (C'C + G_A'G_A) (FP64) ----
-  const int bad = factor_instance<double, NX, NU, NG>(L, g, a.sigma_b, a.rho_b, 0.0, a.w);
+  const int bad = factor_instance<double, NX, NU, NG, false>(L, g, a.sigma_b, a.rho_b, 0.0, a.w);
 
   // ---- refinement sweeps ----
   for (int sweep = 0; sweep < a.sweeps && !bad; ++sweep) {

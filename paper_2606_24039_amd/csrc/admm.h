@@ -27,18 +27,26 @@ struct Proj {
   T z, xi;
 };
 
-// slack update for one inequality row (see oracle/admm.py `project`)
+// Constants of the slack update for one rho_g (see oracle/admm.py `project`):
+// L2 rows z = c_v v + c_p Pi(v), xi = c_v (Pi(v) - v) with c_v = rho/(g2+rho),
+// c_p = g2/(g2+rho); L1 rows xi = shrink(Pi(v) - v, kappa), kappa = g1/rho.
 template <typename T>
-__device__ __forceinline__ Proj<T> project_row(T v, T lo, T hi, int kind, T rho_g, T gamma2, T gamma1) {
+struct ProjConst {
+  T inv_rho, cv, cp, kap;
+  __device__ ProjConst(T rho_g, T gamma2, T gamma1)
+      : inv_rho(T(1) / rho_g), cv(rho_g / (gamma2 + rho_g)), cp(gamma2 / (gamma2 + rho_g)), kap(gamma1 / rho_g) {}
+};
+
+template <typename T>
+__device__ __forceinline__ Proj<T> project_row(T v, T lo, T hi, int kind, const ProjConst<T>& c) {
   const T pv = clampv(v, lo, hi);
   Proj<T> p{pv, T(0)};
   if (kind == 1) {
-    p.z = (rho_g * v + gamma2 * pv) / (gamma2 + rho_g);
-    p.xi = rho_g * (pv - v) / (gamma2 + rho_g);
+    p.z = c.cv * v + c.cp * pv;
+    p.xi = c.cv * (pv - v);
   } else if (kind == 2) {
-    const T kap = gamma1 / rho_g;
     const T d = pv - v;
-    p.xi = d - clampv(d, -kap, kap);
+    p.xi = d - clampv(d, -c.kap, c.kap);
     p.z = pv - p.xi;
   }
   return p;
@@ -78,6 +86,48 @@ struct TIBlocks {
   }
 };
 
+// Per-row base pointers of the per-iteration data, advanced one stage at a
+// time.  Lanes past the block height read a valid row (their results are
+// never broadcast or stored).
+template <typename T, int NX, int NU, int NG>
+struct StagePtrs {
+  static constexpr int n = NX + NU;
+  const T *Lr, *Mr, *Lc, *Mc;      // factor rows (Linv, M) and transposed rows
+  const T *AmC, *ApC, *GC;         // column `lane` of the time-varying blocks
+  const T *AmR, *ApR, *GR;         // row `lane` of the time-varying blocks
+  const T *lo, *hi, *bd, *q;
+  T *x, *v, *yf, *zg, *yg, *xi;    // padded state of stage t (y_f: slot of stage t)
+  __device__ StagePtrs(const Layout& L, const Group& g) {
+    const size_t nn = (size_t)n * n;
+    const int i = g.lane;
+    const int ir = i < n ? i : n - 1;
+    const int ix = i < NX ? i : NX - 1;
+    const int ig = i < NG ? i : NG - 1;
+    const int64_t s0 = g.s0;
+    Lr = (const T*)L.LinvT + (size_t)s0 * nn + (size_t)ir * n;
+    Mr = (const T*)L.MT + (size_t)s0 * nn + (size_t)ir * n;
+    Lc = (const T*)L.LinvTr + (size_t)s0 * nn + (size_t)ir * n;
+    Mc = (const T*)L.MTr + (size_t)s0 * nn + (size_t)ir * n;
+    AmC = (const T*)L.AmT + (size_t)s0 * NX * n + ir;
+    ApC = (const T*)L.ApT + (size_t)s0 * NX * n + ir;
+    GC = (const T*)L.GT + (size_t)s0 * NG * n + ir;
+    AmR = (const T*)L.AmT + (size_t)s0 * NX * n + (size_t)ix * n;
+    ApR = (const T*)L.ApT + (size_t)s0 * NX * n + (size_t)ix * n;
+    GR = (const T*)L.GT + (size_t)s0 * NG * n + (size_t)ig * n;
+    lo = (const T*)L.loT + (size_t)s0 * NG + ig;
+    hi = (const T*)L.hiT + (size_t)s0 * NG + ig;
+    bd = L.bdT ? (const T*)L.bdT + (size_t)s0 * NX + ix : nullptr;
+    q = L.qT ? (const T*)L.qT + (size_t)s0 * n + ir : nullptr;
+    const size_t sv = (size_t)s0 * ROW + i;
+    x = (T*)L.x + sv;
+    v = (T*)L.v + sv;
+    yf = (T*)L.yf + sv;
+    zg = (T*)L.zg + sv;
+    yg = (T*)L.yg + sv;
+    xi = (T*)L.xi + sv;
+  }
+};
+
 // Data of one stage for the forward sweep (prefetched PF stages ahead).
 template <typename T, int NX, int NU, int NG, bool TI>
 struct FwdStage {
@@ -88,25 +138,25 @@ struct FwdStage {
 };
 
 template <typename T, int NX, int NU, int NG, bool TI>
-__device__ __forceinline__ void load_fwd(FwdStage<T, NX, NU, NG, TI>& d, const Layout& L, const Group& g, int t) {
+__device__ __forceinline__ void load_fwd(FwdStage<T, NX, NU, NG, TI>& d, const StagePtrs<T, NX, NU, NG>& p, int t,
+                                         int N) {
   constexpr int n = NX + NU;
   const size_t nn = (size_t)n * n;
-  const int i = g.lane;
-  const int64_t s = g.s0 + t;
-  const size_t sv = (size_t)s * ROW + i;
-  load_row<n>(d.Lr, (const T*)L.LinvT + (size_t)s * nn + (size_t)i * n, i < n);
-  load_row<n>(d.Mr, (const T*)L.MT + (size_t)s * nn + (size_t)i * n, i < n && t > 0);
-  d.x = (i < n) ? ((const T*)L.x)[sv] : T(0);
-  d.yf = (i < NX && t < g.N) ? ((const T*)L.yf)[sv + ROW] : T(0);
-  d.zg = (i < NG) ? ((const T*)L.zg)[sv] : T(0);
-  d.yg = (i < NG) ? ((const T*)L.yg)[sv] : T(0);
-  d.q = (L.qT && i < n) ? ((const T*)L.qT)[(size_t)s * n + i] : T(0);
+  const size_t o = (size_t)t * nn;
+  load_row<n>(d.Lr, p.Lr + o, true);
+  load_row<n>(d.Mr, p.Mr + o, t > 0);
+  d.x = p.x[(size_t)t * ROW];
+  d.yf = p.yf[(size_t)t * ROW];  // dynamics row t (slot N holds the initial-state rows)
+  d.zg = p.zg[(size_t)t * ROW];
+  d.yg = p.yg[(size_t)t * ROW];
+  d.q = p.q ? p.q[(size_t)t * n] : T(0);
   if constexpr (!TI) {
-    d.bd = (L.bdT && i < NX && t < g.N) ? ((const T*)L.bdT)[(size_t)s * NX + i] : T(0);
-    load_col<NX>(d.AmC, (const T*)L.AmT + (size_t)s * NX * n + i, n, i < n && t < g.N);
-    load_col<NX>(d.ApC, (const T*)L.ApT + (size_t)s * NX * n + i, n, i < n && t < g.N);
-    load_col<NG>(d.GC, (const T*)L.GT + (size_t)s * NG * n + i, n, i < n);
+    d.bd = p.bd ? p.bd[(size_t)t * NX] : T(0);
+    load_col<NX>(d.AmC, p.AmC + (size_t)t * NX * n, n, true);
+    load_col<NX>(d.ApC, p.ApC + (size_t)t * NX * n, n, true);
+    load_col<NG>(d.GC, p.GC + (size_t)t * NG * n, n, true);
   }
+  (void)N;
 }
 
 // Data of one stage for the backward sweep.
@@ -120,26 +170,24 @@ struct BwdStage {
 };
 
 template <typename T, int NX, int NU, int NG, bool TI>
-__device__ __forceinline__ void load_bwd(BwdStage<T, NX, NU, NG, TI>& d, const Layout& L, const Group& g, int t) {
+__device__ __forceinline__ void load_bwd(BwdStage<T, NX, NU, NG, TI>& d, const StagePtrs<T, NX, NU, NG>& p, int t,
+                                         int N) {
   constexpr int n = NX + NU;
   const size_t nn = (size_t)n * n;
-  const int i = g.lane;
-  const int64_t s = g.s0 + t;
-  const size_t sv = (size_t)s * ROW + i;
-  load_row<n>(d.Lc, (const T*)L.LinvTr + (size_t)s * nn + (size_t)i * n, i < n);
-  load_row<n>(d.Mc, (const T*)L.MTr + (size_t)(s + 1) * nn + (size_t)i * n, i < n && t < g.N);
-  d.v = (i < n) ? ((const T*)L.v)[sv] : T(0);
-  d.x = (i < n) ? ((const T*)L.x)[sv] : T(0);
-  d.zg = (i < NG) ? ((const T*)L.zg)[sv] : T(0);
-  d.yg = (i < NG) ? ((const T*)L.yg)[sv] : T(0);
-  d.yf = (i < NX && t < g.N) ? ((const T*)L.yf)[sv + ROW] : T(0);
+  load_row<n>(d.Lc, p.Lc + (size_t)t * nn, true);
+  load_row<n>(d.Mc, p.Mc + (size_t)(t + 1) * nn, t < N);
+  d.v = p.v[(size_t)t * ROW];
+  d.x = p.x[(size_t)t * ROW];
+  d.zg = p.zg[(size_t)t * ROW];
+  d.yg = p.yg[(size_t)t * ROW];
+  d.yf = p.yf[(size_t)t * ROW];
   if constexpr (!TI) {
-    d.lo = (i < NG) ? ((const T*)L.loT)[(size_t)s * NG + i] : T(0);
-    d.hi = (i < NG) ? ((const T*)L.hiT)[(size_t)s * NG + i] : T(0);
-    d.bd = (L.bdT && i < NX && t < g.N) ? ((const T*)L.bdT)[(size_t)s * NX + i] : T(0);
-    load_row<n>(d.AmR, (const T*)L.AmT + (size_t)s * NX * n + (size_t)i * n, i < NX && t < g.N);
-    load_row<n>(d.ApR, (const T*)L.ApT + (size_t)s * NX * n + (size_t)i * n, i < NX && t < g.N);
-    load_row<n>(d.GR, (const T*)L.GT + (size_t)s * NG * n + (size_t)i * n, i < NG);
+    d.lo = p.lo[(size_t)t * NG];
+    d.hi = p.hi[(size_t)t * NG];
+    d.bd = p.bd ? p.bd[(size_t)t * NX] : T(0);
+    load_row<n>(d.AmR, p.AmR + (size_t)t * NX * n, true);
+    load_row<n>(d.ApR, p.ApR + (size_t)t * NX * n, true);
+    load_row<n>(d.GR, p.GR + (size_t)t * NG * n, true);
   }
 }
 
@@ -151,30 +199,25 @@ constexpr int prefetch_depth() {
 }
 
 template <typename T, int NX, int NU, int NG, typename ST>
-__device__ void admm_iteration(const Layout& L, const Group& g, const TIBlocks<T, NX, NU, NG>& tb, T sigma,
-                               T rho_f, T rho_g, T alpha, int kind, T gamma2, T gamma1) {
+__device__ void admm_iteration(const Layout& L, const Group& g, const TIBlocks<T, NX, NU, NG>& tb,
+                               const StagePtrs<T, NX, NU, NG>& P, T sigma, T rho_f, T rho_g, T alpha, int kind,
+                               const ProjConst<T>& pc, T xinit, T yinit_rho) {
   constexpr int n = NX + NU;
   constexpr bool TI = ST::TI;
   constexpr int PF = prefetch_depth<T, n>();
   const int i = g.lane;
-  const int b = g.b;
   const int N = g.N;
-  T* __restrict__ X = (T*)L.x;
-  T* __restrict__ V = (T*)L.v;
-  T* __restrict__ YF = (T*)L.yf;
-  T* __restrict__ ZG = (T*)L.zg;
-  T* __restrict__ YG = (T*)L.yg;
-  T* __restrict__ XI = (T*)L.xi;
-  const T xinit = (i < NX) ? ((const T*)L.xinitT)[(size_t)b * NX + i] : T(0);
   const int gsel = L.gsel[i < NG ? i : 0];
   const int ginv = L.ginv[i];
+  (void)yinit_rho;
 
   // ---------------- forward sweep ----------------
+  // Branch-free stage bodies: boundary terms multiply zeros (M_0 and the
+  // stage after N are zero slots; w and the A^+ term vanish at the ends).
+  const T yinit = P.yf[(size_t)N * ROW];  // initial-state multipliers (slot N)
   {
     FwdStage<T, NX, NU, NG, TI> buf[PF];
-    sfor<0, PF>([&](auto k) {
-      if (decltype(k)::value <= N) load_fwd(buf[decltype(k)::value], L, g, decltype(k)::value);
-    });
+    sfor<0, PF>([&](auto k) { load_fwd(buf[decltype(k)::value], P, min((int)decltype(k)::value, N), N); });
     T vprev = T(0), wprev = T(0);
     T ApCprev[TI ? 1 : NX];
     if constexpr (!TI) {
@@ -187,44 +230,37 @@ __device__ void admm_iteration(const Layout& L, const Group& g, const TIBlocks<T
         const int t = t0 + k;
         if (t <= N) {
           FwdStage<T, NX, NU, NG, TI>& d = buf[k];
-          const int64_t s = g.s0 + t;
           T eta = sigma * d.x - d.q;
-          T w = T(0);
-          if (t < N) {
-            const T bdv = TI ? tb.bd : d.bd;
-            w = (i < NX) ? rho_f * bdv - d.yf : T(0);
-            if constexpr (TI) eta = dotb<NX>(tb.AmC, w, eta);
-            else eta = dotb<NX>(d.AmC, w, eta);
+          const T w = (t < N && i < NX) ? rho_f * (TI ? tb.bd : d.bd) - d.yf : T(0);
+          if constexpr (TI) eta = dotb<NX>(tb.AmC, w, eta);
+          else eta = dotb<NX>(d.AmC, w, eta);
+          if constexpr (ST::APNEG) {
+            eta -= (i < NX) ? wprev : T(0);
+          } else if constexpr (TI) {
+            eta = dotb<NX>(tb.ApC, wprev, eta);
+          } else {
+            eta = dotb<NX>(ApCprev, wprev, eta);
           }
-          if (t > 0) {
-            if constexpr (ST::APNEG) {
-              if (i < NX) eta -= wprev;
-            } else if constexpr (TI) {
-              eta = dotb<NX>(tb.ApC, wprev, eta);
-            } else {
-              eta = dotb<NX>(ApCprev, wprev, eta);
-            }
-          }
-          if (t == 0 && i < NX) eta += rho_f * xinit - ((const T*)YF)[(size_t)s * ROW + i];
+          eta += (t == 0 && i < NX) ? rho_f * xinit - yinit : T(0);
           const T u = (i < NG) ? rho_g * d.zg - d.yg : T(0);
           if constexpr (ST::GSEL) {
             const T gu = row_gather(u, ginv < 0 ? 0 : ginv);
-            if (ginv >= 0) eta += gu;
+            eta += (ginv >= 0) ? gu : T(0);
           } else if constexpr (TI) {
             eta = dotb<NG>(tb.GC, u, eta);
           } else {
             eta = dotb<NG>(d.GC, u, eta);
           }
-          if (t > 0) eta -= dotb<n>(d.Mr, vprev, T(0));
+          eta -= dotb<n>(d.Mr, vprev, T(0));
           const T vv = dotb<n>(d.Lr, eta, T(0));
-          if (i < n) V[(size_t)s * ROW + i] = vv;
+          P.v[(size_t)t * ROW] = vv;
           vprev = vv;
           wprev = w;
           if constexpr (!TI) {
 #pragma unroll
             for (int r = 0; r < NX; ++r) ApCprev[r] = d.ApC[r];
           }
-          if (t + PF <= N) load_fwd(d, L, g, t + PF);
+          load_fwd(d, P, min(t + PF, N), N);
         }
       });
     }
@@ -233,35 +269,32 @@ __device__ void admm_iteration(const Layout& L, const Group& g, const TIBlocks<T
   // ---------------- backward sweep + constraint-row updates ----------------
   {
     BwdStage<T, NX, NU, NG, TI> buf[PF];
-    sfor<0, PF>([&](auto k) {
-      if (N - decltype(k)::value >= 0) load_bwd(buf[decltype(k)::value], L, g, N - decltype(k)::value);
-    });
+    sfor<0, PF>([&](auto k) { load_bwd(buf[decltype(k)::value], P, max(N - (int)decltype(k)::value, 0), N); });
     T xnext = T(0);
     const T oma = T(1) - alpha;
+    const T rfa = rho_f * alpha;
     for (int t0 = N; t0 >= 0; t0 -= PF) {
       sfor<0, PF>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
         const int t = t0 - k;
         if (t >= 0) {
           BwdStage<T, NX, NU, NG, TI>& d = buf[k];
-          const int64_t s = g.s0 + t;
-          const size_t sv = (size_t)s * ROW + i;
-          T vv = d.v;
-          if (t < N) vv -= dotb<n>(d.Mc, xnext, T(0));
+          const size_t o = (size_t)t * ROW;
+          const T vv = d.v - dotb<n>(d.Mc, xnext, T(0));  // M_{N+1} is a zero slot
           const T xt = dotb<n>(d.Lc, vv, T(0));
-          if (t < N) {  // dynamics row t:  y_f += rho_f alpha (A^- x~_t + A^+ x~_{t+1} - c_t)
-            T zf;
-            if constexpr (TI) zf = dotb<n>(tb.AmR, xt, T(0));
-            else zf = dotb<n>(d.AmR, xt, T(0));
-            if constexpr (ST::APNEG) {
-              zf -= xnext;
-            } else if constexpr (TI) {
-              zf = dotb<n>(tb.ApR, xnext, zf);
-            } else {
-              zf = dotb<n>(d.ApR, xnext, zf);
-            }
-            if (i < NX) YF[sv + ROW] = d.yf + rho_f * alpha * (zf - (TI ? tb.bd : d.bd));
+          // dynamics row t:  y_f += rho_f alpha (A^- x~_t + A^+ x~_{t+1} - c_t)
+          T zf;
+          if constexpr (TI) zf = dotb<n>(tb.AmR, xt, T(0));
+          else zf = dotb<n>(d.AmR, xt, T(0));
+          if constexpr (ST::APNEG) {
+            zf -= xnext;
+          } else if constexpr (TI) {
+            zf = dotb<n>(tb.ApR, xnext, zf);
+          } else {
+            zf = dotb<n>(d.ApR, xnext, zf);
           }
+          P.yf[o] = (t < N) ? d.yf + rfa * (zf - (TI ? tb.bd : d.bd)) : d.yf;
+          // inequality rows of stage t (lanes past ng update padding)
           T zt;
           if constexpr (ST::GSEL) {
             zt = row_gather(xt, gsel);
@@ -270,21 +303,20 @@ __device__ void admm_iteration(const Layout& L, const Group& g, const TIBlocks<T
           } else {
             zt = dotb<n>(d.GR, xt, T(0));
           }
-          if (i < NG) {  // inequality rows of stage t
-            const T zh = alpha * zt + oma * d.zg;
-            const Proj<T> p = project_row<T>(zh + d.yg / rho_g, TI ? tb.lo : d.lo, TI ? tb.hi : d.hi, kind, rho_g,
-                                             gamma2, gamma1);
-            ZG[sv] = p.z;
-            XI[sv] = p.xi;
-            YG[sv] = d.yg + rho_g * (zh - p.z);
-          }
-          if (i < n) X[sv] = alpha * xt + oma * d.x;
-          if (t == 0 && i < NX) YF[sv] += rho_f * alpha * (xt - xinit);
+          const T zh = alpha * zt + oma * d.zg;
+          const Proj<T> pr = project_row<T>(fma(d.yg, pc.inv_rho, zh), TI ? tb.lo : d.lo, TI ? tb.hi : d.hi, kind,
+                                            pc);
+          P.zg[o] = pr.z;
+          P.xi[o] = pr.xi;
+          P.yg[o] = d.yg + rho_g * (zh - pr.z);
+          P.x[o] = alpha * xt + oma * d.x;
           xnext = xt;
-          if (t - PF >= 0) load_bwd(d, L, g, t - PF);
+          load_bwd(d, P, max(t - PF, 0), N);
         }
       });
     }
+    // initial-state rows: y_init += rho_f alpha (x~_0 - x_init)
+    if (i < NX) P.yf[(size_t)N * ROW] = yinit + rfa * (xnext - xinit);
   }
 }
 
@@ -339,7 +371,7 @@ __device__ Resid residuals(const Layout& L, const Group& g, int kind, double gam
       load_row<n>(Eprev, Ep + (size_t)i * n, i < n);
     }
     // (A' y)_t row i
-    const double yfc = (t < N && i < NX) ? double(YF[sv + ROW]) : 0.0;
+    const double yfc = (t < N && i < NX) ? double(YF[sv]) : 0.0;
     double aty = 0.0;
     double Amc[NX], Amr[n], Apr[n];
     if (t < N) {
@@ -351,7 +383,7 @@ __device__ Resid residuals(const Layout& L, const Group& g, int kind, double gam
       aty = dotb<NX>(Amc, yfc, aty);
     }
     if (t > 0) aty = dotb<NX>(Apcm, yfm, aty);
-    if (t == 0 && i < NX) aty += double(YF[sv]);
+    if (t == 0 && i < NX) aty += double(YF[(size_t)(g.s0 + N) * ROW + i]);
     const double* Gp = L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n);
     double Gc[NG], Gr[n];
     load_col<NG>(Gc, Gp + i, n, i < n);
@@ -461,7 +493,9 @@ __global__ __launch_bounds__(64) void admm_factor_kernel(Layout L, Settings st, 
   if (!row_group(L, g)) return;
   if (L.status[g.b] != ST_RUNNING || !need[g.b]) return;
   const double rho_bar = L.rho[g.b];
-  const int bad = factor_instance<T, NX, NU, NG>(L, g, st.sigma, st.rho_f_scale * rho_bar, rho_bar, nullptr);
+  const int bad = L.ti ? factor_instance<T, NX, NU, NG, true>(L, g, st.sigma, st.rho_f_scale * rho_bar, rho_bar, nullptr)
+                       : factor_instance<T, NX, NU, NG, false>(L, g, st.sigma, st.rho_f_scale * rho_bar, rho_bar,
+                                                               nullptr);
   if (g.lane == 0) {
     need[g.b] = 0;
     if (bad)
@@ -483,10 +517,13 @@ __global__ __launch_bounds__(64) void admm_iter_kernel(Layout L, Settings st, in
   const double rho_bar = L.rho[g.b];
   TIBlocks<T, NX, NU, NG> tb;
   if constexpr (ST::TI) tb.load(L, g.b, i);
+  const StagePtrs<T, NX, NU, NG> P(L, g);
+  const ProjConst<T> pc(T(rho_bar), T(L.gamma2), T(L.gamma1));
+  const T xinit = ((const T*)L.xinitT)[(size_t)g.b * NX + (i < NX ? i : 0)];
   int k = L.iters[g.b];
   for (; k < kend; ++k)
-    admm_iteration<T, NX, NU, NG, ST>(L, g, tb, T(st.sigma), T(st.rho_f_scale * rho_bar), T(rho_bar), T(st.alpha),
-                                      kind, T(L.gamma2), T(L.gamma1));
+    admm_iteration<T, NX, NU, NG, ST>(L, g, tb, P, T(st.sigma), T(st.rho_f_scale * rho_bar), T(rho_bar),
+                                      T(st.alpha), kind, pc, xinit, T(0));
   if (i == 0) L.iters[g.b] = k;
 }
 

@@ -363,8 +363,8 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     grad[0] += nx_ * yg[2];
     grad[1] += ny_ * yg[2];
     double f[4], Ml[4][6], Mr[4][6];
-    if (t < N) {  // dynamics row t: A_t^-' y
-      const double* yf = a.yfbar + (s + 1) * ROW;
+    if (t < N) {  // dynamics row t (slot t): A_t^-' y
+      const double* yf = a.yfbar + s * ROW;
       bike_midpoint(xb, xb + 4, xb + ROW, a.dt, a.Lw, f, Ml, Mr);
 #pragma unroll
       for (int k = 0; k < 6; ++k)
@@ -373,16 +373,16 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
 #pragma unroll
       for (int k = 0; k < 4; ++k) fe = fmax(fe, fabs(f[k]));
     }
-    if (t > 0) {  // dynamics row t-1: A_{t-1}^+' y
-      const double* yf = a.yfbar + s * ROW;
+    if (t > 0) {  // dynamics row t-1 (slot t-1): A_{t-1}^+' y
+      const double* yf = a.yfbar + (s - 1) * ROW;
       const double* xp = xb - ROW;
       bike_midpoint(xp, xp + 4, xb, a.dt, a.Lw, f, Ml, Mr);
 #pragma unroll
       for (int k = 0; k < 6; ++k)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) grad[k] += Mr[rr][k] * yf[rr];
-    } else {
-      const double* yf = a.yfbar + s * ROW;
+    } else {  // initial-state rows (slot N)
+      const double* yf = a.yfbar + (s0 + N) * ROW;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         grad[k] += yf[k];

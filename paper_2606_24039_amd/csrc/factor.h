@@ -31,56 +31,98 @@ __device__ __forceinline__ void cross_row(const double (&a)[R], const double (&b
   });
 }
 
+// Per-stage FP64 inputs of the factorisation (lane i: row / column i).
+template <int NX, int NU, int NG>
+struct FacStage {
+  static constexpr int n = NX + NU;
+  double D[n], E[n];        // row i of D_t, E_t
+  double Amc[NX], Apc[NX];  // column i of A_t^-, A_t^+
+  double Gc[NG], w[NG];     // column i of G_t, inequality-row weights
+};
+
+template <int NX, int NU, int NG>
+__device__ __forceinline__ void load_fac(FacStage<NX, NU, NG>& d, const Layout& L, const Group& g, int t, double rho_g,
+                                         const double* __restrict__ rhog_rows) {
+  constexpr int n = NX + NU;
+  const size_t nn = (size_t)n * n;
+  const int i = g.lane, b = g.b, N = g.N;
+  const int ic = i < n ? i : n - 1;  // lanes past n read a valid row (results unused)
+  const int64_t s = g.s0 + t;
+  const double* Dp = L.ti ? L.D + (size_t)(2 * b + (t == N ? 1 : 0)) * nn : L.D + (size_t)s * nn;
+  load_row<n>(d.D, Dp + (size_t)ic * n, true);
+  if (L.E && t < N)
+    load_row<n>(d.E, L.E + ti_or_tv(L.ti, b, s, nn) + (size_t)ic * n, true);
+  else
+#pragma unroll
+    for (int k = 0; k < n; ++k) d.E[k] = 0.0;
+  load_col<NX>(d.Amc, L.Am + ti_or_tv(L.ti, b, s, (size_t)NX * n) + ic, n, t < N);
+  load_col<NX>(d.Apc, L.Ap + ti_or_tv(L.ti, b, s, (size_t)NX * n) + ic, n, t < N);
+  load_col<NG>(d.Gc, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + ic, n, true);
+#pragma unroll
+  for (int r = 0; r < NG; ++r) d.w[r] = rhog_rows ? rhog_rows[(size_t)s * ROW + r] : rho_g;
+}
+
 // Factor one instance.  rhog_rows: optional per-row inequality weights
 // ([S][ROW], FP64); when null every inequality row uses rho_g.
+// HOIST: time-invariant blocks and uniform weights, so the rho-independent
+// products A^-'A^-, A^+'A^+, G'G and A^+'A^- are formed once per instance.
 // Returns 0 on success, 1 on a non-positive / non-finite pivot.
-template <typename T, int NX, int NU, int NG>
+template <typename T, int NX, int NU, int NG, bool HOIST>
 __device__ int factor_instance(const Layout& L, const Group& g, double sigma, double rho_f, double rho_g,
                                const double* __restrict__ rhog_rows) {
   constexpr int n = NX + NU;
   const int i = g.lane;
   const bool vi = i < n;
-  const int b = g.b;
   const int N = g.N;
   const size_t nn = (size_t)n * n;
 
-  double Mrow[n];   // row i of M_t
-  double Apc[NX];   // column i of A_{t-1}^+
+  double Mrow[n];     // row i of M_t
+  double ApcPrev[NX]; // column i of A_{t-1}^+
 #pragma unroll
   for (int k = 0; k < n; ++k) Mrow[k] = 0.0;
 #pragma unroll
-  for (int r = 0; r < NX; ++r) Apc[r] = 0.0;
+  for (int r = 0; r < NX; ++r) ApcPrev[r] = 0.0;
+
+  // rho-independent products (row i), formed once when the blocks do not vary
+  double PAm[HOIST ? n : 1], PAp[HOIST ? n : 1], PG[HOIST ? n : 1], PPhi[HOIST ? n : 1];
+  FacStage<NX, NU, NG> cur, nxt;
+  load_fac(cur, L, g, 0, rho_g, rhog_rows);
+  if constexpr (HOIST) {
+    FacStage<NX, NU, NG> any;  // the blocks of an interior stage (all equal)
+    load_fac(any, L, g, 0, rho_g, rhog_rows);
+#pragma unroll
+    for (int k = 0; k < n; ++k) PAm[k] = PAp[k] = PG[k] = PPhi[k] = 0.0;
+    cross_row<NX, n>(any.Amc, any.Amc, PAm, 1.0);
+    cross_row<NX, n>(any.Apc, any.Apc, PAp, 1.0);
+    double Gw[NG];
+#pragma unroll
+    for (int r = 0; r < NG; ++r) Gw[r] = any.w[r] * any.Gc[r];
+    cross_row<NG, n>(Gw, any.Gc, PG, 1.0);
+    cross_row<NX, n>(any.Apc, any.Amc, PPhi, 1.0);
+  }
 
   int bad = 0;
   for (int t = 0; t <= N; ++t) {
     const int64_t s = g.s0 + t;
-    const double* Dp = L.ti ? L.D + (size_t)(2 * b + (t == N ? 1 : 0)) * nn : L.D + (size_t)s * nn;
+    if (t < N) load_fac(nxt, L, g, t + 1, rho_g, rhog_rows);  // prefetch
     double S[n];
-    load_row<n>(S, Dp + (size_t)i * n, vi);
+#pragma unroll
+    for (int k = 0; k < n; ++k) S[k] = cur.D[k];
     sfor<0, n>([&](auto j) {
       constexpr int jj = decltype(j)::value;
-      if (i == jj) S[jj] += sigma;
+      if (i == jj) S[jj] += sigma + ((t == 0 && jj < NX) ? rho_f : 0.0);
     });
-    if (t == 0) {
-      sfor<0, NX>([&](auto j) {
-        constexpr int jj = decltype(j)::value;
-        if (i == jj) S[jj] += rho_f;
-      });
-    }
-    double Amc[NX];
-    if (t < N) {
-      const double* Amp = L.Am + ti_or_tv(L.ti, b, s, (size_t)NX * n);
-      load_col<NX>(Amc, Amp + i, n, vi);
-      cross_row<NX, n>(Amc, Amc, S, rho_f);
-    }
-    if (t > 0) cross_row<NX, n>(Apc, Apc, S, rho_f);
-    {
-      const double* Gp = L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n);
-      double Gc[NG], Gw[NG];
-      load_col<NG>(Gc, Gp + i, n, vi);
+    if constexpr (HOIST) {
+      const double ca = (t < N) ? rho_f : 0.0, cp = (t > 0) ? rho_f : 0.0;
 #pragma unroll
-      for (int r = 0; r < NG; ++r) Gw[r] = (rhog_rows ? rhog_rows[(size_t)s * ROW + r] : rho_g) * Gc[r];
-      cross_row<NG, n>(Gw, Gc, S, 1.0);
+      for (int k = 0; k < n; ++k) S[k] += ca * PAm[k] + cp * PAp[k] + PG[k];
+    } else {
+      if (t < N) cross_row<NX, n>(cur.Amc, cur.Amc, S, rho_f);
+      if (t > 0) cross_row<NX, n>(ApcPrev, ApcPrev, S, rho_f);
+      double Gw[NG];
+#pragma unroll
+      for (int r = 0; r < NG; ++r) Gw[r] = cur.w[r] * cur.Gc[r];
+      cross_row<NG, n>(Gw, cur.Gc, S, 1.0);
     }
     if (t > 0) cross_row<n, n>(Mrow, Mrow, S, -1.0);
 
@@ -140,16 +182,14 @@ __device__ int factor_instance(const Layout& L, const Group& g, double sigma, do
     if (t < N) {
       // Phi_t row i = E_t row i + rho_f sum_r A_t^+[r][i] A_t^-[r][:]
       double Phi[n];
-      if (L.E) {
-        const double* Ep = L.E + ti_or_tv(L.ti, b, s, nn);
-        load_row<n>(Phi, Ep + (size_t)i * n, vi);
-      } else {
 #pragma unroll
-        for (int k = 0; k < n; ++k) Phi[k] = 0.0;
+      for (int k = 0; k < n; ++k) Phi[k] = cur.E[k];
+      if constexpr (HOIST) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) Phi[k] += rho_f * PPhi[k];
+      } else {
+        cross_row<NX, n>(cur.Apc, cur.Amc, Phi, rho_f);
       }
-      const double* App = L.Ap + ti_or_tv(L.ti, b, s, (size_t)NX * n);
-      load_col<NX>(Apc, App + i, n, vi);
-      cross_row<NX, n>(Apc, Amc, Phi, rho_f);
       // M_{t+1} row i: M[i][j] = sum_{k<=j} Phi[i][k] Linv[j][k]
       sfor<0, n>([&](auto j) {
         constexpr int jj = decltype(j)::value;
@@ -177,6 +217,9 @@ __device__ int factor_instance(const Layout& L, const Group& g, double sigma, do
           for (int j = 0; j < n; ++j) dT[(size_t)j * n] = T(Mrow[j]);
         }
       }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) ApcPrev[r] = cur.Apc[r];
+      cur = nxt;
     }
   }
   return bad;

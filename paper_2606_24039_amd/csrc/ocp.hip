@@ -226,19 +226,21 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
       A_(h->qT, ts * n * (size_t)S);
       A_(h->bdT, ts * nx * blkI);
     }
-    A_(h->LinvT, ts * nn * S);
-    A_(h->MT, ts * nn * S);
+    A_(h->LinvT, ts * nn * (S + 1));
+    A_(h->MT, ts * nn * (S + 1));
   }
-  A_(h->Linv64, sizeof(double) * nn * S);
-  A_(h->M64, sizeof(double) * nn * S);
-  A_(h->LinvTr, ts * nn * S);
-  A_(h->MTr, ts * nn * S);
-  A_(h->x, ts * ROW * S);
-  A_(h->v, ts * ROW * S);
-  A_(h->yf, ts * ROW * S);
-  A_(h->zg, ts * ROW * S);
-  A_(h->yg, ts * ROW * S);
-  A_(h->xi, ts * ROW * S);
+  // factor and state carry one zero padding stage past the last instance
+  const size_t S1 = (size_t)S + 1;
+  A_(h->Linv64, sizeof(double) * nn * S1);
+  A_(h->M64, sizeof(double) * nn * S1);
+  A_(h->LinvTr, ts * nn * S1);
+  A_(h->MTr, ts * nn * S1);
+  A_(h->x, ts * ROW * S1);
+  A_(h->v, ts * ROW * S1);
+  A_(h->yf, ts * ROW * S1);
+  A_(h->zg, ts * ROW * S1);
+  A_(h->yg, ts * ROW * S1);
+  A_(h->xi, ts * ROW * S1);
   A_(h->rho, sizeof(double) * B);
   A_(h->rprim, sizeof(double) * B);
   A_(h->rdual, sizeof(double) * B);
@@ -258,8 +260,8 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
     A_(h->kkt, sizeof(double) * 3 * B);
     A_(h->sqp_done, sizeof(int32_t) * B);
     A_(h->sqp_frozen, sizeof(int32_t) * B);
-    A_(h->stage_inst, sizeof(int32_t) * S);
   }
+  A_(h->stage_inst, sizeof(int32_t) * S);
   A_(h->adj_rhog, sizeof(double) * ROW * S);
   A_(h->adj_ex, sizeof(double) * ROW * S);
   A_(h->adj_ey, sizeof(double) * ROW * S);
@@ -288,7 +290,7 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   std::vector<int32_t> ord(B);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return horizons[a] > horizons[c]; });
-  if (h->stage_inst) {
+  {
     std::vector<int32_t> si((size_t)S);
     for (int b = 0; b < B; ++b)
       for (int64_t k = off[b]; k < off[b + 1]; ++k) si[(size_t)k] = b;
@@ -299,6 +301,18 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
       hipMemcpy(h->order, ord.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(h->soft, 0, 16) != hipSuccess || hipMemset(h->rho, 0, sizeof(double) * B) != hipSuccess)
     return OCP_E_HIP;
+  // M_0 of every instance and the padding stage stay zero for the lifetime of
+  // the handle (the factorisation writes M_1..M_N only); state starts at zero
+  {
+    const size_t S1 = (size_t)S + 1;
+    const size_t tsz = h->tsz();
+    void* zero_bufs[] = {h->M64, h->MTr, h->x, h->v, h->yf, h->zg, h->yg, h->xi};
+    size_t zero_len[] = {sizeof(double) * nn * S1, tsz * nn * S1, tsz * ROW * S1, tsz * ROW * S1,
+                         tsz * ROW * S1,          tsz * ROW * S1, tsz * ROW * S1, tsz * ROW * S1};
+    for (int k = 0; k < 8; ++k)
+      if (hipMemset(zero_bufs[k], 0, zero_len[k]) != hipSuccess) return OCP_E_HIP;
+    if (h->mixed && hipMemset(h->MT, 0, tsz * nn * S1) != hipSuccess) return OCP_E_HIP;
+  }
   return OCP_OK;
 }
 
@@ -418,6 +432,14 @@ void unpad(const void* src, double* dst, int64_t S, int w, hipStream_t st) {
                      w);
 }
 
+template <typename T>
+void unpad_yf(ocp_handle h, const void* src, double* dst, hipStream_t st) {
+  if (!dst) return;
+  const size_t len = (size_t)h->S * h->d.nx;
+  hipLaunchKernelGGL(unpad_yf_kernel<T>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, (const T*)src, dst,
+                     h->stage_off, h->stage_inst, h->S, h->d.nx);
+}
+
 ocp_status copy_out(ocp_handle h, const ocp_solution* o, hipStream_t st) {
   if (!o) return OCP_OK;
   const int64_t S = h->S;
@@ -426,19 +448,19 @@ ocp_status copy_out(ocp_handle h, const ocp_solution* o, hipStream_t st) {
     unpad<float>(h->x, o->x, S, h->n, st);
     unpad<float>(h->xi, o->xi, S, h->d.ng, st);
     unpad<float>(h->zg, o->z_g, S, h->d.ng, st);
-    unpad<float>(h->yf, o->y_f, S, h->d.nx, st);
+    unpad_yf<float>(h, h->yf, o->y_f, st);
     unpad<float>(h->yg, o->y_g, S, h->d.ng, st);
   } else {
     unpad<double>(h->x, o->x, S, h->n, st);
     unpad<double>(h->xi, o->xi, S, h->d.ng, st);
     unpad<double>(h->zg, o->z_g, S, h->d.ng, st);
-    unpad<double>(h->yf, o->y_f, S, h->d.nx, st);
+    unpad_yf<double>(h, h->yf, o->y_f, st);
     unpad<double>(h->yg, o->y_g, S, h->d.ng, st);
   }
   if (h->d.model == OCP_MODEL_BICYCLE) {  // the SQP iterate is the solution
     unpad<double>(h->xbar, o->x, S, h->n, st);
     unpad<double>(h->xibar, o->xi, S, h->d.ng, st);
-    unpad<double>(h->yfbar, o->y_f, S, h->d.nx, st);
+    unpad_yf<double>(h, h->yfbar, o->y_f, st);
     unpad<double>(h->ygbar, o->y_g, S, h->d.ng, st);
     if (o->sqp_kkt && hipMemcpyAsync(o->sqp_kkt, h->kkt, sizeof(double) * 3 * B, hipMemcpyDeviceToDevice, st) != hipSuccess)
       return OCP_E_HIP;
@@ -688,6 +710,12 @@ ocp_status ocp_set_qp(ocp_handle h, const ocp_qp* p, void* stream) {
     ok = ok && hipMemsetAsync(h->soft, 0, 16, st) == hipSuccess;
   }
   if (!ok) return OCP_E_HIP;
+  if (!h->ti) {
+    hipLaunchKernelGGL(zero_last_stage_kernel, dim3(h->B), dim3(64), 0, st, h->Am, h->stage_off, h->B, nx * n);
+    hipLaunchKernelGGL(zero_last_stage_kernel, dim3(h->B), dim3(64), 0, st, h->Ap, h->stage_off, h->B, nx * n);
+    hipLaunchKernelGGL(zero_last_stage_kernel, dim3(h->B), dim3(64), 0, st, h->bd, h->stage_off, h->B, nx);
+    if (p->E) hipLaunchKernelGGL(zero_last_stage_kernel, dim3(h->B), dim3(64), 0, st, h->E, h->stage_off, h->B, n * n);
+  }
   h->gamma2 = p->gamma2;
   h->gamma1 = p->gamma1;
   h->variant = h->ti ? VAR_TI : VAR_TV;

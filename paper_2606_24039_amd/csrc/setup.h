@@ -71,6 +71,30 @@ __global__ void unpad_kernel(const T* __restrict__ src, double* __restrict__ dst
   dst[k] = double(src[s * ROW + j]);
 }
 
+// y_f: internal slots (dynamics row t at stage t, initial-state rows at the
+// last stage of each instance) -> output order (initial rows at the first
+// stage, dynamics row t at stage t+1)
+template <typename T>
+__global__ void unpad_yf_kernel(const T* __restrict__ src, double* __restrict__ dst, const int64_t* __restrict__ off,
+                                const int32_t* __restrict__ inst, int64_t S, int w) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (size_t)S * w) return;
+  const int64_t s = (int64_t)(k / w);
+  const size_t j = k % w;
+  const int b = inst[s];
+  const int64_t from = (s == off[b]) ? off[b + 1] - 1 : s - 1;
+  dst[k] = double(src[(size_t)from * ROW + j]);
+}
+
+// zero the unused last-stage slot of per-stage blocks (dynamics blocks of
+// stage N have no row), so boundary terms in the branch-free sweeps vanish
+__global__ void zero_last_stage_kernel(double* __restrict__ p, const int64_t* __restrict__ off, int B, int sz) {
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  double* q = p + (size_t)(off[b + 1] - 1) * sz;
+  for (int k = threadIdx.x; k < sz; k += blockDim.x) q[k] = 0.0;
+}
+
 // compact FP64 [S][w] -> padded [S][ROW] state
 template <typename T>
 __global__ void pad_kernel(const double* __restrict__ src, T* __restrict__ dst, int64_t S, int w) {
