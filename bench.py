@@ -4,8 +4,8 @@
 One step = one pass of the hot path over the batch: for every instance the
 FP64 block factorisation, the ADMM iterations (FP32 over the FP64 factor, or
 plain FP64), the rho adaptations with their refactorisations and the FP64
-stopping test; and, once the adjoint is available, the implicit-gradient
-solve ("+grad").  An instance counts as solved only if its FP64-evaluated
+stopping test, then the implicit-gradient adjoint ("+grad") of every
+instance for a seeded upstream gradient.  An instance counts as solved only if its FP64-evaluated
 residuals pass the stopping test at eps_abs = eps_rel = 1e-4.
 
 Prints ONE JSON line (rank 0).  Details go to stderr.
@@ -60,8 +60,9 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(batch, sample, settings_kw):
-    """The FP64 oracle on the host cores, one instance per task."""
+def cpu_baseline(batch, sample, settings_kw, grad):
+    """The FP64 oracle on the host cores, one instance per task: the ADMM
+    solve and (with grad) the dense-LU adjoint of the same instance."""
     import multiprocessing as mp
 
     global _CPU_BATCH
@@ -69,34 +70,66 @@ def cpu_baseline(batch, sample, settings_kw):
     cores = min(len(os.sched_getaffinity(0)), 16, sample)
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores, initializer=_worker_init) as pool:
-        res = pool.map(_oracle_one, [(i, settings_kw) for i in range(sample)])
+        res = pool.map(_oracle_one, [(i, settings_kw, grad) for i in range(sample)])
     wall = time.perf_counter() - t0
     solved = sum(1 for ok, _ in res if ok)
     iters = sum(it for _, it in res)
     return {"value": solved / wall, "unit": "QP solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {sample} of {batch.batch} instances, FP64 NumPy/SciPy oracle, eps 1e-4",
+            "sample": (f"first {sample} of {batch.batch} instances, FP64 NumPy/SciPy oracle, eps 1e-4"
+                       + (", ADMM solve + sparse-LU adjoint" if grad else ", ADMM solve")),
             "solved": solved, "wall_s": round(wall, 3), "admm_iters_per_s": iters / wall}
 
 
 def _worker_init():
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[k] = "1"
+    # the BLAS pools were created before the fork: cap them in each worker
+    from threadpoolctl import threadpool_limits
+
+    threadpool_limits(1)
 
 
 _CPU_BATCH = None
 
 
 def _oracle_one(args):
-    i, kw = args
+    i, kw, grad = args
     batch = _CPU_BATCH
     from oracle.admm import ADMMSettings, admm_solve
     from oracle.qp import lti_batch_qp
 
-    r = admm_solve(lti_batch_qp(batch, i), ADMMSettings(**kw))
+    qp = lti_batch_qp(batch, i)
+    r = admm_solve(qp, ADMMSettings(**kw))
+    if grad:
+        from oracle.adjoint import active_set, adjoint_dense, adjoint_refined, qp_vjp
+
+        S = batch.N + 1
+        dl = upstream_gradient(batch)[i * S:(i + 1) * S].reshape(-1)
+        lower, upper = active_set(qp, r.x, r.y_g, r.xi)
+        import warnings
+
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            try:  # sparse LU of the KKT matrix (the definition)
+                ex, ef, eg = adjoint_dense(qp, r.x, dl, lower, upper)
+            except RuntimeError:
+                ex = None
+        if ex is None or not np.all(np.isfinite(ex)):
+            # dependent active rows make K singular: the regularised
+            # refinement (the GPU's scheme) is still defined
+            ex, ef, eg = adjoint_refined(qp, r.x, dl, lower, upper, sigma_b=1e-9, rho_b=1e6, sweeps=6)
+        qp_vjp(qp, r.x, ex, ef, eg, lower, upper)
     return r.status == 0, r.iters
 
 
-def run_gpu(batch, precision, steps, warmup, settings_kw):
+def upstream_gradient(batch, seed=11):
+    """Seeded dL/dx for the "+grad" leg: one fixed cotangent per stage
+    variable, standard normal (the loss itself is the caller's)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((batch.batch * (batch.N + 1), batch.nx + batch.nu))
+
+
+def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True):
     import torch
 
     from paper_2606_24039_amd import _abi as A
@@ -108,35 +141,40 @@ def run_gpu(batch, precision, steps, warmup, settings_kw):
     st = A.default_settings(**settings_kw)
     out = s.alloc_solution()
     sol = s.solution_struct(out)
+    grads = s.alloc_grads()
+    gstruct = s.grads_struct(grads)
+    dl = torch.as_tensor(upstream_gradient(batch), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def step(ev0=None, ev1=None):
-        if ev0 is not None:
-            ev0.record(stream)
-        s.solve_raw(st, None)  # exactly one kernel: the persistent ADMM solve
-        if ev1 is not None:
-            ev1.record(stream)
+    def step():
+        s.solve_raw(st, None)
         A.check(s.lib.ocp_get_solution(s.h, A.C.byref(sol), A.C.c_void_p(stream.cuda_stream)), "get_solution")
+        if grad:
+            s.adjoint_raw(st, dl, gstruct)
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    torch.cuda.synchronize()
+    s.profile(True)
+    s.profile_read()
     t0 = time.perf_counter()
-    for k in range(steps):
-        step(*evs[k])
+    for _ in range(steps):
+        step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    kt = s.profile_read()
+    s.profile(False)
     status = out["status"].cpu().numpy()
     iters = out["admm_iters"].cpu().numpy()
     nfact = out["n_factor"].cpu().numpy()
     solved = int((status == 0).sum())
-    res = {"wall_s": wall, "ms_per_step": wall / steps * 1e3, "kernel_ms": kern_ms, "solved": solved,
-           "batch": batch.batch, "iters_mean": float(iters.mean()), "iters_sum": int(iters.sum()),
-           "nfact_sum": int(nfact.sum()), "status_counts": {int(k): int(v) for k, v in
-                                                           zip(*np.unique(status, return_counts=True))}}
+    finite_grad = bool(torch.isfinite(grads["d_q"]).all().item()) if grad else None
+    res = {"wall_s": wall, "ms_per_step": wall / steps * 1e3, "solved": solved, "batch": batch.batch,
+           "iters_mean": float(iters.mean()), "iters_max": int(iters.max()), "iters_sum": int(iters.sum()),
+           "nfact_sum": int(nfact.sum()),
+           "status_counts": {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
+           "kernels": {k: {"ms_per_step": ms / steps, "launches_per_step": c / steps} for k, (ms, c) in kt.items()},
+           "grad_finite": finite_grad}
     s.close()
     return res
 
@@ -147,8 +185,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--cpu-sample", type=int, default=96, help="instances timed on the oracle (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=256, help="instances timed on the oracle (0 = skip)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison")
+    ap.add_argument("--no-grad", action="store_true", help="forward solves only (no adjoint in the step)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: the batched solve has no "
@@ -161,44 +200,51 @@ def main():
     stages = batch.N + 1
 
     log(f"[bench] workload: {desc}")
-    mixed = run_gpu(batch, 1, args.steps, args.warmup, settings_kw)
+    mixed = run_gpu(batch, 1, args.steps, args.warmup, settings_kw, grad=not args.no_grad)
     log(f"[bench] mixed: {json.dumps(mixed)}")
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_gpu(batch, 0, max(3, args.steps // 4), 1, settings_kw)
+        fp64 = run_gpu(batch, 0, max(3, args.steps // 4), 1, settings_kw, grad=not args.no_grad)
         log(f"[bench] fp64: {json.dumps(fp64)}")
 
     value = mixed["solved"] / (mixed["ms_per_step"] * 1e-3)
-    # roofline of the dominant kernel (the persistent ADMM solve), per launch
+    # roofline of the dominant kernel (the ADMM iteration kernel): algorithmic
+    # flops of all its launches in a step / its GPU time in a step (= average
+    # flops per launch / average launch duration)
+    kit = mixed["kernels"]["iter"]
     F32 = mixed["iters_sum"] * stages * f_it
-    F64 = mixed["nfact_sum"] * stages * f_fac
-    t = mixed["kernel_ms"] * 1e-3
-    achieved = (F32 + F64 * PEAK_FP32 / PEAK_FP64) / t / 1e12  # FP32-equivalent TFLOP/s
+    t_it = kit["ms_per_step"] * 1e-3
+    achieved = F32 / t_it / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32, 6), "traffic": None,
-            "kernel": "admm_solve_kernel<float,12,4,16,TI>", "kernel_ms": round(mixed["kernel_ms"], 4),
-            "flops_fp32_per_launch": F32, "flops_fp64_per_launch": F64,
-            "note": "FP64 flops weighted by the FP32/FP64 peak ratio"}
+            "kernel": f"admm_iter_kernel<float,{batch.nx},{batch.nu},{batch.ng},box>",
+            "avg_launch_us": round(kit["ms_per_step"] / max(kit["launches_per_step"], 1) * 1e3, 2),
+            "launches_per_step": kit["launches_per_step"],
+            "flops_per_launch": F32 / max(kit["launches_per_step"], 1),
+            "flops_per_stage_iteration": f_it}
     out = {
         "metric": "QP solves/s at 1e-4 KKT residual, FP32+grad vs plain FP64, 1 MI355X",
         "value": round(value, 2), "unit": "QP solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(mixed["ms_per_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": desc, "batch": batch.batch, "horizon": batch.N, "nx": batch.nx, "nu": batch.nu,
-                   "ng": batch.ng, "precision": "fp32 ADMM iterations, fp64 factorisation and gate",
-                   "eps": 1e-4, "grad": False, "parallelism": "single GPU, one instance per 16-lane row"},
+                   "ng": batch.ng, "precision": "fp32 ADMM iterations, fp64 factorisation, gate and adjoint",
+                   "eps": 1e-4, "max_admm": 1000, "grad": not args.no_grad,
+                   "parallelism": "single GPU, one instance per 16-lane row"},
         "admm_iters_per_s": round(mixed["iters_sum"] / (mixed["ms_per_step"] * 1e-3), 1),
+        "kernel_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in mixed["kernels"].items()},
         "solved_fraction": mixed["solved"] / batch.batch,
         "roofline": roof,
     }
     if fp64 is not None:
         out["fp64"] = {"value": round(fp64["solved"] / (fp64["ms_per_step"] * 1e-3), 2),
-                       "ms_per_step": round(fp64["ms_per_step"], 4), "kernel_ms": round(fp64["kernel_ms"], 4),
+                       "ms_per_step": round(fp64["ms_per_step"], 4),
+                       "kernel_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in fp64["kernels"].items()},
                        "solved_fraction": fp64["solved"] / batch.batch, "iters_mean": fp64["iters_mean"]}
         out["speedup_vs_fp64"] = round(value / max(out["fp64"]["value"], 1e-9), 3)
     if args.cpu_sample > 0:
         cb_kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_iter=1000, k_check=25, k_rho=25)
-        out["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_sample, batch.batch), cb_kw)
+        out["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_sample, batch.batch), cb_kw, not args.no_grad)
         log(f"[bench] cpu: {json.dumps(out['cpu_baseline'])}")
     print(json.dumps(out), flush=True)
 

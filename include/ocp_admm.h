@@ -200,6 +200,32 @@ ocp_status ocp_get_solution(ocp_handle h, const ocp_solution* out, void* stream)
 ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const ocp_qp_grads* out,
                        void* stream);
 
+/* Kernel timing (observability).  Classes of the library's launches: */
+enum {
+  OCP_K_FACTOR = 0,  /* block-tridiagonal Cholesky (Appendix "ADMM", Schur complement) */
+  OCP_K_ITER = 1,    /* ADMM iterations between stopping tests (Algorithm 3) */
+  OCP_K_CHECK = 2,   /* FP64 residuals, stopping test, rho candidate (eq. admm:residuals, rho:update) */
+  OCP_K_ADJOINT = 3, /* implicit-differentiation VJP (Algorithm 2) */
+  OCP_K_SQP = 4,     /* bicycle linearisation and line search (Algorithm 1) */
+  OCP_K_OTHER = 5,   /* per-solve initialisation */
+  OCP_K_COUNT = 6
+};
+/* Accumulated GPU time (HIP events on the caller's stream, bracketing each
+ * launch) and launch counts per class since the last read. */
+typedef struct {
+  double ms[OCP_K_COUNT];
+  int64_t launches[OCP_K_COUNT];
+} ocp_kernel_times;
+
+/* Turn timing on (enable != 0) or off for later calls on this handle.  While
+ * on, every launch of ocp_solve / ocp_adjoint records one event pair (events
+ * are created on first use and kept until ocp_destroy).  Errors: OCP_E_ARG. */
+ocp_status ocp_profile(ocp_handle h, int32_t enable);
+
+/* Wait for the recorded events, return the per-class totals in `out` (HOST
+ * struct) and reset them.  Errors: OCP_E_ARG, OCP_E_HIP. */
+ocp_status ocp_profile_read(ocp_handle h, ocp_kernel_times* out);
+
 #ifdef __cplusplus
 }
 #endif

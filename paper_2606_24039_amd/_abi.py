@@ -58,6 +58,14 @@ class ocp_qp_grads(C.Structure):
 
 
 # (name, restype, argtypes) for every symbol declared in include/ocp_admm.h
+K_FACTOR, K_ITER, K_CHECK, K_ADJOINT, K_SQP, K_OTHER, K_COUNT = range(7)
+K_NAMES = ("factor", "iter", "check", "adjoint", "sqp", "other")
+
+
+class ocp_kernel_times(C.Structure):
+    _fields_ = [("ms", C.c_double * K_COUNT), ("launches", C.c_int64 * K_COUNT)]
+
+
 SIGNATURES = [
     ("ocp_default_settings", None, [C.POINTER(ocp_settings)]),
     ("ocp_status_string", C.c_char_p, [C.c_int]),
@@ -72,6 +80,8 @@ SIGNATURES = [
     ("ocp_get_solution", C.c_int, [C.c_void_p, C.POINTER(ocp_solution), C.c_void_p]),
     ("ocp_adjoint", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_void_p, C.POINTER(ocp_qp_grads),
                               C.c_void_p]),
+    ("ocp_profile", C.c_int, [C.c_void_p, C.c_int32]),
+    ("ocp_profile_read", C.c_int, [C.c_void_p, C.POINTER(ocp_kernel_times)]),
 ]
 
 _LIB = None

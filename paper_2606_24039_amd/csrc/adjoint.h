@@ -50,7 +50,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   constexpr int n = NX + NU;
   Group g;
   g.lane = threadIdx.x & (ROW - 1);
-  const int slot = blockIdx.x * ROWS_PER_WAVE + (threadIdx.x >> 4);
+  const int slot = row_slot();
   if (slot >= L.B) return;
   g.b = L.order ? L.order[slot] : slot;
   g.s0 = L.stage_off[g.b];

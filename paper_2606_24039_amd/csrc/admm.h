@@ -478,7 +478,7 @@ __global__ void admm_init_kernel(Layout L, Settings st, int32_t* __restrict__ ne
 
 __device__ __forceinline__ bool row_group(const Layout& L, Group& g) {
   g.lane = threadIdx.x & (ROW - 1);
-  const int slot = blockIdx.x * ROWS_PER_WAVE + (threadIdx.x >> 4);
+  const int slot = row_slot();
   if (slot >= L.B) return false;
   g.b = L.order ? L.order[slot] : slot;
   g.s0 = L.stage_off[g.b];

@@ -234,7 +234,7 @@ template <typename T>
 __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs a) {
   constexpr int NA = 8;  // alpha in {1, 1/2, ..., 1/128}
   const int lane = threadIdx.x & (ROW - 1);
-  const int slot = blockIdx.x * ROWS_PER_WAVE + (threadIdx.x >> 4);
+  const int slot = row_slot();
   if (slot >= L.B) return;
   const int b = L.order ? L.order[slot] : slot;
   if (a.frozen[b]) return;

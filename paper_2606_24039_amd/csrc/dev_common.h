@@ -17,8 +17,13 @@
 
 namespace ocpk {
 
-constexpr int ROW = 16;           // lanes per instance (one DPP row)
-constexpr int ROWS_PER_WAVE = 4;  // instances per 64-wide wavefront
+constexpr int ROW = 16;  // lanes per instance (one DPP row)
+
+// Instance slot of this 16-lane row: a workgroup of 16 * R threads holds R
+// instances.  The sweeps are issue-bound per wavefront, so R = 4 (a full
+// wave of instances) does four times the work per issued instruction of
+// R = 1.
+__device__ __forceinline__ int row_slot() { return blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4); }
 
 // compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
 template <int B, int E, typename F>

@@ -18,40 +18,113 @@ using namespace ocpk;
 
 namespace {
 
+// instances per workgroup (one 16-lane row each)
+constexpr int kRowsPerWave = 4;
+
+// ---------------------------------------------------------------------------
+// kernel timing: optional HIP-event pairs around the solver's launches, by
+// kernel class (ocp_kernel_class).  Off by default; events are created on
+// first use and recycled after each read.
+// ---------------------------------------------------------------------------
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // 2 per recorded launch
+  std::vector<int> cls;
+  size_t used = 0;
+  double ms[OCP_K_COUNT] = {0};
+  int64_t launches[OCP_K_COUNT] = {0};
+
+  bool begin(int c, hipStream_t st) {
+    if (!on) return false;
+    if (2 * used + 2 > ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return false;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return false;
+      }
+      ev.push_back(a);
+      ev.push_back(b);
+      cls.push_back(c);
+    }
+    cls[used] = c;
+    (void)hipEventRecord(ev[2 * used], st);
+    return true;
+  }
+  void end(hipStream_t st) { (void)hipEventRecord(ev[2 * used++ + 1], st); }
+  hipError_t collect() {
+    for (size_t k = 0; k < used; ++k) {
+      hipError_t e = hipEventSynchronize(ev[2 * k + 1]);
+      if (e != hipSuccess) return e;
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
+      if (e != hipSuccess) return e;
+      ms[cls[k]] += t;
+      launches[cls[k]] += 1;
+    }
+    used = 0;
+    return hipSuccess;
+  }
+  void release() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    cls.clear();
+    used = 0;
+  }
+};
+
+// launch `f` bracketed by a timing pair of class `c` when timing is on
+template <typename F>
+void timed(Prof* p, int c, hipStream_t st, F&& f) {
+  const bool t = p && p->begin(c, st);
+  f();
+  if (t) p->end(st);
+}
+
 // ---------------------------------------------------------------------------
 // dispatch table: one instantiation per compiled (nx, nu, ng)
 // ---------------------------------------------------------------------------
-using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, int, hipStream_t);
-using AdjFn = void (*)(const Layout&, const AdjArgs&, int, hipStream_t);
+using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, int, hipStream_t, Prof*);
+using AdjFn = void (*)(const Layout&, const AdjArgs&, int, hipStream_t, Prof*);
 
 // One ADMM solve: init and factorisation, then up to each boundary (the next
 // multiple of k_check or k_rho, or the cap) the iterations, the FP64 check
 // and, after a rho change, the refactorisation of the instances concerned.
 template <typename T, int NX, int NU, int NG, typename ST>
-void launch_solve(const Layout& L, const Settings& s, int32_t* need, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((admm_init_kernel<T>), dim3(L.init_blocks), dim3(256), 0, st, L, s, need);
-  hipLaunchKernelGGL((admm_factor_kernel<T, NX, NU, NG>), dim3(grid), dim3(64), 0, st, L, s, need);
+void launch_solve(const Layout& L, const Settings& s, int32_t* need, int grid, hipStream_t st, Prof* pf) {
+  const dim3 blk(16 * kRowsPerWave);
+  timed(pf, OCP_K_OTHER, st,
+        [&] { hipLaunchKernelGGL((admm_init_kernel<T>), dim3(L.init_blocks), dim3(256), 0, st, L, s, need); });
+  timed(pf, OCP_K_FACTOR, st,
+        [&] { hipLaunchKernelGGL((admm_factor_kernel<T, NX, NU, NG>), dim3(grid), blk, 0, st, L, s, need); });
   const bool adapt_on = s.adapt_rho && s.k_rho > 0;
   int k = 0;
   while (k < s.max_iter) {
     int nb = s.max_iter;
     if (s.k_check > 0) nb = std::min(nb, (k / s.k_check + 1) * s.k_check);
     if (adapt_on) nb = std::min(nb, (k / s.k_rho + 1) * s.k_rho);
-    hipLaunchKernelGGL((admm_iter_kernel<T, NX, NU, NG, ST>), dim3(grid), dim3(64), 0, st, L, s, nb);
+    timed(pf, OCP_K_ITER, st,
+          [&] { hipLaunchKernelGGL((admm_iter_kernel<T, NX, NU, NG, ST>), dim3(grid), blk, 0, st, L, s, nb); });
     const int check = (s.k_check > 0 && nb % s.k_check == 0) ? 1 : 0;
     const int adapt = (adapt_on && nb % s.k_rho == 0 && nb < s.max_iter) ? 1 : 0;
     const int last = (nb == s.max_iter) ? 1 : 0;
     if (check || adapt || last)
-      hipLaunchKernelGGL((admm_check_kernel<T, NX, NU, NG>), dim3(grid), dim3(64), 0, st, L, s, need, check, adapt,
-                         last);
-    if (adapt) hipLaunchKernelGGL((admm_factor_kernel<T, NX, NU, NG>), dim3(grid), dim3(64), 0, st, L, s, need);
+      timed(pf, OCP_K_CHECK, st, [&] {
+        hipLaunchKernelGGL((admm_check_kernel<T, NX, NU, NG>), dim3(grid), blk, 0, st, L, s, need, check, adapt,
+                           last);
+      });
+    if (adapt)
+      timed(pf, OCP_K_FACTOR, st,
+            [&] { hipLaunchKernelGGL((admm_factor_kernel<T, NX, NU, NG>), dim3(grid), blk, 0, st, L, s, need); });
     k = nb;
   }
 }
 
 template <typename T, int NX, int NU, int NG, bool TI>
-void launch_adjoint(const Layout& L, const AdjArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG, TI>), dim3(grid), dim3(64), 0, st, L, a);
+void launch_adjoint(const Layout& L, const AdjArgs& a, int grid, hipStream_t st, Prof* pf) {
+  timed(pf, OCP_K_ADJOINT, st, [&] {
+    hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG, TI>), dim3(grid), dim3(16 * kRowsPerWave), 0, st, L, a);
+  });
 }
 
 // structure variants of the iteration kernel
@@ -138,6 +211,8 @@ struct ocp_handle_s {
   double *adj_v = nullptr, *adj_rg = nullptr;
   uint8_t soft_host[16] = {0};
   int8_t* adj_act = nullptr;
+
+  Prof prof;
 
   size_t tsz() const { return mixed ? sizeof(float) : sizeof(double); }
 };
@@ -485,13 +560,13 @@ ocp_status copy_out(ocp_handle h, const ocp_solution* o, hipStream_t st) {
 
 void run_admm(ocp_handle h, const Settings& s, hipStream_t st) {
   const Layout L = make_layout(h);
-  const int grid = (h->B + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
+  const int grid = (h->B + kRowsPerWave - 1) / kRowsPerWave;
   const int ti = h->ti ? 1 : 0;
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (ti ? VAR_TI : VAR_TV);
   if (h->mixed)
-    h->entry->f32[var](L, s, h->need, grid, st);
+    h->entry->f32[var](L, s, h->need, grid, st, &h->prof);
   else
-    h->entry->f64[var](L, s, h->need, grid, st);
+    h->entry->f64[var](L, s, h->need, grid, st, &h->prof);
 }
 
 BikeArgs make_bike(ocp_handle h, const ocp_settings* s) {
@@ -534,21 +609,26 @@ ocp_status bicycle_sqp(ocp_handle h, const ocp_settings* s, hipStream_t st) {
   const Layout L = make_layout(h);
   const int64_t S = h->S;
   const unsigned gs = (unsigned)((std::max<int64_t>(S, h->B) + 255) / 256);
-  const int grid = (h->B + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
-  if (!(s->warm_start && h->solved)) hipLaunchKernelGGL(bike_init_kernel, dim3(gs), dim3(256), 0, st, L, a, s->rho0);
+  const int grid = (h->B + kRowsPerWave - 1) / kRowsPerWave;
+  Prof* pf = &h->prof;
+  if (!(s->warm_start && h->solved))
+    timed(pf, OCP_K_OTHER, st,
+          [&] { hipLaunchKernelGGL(bike_init_kernel, dim3(gs), dim3(256), 0, st, L, a, s->rho0); });
   const Settings ad = make_settings(s, 1);
   for (int k = 0; k < s->max_sqp; ++k) {
-    if (h->mixed) {
-      hipLaunchKernelGGL(bike_linearize_kernel<float>, dim3(gs), dim3(256), 0, st, L, a);
-    } else {
-      hipLaunchKernelGGL(bike_linearize_kernel<double>, dim3(gs), dim3(256), 0, st, L, a);
-    }
+    timed(pf, OCP_K_SQP, st, [&] {
+      if (h->mixed)
+        hipLaunchKernelGGL(bike_linearize_kernel<float>, dim3(gs), dim3(256), 0, st, L, a);
+      else
+        hipLaunchKernelGGL(bike_linearize_kernel<double>, dim3(gs), dim3(256), 0, st, L, a);
+    });
     run_admm(h, ad, st);
-    if (h->mixed) {
-      hipLaunchKernelGGL(bike_linesearch_kernel<float>, dim3(grid), dim3(64), 0, st, L, a);
-    } else {
-      hipLaunchKernelGGL(bike_linesearch_kernel<double>, dim3(grid), dim3(64), 0, st, L, a);
-    }
+    timed(pf, OCP_K_SQP, st, [&] {
+      if (h->mixed)
+        hipLaunchKernelGGL(bike_linesearch_kernel<float>, dim3(grid), dim3(16 * kRowsPerWave), 0, st, L, a);
+      else
+        hipLaunchKernelGGL(bike_linesearch_kernel<double>, dim3(grid), dim3(16 * kRowsPerWave), 0, st, L, a);
+    });
   }
   return hip_ok(hipGetLastError());
 }
@@ -629,6 +709,7 @@ ocp_status ocp_create(const ocp_dims* d, const int32_t* horizons, ocp_handle* ou
 ocp_status ocp_destroy(ocp_handle h) {
   if (!h) return OCP_OK;
   (void)hipDeviceSynchronize();
+  h->prof.release();
   free_all(h);
   delete h;
   return OCP_OK;
@@ -809,14 +890,32 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   Layout L = make_layout(h);
   L.LinvTr = nullptr;  // the adjoint factor needs no iteration-precision copies
   L.MTr = nullptr;
-  const int grid = (h->B + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
+  const int grid = (h->B + kRowsPerWave - 1) / kRowsPerWave;
   const int ti = h->ti ? 1 : 0;
   if (h->mixed)
-    h->entry->adj32[ti](L, a, grid, st);
+    h->entry->adj32[ti](L, a, grid, st, &h->prof);
   else
-    h->entry->adj64[ti](L, a, grid, st);
+    h->entry->adj64[ti](L, a, grid, st, &h->prof);
   // the factor now holds the adjoint system: the next solve refactors from scratch
   return hip_ok(hipGetLastError());
+}
+
+ocp_status ocp_profile(ocp_handle h, int32_t enable) {
+  if (!h) return OCP_E_ARG;
+  h->prof.on = enable != 0;
+  return OCP_OK;
+}
+
+ocp_status ocp_profile_read(ocp_handle h, ocp_kernel_times* out) {
+  if (!h || !out) return OCP_E_ARG;
+  if (h->prof.collect() != hipSuccess) return OCP_E_HIP;
+  for (int c = 0; c < OCP_K_COUNT; ++c) {
+    out->ms[c] = h->prof.ms[c];
+    out->launches[c] = h->prof.launches[c];
+    h->prof.ms[c] = 0.0;
+    h->prof.launches[c] = 0;
+  }
+  return OCP_OK;
 }
 
 }  // extern "C"

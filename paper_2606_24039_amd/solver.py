@@ -135,17 +135,38 @@ class OCPSolver:
 
     def adjoint(self, dL_dx, settings=None, **overrides):
         s = settings if settings is not None else A.default_settings(**overrides)
-        f64 = dict(dtype=torch.float64, device=self.device)
-        g = {"d_q": torch.empty(self.S, self.n, **f64), "d_Ddiag": torch.empty(self.S, self.n, **f64),
-             "d_x_init": torch.empty(self.B, self.nx, **f64), "d_lo": torch.empty(self.S, self.ng, **f64),
-             "d_hi": torch.empty(self.S, self.ng, **f64), "eta_x": torch.empty(self.S, self.n, **f64),
-             "active": torch.empty(self.S, self.ng, dtype=torch.int8, device=self.device)}
-        gs = A.ocp_qp_grads(*[g[k].data_ptr() for k, _ in A.ocp_qp_grads._fields_])
+        g = self.alloc_grads()
+        gs = self.grads_struct(g)
         dl = _dev(dL_dx)
         A.check(self.lib.ocp_adjoint(self.h, C.byref(s), C.c_void_p(dl.data_ptr()), C.byref(gs), _stream()),
                 "ocp_adjoint")
         torch.cuda.current_stream().synchronize()
         return g
+
+    def profile(self, enable=True):
+        """Record HIP events around every kernel launch of later calls."""
+        A.check(self.lib.ocp_profile(self.h, int(bool(enable))), "ocp_profile")
+
+    def profile_read(self):
+        """{class: (total ms, launches)} since the last read (waits for the events)."""
+        t = A.ocp_kernel_times()
+        A.check(self.lib.ocp_profile_read(self.h, C.byref(t)), "ocp_profile_read")
+        return {name: (t.ms[k], int(t.launches[k])) for k, name in enumerate(A.K_NAMES)}
+
+    def adjoint_raw(self, settings, dl, grads_struct):
+        """Launch an adjoint with prebuilt arguments (no allocation, no sync)."""
+        A.check(self.lib.ocp_adjoint(self.h, C.byref(settings), C.c_void_p(dl.data_ptr()), C.byref(grads_struct),
+                                     _stream()), "ocp_adjoint")
+
+    def alloc_grads(self):
+        f64 = dict(dtype=torch.float64, device=self.device)
+        return {"d_q": torch.empty(self.S, self.n, **f64), "d_Ddiag": torch.empty(self.S, self.n, **f64),
+                "d_x_init": torch.empty(self.B, self.nx, **f64), "d_lo": torch.empty(self.S, self.ng, **f64),
+                "d_hi": torch.empty(self.S, self.ng, **f64), "eta_x": torch.empty(self.S, self.n, **f64),
+                "active": torch.empty(self.S, self.ng, dtype=torch.int8, device=self.device)}
+
+    def grads_struct(self, g):
+        return A.ocp_qp_grads(*[g[k].data_ptr() for k, _ in A.ocp_qp_grads._fields_])
 
     def split(self, arr, i):
         """Rows of a stage-concatenated array that belong to instance i."""

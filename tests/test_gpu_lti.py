@@ -138,3 +138,21 @@ def test_deterministic_across_runs():
     o2 = s.solve(_settings())
     for k in ("x", "y_f", "y_g", "z_g"):
         assert np.array_equal(o1[k].cpu().numpy(), o2[k].cpu().numpy())
+
+
+def test_kernel_timing_counts_launches():
+    """The library's event timing sees the schedule the host loop launches:
+    one factor + per-boundary iteration / check launches."""
+    b = random_lti(8, N=20, seed=2)
+    s = lti_solver(b, MIXED)
+    s.profile(True)
+    st = _settings(max_admm=100, k_check=25, k_rho=25)
+    s.solve(st)
+    t = s.profile_read()
+    assert t["iter"][1] == 4 and t["check"][1] == 4
+    assert t["factor"][1] >= 1 + 0 and t["factor"][1] <= 4
+    assert all(ms >= 0.0 for ms, _ in t.values()) and t["iter"][0] > 0.0
+    s.profile(False)
+    s.solve(st)
+    t2 = s.profile_read()
+    assert all(c == 0 for _, c in t2.values())
