@@ -208,7 +208,9 @@ enum {
   OCP_K_ADJOINT = 3, /* implicit-differentiation VJP (Algorithm 2) */
   OCP_K_SQP = 4,     /* bicycle linearisation and line search (Algorithm 1) */
   OCP_K_OTHER = 5,   /* per-solve initialisation */
-  OCP_K_COUNT = 6
+  OCP_K_SOLVE = 6,   /* persistent ADMM solve: factorisation, iterations, checks and rho
+                        adaptation of every instance in one launch (Algorithm 3) */
+  OCP_K_COUNT = 7
 };
 /* Accumulated GPU time (HIP events on the caller's stream, bracketing each
  * launch) and launch counts per class since the last read. */

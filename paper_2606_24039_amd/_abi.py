@@ -58,8 +58,8 @@ class ocp_qp_grads(C.Structure):
 
 
 # (name, restype, argtypes) for every symbol declared in include/ocp_admm.h
-K_FACTOR, K_ITER, K_CHECK, K_ADJOINT, K_SQP, K_OTHER, K_COUNT = range(7)
-K_NAMES = ("factor", "iter", "check", "adjoint", "sqp", "other")
+K_FACTOR, K_ITER, K_CHECK, K_ADJOINT, K_SQP, K_OTHER, K_SOLVE, K_COUNT = range(8)
+K_NAMES = ("factor", "iter", "check", "adjoint", "sqp", "other", "solve")
 
 
 class ocp_kernel_times(C.Structure):

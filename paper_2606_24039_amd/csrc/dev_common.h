@@ -84,24 +84,51 @@ __device__ __forceinline__ double row_gather(double v, int src) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int K, typename T>
-__device__ __forceinline__ void load_row(T (&dst)[K], const T* __restrict__ p, bool valid) {
+// Every buffer the kernels touch is device (global) memory.  Pointers that
+// reach a kernel through a structure whose address escapes (passed by
+// reference to a non-inlined function) lose that knowledge and would compile
+// to flat accesses; the helpers below restore it.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<const T> as_global(const T* p) {
+  return (gptr<const T>)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(gptr<T> p) {
+  return p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<const T> as_global(gptr<const T> p) {
+  return p;
+}
+
+template <int K, typename T, typename PT>
+__device__ __forceinline__ void load_row(T (&dst)[K], PT p_, bool valid) {
+  const gptr<const T> p = as_global(p_);
 #pragma unroll
   for (int k = 0; k < K; ++k) dst[k] = valid ? p[k] : T(0);
 }
 // dst[r] = base[r * stride] for r < R
-template <int R, typename T>
-__device__ __forceinline__ void load_col(T (&dst)[R], const T* __restrict__ p, int stride, bool valid) {
+template <int R, typename T, typename PT>
+__device__ __forceinline__ void load_col(T (&dst)[R], PT p_, int stride, bool valid) {
+  const gptr<const T> p = as_global(p_);
 #pragma unroll
   for (int r = 0; r < R; ++r) dst[r] = valid ? p[r * stride] : T(0);
 }
 template <int K, typename TD, typename TS>
-__device__ __forceinline__ void load_row_cvt(TD (&dst)[K], const TS* __restrict__ p, bool valid) {
+__device__ __forceinline__ void load_row_cvt(TD (&dst)[K], const TS* __restrict__ p_, bool valid) {
+  const gptr<const TS> p = as_global(p_);
 #pragma unroll
   for (int k = 0; k < K; ++k) dst[k] = valid ? TD(p[k]) : TD(0);
 }
 template <int R, typename TD, typename TS>
-__device__ __forceinline__ void load_col_cvt(TD (&dst)[R], const TS* __restrict__ p, int stride, bool valid) {
+__device__ __forceinline__ void load_col_cvt(TD (&dst)[R], const TS* __restrict__ p_, int stride, bool valid) {
+  const gptr<const TS> p = as_global(p_);
 #pragma unroll
   for (int r = 0; r < R; ++r) dst[r] = valid ? TD(p[r * stride]) : TD(0);
 }
@@ -145,13 +172,15 @@ struct Layout {
   const void* hiT;
   const void* xinitT;
 
-  // factor: FP64 master and iteration-precision copy; [S][n][n]
+  // factor, [S][n][n] row-major.  FP64 Linv_t and M_t (adjoint); in
+  // iteration precision for the ADMM substitutions: Linv_t, its transpose
+  // (row i = column i of Linv_t), W_t = Linv_t M_t, V_t = (M_{t+1} Linv_t)'
   double* Linv64;
   double* M64;
   void* LinvT;
-  void* MT;
-  void* LinvTr;  // iteration-precision transposes: row i = column i of Linv_t / M_t
-  void* MTr;
+  void* LinvTr;
+  void* WT;
+  void* VT;
   // structure of time-invariant LTI data: G rows are unit selectors
   int8_t gsel[16];  // variable selected by inequality row r
   int8_t ginv[16];  // inequality row selecting variable i, or -1

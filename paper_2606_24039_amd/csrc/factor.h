@@ -59,17 +59,40 @@ __device__ __forceinline__ void load_fac(FacStage<NX, NU, NG>& d, const Layout& 
   load_col<NX>(d.Apc, L.Ap + ti_or_tv(L.ti, b, s, (size_t)NX * n) + ic, n, t < N);
   load_col<NG>(d.Gc, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + ic, n, true);
 #pragma unroll
-  for (int r = 0; r < NG; ++r) d.w[r] = rhog_rows ? rhog_rows[(size_t)s * ROW + r] : rho_g;
+  for (int r = 0; r < NG; ++r) d.w[r] = rhog_rows ? as_global(rhog_rows)[(size_t)s * ROW + r] : rho_g;
+}
+
+// a[4 q + JJ] on row q (zero past the end of a)
+template <int JJ, int K, typename T>
+__device__ __forceinline__ T quarter_pick(const T (&a)[K], int q) {
+  T v[4];
+  sfor<0, 4>([&](auto r) {
+    constexpr int idx = 4 * decltype(r)::value + JJ;
+    if constexpr (idx < K)
+      v[decltype(r)::value] = a[idx];
+    else
+      v[decltype(r)::value] = T(0);
+  });
+  const T a0 = (q & 1) ? v[1] : v[0];
+  const T a1 = (q & 1) ? v[3] : v[2];
+  return (q & 2) ? a1 : a0;
 }
 
 // Factor one instance.  rhog_rows: optional per-row inequality weights
 // ([S][ROW], FP64); when null every inequality row uses rho_g.
 // HOIST: time-invariant blocks and uniform weights, so the rho-independent
 // products A^-'A^-, A^+'A^+, G'G and A^+'A^- are formed once per instance.
+// WV (the ADMM solve): the outputs are what the substitutions read in
+// iteration precision -- rows and columns of Linv_t and the products
+//   W_t = Linv_t M_t            (forward:  v_t  = Linv_t eta_t - W_t v_{t-1})
+//   V_t = (M_{t+1} Linv_t)'     (backward: x~_t = Linv_t' v_t - V_t x~_{t+1})
+// -- with the four 16-lane rows of the wavefront each forming and storing
+// the output columns 4 qrow .. 4 qrow + 3 (the recurrence itself runs on
+// every row).  Without WV (the adjoint) the FP64 Linv_t and M_t are stored.
 // Returns 0 on success, 1 on a non-positive / non-finite pivot.
-template <typename T, int NX, int NU, int NG, bool HOIST>
-__device__ int factor_instance(const Layout& L, const Group& g, double sigma, double rho_f, double rho_g,
-                               const double* __restrict__ rhog_rows) {
+template <typename T, int NX, int NU, int NG, bool HOIST, bool WV = false>
+__device__ __noinline__ int factor_instance(const Layout& L, const Group& g, double sigma, double rho_f, double rho_g,
+                                            const double* __restrict__ rhog_rows, int qrow = 0) {
   constexpr int n = NX + NU;
   const int i = g.lane;
   const bool vi = i < n;
@@ -78,6 +101,7 @@ __device__ int factor_instance(const Layout& L, const Group& g, double sigma, do
 
   double Mrow[n];     // row i of M_t
   double ApcPrev[NX]; // column i of A_{t-1}^+
+  double Xprev[WV ? n : 1];  // row i of Linv_{t-1}
 #pragma unroll
   for (int k = 0; k < n; ++k) Mrow[k] = 0.0;
 #pragma unroll
@@ -164,20 +188,38 @@ __device__ int factor_instance(const Layout& L, const Group& g, double sigma, do
         X[jj] = fma(-lik, bc<kk>(X[jj]), X[jj]);
       });
     });
-    if (vi) {
-      double* dst = L.Linv64 + (size_t)s * nn + (size_t)i * n;
+    if constexpr (WV) {
+      // rows / columns 4 qrow .. 4 qrow + 3 of Linv_t, W_t and V_{t-1}
+      const gptr<T> lr = as_global((T*)L.LinvT + (size_t)s * nn + (size_t)i * n);
+      const gptr<T> lc = as_global((T*)L.LinvTr + (size_t)s * nn + i);
+      const gptr<T> wr = as_global((T*)L.WT + (size_t)s * nn + (size_t)i * n);
+      const gptr<T> vc = as_global((T*)L.VT + (size_t)(t > 0 ? s - 1 : s) * nn + i);
+      sfor<0, 4>([&](auto jj_) {
+        constexpr int jj = decltype(jj_)::value;
+        const int j = 4 * qrow + jj;
+        const double xj = quarter_pick<jj>(X, qrow);
+        double wij = 0.0, uji = 0.0;
+        if (t > 0) {
+          // W_t[i][j] = sum_k Linv_t[i][k] M_t[k][j]
+          wij = dotb<n>(X, quarter_pick<jj>(Mrow, qrow), 0.0);
+          // (M_t Linv_{t-1})[i][j] = sum_k M_t[i][k] Linv_{t-1}[k][j]  (= V_{t-1}[j][i])
+          uji = dotb<n>(Mrow, quarter_pick<jj>(Xprev, qrow), 0.0);
+        }
+        if (vi && j < n) {
+          lr[j] = T(xj);
+          lc[(size_t)j * n] = T(xj);
+          if (t > 0) {
+            wr[j] = T(wij);
+            vc[(size_t)j * n] = T(uji);
+          }
+        }
+      });
+#pragma unroll
+      for (int k = 0; k < n; ++k) Xprev[k] = X[k];
+    } else if (vi) {
+      const gptr<double> dst = as_global(L.Linv64 + (size_t)s * nn + (size_t)i * n);
 #pragma unroll
       for (int j = 0; j < n; ++j) dst[j] = X[j];
-      if constexpr (!std::is_same<T, double>::value) {
-        T* dT = (T*)L.LinvT + (size_t)s * nn + (size_t)i * n;
-#pragma unroll
-        for (int j = 0; j < n; ++j) dT[j] = T(X[j]);
-      }
-      if (L.LinvTr) {  // transpose: lane i writes column i
-        T* dT = (T*)L.LinvTr + (size_t)s * nn + i;
-#pragma unroll
-        for (int j = 0; j < n; ++j) dT[(size_t)j * n] = T(X[j]);
-      }
     }
     if (t < N) {
       // Phi_t row i = E_t row i + rho_f sum_r A_t^+[r][i] A_t^-[r][:]
@@ -202,20 +244,10 @@ __device__ int factor_instance(const Layout& L, const Group& g, double sigma, do
         DotC<jj + 1, double>::template f<jj>(acc, xs, ps);
         Mrow[jj] = acc;
       });
-      if (vi) {
-        double* dst = L.M64 + (size_t)(s + 1) * nn + (size_t)i * n;
+      if (!WV && vi) {
+        const gptr<double> dst = as_global(L.M64 + (size_t)(s + 1) * nn + (size_t)i * n);
 #pragma unroll
         for (int j = 0; j < n; ++j) dst[j] = Mrow[j];
-        if constexpr (!std::is_same<T, double>::value) {
-          T* dT = (T*)L.MT + (size_t)(s + 1) * nn + (size_t)i * n;
-#pragma unroll
-          for (int j = 0; j < n; ++j) dT[j] = T(Mrow[j]);
-        }
-        if (L.MTr) {
-          T* dT = (T*)L.MTr + (size_t)(s + 1) * nn + i;
-#pragma unroll
-          for (int j = 0; j < n; ++j) dT[(size_t)j * n] = T(Mrow[j]);
-        }
       }
 #pragma unroll
       for (int r = 0; r < NX; ++r) ApcPrev[r] = cur.Apc[r];

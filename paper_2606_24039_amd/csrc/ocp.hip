@@ -13,6 +13,7 @@
 #include "bicycle.h"
 #include "ocp_admm.h"
 #include "setup.h"
+#include "wave.h"
 
 using namespace ocpk;
 
@@ -87,37 +88,16 @@ void timed(Prof* p, int c, hipStream_t st, F&& f) {
 using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, int, hipStream_t, Prof*);
 using AdjFn = void (*)(const Layout&, const AdjArgs&, int, hipStream_t, Prof*);
 
-// One ADMM solve: init and factorisation, then up to each boundary (the next
-// multiple of k_check or k_rho, or the cap) the iterations, the FP64 check
-// and, after a rho change, the refactorisation of the instances concerned.
+// One ADMM solve: per-solve initialisation, then one wavefront per instance
+// runs the whole of Algorithm 3 (factorisation, iterations, FP64 checks, rho
+// adaptation and refactorisation) without waiting for other instances.
 template <typename T, int NX, int NU, int NG, typename ST>
 void launch_solve(const Layout& L, const Settings& s, int32_t* need, int grid, hipStream_t st, Prof* pf) {
-  const dim3 blk(16 * kRowsPerWave);
+  (void)grid;
   timed(pf, OCP_K_OTHER, st,
         [&] { hipLaunchKernelGGL((admm_init_kernel<T>), dim3(L.init_blocks), dim3(256), 0, st, L, s, need); });
-  timed(pf, OCP_K_FACTOR, st,
-        [&] { hipLaunchKernelGGL((admm_factor_kernel<T, NX, NU, NG>), dim3(grid), blk, 0, st, L, s, need); });
-  const bool adapt_on = s.adapt_rho && s.k_rho > 0;
-  int k = 0;
-  while (k < s.max_iter) {
-    int nb = s.max_iter;
-    if (s.k_check > 0) nb = std::min(nb, (k / s.k_check + 1) * s.k_check);
-    if (adapt_on) nb = std::min(nb, (k / s.k_rho + 1) * s.k_rho);
-    timed(pf, OCP_K_ITER, st,
-          [&] { hipLaunchKernelGGL((admm_iter_kernel<T, NX, NU, NG, ST>), dim3(grid), blk, 0, st, L, s, nb); });
-    const int check = (s.k_check > 0 && nb % s.k_check == 0) ? 1 : 0;
-    const int adapt = (adapt_on && nb % s.k_rho == 0 && nb < s.max_iter) ? 1 : 0;
-    const int last = (nb == s.max_iter) ? 1 : 0;
-    if (check || adapt || last)
-      timed(pf, OCP_K_CHECK, st, [&] {
-        hipLaunchKernelGGL((admm_check_kernel<T, NX, NU, NG>), dim3(grid), blk, 0, st, L, s, need, check, adapt,
-                           last);
-      });
-    if (adapt)
-      timed(pf, OCP_K_FACTOR, st,
-            [&] { hipLaunchKernelGGL((admm_factor_kernel<T, NX, NU, NG>), dim3(grid), blk, 0, st, L, s, need); });
-    k = nb;
-  }
+  timed(pf, OCP_K_SOLVE, st,
+        [&] { hipLaunchKernelGGL((admm_solve_wave_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, s); });
 }
 
 template <typename T, int NX, int NU, int NG, bool TI>
@@ -186,7 +166,7 @@ struct ocp_handle_s {
   void *AmT = nullptr, *ApT = nullptr, *GT = nullptr, *qT = nullptr, *bdT = nullptr;
   void *loT = nullptr, *hiT = nullptr, *xinitT = nullptr;
   double *Linv64 = nullptr, *M64 = nullptr;
-  void *LinvT = nullptr, *MT = nullptr, *LinvTr = nullptr, *MTr = nullptr;
+  void *LinvT = nullptr, *LinvTr = nullptr, *WT = nullptr, *VT = nullptr;
   int variant = 0;
   int8_t gsel[16] = {0}, ginv[16] = {0};
   void *x = nullptr, *v = nullptr, *yf = nullptr, *zg = nullptr, *yg = nullptr, *xi = nullptr;
@@ -302,14 +282,14 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
       A_(h->bdT, ts * nx * blkI);
     }
     A_(h->LinvT, ts * nn * (S + 1));
-    A_(h->MT, ts * nn * (S + 1));
   }
   // factor and state carry one zero padding stage past the last instance
   const size_t S1 = (size_t)S + 1;
   A_(h->Linv64, sizeof(double) * nn * S1);
   A_(h->M64, sizeof(double) * nn * S1);
   A_(h->LinvTr, ts * nn * S1);
-  A_(h->MTr, ts * nn * S1);
+  A_(h->WT, ts * nn * S1);
+  A_(h->VT, ts * nn * S1);
   A_(h->x, ts * ROW * S1);
   A_(h->v, ts * ROW * S1);
   A_(h->yf, ts * ROW * S1);
@@ -357,7 +337,6 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
     h->qT = h->q;
     h->bdT = h->bd;
     h->LinvT = h->Linv64;
-    h->MT = h->M64;
   }
   // stage offsets and longest-first processing order (host -> device, once)
   std::vector<int64_t> off(B + 1, 0);
@@ -376,17 +355,18 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
       hipMemcpy(h->order, ord.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(h->soft, 0, 16) != hipSuccess || hipMemset(h->rho, 0, sizeof(double) * B) != hipSuccess)
     return OCP_E_HIP;
-  // M_0 of every instance and the padding stage stay zero for the lifetime of
-  // the handle (the factorisation writes M_1..M_N only); state starts at zero
+  // M_0, W_0 and V_N of every instance and the padding stage stay zero for
+  // the lifetime of the handle (the factorisations never write them); state
+  // starts at zero
   {
     const size_t S1 = (size_t)S + 1;
     const size_t tsz = h->tsz();
-    void* zero_bufs[] = {h->M64, h->MTr, h->x, h->v, h->yf, h->zg, h->yg, h->xi};
-    size_t zero_len[] = {sizeof(double) * nn * S1, tsz * nn * S1, tsz * ROW * S1, tsz * ROW * S1,
-                         tsz * ROW * S1,          tsz * ROW * S1, tsz * ROW * S1, tsz * ROW * S1};
-    for (int k = 0; k < 8; ++k)
+    void* zero_bufs[] = {h->M64, h->WT, h->VT, h->x, h->v, h->yf, h->zg, h->yg, h->xi};
+    size_t zero_len[] = {sizeof(double) * nn * S1, tsz * nn * S1,  tsz * nn * S1,
+                         tsz * ROW * S1,          tsz * ROW * S1, tsz * ROW * S1,
+                         tsz * ROW * S1,          tsz * ROW * S1, tsz * ROW * S1};
+    for (int k = 0; k < 9; ++k)
       if (hipMemset(zero_bufs[k], 0, zero_len[k]) != hipSuccess) return OCP_E_HIP;
-    if (h->mixed && hipMemset(h->MT, 0, tsz * nn * S1) != hipSuccess) return OCP_E_HIP;
   }
   return OCP_OK;
 }
@@ -448,9 +428,9 @@ Layout make_layout(ocp_handle h) {
   L.Linv64 = h->Linv64;
   L.M64 = h->M64;
   L.LinvT = h->LinvT;
-  L.MT = h->MT;
   L.LinvTr = h->LinvTr;
-  L.MTr = h->MTr;
+  L.WT = h->WT;
+  L.VT = h->VT;
   for (int k = 0; k < 16; ++k) {
     L.gsel[k] = h->gsel[k];
     L.ginv[k] = h->ginv[k];
@@ -887,9 +867,7 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   a.d_hi = out->d_hi;
   a.eta_x = out->eta_x;
   a.active = out->active;
-  Layout L = make_layout(h);
-  L.LinvTr = nullptr;  // the adjoint factor needs no iteration-precision copies
-  L.MTr = nullptr;
+  const Layout L = make_layout(h);
   const int grid = (h->B + kRowsPerWave - 1) / kRowsPerWave;
   const int ti = h->ti ? 1 : 0;
   if (h->mixed)
