@@ -79,7 +79,7 @@ struct TIBlocks {
 template <typename T, int NX, int NU, int NG>
 struct StagePtrs {
   static constexpr int n = NX + NU;
-  gptr<const T> Lr, Lc, Wr, Vr;     // rows of Linv_t, Linv_t', W_t, V_t
+  gptr<const T> SAr, SBr, CFr, CBr;  // rows of SubA, SubB, ChF, ChB
   gptr<const T> AmC, ApC, GC;       // column `lane` of the time-varying blocks
   gptr<const T> AmR, ApR, GR;       // row `lane` of the time-varying blocks
   gptr<const T> lo, hi, bd, q;
@@ -91,10 +91,10 @@ struct StagePtrs {
     const int ix = i < NX ? i : NX - 1;
     const int ig = i < NG ? i : NG - 1;
     const int64_t s0 = g.s0;
-    Lr = as_global((const T*)L.LinvT + (size_t)s0 * nn + (size_t)ir * n);
-    Lc = as_global((const T*)L.LinvTr + (size_t)s0 * nn + (size_t)ir * n);
-    Wr = as_global((const T*)L.WT + (size_t)s0 * nn + (size_t)ir * n);
-    Vr = as_global((const T*)L.VT + (size_t)s0 * nn + (size_t)ir * n);
+    SAr = as_global((const T*)L.SubA + (size_t)s0 * nn + (size_t)ir * n);
+    SBr = as_global((const T*)L.SubB + (size_t)s0 * nn + (size_t)ir * n);
+    CFr = as_global((const T*)L.ChF + (size_t)s0 * nn + (size_t)ir * n);
+    CBr = as_global((const T*)L.ChB + (size_t)s0 * nn + (size_t)ir * n);
     AmC = as_global((const T*)L.AmT + (size_t)s0 * NX * n + ir);
     ApC = as_global((const T*)L.ApT + (size_t)s0 * NX * n + ir);
     GC = as_global((const T*)L.GT + (size_t)s0 * NG * n + ir);
@@ -116,7 +116,7 @@ struct StagePtrs {
 };
 
 // prefetch distance (stages) of the substitution chains: deeper for FP32
-// (a chain stage holds one n-row of W_t or V_t plus one vector entry)
+// (a chain stage holds one n-row of a chain block plus one vector entry)
 template <typename T, int n>
 constexpr int chain_prefetch() {
   return sizeof(T) == 8 ? 4 : 8;

@@ -173,14 +173,15 @@ struct Layout {
   const void* xinitT;
 
   // factor, [S][n][n] row-major.  FP64 Linv_t and M_t (adjoint); in
-  // iteration precision for the ADMM substitutions: Linv_t, its transpose
-  // (row i = column i of Linv_t), W_t = Linv_t M_t, V_t = (M_{t+1} Linv_t)'
+  // iteration precision the blocks the ADMM substitutions read (factor.h,
+  // FACTOR_WV / FACTOR_PK): SubA multiplies eta_t, SubB the forward result,
+  // ChF / ChB carry the forward / backward chains
   double* Linv64;
   double* M64;
-  void* LinvT;
-  void* LinvTr;
-  void* WT;
-  void* VT;
+  void* SubA;
+  void* SubB;
+  void* ChF;
+  void* ChB;
   // structure of time-invariant LTI data: G rows are unit selectors
   int8_t gsel[16];  // variable selected by inequality row r
   int8_t ginv[16];  // inequality row selecting variable i, or -1

@@ -82,17 +82,29 @@ __device__ __forceinline__ T quarter_pick(const T (&a)[K], int q) {
 // ([S][ROW], FP64); when null every inequality row uses rho_g.
 // HOIST: time-invariant blocks and uniform weights, so the rho-independent
 // products A^-'A^-, A^+'A^+, G'G and A^+'A^- are formed once per instance.
-// WV (the ADMM solve): the outputs are what the substitutions read in
-// iteration precision -- rows and columns of Linv_t and the products
-//   W_t = Linv_t M_t            (forward:  v_t  = Linv_t eta_t - W_t v_{t-1})
-//   V_t = (M_{t+1} Linv_t)'     (backward: x~_t = Linv_t' v_t - V_t x~_{t+1})
-// -- with the four 16-lane rows of the wavefront each forming and storing
-// the output columns 4 qrow .. 4 qrow + 3 (the recurrence itself runs on
-// every row).  Without WV (the adjoint) the FP64 Linv_t and M_t are stored.
-// Returns 0 on success, 1 on a non-positive / non-finite pivot.
-template <typename T, int NX, int NU, int NG, bool HOIST, bool WV = false>
+// FORM selects the outputs (all row-major, [S][n][n]):
+//   FACTOR_M   (adjoint)  FP64 Linv_t and M_t.
+//   FACTOR_WV  (ADMM solve, FP32 iterations) in iteration precision
+//              SubA = Linv_t, SubB = Linv_t', ChF = W_t = Linv_t M_t (W_0 = 0),
+//              ChB = V_t = Linv_t' M_{t+1}' (V_N = 0):
+//                v_t = Linv_t eta_t - W_t v_{t-1},  x_t = Linv_t' v_t - V_t x_{t+1}.
+//   FACTOR_PK  (ADMM solve, FP64 iterations) SubB = P_t = (L_t L_t')^{-1},
+//              ChF = K_t = Phi_{t-1} P_{t-1} (K_0 = 0), ChB = Kb_t = K_{t+1}'
+//              (Kb_N = 0):
+//                v~_t = eta_t - K_t v~_{t-1},  x_t = P_t v~_t - Kb_t x_{t+1}
+//              (v~_t = L_t v_t; M_{t+1}' = Linv_t Phi_t').  Three blocks per
+//              stage instead of four, but P_t carries the full condition number
+//              of the Schur block, so FP32 iterations keep the Linv form.
+// In the two solve forms the four 16-lane rows of the wavefront each form and
+// store the output columns 4 qrow .. 4 qrow + 3 (the recurrence itself runs
+// on every row).  Returns 0 on success, 1 on a non-positive / non-finite pivot.
+enum { FACTOR_M = 0, FACTOR_WV = 1, FACTOR_PK = 2 };
+
+template <typename T, int NX, int NU, int NG, bool HOIST, int FORM = FACTOR_M>
 __device__ __noinline__ int factor_instance(const Layout& L, const Group& g, double sigma, double rho_f, double rho_g,
                                             const double* __restrict__ rhog_rows, int qrow = 0) {
+  constexpr bool WV = FORM == FACTOR_WV;
+  constexpr bool PK = FORM == FACTOR_PK;
   constexpr int n = NX + NU;
   const int i = g.lane;
   const bool vi = i < n;
@@ -188,12 +200,13 @@ __device__ __noinline__ int factor_instance(const Layout& L, const Group& g, dou
         X[jj] = fma(-lik, bc<kk>(X[jj]), X[jj]);
       });
     });
+    double Pc[PK ? 4 : 1];  // columns 4 qrow .. 4 qrow + 3 of P_t, row i
     if constexpr (WV) {
       // rows / columns 4 qrow .. 4 qrow + 3 of Linv_t, W_t and V_{t-1}
-      const gptr<T> lr = as_global((T*)L.LinvT + (size_t)s * nn + (size_t)i * n);
-      const gptr<T> lc = as_global((T*)L.LinvTr + (size_t)s * nn + i);
-      const gptr<T> wr = as_global((T*)L.WT + (size_t)s * nn + (size_t)i * n);
-      const gptr<T> vc = as_global((T*)L.VT + (size_t)(t > 0 ? s - 1 : s) * nn + i);
+      const gptr<T> lr = as_global((T*)L.SubA + (size_t)s * nn + (size_t)i * n);
+      const gptr<T> lc = as_global((T*)L.SubB + (size_t)s * nn + i);
+      const gptr<T> wr = as_global((T*)L.ChF + (size_t)s * nn + (size_t)i * n);
+      const gptr<T> vc = as_global((T*)L.ChB + (size_t)(t > 0 ? s - 1 : s) * nn + i);
       sfor<0, 4>([&](auto jj_) {
         constexpr int jj = decltype(jj_)::value;
         const int j = 4 * qrow + jj;
@@ -216,6 +229,27 @@ __device__ __noinline__ int factor_instance(const Layout& L, const Group& g, dou
       });
 #pragma unroll
       for (int k = 0; k < n; ++k) Xprev[k] = X[k];
+    } else if constexpr (PK) {
+      // Linv_t' through LDS: lane i receives column i of Linv_t
+      __shared__ double xt_lds[16 * 17];
+      if (qrow == 0 && vi) {
+#pragma unroll
+        for (int j = 0; j < n; ++j) xt_lds[i * 17 + j] = X[j];
+      }
+      __syncthreads();
+      double XT[n];
+      const int ic = vi ? i : n - 1;
+#pragma unroll
+      for (int k = 0; k < n; ++k) XT[k] = xt_lds[k * 17 + ic];
+      __syncthreads();  // the buffer is rewritten at the next stage
+      // P_t = Linv_t' Linv_t: P[i][j] = sum_k Linv_t[k][i] Linv_t[k][j]
+      const gptr<T> pr = as_global((T*)L.SubB + (size_t)s * nn + (size_t)i * n);
+      sfor<0, 4>([&](auto jj_) {
+        constexpr int jj = decltype(jj_)::value;
+        const int j = 4 * qrow + jj;
+        Pc[jj] = dotb<n>(XT, quarter_pick<jj>(X, qrow), 0.0);
+        if (vi && j < n) pr[j] = T(Pc[jj]);
+      });
     } else if (vi) {
       const gptr<double> dst = as_global(L.Linv64 + (size_t)s * nn + (size_t)i * n);
 #pragma unroll
@@ -244,7 +278,21 @@ __device__ __noinline__ int factor_instance(const Layout& L, const Group& g, dou
         DotC<jj + 1, double>::template f<jj>(acc, xs, ps);
         Mrow[jj] = acc;
       });
-      if (!WV && vi) {
+      if constexpr (PK) {
+        // K_{t+1} = Phi_t P_t (columns 4 qrow .. 4 qrow + 3 of row i) and its
+        // transpose Kb_t = K_{t+1}'
+        const gptr<T> kr = as_global((T*)L.ChF + (size_t)(s + 1) * nn + (size_t)i * n);
+        const gptr<T> kb = as_global((T*)L.ChB + (size_t)s * nn + i);
+        sfor<0, 4>([&](auto jj_) {
+          constexpr int jj = decltype(jj_)::value;
+          const int j = 4 * qrow + jj;
+          const double kij = dotb<n>(Phi, Pc[jj], 0.0);
+          if (vi && j < n) {
+            kr[j] = T(kij);
+            kb[(size_t)j * n] = T(kij);
+          }
+        });
+      } else if (!WV && vi) {
         const gptr<double> dst = as_global(L.M64 + (size_t)(s + 1) * nn + (size_t)i * n);
 #pragma unroll
         for (int j = 0; j < n; ++j) dst[j] = Mrow[j];

@@ -166,7 +166,7 @@ struct ocp_handle_s {
   void *AmT = nullptr, *ApT = nullptr, *GT = nullptr, *qT = nullptr, *bdT = nullptr;
   void *loT = nullptr, *hiT = nullptr, *xinitT = nullptr;
   double *Linv64 = nullptr, *M64 = nullptr;
-  void *LinvT = nullptr, *LinvTr = nullptr, *WT = nullptr, *VT = nullptr;
+  void *SubA = nullptr, *SubB = nullptr, *ChF = nullptr, *ChB = nullptr;
   int variant = 0;
   int8_t gsel[16] = {0}, ginv[16] = {0};
   void *x = nullptr, *v = nullptr, *yf = nullptr, *zg = nullptr, *yg = nullptr, *xi = nullptr;
@@ -281,15 +281,15 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
       A_(h->qT, ts * n * (size_t)S);
       A_(h->bdT, ts * nx * blkI);
     }
-    A_(h->LinvT, ts * nn * (S + 1));
   }
   // factor and state carry one zero padding stage past the last instance
   const size_t S1 = (size_t)S + 1;
   A_(h->Linv64, sizeof(double) * nn * S1);
   A_(h->M64, sizeof(double) * nn * S1);
-  A_(h->LinvTr, ts * nn * S1);
-  A_(h->WT, ts * nn * S1);
-  A_(h->VT, ts * nn * S1);
+  if (h->mixed) A_(h->SubA, ts * nn * S1);  // Linv_t (FP32 iterations only)
+  A_(h->SubB, ts * nn * S1);
+  A_(h->ChF, ts * nn * S1);
+  A_(h->ChB, ts * nn * S1);
   A_(h->x, ts * ROW * S1);
   A_(h->v, ts * ROW * S1);
   A_(h->yf, ts * ROW * S1);
@@ -336,7 +336,6 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
     h->xinitT = h->xinit;
     h->qT = h->q;
     h->bdT = h->bd;
-    h->LinvT = h->Linv64;
   }
   // stage offsets and longest-first processing order (host -> device, once)
   std::vector<int64_t> off(B + 1, 0);
@@ -355,13 +354,13 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
       hipMemcpy(h->order, ord.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(h->soft, 0, 16) != hipSuccess || hipMemset(h->rho, 0, sizeof(double) * B) != hipSuccess)
     return OCP_E_HIP;
-  // M_0, W_0 and V_N of every instance and the padding stage stay zero for
-  // the lifetime of the handle (the factorisations never write them); state
-  // starts at zero
+  // M_0 and the chain blocks of stage 0 (forward) and N (backward) of every
+  // instance, and the padding stage, stay zero for the lifetime of the handle
+  // (the factorisations never write them); state starts at zero
   {
     const size_t S1 = (size_t)S + 1;
     const size_t tsz = h->tsz();
-    void* zero_bufs[] = {h->M64, h->WT, h->VT, h->x, h->v, h->yf, h->zg, h->yg, h->xi};
+    void* zero_bufs[] = {h->M64, h->ChF, h->ChB, h->x, h->v, h->yf, h->zg, h->yg, h->xi};
     size_t zero_len[] = {sizeof(double) * nn * S1, tsz * nn * S1,  tsz * nn * S1,
                          tsz * ROW * S1,          tsz * ROW * S1, tsz * ROW * S1,
                          tsz * ROW * S1,          tsz * ROW * S1, tsz * ROW * S1};
@@ -427,10 +426,10 @@ Layout make_layout(ocp_handle h) {
   L.xinitT = h->xinitT;
   L.Linv64 = h->Linv64;
   L.M64 = h->M64;
-  L.LinvT = h->LinvT;
-  L.LinvTr = h->LinvTr;
-  L.WT = h->WT;
-  L.VT = h->VT;
+  L.SubA = h->SubA;
+  L.SubB = h->SubB;
+  L.ChF = h->ChF;
+  L.ChB = h->ChB;
   for (int k = 0; k < 16; ++k) {
     L.gsel[k] = h->gsel[k];
     L.ginv[k] = h->ginv[k];

@@ -2,23 +2,23 @@
 //
 // The 64 lanes form four 16-lane rows.  Work that is independent across
 // stages runs on four stages at once (stage t on row t mod 4); the two block
-// substitutions are serial chains over the horizon and run on row 0 alone,
-// one n-row matrix-vector product per stage, over the products W_t and V_t
-// that the factorisation prepares:
+// substitutions of S x~ = eta are serial chains over the horizon and run on
+// row 0 alone, one n-row matrix-vector product per stage, over the blocks the
+// factorisation prepares (factor.h: Linv/W/V for FP32 iterations, P/K for
+// FP64):
 //
-//   pass 1  rows   r_t  = Linv_t eta_t,  eta_t = sigma x_t - q_t + A_t^-'w_t
-//                         + A_{t-1}^+'w_{t-1} + [t=0](rho_f x_init - y_init)
-//                         + G_t'(rho_g z_t - y_t),  w_t = rho_f c_t - y_f,t
-//   pass 2  row 0  v_t  = r_t - W_t v_{t-1}           (t = 0..N)
-//   pass 3  rows   s_t  = Linv_t' v_t
-//   pass 4  row 0  x~_t = s_t - V_t x~_{t+1}          (t = N..0)
+//   pass 1  rows   eta_t = sigma x_t - q_t + A_t^-'w_t + A_{t-1}^+'w_{t-1}
+//                          + [t=0](rho_f x_init - y_init) + G_t'(rho_g z_t - y_t),
+//                  w_t = rho_f c_t - y_f,t;  r_t = Linv_t eta_t (FP32) or eta_t
+//   pass 2  row 0  v_t  = r_t - W_t v_{t-1}   (K_t)          (t = 0..N)
+//   pass 3  rows   s_t  = Linv_t' v_t         (P_t v_t)
+//   pass 4  row 0  x~_t = s_t - V_t x~_{t+1}  (Kb_t)         (t = N..0)
 //   pass 5  rows   over-relaxation, projection and dual update of every
 //                  constraint row of stage t from x~_t and x~_{t+1}
 //
-// (v_t = Linv_t (eta_t - M_t v_{t-1}) and x~_t = Linv_t'(v_t - M_{t+1}'
-// x~_{t+1}) with W_t = Linv_t M_t, V_t = Linv_t' M_{t+1}'.)  The passes hand
-// vectors to other lanes through the per-instance buffer v and are separated
-// by workgroup barriers (the workgroup is the one wavefront).
+// The passes hand vectors to other lanes through the per-instance buffer v
+// and are separated by workgroup barriers (the workgroup is the one
+// wavefront).
 #pragma once
 
 #include "admm.h"
@@ -48,7 +48,8 @@ __device__ __forceinline__ bool wave_group(const Layout& L, WaveGroup& w) {
 template <typename T, int NX, int NU, int NG, bool TI>
 struct EtaIn {
   static constexpr int n = NX + NU;
-  T Lr[n];  // row `lane` of Linv_t
+  static constexpr bool SA = sizeof(T) == 4;  // FP32 iterations multiply by Linv_t here
+  T Ar[SA ? n : 1];                           // row `lane` of SubA
   T x, q, yf, yfm, zg, yg, bd, bdm;
   T AmC[TI ? 1 : NX], ApCm[TI ? 1 : NX], GC[TI ? 1 : NG];
 };
@@ -57,7 +58,7 @@ template <typename T, int NX, int NU, int NG, bool TI>
 __device__ __forceinline__ void load_eta(EtaIn<T, NX, NU, NG, TI>& d, const StagePtrs<T, NX, NU, NG>& p, int t) {
   constexpr int n = NX + NU;
   const int tm = t > 0 ? t - 1 : 0;
-  load_row<n>(d.Lr, p.Lr + (size_t)t * n * n, true);
+  if constexpr (EtaIn<T, NX, NU, NG, TI>::SA) load_row<n>(d.Ar, p.SAr + (size_t)t * n * n, true);
   d.x = p.x[(size_t)t * ROW];
   d.q = p.q ? p.q[(size_t)t * n] : T(0);
   d.yf = p.yf[(size_t)t * ROW];
@@ -73,10 +74,10 @@ __device__ __forceinline__ void load_eta(EtaIn<T, NX, NU, NG, TI>& d, const Stag
   }
 }
 
-// pass-3 inputs: row `lane` of Linv_t' and v_t
+// pass-3 inputs: row `lane` of SubB and v_t
 template <typename T, int n>
 struct TrIn {
-  T Lc[n];
+  T Br[n];
   T v;
 };
 
@@ -109,7 +110,7 @@ __device__ __forceinline__ void load_upd(UpdIn<T, NX, NU, NG, TI>& d, const Stag
   }
 }
 
-// chain inputs of one stage: row `lane` of W_t (or V_t) and one vector entry
+// chain inputs of one stage: row `lane` of a chain block and one vector entry
 template <typename T, int n>
 struct ChainIn {
   T A[n];
@@ -126,7 +127,7 @@ __device__ __forceinline__ void load_chain(ChainIn<T, n>& d, gptr<const T> a, gp
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
 // One substitution chain on row 0: y_t = R[t] - B_t y_prev over the stages
-// in `dir` order (+1: 0..N with B = W; -1: N..0 with B = V); y_t -> R[t].
+// in `dir` order (+1: 0..N with B = ChF; -1: N..0 with B = ChB); y_t -> R[t].
 template <typename T, int n, int DIR>
 __device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, int N) {
   constexpr int PF = chain_prefetch<T, n>();
@@ -145,7 +146,7 @@ __device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, int N) {
       const int k = k0 + jj;
       if (k <= N) {
         ChainIn<T, n>& d = buf[jj];
-        const T y = d.r - dotb<n>(d.A, yprev, T(0));  // W_0 and V_N are zero slots
+        const T y = d.r - dotb<n>(d.A, yprev, T(0));  // stage 0 / N chain blocks are zero slots
         R[(size_t)stage(k) * ROW] = y;
         yprev = y;
         const int t = stage(min(k + PF, N));
@@ -168,7 +169,7 @@ __device__ __forceinline__ void wave_iteration(const Layout& L, const WaveGroup&
   const T yinit = P.yf[(size_t)N * ROW];  // initial-state multipliers (slot N)
   const gptr<T> R = P.v;                  // per-lane base of the exchange buffer
 
-  // ---------------- pass 1: r_t = Linv_t eta_t on row t mod 4 ----------------
+  // ---------------- pass 1: r_t (eta_t, times Linv_t for FP32) on row t mod 4 ----------------
   {
     EtaIn<T, NX, NU, NG, TI> cur, nxt;
     load_eta(cur, P, min(q, N));
@@ -200,36 +201,39 @@ __device__ __forceinline__ void wave_iteration(const Layout& L, const WaveGroup&
         } else {
           eta = dotb<NG>(cur.GC, u, eta);
         }
-        R[(size_t)t * ROW] = dotb<n>(cur.Lr, eta, T(0));
+        if constexpr (EtaIn<T, NX, NU, NG, TI>::SA)
+          R[(size_t)t * ROW] = dotb<n>(cur.Ar, eta, T(0));
+        else
+          R[(size_t)t * ROW] = eta;
       }
       cur = nxt;
     }
   }
   wave_sync();
 
-  // ---------------- pass 2: v_t = r_t - W_t v_{t-1} (row 0) ----------------
-  if (q == 0) chain<T, n, +1>(R, P.Wr, N);
+  // ---------------- pass 2: forward chain (row 0) ----------------
+  if (q == 0) chain<T, n, +1>(R, P.CFr, N);
   wave_sync();
 
-  // ---------------- pass 3: s_t = Linv_t' v_t on row t mod 4 ----------------
+  // ---------------- pass 3: s_t = SubB_t v_t on row t mod 4 ----------------
   {
     TrIn<T, n> cur, nxt;
     auto load_tr = [&](TrIn<T, n>& d, int t) {
-      load_row<n>(d.Lc, P.Lc + (size_t)t * nn, true);
+      load_row<n>(d.Br, P.SBr + (size_t)t * nn, true);
       d.v = R[(size_t)t * ROW];
     };
     load_tr(cur, min(q, N));
     for (int blk = 0; blk < nbl; ++blk) {
       const int t = 4 * blk + q;
       load_tr(nxt, min(t + 4, N));
-      if (t <= N) R[(size_t)t * ROW] = dotb<n>(cur.Lc, cur.v, T(0));
+      if (t <= N) R[(size_t)t * ROW] = dotb<n>(cur.Br, cur.v, T(0));
       cur = nxt;
     }
   }
   wave_sync();
 
-  // ---------------- pass 4: x~_t = s_t - V_t x~_{t+1} (row 0) ----------------
-  if (q == 0) chain<T, n, -1>(R, P.Vr, N);
+  // ---------------- pass 4: backward chain (row 0) ----------------
+  if (q == 0) chain<T, n, -1>(R, P.CBr, N);
   wave_sync();
 
   // ---------------- pass 5: constraint-row updates on row t mod 4 ----------------
@@ -486,7 +490,8 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
   bool need = true;
   for (;;) {
     if (need) {  // the only call site of the factorisation
-      const int bad = factor_instance<T, NX, NU, NG, ST::TI, true>(L, g, st.sigma, st.rho_f_scale * rho_bar,
+      constexpr int FORM = sizeof(T) == 4 ? FACTOR_WV : FACTOR_PK;
+      const int bad = factor_instance<T, NX, NU, NG, ST::TI, FORM>(L, g, st.sigma, st.rho_f_scale * rho_bar,
                                                                    rho_bar, nullptr, w.row);
       wave_sync();
       if (bad) {
