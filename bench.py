@@ -25,6 +25,16 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32 = 157.3  # TFLOP/s, MI355X vector FP32 (published)
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X vector FP64 (published)
+PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E (published)
+
+# HBM traffic of the persistent solve launch, per launch, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE) of `bench.py --steps 1 --warmup 0
+# --cpu-sample 0 --no-fp64`, each scaled by the same counter's reading for a
+# plain 1 GiB device copy (`bench.py --copy-calibration 1024`: FETCH_SIZE
+# reads 0.500 of the copied bytes, WRITE_SIZE 1.000).  Summary and commands:
+# profiles/admm_solve_wave_lti1024_n50.md.  Keyed by (workload, precision);
+# valid for the kernel as profiled -- set to None when the kernel changes.
+TRAFFIC_BYTES = {("c2", "mixed"): (25385892.0 * 2.0 + 7207149.7 * 1.0) * 1024}
 
 
 def log(*a):
@@ -47,6 +57,15 @@ def lti_flops_per_stage(nx, nu, ng):
     f_it = f_eta + f_sub + f_az + f_elem
     f_fac = 2 * nx * n * n + 2 * nx * n + n ** 3 + n ** 3 / 3 + n ** 3 / 3 + n ** 3
     return f_it, f_fac
+
+
+def lti_bytes_per_stage(n, ts, blocks):
+    """Algorithmic bytes one ADMM iteration moves per stage (HBM model: every
+    operand read and every result written once): `blocks` n x n factor blocks
+    (4 for FP32 iterations: Linv_t, Linv_t', W_t, V_t; 3 for FP64: P_t, K_t,
+    K_{t+1}') and 21 padded 16-entry stage vectors (12 read, 9 written over
+    the five passes)."""
+    return blocks * n * n * ts + 21 * 16 * ts
 
 
 def make_workload(name):
@@ -188,7 +207,21 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=256, help="instances timed on the oracle (0 = skip)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison")
     ap.add_argument("--no-grad", action="store_true", help="forward solves only (no adjoint in the step)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "copies": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: the batched solve has no "
                                    "cross-GPU exchange; run one process per GPU on disjoint instance shards"}))
@@ -208,24 +241,30 @@ def main():
         log(f"[bench] fp64: {json.dumps(fp64)}")
 
     value = mixed["solved"] / (mixed["ms_per_step"] * 1e-3)
-    # roofline of the dominant kernel (the persistent ADMM solve): algorithmic
-    # flops of all its launches in a step / its GPU time in a step (= average
-    # flops per launch / average launch duration).  FP32 iteration flops plus
-    # the FP64 factorisation flops, the latter weighted by the FP32/FP64 peak
-    # ratio; the FP64 residual checks (one per 25 iterations) are not counted.
+    # roofline of the dominant kernel (the persistent ADMM solve).  It streams
+    # the factor blocks of every running instance once per iteration and is
+    # bound by memory traffic while the batch is full (the FP32 factor copies
+    # of 1024 instances, 213 MB, exceed the L2), so the bound is HBM: achieved
+    # = algorithmic bytes of all its launches in a step / its GPU time in a
+    # step (= average bytes per launch / average launch duration).
     kit = mixed["kernels"]["solve"]
+    n = batch.nx + batch.nu
+    b_it = lti_bytes_per_stage(n, 4, 4)
+    bytes_launch = mixed["iters_sum"] * stages * b_it / max(kit["launches_per_step"], 1)
+    t_launch = kit["ms_per_step"] * 1e-3 / max(kit["launches_per_step"], 1)
+    achieved = bytes_launch / t_launch / 1e9
     F32 = mixed["iters_sum"] * stages * f_it
     F64 = mixed["nfact_sum"] * stages * f_fac
-    t_it = kit["ms_per_step"] * 1e-3
-    achieved = (F32 + F64 * PEAK_FP32 / PEAK_FP64) / t_it / 1e12
-    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32, 6), "traffic": None,
+    traffic = TRAFFIC_BYTES.get((args.workload, "mixed"))
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM, 5), "traffic": traffic,
             "kernel": f"admm_solve_wave_kernel<float,{batch.nx},{batch.nu},{batch.ng},box>",
-            "avg_launch_us": round(kit["ms_per_step"] / max(kit["launches_per_step"], 1) * 1e3, 2),
-            "launches_per_step": kit["launches_per_step"],
-            "flops_fp32_per_launch": F32 / max(kit["launches_per_step"], 1),
-            "flops_fp64_per_launch": F64 / max(kit["launches_per_step"], 1),
-            "flops_per_stage_iteration": f_it}
+            "avg_launch_us": round(t_launch * 1e6, 2), "launches_per_step": kit["launches_per_step"],
+            "bytes_per_launch": bytes_launch, "bytes_per_stage_iteration": b_it,
+            "alu_tflops": round((F32 + F64 * PEAK_FP32 / PEAK_FP64) / (t_launch * kit["launches_per_step"]) / 1e12,
+                                4),
+            "alu_frac_fp32_peak": round((F32 + F64 * PEAK_FP32 / PEAK_FP64) / (t_launch * kit["launches_per_step"])
+                                        / 1e12 / PEAK_FP32, 6)}
     out = {
         "metric": "QP solves/s at 1e-4 KKT residual, FP32+grad vs plain FP64, 1 MI355X",
         "value": round(value, 2), "unit": "QP solves/s", "n_gpus": 1, "steps": args.steps,
