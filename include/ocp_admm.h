@@ -228,6 +228,27 @@ ocp_status ocp_profile(ocp_handle h, int32_t enable);
  * struct) and reset them.  Errors: OCP_E_ARG, OCP_E_HIP. */
 ocp_status ocp_profile_read(ocp_handle h, ocp_kernel_times* out);
 
+/* Graph capture of a whole step (batching and scheduling: the launch sequence
+ * of one solve, and optionally the adjoint after it, recorded once and
+ * replayed without per-launch host work).  Records, on `stream` (not NULL),
+ * exactly the launches ocp_solve(h, s, out, stream) and -- when dL_dx and
+ * grads are both given -- ocp_adjoint(h, s, dL_dx, grads, stream) would issue
+ * now, into a HIP graph owned by the handle (replacing any earlier one).
+ * Nothing runs during capture.  The graph keeps the given device pointers:
+ * the caller keeps `out`, `dL_dx` and the `grads` buffers alive and in place
+ * while it replays.  Host-side decisions are frozen at capture time (for the
+ * bicycle model: a cold SQP start unless warm_start was set and a solve had
+ * run).  Kernel timing is suspended while capturing.  Errors: OCP_E_ARG
+ * (null handle / settings / stream, dL_dx without grads or vice versa),
+ * OCP_E_ORDER (no problem data), OCP_E_UNSUPPORTED (adjoint of L2-slack
+ * rows), OCP_E_HIP. */
+ocp_status ocp_graph_capture(ocp_handle h, const ocp_settings* s, const ocp_solution* out, const double* dL_dx,
+                             const ocp_qp_grads* grads, void* stream);
+
+/* Replay the captured graph on `stream`.  Errors: OCP_E_ARG, OCP_E_ORDER
+ * (nothing captured), OCP_E_HIP. */
+ocp_status ocp_graph_launch(ocp_handle h, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

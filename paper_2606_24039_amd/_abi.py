@@ -81,6 +81,9 @@ SIGNATURES = [
     ("ocp_adjoint", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_void_p, C.POINTER(ocp_qp_grads),
                               C.c_void_p]),
     ("ocp_profile", C.c_int, [C.c_void_p, C.c_int32]),
+    ("ocp_graph_capture", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.POINTER(ocp_solution), C.c_void_p,
+                                    C.POINTER(ocp_qp_grads), C.c_void_p]),
+    ("ocp_graph_launch", C.c_int, [C.c_void_p, C.c_void_p]),
     ("ocp_profile_read", C.c_int, [C.c_void_p, C.POINTER(ocp_kernel_times)]),
 ]
 

@@ -193,6 +193,8 @@ struct ocp_handle_s {
   int8_t* adj_act = nullptr;
 
   Prof prof;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
 
   size_t tsz() const { return mixed ? sizeof(float) : sizeof(double); }
 };
@@ -689,6 +691,8 @@ ocp_status ocp_destroy(ocp_handle h) {
   if (!h) return OCP_OK;
   (void)hipDeviceSynchronize();
   h->prof.release();
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
   free_all(h);
   delete h;
   return OCP_OK;
@@ -892,6 +896,54 @@ ocp_status ocp_profile_read(ocp_handle h, ocp_kernel_times* out) {
     h->prof.ms[c] = 0.0;
     h->prof.launches[c] = 0;
   }
+  return OCP_OK;
+}
+
+ocp_status ocp_graph_capture(ocp_handle h, const ocp_settings* s, const ocp_solution* out, const double* dL_dx,
+                             const ocp_qp_grads* grads, void* stream) {
+  if (!h || !s || !stream) return OCP_E_ARG;
+  if ((dL_dx == nullptr) != (grads == nullptr)) return OCP_E_ARG;
+  ocp_status st = check_settings(s);
+  if (st != OCP_OK) return st;
+  if (!h->data_set) return OCP_E_ORDER;
+  hipStream_t cs = (hipStream_t)stream;
+  if (h->graph_exec) {
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  const bool prof_on = h->prof.on;
+  h->prof.on = false;  // no event records inside the graph
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    h->prof.on = prof_on;
+    return OCP_E_HIP;
+  }
+  st = ocp_solve(h, s, out, stream);
+  if (st == OCP_OK && dL_dx) st = ocp_adjoint(h, s, dL_dx, grads, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &g);
+  h->prof.on = prof_on;
+  if (st != OCP_OK || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != OCP_OK ? st : OCP_E_HIP;
+  }
+  if (hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    h->graph_exec = nullptr;
+    return OCP_E_HIP;
+  }
+  h->graph = g;
+  return OCP_OK;
+}
+
+ocp_status ocp_graph_launch(ocp_handle h, void* stream) {
+  if (!h) return OCP_E_ARG;
+  if (!h->graph_exec) return OCP_E_ORDER;
+  if (hipGraphLaunch(h->graph_exec, (hipStream_t)stream) != hipSuccess) return OCP_E_HIP;
+  h->solved = true;
   return OCP_OK;
 }
 

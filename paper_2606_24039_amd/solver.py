@@ -168,6 +168,21 @@ class OCPSolver:
     def grads_struct(self, g):
         return A.ocp_qp_grads(*[g[k].data_ptr() for k, _ in A.ocp_qp_grads._fields_])
 
+    def graph_capture(self, settings, out, dl=None, grads=None):
+        """Record one solve (and the adjoint for dl, grads) into the handle's
+        HIP graph on the current stream; `out`, `dl` and `grads` must stay
+        alive and in place while the graph is replayed."""
+        sol = self.solution_struct(out)
+        gs = self.grads_struct(grads) if grads is not None else None
+        self._graph_keep = (out, dl, grads, sol, gs)
+        A.check(self.lib.ocp_graph_capture(self.h, C.byref(settings), C.byref(sol),
+                                           C.c_void_p(dl.data_ptr()) if dl is not None else None,
+                                           C.byref(gs) if gs is not None else None, _stream()),
+                "ocp_graph_capture")
+
+    def graph_launch(self):
+        A.check(self.lib.ocp_graph_launch(self.h, _stream()), "ocp_graph_launch")
+
     def split(self, arr, i):
         """Rows of a stage-concatenated array that belong to instance i."""
         return arr[int(self.stage_off[i]):int(self.stage_off[i + 1])]
