@@ -19,6 +19,11 @@ namespace ocpk {
 
 constexpr int ROW = 16;  // lanes per instance (one DPP row)
 
+// Padding stages on both sides of the factor-block and state buffers the
+// iteration streams: prefetches run up to this many stages past either end
+// of an instance without clamping (what they read there is never used).
+constexpr int STAGE_PAD = 8;
+
 // Instance slot of this 16-lane row: a workgroup of 16 * R threads holds R
 // instances.  The sweeps are issue-bound per wavefront, so R = 4 (a full
 // wave of instances) does four times the work per issued instruction of

@@ -284,20 +284,23 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
       A_(h->bdT, ts * nx * blkI);
     }
   }
-  // factor and state carry one zero padding stage past the last instance
+  // factor and state carry one zero padding stage past the last instance;
+  // the buffers the iteration streams carry STAGE_PAD more stages on both
+  // sides (pointers are moved past the leading ones below)
   const size_t S1 = (size_t)S + 1;
+  const size_t SP = S1 + 2 * (size_t)STAGE_PAD;
   A_(h->Linv64, sizeof(double) * nn * S1);
   A_(h->M64, sizeof(double) * nn * S1);
-  if (h->mixed) A_(h->SubA, ts * nn * S1);  // Linv_t (FP32 iterations only)
-  A_(h->SubB, ts * nn * S1);
-  A_(h->ChF, ts * nn * S1);
-  A_(h->ChB, ts * nn * S1);
-  A_(h->x, ts * ROW * S1);
-  A_(h->v, ts * ROW * S1);
-  A_(h->yf, ts * ROW * S1);
-  A_(h->zg, ts * ROW * S1);
-  A_(h->yg, ts * ROW * S1);
-  A_(h->xi, ts * ROW * S1);
+  if (h->mixed) A_(h->SubA, ts * nn * SP);  // Linv_t (FP32 iterations only)
+  A_(h->SubB, ts * nn * SP);
+  A_(h->ChF, ts * nn * SP);
+  A_(h->ChB, ts * nn * SP);
+  A_(h->x, ts * ROW * SP);
+  A_(h->v, ts * ROW * SP);
+  A_(h->yf, ts * ROW * SP);
+  A_(h->zg, ts * ROW * SP);
+  A_(h->yg, ts * ROW * SP);
+  A_(h->xi, ts * ROW * SP);
   A_(h->rho, sizeof(double) * B);
   A_(h->rprim, sizeof(double) * B);
   A_(h->rdual, sizeof(double) * B);
@@ -357,17 +360,19 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
       hipMemset(h->soft, 0, 16) != hipSuccess || hipMemset(h->rho, 0, sizeof(double) * B) != hipSuccess)
     return OCP_E_HIP;
   // M_0 and the chain blocks of stage 0 (forward) and N (backward) of every
-  // instance, and the padding stage, stay zero for the lifetime of the handle
-  // (the factorisations never write them); state starts at zero
+  // instance, and all padding, stay zero for the lifetime of the handle (the
+  // factorisations never write them); state starts at zero
   {
-    const size_t S1 = (size_t)S + 1;
     const size_t tsz = h->tsz();
-    void* zero_bufs[] = {h->M64, h->ChF, h->ChB, h->x, h->v, h->yf, h->zg, h->yg, h->xi};
-    size_t zero_len[] = {sizeof(double) * nn * S1, tsz * nn * S1,  tsz * nn * S1,
-                         tsz * ROW * S1,          tsz * ROW * S1, tsz * ROW * S1,
-                         tsz * ROW * S1,          tsz * ROW * S1, tsz * ROW * S1};
-    for (int k = 0; k < 9; ++k)
-      if (hipMemset(zero_bufs[k], 0, zero_len[k]) != hipSuccess) return OCP_E_HIP;
+    if (hipMemset(h->M64, 0, sizeof(double) * nn * S1) != hipSuccess) return OCP_E_HIP;
+    void** padded[] = {&h->SubA, &h->SubB, &h->ChF, &h->ChB, &h->x, &h->v, &h->yf, &h->zg, &h->yg, &h->xi};
+    const size_t stage_bytes[] = {tsz * nn,  tsz * nn,  tsz * nn,  tsz * nn,  tsz * ROW,
+                                  tsz * ROW, tsz * ROW, tsz * ROW, tsz * ROW, tsz * ROW};
+    for (int k = 0; k < 10; ++k) {
+      if (!*padded[k]) continue;
+      if (hipMemset(*padded[k], 0, stage_bytes[k] * SP) != hipSuccess) return OCP_E_HIP;
+      *padded[k] = (char*)*padded[k] + stage_bytes[k] * STAGE_PAD;
+    }
   }
   return OCP_OK;
 }

@@ -54,23 +54,27 @@ struct EtaIn {
   T AmC[TI ? 1 : NX], ApCm[TI ? 1 : NX], GC[TI ? 1 : NG];
 };
 
+// t may run up to STAGE_PAD - 1 stages past N: the padded state and factor
+// buffers are read unclamped, the exactly sized problem data at min(t, N)
 template <typename T, int NX, int NU, int NG, bool TI>
-__device__ __forceinline__ void load_eta(EtaIn<T, NX, NU, NG, TI>& d, const StagePtrs<T, NX, NU, NG>& p, int t) {
+__device__ __forceinline__ void load_eta(EtaIn<T, NX, NU, NG, TI>& d, const StagePtrs<T, NX, NU, NG>& p, int t,
+                                         int N) {
   constexpr int n = NX + NU;
-  const int tm = t > 0 ? t - 1 : 0;
-  if constexpr (EtaIn<T, NX, NU, NG, TI>::SA) load_row<n>(d.Ar, p.SAr + (size_t)t * n * n, true);
-  d.x = p.x[(size_t)t * ROW];
-  d.q = p.q ? p.q[(size_t)t * n] : T(0);
-  d.yf = p.yf[(size_t)t * ROW];
-  d.yfm = p.yf[(size_t)tm * ROW];
-  d.zg = p.zg[(size_t)t * ROW];
-  d.yg = p.yg[(size_t)t * ROW];
+  const int tc = min(t, N);
+  const int tm = tc > 0 ? tc - 1 : 0;
+  if constexpr (EtaIn<T, NX, NU, NG, TI>::SA) load_row<n>(d.Ar, p.SAr + (long)t * n * n, true);
+  d.x = p.x[(long)t * ROW];
+  d.q = p.q ? p.q[(size_t)tc * n] : T(0);
+  d.yf = p.yf[(long)t * ROW];
+  d.yfm = p.yf[(long)(t - 1) * ROW];
+  d.zg = p.zg[(long)t * ROW];
+  d.yg = p.yg[(long)t * ROW];
   if constexpr (!TI) {
-    d.bd = p.bd ? p.bd[(size_t)t * NX] : T(0);
+    d.bd = p.bd ? p.bd[(size_t)tc * NX] : T(0);
     d.bdm = p.bd ? p.bd[(size_t)tm * NX] : T(0);
-    load_col<NX>(d.AmC, p.AmC + (size_t)t * NX * n, n, true);
+    load_col<NX>(d.AmC, p.AmC + (size_t)tc * NX * n, n, true);
     load_col<NX>(d.ApCm, p.ApC + (size_t)tm * NX * n, n, true);
-    load_col<NG>(d.GC, p.GC + (size_t)t * NG * n, n, true);
+    load_col<NG>(d.GC, p.GC + (size_t)tc * NG * n, n, true);
   }
 }
 
@@ -94,19 +98,20 @@ template <typename T, int NX, int NU, int NG, bool TI>
 __device__ __forceinline__ void load_upd(UpdIn<T, NX, NU, NG, TI>& d, const StagePtrs<T, NX, NU, NG>& p,
                                          gptr<const T> R, int t, int N) {
   constexpr int n = NX + NU;
-  d.xt = R[(size_t)t * ROW];
-  d.xt1 = (t < N) ? R[(size_t)(t + 1) * ROW] : T(0);
-  d.x = p.x[(size_t)t * ROW];
-  d.yf = p.yf[(size_t)t * ROW];
-  d.zg = p.zg[(size_t)t * ROW];
-  d.yg = p.yg[(size_t)t * ROW];
+  const int tc = min(t, N);
+  d.xt = R[(long)t * ROW];
+  d.xt1 = (t < N) ? R[(long)(t + 1) * ROW] : T(0);
+  d.x = p.x[(long)t * ROW];
+  d.yf = p.yf[(long)t * ROW];
+  d.zg = p.zg[(long)t * ROW];
+  d.yg = p.yg[(long)t * ROW];
   if constexpr (!TI) {
-    d.lo = p.lo[(size_t)t * NG];
-    d.hi = p.hi[(size_t)t * NG];
-    d.bd = p.bd ? p.bd[(size_t)t * NX] : T(0);
-    load_row<n>(d.AmR, p.AmR + (size_t)t * NX * n, true);
-    load_row<n>(d.ApR, p.ApR + (size_t)t * NX * n, true);
-    load_row<n>(d.GR, p.GR + (size_t)t * NG * n, true);
+    d.lo = p.lo[(size_t)tc * NG];
+    d.hi = p.hi[(size_t)tc * NG];
+    d.bd = p.bd ? p.bd[(size_t)tc * NX] : T(0);
+    load_row<n>(d.AmR, p.AmR + (size_t)tc * NX * n, true);
+    load_row<n>(d.ApR, p.ApR + (size_t)tc * NX * n, true);
+    load_row<n>(d.GR, p.GR + (size_t)tc * NG * n, true);
   }
 }
 
@@ -131,29 +136,37 @@ __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 template <typename T, int n, int DIR>
 __device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, int N) {
   constexpr int PF = chain_prefetch<T, n>();
-  const size_t nn = (size_t)n * n;
-  auto stage = [&](int k) { return DIR > 0 ? k : N - k; };  // k-th stage of the sweep
+  static_assert(PF <= STAGE_PAD, "prefetch reaches past the buffer padding");
+  constexpr long dB = DIR * (long)n * n;  // block stride of one step of the sweep
+  constexpr long dR = DIR * (long)ROW;
+  // running pointers at the sweep's k0-th stage (t = 0 forward, t = N
+  // backward); prefetches run up to PF stages past either end of the
+  // instance, into the neighbouring instances or the padding
+  gptr<const T> Bk = Bm + (DIR > 0 ? 0 : (long)N * n * n);
+  gptr<T> Rk = R + (DIR > 0 ? 0 : (long)N * ROW);
   ChainIn<T, n> buf[PF];
   sfor<0, PF>([&](auto j) {
     constexpr int jj = decltype(j)::value;
-    const int t = stage(min(jj, N));
-    load_chain(buf[jj], Bm + (size_t)t * nn, R + (size_t)t * ROW);
+    load_chain(buf[jj], Bk + jj * dB, Rk + jj * dR);
   });
   T yprev = T(0);
-  for (int k0 = 0; k0 <= N; k0 += PF) {
-    sfor<0, PF>([&](auto j) {
-      constexpr int jj = decltype(j)::value;
-      const int k = k0 + jj;
-      if (k <= N) {
-        ChainIn<T, n>& d = buf[jj];
-        const T y = d.r - dotb<n>(d.A, yprev, T(0));  // stage 0 / N chain blocks are zero slots
-        R[(size_t)stage(k) * ROW] = y;
-        yprev = y;
-        const int t = stage(min(k + PF, N));
-        load_chain(d, Bm + (size_t)t * nn, R + (size_t)t * ROW);
-      }
-    });
+  auto body = [&](auto j) {
+    constexpr int jj = decltype(j)::value;
+    ChainIn<T, n>& d = buf[jj];
+    const T y = d.r - dotb<n>(d.A, yprev, T(0));  // stage 0 / N chain blocks are zero slots
+    Rk[jj * dR] = y;
+    yprev = y;
+    load_chain(d, Bk + (jj + PF) * dB, Rk + (jj + PF) * dR);
+  };
+  int k0 = 0;
+  for (; k0 + PF - 1 <= N; k0 += PF) {
+    sfor<0, PF>(body);
+    Bk += PF * dB;
+    Rk += PF * dR;
   }
+  sfor<0, PF>([&](auto j) {
+    if (k0 + decltype(j)::value <= N) body(j);
+  });
 }
 
 template <typename T, int NX, int NU, int NG, typename ST>
@@ -172,10 +185,10 @@ __device__ __forceinline__ void wave_iteration(const Layout& L, const WaveGroup&
   // ---------------- pass 1: r_t (eta_t, times Linv_t for FP32) on row t mod 4 ----------------
   {
     EtaIn<T, NX, NU, NG, TI> cur, nxt;
-    load_eta(cur, P, min(q, N));
+    load_eta(cur, P, q, N);  // stages past N read padding or the next instance (unused)
     for (int blk = 0; blk < nbl; ++blk) {
       const int t = 4 * blk + q;
-      load_eta(nxt, P, min(t + 4, N));
+      load_eta(nxt, P, t + 4, N);
       if (t <= N) {
         T eta = sigma * cur.x - cur.q;
         const T w_ = (t < N && i < NX) ? rho_f * (TI ? tb.bd : cur.bd) - cur.yf : T(0);
@@ -222,10 +235,10 @@ __device__ __forceinline__ void wave_iteration(const Layout& L, const WaveGroup&
       load_row<n>(d.Br, P.SBr + (size_t)t * nn, true);
       d.v = R[(size_t)t * ROW];
     };
-    load_tr(cur, min(q, N));
+    load_tr(cur, q);
     for (int blk = 0; blk < nbl; ++blk) {
       const int t = 4 * blk + q;
-      load_tr(nxt, min(t + 4, N));
+      load_tr(nxt, t + 4);
       if (t <= N) R[(size_t)t * ROW] = dotb<n>(cur.Br, cur.v, T(0));
       cur = nxt;
     }
@@ -241,10 +254,10 @@ __device__ __forceinline__ void wave_iteration(const Layout& L, const WaveGroup&
     const T oma = T(1) - alpha;
     const T rfa = rho_f * alpha;
     UpdIn<T, NX, NU, NG, TI> cur, nxt;
-    load_upd(cur, P, R, min(q, N), N);
+    load_upd(cur, P, R, q, N);
     for (int blk = 0; blk < nbl; ++blk) {
       const int t = 4 * blk + q;
-      load_upd(nxt, P, R, min(t + 4, N), N);
+      load_upd(nxt, P, R, t + 4, N);
       if (t <= N) {
         const T xt = cur.xt, xt1 = cur.xt1;
         const size_t o = (size_t)t * ROW;
