@@ -100,7 +100,10 @@ __device__ __forceinline__ T quarter_pick(const T (&a)[K], int q) {
 // on every row).  Returns 0 on success, 1 on a non-positive / non-finite pivot.
 enum { FACTOR_M = 0, FACTOR_WV = 1, FACTOR_PK = 2 };
 
-template <typename T, int NX, int NU, int NG, bool HOIST, int FORM = FACTOR_M>
+// TAG only separates the instantiations called from kernels with different
+// occupancy targets (the register budget of a called function follows its
+// callers).
+template <typename T, int NX, int NU, int NG, bool HOIST, int FORM = FACTOR_M, int TAG = 0>
 __device__ __noinline__ int factor_instance(const Layout& L, const Group& g, double sigma, double rho_f, double rho_g,
                                             const double* __restrict__ rhog_rows, int qrow = 0) {
   constexpr bool WV = FORM == FACTOR_WV;

@@ -85,15 +85,14 @@ void timed(Prof* p, int c, hipStream_t st, F&& f) {
 // ---------------------------------------------------------------------------
 // dispatch table: one instantiation per compiled (nx, nu, ng)
 // ---------------------------------------------------------------------------
-using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, int, hipStream_t, Prof*);
+using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, hipStream_t, Prof*);
 using AdjFn = void (*)(const Layout&, const AdjArgs&, int, hipStream_t, Prof*);
 
 // One ADMM solve: per-solve initialisation, then one wavefront per instance
 // runs the whole of Algorithm 3 (factorisation, iterations, FP64 checks, rho
 // adaptation and refactorisation) without waiting for other instances.
 template <typename T, int NX, int NU, int NG, typename ST>
-void launch_solve(const Layout& L, const Settings& s, int32_t* need, int grid, hipStream_t st, Prof* pf) {
-  (void)grid;
+void launch_solve(const Layout& L, const Settings& s, int32_t* need, hipStream_t st, Prof* pf) {
   timed(pf, OCP_K_OTHER, st,
         [&] { hipLaunchKernelGGL((admm_init_kernel<T>), dim3(L.init_blocks), dim3(256), 0, st, L, s, need); });
   timed(pf, OCP_K_SOLVE, st,
@@ -546,13 +545,12 @@ ocp_status copy_out(ocp_handle h, const ocp_solution* o, hipStream_t st) {
 
 void run_admm(ocp_handle h, const Settings& s, hipStream_t st) {
   const Layout L = make_layout(h);
-  const int grid = (h->B + kRowsPerWave - 1) / kRowsPerWave;
   const int ti = h->ti ? 1 : 0;
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (ti ? VAR_TI : VAR_TV);
   if (h->mixed)
-    h->entry->f32[var](L, s, h->need, grid, st, &h->prof);
+    h->entry->f32[var](L, s, h->need, st, &h->prof);
   else
-    h->entry->f64[var](L, s, h->need, grid, st, &h->prof);
+    h->entry->f64[var](L, s, h->need, st, &h->prof);
 }
 
 BikeArgs make_bike(ocp_handle h, const ocp_settings* s) {

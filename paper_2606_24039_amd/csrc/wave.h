@@ -115,6 +115,28 @@ __device__ __forceinline__ void load_upd(UpdIn<T, NX, NU, NG, TI>& d, const Stag
   }
 }
 
+// the state part of the pass-5 inputs (x~ comes from elsewhere); t may lie
+// up to STAGE_PAD stages outside 0..N (padded state read unclamped, problem
+// data at the nearest stage)
+template <typename T, int NX, int NU, int NG, bool TI>
+__device__ __forceinline__ void load_upd_state(UpdIn<T, NX, NU, NG, TI>& d, const StagePtrs<T, NX, NU, NG>& p, int t,
+                                               int N) {
+  constexpr int n = NX + NU;
+  const int tc = t < 0 ? 0 : (t > N ? N : t);
+  d.x = p.x[(long)t * ROW];
+  d.yf = p.yf[(long)t * ROW];
+  d.zg = p.zg[(long)t * ROW];
+  d.yg = p.yg[(long)t * ROW];
+  if constexpr (!TI) {
+    d.lo = p.lo[(size_t)tc * NG];
+    d.hi = p.hi[(size_t)tc * NG];
+    d.bd = p.bd ? p.bd[(size_t)tc * NX] : T(0);
+    load_row<n>(d.AmR, p.AmR + (size_t)tc * NX * n, true);
+    load_row<n>(d.ApR, p.ApR + (size_t)tc * NX * n, true);
+    load_row<n>(d.GR, p.GR + (size_t)tc * NG * n, true);
+  }
+}
+
 // chain inputs of one stage: row `lane` of a chain block and one vector entry
 template <typename T, int n>
 struct ChainIn {
@@ -169,56 +191,121 @@ __device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, int N) {
   });
 }
 
+// Scalars of one ADMM iteration of one instance (this lane's view).
 template <typename T, int NX, int NU, int NG, typename ST>
-__device__ __forceinline__ void wave_iteration(const Layout& L, const WaveGroup& w, const TIBlocks<T, NX, NU, NG>& tb,
-                                               const StagePtrs<T, NX, NU, NG>& P, T sigma, T rho_f, T rho_g,
-                                               T alpha, int kind, const ProjConst<T>& pc, T xinit, int gsel,
-                                               int ginv) {
+struct IterCtx {
+  const TIBlocks<T, NX, NU, NG>& tb;
+  const StagePtrs<T, NX, NU, NG>& P;
+  T sigma, rho_f, rho_g, alpha, oma, rfa;
+  int kind;
+  ProjConst<T> pc;
+  T xinit, yinit;
+  int gsel, ginv;
+  int i, N;
+};
+
+// r_t of the stage on this row: eta_t, times Linv_t for FP32 iterations
+template <typename T, int NX, int NU, int NG, typename ST>
+__device__ __forceinline__ T stage_r(const IterCtx<T, NX, NU, NG, ST>& c, const EtaIn<T, NX, NU, NG, ST::TI>& cur,
+                                     int t) {
   constexpr int n = NX + NU;
   constexpr bool TI = ST::TI;
-  const int i = w.lane, q = w.row, N = w.N;
+  const int i = c.i, N = c.N;
+  const auto& tb = c.tb;
+  T eta = c.sigma * cur.x - cur.q;
+  const T w_ = (t < N && i < NX) ? c.rho_f * (TI ? tb.bd : cur.bd) - cur.yf : T(0);
+  const T wm = (t > 0 && i < NX) ? c.rho_f * (TI ? tb.bd : cur.bdm) - cur.yfm : T(0);
+  if constexpr (TI)
+    eta = dotb<NX>(tb.AmC, w_, eta);
+  else
+    eta = dotb<NX>(cur.AmC, w_, eta);
+  if constexpr (ST::APNEG) {
+    eta -= wm;
+  } else if constexpr (TI) {
+    eta = dotb<NX>(tb.ApC, wm, eta);
+  } else {
+    eta = dotb<NX>(cur.ApCm, wm, eta);
+  }
+  eta += (t == 0 && i < NX) ? c.rho_f * c.xinit - c.yinit : T(0);
+  const T u = (i < NG) ? c.rho_g * cur.zg - cur.yg : T(0);
+  if constexpr (ST::GSEL) {
+    const T gu = row_gather(u, c.ginv < 0 ? 0 : c.ginv);
+    eta += (c.ginv >= 0) ? gu : T(0);
+  } else if constexpr (TI) {
+    eta = dotb<NG>(tb.GC, u, eta);
+  } else {
+    eta = dotb<NG>(cur.GC, u, eta);
+  }
+  if constexpr (EtaIn<T, NX, NU, NG, TI>::SA)
+    return dotb<n>(cur.Ar, eta, T(0));
+  else
+    return eta;
+}
+
+// over-relaxation, projection and dual update of every constraint row of
+// the stage on this row, from x~_t and x~_{t+1}
+template <typename T, int NX, int NU, int NG, typename ST>
+__device__ __forceinline__ void stage_update(const IterCtx<T, NX, NU, NG, ST>& c,
+                                             const UpdIn<T, NX, NU, NG, ST::TI>& cur, T xt, T xt1, int t) {
+  constexpr int n = NX + NU;
+  constexpr bool TI = ST::TI;
+  const int i = c.i, N = c.N;
+  const auto& tb = c.tb;
+  const auto& P = c.P;
+  const size_t o = (size_t)t * ROW;
+  // dynamics row t: y_f += rho_f alpha (A^- x~_t + A^+ x~_{t+1} - c_t)
+  T zf;
+  if constexpr (TI)
+    zf = dotb<n>(tb.AmR, xt, T(0));
+  else
+    zf = dotb<n>(cur.AmR, xt, T(0));
+  if constexpr (ST::APNEG) {
+    zf -= xt1;
+  } else if constexpr (TI) {
+    zf = dotb<n>(tb.ApR, xt1, zf);
+  } else {
+    zf = dotb<n>(cur.ApR, xt1, zf);
+  }
+  if (t < N) P.yf[o] = cur.yf + c.rfa * (zf - (TI ? tb.bd : cur.bd));
+  // inequality rows of stage t (lanes past ng update padding)
+  T zt;
+  if constexpr (ST::GSEL)
+    zt = row_gather(xt, c.gsel);
+  else if constexpr (TI)
+    zt = dotb<n>(tb.GR, xt, T(0));
+  else
+    zt = dotb<n>(cur.GR, xt, T(0));
+  const T zh = c.alpha * zt + c.oma * cur.zg;
+  const Proj<T> pr =
+      project_row<T>(fma(cur.yg, c.pc.inv_rho, zh), TI ? tb.lo : cur.lo, TI ? tb.hi : cur.hi, c.kind, c.pc);
+  P.zg[o] = pr.z;
+  P.xi[o] = pr.xi;
+  P.yg[o] = cur.yg + c.rho_g * (zh - pr.z);
+  P.x[o] = c.alpha * xt + c.oma * cur.x;
+  // initial-state rows: y_init += rho_f alpha (x~_0 - x_init)
+  if (t == 0 && i < NX) P.yf[(size_t)N * ROW] = c.yinit + c.rfa * (xt - c.xinit);
+}
+
+// One iteration on one wavefront (the vectors handed between passes go
+// through the instance's v buffer in global memory).
+template <typename T, int NX, int NU, int NG, typename ST>
+__device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>& c, int q) {
+  constexpr int n = NX + NU;
+  constexpr bool TI = ST::TI;
+  const int N = c.N;
   const int nbl = (N + 4) / 4;  // 4-stage blocks covering 0..N
   const size_t nn = (size_t)n * n;
-  const T yinit = P.yf[(size_t)N * ROW];  // initial-state multipliers (slot N)
-  const gptr<T> R = P.v;                  // per-lane base of the exchange buffer
+  const auto& P = c.P;
+  const gptr<T> R = P.v;  // per-lane base of the exchange buffer
 
-  // ---------------- pass 1: r_t (eta_t, times Linv_t for FP32) on row t mod 4 ----------------
+  // ---------------- pass 1: r_t on row t mod 4 ----------------
   {
     EtaIn<T, NX, NU, NG, TI> cur, nxt;
     load_eta(cur, P, q, N);  // stages past N read padding or the next instance (unused)
     for (int blk = 0; blk < nbl; ++blk) {
       const int t = 4 * blk + q;
       load_eta(nxt, P, t + 4, N);
-      if (t <= N) {
-        T eta = sigma * cur.x - cur.q;
-        const T w_ = (t < N && i < NX) ? rho_f * (TI ? tb.bd : cur.bd) - cur.yf : T(0);
-        const T wm = (t > 0 && i < NX) ? rho_f * (TI ? tb.bd : cur.bdm) - cur.yfm : T(0);
-        if constexpr (TI)
-          eta = dotb<NX>(tb.AmC, w_, eta);
-        else
-          eta = dotb<NX>(cur.AmC, w_, eta);
-        if constexpr (ST::APNEG) {
-          eta -= wm;
-        } else if constexpr (TI) {
-          eta = dotb<NX>(tb.ApC, wm, eta);
-        } else {
-          eta = dotb<NX>(cur.ApCm, wm, eta);
-        }
-        eta += (t == 0 && i < NX) ? rho_f * xinit - yinit : T(0);
-        const T u = (i < NG) ? rho_g * cur.zg - cur.yg : T(0);
-        if constexpr (ST::GSEL) {
-          const T gu = row_gather(u, ginv < 0 ? 0 : ginv);
-          eta += (ginv >= 0) ? gu : T(0);
-        } else if constexpr (TI) {
-          eta = dotb<NG>(tb.GC, u, eta);
-        } else {
-          eta = dotb<NG>(cur.GC, u, eta);
-        }
-        if constexpr (EtaIn<T, NX, NU, NG, TI>::SA)
-          R[(size_t)t * ROW] = dotb<n>(cur.Ar, eta, T(0));
-        else
-          R[(size_t)t * ROW] = eta;
-      }
+      if (t <= N) R[(size_t)t * ROW] = stage_r(c, cur, t);
       cur = nxt;
     }
   }
@@ -251,48 +338,12 @@ __device__ __forceinline__ void wave_iteration(const Layout& L, const WaveGroup&
 
   // ---------------- pass 5: constraint-row updates on row t mod 4 ----------------
   {
-    const T oma = T(1) - alpha;
-    const T rfa = rho_f * alpha;
     UpdIn<T, NX, NU, NG, TI> cur, nxt;
     load_upd(cur, P, R, q, N);
     for (int blk = 0; blk < nbl; ++blk) {
       const int t = 4 * blk + q;
       load_upd(nxt, P, R, t + 4, N);
-      if (t <= N) {
-        const T xt = cur.xt, xt1 = cur.xt1;
-        const size_t o = (size_t)t * ROW;
-        // dynamics row t: y_f += rho_f alpha (A^- x~_t + A^+ x~_{t+1} - c_t)
-        T zf;
-        if constexpr (TI)
-          zf = dotb<n>(tb.AmR, xt, T(0));
-        else
-          zf = dotb<n>(cur.AmR, xt, T(0));
-        if constexpr (ST::APNEG) {
-          zf -= xt1;
-        } else if constexpr (TI) {
-          zf = dotb<n>(tb.ApR, xt1, zf);
-        } else {
-          zf = dotb<n>(cur.ApR, xt1, zf);
-        }
-        if (t < N) P.yf[o] = cur.yf + rfa * (zf - (TI ? tb.bd : cur.bd));
-        // inequality rows of stage t (lanes past ng update padding)
-        T zt;
-        if constexpr (ST::GSEL)
-          zt = row_gather(xt, gsel);
-        else if constexpr (TI)
-          zt = dotb<n>(tb.GR, xt, T(0));
-        else
-          zt = dotb<n>(cur.GR, xt, T(0));
-        const T zh = alpha * zt + oma * cur.zg;
-        const Proj<T> pr =
-            project_row<T>(fma(cur.yg, pc.inv_rho, zh), TI ? tb.lo : cur.lo, TI ? tb.hi : cur.hi, kind, pc);
-        P.zg[o] = pr.z;
-        P.xi[o] = pr.xi;
-        P.yg[o] = cur.yg + rho_g * (zh - pr.z);
-        P.x[o] = alpha * xt + oma * cur.x;
-        // initial-state rows: y_init += rho_f alpha (x~_0 - x_init)
-        if (t == 0 && i < NX) P.yf[(size_t)N * ROW] = yinit + rfa * (xt - xinit);
-      }
+      if (t <= N) stage_update(c, cur, cur.xt, cur.xt1, t);
       cur = nxt;
     }
   }
@@ -315,7 +366,7 @@ __device__ __forceinline__ T rows_max(T v) {
 // admm:termination:slack with the stages spread over the four rows (stage t
 // on row t mod 4); every row reads the neighbouring stages it needs directly.
 // TI: the blocks are the same at every stage and are read once.
-template <typename T, int NX, int NU, int NG, bool TI>
+template <typename T, int NX, int NU, int NG, bool TI, int TAG = 0>
 __device__ __noinline__ Resid residuals_wave(const Layout& L, const WaveGroup& w, int kind, double gamma2,
                                              double gamma1) {
   constexpr int n = NX + NU;
@@ -524,11 +575,15 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
       const StagePtrs<T, NX, NU, NG> P(L, g);
       const ProjConst<T> pc(T(rho_bar), T(L.gamma2), T(L.gamma1));
       const T xinit = ((const T*)L.xinitT)[(size_t)w.b * NX + (i < NX ? i : 0)];
-      const int gsel = L.gsel[i < NG ? i : 0];
-      const int ginv = L.ginv[i];
-      for (; k < nb; ++k)
-        wave_iteration<T, NX, NU, NG, ST>(L, w, tb, P, T(st.sigma), T(st.rho_f_scale * rho_bar), T(rho_bar),
-                                          T(st.alpha), kind, pc, xinit, gsel, ginv);
+      const T rho_f = T(st.rho_f_scale * rho_bar), alpha = T(st.alpha);
+      const IterCtx<T, NX, NU, NG, ST> c{tb,          P,           T(st.sigma),        rho_f, T(rho_bar), alpha,
+                                         T(1) - alpha, rho_f * alpha, kind,          pc,    xinit,      T(0),
+                                         L.gsel[i < NG ? i : 0],   L.ginv[i],          i,     w.N};
+      for (; k < nb; ++k) {
+        IterCtx<T, NX, NU, NG, ST> ck = c;
+        ck.yinit = P.yf[(size_t)w.N * ROW];  // initial-state multipliers (slot N)
+        wave_iteration<T, NX, NU, NG, ST>(ck, w.row);
+      }
     }
     const int check = (st.k_check > 0 && nb % st.k_check == 0) ? 1 : 0;
     const int adapt = (adapt_on && nb % st.k_rho == 0 && nb < st.max_iter) ? 1 : 0;
