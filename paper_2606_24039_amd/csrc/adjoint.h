@@ -1,6 +1,8 @@
 // Implicit-differentiation adjoint (Algorithm 2; Sec. "Backward Pass";
-// Appendix "Backward Pass: Sensitivities Computation"), one instance per
-// 16-lane row, FP64 throughout.
+// Appendix "Backward Pass: Sensitivities Computation"), FP64 throughout, one
+// instance per wavefront in the layout of the ADMM solve (wave.h): work that
+// is independent across stages runs on four stages at once (stage t on row
+// t mod 4), the block substitutions are serial chains on row 0.
 //
 // 1. Active set (Appendix, "Active constraints identification"): the dual
 //    sign decides (y < -eps_g lower, y > eps_g upper); closeness to a bound is
@@ -11,19 +13,22 @@
 //      K = [[H, J'], [J, 0]],  J = [C; G_A]
 //    has a zero (2,2) block and no Schur form.  Its regularisation
 //      K_reg = [[H + sigma_b I, J'], [J, -rho_b^{-1} I]]
-//    does: (H + sigma_b I + rho_b J'J) e_x = r_x + rho_b J' r_y,
-//    e_y = rho_b (J e_x - r_y), and H + sigma_b I + rho_b J'J is block
-//    tridiagonal, factored by the forward solver's block Cholesky with
-//    rho_f = rho_b and per-row inequality weights rho_b [row active].
+//    does: (H + sigma_b I + rho_b J'J) d_x = r_x + rho_b J' r_y,
+//    d_y = rho_b (J d_x - r_y), and H + sigma_b I + rho_b J'J is block
+//    tridiagonal, factored by the solve's block Cholesky (P/K form, FP64)
+//    with rho_f = rho_b and per-row inequality weights rho_b [row active].
 //    Iterative refinement e <- e + K_reg^{-1}(r - K e) with the residual in
 //    FP64 converges to K^{-1} r (the regularisation is a perturbation of
 //    size max(sigma_b, 1/rho_b)).
 // 3. VJP (eq. loss_gradient): dL/dq = -eta_x, dL/dx_init = eta_f(initial
 //    rows), dL/dD_t[i,i] = -eta_x,t,i x_t,i, dL/dlo = eta_g on lower-active
 //    rows, dL/dhi = eta_g on upper-active rows.
+//
+// Equality-row vectors (e_f, r_f) use the output slot convention: the
+// initial-state rows at stage 0, dynamics row t at stage t + 1.
 #pragma once
 
-#include "admm.h"
+#include "wave.h"
 
 namespace ocpk {
 
@@ -31,220 +36,241 @@ struct AdjArgs {
   const double* dLdx;  // [S][n]
   double sigma_b, rho_b, eps_active;
   int sweeps;
-  // scratch, FP64 padded [S][ROW]
+  // scratch, FP64 padded [S][ROW] (v carries STAGE_PAD padding stages)
   double* w;    // inequality-row weights (rho_b on active rows)
   double* ex;   // eta_x
-  double* ef;   // eta_f (slot convention of y_f)
+  double* ef;   // eta_f
   double* eg;   // eta_g
   double* rf;   // equality-row residual of the current sweep
   double* rg;   // inequality-row residual of the current sweep
-  double* v;    // forward-substitution scratch
+  double* v;    // exchange buffer of the substitution passes
   int8_t* act;  // -1 lower, +1 upper, 0 inactive
+  // factor of the regularised Schur matrix, FP64 P/K form (factor.h), padded
+  double *P, *K, *Kb;
   // outputs (FP64, may be null)
   double *d_q, *d_Ddiag, *d_x_init, *d_lo, *d_hi, *eta_x;
   int8_t* active;
 };
 
-template <typename T, int NX, int NU, int NG, bool TI>
+// Blocks of stage t a row needs for the products with H, C and G (FP64).
+template <int NX, int NU, int NG>
+struct AdjBlocks {
+  static constexpr int n = NX + NU;
+  double Dr[n];           // row i of D_t
+  double Er[n], Ec[n];    // row i of E_{t-1}, column i of E_t
+  double Amc[NX], Apcm[NX];  // column i of A_t^-, of A_{t-1}^+
+  double Amr[n], Apr[n];  // row i of A_t^-, A_t^+
+  double Amrm[n], Aprm[n];   // row i of A_{t-1}^-, A_{t-1}^+
+  double Gc[NG], Gr[n];   // column i, row i of G_t
+};
+
+template <int NX, int NU, int NG>
+__device__ __forceinline__ void load_adj_blocks(AdjBlocks<NX, NU, NG>& d, const Layout& L, int b, int64_t s0,
+                                                int t, int N, int i) {
+  constexpr int n = NX + NU;
+  const size_t nn = (size_t)n * n;
+  const int ic = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
+  const int64_t s = s0 + t;
+  const int64_t sm = s0 + (t > 0 ? t - 1 : 0);
+  const double* Dp = L.ti ? L.D + (size_t)(2 * b + (t == N ? 1 : 0)) * nn : L.D + (size_t)s * nn;
+  load_row<n>(d.Dr, Dp + (size_t)ic * n, true);
+  if (L.E) {
+    load_row<n>(d.Er, L.E + ti_or_tv(L.ti, b, sm, nn) + (size_t)ic * n, t > 0);
+    load_col<n>(d.Ec, L.E + ti_or_tv(L.ti, b, s, nn) + ic, n, t < N);
+  } else {
+#pragma unroll
+    for (int k = 0; k < n; ++k) d.Er[k] = d.Ec[k] = 0.0;
+  }
+  const size_t oa = ti_or_tv(L.ti, b, s, (size_t)NX * n), oam = ti_or_tv(L.ti, b, sm, (size_t)NX * n);
+  load_col<NX>(d.Amc, L.Am + oa + ic, n, t < N);
+  load_col<NX>(d.Apcm, L.Ap + oam + ic, n, t > 0);
+  load_row<n>(d.Amr, L.Am + oa + (size_t)ix * n, t < N);
+  load_row<n>(d.Apr, L.Ap + oa + (size_t)ix * n, t < N);
+  load_row<n>(d.Amrm, L.Am + oam + (size_t)ix * n, t > 0);
+  load_row<n>(d.Aprm, L.Ap + oam + (size_t)ix * n, t > 0);
+  const size_t og = ti_or_tv(L.ti, b, s, (size_t)NG * n);
+  load_col<NG>(d.Gc, L.G + og + ic, n, true);
+  load_row<n>(d.Gr, L.G + og + (size_t)ig * n, true);
+}
+
+template <typename T, int NX, int NU, int NG>
 __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   constexpr int n = NX + NU;
-  Group g;
-  g.lane = threadIdx.x & (ROW - 1);
-  const int slot = row_slot();
-  if (slot >= L.B) return;
-  g.b = L.order ? L.order[slot] : slot;
-  g.s0 = L.stage_off[g.b];
-  g.N = (int)(L.stage_off[g.b + 1] - g.s0) - 1;
-  const int i = g.lane, b = g.b, N = g.N;
+  WaveGroup w;
+  if (!wave_group(L, w)) return;
+  const int i = w.lane, q = w.row, b = w.b, N = w.N;
+  const int64_t s0 = w.s0;
+  const Group g{w.lane, w.b, w.s0, w.N};
+  const int nbl = (N + 4) / 4;
   const size_t nn = (size_t)n * n;
-  const T* X = (const T*)L.x;
-  const T* YG = (const T*)L.yg;
-  const T* XI = (const T*)L.xi;
+  const gptr<const T> X = as_global((const T*)L.x);
+  const gptr<const T> YG = as_global((const T*)L.yg);
+  const gptr<const T> XI = as_global((const T*)L.xi);
+  const gptr<double> ex = as_global(a.ex), ef = as_global(a.ef), eg = as_global(a.eg);
+  const gptr<double> rf = as_global(a.rf), rg = as_global(a.rg), wv = as_global(a.w);
   const int kind = (i < NG) ? (int)L.soft[i] : 0;
+  const double rb = a.rho_b;
 
   // ---- 1. active set ----
   double ymax = 0.0;
-  for (int t = 0; t <= N; ++t) {
-    const size_t sv = (size_t)(g.s0 + t) * ROW + i;
-    if (i < NG) ymax = fmax(ymax, fabs(double(YG[sv])));
+  for (int blk = 0; blk < nbl; ++blk) {
+    const int t = 4 * blk + q;
+    if (t <= N && i < NG) ymax = fmax(ymax, fabs(double(YG[(size_t)(s0 + t) * ROW + i])));
   }
-  ymax = row_max(ymax);
-  const double eg = 10.0 * a.eps_active * fmax(1.0, ymax);
-  for (int t = 0; t <= N; ++t) {
-    const int64_t s = g.s0 + t;
+  ymax = rows_max(row_max(ymax));
+  const double epsg = 10.0 * a.eps_active * fmax(1.0, ymax);
+  for (int blk = 0; blk < nbl; ++blk) {
+    const int t = 4 * blk + q;
+    if (t > N) break;
+    const int64_t s = s0 + t;
     const size_t sv = (size_t)s * ROW + i;
     const double xc = (i < n) ? double(X[sv]) : 0.0;
     double Gr[n];
-    load_row<n>(Gr, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (size_t)i * n, i < NG);
+    load_row<n>(Gr, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (size_t)(i < NG ? i : NG - 1) * n, true);
     const double gx = dotb<n>(Gr, xc, 0.0);
     int act = 0;
     if (i < NG) {
       const size_t sb = ti_or_tv(L.ti, b, s, NG) + i;
       const double lo = L.lo[sb], hi = L.hi[sb], y = double(YG[sv]);
-      const bool amb = fabs(y) < eg;
-      bool lower = (y < -eg) || (amb && (gx - lo <= eg * fmax(1.0, fabs(lo))));
-      bool upper = (y > eg) || (amb && (hi - gx <= eg * fmax(1.0, fabs(hi))));
+      const bool amb = fabs(y) < epsg;
+      bool lower = (y < -epsg) || (amb && (gx - lo <= epsg * fmax(1.0, fabs(lo))));
+      bool upper = (y > epsg) || (amb && (hi - gx <= epsg * fmax(1.0, fabs(hi))));
       if (lower && upper) {
-        if (y > 0) lower = false;
-        else upper = false;
+        if (y > 0)
+          lower = false;
+        else
+          upper = false;
       }
       if (kind == 2 && double(XI[sv]) != 0.0) lower = upper = false;
       act = lower ? -1 : (upper ? 1 : 0);
     }
     a.act[sv] = (int8_t)act;
-    a.w[sv] = act ? a.rho_b : 0.0;
-    a.ex[sv] = 0.0;
-    a.ef[sv] = 0.0;
-    a.eg[sv] = 0.0;
+    wv[sv] = act ? rb : 0.0;
+    ex[sv] = 0.0;
+    ef[sv] = 0.0;
+    eg[sv] = 0.0;
   }
+  wave_sync();
 
-  // ---- 2. factor H + sigma_b I + rho_b (C'C + G_A'G_A) (FP64) ----
-  const int bad = factor_instance<double, NX, NU, NG, false>(L, g, a.sigma_b, a.rho_b, 0.0, a.w);
+  // ---- 2. factor H + sigma_b I + rho_b (C'C + G_A'G_A) (FP64, P/K form) ----
+  Layout LF = L;
+  LF.SubB = a.P;
+  LF.ChF = a.K;
+  LF.ChB = a.Kb;
+  const int bad = factor_instance<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
+  wave_sync();
 
   // ---- refinement sweeps ----
+  const gptr<double> R = as_global(a.v) + (size_t)s0 * ROW + i;
+  const gptr<const double> Pr = as_global((const double*)a.P) + (size_t)s0 * nn + (size_t)(i < n ? i : n - 1) * n;
+  const gptr<const double> Kr = as_global((const double*)a.K) + (size_t)s0 * nn + (size_t)(i < n ? i : n - 1) * n;
+  const gptr<const double> Kbr = as_global((const double*)a.Kb) + (size_t)s0 * nn + (size_t)(i < n ? i : n - 1) * n;
   for (int sweep = 0; sweep < a.sweeps && !bad; ++sweep) {
-    // forward pass: residual r - K e and the Schur right-hand side, then
-    // v_t = Linv_t (rhs_t - M_t v_{t-1})
-    double em = 0.0, ec = (i < n) ? a.ex[(size_t)g.s0 * ROW + i] : 0.0;
-    double efm = 0.0;  // eta_f of dynamics row t-1
-    double rfm = 0.0;  // residual of dynamics row t-1
-    double Apcm[NX], Eprev[n];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) Apcm[r] = 0.0;
-#pragma unroll
-    for (int k = 0; k < n; ++k) Eprev[k] = 0.0;
-    double vprev = 0.0;
-    for (int t = 0; t <= N; ++t) {
-      const int64_t s = g.s0 + t;
+    // pass 1: residual r - K e and the Schur right-hand side
+    //   rhs_t = r_x,t + rho_b (C' r_f)_t + G_t'(w .* r_g,t)
+    for (int blk = 0; blk < nbl; ++blk) {
+      const int t = 4 * blk + q;
+      if (t > N) break;
+      const int64_t s = s0 + t;
       const size_t sv = (size_t)s * ROW + i;
-      const double en = (t < N && i < n) ? a.ex[sv + ROW] : 0.0;
-      // H e_x (rows of stage t)
-      const double* Dp = L.ti ? L.D + (size_t)(2 * b + (t == N ? 1 : 0)) * nn : L.D + (size_t)s * nn;
-      double Dr[n];
-      load_row<n>(Dr, Dp + (size_t)i * n, i < n);
-      double he = dotb<n>(Dr, ec, 0.0);
-      if (t > 0) he = dotb<n>(Eprev, em, he);
-      if (L.E && t < N) {
-        const double* Ep = L.E + ti_or_tv(L.ti, b, s, nn);
-        double Ec[n];
-        load_col<n>(Ec, Ep + i, n, i < n);
-        he = dotb<n>(Ec, en, he);
-        load_row<n>(Eprev, Ep + (size_t)i * n, i < n);
-      }
-      // J' e_y (rows of stage t) and J e_x (rows touching stage t)
-      const double efc = (t < N && i < NX) ? a.ef[sv + ROW] : 0.0;
-      double jte = 0.0;
-      double Amc[NX], Amr[n], Apr[n];
-      if (t < N) {
-        const double* Amp = L.Am + ti_or_tv(L.ti, b, s, (size_t)NX * n);
-        const double* App = L.Ap + ti_or_tv(L.ti, b, s, (size_t)NX * n);
-        load_col<NX>(Amc, Amp + i, n, i < n);
-        load_row<n>(Amr, Amp + (size_t)i * n, i < NX);
-        load_row<n>(Apr, App + (size_t)i * n, i < NX);
-        jte = dotb<NX>(Amc, efc, jte);
-      }
-      if (t > 0) jte = dotb<NX>(Apcm, efm, jte);
-      if (t == 0 && i < NX) jte += a.ef[sv];
-      const double* Gp = L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n);
-      double Gc[NG], Gr[n];
-      load_col<NG>(Gc, Gp + i, n, i < n);
-      load_row<n>(Gr, Gp + (size_t)i * n, i < NG);
-      const double wv = (i < NG) ? a.w[sv] : 0.0;
-      const double egv = (i < NG) ? a.eg[sv] : 0.0;
-      jte = dotb<NG>(Gc, (wv != 0.0) ? egv : 0.0, jte);
-      // residuals of this sweep
+      AdjBlocks<NX, NU, NG> B;
+      load_adj_blocks(B, L, b, s0, t, N, i);
+      const double ec = (i < n) ? ex[sv] : 0.0;
+      const double em = (t > 0 && i < n) ? ex[sv - ROW] : 0.0;
+      const double en = (t < N && i < n) ? ex[sv + ROW] : 0.0;
+      // H e_x
+      double he = dotb<n>(B.Dr, ec, 0.0);
+      he = dotb<n>(B.Er, em, he);
+      he = dotb<n>(B.Ec, en, he);
+      // J' e_y
+      const double efc = (t < N && i < NX) ? ef[sv + ROW] : 0.0;  // dynamics row t
+      const double efm = (t > 0 && i < NX) ? ef[sv] : 0.0;        // dynamics row t-1
+      double jte = dotb<NX>(B.Amc, efc, 0.0);
+      jte = dotb<NX>(B.Apcm, efm, jte);
+      if (t == 0 && i < NX) jte += ef[sv];  // initial-state rows
+      const double wc = (i < NG) ? wv[sv] : 0.0;
+      const double egv = (i < NG && wc != 0.0) ? eg[sv] : 0.0;
+      jte = dotb<NG>(B.Gc, egv, jte);
       const double rx = ((i < n) ? a.dLdx[(size_t)s * n + i] : 0.0) - (he + jte);
-      double rf0 = 0.0;  // initial rows (t == 0)
-      if (t == 0 && i < NX) rf0 = -ec;
-      double rfc = 0.0;  // dynamics row t
-      if (t < N) {
-        double cx = dotb<n>(Amr, ec, 0.0);
-        cx = dotb<n>(Apr, en, cx);
-        rfc = (i < NX) ? -cx : 0.0;
-      }
-      const double gx = dotb<n>(Gr, ec, 0.0);
-      const double rgc = (wv != 0.0) ? -gx : 0.0;
-      // Schur right-hand side  r_x + rho_b C' r_f + G'(w .* r_g), w = rho_b [row active]
-      double tc = 0.0;
-      if (t < N) tc = dotb<NX>(Amc, rfc, tc);
-      if (t > 0) tc = dotb<NX>(Apcm, rfm, tc);
-      if (t == 0 && i < NX) tc += rf0;
-      double rhs = rx + a.rho_b * tc;
-      rhs = dotb<NG>(Gc, wv * rgc, rhs);
-      if (i < NX && t == 0) a.rf[sv] = rf0;
-      if (t < N && i < NX) a.rf[sv + ROW] = rfc;
-      if (i < NG) a.rg[sv] = rgc;
-      // forward substitution
-      if (t > 0) {
-        double Mr[n];
-        load_row<n>(Mr, L.M64 + (size_t)s * nn + (size_t)i * n, i < n);
-        rhs -= dotb<n>(Mr, vprev, 0.0);
-      }
-      double Lr[n];
-      load_row<n>(Lr, L.Linv64 + (size_t)s * nn + (size_t)i * n, i < n);
-      const double vv = dotb<n>(Lr, rhs, 0.0);
-      if (i < n) a.v[sv] = vv;
-      vprev = vv;
-      // shift
-      if (t < N) load_col<NX>(Apcm, L.Ap + ti_or_tv(L.ti, b, s, (size_t)NX * n) + i, n, i < n);
-      efm = efc;
-      rfm = rfc;
-      em = ec;
-      ec = en;
+      // equality-row residuals -J e_x of the rows touching stage t
+      double cx = dotb<n>(B.Amr, ec, 0.0);
+      cx = dotb<n>(B.Apr, en, cx);
+      const double rfc = (t < N && i < NX) ? -cx : 0.0;  // dynamics row t
+      double cxm = dotb<n>(B.Amrm, em, 0.0);
+      cxm = dotb<n>(B.Aprm, ec, cxm);
+      const double rfm = (t > 0 && i < NX) ? -cxm : 0.0;  // dynamics row t-1
+      const double rf0 = (t == 0 && i < NX) ? -ec : 0.0;  // initial-state rows
+      const double gx = dotb<n>(B.Gr, ec, 0.0);
+      const double rgc = (wc != 0.0) ? -gx : 0.0;
+      double tc = dotb<NX>(B.Amc, rfc, 0.0);
+      tc = dotb<NX>(B.Apcm, rfm, tc);
+      tc += rf0;
+      double rhs = rx + rb * tc;
+      rhs = dotb<NG>(B.Gc, wc * rgc, rhs);
+      if (t == 0 && i < NX) rf[sv] = rf0;
+      if (t < N && i < NX) rf[sv + ROW] = rfc;
+      if (i < NG) rg[sv] = rgc;
+      R[(size_t)t * ROW] = rhs;
     }
-    // backward pass: d_x = L^-T(...), d_y = rho_b (J d_x - r_y), e += d
-    double dnext = 0.0;
-    for (int t = N; t >= 0; --t) {
-      const int64_t s = g.s0 + t;
+    wave_sync();
+    // passes 2-4: d_x = S^{-1} rhs
+    if (q == 0) chain<double, n, +1>(R, Kr, N);
+    wave_sync();
+    for (int blk = 0; blk < nbl; ++blk) {
+      const int t = 4 * blk + q;
+      if (t > N) break;
+      double Prow[n];
+      load_row<n>(Prow, Pr + (size_t)t * nn, true);
+      R[(size_t)t * ROW] = dotb<n>(Prow, R[(size_t)t * ROW], 0.0);
+    }
+    wave_sync();
+    if (q == 0) chain<double, n, -1>(R, Kbr, N);
+    wave_sync();
+    // pass 5: d_y = rho_b (J d_x - r_y), e += d
+    for (int blk = 0; blk < nbl; ++blk) {
+      const int t = 4 * blk + q;
+      if (t > N) break;
+      const int64_t s = s0 + t;
       const size_t sv = (size_t)s * ROW + i;
-      double vv = (i < n) ? a.v[sv] : 0.0;
-      if (t < N) {
-        double Mc[n];
-        load_col<n>(Mc, L.M64 + (size_t)(s + 1) * nn + i, n, i < n);
-        vv -= dotb<n>(Mc, dnext, 0.0);
-      }
-      double Lc[n];
-      load_col<n>(Lc, L.Linv64 + (size_t)s * nn + i, n, i < n);
-      const double dx = dotb<n>(Lc, vv, 0.0);
-      if (t < N) {
-        double Amr[n], Apr[n];
-        load_row<n>(Amr, L.Am + ti_or_tv(L.ti, b, s, (size_t)NX * n) + (size_t)i * n, i < NX);
-        load_row<n>(Apr, L.Ap + ti_or_tv(L.ti, b, s, (size_t)NX * n) + (size_t)i * n, i < NX);
-        double jd = dotb<n>(Amr, dx, 0.0);
-        jd = dotb<n>(Apr, dnext, jd);
-        if (i < NX) a.ef[sv + ROW] += a.rho_b * (jd - a.rf[sv + ROW]);
-      }
-      {
-        double Gr[n];
-        load_row<n>(Gr, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (size_t)i * n, i < NG);
-        const double gd = dotb<n>(Gr, dx, 0.0);
-        if (i < NG && a.w[sv] != 0.0) a.eg[sv] += a.rho_b * (gd - a.rg[sv]);
-      }
-      if (t == 0 && i < NX) a.ef[sv] += a.rho_b * (dx - a.rf[sv]);
-      if (i < n) a.ex[sv] += dx;
-      dnext = dx;
+      const double dx = R[(size_t)t * ROW];
+      const double dn = (t < N) ? R[(size_t)(t + 1) * ROW] : 0.0;
+      const size_t oa = ti_or_tv(L.ti, b, s, (size_t)NX * n);
+      double Amr[n], Apr[n], Gr[n];
+      load_row<n>(Amr, L.Am + oa + (size_t)(i < NX ? i : NX - 1) * n, t < N);
+      load_row<n>(Apr, L.Ap + oa + (size_t)(i < NX ? i : NX - 1) * n, t < N);
+      load_row<n>(Gr, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (size_t)(i < NG ? i : NG - 1) * n, true);
+      double jd = dotb<n>(Amr, dx, 0.0);
+      jd = dotb<n>(Apr, dn, jd);
+      if (t < N && i < NX) ef[sv + ROW] += rb * (jd - rf[sv + ROW]);
+      const double gd = dotb<n>(Gr, dx, 0.0);
+      if (i < NG && wv[sv] != 0.0) eg[sv] += rb * (gd - rg[sv]);
+      if (t == 0 && i < NX) ef[sv] += rb * (dx - rf[sv]);
+      if (i < n) ex[sv] += dx;
     }
+    wave_sync();
   }
 
   // ---- 3. VJP outputs ----
-  for (int t = 0; t <= N; ++t) {
-    const int64_t s = g.s0 + t;
+  const double nanv = bad ? NAN : 0.0;
+  for (int blk = 0; blk < nbl; ++blk) {
+    const int t = 4 * blk + q;
+    if (t > N) break;
+    const int64_t s = s0 + t;
     const size_t sv = (size_t)s * ROW + i;
-    const double nanv = bad ? NAN : 0.0;
     if (i < n) {
-      const double e = a.ex[sv] + nanv;
+      const double e = ex[sv] + nanv;
       if (a.eta_x) a.eta_x[(size_t)s * n + i] = e;
       if (a.d_q) a.d_q[(size_t)s * n + i] = -e;
       if (a.d_Ddiag) a.d_Ddiag[(size_t)s * n + i] = -e * double(X[sv]);
     }
     if (i < NG) {
       const int act = a.act[sv];
-      const double e = a.eg[sv] + nanv;
+      const double e = eg[sv] + nanv;
       if (a.d_lo) a.d_lo[(size_t)s * NG + i] = (act < 0) ? e : 0.0;
       if (a.d_hi) a.d_hi[(size_t)s * NG + i] = (act > 0) ? e : 0.0;
       if (a.active) a.active[(size_t)s * NG + i] = (int8_t)act;
     }
-    if (t == 0 && i < NX && a.d_x_init) a.d_x_init[(size_t)b * NX + i] = a.ef[sv] + nanv;
+    if (t == 0 && i < NX && a.d_x_init) a.d_x_init[(size_t)b * NX + i] = ef[sv] + nanv;
   }
 }
 

@@ -86,7 +86,7 @@ void timed(Prof* p, int c, hipStream_t st, F&& f) {
 // dispatch table: one instantiation per compiled (nx, nu, ng)
 // ---------------------------------------------------------------------------
 using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, hipStream_t, Prof*);
-using AdjFn = void (*)(const Layout&, const AdjArgs&, int, hipStream_t, Prof*);
+using AdjFn = void (*)(const Layout&, const AdjArgs&, hipStream_t, Prof*);
 
 // One ADMM solve: per-solve initialisation, then one wavefront per instance
 // runs the whole of Algorithm 3 (factorisation, iterations, FP64 checks, rho
@@ -99,11 +99,11 @@ void launch_solve(const Layout& L, const Settings& s, int32_t* need, hipStream_t
         [&] { hipLaunchKernelGGL((admm_solve_wave_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, s); });
 }
 
-template <typename T, int NX, int NU, int NG, bool TI>
-void launch_adjoint(const Layout& L, const AdjArgs& a, int grid, hipStream_t st, Prof* pf) {
-  timed(pf, OCP_K_ADJOINT, st, [&] {
-    hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG, TI>), dim3(grid), dim3(16 * kRowsPerWave), 0, st, L, a);
-  });
+// one instance per wavefront
+template <typename T, int NX, int NU, int NG>
+void launch_adjoint(const Layout& L, const AdjArgs& a, hipStream_t st, Prof* pf) {
+  timed(pf, OCP_K_ADJOINT, st,
+        [&] { hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG>), dim3(L.B), dim3(64), 0, st, L, a); });
 }
 
 // structure variants of the iteration kernel
@@ -116,8 +116,8 @@ struct Entry {
   int nx, nu, ng;
   SolveFn f64[3];  // [variant]
   SolveFn f32[3];
-  AdjFn adj64[2];
-  AdjFn adj32[2];
+  AdjFn adj64;
+  AdjFn adj32;
 };
 
 #define OCP_ENTRY(NX, NU, NG)                                                                       \
@@ -127,8 +127,7 @@ struct Entry {
          launch_solve<double, NX, NU, NG, StBox>},                                                  \
         {launch_solve<float, NX, NU, NG, StTV>, launch_solve<float, NX, NU, NG, StTI>,              \
          launch_solve<float, NX, NU, NG, StBox>},                                                   \
-        {launch_adjoint<double, NX, NU, NG, false>, launch_adjoint<double, NX, NU, NG, true>},      \
-        {launch_adjoint<float, NX, NU, NG, false>, launch_adjoint<float, NX, NU, NG, true>},        \
+        launch_adjoint<double, NX, NU, NG>, launch_adjoint<float, NX, NU, NG>,                       \
   }
 
 const Entry kTable[] = {
@@ -188,6 +187,7 @@ struct ocp_handle_s {
   // adjoint scratch (FP64, padded [S][ROW])
   double *adj_rhog = nullptr, *adj_ex = nullptr, *adj_ey = nullptr, *adj_eg = nullptr, *adj_r = nullptr;
   double *adj_v = nullptr, *adj_rg = nullptr;
+  double *adj_P = nullptr, *adj_K = nullptr, *adj_Kb = nullptr;  // adjoint factor, FP64 P/K form
   uint8_t soft_host[16] = {0};
   int8_t* adj_act = nullptr;
 
@@ -326,7 +326,10 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   A_(h->adj_ey, sizeof(double) * ROW * S);
   A_(h->adj_eg, sizeof(double) * ROW * S);
   A_(h->adj_r, sizeof(double) * ROW * S);
-  A_(h->adj_v, sizeof(double) * ROW * S);
+  A_(h->adj_v, sizeof(double) * ROW * SP);
+  A_(h->adj_P, sizeof(double) * nn * SP);
+  A_(h->adj_K, sizeof(double) * nn * SP);
+  A_(h->adj_Kb, sizeof(double) * nn * SP);
   A_(h->adj_rg, sizeof(double) * ROW * S);
   A_(h->adj_act, sizeof(int8_t) * ROW * S);
 #undef A_
@@ -364,10 +367,13 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   {
     const size_t tsz = h->tsz();
     if (hipMemset(h->M64, 0, sizeof(double) * nn * S1) != hipSuccess) return OCP_E_HIP;
-    void** padded[] = {&h->SubA, &h->SubB, &h->ChF, &h->ChB, &h->x, &h->v, &h->yf, &h->zg, &h->yg, &h->xi};
+    void** padded[] = {&h->SubA, &h->SubB, &h->ChF, &h->ChB, &h->x, &h->v, &h->yf, &h->zg, &h->yg, &h->xi,
+                       (void**)&h->adj_v, (void**)&h->adj_P, (void**)&h->adj_K, (void**)&h->adj_Kb};
     const size_t stage_bytes[] = {tsz * nn,  tsz * nn,  tsz * nn,  tsz * nn,  tsz * ROW,
-                                  tsz * ROW, tsz * ROW, tsz * ROW, tsz * ROW, tsz * ROW};
-    for (int k = 0; k < 10; ++k) {
+                                  tsz * ROW, tsz * ROW, tsz * ROW, tsz * ROW, tsz * ROW,
+                                  sizeof(double) * ROW, sizeof(double) * nn, sizeof(double) * nn,
+                                  sizeof(double) * nn};
+    for (int k = 0; k < 14; ++k) {
       if (!*padded[k]) continue;
       if (hipMemset(*padded[k], 0, stage_bytes[k] * SP) != hipSuccess) return OCP_E_HIP;
       *padded[k] = (char*)*padded[k] + stage_bytes[k] * STAGE_PAD;
@@ -866,6 +872,9 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   a.rg = h->adj_rg;
   a.v = h->adj_v;
   a.act = h->adj_act;
+  a.P = h->adj_P;
+  a.K = h->adj_K;
+  a.Kb = h->adj_Kb;
   a.d_q = out->d_q;
   a.d_Ddiag = out->d_Ddiag;
   a.d_x_init = out->d_x_init;
@@ -874,13 +883,10 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   a.eta_x = out->eta_x;
   a.active = out->active;
   const Layout L = make_layout(h);
-  const int grid = (h->B + kRowsPerWave - 1) / kRowsPerWave;
-  const int ti = h->ti ? 1 : 0;
   if (h->mixed)
-    h->entry->adj32[ti](L, a, grid, st, &h->prof);
+    h->entry->adj32(L, a, st, &h->prof);
   else
-    h->entry->adj64[ti](L, a, grid, st, &h->prof);
-  // the factor now holds the adjoint system: the next solve refactors from scratch
+    h->entry->adj64(L, a, st, &h->prof);
   return hip_ok(hipGetLastError());
 }
 
