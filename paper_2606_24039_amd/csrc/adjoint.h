@@ -157,7 +157,8 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   LF.SubB = a.P;
   LF.ChF = a.K;
   LF.ChB = a.Kb;
-  const int bad = factor_instance<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
+  const int bad = L.ti ? factor_instance<double, NX, NU, NG, true, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q)
+                       : factor_instance<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
   wave_sync();
 
   // ---- refinement sweeps ----

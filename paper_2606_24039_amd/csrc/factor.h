@@ -80,8 +80,9 @@ __device__ __forceinline__ T quarter_pick(const T (&a)[K], int q) {
 
 // Factor one instance.  rhog_rows: optional per-row inequality weights
 // ([S][ROW], FP64); when null every inequality row uses rho_g.
-// HOIST: time-invariant blocks and uniform weights, so the rho-independent
-// products A^-'A^-, A^+'A^+, G'G and A^+'A^- are formed once per instance.
+// HOIST: time-invariant blocks; the blocks are read once and the products
+// A^-'A^-, A^+'A^+, A^+'A^- (and G'G under uniform weights) are formed once
+// per instance, so a stage reads nothing but its row weights.
 // FORM selects the outputs (all row-major, [S][n][n]):
 //   FACTOR_M   (adjoint)  FP64 Linv_t and M_t.
 //   FACTOR_WV  (ADMM solve, FP32 iterations) in iteration precision
@@ -124,29 +125,46 @@ __device__ __noinline__ int factor_instance(const Layout& L, const Group& g, dou
 
   // rho-independent products (row i), formed once when the blocks do not vary
   double PAm[HOIST ? n : 1], PAp[HOIST ? n : 1], PG[HOIST ? n : 1], PPhi[HOIST ? n : 1];
+  double Dint[HOIST ? n : 1], Dter[HOIST ? n : 1], Erow[HOIST ? n : 1], GcH[HOIST ? NG : 1];
   FacStage<NX, NU, NG> cur, nxt;
-  load_fac(cur, L, g, 0, rho_g, rhog_rows);
   if constexpr (HOIST) {
-    FacStage<NX, NU, NG> any;  // the blocks of an interior stage (all equal)
-    load_fac(any, L, g, 0, rho_g, rhog_rows);
+    const int ic = i < n ? i : n - 1;
+    const size_t b = (size_t)g.b;
+    load_row<n>(Dint, L.D + (2 * b) * nn + (size_t)ic * n, true);
+    load_row<n>(Dter, L.D + (2 * b + 1) * nn + (size_t)ic * n, true);
+    if (L.E)
+      load_row<n>(Erow, L.E + b * nn + (size_t)ic * n, true);
+    else
+#pragma unroll
+      for (int k = 0; k < n; ++k) Erow[k] = 0.0;
+    double Amc[NX], Apc[NX];
+    load_col<NX>(Amc, L.Am + b * NX * n + ic, n, true);
+    load_col<NX>(Apc, L.Ap + b * NX * n + ic, n, true);
+    load_col<NG>(GcH, L.G + b * NG * n + ic, n, true);
 #pragma unroll
     for (int k = 0; k < n; ++k) PAm[k] = PAp[k] = PG[k] = PPhi[k] = 0.0;
-    cross_row<NX, n>(any.Amc, any.Amc, PAm, 1.0);
-    cross_row<NX, n>(any.Apc, any.Apc, PAp, 1.0);
-    double Gw[NG];
-#pragma unroll
-    for (int r = 0; r < NG; ++r) Gw[r] = any.w[r] * any.Gc[r];
-    cross_row<NG, n>(Gw, any.Gc, PG, 1.0);
-    cross_row<NX, n>(any.Apc, any.Amc, PPhi, 1.0);
+    cross_row<NX, n>(Amc, Amc, PAm, 1.0);
+    cross_row<NX, n>(Apc, Apc, PAp, 1.0);
+    cross_row<NX, n>(Apc, Amc, PPhi, 1.0);
+    if (!rhog_rows) cross_row<NG, n>(GcH, GcH, PG, rho_g);
+  } else {
+    load_fac(cur, L, g, 0, rho_g, rhog_rows);
   }
 
   int bad = 0;
   for (int t = 0; t <= N; ++t) {
     const int64_t s = g.s0 + t;
-    if (t < N) load_fac(nxt, L, g, t + 1, rho_g, rhog_rows);  // prefetch
+    if constexpr (!HOIST) {
+      if (t < N) load_fac(nxt, L, g, t + 1, rho_g, rhog_rows);  // prefetch
+    }
     double S[n];
+    if constexpr (HOIST) {
 #pragma unroll
-    for (int k = 0; k < n; ++k) S[k] = cur.D[k];
+      for (int k = 0; k < n; ++k) S[k] = (t == N) ? Dter[k] : Dint[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < n; ++k) S[k] = cur.D[k];
+    }
     sfor<0, n>([&](auto j) {
       constexpr int jj = decltype(j)::value;
       if (i == jj) S[jj] += sigma + ((t == 0 && jj < NX) ? rho_f : 0.0);
@@ -155,6 +173,12 @@ __device__ __noinline__ int factor_instance(const Layout& L, const Group& g, dou
       const double ca = (t < N) ? rho_f : 0.0, cp = (t > 0) ? rho_f : 0.0;
 #pragma unroll
       for (int k = 0; k < n; ++k) S[k] += ca * PAm[k] + cp * PAp[k] + PG[k];
+      if (rhog_rows) {  // stage weights (the same address on every lane)
+        double Gw[NG];
+#pragma unroll
+        for (int r = 0; r < NG; ++r) Gw[r] = as_global(rhog_rows)[(size_t)s * ROW + r] * GcH[r];
+        cross_row<NG, n>(Gw, GcH, S, 1.0);
+      }
     } else {
       if (t < N) cross_row<NX, n>(cur.Amc, cur.Amc, S, rho_f);
       if (t > 0) cross_row<NX, n>(ApcPrev, ApcPrev, S, rho_f);
@@ -261,12 +285,12 @@ __device__ __noinline__ int factor_instance(const Layout& L, const Group& g, dou
     if (t < N) {
       // Phi_t row i = E_t row i + rho_f sum_r A_t^+[r][i] A_t^-[r][:]
       double Phi[n];
-#pragma unroll
-      for (int k = 0; k < n; ++k) Phi[k] = cur.E[k];
       if constexpr (HOIST) {
 #pragma unroll
-        for (int k = 0; k < n; ++k) Phi[k] += rho_f * PPhi[k];
+        for (int k = 0; k < n; ++k) Phi[k] = Erow[k] + rho_f * PPhi[k];
       } else {
+#pragma unroll
+        for (int k = 0; k < n; ++k) Phi[k] = cur.E[k];
         cross_row<NX, n>(cur.Apc, cur.Amc, Phi, rho_f);
       }
       // M_{t+1} row i: M[i][j] = sum_{k<=j} Phi[i][k] Linv[j][k]
@@ -300,9 +324,11 @@ __device__ __noinline__ int factor_instance(const Layout& L, const Group& g, dou
 #pragma unroll
         for (int j = 0; j < n; ++j) dst[j] = Mrow[j];
       }
+      if constexpr (!HOIST) {
 #pragma unroll
-      for (int r = 0; r < NX; ++r) ApcPrev[r] = cur.Apc[r];
-      cur = nxt;
+        for (int r = 0; r < NX; ++r) ApcPrev[r] = cur.Apc[r];
+        cur = nxt;
+      }
     }
   }
   return bad;
