@@ -164,8 +164,13 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   // ---- refinement sweeps ----
   const gptr<double> R = as_global(a.v) + (size_t)s0 * ROW + i;
   const gptr<const double> Pr = as_global((const double*)a.P) + (size_t)s0 * nn + (size_t)(i < n ? i : n - 1) * n;
-  const gptr<const double> Kr = as_global((const double*)a.K) + (size_t)s0 * nn + (size_t)(i < n ? i : n - 1) * n;
-  const gptr<const double> Kbr = as_global((const double*)a.Kb) + (size_t)s0 * nn + (size_t)(i < n ? i : n - 1) * n;
+  // the chains take bases STAGE_PAD stages before stage 0 and lane offsets
+  const int64_t sp = s0 - STAGE_PAD;
+  const gptr<double> Rb = as_global(a.v) + sp * ROW;
+  const gptr<const double> Kb0 = as_global((const double*)a.K) + sp * (int64_t)nn;
+  const gptr<const double> Kbb0 = as_global((const double*)a.Kb) + sp * (int64_t)nn;
+  const uint32_t orow = (uint32_t)((STAGE_PAD * ROW + i) * (int)sizeof(double));
+  const uint32_t oblk = (uint32_t)((STAGE_PAD * (int)nn + (i < n ? i : n - 1) * n) * (int)sizeof(double));
   for (int sweep = 0; sweep < a.sweeps && !bad; ++sweep) {
     // pass 1: residual r - K e and the Schur right-hand side
     //   rhs_t = r_x,t + rho_b (C' r_f)_t + G_t'(w .* r_g,t)
@@ -215,7 +220,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     }
     wave_sync();
     // passes 2-4: d_x = S^{-1} rhs
-    if (q == 0) chain<double, n, +1>(R, Kr, N);
+    if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
     wave_sync();
     for (int blk = 0; blk < nbl; ++blk) {
       const int t = 4 * blk + q;
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
       R[(size_t)t * ROW] = dotb<n>(Prow, R[(size_t)t * ROW], 0.0);
     }
     wave_sync();
-    if (q == 0) chain<double, n, -1>(R, Kbr, N);
+    if (q == 0) chain<double, n, -1>(Rb, Kbb0, orow, oblk, N);
     wave_sync();
     // pass 5: d_y = rho_b (J d_x - r_y), e += d
     for (int blk = 0; blk < nbl; ++blk) {

@@ -1,8 +1,7 @@
 // Building blocks of the ADMM iteration of Algorithm 3 (the iteration itself
 // is in wave.h): the slack/projection update of one inequality row, the
 // compile-time structure of the per-iteration data, the time-invariant blocks
-// held in registers, per-lane base pointers of the stage data and the
-// per-solve initialisation.
+// held in registers and the per-solve initialisation.
 #pragma once
 
 #include "factor.h"
@@ -70,48 +69,6 @@ struct TIBlocks {
     lo = (i < NG) ? ((const T*)L.loT)[(size_t)b * NG + i] : T(0);
     hi = (i < NG) ? ((const T*)L.hiT)[(size_t)b * NG + i] : T(0);
     bd = (L.bdT && i < NX) ? ((const T*)L.bdT)[(size_t)b * NX + i] : T(0);
-  }
-};
-
-// Per-row base pointers of the per-iteration data, advanced one stage at a
-// time.  Lanes past the block height read a valid row (their results are
-// never broadcast or stored).
-template <typename T, int NX, int NU, int NG>
-struct StagePtrs {
-  static constexpr int n = NX + NU;
-  gptr<const T> SAr, SBr, CFr, CBr;  // rows of SubA, SubB, ChF, ChB
-  gptr<const T> AmC, ApC, GC;       // column `lane` of the time-varying blocks
-  gptr<const T> AmR, ApR, GR;       // row `lane` of the time-varying blocks
-  gptr<const T> lo, hi, bd, q;
-  gptr<T> x, v, yf, zg, yg, xi;     // padded state of stage t (y_f: slot of stage t)
-  __device__ StagePtrs(const Layout& L, const Group& g) {
-    const size_t nn = (size_t)n * n;
-    const int i = g.lane;
-    const int ir = i < n ? i : n - 1;
-    const int ix = i < NX ? i : NX - 1;
-    const int ig = i < NG ? i : NG - 1;
-    const int64_t s0 = g.s0;
-    SAr = as_global((const T*)L.SubA + (size_t)s0 * nn + (size_t)ir * n);
-    SBr = as_global((const T*)L.SubB + (size_t)s0 * nn + (size_t)ir * n);
-    CFr = as_global((const T*)L.ChF + (size_t)s0 * nn + (size_t)ir * n);
-    CBr = as_global((const T*)L.ChB + (size_t)s0 * nn + (size_t)ir * n);
-    AmC = as_global((const T*)L.AmT + (size_t)s0 * NX * n + ir);
-    ApC = as_global((const T*)L.ApT + (size_t)s0 * NX * n + ir);
-    GC = as_global((const T*)L.GT + (size_t)s0 * NG * n + ir);
-    AmR = as_global((const T*)L.AmT + (size_t)s0 * NX * n + (size_t)ix * n);
-    ApR = as_global((const T*)L.ApT + (size_t)s0 * NX * n + (size_t)ix * n);
-    GR = as_global((const T*)L.GT + (size_t)s0 * NG * n + (size_t)ig * n);
-    lo = as_global((const T*)L.loT + (size_t)s0 * NG + ig);
-    hi = as_global((const T*)L.hiT + (size_t)s0 * NG + ig);
-    bd = L.bdT ? as_global((const T*)L.bdT + (size_t)s0 * NX + ix) : nullptr;
-    q = L.qT ? as_global((const T*)L.qT + (size_t)s0 * n + ir) : nullptr;
-    const size_t sv = (size_t)s0 * ROW + i;
-    x = as_global((T*)L.x + sv);
-    v = as_global((T*)L.v + sv);
-    yf = as_global((T*)L.yf + sv);
-    zg = as_global((T*)L.zg + sv);
-    yg = as_global((T*)L.yg + sv);
-    xi = as_global((T*)L.xi + sv);
   }
 };
 

@@ -18,7 +18,8 @@
 //
 // The passes hand vectors to other lanes through the per-instance buffer v
 // and are separated by workgroup barriers (the workgroup is the one
-// wavefront).
+// wavefront).  A stage-parallel pass walks 4-stage blocks; all blocks but
+// the last hold stages t < N only and run without masks.
 #pragma once
 
 #include "admm.h"
@@ -44,98 +45,84 @@ __device__ __forceinline__ bool wave_group(const Layout& L, WaveGroup& w) {
   return true;
 }
 
-// pass-1 inputs of the stage on this row
-template <typename T, int NX, int NU, int NG, bool TI>
-struct EtaIn {
+
+// ---------------------------------------------------------------------------
+// Addressing.  Every buffer the iteration streams is reached from a
+// wave-uniform base pointer (scalar registers) plus a 32-bit per-lane byte
+// offset, so that loads and stores take the scalar-base + vector-offset form
+// and the constant stage steps fold into the instructions' immediate offsets.
+// The bases of the padded buffers (factor products, stage vectors) sit
+// STAGE_PAD stages before stage 0 of the instance, so the offsets of the
+// accesses before stage 0 (y_f,t-1 at t = 0, the backward-chain prefetch)
+// stay non-negative.
+// ---------------------------------------------------------------------------
+template <int IMM = 0, typename T>
+__device__ __forceinline__ std::remove_const_t<T> ldo(gptr<T> base, uint32_t off) {
+  return *(gptr<const T>)((gptr<const char>)base + off + IMM);
+}
+template <int IMM = 0, typename T>
+__device__ __forceinline__ void sto(gptr<T> base, uint32_t off, T v) {
+  *(gptr<T>)((gptr<char>)base + off + IMM) = v;
+}
+// K consecutive entries from base + off (16-byte aligned: whole 16-byte
+// loads), or K entries STRIDE apart
+template <typename T>
+struct Vec16 {
+  static constexpr int N = 16 / (int)sizeof(T);
+  typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+};
+template <int K, int STRIDE = 1, typename T>
+__device__ __forceinline__ void ldo_n(T (&d)[K], gptr<const T> base, uint32_t off) {
+  using V = Vec16<T>;
+  if constexpr (STRIDE == 1 && K % V::N == 0) {
+    const gptr<const typename V::type> p = (gptr<const typename V::type>)((gptr<const char>)base + off);
+#pragma unroll
+    for (int k = 0; k < K / V::N; ++k) {
+      const typename V::type u = p[k];
+#pragma unroll
+      for (int e = 0; e < V::N; ++e) d[V::N * k + e] = u[e];
+    }
+  } else {
+    const gptr<const T> p = (gptr<const T>)((gptr<const char>)base + off);
+#pragma unroll
+    for (int k = 0; k < K; ++k) d[k] = p[k * STRIDE];
+  }
+}
+
+// Uniform base pointers of one instance.
+template <typename T, int NX, int NU, int NG>
+struct IterPtrs {
   static constexpr int n = NX + NU;
-  static constexpr bool SA = sizeof(T) == 4;  // FP32 iterations multiply by Linv_t here
-  T Ar[SA ? n : 1];                           // row `lane` of SubA
-  T x, q, yf, yfm, zg, yg, bd, bdm;
-  T AmC[TI ? 1 : NX], ApCm[TI ? 1 : NX], GC[TI ? 1 : NG];
+  gptr<const T> SA, SB, CF, CB;  // factor products (SubA, SubB, ChF, ChB), at stage -STAGE_PAD
+  gptr<T> x, v, yf, zg, yg, xi;  // stage vectors, at stage -STAGE_PAD
+  gptr<const T> Am, Ap, G;       // TI: the instance's blocks; TV: stage 0 of the instance
+  gptr<const T> lo, hi, bd;      // likewise (bd may be null)
+  gptr<const T> q;               // stage 0 of the instance (may be null)
+  __device__ IterPtrs(const Layout& L, int b, int64_t s0) {
+    const int64_t nn = (int64_t)n * n;
+    const int64_t sp = s0 - STAGE_PAD;
+    const int64_t u = L.ti ? (int64_t)b : s0;  // unit of the constraint data
+    SA = L.SubA ? as_global((const T*)L.SubA + sp * nn) : nullptr;
+    SB = as_global((const T*)L.SubB + sp * nn);
+    CF = as_global((const T*)L.ChF + sp * nn);
+    CB = as_global((const T*)L.ChB + sp * nn);
+    x = as_global((T*)L.x + sp * ROW);
+    v = as_global((T*)L.v + sp * ROW);
+    yf = as_global((T*)L.yf + sp * ROW);
+    zg = as_global((T*)L.zg + sp * ROW);
+    yg = as_global((T*)L.yg + sp * ROW);
+    xi = as_global((T*)L.xi + sp * ROW);
+    Am = as_global((const T*)L.AmT + u * NX * n);
+    Ap = as_global((const T*)L.ApT + u * NX * n);
+    G = as_global((const T*)L.GT + u * NG * n);
+    lo = as_global((const T*)L.loT + u * NG);
+    hi = as_global((const T*)L.hiT + u * NG);
+    bd = L.bdT ? as_global((const T*)L.bdT + u * NX) : nullptr;
+    q = L.qT ? as_global((const T*)L.qT + s0 * n) : nullptr;
+  }
 };
 
-// t may run up to STAGE_PAD - 1 stages past N: the padded state and factor
-// buffers are read unclamped, the exactly sized problem data at min(t, N)
-template <typename T, int NX, int NU, int NG, bool TI>
-__device__ __forceinline__ void load_eta(EtaIn<T, NX, NU, NG, TI>& d, const StagePtrs<T, NX, NU, NG>& p, int t,
-                                         int N) {
-  constexpr int n = NX + NU;
-  const int tc = min(t, N);
-  const int tm = tc > 0 ? tc - 1 : 0;
-  if constexpr (EtaIn<T, NX, NU, NG, TI>::SA) load_row<n>(d.Ar, p.SAr + (long)t * n * n, true);
-  d.x = p.x[(long)t * ROW];
-  d.q = p.q ? p.q[(size_t)tc * n] : T(0);
-  d.yf = p.yf[(long)t * ROW];
-  d.yfm = p.yf[(long)(t - 1) * ROW];
-  d.zg = p.zg[(long)t * ROW];
-  d.yg = p.yg[(long)t * ROW];
-  if constexpr (!TI) {
-    d.bd = p.bd ? p.bd[(size_t)tc * NX] : T(0);
-    d.bdm = p.bd ? p.bd[(size_t)tm * NX] : T(0);
-    load_col<NX>(d.AmC, p.AmC + (size_t)tc * NX * n, n, true);
-    load_col<NX>(d.ApCm, p.ApC + (size_t)tm * NX * n, n, true);
-    load_col<NG>(d.GC, p.GC + (size_t)tc * NG * n, n, true);
-  }
-}
-
-// pass-3 inputs: row `lane` of SubB and v_t
-template <typename T, int n>
-struct TrIn {
-  T Br[n];
-  T v;
-};
-
-// pass-5 inputs of the stage on this row
-template <typename T, int NX, int NU, int NG, bool TI>
-struct UpdIn {
-  static constexpr int n = NX + NU;
-  T xt, xt1;  // x~_t, x~_{t+1}
-  T x, yf, zg, yg, lo, hi, bd;
-  T AmR[TI ? 1 : n], ApR[TI ? 1 : n], GR[TI ? 1 : n];
-};
-
-template <typename T, int NX, int NU, int NG, bool TI>
-__device__ __forceinline__ void load_upd(UpdIn<T, NX, NU, NG, TI>& d, const StagePtrs<T, NX, NU, NG>& p,
-                                         gptr<const T> R, int t, int N) {
-  constexpr int n = NX + NU;
-  const int tc = min(t, N);
-  d.xt = R[(long)t * ROW];
-  d.xt1 = (t < N) ? R[(long)(t + 1) * ROW] : T(0);
-  d.x = p.x[(long)t * ROW];
-  d.yf = p.yf[(long)t * ROW];
-  d.zg = p.zg[(long)t * ROW];
-  d.yg = p.yg[(long)t * ROW];
-  if constexpr (!TI) {
-    d.lo = p.lo[(size_t)tc * NG];
-    d.hi = p.hi[(size_t)tc * NG];
-    d.bd = p.bd ? p.bd[(size_t)tc * NX] : T(0);
-    load_row<n>(d.AmR, p.AmR + (size_t)tc * NX * n, true);
-    load_row<n>(d.ApR, p.ApR + (size_t)tc * NX * n, true);
-    load_row<n>(d.GR, p.GR + (size_t)tc * NG * n, true);
-  }
-}
-
-// the state part of the pass-5 inputs (x~ comes from elsewhere); t may lie
-// up to STAGE_PAD stages outside 0..N (padded state read unclamped, problem
-// data at the nearest stage)
-template <typename T, int NX, int NU, int NG, bool TI>
-__device__ __forceinline__ void load_upd_state(UpdIn<T, NX, NU, NG, TI>& d, const StagePtrs<T, NX, NU, NG>& p, int t,
-                                               int N) {
-  constexpr int n = NX + NU;
-  const int tc = t < 0 ? 0 : (t > N ? N : t);
-  d.x = p.x[(long)t * ROW];
-  d.yf = p.yf[(long)t * ROW];
-  d.zg = p.zg[(long)t * ROW];
-  d.yg = p.yg[(long)t * ROW];
-  if constexpr (!TI) {
-    d.lo = p.lo[(size_t)tc * NG];
-    d.hi = p.hi[(size_t)tc * NG];
-    d.bd = p.bd ? p.bd[(size_t)tc * NX] : T(0);
-    load_row<n>(d.AmR, p.AmR + (size_t)tc * NX * n, true);
-    load_row<n>(d.ApR, p.ApR + (size_t)tc * NX * n, true);
-    load_row<n>(d.GR, p.GR + (size_t)tc * NG * n, true);
-  }
-}
+__device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
 // chain inputs of one stage: row `lane` of a chain block and one vector entry
 template <typename T, int n>
@@ -144,47 +131,43 @@ struct ChainIn {
   T r;
 };
 
-template <typename T, int n>
-__device__ __forceinline__ void load_chain(ChainIn<T, n>& d, gptr<const T> a, gptr<const T> r) {
-#pragma unroll
-  for (int k = 0; k < n; ++k) d.A[k] = a[k];
-  d.r = *r;
-}
-
-__device__ __forceinline__ void wave_sync() { __syncthreads(); }
-
-// One substitution chain on row 0: y_t = R[t] - B_t y_prev over the stages
-// in `dir` order (+1: 0..N with B = ChF; -1: N..0 with B = ChB); y_t -> R[t].
+// One substitution chain on row 0: y_t = R_t - B_t y_prev over the stages in
+// `dir` order (+1: 0..N with B = ChF; -1: N..0 with B = ChB); y_t -> R_t.
+// R, Bm: biased bases; orow / oblk: this lane's offsets at stage 0.  The
+// running stage position lives in the (uniform) base pointers, the lane
+// offsets stay fixed.
 template <typename T, int n, int DIR>
-__device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, int N) {
+__device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, uint32_t orow, uint32_t oblk, int N) {
   constexpr int PF = chain_prefetch<T, n>();
   static_assert(PF <= STAGE_PAD, "prefetch reaches past the buffer padding");
-  constexpr long dB = DIR * (long)n * n;  // block stride of one step of the sweep
-  constexpr long dR = DIR * (long)ROW;
-  // running pointers at the sweep's k0-th stage (t = 0 forward, t = N
-  // backward); prefetches run up to PF stages past either end of the
-  // instance, into the neighbouring instances or the padding
-  gptr<const T> Bk = Bm + (DIR > 0 ? 0 : (long)N * n * n);
+  constexpr int VS = DIR * ROW * (int)sizeof(T);  // one step of the sweep in a vector, bytes
+  constexpr long BS = DIR * (long)n * n;          // one step in the blocks, elements
+  // bases at the sweep's k0-th stage (t = 0 forward, t = N backward);
+  // prefetches run up to PF stages past either end of the instance, into
+  // the neighbouring instances or the padding
   gptr<T> Rk = R + (DIR > 0 ? 0 : (long)N * ROW);
+  gptr<const T> Bk = Bm + (DIR > 0 ? 0 : (long)N * n * n);
   ChainIn<T, n> buf[PF];
-  sfor<0, PF>([&](auto j) {
+  auto load = [&](ChainIn<T, n>& d, auto j) {
     constexpr int jj = decltype(j)::value;
-    load_chain(buf[jj], Bk + jj * dB, Rk + jj * dR);
-  });
+    ldo_n<n>(d.A, Bk + jj * BS, oblk);
+    d.r = ldo<jj * VS>(Rk, orow);
+  };
+  sfor<0, PF>([&](auto j) { load(buf[decltype(j)::value], j); });
   T yprev = T(0);
   auto body = [&](auto j) {
     constexpr int jj = decltype(j)::value;
     ChainIn<T, n>& d = buf[jj];
     const T y = d.r - dotb<n>(d.A, yprev, T(0));  // stage 0 / N chain blocks are zero slots
-    Rk[jj * dR] = y;
+    sto<jj * VS>(Rk, orow, y);
     yprev = y;
-    load_chain(d, Bk + (jj + PF) * dB, Rk + (jj + PF) * dR);
+    load(d, std::integral_constant<int, jj + PF>{});
   };
   int k0 = 0;
   for (; k0 + PF - 1 <= N; k0 += PF) {
     sfor<0, PF>(body);
-    Bk += PF * dB;
-    Rk += PF * dR;
+    Rk += PF * DIR * ROW;
+    Bk += PF * BS;
   }
   sfor<0, PF>([&](auto j) {
     if (k0 + decltype(j)::value <= N) body(j);
@@ -195,25 +178,93 @@ __device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, int N) {
 template <typename T, int NX, int NU, int NG, typename ST>
 struct IterCtx {
   const TIBlocks<T, NX, NU, NG>& tb;
-  const StagePtrs<T, NX, NU, NG>& P;
+  const IterPtrs<T, NX, NU, NG>& P;
   T sigma, rho_f, rho_g, alpha, oma, rfa;
   int kind;
   ProjConst<T> pc;
   T xinit, yinit;
   int gsel, ginv;
-  int i, N;
+  int i, q, N;
+  bool gid;   // (uniform) the selection of every inequality row r < ng is variable r
+  bool hard;  // (uniform) no soft inequality rows
 };
 
-// r_t of the stage on this row: eta_t, times Linv_t for FP32 iterations
-template <typename T, int NX, int NU, int NG, typename ST>
+// this lane's byte offsets at block 0 (stage q of row q)
+template <typename T, int n>
+struct LaneOff {
+  static constexpr uint32_t VS = ROW * sizeof(T);          // one stage of a vector
+  static constexpr uint32_t FS = (uint32_t)n * n * sizeof(T);  // one stage of a factor product
+  static constexpr uint32_t VB = 4 * VS, FB = 4 * FS;      // one 4-stage block
+  uint32_t v, f;  // entry `lane` of the vectors / row `lane` of the factor products
+  __device__ LaneOff(int q, int lane) {
+    const int ir = lane < n ? lane : n - 1;
+    v = (uint32_t)(((STAGE_PAD + q) * ROW + lane) * (int)sizeof(T));
+    f = (uint32_t)(((STAGE_PAD + q) * n * n + ir * n) * (int)sizeof(T));
+  }
+};
+
+// Stage blocks of a stage-parallel pass: blocks 0..nfull-1 hold four stages
+// t < N each (no masking); block nfull holds the rest (t = 4 nfull + q up to
+// N, rows past N idle).  Inputs of block b+1 are loaded while block b
+// computes, in two alternating buffers.
+template <typename In, typename Load, typename Comp>
+__device__ __forceinline__ void stage_blocks(int nfull, Load&& load, Comp&& comp) {
+  In a, b;
+  load(a, 0);
+  int blk = 0;
+  for (; blk + 2 <= nfull; blk += 2) {
+    load(b, blk + 1);
+    comp(a, blk, std::true_type{});
+    load(a, blk + 2);
+    comp(b, blk + 1, std::true_type{});
+  }
+  if (blk < nfull) {
+    load(b, blk + 1);
+    comp(a, blk, std::true_type{});
+    comp(b, blk + 1, std::false_type{});
+  } else {
+    comp(a, blk, std::false_type{});
+  }
+}
+
+// pass-1 inputs of the stage on this row
+template <typename T, int NX, int NU, int NG, bool TI>
+struct EtaIn {
+  static constexpr int n = NX + NU;
+  static constexpr bool SA = sizeof(T) == 4;  // FP32 iterations multiply by Linv_t here
+  T Ar[SA ? n : 1];                           // row `lane` of SubA
+  T x, q, yf, yfm, zg, yg, bd, bdm;
+  T AmC[TI ? 1 : NX], ApCm[TI ? 1 : NX], GC[TI ? 1 : NG];
+};
+
+// pass-5 inputs of the stage on this row
+template <typename T, int NX, int NU, int NG, bool TI>
+struct UpdIn {
+  static constexpr int n = NX + NU;
+  T xt, xt1;  // x~_t, x~_{t+1} (x~_{t+1} past N is never used)
+  T x, yf, zg, yg, lo, hi, bd;
+  T AmR[TI ? 1 : n], ApR[TI ? 1 : n], GR[TI ? 1 : n];
+};
+
+// pass-3 inputs: row `lane` of SubB and v_t
+template <typename T, int n>
+struct TrIn {
+  T Br[n];
+  T v;
+};
+
+// r_t of the stage on this row: eta_t, times Linv_t for FP32 iterations.
+// `init` is this lane's initial-state term (rho_f x_init - y_init on lanes
+// < nx), added at t = 0.
+template <bool FULL, typename T, int NX, int NU, int NG, typename ST>
 __device__ __forceinline__ T stage_r(const IterCtx<T, NX, NU, NG, ST>& c, const EtaIn<T, NX, NU, NG, ST::TI>& cur,
-                                     int t) {
+                                     int t, T init) {
   constexpr int n = NX + NU;
   constexpr bool TI = ST::TI;
-  const int i = c.i, N = c.N;
+  const int i = c.i;
   const auto& tb = c.tb;
   T eta = c.sigma * cur.x - cur.q;
-  const T w_ = (t < N && i < NX) ? c.rho_f * (TI ? tb.bd : cur.bd) - cur.yf : T(0);
+  const T w_ = ((FULL || t < c.N) && i < NX) ? c.rho_f * (TI ? tb.bd : cur.bd) - cur.yf : T(0);
   const T wm = (t > 0 && i < NX) ? c.rho_f * (TI ? tb.bd : cur.bdm) - cur.yfm : T(0);
   if constexpr (TI)
     eta = dotb<NX>(tb.AmC, w_, eta);
@@ -226,11 +277,15 @@ __device__ __forceinline__ T stage_r(const IterCtx<T, NX, NU, NG, ST>& c, const 
   } else {
     eta = dotb<NX>(cur.ApCm, wm, eta);
   }
-  eta += (t == 0 && i < NX) ? c.rho_f * c.xinit - c.yinit : T(0);
+  eta += (t == 0) ? init : T(0);
   const T u = (i < NG) ? c.rho_g * cur.zg - cur.yg : T(0);
   if constexpr (ST::GSEL) {
-    const T gu = row_gather(u, c.ginv < 0 ? 0 : c.ginv);
-    eta += (c.ginv >= 0) ? gu : T(0);
+    if (c.gid) {
+      eta += u;
+    } else {
+      const T gu = row_gather(u, c.ginv < 0 ? 0 : c.ginv);
+      eta += (c.ginv >= 0) ? gu : T(0);
+    }
   } else if constexpr (TI) {
     eta = dotb<NG>(tb.GC, u, eta);
   } else {
@@ -243,16 +298,16 @@ __device__ __forceinline__ T stage_r(const IterCtx<T, NX, NU, NG, ST>& c, const 
 }
 
 // over-relaxation, projection and dual update of every constraint row of
-// the stage on this row, from x~_t and x~_{t+1}
-template <typename T, int NX, int NU, int NG, typename ST>
+// the stage on this row, from x~_t and x~_{t+1}; stores the new state
+// (rows past N store nothing, y_f only for t < N)
+template <bool FULL, typename T, int NX, int NU, int NG, typename ST>
 __device__ __forceinline__ void stage_update(const IterCtx<T, NX, NU, NG, ST>& c,
-                                             const UpdIn<T, NX, NU, NG, ST::TI>& cur, T xt, T xt1, int t) {
+                                             const UpdIn<T, NX, NU, NG, ST::TI>& cur, int t, uint32_t o) {
   constexpr int n = NX + NU;
   constexpr bool TI = ST::TI;
-  const int i = c.i, N = c.N;
   const auto& tb = c.tb;
   const auto& P = c.P;
-  const size_t o = (size_t)t * ROW;
+  const T xt = cur.xt, xt1 = cur.xt1;
   // dynamics row t: y_f += rho_f alpha (A^- x~_t + A^+ x~_{t+1} - c_t)
   T zf;
   if constexpr (TI)
@@ -266,91 +321,144 @@ __device__ __forceinline__ void stage_update(const IterCtx<T, NX, NU, NG, ST>& c
   } else {
     zf = dotb<n>(cur.ApR, xt1, zf);
   }
-  if (t < N) P.yf[o] = cur.yf + c.rfa * (zf - (TI ? tb.bd : cur.bd));
+  const T yfn = cur.yf + c.rfa * (zf - (TI ? tb.bd : cur.bd));
   // inequality rows of stage t (lanes past ng update padding)
   T zt;
   if constexpr (ST::GSEL)
-    zt = row_gather(xt, c.gsel);
+    zt = c.gid ? xt : row_gather(xt, c.gsel);
   else if constexpr (TI)
     zt = dotb<n>(tb.GR, xt, T(0));
   else
     zt = dotb<n>(cur.GR, xt, T(0));
   const T zh = c.alpha * zt + c.oma * cur.zg;
-  const Proj<T> pr =
-      project_row<T>(fma(cur.yg, c.pc.inv_rho, zh), TI ? tb.lo : cur.lo, TI ? tb.hi : cur.hi, c.kind, c.pc);
-  P.zg[o] = pr.z;
-  P.xi[o] = pr.xi;
-  P.yg[o] = cur.yg + c.rho_g * (zh - pr.z);
-  P.x[o] = c.alpha * xt + c.oma * cur.x;
-  // initial-state rows: y_init += rho_f alpha (x~_0 - x_init)
-  if (t == 0 && i < NX) P.yf[(size_t)N * ROW] = c.yinit + c.rfa * (xt - c.xinit);
+  const T pin = fma(cur.yg, c.pc.inv_rho, zh);
+  const T lo = TI ? tb.lo : cur.lo, hi = TI ? tb.hi : cur.hi;
+  Proj<T> pr;
+  if (c.hard)
+    pr = Proj<T>{clampv(pin, lo, hi), T(0)};
+  else
+    pr = project_row<T>(pin, lo, hi, c.kind, c.pc);
+  const T ygn = cur.yg + c.rho_g * (zh - pr.z);
+  const T xn = c.alpha * xt + c.oma * cur.x;
+  if (FULL || t <= c.N) {
+    if (FULL || t < c.N) sto(P.yf, o, yfn);
+    sto(P.zg, o, pr.z);
+    sto(P.xi, o, pr.xi);
+    sto(P.yg, o, ygn);
+    sto(P.x, o, xn);
+  }
 }
 
 // One iteration on one wavefront (the vectors handed between passes go
-// through the instance's v buffer in global memory).
+// through the instance's v buffer).
 template <typename T, int NX, int NU, int NG, typename ST>
-__device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>& c, int q) {
+__device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>& c, const LaneOff<T, NX + NU>& lo) {
   constexpr int n = NX + NU;
   constexpr bool TI = ST::TI;
-  const int N = c.N;
-  const int nbl = (N + 4) / 4;  // 4-stage blocks covering 0..N
-  const size_t nn = (size_t)n * n;
+  using LO = LaneOff<T, n>;
+  const int N = c.N, q = c.q, i = c.i;
+  const int nfull = N / 4;  // blocks whose four stages all satisfy t < N
   const auto& P = c.P;
-  const gptr<T> R = P.v;  // per-lane base of the exchange buffer
+  const int ir = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
+  const T init = (i < NX) ? c.rho_f * c.xinit - c.yinit : T(0);
 
   // ---------------- pass 1: r_t on row t mod 4 ----------------
   {
-    EtaIn<T, NX, NU, NG, TI> cur, nxt;
-    load_eta(cur, P, q, N);  // stages past N read padding or the next instance (unused)
-    for (int blk = 0; blk < nbl; ++blk) {
+    using In = EtaIn<T, NX, NU, NG, TI>;
+    auto load = [&](In& d, int blk) {
       const int t = 4 * blk + q;
-      load_eta(nxt, P, t + 4, N);
-      if (t <= N) R[(size_t)t * ROW] = stage_r(c, cur, t);
-      cur = nxt;
-    }
+      const uint32_t ov = lo.v + blk * LO::VB;
+      if constexpr (In::SA) ldo_n<n>(d.Ar, P.SA, lo.f + blk * LO::FB);
+      d.x = ldo(P.x, ov);
+      d.yf = ldo(P.yf, ov);
+      d.yfm = ldo<-(int)LO::VS>(P.yf, ov);
+      d.zg = ldo(P.zg, ov);
+      d.yg = ldo(P.yg, ov);
+      // problem data is exactly sized: read at the nearest stage
+      const int tc = min(t, N);
+      const int tm = tc > 0 ? tc - 1 : 0;
+      d.q = P.q ? ldo(P.q, (uint32_t)((tc * n + ir) * (int)sizeof(T))) : T(0);
+      if constexpr (!TI) {
+        d.bd = P.bd ? ldo(P.bd, (uint32_t)((tc * NX + ix) * (int)sizeof(T))) : T(0);
+        d.bdm = P.bd ? ldo(P.bd, (uint32_t)((tm * NX + ix) * (int)sizeof(T))) : T(0);
+        ldo_n<NX, n>(d.AmC, P.Am, (uint32_t)((tc * NX * n + ir) * (int)sizeof(T)));
+        ldo_n<NX, n>(d.ApCm, P.Ap, (uint32_t)((tm * NX * n + ir) * (int)sizeof(T)));
+        ldo_n<NG, n>(d.GC, P.G, (uint32_t)((tc * NG * n + ir) * (int)sizeof(T)));
+      }
+    };
+    auto comp = [&](const In& d, int blk, auto full) {
+      constexpr bool FULL = decltype(full)::value;
+      const int t = 4 * blk + q;
+      const T r = stage_r<FULL>(c, d, t, init);
+      if (FULL || t <= N) sto(P.v, lo.v + blk * LO::VB, r);
+    };
+    stage_blocks<In>(nfull, load, comp);
   }
   wave_sync();
 
   // ---------------- pass 2: forward chain (row 0) ----------------
-  if (q == 0) chain<T, n, +1>(R, P.CFr, N);
+  if (q == 0) chain<T, n, +1>(P.v, P.CF, lo.v, lo.f, N);
   wave_sync();
 
   // ---------------- pass 3: s_t = SubB_t v_t on row t mod 4 ----------------
   {
-    TrIn<T, n> cur, nxt;
-    auto load_tr = [&](TrIn<T, n>& d, int t) {
-      load_row<n>(d.Br, P.SBr + (size_t)t * nn, true);
-      d.v = R[(size_t)t * ROW];
+    using In = TrIn<T, n>;
+    auto load = [&](In& d, int blk) {
+      ldo_n<n>(d.Br, P.SB, lo.f + blk * LO::FB);
+      d.v = ldo(P.v, lo.v + blk * LO::VB);
     };
-    load_tr(cur, q);
-    for (int blk = 0; blk < nbl; ++blk) {
+    auto comp = [&](const In& d, int blk, auto full) {
+      constexpr bool FULL = decltype(full)::value;
       const int t = 4 * blk + q;
-      load_tr(nxt, t + 4);
-      if (t <= N) R[(size_t)t * ROW] = dotb<n>(cur.Br, cur.v, T(0));
-      cur = nxt;
-    }
+      const T s = dotb<n>(d.Br, d.v, T(0));
+      if (FULL || t <= N) sto(P.v, lo.v + blk * LO::VB, s);
+    };
+    stage_blocks<In>(nfull, load, comp);
   }
   wave_sync();
 
   // ---------------- pass 4: backward chain (row 0) ----------------
-  if (q == 0) chain<T, n, -1>(R, P.CBr, N);
+  if (q == 0) chain<T, n, -1>(P.v, P.CB, lo.v, lo.f, N);
   wave_sync();
 
   // ---------------- pass 5: constraint-row updates on row t mod 4 ----------------
   {
-    UpdIn<T, NX, NU, NG, TI> cur, nxt;
-    load_upd(cur, P, R, q, N);
-    for (int blk = 0; blk < nbl; ++blk) {
+    using In = UpdIn<T, NX, NU, NG, TI>;
+    auto load = [&](In& d, int blk) {
       const int t = 4 * blk + q;
-      load_upd(nxt, P, R, t + 4, N);
-      if (t <= N) stage_update(c, cur, cur.xt, cur.xt1, t);
-      cur = nxt;
-    }
+      const uint32_t ov = lo.v + blk * LO::VB;
+      d.xt = ldo(P.v, ov);
+      d.xt1 = ldo<(int)LO::VS>(P.v, ov);
+      d.x = ldo(P.x, ov);
+      d.yf = ldo(P.yf, ov);
+      d.zg = ldo(P.zg, ov);
+      d.yg = ldo(P.yg, ov);
+      if constexpr (!TI) {
+        const int tc = min(t, N);
+        d.lo = ldo(P.lo, (uint32_t)((tc * NG + ig) * (int)sizeof(T)));
+        d.hi = ldo(P.hi, (uint32_t)((tc * NG + ig) * (int)sizeof(T)));
+        d.bd = P.bd ? ldo(P.bd, (uint32_t)((tc * NX + ix) * (int)sizeof(T))) : T(0);
+        ldo_n<n>(d.AmR, P.Am, (uint32_t)((tc * NX * n + ix * n) * (int)sizeof(T)));
+        ldo_n<n>(d.ApR, P.Ap, (uint32_t)((tc * NX * n + ix * n) * (int)sizeof(T)));
+        ldo_n<n>(d.GR, P.G, (uint32_t)((tc * NG * n + ig * n) * (int)sizeof(T)));
+      }
+    };
+    auto comp = [&](const In& d, int blk, auto full) {
+      constexpr bool FULL = decltype(full)::value;
+      stage_update<FULL>(c, d, 4 * blk + q, lo.v + blk * LO::VB);
+    };
+    stage_blocks<In>(nfull, load, comp);
+  }
+  // initial-state rows: y_init += rho_f alpha (x~_0 - x_init), slot N of y_f
+  if (q == 0 && i < NX) {
+    const T x0 = ldo(P.v, lo.v);
+    sto(P.yf, lo.v + (uint32_t)(N * LO::VS), c.yinit + c.rfa * (x0 - c.xinit));
   }
   wave_sync();
 }
 
 }  // namespace ocpk
+
 
 namespace ocpk {
 
@@ -539,9 +647,19 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
   WaveGroup w;
   if (!wave_group(L, w)) return;
   if (L.status[w.b] != ST_RUNNING) return;
+  // the non-inlined callees get their own copy: the kernel argument itself
+  // never has its address taken, so every field read from it here stays a
+  // wave-uniform (scalar) value
+  const Layout Lc = L;
   const int i = w.lane;
   const Group g{w.lane, w.b, w.s0, w.N};
   const int kind = (i < NG) ? (int)L.soft[i] : 0;
+  const bool hard = __ballot(kind != 0) == 0;
+  const int gsel = L.gsel[i < NG ? i : 0], ginv = L.ginv[i];
+  const bool gid = __ballot(i < NG && gsel != i) == 0;
+  const IterPtrs<T, NX, NU, NG> P(L, w.b, w.s0);
+  const LaneOff<T, NX + NU> lo(w.row, i);
+  const uint32_t o_yinit = (uint32_t)(((STAGE_PAD + w.N) * ROW + i) * (int)sizeof(T));
   double rho_bar = L.rho[w.b];
   int nfact = L.nfact[w.b];
   int status = ST_RUNNING;
@@ -555,7 +673,7 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
   for (;;) {
     if (need) {  // the only call site of the factorisation
       constexpr int FORM = sizeof(T) == 4 ? FACTOR_WV : FACTOR_PK;
-      const int bad = factor_instance<T, NX, NU, NG, ST::TI, FORM>(L, g, st.sigma, st.rho_f_scale * rho_bar,
+      const int bad = factor_instance<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
                                                                    rho_bar, nullptr, w.row);
       wave_sync();
       if (bad) {
@@ -572,24 +690,22 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
     {
       TIBlocks<T, NX, NU, NG> tb;
       if constexpr (ST::TI) tb.load(L, w.b, i);
-      const StagePtrs<T, NX, NU, NG> P(L, g);
       const ProjConst<T> pc(T(rho_bar), T(L.gamma2), T(L.gamma1));
       const T xinit = ((const T*)L.xinitT)[(size_t)w.b * NX + (i < NX ? i : 0)];
       const T rho_f = T(st.rho_f_scale * rho_bar), alpha = T(st.alpha);
-      const IterCtx<T, NX, NU, NG, ST> c{tb,          P,           T(st.sigma),        rho_f, T(rho_bar), alpha,
-                                         T(1) - alpha, rho_f * alpha, kind,          pc,    xinit,      T(0),
-                                         L.gsel[i < NG ? i : 0],   L.ginv[i],          i,     w.N};
+      const IterCtx<T, NX, NU, NG, ST> c{tb,   P,    T(st.sigma), rho_f, T(rho_bar), alpha, T(1) - alpha,
+                                         rho_f * alpha, kind, pc, xinit, T(0), gsel, ginv, i, w.row, w.N, gid, hard};
       for (; k < nb; ++k) {
         IterCtx<T, NX, NU, NG, ST> ck = c;
-        ck.yinit = P.yf[(size_t)w.N * ROW];  // initial-state multipliers (slot N)
-        wave_iteration<T, NX, NU, NG, ST>(ck, w.row);
+        ck.yinit = ldo(P.yf, o_yinit);  // initial-state multipliers (slot N)
+        wave_iteration<T, NX, NU, NG, ST>(ck, lo);
       }
     }
     const int check = (st.k_check > 0 && nb % st.k_check == 0) ? 1 : 0;
     const int adapt = (adapt_on && nb % st.k_rho == 0 && nb < st.max_iter) ? 1 : 0;
     const int last = (nb == st.max_iter) ? 1 : 0;
     if (check || adapt || last) {
-      R = residuals_wave<T, NX, NU, NG, ST::TI>(L, w, kind, L.gamma2, L.gamma1);
+      R = residuals_wave<T, NX, NU, NG, ST::TI>(Lc, w, kind, L.gamma2, L.gamma1);
       status = boundary_decision(R, st, check, adapt, last, rho_bar, need);
       if (status != ST_RUNNING) break;
     }
