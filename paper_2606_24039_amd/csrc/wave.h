@@ -174,6 +174,68 @@ __device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, uint32_t orow
   });
 }
 
+// The same chain on all four rows (FP32, n a multiple of 4): row q holds
+// columns q n/4 .. (q+1) n/4 - 1 of the chain block's rows, multiplies them
+// with the matching entries of y_prev (moved to lanes 0..n/4-1 of the row
+// by a row-masked DPP shift) and the four partial sums are added across the
+// rows by two permlane swaps, which leaves the same y_t on every row.  Per
+// stage: three shifts, n/4 broadcast FMAs and the two swap-adds in place of
+// n broadcast FMAs on one row, and one 16-byte load per lane.
+template <int n, int DIR>
+__device__ __forceinline__ void chain_rows(gptr<float> R, gptr<const float> Bm, uint32_t orow, uint32_t oblk, int N) {
+  static_assert(n % 4 == 0 && n <= ROW, "row-split chain needs n = 4k <= 16");
+  constexpr int QS = n / 4;
+  constexpr int PF = chain_prefetch<float, n>();
+  static_assert(PF <= STAGE_PAD, "prefetch reaches past the buffer padding");
+  constexpr int VS = DIR * ROW * (int)sizeof(float);
+  constexpr long BS = DIR * (long)n * n;
+  gptr<float> Rk = R + (DIR > 0 ? 0 : (long)N * ROW);
+  gptr<const float> Bk = Bm + (DIR > 0 ? 0 : (long)N * n * n);
+  struct In {
+    float A[QS];
+    float r;
+  };
+  In buf[PF];
+  auto load = [&](In& d, auto j) {
+    constexpr int jj = decltype(j)::value;
+    ldo_n<QS>(d.A, Bk + jj * BS, oblk);
+    d.r = ldo<jj * VS>(Rk, orow);
+  };
+  sfor<0, PF>([&](auto j) { load(buf[decltype(j)::value], j); });
+  float y = 0.f;
+  auto body = [&](auto j) {
+    constexpr int jj = decltype(j)::value;
+    In& d = buf[jj];
+    float z = y;  // row q: y[q QS + k] at lane k
+    z = __builtin_amdgcn_update_dpp(z, y, 0x100 + QS, 0x2, 0xf, false);
+    z = __builtin_amdgcn_update_dpp(z, y, 0x100 + 2 * QS, 0x4, 0xf, false);
+    z = __builtin_amdgcn_update_dpp(z, y, 0x100 + 3 * QS, 0x8, 0xf, false);
+    const float pq = dotb<QS>(d.A, z, 0.f);
+    const unsigned ub = __builtin_bit_cast(unsigned, pq);
+    const auto h = __builtin_amdgcn_permlane32_swap(ub, ub, false, false);  // rows q, q^2
+    const float c = __builtin_bit_cast(float, (unsigned)h[0]) + __builtin_bit_cast(float, (unsigned)h[1]);
+    const unsigned uc = __builtin_bit_cast(unsigned, c);
+    const auto g = __builtin_amdgcn_permlane16_swap(uc, uc, false, false);  // rows q, q^1
+    const float sum = __builtin_bit_cast(float, (unsigned)g[0]) + __builtin_bit_cast(float, (unsigned)g[1]);
+    y = d.r - sum;  // stage 0 / N chain blocks are zero slots
+    sto<jj * VS>(Rk, orow, y);
+    load(d, std::integral_constant<int, jj + PF>{});
+  };
+  int k0 = 0;
+  for (; k0 + PF - 1 <= N; k0 += PF) {
+    sfor<0, PF>(body);
+    Rk += PF * DIR * ROW;
+    Bk += PF * BS;
+  }
+  sfor<0, PF>([&](auto j) {
+    if (k0 + decltype(j)::value <= N) body(j);
+  });
+}
+
+// FP32 chains with n = 4k run on all four rows
+template <typename T, int n>
+constexpr bool ROWSPLIT_CHAIN = sizeof(T) == 4 && n % 4 == 0 && n <= ROW;
+
 // Scalars of one ADMM iteration of one instance (this lane's view).
 template <typename T, int NX, int NU, int NG, typename ST>
 struct IterCtx {
@@ -196,10 +258,14 @@ struct LaneOff {
   static constexpr uint32_t FS = (uint32_t)n * n * sizeof(T);  // one stage of a factor product
   static constexpr uint32_t VB = 4 * VS, FB = 4 * FS;      // one 4-stage block
   uint32_t v, f;  // entry `lane` of the vectors / row `lane` of the factor products
+  uint32_t v0;    // entry `lane` of stage 0 (every row)
+  uint32_t fq;    // stage 0, row `lane`, columns q n/4.. (row-split chains)
   __device__ LaneOff(int q, int lane) {
     const int ir = lane < n ? lane : n - 1;
     v = (uint32_t)(((STAGE_PAD + q) * ROW + lane) * (int)sizeof(T));
     f = (uint32_t)(((STAGE_PAD + q) * n * n + ir * n) * (int)sizeof(T));
+    v0 = (uint32_t)((STAGE_PAD * ROW + lane) * (int)sizeof(T));
+    fq = (uint32_t)((STAGE_PAD * n * n + ir * n + q * (n / 4)) * (int)sizeof(T));
   }
 };
 
@@ -397,7 +463,10 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
   wave_sync();
 
   // ---------------- pass 2: forward chain (row 0) ----------------
-  if (q == 0) chain<T, n, +1>(P.v, P.CF, lo.v, lo.f, N);
+  if constexpr (ROWSPLIT_CHAIN<T, n>)
+    chain_rows<n, +1>(P.v, P.CF, lo.v0, lo.fq, N);
+  else if (q == 0)
+    chain<T, n, +1>(P.v, P.CF, lo.v, lo.f, N);
   wave_sync();
 
   // ---------------- pass 3: s_t = SubB_t v_t on row t mod 4 ----------------
@@ -418,7 +487,10 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
   wave_sync();
 
   // ---------------- pass 4: backward chain (row 0) ----------------
-  if (q == 0) chain<T, n, -1>(P.v, P.CB, lo.v, lo.f, N);
+  if constexpr (ROWSPLIT_CHAIN<T, n>)
+    chain_rows<n, -1>(P.v, P.CB, lo.v0, lo.fq, N);
+  else if (q == 0)
+    chain<T, n, -1>(P.v, P.CB, lo.v, lo.f, N);
   wave_sync();
 
   // ---------------- pass 5: constraint-row updates on row t mod 4 ----------------
