@@ -710,6 +710,81 @@ __device__ __forceinline__ int boundary_decision(const Resid& R, const Settings&
   return ST_RUNNING;
 }
 
+// wave-uniform copies of values that reach a non-inlined function in vector
+// registers (every lane holds the same value)
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+}
+__device__ __forceinline__ double uni(double v) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, v))); }
+template <typename P>
+__device__ __forceinline__ P* uni(P* p) {
+  return (P*)uni((int64_t)p);
+}
+__device__ __forceinline__ Layout uni(const Layout& L) {
+  Layout u = L;
+  u.stage_off = uni(L.stage_off);
+  u.SubA = uni(L.SubA);
+  u.SubB = uni(L.SubB);
+  u.ChF = uni(L.ChF);
+  u.ChB = uni(L.ChB);
+  u.x = uni(L.x);
+  u.v = uni(L.v);
+  u.yf = uni(L.yf);
+  u.zg = uni(L.zg);
+  u.yg = uni(L.yg);
+  u.xi = uni(L.xi);
+  u.AmT = uni(L.AmT);
+  u.ApT = uni(L.ApT);
+  u.GT = uni(L.GT);
+  u.loT = uni(L.loT);
+  u.hiT = uni(L.hiT);
+  u.bdT = uni(L.bdT);
+  u.qT = uni(L.qT);
+  u.xinitT = uni(L.xinitT);
+  u.ti = uni(L.ti);
+  u.gamma1 = uni(L.gamma1);
+  u.gamma2 = uni(L.gamma2);
+  return u;
+}
+
+// ADMM iterations k0 .. nb-1 of one instance at a fixed rho (a segment of the
+// schedule between two boundaries).  Not inlined: the loop gets the register
+// file to itself, the solve-level state of the caller stays out of it.
+// Returns the iteration count reached.
+template <typename T, int NX, int NU, int NG, typename ST>
+__device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, int b_, int64_t s0_, int N_, int k0_,
+                                        int nb_, double rho_bar_) {
+  const Layout L = uni(Lm);
+  const int b = uni(b_), N = uni(N_), nb = uni(nb_);
+  const int64_t s0 = uni(s0_);
+  const double rho_bar = uni(rho_bar_);
+  const int i = threadIdx.x & (ROW - 1), q = threadIdx.x >> 4;
+  const int kind = (i < NG) ? (int)L.soft[i] : 0;
+  const bool hard = __ballot(kind != 0) == 0;
+  const int gsel = L.gsel[i < NG ? i : 0], ginv = L.ginv[i];
+  const bool gid = __ballot(i < NG && gsel != i) == 0;
+  const IterPtrs<T, NX, NU, NG> P(L, b, s0);
+  const LaneOff<T, NX + NU> lo(q, i);
+  const uint32_t o_yinit = (uint32_t)(((STAGE_PAD + N) * ROW + i) * (int)sizeof(T));
+  TIBlocks<T, NX, NU, NG> tb;
+  if constexpr (ST::TI) tb.load(L, b, i);
+  const ProjConst<T> pc(T(rho_bar), T(L.gamma2), T(L.gamma1));
+  const T xinit = ((const T*)L.xinitT)[(size_t)b * NX + (i < NX ? i : 0)];
+  const T rho_f = T(uni(st.rho_f_scale) * rho_bar), alpha = T(uni(st.alpha));
+  const IterCtx<T, NX, NU, NG, ST> c{tb,   P,    T(uni(st.sigma)), rho_f, T(rho_bar), alpha, T(1) - alpha,
+                                     rho_f * alpha, kind, pc, xinit, T(0), gsel, ginv, i, q, N, gid, hard};
+  int k = uni(k0_);
+  for (; k < nb; ++k) {
+    IterCtx<T, NX, NU, NG, ST> ck = c;
+    ck.yinit = ldo(P.yf, o_yinit);  // initial-state multipliers (slot N)
+    wave_iteration<T, NX, NU, NG, ST>(ck, lo);
+  }
+  return k;
+}
+
 // One complete ADMM solve per wavefront (Algorithm 3 with the stopping test
 // and rho adaptation): FP64 factorisation, iterations up to each boundary,
 // FP64 residuals and decisions at the boundary, refactorisation after an
@@ -719,26 +794,18 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
   WaveGroup w;
   if (!wave_group(L, w)) return;
   if (L.status[w.b] != ST_RUNNING) return;
-  // the non-inlined callees get their own copy: the kernel argument itself
-  // never has its address taken, so every field read from it here stays a
-  // wave-uniform (scalar) value
+  // the non-inlined callees get copies in memory: the kernel arguments
+  // themselves never have their address taken
   const Layout Lc = L;
+  const Settings sc = st;
   const int i = w.lane;
   const Group g{w.lane, w.b, w.s0, w.N};
   const int kind = (i < NG) ? (int)L.soft[i] : 0;
-  const bool hard = __ballot(kind != 0) == 0;
-  const int gsel = L.gsel[i < NG ? i : 0], ginv = L.ginv[i];
-  const bool gid = __ballot(i < NG && gsel != i) == 0;
-  const IterPtrs<T, NX, NU, NG> P(L, w.b, w.s0);
-  const LaneOff<T, NX + NU> lo(w.row, i);
-  const uint32_t o_yinit = (uint32_t)(((STAGE_PAD + w.N) * ROW + i) * (int)sizeof(T));
   double rho_bar = L.rho[w.b];
   int nfact = L.nfact[w.b];
   int status = ST_RUNNING;
   Resid R{INFINITY, INFINITY, 0.0, 0.0, 0};
 
-  // time-invariant blocks (ST::TI) are exactly the handles whose factor
-  // products can be hoisted
   const bool adapt_on = st.adapt_rho && st.k_rho > 0;
   int k = L.iters[w.b];
   bool need = true;
@@ -759,20 +826,7 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
     int nb = st.max_iter;
     if (st.k_check > 0) nb = min(nb, (k / st.k_check + 1) * st.k_check);
     if (adapt_on) nb = min(nb, (k / st.k_rho + 1) * st.k_rho);
-    {
-      TIBlocks<T, NX, NU, NG> tb;
-      if constexpr (ST::TI) tb.load(L, w.b, i);
-      const ProjConst<T> pc(T(rho_bar), T(L.gamma2), T(L.gamma1));
-      const T xinit = ((const T*)L.xinitT)[(size_t)w.b * NX + (i < NX ? i : 0)];
-      const T rho_f = T(st.rho_f_scale * rho_bar), alpha = T(st.alpha);
-      const IterCtx<T, NX, NU, NG, ST> c{tb,   P,    T(st.sigma), rho_f, T(rho_bar), alpha, T(1) - alpha,
-                                         rho_f * alpha, kind, pc, xinit, T(0), gsel, ginv, i, w.row, w.N, gid, hard};
-      for (; k < nb; ++k) {
-        IterCtx<T, NX, NU, NG, ST> ck = c;
-        ck.yinit = ldo(P.yf, o_yinit);  // initial-state multipliers (slot N)
-        wave_iteration<T, NX, NU, NG, ST>(ck, lo);
-      }
-    }
+    k = run_segment<T, NX, NU, NG, ST>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
     const int check = (st.k_check > 0 && nb % st.k_check == 0) ? 1 : 0;
     const int adapt = (adapt_on && nb % st.k_rho == 0 && nb < st.max_iter) ? 1 : 0;
     const int last = (nb == st.max_iter) ? 1 : 0;
