@@ -271,27 +271,43 @@ struct LaneOff {
 
 // Stage blocks of a stage-parallel pass: blocks 0..nfull-1 hold four stages
 // t < N each (no masking); block nfull holds the rest (t = 4 nfull + q up to
-// N, rows past N idle).  Inputs of block b+1 are loaded while block b
-// computes, in two alternating buffers.
-template <typename In, typename Load, typename Comp>
-__device__ __forceinline__ void stage_blocks(int nfull, Load&& load, Comp&& comp) {
-  In a, b;
-  load(a, 0);
-  int blk = 0;
-  for (; blk + 2 <= nfull; blk += 2) {
-    load(b, blk + 1);
-    comp(a, blk, std::true_type{});
-    load(a, blk + 2);
-    comp(b, blk + 1, std::true_type{});
-  }
-  if (blk < nfull) {
-    load(b, blk + 1);
-    comp(a, blk, std::true_type{});
-    comp(b, blk + 1, std::false_type{});
-  } else {
-    comp(a, blk, std::false_type{});
-  }
+// N, rows past N idle).  Inputs are loaded D-1 blocks ahead into D rotating
+// buffers; the loop body is unrolled D times so that every buffer index is a
+// compile-time constant.  Loads run at most 4 (D - 1) + 3 stages past the
+// tail block's first stage (into padding or the next instance; unused).
+template <int D>
+constexpr int stage_blocks_reach() {
+  return 4 * (D - 1) + 3;
 }
+template <int D, typename In, typename Load, typename Comp>
+__device__ __forceinline__ void stage_blocks(int nfull, Load&& load, Comp&& comp) {
+  static_assert(stage_blocks_reach<D>() - 3 <= STAGE_PAD, "stage-block prefetch reaches past the padding");
+  In buf[D];
+  sfor<0, D - 1>([&](auto j) { load(buf[decltype(j)::value], decltype(j)::value); });
+  int blk = 0;
+  for (; blk + D <= nfull; blk += D) {
+    sfor<0, D>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      load(buf[(jj + D - 1) % D], blk + jj + D - 1);
+      comp(buf[jj], blk + jj, std::true_type{});
+    });
+  }
+  // fewer than D full blocks and the tail block remain
+  bool done = false;
+  sfor<0, D>([&](auto j) {
+    constexpr int jj = decltype(j)::value;
+    const int bb = blk + jj;
+    if (done) return;
+    if (bb + D - 1 <= nfull) load(buf[(jj + D - 1) % D], bb + D - 1);
+    if (bb < nfull) {
+      comp(buf[jj], bb, std::true_type{});
+    } else {
+      comp(buf[jj], bb, std::false_type{});
+      done = true;
+    }
+  });
+}
+constexpr int STAGE_BLOCK_DEPTH = 3;
 
 // pass-1 inputs of the stage on this row
 template <typename T, int NX, int NU, int NG, bool TI>
@@ -458,7 +474,7 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
       const T r = stage_r<FULL>(c, d, t, init);
       if (FULL || t <= N) sto(P.v, lo.v + blk * LO::VB, r);
     };
-    stage_blocks<In>(nfull, load, comp);
+    stage_blocks<STAGE_BLOCK_DEPTH, In>(nfull, load, comp);
   }
   wave_sync();
 
@@ -482,7 +498,7 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
       const T s = dotb<n>(d.Br, d.v, T(0));
       if (FULL || t <= N) sto(P.v, lo.v + blk * LO::VB, s);
     };
-    stage_blocks<In>(nfull, load, comp);
+    stage_blocks<STAGE_BLOCK_DEPTH, In>(nfull, load, comp);
   }
   wave_sync();
 
@@ -519,7 +535,7 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
       constexpr bool FULL = decltype(full)::value;
       stage_update<FULL>(c, d, 4 * blk + q, lo.v + blk * LO::VB);
     };
-    stage_blocks<In>(nfull, load, comp);
+    stage_blocks<STAGE_BLOCK_DEPTH, In>(nfull, load, comp);
   }
   // initial-state rows: y_init += rho_f alpha (x~_0 - x_init), slot N of y_f
   if (q == 0 && i < NX) {
