@@ -93,7 +93,254 @@ __device__ __forceinline__ void load_adj_blocks(AdjBlocks<NX, NU, NG>& d, const 
   load_row<n>(d.Gr, L.G + og + (size_t)ig * n, true);
 }
 
-template <typename T, int NX, int NU, int NG>
+// Time-invariant blocks the refinement sweeps multiply with (FP64), read
+// once: row / column `lane` of D (interior, and the terminal minus the
+// interior), E (if present), A^-, A^+ and G (the last two only without the
+// explicit-dynamics / selection structure).
+template <int NX, int NU, int NG, typename ST>
+struct AdjTI {
+  static constexpr int n = NX + NU;
+  double Dr[n], dDN[n];
+  double Er[n], Ec[n];
+  double Amc[NX], Amr[n];
+  double Apc[ST::APNEG ? 1 : NX], Apr[ST::APNEG ? 1 : n];
+  double Gc[ST::GSEL ? 1 : NG], Gr[ST::GSEL ? 1 : n];
+  __device__ void load(const Layout& L, int b, int i) {
+    const size_t nn = (size_t)n * n;
+    const int ic = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
+    const double* D = L.D + (size_t)(2 * b) * nn;
+    load_row<n>(Dr, D + (size_t)ic * n, true);
+    load_row<n>(dDN, D + nn + (size_t)ic * n, true);
+#pragma unroll
+    for (int k = 0; k < n; ++k) dDN[k] -= Dr[k];
+    if (L.E) {
+      load_row<n>(Er, L.E + (size_t)b * nn + (size_t)ic * n, true);
+      load_col<n>(Ec, L.E + (size_t)b * nn + ic, n, true);
+    } else {
+#pragma unroll
+      for (int k = 0; k < n; ++k) Er[k] = Ec[k] = 0.0;
+    }
+    const double* Am = L.Am + (size_t)b * NX * n;
+    load_col<NX>(Amc, Am + ic, n, true);
+    load_row<n>(Amr, Am + (size_t)ix * n, i < NX);
+    if constexpr (!ST::APNEG) {
+      const double* Ap = L.Ap + (size_t)b * NX * n;
+      load_col<NX>(Apc, Ap + ic, n, true);
+      load_row<n>(Apr, Ap + (size_t)ix * n, i < NX);
+    }
+    if constexpr (!ST::GSEL) {
+      const double* G = L.G + (size_t)b * NG * n;
+      load_col<NG>(Gc, G + ic, n, true);
+      load_row<n>(Gr, G + (size_t)ig * n, i < NG);
+    }
+  }
+};
+
+// pass-1 inputs of one stage of a sweep (time-invariant data)
+struct AdjIn1 {
+  double ec, em, en, efc, efr, wc, eg, dl;
+};
+// pass-5 inputs
+struct AdjIn5 {
+  double dx, dn, efn, rfn, wc, eg, rg, ef0, rf0, ex;
+};
+
+// Refinement sweeps for time-invariant data (the blocks of AdjTI), with the
+// explicit-dynamics and selection structure of ST.  Passes as in the general
+// sweep below; stage inputs are loaded two blocks ahead (stage_blocks).  The
+// unpadded FP64 scratch vectors are read at stages clamped to 0..N (the
+// clamped values are never used).
+template <int NX, int NU, int NG, typename ST>
+__device__ __forceinline__ void adjoint_sweeps_ti(const Layout& L, const AdjArgs& a, const WaveGroup& w, int bad) {
+  constexpr int n = NX + NU;
+  constexpr uint32_t VS = ROW * sizeof(double);
+  const int i = w.lane, q = w.row, N = w.N;
+  const int64_t s0 = w.s0;
+  const int ic = i < n ? i : n - 1;
+  const int nfull = N / 4;
+  const double rb = a.rho_b;
+  AdjTI<NX, NU, NG, ST> tb;
+  tb.load(L, w.b, i);
+  const bool hasE = L.E != nullptr;
+  const int gsel = L.gsel[i < NG ? i : 0], ginv = L.ginv[i];
+  const bool gid = __ballot(i < NG && gsel != i) == 0;
+  auto gather_t = [&](double u) { return gid ? u : row_gather(u, ginv < 0 ? 0 : ginv); };  // G' u (lane i)
+  auto gather = [&](double u) { return gid ? u : row_gather(u, gsel); };                    // G u (row i)
+  // instance bases (uniform) and lane offsets
+  const gptr<double> ex = as_global(a.ex) + s0 * ROW, ef = as_global(a.ef) + s0 * ROW;
+  const gptr<double> eg = as_global(a.eg) + s0 * ROW, rf = as_global(a.rf) + s0 * ROW;
+  const gptr<double> rg = as_global(a.rg) + s0 * ROW, wv = as_global(a.w) + s0 * ROW;
+  const gptr<const double> dL = as_global(a.dLdx) + s0 * n;
+  const gptr<double> Rb = as_global(a.v) + (s0 - STAGE_PAD) * ROW;
+  const int64_t nn = (int64_t)n * n;
+  const gptr<const double> Pb = as_global((const double*)a.P) + (s0 - STAGE_PAD) * nn;
+  const gptr<const double> Kb0 = as_global((const double*)a.K) + (s0 - STAGE_PAD) * nn;
+  const gptr<const double> Kbb0 = as_global((const double*)a.Kb) + (s0 - STAGE_PAD) * nn;
+  const uint32_t orow = (uint32_t)((STAGE_PAD * ROW + i) * (int)sizeof(double));
+  const uint32_t oblk = (uint32_t)((STAGE_PAD * (int)nn + ic * n) * (int)sizeof(double));
+  // offset of entry `lane` of stage t of the unpadded vectors, t clamped to 0..N
+  auto ov = [&](int t) { return (uint32_t)((min(max(t, 0), N) * ROW + i) * (int)sizeof(double)); };
+  // of the padded exchange buffer (no clamping needed within the padding)
+  auto oR = [&](int t) { return (uint32_t)(((STAGE_PAD + t) * ROW + i) * (int)sizeof(double)); };
+
+  for (int sweep = 0; sweep < a.sweeps && !bad; ++sweep) {
+    // pass 1: residual r - K e and the Schur right-hand side
+    //   rhs_t = r_x,t + rho_b (C' r_f)_t + G'(w .* r_g,t)
+    {
+      auto load = [&](AdjIn1& d, int blk) {
+        const int t = 4 * blk + q;
+        const uint32_t o = ov(t);
+        d.ec = ldo(ex, o);
+        d.em = ldo(ex, ov(t - 1));
+        d.en = ldo(ex, ov(t + 1));
+        d.efc = ldo(ef, ov(t + 1));  // dynamics row t
+        d.efr = ldo(ef, o);          // dynamics row t-1, or the initial-state rows at t = 0
+        d.wc = ldo(wv, o);
+        d.eg = ldo(eg, o);
+        d.dl = ldo(dL, (uint32_t)((min(t, N) * n + ic) * (int)sizeof(double)));
+      };
+      auto comp = [&](const AdjIn1& d, int blk, auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        const int t = 4 * blk + q;
+        const bool xr = i < NX, tlo = t > 0, thi = FULL || t < N;
+        const double ec = (i < n) ? d.ec : 0.0;
+        const double em = (tlo && i < n) ? d.em : 0.0;
+        const double en = (thi && i < n) ? d.en : 0.0;
+        // H e_x
+        double he = dotb<n>(tb.Dr, ec, 0.0);
+        if (!FULL && t == N) he = dotb<n>(tb.dDN, ec, he);
+        if (hasE) {
+          he = dotb<n>(tb.Er, em, he);
+          he = dotb<n>(tb.Ec, en, he);
+        }
+        // J' e_y
+        const double efc = (thi && xr) ? d.efc : 0.0;
+        const double efm = (tlo && xr) ? d.efr : 0.0;
+        double jte = dotb<NX>(tb.Amc, efc, 0.0);
+        if constexpr (ST::APNEG)
+          jte -= efm;
+        else
+          jte = dotb<NX>(tb.Apc, efm, jte);
+        jte += (t == 0 && xr) ? d.efr : 0.0;  // initial-state rows
+        const double wc = (i < NG) ? d.wc : 0.0;
+        const double egv = (i < NG && wc != 0.0) ? d.eg : 0.0;
+        if constexpr (ST::GSEL) {
+          const double gt = gather_t(egv);
+          jte += (ginv >= 0) ? gt : 0.0;
+        } else {
+          jte = dotb<NG>(tb.Gc, egv, jte);
+        }
+        const double rx = ((i < n) ? d.dl : 0.0) - (he + jte);
+        // equality-row residuals -J e_x of the rows touching stage t
+        double cx = dotb<n>(tb.Amr, ec, 0.0);
+        double cxm = dotb<n>(tb.Amr, em, 0.0);
+        if constexpr (ST::APNEG) {
+          cx -= en;
+          cxm -= ec;
+        } else {
+          cx = dotb<n>(tb.Apr, en, cx);
+          cxm = dotb<n>(tb.Apr, ec, cxm);
+        }
+        const double rfc = (thi && xr) ? -cx : 0.0;   // dynamics row t
+        const double rfm = (tlo && xr) ? -cxm : 0.0;  // dynamics row t-1
+        const double rf0 = (t == 0 && xr) ? -ec : 0.0;  // initial-state rows
+        double gx;
+        if constexpr (ST::GSEL)
+          gx = gather(ec);
+        else
+          gx = dotb<n>(tb.Gr, ec, 0.0);
+        const double rgc = (wc != 0.0) ? -gx : 0.0;
+        double tc = dotb<NX>(tb.Amc, rfc, 0.0);
+        if constexpr (ST::APNEG)
+          tc -= rfm;
+        else
+          tc = dotb<NX>(tb.Apc, rfm, tc);
+        tc += rf0;
+        double rhs = rx + rb * tc;
+        if constexpr (ST::GSEL) {
+          const double gt = gather_t(wc * rgc);
+          rhs += (ginv >= 0) ? gt : 0.0;
+        } else {
+          rhs = dotb<NG>(tb.Gc, wc * rgc, rhs);
+        }
+        if (FULL || t <= N) {
+          const uint32_t o = ov(t);
+          if (t == 0 && xr) sto(rf, o, rf0);
+          if (thi && xr) sto(rf, o + VS, rfc);
+          if (i < NG) sto(rg, o, rgc);
+          sto(Rb, oR(t), rhs);
+        }
+      };
+      stage_blocks<STAGE_BLOCK_DEPTH, AdjIn1>(nfull, load, comp);
+    }
+    wave_sync();
+    // passes 2-4: d_x = S^{-1} rhs
+    if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
+    wave_sync();
+    {
+      auto load = [&](TrIn<double, n>& d, int blk) {
+        const int t = 4 * blk + q;
+        ldo_n<n>(d.Br, Pb + (int64_t)(STAGE_PAD + t) * nn, (uint32_t)(ic * n * (int)sizeof(double)));
+        d.v = ldo(Rb, oR(t));
+      };
+      auto comp = [&](const TrIn<double, n>& d, int blk, auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        const int t = 4 * blk + q;
+        const double r = dotb<n>(d.Br, d.v, 0.0);
+        if (FULL || t <= N) sto(Rb, oR(t), r);
+      };
+      stage_blocks<STAGE_BLOCK_DEPTH, TrIn<double, n>>(nfull, load, comp);
+    }
+    wave_sync();
+    if (q == 0) chain<double, n, -1>(Rb, Kbb0, orow, oblk, N);
+    wave_sync();
+    // pass 5: d_y = rho_b (J d_x - r_y), e += d
+    {
+      auto load = [&](AdjIn5& d, int blk) {
+        const int t = 4 * blk + q;
+        const uint32_t o = ov(t);
+        d.dx = ldo(Rb, oR(t));
+        d.dn = ldo(Rb, oR(t + 1));
+        d.efn = ldo(ef, ov(t + 1));
+        d.rfn = ldo(rf, ov(t + 1));
+        d.wc = ldo(wv, o);
+        d.eg = ldo(eg, o);
+        d.rg = ldo(rg, o);
+        d.ef0 = ldo(ef, o);
+        d.rf0 = ldo(rf, o);
+        d.ex = ldo(ex, o);
+      };
+      auto comp = [&](const AdjIn5& d, int blk, auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        const int t = 4 * blk + q;
+        const bool xr = i < NX, thi = FULL || t < N;
+        const double dx = d.dx;
+        const double dn = thi ? d.dn : 0.0;
+        double jd = dotb<n>(tb.Amr, dx, 0.0);
+        if constexpr (ST::APNEG)
+          jd -= dn;
+        else
+          jd = dotb<n>(tb.Apr, dn, jd);
+        double gd;
+        if constexpr (ST::GSEL)
+          gd = gather(dx);
+        else
+          gd = dotb<n>(tb.Gr, dx, 0.0);
+        if (FULL || t <= N) {
+          const uint32_t o = ov(t);
+          if (thi && xr) sto(ef, o + VS, d.efn + rb * (jd - d.rfn));
+          if (i < NG && d.wc != 0.0) sto(eg, o, d.eg + rb * (gd - d.rg));
+          if (t == 0 && xr) sto(ef, o, d.ef0 + rb * (dx - d.rf0));
+          if (i < n) sto(ex, o, d.ex + dx);
+        }
+      };
+      stage_blocks<STAGE_BLOCK_DEPTH, AdjIn5>(nfull, load, comp);
+    }
+    wave_sync();
+  }
+}
+
+template <typename T, int NX, int NU, int NG, typename ST>
 __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   constexpr int n = NX + NU;
   WaveGroup w;
@@ -171,89 +418,93 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   const gptr<const double> Kbb0 = as_global((const double*)a.Kb) + sp * (int64_t)nn;
   const uint32_t orow = (uint32_t)((STAGE_PAD * ROW + i) * (int)sizeof(double));
   const uint32_t oblk = (uint32_t)((STAGE_PAD * (int)nn + (i < n ? i : n - 1) * n) * (int)sizeof(double));
-  for (int sweep = 0; sweep < a.sweeps && !bad; ++sweep) {
-    // pass 1: residual r - K e and the Schur right-hand side
-    //   rhs_t = r_x,t + rho_b (C' r_f)_t + G_t'(w .* r_g,t)
-    for (int blk = 0; blk < nbl; ++blk) {
-      const int t = 4 * blk + q;
-      if (t > N) break;
-      const int64_t s = s0 + t;
-      const size_t sv = (size_t)s * ROW + i;
-      AdjBlocks<NX, NU, NG> B;
-      load_adj_blocks(B, L, b, s0, t, N, i);
-      const double ec = (i < n) ? ex[sv] : 0.0;
-      const double em = (t > 0 && i < n) ? ex[sv - ROW] : 0.0;
-      const double en = (t < N && i < n) ? ex[sv + ROW] : 0.0;
-      // H e_x
-      double he = dotb<n>(B.Dr, ec, 0.0);
-      he = dotb<n>(B.Er, em, he);
-      he = dotb<n>(B.Ec, en, he);
-      // J' e_y
-      const double efc = (t < N && i < NX) ? ef[sv + ROW] : 0.0;  // dynamics row t
-      const double efm = (t > 0 && i < NX) ? ef[sv] : 0.0;        // dynamics row t-1
-      double jte = dotb<NX>(B.Amc, efc, 0.0);
-      jte = dotb<NX>(B.Apcm, efm, jte);
-      if (t == 0 && i < NX) jte += ef[sv];  // initial-state rows
-      const double wc = (i < NG) ? wv[sv] : 0.0;
-      const double egv = (i < NG && wc != 0.0) ? eg[sv] : 0.0;
-      jte = dotb<NG>(B.Gc, egv, jte);
-      const double rx = ((i < n) ? a.dLdx[(size_t)s * n + i] : 0.0) - (he + jte);
-      // equality-row residuals -J e_x of the rows touching stage t
-      double cx = dotb<n>(B.Amr, ec, 0.0);
-      cx = dotb<n>(B.Apr, en, cx);
-      const double rfc = (t < N && i < NX) ? -cx : 0.0;  // dynamics row t
-      double cxm = dotb<n>(B.Amrm, em, 0.0);
-      cxm = dotb<n>(B.Aprm, ec, cxm);
-      const double rfm = (t > 0 && i < NX) ? -cxm : 0.0;  // dynamics row t-1
-      const double rf0 = (t == 0 && i < NX) ? -ec : 0.0;  // initial-state rows
-      const double gx = dotb<n>(B.Gr, ec, 0.0);
-      const double rgc = (wc != 0.0) ? -gx : 0.0;
-      double tc = dotb<NX>(B.Amc, rfc, 0.0);
-      tc = dotb<NX>(B.Apcm, rfm, tc);
-      tc += rf0;
-      double rhs = rx + rb * tc;
-      rhs = dotb<NG>(B.Gc, wc * rgc, rhs);
-      if (t == 0 && i < NX) rf[sv] = rf0;
-      if (t < N && i < NX) rf[sv + ROW] = rfc;
-      if (i < NG) rg[sv] = rgc;
-      R[(size_t)t * ROW] = rhs;
+  if constexpr (ST::TI) {
+    adjoint_sweeps_ti<NX, NU, NG, ST>(L, a, w, bad);
+  } else {
+    for (int sweep = 0; sweep < a.sweeps && !bad; ++sweep) {
+      // pass 1: residual r - K e and the Schur right-hand side
+      //   rhs_t = r_x,t + rho_b (C' r_f)_t + G_t'(w .* r_g,t)
+      for (int blk = 0; blk < nbl; ++blk) {
+        const int t = 4 * blk + q;
+        if (t > N) break;
+        const int64_t s = s0 + t;
+        const size_t sv = (size_t)s * ROW + i;
+        AdjBlocks<NX, NU, NG> B;
+        load_adj_blocks(B, L, b, s0, t, N, i);
+        const double ec = (i < n) ? ex[sv] : 0.0;
+        const double em = (t > 0 && i < n) ? ex[sv - ROW] : 0.0;
+        const double en = (t < N && i < n) ? ex[sv + ROW] : 0.0;
+        // H e_x
+        double he = dotb<n>(B.Dr, ec, 0.0);
+        he = dotb<n>(B.Er, em, he);
+        he = dotb<n>(B.Ec, en, he);
+        // J' e_y
+        const double efc = (t < N && i < NX) ? ef[sv + ROW] : 0.0;  // dynamics row t
+        const double efm = (t > 0 && i < NX) ? ef[sv] : 0.0;        // dynamics row t-1
+        double jte = dotb<NX>(B.Amc, efc, 0.0);
+        jte = dotb<NX>(B.Apcm, efm, jte);
+        if (t == 0 && i < NX) jte += ef[sv];  // initial-state rows
+        const double wc = (i < NG) ? wv[sv] : 0.0;
+        const double egv = (i < NG && wc != 0.0) ? eg[sv] : 0.0;
+        jte = dotb<NG>(B.Gc, egv, jte);
+        const double rx = ((i < n) ? a.dLdx[(size_t)s * n + i] : 0.0) - (he + jte);
+        // equality-row residuals -J e_x of the rows touching stage t
+        double cx = dotb<n>(B.Amr, ec, 0.0);
+        cx = dotb<n>(B.Apr, en, cx);
+        const double rfc = (t < N && i < NX) ? -cx : 0.0;  // dynamics row t
+        double cxm = dotb<n>(B.Amrm, em, 0.0);
+        cxm = dotb<n>(B.Aprm, ec, cxm);
+        const double rfm = (t > 0 && i < NX) ? -cxm : 0.0;  // dynamics row t-1
+        const double rf0 = (t == 0 && i < NX) ? -ec : 0.0;  // initial-state rows
+        const double gx = dotb<n>(B.Gr, ec, 0.0);
+        const double rgc = (wc != 0.0) ? -gx : 0.0;
+        double tc = dotb<NX>(B.Amc, rfc, 0.0);
+        tc = dotb<NX>(B.Apcm, rfm, tc);
+        tc += rf0;
+        double rhs = rx + rb * tc;
+        rhs = dotb<NG>(B.Gc, wc * rgc, rhs);
+        if (t == 0 && i < NX) rf[sv] = rf0;
+        if (t < N && i < NX) rf[sv + ROW] = rfc;
+        if (i < NG) rg[sv] = rgc;
+        R[(size_t)t * ROW] = rhs;
+      }
+      wave_sync();
+      // passes 2-4: d_x = S^{-1} rhs
+      if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
+      wave_sync();
+      for (int blk = 0; blk < nbl; ++blk) {
+        const int t = 4 * blk + q;
+        if (t > N) break;
+        double Prow[n];
+        load_row<n>(Prow, Pr + (size_t)t * nn, true);
+        R[(size_t)t * ROW] = dotb<n>(Prow, R[(size_t)t * ROW], 0.0);
+      }
+      wave_sync();
+      if (q == 0) chain<double, n, -1>(Rb, Kbb0, orow, oblk, N);
+      wave_sync();
+      // pass 5: d_y = rho_b (J d_x - r_y), e += d
+      for (int blk = 0; blk < nbl; ++blk) {
+        const int t = 4 * blk + q;
+        if (t > N) break;
+        const int64_t s = s0 + t;
+        const size_t sv = (size_t)s * ROW + i;
+        const double dx = R[(size_t)t * ROW];
+        const double dn = (t < N) ? R[(size_t)(t + 1) * ROW] : 0.0;
+        const size_t oa = ti_or_tv(L.ti, b, s, (size_t)NX * n);
+        double Amr[n], Apr[n], Gr[n];
+        load_row<n>(Amr, L.Am + oa + (size_t)(i < NX ? i : NX - 1) * n, t < N);
+        load_row<n>(Apr, L.Ap + oa + (size_t)(i < NX ? i : NX - 1) * n, t < N);
+        load_row<n>(Gr, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (size_t)(i < NG ? i : NG - 1) * n, true);
+        double jd = dotb<n>(Amr, dx, 0.0);
+        jd = dotb<n>(Apr, dn, jd);
+        if (t < N && i < NX) ef[sv + ROW] += rb * (jd - rf[sv + ROW]);
+        const double gd = dotb<n>(Gr, dx, 0.0);
+        if (i < NG && wv[sv] != 0.0) eg[sv] += rb * (gd - rg[sv]);
+        if (t == 0 && i < NX) ef[sv] += rb * (dx - rf[sv]);
+        if (i < n) ex[sv] += dx;
+      }
+      wave_sync();
     }
-    wave_sync();
-    // passes 2-4: d_x = S^{-1} rhs
-    if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
-    wave_sync();
-    for (int blk = 0; blk < nbl; ++blk) {
-      const int t = 4 * blk + q;
-      if (t > N) break;
-      double Prow[n];
-      load_row<n>(Prow, Pr + (size_t)t * nn, true);
-      R[(size_t)t * ROW] = dotb<n>(Prow, R[(size_t)t * ROW], 0.0);
-    }
-    wave_sync();
-    if (q == 0) chain<double, n, -1>(Rb, Kbb0, orow, oblk, N);
-    wave_sync();
-    // pass 5: d_y = rho_b (J d_x - r_y), e += d
-    for (int blk = 0; blk < nbl; ++blk) {
-      const int t = 4 * blk + q;
-      if (t > N) break;
-      const int64_t s = s0 + t;
-      const size_t sv = (size_t)s * ROW + i;
-      const double dx = R[(size_t)t * ROW];
-      const double dn = (t < N) ? R[(size_t)(t + 1) * ROW] : 0.0;
-      const size_t oa = ti_or_tv(L.ti, b, s, (size_t)NX * n);
-      double Amr[n], Apr[n], Gr[n];
-      load_row<n>(Amr, L.Am + oa + (size_t)(i < NX ? i : NX - 1) * n, t < N);
-      load_row<n>(Apr, L.Ap + oa + (size_t)(i < NX ? i : NX - 1) * n, t < N);
-      load_row<n>(Gr, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (size_t)(i < NG ? i : NG - 1) * n, true);
-      double jd = dotb<n>(Amr, dx, 0.0);
-      jd = dotb<n>(Apr, dn, jd);
-      if (t < N && i < NX) ef[sv + ROW] += rb * (jd - rf[sv + ROW]);
-      const double gd = dotb<n>(Gr, dx, 0.0);
-      if (i < NG && wv[sv] != 0.0) eg[sv] += rb * (gd - rg[sv]);
-      if (t == 0 && i < NX) ef[sv] += rb * (dx - rf[sv]);
-      if (i < n) ex[sv] += dx;
-    }
-    wave_sync();
   }
 
   // ---- 3. VJP outputs ----

@@ -221,6 +221,38 @@ struct Group {
   int N;       // horizon (stages 0..N)
 };
 
+// Wave-uniform copies of values that reach a non-inlined function in vector
+// registers or through memory (every lane holds the same value): with them
+// the callee keeps its base pointers and loop bounds in scalar registers and
+// addresses memory as scalar base + vector offset.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+}
+__device__ __forceinline__ double uni(double v) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, v))); }
+template <typename P>
+__device__ __forceinline__ P* uni(P* p) {
+  return (P*)uni((int64_t)p);
+}
+__device__ __forceinline__ Layout uni(const Layout& L) {
+  Layout u = L;
+  u.B = uni(L.B), u.nx = uni(L.nx), u.nu = uni(L.nu), u.ng = uni(L.ng), u.n = uni(L.n), u.ti = uni(L.ti);
+  u.stage_off = uni(L.stage_off), u.order = uni(L.order);
+  u.D = uni(L.D), u.E = uni(L.E), u.q = uni(L.q), u.Am = uni(L.Am), u.Ap = uni(L.Ap), u.bd = uni(L.bd);
+  u.G = uni(L.G), u.lo = uni(L.lo), u.hi = uni(L.hi), u.x_init = uni(L.x_init), u.soft = uni(L.soft);
+  u.gamma2 = uni(L.gamma2), u.gamma1 = uni(L.gamma1);
+  u.AmT = uni(L.AmT), u.ApT = uni(L.ApT), u.GT = uni(L.GT), u.qT = uni(L.qT), u.bdT = uni(L.bdT);
+  u.loT = uni(L.loT), u.hiT = uni(L.hiT), u.xinitT = uni(L.xinitT);
+  u.Linv64 = uni(L.Linv64), u.M64 = uni(L.M64);
+  u.SubA = uni(L.SubA), u.SubB = uni(L.SubB), u.ChF = uni(L.ChF), u.ChB = uni(L.ChB);
+  u.x = uni(L.x), u.v = uni(L.v), u.yf = uni(L.yf), u.zg = uni(L.zg), u.yg = uni(L.yg), u.xi = uni(L.xi);
+  u.rho = uni(L.rho), u.status = uni(L.status), u.iters = uni(L.iters), u.nfact = uni(L.nfact);
+  u.rprim = uni(L.rprim), u.rdual = uni(L.rdual);
+  return u;
+}
+
 __device__ __forceinline__ size_t ti_or_tv(int ti, int b, int64_t s, size_t sz) {
   return ti ? (size_t)b * sz : (size_t)s * sz;
 }

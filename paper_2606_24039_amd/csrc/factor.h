@@ -105,8 +105,12 @@ enum { FACTOR_M = 0, FACTOR_WV = 1, FACTOR_PK = 2 };
 // occupancy targets (the register budget of a called function follows its
 // callers).
 template <typename T, int NX, int NU, int NG, bool HOIST, int FORM = FACTOR_M, int TAG = 0>
-__device__ __noinline__ int factor_instance(const Layout& L, const Group& g, double sigma, double rho_f, double rho_g,
-                                            const double* __restrict__ rhog_rows, int qrow = 0) {
+__device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, double sigma_, double rho_f_,
+                                            double rho_g_, const double* __restrict__ rhog_rows_, int qrow = 0) {
+  const Layout L = uni(Lm);
+  const Group g{gm.lane, uni(gm.b), uni(gm.s0), uni(gm.N)};
+  const double sigma = uni(sigma_), rho_f = uni(rho_f_), rho_g = uni(rho_g_);
+  const double* __restrict__ rhog_rows = uni(rhog_rows_);
   constexpr bool WV = FORM == FACTOR_WV;
   constexpr bool PK = FORM == FACTOR_PK;
   constexpr int n = NX + NU;

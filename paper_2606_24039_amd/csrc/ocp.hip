@@ -100,10 +100,10 @@ void launch_solve(const Layout& L, const Settings& s, int32_t* need, hipStream_t
 }
 
 // one instance per wavefront
-template <typename T, int NX, int NU, int NG>
+template <typename T, int NX, int NU, int NG, typename ST>
 void launch_adjoint(const Layout& L, const AdjArgs& a, hipStream_t st, Prof* pf) {
   timed(pf, OCP_K_ADJOINT, st,
-        [&] { hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG>), dim3(L.B), dim3(64), 0, st, L, a); });
+        [&] { hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, a); });
 }
 
 // structure variants of the iteration kernel
@@ -116,8 +116,8 @@ struct Entry {
   int nx, nu, ng;
   SolveFn f64[3];  // [variant]
   SolveFn f32[3];
-  AdjFn adj64;
-  AdjFn adj32;
+  AdjFn adj64[3];  // [variant]
+  AdjFn adj32[3];
 };
 
 #define OCP_ENTRY(NX, NU, NG)                                                                       \
@@ -127,7 +127,10 @@ struct Entry {
          launch_solve<double, NX, NU, NG, StBox>},                                                  \
         {launch_solve<float, NX, NU, NG, StTV>, launch_solve<float, NX, NU, NG, StTI>,              \
          launch_solve<float, NX, NU, NG, StBox>},                                                   \
-        launch_adjoint<double, NX, NU, NG>, launch_adjoint<float, NX, NU, NG>,                       \
+        {launch_adjoint<double, NX, NU, NG, StTV>, launch_adjoint<double, NX, NU, NG, StTI>,        \
+         launch_adjoint<double, NX, NU, NG, StBox>},                                                \
+        {launch_adjoint<float, NX, NU, NG, StTV>, launch_adjoint<float, NX, NU, NG, StTI>,          \
+         launch_adjoint<float, NX, NU, NG, StBox>},                                                 \
   }
 
 const Entry kTable[] = {
@@ -883,10 +886,11 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   a.eta_x = out->eta_x;
   a.active = out->active;
   const Layout L = make_layout(h);
+  const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (h->ti ? VAR_TI : VAR_TV);
   if (h->mixed)
-    h->entry->adj32(L, a, st, &h->prof);
+    h->entry->adj32[var](L, a, st, &h->prof);
   else
-    h->entry->adj64(L, a, st, &h->prof);
+    h->entry->adj64[var](L, a, st, &h->prof);
   return hip_ok(hipGetLastError());
 }
 

@@ -563,9 +563,13 @@ __device__ __forceinline__ T rows_max(T v) {
 // on row t mod 4); every row reads the neighbouring stages it needs directly.
 // TI: the blocks are the same at every stage and are read once.
 template <typename T, int NX, int NU, int NG, bool TI, int TAG = 0>
-__device__ __noinline__ Resid residuals_wave(const Layout& L, const WaveGroup& w, int kind, double gamma2,
-                                             double gamma1) {
+__device__ __noinline__ Resid residuals_wave(const Layout& Lm, const WaveGroup& wm, int kind, double gamma2_,
+                                             double gamma1_) {
   constexpr int n = NX + NU;
+  const Layout L = uni(Lm);
+  WaveGroup w = wm;
+  w.b = uni(wm.b), w.s0 = uni(wm.s0), w.N = uni(wm.N);
+  const double gamma2 = uni(gamma2_), gamma1 = uni(gamma1_);
   const int i = w.lane, q = w.row, b = w.b, N = w.N;
   const int ic = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
   const size_t nn = (size_t)n * n;
@@ -724,46 +728,6 @@ __device__ __forceinline__ int boundary_decision(const Resid& R, const Settings&
     }
   }
   return ST_RUNNING;
-}
-
-// wave-uniform copies of values that reach a non-inlined function in vector
-// registers (every lane holds the same value)
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int64_t uni(int64_t v) {
-  const uint64_t u = (uint64_t)v;
-  return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
-                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
-}
-__device__ __forceinline__ double uni(double v) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, v))); }
-template <typename P>
-__device__ __forceinline__ P* uni(P* p) {
-  return (P*)uni((int64_t)p);
-}
-__device__ __forceinline__ Layout uni(const Layout& L) {
-  Layout u = L;
-  u.stage_off = uni(L.stage_off);
-  u.SubA = uni(L.SubA);
-  u.SubB = uni(L.SubB);
-  u.ChF = uni(L.ChF);
-  u.ChB = uni(L.ChB);
-  u.x = uni(L.x);
-  u.v = uni(L.v);
-  u.yf = uni(L.yf);
-  u.zg = uni(L.zg);
-  u.yg = uni(L.yg);
-  u.xi = uni(L.xi);
-  u.AmT = uni(L.AmT);
-  u.ApT = uni(L.ApT);
-  u.GT = uni(L.GT);
-  u.loT = uni(L.loT);
-  u.hiT = uni(L.hiT);
-  u.bdT = uni(L.bdT);
-  u.qT = uni(L.qT);
-  u.xinitT = uni(L.xinitT);
-  u.ti = uni(L.ti);
-  u.gamma1 = uni(L.gamma1);
-  u.gamma2 = uni(L.gamma2);
-  return u;
 }
 
 // ADMM iterations k0 .. nb-1 of one instance at a fixed rho (a segment of the
