@@ -72,6 +72,49 @@ struct TIBlocks {
   }
 };
 
+// Time-invariant blocks in FP64 (FP64 residuals, adjoint sweeps), read once:
+// row / column `lane` of D (interior, and the terminal minus the interior),
+// E (zero if absent), A^-, A^+ and G (the last two only without the
+// explicit-dynamics / selection structure).
+template <int NX, int NU, int NG, typename ST>
+struct TIBlocks64 {
+  static constexpr int n = NX + NU;
+  double Dr[n], dDN[n];
+  double Er[n], Ec[n];
+  double Amc[NX], Amr[n];
+  double Apc[ST::APNEG ? 1 : NX], Apr[ST::APNEG ? 1 : n];
+  double Gc[ST::GSEL ? 1 : NG], Gr[ST::GSEL ? 1 : n];
+  __device__ void load(const Layout& L, int b, int i) {
+    const size_t nn = (size_t)n * n;
+    const int ic = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
+    const double* D = L.D + (size_t)(2 * b) * nn;
+    load_row<n>(Dr, D + (size_t)ic * n, true);
+    load_row<n>(dDN, D + nn + (size_t)ic * n, true);
+#pragma unroll
+    for (int k = 0; k < n; ++k) dDN[k] -= Dr[k];
+    if (L.E) {
+      load_row<n>(Er, L.E + (size_t)b * nn + (size_t)ic * n, true);
+      load_col<n>(Ec, L.E + (size_t)b * nn + ic, n, true);
+    } else {
+#pragma unroll
+      for (int k = 0; k < n; ++k) Er[k] = Ec[k] = 0.0;
+    }
+    const double* Am = L.Am + (size_t)b * NX * n;
+    load_col<NX>(Amc, Am + ic, n, true);
+    load_row<n>(Amr, Am + (size_t)ix * n, i < NX);
+    if constexpr (!ST::APNEG) {
+      const double* Ap = L.Ap + (size_t)b * NX * n;
+      load_col<NX>(Apc, Ap + ic, n, true);
+      load_row<n>(Apr, Ap + (size_t)ix * n, i < NX);
+    }
+    if constexpr (!ST::GSEL) {
+      const double* G = L.G + (size_t)b * NG * n;
+      load_col<NG>(Gc, G + ic, n, true);
+      load_row<n>(Gr, G + (size_t)ig * n, i < NG);
+    }
+  }
+};
+
 // prefetch distance (stages) of the substitution chains: deeper for FP32
 // (a chain stage holds one n-row of a chain block plus one vector entry)
 template <typename T, int n>

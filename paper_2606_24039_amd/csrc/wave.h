@@ -561,15 +561,11 @@ __device__ __forceinline__ T rows_max(T v) {
 // FP64 residuals of eq. admm:residuals and the scales of eq.
 // admm:termination:slack with the stages spread over the four rows (stage t
 // on row t mod 4); every row reads the neighbouring stages it needs directly.
-// TI: the blocks are the same at every stage and are read once.
-template <typename T, int NX, int NU, int NG, bool TI, int TAG = 0>
-__device__ __noinline__ Resid residuals_wave(const Layout& Lm, const WaveGroup& wm, int kind, double gamma2_,
-                                             double gamma1_) {
+// General form: the blocks of every stage are read where they are used.
+template <typename T, int NX, int NU, int NG, bool TI>
+__device__ __forceinline__ Resid residuals_gen(const Layout& L, const WaveGroup& w, int kind, double gamma2,
+                                               double gamma1) {
   constexpr int n = NX + NU;
-  const Layout L = uni(Lm);
-  WaveGroup w = wm;
-  w.b = uni(wm.b), w.s0 = uni(wm.s0), w.N = uni(wm.N);
-  const double gamma2 = uni(gamma2_), gamma1 = uni(gamma1_);
   const int i = w.lane, q = w.row, b = w.b, N = w.N;
   const int ic = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
   const size_t nn = (size_t)n * n;
@@ -708,6 +704,157 @@ __device__ __noinline__ Resid residuals_wave(const Layout& Lm, const WaveGroup& 
   return R;
 }
 
+// per-stage inputs of the residual evaluation (time-invariant data)
+template <typename T>
+struct ResIn {
+  T xc, xm, xn, yfc, yfm, yg, zg, xi;
+  double q;
+};
+
+// The same residuals for time-invariant data: blocks read once (FP64), the
+// explicit-dynamics and selection structure of ST used, stage inputs loaded
+// two blocks ahead.
+template <typename T, int NX, int NU, int NG, typename ST>
+__device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& w, int kind, double gamma2,
+                                              double gamma1) {
+  constexpr int n = NX + NU;
+  constexpr int VS = ROW * (int)sizeof(T);
+  const int i = w.lane, q = w.row, b = w.b, N = w.N;
+  const int ic = i < n ? i : n - 1, ix = i < NX ? i : NX - 1;
+  const int64_t sp = w.s0 - STAGE_PAD;
+  TIBlocks64<NX, NU, NG, ST> tb;
+  tb.load(L, b, i);
+  const bool hasE = L.E != nullptr;
+  const gptr<const T> X = as_global((const T*)L.x + sp * ROW), YF = as_global((const T*)L.yf + sp * ROW);
+  const gptr<const T> ZG = as_global((const T*)L.zg + sp * ROW), YG = as_global((const T*)L.yg + sp * ROW);
+  const gptr<const T> XI = as_global((const T*)L.xi + sp * ROW);
+  const gptr<const double> Q = L.q ? as_global(L.q + w.s0 * n) : nullptr;
+  const double cv = L.bd ? L.bd[(size_t)b * NX + ix] : 0.0;
+  const double xi0 = L.x_init[(size_t)b * NX + ix];
+  const double yinit = double(ldo(YF, (uint32_t)(((STAGE_PAD + N) * ROW + i) * (int)sizeof(T))));
+  const int gsel = L.gsel[i < NG ? i : 0], ginv = L.ginv[i];
+  const bool gid = __ballot(i < NG && gsel != i) == 0;
+  double m_cxc = 0, m_cx = 0, m_c = 0, m_gxz = 0, m_gx = 0, m_z = 0;
+  double m_dual = 0, m_px = 0, m_aty = 0, m_q = 0, m_sres = 0, m_sscale = 0;
+  int nf = 0;
+  auto upd = [&](double& m, double v) {
+    if (!isfinite(v)) nf = 1;
+    m = fmax(m, fabs(v));
+  };
+  auto load = [&](ResIn<T>& d, int blk) {
+    const int t = 4 * blk + q;
+    const uint32_t o = (uint32_t)(((STAGE_PAD + t) * ROW + i) * (int)sizeof(T));
+    d.xc = ldo(X, o);
+    d.xm = ldo<-VS>(X, o);
+    d.xn = ldo<VS>(X, o);
+    d.yfc = ldo(YF, o);
+    d.yfm = ldo<-VS>(YF, o);
+    d.yg = ldo(YG, o);
+    d.zg = ldo(ZG, o);
+    d.xi = ldo(XI, o);
+    d.q = Q ? ldo(Q, (uint32_t)((min(t, N) * n + ic) * (int)sizeof(double))) : 0.0;
+  };
+  auto comp = [&](const ResIn<T>& d, int blk, auto full) {
+    constexpr bool FULL = decltype(full)::value;
+    const int t = 4 * blk + q;
+    if (!FULL && t > N) return;
+    const bool thi = FULL || t < N, xr = i < NX;
+    const double xc = double(d.xc);
+    const double xm = (t > 0) ? double(d.xm) : 0.0;
+    const double xn = thi ? double(d.xn) : 0.0;
+    const double yfc = (thi && xr) ? double(d.yfc) : 0.0;
+    const double yfm = (t > 0 && xr) ? double(d.yfm) : 0.0;
+    // (P x)_t row i = D_t x_t + E_{t-1} x_{t-1} + E_t' x_{t+1}
+    double px = dotb<n>(tb.Dr, xc, 0.0);
+    if (!FULL && t == N) px = dotb<n>(tb.dDN, xc, px);
+    if (hasE) {
+      px = dotb<n>(tb.Er, xm, px);
+      px = dotb<n>(tb.Ec, xn, px);
+    }
+    // (A' y)_t row i
+    double aty = dotb<NX>(tb.Amc, yfc, 0.0);
+    if constexpr (ST::APNEG)
+      aty -= yfm;
+    else
+      aty = dotb<NX>(tb.Apc, yfm, aty);
+    if (t == 0 && xr) aty += yinit;
+    const double ygv = (i < NG) ? double(d.yg) : 0.0;
+    if constexpr (ST::GSEL) {
+      const double gt = gid ? ygv : row_gather(ygv, ginv < 0 ? 0 : ginv);
+      aty += (ginv >= 0) ? gt : 0.0;
+    } else {
+      aty = dotb<NG>(tb.Gc, ygv, aty);
+    }
+    const double qv = (i < n) ? d.q : 0.0;
+    if (i < n) {
+      upd(m_dual, px + qv + aty);
+      upd(m_px, px);
+      upd(m_aty, aty);
+      upd(m_q, qv);
+    }
+    // equality rows touching stage t
+    if (t == 0 && xr) {
+      upd(m_cxc, xc - xi0);
+      upd(m_cx, xc);
+      upd(m_c, xi0);
+    }
+    double cx = dotb<n>(tb.Amr, xc, 0.0);
+    if constexpr (ST::APNEG)
+      cx -= xn;
+    else
+      cx = dotb<n>(tb.Apr, xn, cx);
+    if (thi && xr) {
+      upd(m_cxc, cx - cv);
+      upd(m_cx, cx);
+      upd(m_c, cv);
+    }
+    // inequality rows of stage t
+    double gx;
+    if constexpr (ST::GSEL)
+      gx = gid ? xc : row_gather(xc, gsel);
+    else
+      gx = dotb<n>(tb.Gr, xc, 0.0);
+    if (i < NG) {
+      const double zv = double(d.zg);
+      upd(m_gxz, gx - zv);
+      upd(m_gx, gx);
+      upd(m_z, zv);
+      const double xiv = double(d.xi);
+      if (kind == 1) {
+        upd(m_sres, gamma2 * xiv + ygv);
+        upd(m_sscale, gamma2 * xiv);
+        upd(m_sscale, ygv);
+      } else if (kind == 2) {
+        const double r1 = (xiv != 0.0) ? fabs(ygv + gamma1 * (xiv > 0 ? 1.0 : -1.0)) : fmax(fabs(ygv) - gamma1, 0.0);
+        upd(m_sres, r1);
+        upd(m_sscale, xiv != 0.0 ? gamma1 : 0.0);
+        upd(m_sscale, ygv);
+      }
+    }
+  };
+  stage_blocks<STAGE_BLOCK_DEPTH, ResIn<T>>(N / 4, load, comp);
+  Resid R;
+  R.rp = rows_max(row_max(fmax(m_cxc, m_gxz)));
+  R.ps = rows_max(row_max(fmax(fmax(m_cx, m_gx), fmax(m_c, m_z))));
+  R.rd = rows_max(row_max(fmax(m_dual, m_sres)));
+  R.ds = rows_max(row_max(fmax(fmax(m_px, m_aty), fmax(m_q, m_sscale))));
+  R.nonfinite = rows_max(row_max(nf));
+  return R;
+}
+
+template <typename T, int NX, int NU, int NG, typename ST, int TAG = 0>
+__device__ __noinline__ Resid residuals_wave(const Layout& Lm, const WaveGroup& wm, int kind, double gamma2_,
+                                             double gamma1_) {
+  const Layout L = uni(Lm);
+  WaveGroup w = wm;
+  w.b = uni(wm.b), w.s0 = uni(wm.s0), w.N = uni(wm.N);
+  const double gamma2 = uni(gamma2_), gamma1 = uni(gamma1_);
+  if constexpr (ST::TI)
+    return residuals_ti<T, NX, NU, NG, ST>(L, w, kind, gamma2, gamma1);
+  else
+    return residuals_gen<T, NX, NU, NG, false>(L, w, kind, gamma2, gamma1);
+}
+
 // Boundary decision of the schedule (eq. admm:termination:slack, rho:update):
 // returns the new status (ST_RUNNING to continue) and may change rho_bar.
 __device__ __forceinline__ int boundary_decision(const Resid& R, const Settings& st, int check, int adapt, int last,
@@ -811,7 +958,7 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
     const int adapt = (adapt_on && nb % st.k_rho == 0 && nb < st.max_iter) ? 1 : 0;
     const int last = (nb == st.max_iter) ? 1 : 0;
     if (check || adapt || last) {
-      R = residuals_wave<T, NX, NU, NG, ST::TI>(Lc, w, kind, L.gamma2, L.gamma1);
+      R = residuals_wave<T, NX, NU, NG, ST>(Lc, w, kind, L.gamma2, L.gamma1);
       status = boundary_decision(R, st, check, adapt, last, rho_bar, need);
       if (status != ST_RUNNING) break;
     }
