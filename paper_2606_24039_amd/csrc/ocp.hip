@@ -168,6 +168,7 @@ struct ocp_handle_s {
   void *loT = nullptr, *hiT = nullptr, *xinitT = nullptr;
   double *Linv64 = nullptr, *M64 = nullptr;
   void *SubA = nullptr, *SubB = nullptr, *ChF = nullptr, *ChB = nullptr;
+  void *SegT = nullptr, *SegU = nullptr, *SegX = nullptr;
   int variant = 0;
   int8_t gsel[16] = {0}, ginv[16] = {0};
   void *x = nullptr, *v = nullptr, *yf = nullptr, *zg = nullptr, *yg = nullptr, *xi = nullptr;
@@ -297,6 +298,9 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   A_(h->SubB, ts * nn * SP);
   A_(h->ChF, ts * nn * SP);
   A_(h->ChB, ts * nn * SP);
+  A_(h->SegT, ts * nn * 4 * (size_t)B);
+  A_(h->SegU, ts * nn * 4 * (size_t)B);
+  A_(h->SegX, ts * ROW * 8 * (size_t)B);
   A_(h->x, ts * ROW * SP);
   A_(h->v, ts * ROW * SP);
   A_(h->yf, ts * ROW * SP);
@@ -445,6 +449,9 @@ Layout make_layout(ocp_handle h) {
   L.SubB = h->SubB;
   L.ChF = h->ChF;
   L.ChB = h->ChB;
+  L.SegT = h->SegT;
+  L.SegU = h->SegU;
+  L.SegX = h->SegX;
   for (int k = 0; k < 16; ++k) {
     L.gsel[k] = h->gsel[k];
     L.ginv[k] = h->ginv[k];

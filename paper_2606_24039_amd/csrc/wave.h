@@ -309,6 +309,32 @@ __device__ __forceinline__ void stage_blocks(int nfull, Load&& load, Comp&& comp
 }
 constexpr int STAGE_BLOCK_DEPTH = 3;
 
+// Sequential walk over the stages of a row's quarter, k = 0..steps-1 (rows
+// with shorter quarters skip their last steps inside comp); the inputs of
+// step k + AHEAD are loaded while step k computes.  Loads run up to AHEAD
+// steps past a quarter's end (into the neighbouring quarter or padding).
+template <int AHEAD, typename In, typename Load, typename Comp>
+__device__ __forceinline__ void seg_walk(int steps, Load&& load, Comp&& comp) {
+  constexpr int D = AHEAD + 1;
+  In buf[D];
+  sfor<0, AHEAD>([&](auto j) { load(buf[decltype(j)::value], decltype(j)::value); });
+  int k = 0;
+  for (; k + D <= steps; k += D) {
+    sfor<0, D>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      load(buf[(jj + AHEAD) % D], k + jj + AHEAD);
+      comp(buf[jj], k + jj);
+    });
+  }
+  sfor<0, D>([&](auto j) {
+    constexpr int jj = decltype(j)::value;
+    if (k + jj < steps) {
+      if (k + jj + AHEAD < steps) load(buf[(jj + AHEAD) % D], k + jj + AHEAD);
+      comp(buf[jj], k + jj);
+    }
+  });
+}
+
 // pass-1 inputs of the stage on this row
 template <typename T, int NX, int NU, int NG, bool TI>
 struct EtaIn {
@@ -541,6 +567,263 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
   if (q == 0 && i < NX) {
     const T x0 = ldo(P.v, lo.v);
     sto(P.yf, lo.v + (uint32_t)(N * LO::VS), c.yinit + c.rfa * (x0 - c.xinit));
+  }
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Segmented substitutions.  The horizon is cut into four contiguous
+// quarters, quarter q on row q.  A chain over a quarter from a zero start
+// gives a particular solution; the true value at the quarter's end differs by
+// the quarter's transfer block applied to the value entering it:
+//   forward   v_b = p_b + T_q v_{a-1},   T_q = (-B_b) ... (-B_a),  B = ChF
+//   backward  x_a = p_a + U_q x_{b+1},   U_q = (-B_a) ... (-B_b),  B = ChB
+// (quarter q covers stages a..b).  One iteration: every row runs its
+// quarter's forward chain from zero (with the eta_t / r_t work of each stage),
+// a short serial pass over the four quarter ends finds each quarter's true
+// entering value, every row re-runs its quarter from that value (with the
+// SubB_t product), and the same for the backward chain (with the constraint
+// updates of each stage).  Serial depth per chain: two quarter lengths plus
+// three block products, in place of the whole horizon.  T_q and U_q depend
+// only on the factorisation and are formed after it by pushing the identity
+// through each quarter's chain (prepare_segments).
+// ---------------------------------------------------------------------------
+constexpr int SEG_MIN_N = 128;  // shorter horizons keep the interleaved iteration
+
+struct SegRange {
+  int a, len;  // first stage and stage count of this row's quarter
+};
+__device__ __forceinline__ SegRange seg_range(int q, int N) {
+  const int S = N + 1, base = S / 4, rem = S % 4;
+  return SegRange{q * base + min(q, rem), base + (q < rem ? 1 : 0)};
+}
+
+// T_q and U_q of every quarter of one instance (all rows; row q forms its own
+// quarter's blocks): lane i keeps row i of the running product in H[0..n).
+template <typename T, int NX, int NU, int NG>
+__device__ __noinline__ void prepare_segments(const Layout& Lm, int b_, int64_t s0_, int N_) {
+  constexpr int n = NX + NU;
+  const Layout L = uni(Lm);
+  const int b = uni(b_), N = uni(N_);
+  const int64_t s0 = uni(s0_);
+  const int i = threadIdx.x & (ROW - 1), q = threadIdx.x >> 4;
+  const int ir = i < n ? i : n - 1;
+  const SegRange sg = seg_range(q, N);
+  const int64_t nn = (int64_t)n * n;
+  const uint32_t orow = (uint32_t)(ir * n * (int)sizeof(T));
+  for (int dir = 0; dir < 2; ++dir) {
+    const gptr<const T> Bm = as_global((const T*)(dir == 0 ? L.ChF : L.ChB) + s0 * nn);
+    T H[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) H[j] = (i == j) ? T(1) : T(0);
+    for (int k = 0; k < sg.len; ++k) {
+      const int t = dir == 0 ? sg.a + k : sg.a + sg.len - 1 - k;
+      T Br[n];
+      ldo_n<n>(Br, Bm + t * nn, orow);
+      T Hn[n];
+#pragma unroll
+      for (int j = 0; j < n; ++j) Hn[j] = -dotb<n>(Br, H[j], T(0));
+#pragma unroll
+      for (int j = 0; j < n; ++j) H[j] = Hn[j];
+    }
+    if (i < n) {
+      T* out = (T*)(dir == 0 ? L.SegT : L.SegU) + ((int64_t)b * 4 + q) * nn + (int64_t)i * n;
+#pragma unroll
+      for (int j = 0; j < n; ++j) out[j] = H[j];
+    }
+  }
+}
+
+// The serial pass over the quarter ends.  Every row stores its particular
+// value pe (lane i: entry i) into slot `dir * 4 + q`, then every row forms the
+// true values in sweep order and returns the value entering its own quarter.
+// dir 0 (forward): v_0 = pe_0, v_q = pe_q + T_q v_{q-1}; row q gets v_{q-1}
+// (zero on row 0).  dir 1 (backward): x_3 = pe_3, x_q = pe_q + U_q x_{q+1};
+// row q gets x_{q+1} (zero on row 3).
+template <typename T, int n>
+__device__ __forceinline__ T seg_link(T pe, int dir, gptr<T> X, gptr<const T> TU, int q, int i) {
+  const int ir = i < n ? i : n - 1;
+  const uint32_t ol = (uint32_t)(i * (int)sizeof(T));
+  sto(X + (dir * 4 + q) * ROW, ol, pe);
+  wave_sync();
+  T p[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[k] = ldo(X + (dir * 4 + k) * ROW, ol);
+  const uint32_t orow = (uint32_t)(ir * n * (int)sizeof(T));
+  T in = T(0);
+  if (dir == 0) {
+    T v = p[0];  // true end value of quarter 0
+    in = (q == 1) ? v : in;
+#pragma unroll
+    for (int k = 1; k < 3; ++k) {
+      T Br[n];
+      ldo_n<n>(Br, TU + k * n * n, orow);
+      v = dotb<n>(Br, v, p[k]);
+      in = (q == k + 1) ? v : in;
+    }
+  } else {
+    T x = p[3];  // true start value of quarter 3
+    in = (q == 2) ? x : in;
+#pragma unroll
+    for (int k = 2; k > 0; --k) {
+      T Br[n];
+      ldo_n<n>(Br, TU + k * n * n, orow);
+      x = dotb<n>(Br, x, p[k]);
+      in = (q == k - 1) ? x : in;
+    }
+  }
+  return in;
+}
+
+// inputs of one stage of the segmented forward sweep
+template <typename T, int NX, int NU, int NG, bool TI>
+struct SegFwdIn {
+  EtaIn<T, NX, NU, NG, TI> e;
+  T Cr[NX + NU];  // row `lane` of ChF_t
+};
+
+// One ADMM iteration with segmented substitutions (see above).  X: the
+// instance's exchange slots; Tq / Uq: its transfer blocks.
+template <typename T, int NX, int NU, int NG, typename ST>
+__device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, ST>& c, gptr<T> X, gptr<const T> Tq,
+                                                   gptr<const T> Uq) {
+  constexpr int n = NX + NU;
+  constexpr bool TI = ST::TI;
+  constexpr int VS = ROW * (int)sizeof(T);
+  const int N = c.N, q = c.q, i = c.i;
+  const auto& P = c.P;
+  const int ir = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
+  const T init = (i < NX) ? c.rho_f * c.xinit - c.yinit : T(0);
+  const SegRange sg = seg_range(q, N);
+  const int steps = (N + 4) / 4;  // the longest quarter
+  // offsets of stage t on this lane (vector entry, factor row)
+  auto ov = [&](int t) { return (uint32_t)(((STAGE_PAD + t) * ROW + i) * (int)sizeof(T)); };
+  auto of = [&](int t) { return (uint32_t)(((STAGE_PAD + t) * n * n + ir * n) * (int)sizeof(T)); };
+  auto load_eta_t = [&](EtaIn<T, NX, NU, NG, TI>& d, int t) {
+    const uint32_t o = ov(t);
+    if constexpr (EtaIn<T, NX, NU, NG, TI>::SA) ldo_n<n>(d.Ar, P.SA, of(t));
+    d.x = ldo(P.x, o);
+    d.yf = ldo(P.yf, o);
+    d.yfm = ldo<-VS>(P.yf, o);
+    d.zg = ldo(P.zg, o);
+    d.yg = ldo(P.yg, o);
+    const int tc = min(max(t, 0), N);
+    const int tm = tc > 0 ? tc - 1 : 0;
+    d.q = P.q ? ldo(P.q, (uint32_t)((tc * n + ir) * (int)sizeof(T))) : T(0);
+    if constexpr (!TI) {
+      d.bd = P.bd ? ldo(P.bd, (uint32_t)((tc * NX + ix) * (int)sizeof(T))) : T(0);
+      d.bdm = P.bd ? ldo(P.bd, (uint32_t)((tm * NX + ix) * (int)sizeof(T))) : T(0);
+      ldo_n<NX, n>(d.AmC, P.Am, (uint32_t)((tc * NX * n + ir) * (int)sizeof(T)));
+      ldo_n<NX, n>(d.ApCm, P.Ap, (uint32_t)((tm * NX * n + ir) * (int)sizeof(T)));
+      ldo_n<NG, n>(d.GC, P.G, (uint32_t)((tc * NG * n + ir) * (int)sizeof(T)));
+    }
+  };
+
+  // ---- forward, particular: r_t and p_t = r_t - ChF_t p_{t-1} from zero ----
+  T pe = T(0);
+  {
+    using In = SegFwdIn<T, NX, NU, NG, TI>;
+    auto load = [&](In& d, int k) {
+      const int t = sg.a + k;
+      load_eta_t(d.e, t);
+      ldo_n<n>(d.Cr, P.CF, of(t));
+    };
+    T p = T(0);
+    auto comp = [&](In& d, int k) {
+      if (k >= sg.len) return;
+      const int t = sg.a + k;
+      const T r = stage_r<false>(c, d.e, t, init);
+      sto(P.v, ov(t), r);
+      p = r - dotb<n>(d.Cr, p, T(0));  // p = 0 before the quarter's first stage
+    };
+    seg_walk<2, In>(steps, load, comp);
+    pe = p;
+  }
+  const T vin = seg_link<T, n>(pe, 0, X, Tq, q, i);
+
+  // ---- forward, true values from vin, then s_t = SubB_t v_t ----
+  {
+    struct In {
+      T Cr[n], Br[n];
+      T r;
+    };
+    auto load = [&](In& d, int k) {
+      const int t = sg.a + k;
+      ldo_n<n>(d.Cr, P.CF, of(t));
+      ldo_n<n>(d.Br, P.SB, of(t));
+      d.r = ldo(P.v, ov(t));
+    };
+    T v = vin;
+    auto comp = [&](In& d, int k) {
+      if (k >= sg.len) return;
+      const int t = sg.a + k;
+      v = d.r - dotb<n>(d.Cr, v, T(0));
+      sto(P.v, ov(t), dotb<n>(d.Br, v, T(0)));
+    };
+    seg_walk<2, In>(steps, load, comp);
+  }
+  wave_sync();
+
+  // ---- backward, particular: p_t = s_t - ChB_t p_{t+1} from zero ----
+  {
+    struct In {
+      T Cr[n];
+      T s;
+    };
+    auto load = [&](In& d, int k) {
+      const int t = sg.a + sg.len - 1 - k;
+      ldo_n<n>(d.Cr, P.CB, of(t));
+      d.s = ldo(P.v, ov(t));
+    };
+    T p = T(0);
+    auto comp = [&](In& d, int k) {
+      if (k >= sg.len) return;
+      p = d.s - dotb<n>(d.Cr, p, T(0));  // p = 0 past the quarter's last stage
+    };
+    seg_walk<2, In>(steps, load, comp);
+    pe = p;
+  }
+  const T xin = seg_link<T, n>(pe, 1, X, Uq, q, i);
+
+  // ---- backward, true values from xin, with the constraint-row updates ----
+  {
+    struct In {
+      T Cr[n];
+      T s;
+      UpdIn<T, NX, NU, NG, TI> u;
+    };
+    auto load = [&](In& d, int k) {
+      const int t = sg.a + sg.len - 1 - k;
+      const uint32_t o = ov(t);
+      ldo_n<n>(d.Cr, P.CB, of(t));
+      d.s = ldo(P.v, o);
+      d.u.x = ldo(P.x, o);
+      d.u.yf = ldo(P.yf, o);
+      d.u.zg = ldo(P.zg, o);
+      d.u.yg = ldo(P.yg, o);
+      if constexpr (!TI) {
+        const int tc = min(max(t, 0), N);
+        d.u.lo = ldo(P.lo, (uint32_t)((tc * NG + ig) * (int)sizeof(T)));
+        d.u.hi = ldo(P.hi, (uint32_t)((tc * NG + ig) * (int)sizeof(T)));
+        d.u.bd = P.bd ? ldo(P.bd, (uint32_t)((tc * NX + ix) * (int)sizeof(T))) : T(0);
+        ldo_n<n>(d.u.AmR, P.Am, (uint32_t)((tc * NX * n + ix * n) * (int)sizeof(T)));
+        ldo_n<n>(d.u.ApR, P.Ap, (uint32_t)((tc * NX * n + ix * n) * (int)sizeof(T)));
+        ldo_n<n>(d.u.GR, P.G, (uint32_t)((tc * NG * n + ig * n) * (int)sizeof(T)));
+      }
+    };
+    T xn = xin;  // x~_{t+1}
+    auto comp = [&](In& d, int k) {
+      if (k >= sg.len) return;
+      const int t = sg.a + sg.len - 1 - k;
+      const T xt = d.s - dotb<n>(d.Cr, xn, T(0));
+      d.u.xt = xt;
+      d.u.xt1 = xn;
+      stage_update<false>(c, d.u, t, ov(t));
+      // initial-state rows: y_init += rho_f alpha (x~_0 - x_init), slot N of y_f
+      if (t == 0 && i < NX) sto(P.yf, ov(N), c.yinit + c.rfa * (xt - c.xinit));
+      xn = xt;
+    };
+    seg_walk<2, In>(steps, load, comp);
   }
   wave_sync();
 }
@@ -881,7 +1164,7 @@ __device__ __forceinline__ int boundary_decision(const Resid& R, const Settings&
 // schedule between two boundaries).  Not inlined: the loop gets the register
 // file to itself, the solve-level state of the caller stays out of it.
 // Returns the iteration count reached.
-template <typename T, int NX, int NU, int NG, typename ST>
+template <typename T, int NX, int NU, int NG, typename ST, bool SEG>
 __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, int b_, int64_t s0_, int N_, int k0_,
                                         int nb_, double rho_bar_) {
   const Layout L = uni(Lm);
@@ -903,11 +1186,18 @@ __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, in
   const T rho_f = T(uni(st.rho_f_scale) * rho_bar), alpha = T(uni(st.alpha));
   const IterCtx<T, NX, NU, NG, ST> c{tb,   P,    T(uni(st.sigma)), rho_f, T(rho_bar), alpha, T(1) - alpha,
                                      rho_f * alpha, kind, pc, xinit, T(0), gsel, ginv, i, q, N, gid, hard};
+  constexpr int64_t nn = (int64_t)(NX + NU) * (NX + NU);
+  const gptr<T> X = as_global((T*)L.SegX + (int64_t)b * 8 * ROW);
+  const gptr<const T> Tq = as_global((const T*)L.SegT + (int64_t)b * 4 * nn);
+  const gptr<const T> Uq = as_global((const T*)L.SegU + (int64_t)b * 4 * nn);
   int k = uni(k0_);
   for (; k < nb; ++k) {
     IterCtx<T, NX, NU, NG, ST> ck = c;
     ck.yinit = ldo(P.yf, o_yinit);  // initial-state multipliers (slot N)
-    wave_iteration<T, NX, NU, NG, ST>(ck, lo);
+    if constexpr (SEG)
+      wave_iteration_seg<T, NX, NU, NG, ST>(ck, X, Tq, Uq);
+    else
+      wave_iteration<T, NX, NU, NG, ST>(ck, lo);
   }
   return k;
 }
@@ -948,12 +1238,17 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
       }
       ++nfact;
       need = false;
+      if (w.N >= SEG_MIN_N) {
+        prepare_segments<T, NX, NU, NG>(Lc, w.b, w.s0, w.N);
+        wave_sync();
+      }
     }
     if (k >= st.max_iter) break;
     int nb = st.max_iter;
     if (st.k_check > 0) nb = min(nb, (k / st.k_check + 1) * st.k_check);
     if (adapt_on) nb = min(nb, (k / st.k_rho + 1) * st.k_rho);
-    k = run_segment<T, NX, NU, NG, ST>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
+    k = (w.N >= SEG_MIN_N) ? run_segment<T, NX, NU, NG, ST, true>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar)
+                           : run_segment<T, NX, NU, NG, ST, false>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
     const int check = (st.k_check > 0 && nb % st.k_check == 0) ? 1 : 0;
     const int adapt = (adapt_on && nb % st.k_rho == 0 && nb < st.max_iter) ? 1 : 0;
     const int last = (nb == st.max_iter) ? 1 : 0;
