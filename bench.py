@@ -34,7 +34,7 @@ PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E (published)
 # reads 0.500 of the copied bytes, WRITE_SIZE 1.000).  Summary and commands:
 # profiles/admm_solve_wave_lti1024_n50.md.  Keyed by (workload, precision);
 # valid for the kernel as profiled -- set to None when the kernel changes.
-TRAFFIC_BYTES = {("c2", "mixed"): (28431659.5 * 1.99994 + 7244450.0 * 1.0) * 1024}
+TRAFFIC_BYTES = {("c2", "mixed"): (27552668.0 * 1.99994 + 7772595.6 * 1.0) * 1024}
 
 
 def log(*a):
