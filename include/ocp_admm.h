@@ -249,6 +249,32 @@ ocp_status ocp_graph_capture(ocp_handle h, const ocp_settings* s, const ocp_solu
  * (nothing captured), OCP_E_HIP. */
 ocp_status ocp_graph_launch(ocp_handle h, void* stream);
 
+/* Launch shape (batching and scheduling).  The substitutions of S x = eta
+ * (Sec. "Primal update") run as one serial chain over the horizon
+ * (interleaved iteration) for short horizons and, for horizons
+ * N >= seg_min_n, segmented: the horizon is cut into four segments whose
+ * chains run side by side from a zero start and are joined through the
+ * segments' transfer blocks, formed after each factorisation.  Both solve the
+ * same system; results agree up to rounding.  The default switch is
+ * N >= 128.
+ *
+ * ocp_set_segmented: set the switch for later solves on this handle (values
+ * below 15 are raised to 15: segments of at least four stages; INT32_MAX
+ * keeps every instance interleaved).  Drops a captured graph.  Errors:
+ * OCP_E_ARG (null handle). */
+ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n);
+
+/* Autotuner over the launch shape: times `reps` cold-start ocp_solve calls
+ * with settings `s` on the handle's own batch for each switch point --
+ * 15 (every instance segmented), 128 (the default) and INT32_MAX (none) --
+ * on `stream` (one warm-up solve each; synchronises the stream), keeps the
+ * fastest for later solves and returns it in *seg_min_n (HOST int32; may be
+ * NULL).  The solution state afterwards is that of the last timed solve:
+ * solve again before reading results.  Kernel timing is suspended while it
+ * runs.  Errors: OCP_E_ARG (null handle / settings, reps < 1, invalid
+ * settings), OCP_E_ORDER (no problem data), OCP_E_HIP. */
+ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void* stream, int32_t* seg_min_n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,6 +84,8 @@ SIGNATURES = [
     ("ocp_graph_capture", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.POINTER(ocp_solution), C.c_void_p,
                                     C.POINTER(ocp_qp_grads), C.c_void_p]),
     ("ocp_graph_launch", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("ocp_set_segmented", C.c_int, [C.c_void_p, C.c_int32]),
+    ("ocp_autotune", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     ("ocp_profile_read", C.c_int, [C.c_void_p, C.POINTER(ocp_kernel_times)]),
 ]
 

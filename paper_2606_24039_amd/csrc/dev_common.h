@@ -218,6 +218,7 @@ struct Layout {
 struct Settings {
   double sigma, rho0, rho_f_scale, rho_min, rho_max, k_ratio, alpha, eps_abs, eps_rel;
   int max_iter, k_rho, k_check, adapt_rho, warm;
+  int seg_min_n;  // horizons N >= seg_min_n run the segmented substitutions
 };
 
 struct Group {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -170,6 +172,7 @@ struct ocp_handle_s {
   void *SubA = nullptr, *SubB = nullptr, *ChF = nullptr, *ChB = nullptr;
   void *SegT = nullptr, *SegU = nullptr, *SegX = nullptr;
   int variant = 0;
+  int seg_min_n = SEG_MIN_N;  // launch shape: horizons from which the substitutions run segmented
   int8_t gsel[16] = {0}, ginv[16] = {0};
   void *x = nullptr, *v = nullptr, *yf = nullptr, *zg = nullptr, *yg = nullptr, *xi = nullptr;
   double *rho = nullptr, *rprim = nullptr, *rdual = nullptr;
@@ -559,8 +562,10 @@ ocp_status copy_out(ocp_handle h, const ocp_solution* o, hipStream_t st) {
   return hip_ok(hipGetLastError());
 }
 
-void run_admm(ocp_handle h, const Settings& s, hipStream_t st) {
+void run_admm(ocp_handle h, const Settings& s_, hipStream_t st) {
   const Layout L = make_layout(h);
+  Settings s = s_;
+  s.seg_min_n = h->seg_min_n;
   const int ti = h->ti ? 1 : 0;
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (ti ? VAR_TI : VAR_TV);
   if (h->mixed)
@@ -965,6 +970,59 @@ ocp_status ocp_graph_launch(ocp_handle h, void* stream) {
   if (hipGraphLaunch(h->graph_exec, (hipStream_t)stream) != hipSuccess) return OCP_E_HIP;
   h->solved = true;
   return OCP_OK;
+}
+
+ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n) {
+  if (!h) return OCP_E_ARG;
+  if (h->graph_exec) {  // a captured graph keeps the launch shape it was recorded with
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  h->seg_min_n = std::max<int32_t>(seg_min_n, SEG_FLOOR_N);
+  return OCP_OK;
+}
+
+ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void* stream, int32_t* seg_min_n) {
+  if (!h || !s || reps < 1) return OCP_E_ARG;
+  ocp_status st = check_settings(s);
+  if (st != OCP_OK) return st;
+  if (!h->data_set) return OCP_E_ORDER;
+  hipStream_t stream_ = (hipStream_t)stream;
+  ocp_settings cold = *s;
+  cold.warm_start = 0;
+  const int32_t cand[3] = {SEG_FLOOR_N, SEG_MIN_N, INT32_MAX};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return OCP_E_HIP;
+  }
+  const bool prof_on = h->prof.on;
+  h->prof.on = false;
+  float best = INFINITY;
+  int32_t pick = h->seg_min_n;
+  for (int c = 0; c < 3 && st == OCP_OK; ++c) {
+    h->seg_min_n = cand[c];
+    st = ocp_solve(h, &cold, nullptr, stream);  // warm-up (and first touch of the transfer blocks)
+    if (st != OCP_OK) break;
+    if (hipEventRecord(e0, stream_) != hipSuccess) st = OCP_E_HIP;
+    for (int r = 0; r < reps && st == OCP_OK; ++r) st = ocp_solve(h, &cold, nullptr, stream);
+    float ms = 0.f;
+    if (st == OCP_OK && (hipEventRecord(e1, stream_) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = OCP_E_HIP;
+    if (st == OCP_OK && ms < best) best = ms, pick = cand[c];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->prof.on = prof_on;
+  if (st != OCP_OK) return st;
+  const ocp_status r = ocp_set_segmented(h, pick);
+  if (seg_min_n) *seg_min_n = h->seg_min_n;
+  return r;
 }
 
 }  // extern "C"

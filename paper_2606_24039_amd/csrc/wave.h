@@ -588,7 +588,8 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
 // only on the factorisation and are formed after it by pushing the identity
 // through each quarter's chain (prepare_segments).
 // ---------------------------------------------------------------------------
-constexpr int SEG_MIN_N = 128;  // shorter horizons keep the interleaved iteration
+constexpr int SEG_MIN_N = 128;  // default switch: shorter horizons keep the interleaved iteration
+constexpr int SEG_FLOOR_N = 15;  // segments of at least four stages
 
 struct SegRange {
   int a, len;  // first stage and stage count of this row's quarter
@@ -1238,7 +1239,7 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
       }
       ++nfact;
       need = false;
-      if (w.N >= SEG_MIN_N) {
+      if (w.N >= st.seg_min_n) {
         prepare_segments<T, NX, NU, NG>(Lc, w.b, w.s0, w.N);
         wave_sync();
       }
@@ -1247,7 +1248,7 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
     int nb = st.max_iter;
     if (st.k_check > 0) nb = min(nb, (k / st.k_check + 1) * st.k_check);
     if (adapt_on) nb = min(nb, (k / st.k_rho + 1) * st.k_rho);
-    k = (w.N >= SEG_MIN_N) ? run_segment<T, NX, NU, NG, ST, true>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar)
+    k = (w.N >= st.seg_min_n) ? run_segment<T, NX, NU, NG, ST, true>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar)
                            : run_segment<T, NX, NU, NG, ST, false>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
     const int check = (st.k_check > 0 && nb % st.k_check == 0) ? 1 : 0;
     const int adapt = (adapt_on && nb % st.k_rho == 0 && nb < st.max_iter) ? 1 : 0;

@@ -183,6 +183,18 @@ class OCPSolver:
     def graph_launch(self):
         A.check(self.lib.ocp_graph_launch(self.h, _stream()), "ocp_graph_launch")
 
+    def set_segmented(self, seg_min_n: int):
+        """Horizons N >= seg_min_n solve with segmented substitutions (ocp_set_segmented)."""
+        A.check(self.lib.ocp_set_segmented(self.h, int(seg_min_n)), "ocp_set_segmented")
+
+    def autotune(self, settings=None, reps: int = 1, **overrides) -> int:
+        """Time the launch-shape candidates on this batch and keep the fastest
+        (ocp_autotune); returns the chosen switch horizon."""
+        s = settings if settings is not None else A.default_settings(**overrides)
+        chosen = C.c_int32(0)
+        A.check(self.lib.ocp_autotune(self.h, C.byref(s), int(reps), _stream(), C.byref(chosen)), "ocp_autotune")
+        return int(chosen.value)
+
     def split(self, arr, i):
         """Rows of a stage-concatenated array that belong to instance i."""
         return arr[int(self.stage_off[i]):int(self.stage_off[i + 1])]
