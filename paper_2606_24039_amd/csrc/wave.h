@@ -64,6 +64,24 @@ template <int IMM = 0, typename T>
 __device__ __forceinline__ void sto(gptr<T> base, uint32_t off, T v) {
   *(gptr<T>)((gptr<char>)base + off + IMM) = v;
 }
+// the same for a wavefront's LDS (the per-instance exchange vector)
+template <typename T>
+using lptr = __attribute__((address_space(3))) T*;
+template <int IMM = 0, typename T>
+__device__ __forceinline__ std::remove_const_t<T> ldo(lptr<T> base, uint32_t off) {
+  return *(lptr<const T>)((lptr<const char>)base + off + IMM);
+}
+template <int IMM = 0, typename T>
+__device__ __forceinline__ void sto(lptr<T> base, uint32_t off, T v) {
+  *(lptr<T>)((lptr<char>)base + off + IMM) = v;
+}
+// LDS stages of the exchange vector: horizons with N + 1 + 2 STAGE_PAD + 8
+// stages or fewer keep it in LDS (16 KB per wavefront in FP32)
+constexpr int XV_LDS_STAGES = 256;
+__device__ __forceinline__ bool xv_in_lds(int N) { return N + 1 + 2 * STAGE_PAD + 8 <= XV_LDS_STAGES; }
+// ordering of a wavefront's own LDS writes before its later LDS reads by
+// other lanes (one wavefront per workgroup: no barrier needed)
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 // K consecutive entries from base + off (16-byte aligned: whole 16-byte
 // loads), or K entries STRIDE apart
 template <typename T>
@@ -136,8 +154,8 @@ struct ChainIn {
 // R, Bm: biased bases; orow / oblk: this lane's offsets at stage 0.  The
 // running stage position lives in the (uniform) base pointers, the lane
 // offsets stay fixed.
-template <typename T, int n, int DIR>
-__device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, uint32_t orow, uint32_t oblk, int N) {
+template <typename T, int n, int DIR, typename RP>
+__device__ __forceinline__ void chain(RP R, gptr<const T> Bm, uint32_t orow, uint32_t oblk, int N) {
   constexpr int PF = chain_prefetch<T, n>();
   static_assert(PF <= STAGE_PAD, "prefetch reaches past the buffer padding");
   constexpr int VS = DIR * ROW * (int)sizeof(T);  // one step of the sweep in a vector, bytes
@@ -145,7 +163,7 @@ __device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, uint32_t orow
   // bases at the sweep's k0-th stage (t = 0 forward, t = N backward);
   // prefetches run up to PF stages past either end of the instance, into
   // the neighbouring instances or the padding
-  gptr<T> Rk = R + (DIR > 0 ? 0 : (long)N * ROW);
+  RP Rk = R + (DIR > 0 ? 0 : (long)N * ROW);
   gptr<const T> Bk = Bm + (DIR > 0 ? 0 : (long)N * n * n);
   ChainIn<T, n> buf[PF];
   auto load = [&](ChainIn<T, n>& d, auto j) {
@@ -181,15 +199,15 @@ __device__ __forceinline__ void chain(gptr<T> R, gptr<const T> Bm, uint32_t orow
 // rows by two permlane swaps, which leaves the same y_t on every row.  Per
 // stage: three shifts, n/4 broadcast FMAs and the two swap-adds in place of
 // n broadcast FMAs on one row, and one 16-byte load per lane.
-template <int n, int DIR>
-__device__ __forceinline__ void chain_rows(gptr<float> R, gptr<const float> Bm, uint32_t orow, uint32_t oblk, int N) {
+template <int n, int DIR, typename RP>
+__device__ __forceinline__ void chain_rows(RP R, gptr<const float> Bm, uint32_t orow, uint32_t oblk, int N) {
   static_assert(n % 4 == 0 && n <= ROW, "row-split chain needs n = 4k <= 16");
   constexpr int QS = n / 4;
   constexpr int PF = chain_prefetch<float, n>();
   static_assert(PF <= STAGE_PAD, "prefetch reaches past the buffer padding");
   constexpr int VS = DIR * ROW * (int)sizeof(float);
   constexpr long BS = DIR * (long)n * n;
-  gptr<float> Rk = R + (DIR > 0 ? 0 : (long)N * ROW);
+  RP Rk = R + (DIR > 0 ? 0 : (long)N * ROW);
   gptr<const float> Bk = Bm + (DIR > 0 ? 0 : (long)N * n * n);
   struct In {
     float A[QS];
@@ -459,8 +477,20 @@ __device__ __forceinline__ void stage_update(const IterCtx<T, NX, NU, NG, ST>& c
 
 // One iteration on one wavefront (the vectors handed between passes go
 // through the instance's v buffer).
-template <typename T, int NX, int NU, int NG, typename ST>
-__device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>& c, const LaneOff<T, NX + NU>& lo) {
+// XV: the exchange vector -- the instance's v buffer in global memory or an
+// LDS array of XV_LDS_STAGES stages (same offsets); with LDS the passes are
+// ordered by LDS waits, only the state handed to the next iteration through
+// global memory needs the full wait at the end.
+template <typename T, int NX, int NU, int NG, typename ST, typename XVP>
+__device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>& c, const LaneOff<T, NX + NU>& lo,
+                                               XVP XV) {
+  constexpr bool XL = !std::is_same_v<XVP, gptr<T>>;
+  auto pass_sync = [] {
+    if constexpr (XL)
+      lds_sync();
+    else
+      wave_sync();
+  };
   constexpr int n = NX + NU;
   constexpr bool TI = ST::TI;
   using LO = LaneOff<T, n>;
@@ -498,42 +528,42 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
       constexpr bool FULL = decltype(full)::value;
       const int t = 4 * blk + q;
       const T r = stage_r<FULL>(c, d, t, init);
-      if (FULL || t <= N) sto(P.v, lo.v + blk * LO::VB, r);
+      if (FULL || t <= N) sto(XV, lo.v + blk * LO::VB, r);
     };
     stage_blocks<STAGE_BLOCK_DEPTH, In>(nfull, load, comp);
   }
-  wave_sync();
+  pass_sync();
 
   // ---------------- pass 2: forward chain (row 0) ----------------
   if constexpr (ROWSPLIT_CHAIN<T, n>)
-    chain_rows<n, +1>(P.v, P.CF, lo.v0, lo.fq, N);
+    chain_rows<n, +1>(XV, P.CF, lo.v0, lo.fq, N);
   else if (q == 0)
-    chain<T, n, +1>(P.v, P.CF, lo.v, lo.f, N);
-  wave_sync();
+    chain<T, n, +1>(XV, P.CF, lo.v, lo.f, N);
+  pass_sync();
 
   // ---------------- pass 3: s_t = SubB_t v_t on row t mod 4 ----------------
   {
     using In = TrIn<T, n>;
     auto load = [&](In& d, int blk) {
       ldo_n<n>(d.Br, P.SB, lo.f + blk * LO::FB);
-      d.v = ldo(P.v, lo.v + blk * LO::VB);
+      d.v = ldo(XV, lo.v + blk * LO::VB);
     };
     auto comp = [&](const In& d, int blk, auto full) {
       constexpr bool FULL = decltype(full)::value;
       const int t = 4 * blk + q;
       const T s = dotb<n>(d.Br, d.v, T(0));
-      if (FULL || t <= N) sto(P.v, lo.v + blk * LO::VB, s);
+      if (FULL || t <= N) sto(XV, lo.v + blk * LO::VB, s);
     };
     stage_blocks<STAGE_BLOCK_DEPTH, In>(nfull, load, comp);
   }
-  wave_sync();
+  pass_sync();
 
   // ---------------- pass 4: backward chain (row 0) ----------------
   if constexpr (ROWSPLIT_CHAIN<T, n>)
-    chain_rows<n, -1>(P.v, P.CB, lo.v0, lo.fq, N);
+    chain_rows<n, -1>(XV, P.CB, lo.v0, lo.fq, N);
   else if (q == 0)
-    chain<T, n, -1>(P.v, P.CB, lo.v, lo.f, N);
-  wave_sync();
+    chain<T, n, -1>(XV, P.CB, lo.v, lo.f, N);
+  pass_sync();
 
   // ---------------- pass 5: constraint-row updates on row t mod 4 ----------------
   {
@@ -541,8 +571,8 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
     auto load = [&](In& d, int blk) {
       const int t = 4 * blk + q;
       const uint32_t ov = lo.v + blk * LO::VB;
-      d.xt = ldo(P.v, ov);
-      d.xt1 = ldo<(int)LO::VS>(P.v, ov);
+      d.xt = ldo(XV, ov);
+      d.xt1 = ldo<(int)LO::VS>(XV, ov);
       d.x = ldo(P.x, ov);
       d.yf = ldo(P.yf, ov);
       d.zg = ldo(P.zg, ov);
@@ -565,7 +595,7 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
   }
   // initial-state rows: y_init += rho_f alpha (x~_0 - x_init), slot N of y_f
   if (q == 0 && i < NX) {
-    const T x0 = ldo(P.v, lo.v);
+    const T x0 = ldo(XV, lo.v);
     sto(P.yf, lo.v + (uint32_t)(N * LO::VS), c.yinit + c.rfa * (x0 - c.xinit));
   }
   wave_sync();
@@ -1191,14 +1221,19 @@ __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, in
   const gptr<T> X = as_global((T*)L.SegX + (int64_t)b * 8 * ROW);
   const gptr<const T> Tq = as_global((const T*)L.SegT + (int64_t)b * 4 * nn);
   const gptr<const T> Uq = as_global((const T*)L.SegU + (int64_t)b * 4 * nn);
+  __shared__ __attribute__((aligned(16))) T xv_buf[SEG ? 1 : XV_LDS_STAGES * ROW];
+  const lptr<T> XVl = (lptr<T>)xv_buf;
+  const bool xv_lds = !SEG && xv_in_lds(N);
   int k = uni(k0_);
   for (; k < nb; ++k) {
     IterCtx<T, NX, NU, NG, ST> ck = c;
     ck.yinit = ldo(P.yf, o_yinit);  // initial-state multipliers (slot N)
     if constexpr (SEG)
       wave_iteration_seg<T, NX, NU, NG, ST>(ck, X, Tq, Uq);
+    else if (xv_lds)
+      wave_iteration<T, NX, NU, NG, ST>(ck, lo, XVl);
     else
-      wave_iteration<T, NX, NU, NG, ST>(ck, lo);
+      wave_iteration<T, NX, NU, NG, ST>(ck, lo, P.v);
   }
   return k;
 }
