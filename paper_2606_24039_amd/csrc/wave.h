@@ -78,6 +78,7 @@ __device__ __forceinline__ void sto(lptr<T> base, uint32_t off, T v) {
 // LDS stages of the exchange vector: horizons with N + 1 + 2 STAGE_PAD + 8
 // stages or fewer keep it in LDS (16 KB per wavefront in FP32)
 constexpr int XV_LDS_STAGES = 256;
+constexpr int STATE_LDS_STAGES = 80;  // FP32: six vectors of 80 stages (30 KB), horizons up to 55
 __device__ __forceinline__ bool xv_in_lds(int N) { return N + 1 + 2 * STAGE_PAD + 8 <= XV_LDS_STAGES; }
 // ordering of a wavefront's own LDS writes before its later LDS reads by
 // other lanes (one wavefront per workgroup: no barrier needed)
@@ -108,11 +109,12 @@ __device__ __forceinline__ void ldo_n(T (&d)[K], gptr<const T> base, uint32_t of
 }
 
 // Uniform base pointers of one instance.
-template <typename T, int NX, int NU, int NG>
+template <typename T, int NX, int NU, int NG, bool LV = false>
 struct IterPtrs {
   static constexpr int n = NX + NU;
+  using VP = std::conditional_t<LV, lptr<T>, gptr<T>>;
   gptr<const T> SA, SB, CF, CB;  // factor products (SubA, SubB, ChF, ChB), at stage -STAGE_PAD
-  gptr<T> x, v, yf, zg, yg, xi;  // stage vectors, at stage -STAGE_PAD
+  VP x, v, yf, zg, yg, xi;       // stage vectors (global, or LDS copies), at stage -STAGE_PAD
   gptr<const T> Am, Ap, G;       // TI: the instance's blocks; TV: stage 0 of the instance
   gptr<const T> lo, hi, bd;      // likewise (bd may be null)
   gptr<const T> q;               // stage 0 of the instance (may be null)
@@ -137,6 +139,17 @@ struct IterPtrs {
     hi = as_global((const T*)L.hiT + u * NG);
     bd = L.bdT ? as_global((const T*)L.bdT + u * NX) : nullptr;
     q = L.qT ? as_global((const T*)L.qT + s0 * n) : nullptr;
+  }
+  // the same data with the stage vectors in LDS: vector k at base + k * stages * ROW
+  template <bool LV2 = LV, typename = std::enable_if_t<LV2>>
+  __device__ IterPtrs(const IterPtrs<T, NX, NU, NG, false>& g, lptr<T> base, int stages)
+      : SA(g.SA), SB(g.SB), CF(g.CF), CB(g.CB), Am(g.Am), Ap(g.Ap), G(g.G), lo(g.lo), hi(g.hi), bd(g.bd), q(g.q) {
+    x = base;
+    v = base + stages * ROW;
+    yf = base + 2 * stages * ROW;
+    zg = base + 3 * stages * ROW;
+    yg = base + 4 * stages * ROW;
+    xi = base + 5 * stages * ROW;
   }
 };
 
@@ -255,10 +268,10 @@ template <typename T, int n>
 constexpr bool ROWSPLIT_CHAIN = sizeof(T) == 4 && n % 4 == 0 && n <= ROW;
 
 // Scalars of one ADMM iteration of one instance (this lane's view).
-template <typename T, int NX, int NU, int NG, typename ST>
+template <typename T, int NX, int NU, int NG, typename ST, bool LV = false>
 struct IterCtx {
   const TIBlocks<T, NX, NU, NG>& tb;
-  const IterPtrs<T, NX, NU, NG>& P;
+  const IterPtrs<T, NX, NU, NG, LV>& P;
   T sigma, rho_f, rho_g, alpha, oma, rfa;
   int kind;
   ProjConst<T> pc;
@@ -382,8 +395,8 @@ struct TrIn {
 // r_t of the stage on this row: eta_t, times Linv_t for FP32 iterations.
 // `init` is this lane's initial-state term (rho_f x_init - y_init on lanes
 // < nx), added at t = 0.
-template <bool FULL, typename T, int NX, int NU, int NG, typename ST>
-__device__ __forceinline__ T stage_r(const IterCtx<T, NX, NU, NG, ST>& c, const EtaIn<T, NX, NU, NG, ST::TI>& cur,
+template <bool FULL, typename T, int NX, int NU, int NG, typename ST, bool LV>
+__device__ __forceinline__ T stage_r(const IterCtx<T, NX, NU, NG, ST, LV>& c, const EtaIn<T, NX, NU, NG, ST::TI>& cur,
                                      int t, T init) {
   constexpr int n = NX + NU;
   constexpr bool TI = ST::TI;
@@ -426,8 +439,8 @@ __device__ __forceinline__ T stage_r(const IterCtx<T, NX, NU, NG, ST>& c, const 
 // over-relaxation, projection and dual update of every constraint row of
 // the stage on this row, from x~_t and x~_{t+1}; stores the new state
 // (rows past N store nothing, y_f only for t < N)
-template <bool FULL, typename T, int NX, int NU, int NG, typename ST>
-__device__ __forceinline__ void stage_update(const IterCtx<T, NX, NU, NG, ST>& c,
+template <bool FULL, typename T, int NX, int NU, int NG, typename ST, bool LV>
+__device__ __forceinline__ void stage_update(const IterCtx<T, NX, NU, NG, ST, LV>& c,
                                              const UpdIn<T, NX, NU, NG, ST::TI>& cur, int t, uint32_t o) {
   constexpr int n = NX + NU;
   constexpr bool TI = ST::TI;
@@ -481,8 +494,8 @@ __device__ __forceinline__ void stage_update(const IterCtx<T, NX, NU, NG, ST>& c
 // LDS array of XV_LDS_STAGES stages (same offsets); with LDS the passes are
 // ordered by LDS waits, only the state handed to the next iteration through
 // global memory needs the full wait at the end.
-template <typename T, int NX, int NU, int NG, typename ST, typename XVP>
-__device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>& c, const LaneOff<T, NX + NU>& lo,
+template <typename T, int NX, int NU, int NG, typename ST, bool LV, typename XVP>
+__device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST, LV>& c, const LaneOff<T, NX + NU>& lo,
                                                XVP XV) {
   constexpr bool XL = !std::is_same_v<XVP, gptr<T>>;
   auto pass_sync = [] {
@@ -598,7 +611,10 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST>&
     const T x0 = ldo(XV, lo.v);
     sto(P.yf, lo.v + (uint32_t)(N * LO::VS), c.yinit + c.rfa * (x0 - c.xinit));
   }
-  wave_sync();
+  if constexpr (LV)
+    lds_sync();  // the whole state is in LDS
+  else
+    wave_sync();
 }
 
 // ---------------------------------------------------------------------------
@@ -1221,10 +1237,47 @@ __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, in
   const gptr<T> X = as_global((T*)L.SegX + (int64_t)b * 8 * ROW);
   const gptr<const T> Tq = as_global((const T*)L.SegT + (int64_t)b * 4 * nn);
   const gptr<const T> Uq = as_global((const T*)L.SegU + (int64_t)b * 4 * nn);
-  __shared__ __attribute__((aligned(16))) T xv_buf[SEG ? 1 : XV_LDS_STAGES * ROW];
-  const lptr<T> XVl = (lptr<T>)xv_buf;
-  const bool xv_lds = !SEG && xv_in_lds(N);
+  // LDS of the interleaved iteration: FP32 horizons up to STATE_LDS_STAGES
+  // keep all six stage vectors there for the segment (copied in here and out
+  // before the boundary's residuals); longer ones, and FP64, the exchange
+  // vector only
+  constexpr int LDS_ELEMS = sizeof(T) == 4 ? 6 * STATE_LDS_STAGES * ROW : XV_LDS_STAGES * ROW;
+  __shared__ __attribute__((aligned(16))) T lds_buf[SEG ? 1 : LDS_ELEMS];
+  const lptr<T> XVl = (lptr<T>)lds_buf;
+  const bool state_lds = !SEG && sizeof(T) == 4 && N + 1 + 2 * STAGE_PAD + 8 <= STATE_LDS_STAGES;
+  const bool xv_lds = !SEG && N + 1 + 2 * STAGE_PAD + 8 <= LDS_ELEMS / ROW;
   int k = uni(k0_);
+  if constexpr (!SEG && sizeof(T) == 4) {
+    if (state_lds) {
+      const IterPtrs<T, NX, NU, NG, true> PL(P, XVl, STATE_LDS_STAGES);
+      // stages 0..N of x, y_f (slot N: the initial-state rows), z_g, y_g, xi
+      const int len = (N + 1) * ROW;
+      const uint32_t o0 = (uint32_t)(STAGE_PAD * ROW * (int)sizeof(T));
+      auto copy = [&](auto dst, auto src) {
+        for (int e = threadIdx.x; e < len; e += 64) sto(dst, o0 + (uint32_t)(e * (int)sizeof(T)), ldo(src, o0 + (uint32_t)(e * (int)sizeof(T))));
+      };
+      copy(PL.x, P.x);
+      copy(PL.yf, P.yf);
+      copy(PL.zg, P.zg);
+      copy(PL.yg, P.yg);
+      copy(PL.xi, P.xi);
+      lds_sync();
+      const IterCtx<T, NX, NU, NG, ST, true> cl{tb, PL,   c.sigma, c.rho_f, c.rho_g, c.alpha, c.oma, c.rfa, c.kind,
+                                                c.pc, c.xinit, T(0), c.gsel, c.ginv, c.i, c.q, c.N, c.gid, c.hard};
+      for (; k < nb; ++k) {
+        IterCtx<T, NX, NU, NG, ST, true> ck = cl;
+        ck.yinit = ldo(PL.yf, o_yinit);
+        wave_iteration<T, NX, NU, NG, ST>(ck, lo, PL.v);
+      }
+      copy(P.x, PL.x);
+      copy(P.yf, PL.yf);
+      copy(P.zg, PL.zg);
+      copy(P.yg, PL.yg);
+      copy(P.xi, PL.xi);
+      wave_sync();  // the boundary's residuals read the state from global memory
+      return k;
+    }
+  }
   for (; k < nb; ++k) {
     IterCtx<T, NX, NU, NG, ST> ck = c;
     ck.yinit = ldo(P.yf, o_yinit);  // initial-state multipliers (slot N)
