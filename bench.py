@@ -34,7 +34,7 @@ PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E (published)
 # reads 0.500 of the copied bytes, WRITE_SIZE 1.000).  Summary and commands:
 # profiles/admm_solve_wave_lti1024_n50.md.  Keyed by (workload, precision);
 # valid for the kernel as profiled -- set to None when the kernel changes.
-TRAFFIC_BYTES = {("c2", "mixed"): (27552668.0 * 1.99994 + 7772595.6 * 1.0) * 1024}
+TRAFFIC_BYTES = {("c2", "mixed"): (23622934.1 * 1.99994 + 2114126.3 * 1.0) * 1024}
 
 
 def log(*a):
@@ -59,13 +59,14 @@ def lti_flops_per_stage(nx, nu, ng):
     return f_it, f_fac
 
 
-def lti_bytes_per_stage(n, ts, blocks):
-    """Algorithmic bytes one ADMM iteration moves per stage (HBM model: every
-    operand read and every result written once): `blocks` n x n factor blocks
-    (4 for FP32 iterations: Linv_t, Linv_t', W_t, V_t; 3 for FP64: P_t, K_t,
-    K_{t+1}') and 21 padded 16-entry stage vectors (12 read, 9 written over
-    the five passes)."""
-    return blocks * n * n * ts + 21 * 16 * ts
+def lti_bytes_per_stage(n, ts, blocks, k_seg=25):
+    """Algorithmic bytes one ADMM iteration moves per stage, for the design
+    measured here (FP32 iterations, horizons up to 55 stages): the `blocks`
+    n x n factor blocks (Linv_t, Linv_t', W_t, V_t) stream from memory once per
+    iteration; the six padded 16-entry stage vectors stay in LDS for a
+    segment of `k_seg` iterations, so five of them (x, y_f, z_g, y_g, xi) move
+    in and out once per segment."""
+    return blocks * n * n * ts + (2 * 5 * 16 * ts) / k_seg
 
 
 def make_workload(name):
@@ -242,14 +243,15 @@ def main():
 
     value = mixed["solved"] / (mixed["ms_per_step"] * 1e-3)
     # roofline of the dominant kernel (the persistent ADMM solve).  It streams
-    # the factor blocks of every running instance once per iteration and is
-    # bound by memory traffic while the batch is full (the FP32 factor copies
-    # of 1024 instances, 213 MB, exceed the L2), so the bound is HBM: achieved
+    # the factor blocks of every running instance once per iteration (the
+    # stage vectors stay in LDS between boundary checks) and is bound by
+    # memory traffic while the batch is full (the FP32 factor copies of 1024
+    # instances, 213 MB, exceed the L2), so the bound is HBM: achieved
     # = algorithmic bytes of all its launches in a step / its GPU time in a
     # step (= average bytes per launch / average launch duration).
     kit = mixed["kernels"]["solve"]
     n = batch.nx + batch.nu
-    b_it = lti_bytes_per_stage(n, 4, 4)
+    b_it = lti_bytes_per_stage(n, 4, 4, min(k for k in (settings_kw.get("k_check", 25), settings_kw.get("k_rho", 25)) if k > 0))
     bytes_launch = mixed["iters_sum"] * stages * b_it / max(kit["launches_per_step"], 1)
     t_launch = kit["ms_per_step"] * 1e-3 / max(kit["launches_per_step"], 1)
     achieved = bytes_launch / t_launch / 1e9
