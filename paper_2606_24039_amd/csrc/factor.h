@@ -31,6 +31,62 @@ __device__ __forceinline__ void cross_row(const double (&a)[R], const double (&b
   });
 }
 
+// 1/sqrt(d) for d > 0 in FP64: the hardware estimate (relative error below
+// 2^-22) refined by one third-order Newton step, y <- y (1 + r/2 + 3 r^2/8)
+// with r = 1 - d y^2, which leaves a relative error of a few units in the
+// last place.  One transcendental and five dependent operations instead of
+// a correctly rounded square root followed by a correctly rounded division.
+__device__ __forceinline__ double rsqrt_pivot(double d) {
+  const double y = __builtin_amdgcn_rsq(d);
+  const double h = d * y;
+  const double r = fma(-h, y, 1.0);
+  const double c = fma(0.375, r, 0.5) * r;
+  return fma(y, c, y);
+}
+
+// Cholesky S = L L' of the n x n block held by rows (lane i of the 16-lane
+// row: row i of S, clobbered) and X = L^{-1} (lane i: row i).  Returns 1 on a
+// non-positive or non-finite pivot (the same on every lane of the row).
+template <int n>
+__device__ __forceinline__ int chol_inv(double (&S)[n], double (&X)[n], int i) {
+  int bad = 0;
+  double Lr[n], invd[n];
+  sfor<0, n>([&](auto k) {
+    constexpr int kk = decltype(k)::value;
+    double dkk = bc<kk>(S[kk]);
+    if (!(dkk > 0.0) || !isfinite(dkk)) {
+      bad = 1;
+      dkk = 1.0;
+    }
+    const double id = rsqrt_pivot(dkk);
+    invd[kk] = id;
+    const double lik = (i >= kk) ? S[kk] * id : 0.0;
+    Lr[kk] = lik;
+    sfor<kk + 1, n>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      S[jj] = fma(-lik, bc<jj>(lik), S[jj]);
+    });
+  });
+  sfor<0, n>([&](auto j) {
+    constexpr int jj = decltype(j)::value;
+    X[jj] = (i == jj) ? 1.0 : 0.0;
+  });
+  sfor<0, n>([&](auto k) {
+    constexpr int kk = decltype(k)::value;
+    const double sc = (i == kk) ? invd[kk] : 1.0;
+    sfor<0, kk + 1>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      X[jj] *= sc;
+    });
+    const double lik = (i > kk) ? Lr[kk] : 0.0;
+    sfor<0, kk + 1>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      X[jj] = fma(-lik, bc<kk>(X[jj]), X[jj]);
+    });
+  });
+  return bad;
+}
+
 // Per-stage FP64 inputs of the factorisation (lane i: row / column i).
 template <int NX, int NU, int NG>
 struct FacStage {
@@ -193,44 +249,9 @@ __device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, d
     }
     if (t > 0) cross_row<n, n>(Mrow, Mrow, S, -1.0);
 
-    // dense Cholesky of S (lane i holds row i), L row i and 1/L_kk
-    double Lr[n], invd[n];
-    sfor<0, n>([&](auto k) {
-      constexpr int kk = decltype(k)::value;
-      double dkk = bc<kk>(S[kk]);
-      if (!(dkk > 0.0) || !isfinite(dkk)) {
-        bad = 1;
-        dkk = 1.0;
-      }
-      const double dk = sqrt(dkk);
-      const double id = 1.0 / dk;
-      invd[kk] = id;
-      const double lik = (i >= kk) ? S[kk] * id : 0.0;
-      Lr[kk] = lik;
-      sfor<kk + 1, n>([&](auto j) {
-        constexpr int jj = decltype(j)::value;
-        S[jj] = fma(-lik, bc<jj>(lik), S[jj]);
-      });
-    });
-    // X = L^{-1}, lane i holds row i
+    // dense Cholesky of S and X = L^{-1} (lane i holds row i)
     double X[n];
-    sfor<0, n>([&](auto j) {
-      constexpr int jj = decltype(j)::value;
-      X[jj] = (i == jj) ? 1.0 : 0.0;
-    });
-    sfor<0, n>([&](auto k) {
-      constexpr int kk = decltype(k)::value;
-      const double sc = (i == kk) ? invd[kk] : 1.0;
-      sfor<0, kk + 1>([&](auto j) {
-        constexpr int jj = decltype(j)::value;
-        X[jj] *= sc;
-      });
-      const double lik = (i > kk) ? Lr[kk] : 0.0;
-      sfor<0, kk + 1>([&](auto j) {
-        constexpr int jj = decltype(j)::value;
-        X[jj] = fma(-lik, bc<kk>(X[jj]), X[jj]);
-      });
-    });
+    bad |= chol_inv<n>(S, X, i);
     double Pc[PK ? 4 : 1];  // columns 4 qrow .. 4 qrow + 3 of P_t, row i
     if constexpr (WV) {
       // rows / columns 4 qrow .. 4 qrow + 3 of Linv_t, W_t and V_{t-1}
@@ -336,6 +357,379 @@ __device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, d
     }
   }
   return bad;
+}
+
+// ---------------------------------------------------------------------------
+// Chunked factorisation of long horizons (same outputs as factor_instance up
+// to rounding, two fifths of its serial depth).
+//
+// The recurrence above carries one n x n state from stage to stage: what
+// enters stage t is M_t (S_t = Theta_t - M_t M_t').  The horizon is cut into
+// five contiguous chunks c = 0..4, chunk c covering stages a_c .. b_c.
+//
+// Phase 1, one chunk per 16-lane row: row 0 factors chunk 0 exactly and
+// stores its blocks.  Row c = 1..3 summarises chunk c as a function of its
+// entering state.  With T the block-tridiagonal matrix of the chunk's
+// interior a_c .. b_c - 1 (no entering term), factored by the same recurrence
+// started from M = 0 (T = L0 L0'), the entering state Z = M M' (M = M_{a_c})
+// changes the interior to T - E Z E' (E: the block column of stage a_c), and
+// the Woodbury identity gives the Schur complement at b_c
+//   S_b = S0_b - K_ba M (I - M' K_aa M)^{-1} M' K_ba',
+// where S0_b is its value for Z = 0, K_aa = E' T^{-1} E and
+// K_ba = Phi_{b-1} (T^{-1})_{b-1,a}.  With U = L0^{-1} E, formed block by
+// block as U_a = L0_a^{-1}, U_t = -W0_t U_{t-1} (W0_t = L0_t^{-1} M0_t), these
+// are K_aa = sum_t U_t' U_t and K_ba = M0_b U_{b-1}.  I - M' K_aa M is SPD
+// because T - E Z E' is (a Schur complement of the SPD Schur matrix).
+// Phase 2, on every row, serially over c = 1..3: from M_{a_1} (row 0's exit)
+// the summaries give M_{a_2}, M_{a_3}, M_{a_4}, and L_{b_c}^{-1}, which the
+// first stage of the next chunk needs for its V block.
+// Phase 3, one chunk per row: rows 1..3 re-run chunks 1..3 and row 0 runs
+// chunk 4, each from its true entering state, storing their blocks.  Every
+// row forms and stores all n columns of its outputs.
+//
+// Scratch: L.FacX, [B][FX_SLOTS][n][n] FP64 per instance.
+// ---------------------------------------------------------------------------
+struct FacChunk {
+  int a, len;  // first stage and stage count
+};
+__device__ __forceinline__ FacChunk fac_chunk(int c, int N) {
+  const int S = N + 1, base = S / 5, rem = S % 5;
+  return FacChunk{c * base + min(c, rem), base + (c < rem ? 1 : 0)};
+}
+// shortest horizon factored in chunks (every chunk then holds at least three
+// stages, so every summarised chunk has an interior)
+constexpr int FAC_CHUNK_MIN_N = 15;
+// FacX slots: M_{a_1} and L_{b_0}^{-1} from row 0; per summarised chunk
+// c = 1..3 the four blocks S0_b, K_aa, K_ba, Phi_b at FX_SUM + 4 (c - 1)
+enum { FX_M1 = 0, FX_X0 = 1, FX_SUM = 2, FX_SLOTS = 14 };
+
+template <typename T, int NX, int NU, int NG, bool HOIST, int FORM, int TAG = 0>
+__device__ __noinline__ int factor_chunked(const Layout& Lm, const Group& gm, double sigma_, double rho_f_,
+                                           double rho_g_, const double* __restrict__ rhog_rows_) {
+  const Layout L = uni(Lm);
+  const Group g{gm.lane, uni(gm.b), uni(gm.s0), uni(gm.N)};
+  const double sigma = uni(sigma_), rho_f = uni(rho_f_), rho_g = uni(rho_g_);
+  const double* __restrict__ rhog_rows = uni(rhog_rows_);
+  constexpr bool WV = FORM == FACTOR_WV;
+  constexpr bool PK = FORM == FACTOR_PK;
+  constexpr int n = NX + NU;
+  const int i = g.lane;
+  const int q = (int)(threadIdx.x >> 4);
+  const bool vi = i < n;
+  const int ic = vi ? i : n - 1;
+  const int N = g.N;
+  const size_t nn = (size_t)n * n;
+  double* const FX = L.FacX + (size_t)g.b * FX_SLOTS * nn;
+
+  // rho-independent products (row i), formed once when the blocks do not vary
+  double PAm[HOIST ? n : 1], PAp[HOIST ? n : 1], PG[HOIST ? n : 1], PPhi[HOIST ? n : 1];
+  double Dint[HOIST ? n : 1], Dter[HOIST ? n : 1], Erow[HOIST ? n : 1], GcH[HOIST ? NG : 1];
+  if constexpr (HOIST) {
+    const size_t b = (size_t)g.b;
+    load_row<n>(Dint, L.D + (2 * b) * nn + (size_t)ic * n, true);
+    load_row<n>(Dter, L.D + (2 * b + 1) * nn + (size_t)ic * n, true);
+    if (L.E)
+      load_row<n>(Erow, L.E + b * nn + (size_t)ic * n, true);
+    else
+#pragma unroll
+      for (int k = 0; k < n; ++k) Erow[k] = 0.0;
+    double Amc[NX], Apc[NX];
+    load_col<NX>(Amc, L.Am + b * NX * n + ic, n, true);
+    load_col<NX>(Apc, L.Ap + b * NX * n + ic, n, true);
+    load_col<NG>(GcH, L.G + b * NG * n + ic, n, true);
+#pragma unroll
+    for (int k = 0; k < n; ++k) PAm[k] = PAp[k] = PG[k] = PPhi[k] = 0.0;
+    cross_row<NX, n>(Amc, Amc, PAm, 1.0);
+    cross_row<NX, n>(Apc, Apc, PAp, 1.0);
+    cross_row<NX, n>(Apc, Amc, PPhi, 1.0);
+    if (!rhog_rows) cross_row<NG, n>(GcH, GcH, PG, rho_g);
+  }
+  FacStage<NX, NU, NG> cur, nxt;
+  double ApcPrev[NX];  // column i of A_{t-1}^+ (time-varying data)
+
+  // row i of Theta_t (no entering term)
+  auto theta = [&](int t, int64_t s, double (&S)[n]) {
+    if constexpr (HOIST) {
+#pragma unroll
+      for (int k = 0; k < n; ++k) S[k] = (t == N) ? Dter[k] : Dint[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < n; ++k) S[k] = cur.D[k];
+    }
+    sfor<0, n>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      if (i == jj) S[jj] += sigma + ((t == 0 && jj < NX) ? rho_f : 0.0);
+    });
+    if constexpr (HOIST) {
+      const double ca = (t < N) ? rho_f : 0.0, cp = (t > 0) ? rho_f : 0.0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) S[k] += ca * PAm[k] + cp * PAp[k] + PG[k];
+      if (rhog_rows) {
+        double Gw[NG];
+#pragma unroll
+        for (int r = 0; r < NG; ++r) Gw[r] = as_global(rhog_rows)[(size_t)s * ROW + r] * GcH[r];
+        cross_row<NG, n>(Gw, GcH, S, 1.0);
+      }
+    } else {
+      if (t < N) cross_row<NX, n>(cur.Amc, cur.Amc, S, rho_f);
+      if (t > 0) cross_row<NX, n>(ApcPrev, ApcPrev, S, rho_f);
+      double Gw[NG];
+#pragma unroll
+      for (int r = 0; r < NG; ++r) Gw[r] = cur.w[r] * cur.Gc[r];
+      cross_row<NG, n>(Gw, cur.Gc, S, 1.0);
+    }
+  };
+  // row i of Phi_t = E_t + rho_f A_t^+' A_t^-  (t < N)
+  auto phi = [&](double (&Phi)[n]) {
+    if constexpr (HOIST) {
+#pragma unroll
+      for (int k = 0; k < n; ++k) Phi[k] = Erow[k] + rho_f * PPhi[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < n; ++k) Phi[k] = cur.E[k];
+      cross_row<NX, n>(cur.Apc, cur.Amc, Phi, rho_f);
+    }
+  };
+  auto store_row = [&](int slot, const double (&r)[n]) {
+    if (vi) {
+      double* dst = FX + (size_t)slot * nn + (size_t)i * n;
+#pragma unroll
+      for (int j = 0; j < n; ++j) dst[j] = r[j];
+    }
+  };
+
+  int bad = 0;
+  // One pass of the recurrence over chunk `ch` on this row.  SUM: phase 1
+  // (rows 1..3 summarise; the entering state is zero).  kmax: the longest
+  // chunk of the pass (rows whose chunk is shorter idle).
+  double Mrow[n], Xprev[n], UT[n], Kaa[n];
+  auto sweep = [&](auto sum_tag, const FacChunk ch, const bool store, const int kmax) {
+    constexpr bool SUM = decltype(sum_tag)::value;
+    const bool summ = SUM && q > 0;
+    if constexpr (!HOIST) {
+      load_fac(cur, L, g, ch.a, rho_g, rhog_rows);
+      const int64_t sp = g.s0 + (ch.a > 0 ? ch.a - 1 : 0);
+      load_col<NX>(ApcPrev, L.Ap + ti_or_tv(L.ti, g.b, sp, (size_t)NX * n) + ic, n, ch.a > 0);
+    }
+    for (int k = 0; k < kmax; ++k) {
+      if (k >= ch.len) continue;  // the same on all lanes of a row
+      const int t = ch.a + k;
+      const int64_t s = g.s0 + t;
+      if constexpr (!HOIST) {
+        if (t < N) load_fac(nxt, L, g, t + 1, rho_g, rhog_rows);  // prefetch
+      }
+      double S[n];
+      theta(t, s, S);
+      if (!SUM || k > 0) cross_row<n, n>(Mrow, Mrow, S, -1.0);
+      if (summ && k == ch.len - 1) {
+        // exit stage b of a summarised chunk: S0_b, K_ba = M0_b U_{b-1}, Phi_b
+        double Kba[n], Phi[n];
+#pragma unroll
+        for (int j = 0; j < n; ++j) Kba[j] = 0.0;
+        cross_row<n, n>(Mrow, UT, Kba, 1.0);
+        phi(Phi);
+        const int base = FX_SUM + 4 * (q - 1);
+        store_row(base + 0, S);
+        store_row(base + 1, Kaa);
+        store_row(base + 2, Kba);
+        store_row(base + 3, Phi);
+        continue;
+      }
+      double X[n];
+      const int bk = chol_inv<n>(S, X, i);
+      bad |= bk;
+      // W_t = Linv_t M_t (row i, every column; zero where M_t = 0)
+      double W[n];
+      sfor<0, n>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        W[jj] = dotb<n>(X, Mrow[jj], 0.0);
+      });
+      if (summ) {
+        // U_t' rows: U_a' = Linv_a', U_t' = -U_{t-1}' W_t'; K_aa += U_t' U_t
+        double Un[n];
+#pragma unroll
+        for (int j = 0; j < n; ++j) Un[j] = 0.0;
+        if (k == 0)
+          cross_row<n, n>(UT, X, Un, 1.0);
+        else
+          cross_row<n, n>(UT, W, Un, -1.0);
+#pragma unroll
+        for (int j = 0; j < n; ++j) UT[j] = Un[j];
+        cross_row<n, n>(UT, UT, Kaa, 1.0);
+      }
+      double Phi[n];
+      if (t < N) phi(Phi);
+      if (store) {
+        if constexpr (WV) {
+          // Linv_t (rows and columns), W_t, and V_{t-1} = (M_t Linv_{t-1})'
+          double V[n];
+          sfor<0, n>([&](auto j) {
+            constexpr int jj = decltype(j)::value;
+            V[jj] = dotb<n>(Mrow, Xprev[jj], 0.0);
+          });
+          if (vi) {
+            const gptr<T> lr = as_global((T*)L.SubA + (size_t)s * nn + (size_t)i * n);
+            const gptr<T> lc = as_global((T*)L.SubB + (size_t)s * nn + i);
+#pragma unroll
+            for (int j = 0; j < n; ++j) {
+              lr[j] = T(X[j]);
+              lc[(size_t)j * n] = T(X[j]);
+            }
+            if (t > 0) {
+              const gptr<T> wr = as_global((T*)L.ChF + (size_t)s * nn + (size_t)i * n);
+              const gptr<T> vc = as_global((T*)L.ChB + (size_t)(s - 1) * nn + i);
+#pragma unroll
+              for (int j = 0; j < n; ++j) {
+                wr[j] = T(W[j]);
+                vc[(size_t)j * n] = T(V[j]);
+              }
+            }
+          }
+        } else if constexpr (PK) {
+          // P_t = Linv_t' Linv_t; K_{t+1} = Phi_t P_t and Kb_t = K_{t+1}'
+          double XT[n], P[n], E1[n];
+#pragma unroll
+          for (int j = 0; j < n; ++j) {
+            XT[j] = 0.0;
+            E1[j] = (i == j) ? 1.0 : 0.0;
+          }
+          cross_row<n, n>(E1, X, XT, 1.0);
+          sfor<0, n>([&](auto j) {
+            constexpr int jj = decltype(j)::value;
+            P[jj] = dotb<n>(XT, X[jj], 0.0);
+          });
+          double K[n];
+          sfor<0, n>([&](auto j) {
+            constexpr int jj = decltype(j)::value;
+            K[jj] = dotb<n>(Phi, P[jj], 0.0);
+          });
+          if (vi) {
+            const gptr<T> pr = as_global((T*)L.SubB + (size_t)s * nn + (size_t)i * n);
+#pragma unroll
+            for (int j = 0; j < n; ++j) pr[j] = T(P[j]);
+            if (t < N) {
+              const gptr<T> kr = as_global((T*)L.ChF + (size_t)(s + 1) * nn + (size_t)i * n);
+              const gptr<T> kb = as_global((T*)L.ChB + (size_t)s * nn + i);
+#pragma unroll
+              for (int j = 0; j < n; ++j) {
+                kr[j] = T(K[j]);
+                kb[(size_t)j * n] = T(K[j]);
+              }
+            }
+          }
+        } else if (vi) {
+          const gptr<double> dst = as_global(L.Linv64 + (size_t)s * nn + (size_t)i * n);
+#pragma unroll
+          for (int j = 0; j < n; ++j) dst[j] = X[j];
+        }
+      }
+      if (t < N) {
+        // M_{t+1} row i: M[i][j] = sum_{k<=j} Phi[i][k] Linv[j][k]
+        sfor<0, n>([&](auto j) {
+          constexpr int jj = decltype(j)::value;
+          double acc = 0.0, xs[jj + 1], ps[jj + 1];
+#pragma unroll
+          for (int kk = 0; kk <= jj; ++kk) {
+            xs[kk] = X[kk];
+            ps[kk] = Phi[kk];
+          }
+          DotC<jj + 1, double>::template f<jj>(acc, xs, ps);
+          Mrow[jj] = acc;
+        });
+        if constexpr (FORM == FACTOR_M) {
+          if (store && vi) {
+            const gptr<double> dst = as_global(L.M64 + (size_t)(s + 1) * nn + (size_t)i * n);
+#pragma unroll
+            for (int j = 0; j < n; ++j) dst[j] = Mrow[j];
+          }
+        }
+        if constexpr (!HOIST) {
+#pragma unroll
+          for (int r = 0; r < NX; ++r) ApcPrev[r] = cur.Apc[r];
+          cur = nxt;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < n; ++j) Xprev[j] = X[j];
+    }
+  };
+
+  // phase 1
+#pragma unroll
+  for (int j = 0; j < n; ++j) {
+    Mrow[j] = 0.0;
+    Xprev[j] = 0.0;
+    UT[j] = (i == j) ? 1.0 : 0.0;
+    Kaa[j] = 0.0;
+  }
+  sweep(std::true_type{}, fac_chunk(q, N), q == 0, fac_chunk(0, N).len);
+  if (q == 0) {
+    store_row(FX_M1, Mrow);
+    store_row(FX_X0, Xprev);
+  }
+  __syncthreads();
+
+  // phase 2: entering states of chunks 2, 3, 4 (every row computes them all)
+  double M[n], Xb[n];
+  load_row<n>(M, FX + FX_M1 * nn + (size_t)ic * n, true);
+  load_row<n>(Xb, FX + FX_X0 * nn + (size_t)ic * n, true);
+#pragma unroll
+  for (int j = 0; j < n; ++j) {
+    Mrow[j] = M[j];
+    Xprev[j] = Xb[j];
+  }
+  for (int c = 1; c <= 3; ++c) {
+    double S0[n], Ka[n], Kb[n], Ph[n];
+    const size_t base = (size_t)(FX_SUM + 4 * (c - 1)) * nn + (size_t)ic * n;
+    load_row<n>(S0, FX + base, true);
+    load_row<n>(Ka, FX + base + nn, true);
+    load_row<n>(Kb, FX + base + 2 * nn, true);
+    load_row<n>(Ph, FX + base + 3 * nn, true);
+    // R = I - M' K_aa M = C C'
+    double MT[n], E1[n], Y[n], R[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      MT[j] = 0.0;
+      E1[j] = (i == j) ? 1.0 : 0.0;
+    }
+    cross_row<n, n>(E1, M, MT, 1.0);  // row i of M'
+    sfor<0, n>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      Y[jj] = dotb<n>(Ka, M[jj], 0.0);  // K_aa M
+    });
+    sfor<0, n>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      R[jj] = E1[jj] - dotb<n>(MT, Y[jj], 0.0);
+    });
+    double Ci[n];
+    bad |= chol_inv<n>(R, Ci, i);
+    // P = K_ba M C^{-T};  S_b = S0_b - P P'
+    double KM[n], P[n];
+    sfor<0, n>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      KM[jj] = dotb<n>(Kb, M[jj], 0.0);
+      P[jj] = 0.0;
+    });
+    cross_row<n, n>(KM, Ci, P, 1.0);
+    cross_row<n, n>(P, P, S0, -1.0);
+    bad |= chol_inv<n>(S0, Xb, i);
+    // M_{a_{c+1}} = Phi_b L_b^{-T}
+#pragma unroll
+    for (int j = 0; j < n; ++j) M[j] = 0.0;
+    cross_row<n, n>(Ph, Xb, M, 1.0);
+    const bool take = (q == c + 1) || (c == 3 && q == 0);
+    if (take) {
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        Mrow[j] = M[j];
+        Xprev[j] = Xb[j];
+      }
+    }
+  }
+
+  // phase 3
+  sweep(std::false_type{}, fac_chunk(q == 0 ? 4 : q, N), true, fac_chunk(1, N).len);
+  return __ballot(bad != 0) != 0ull ? 1 : 0;
 }
 
 }  // namespace ocpk

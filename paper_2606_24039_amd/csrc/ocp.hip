@@ -171,6 +171,7 @@ struct ocp_handle_s {
   double *Linv64 = nullptr, *M64 = nullptr;
   void *SubA = nullptr, *SubB = nullptr, *ChF = nullptr, *ChB = nullptr;
   void *SegT = nullptr, *SegU = nullptr, *SegX = nullptr;
+  double* FacX = nullptr;
   int variant = 0;
   int seg_min_n = SEG_MIN_N;  // launch shape: horizons from which the substitutions run segmented
   int8_t gsel[16] = {0}, ginv[16] = {0};
@@ -304,6 +305,7 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   A_(h->SegT, ts * nn * 4 * (size_t)B);
   A_(h->SegU, ts * nn * 4 * (size_t)B);
   A_(h->SegX, ts * ROW * 8 * (size_t)B);
+  A_(h->FacX, sizeof(double) * nn * FX_SLOTS * (size_t)B);
   A_(h->x, ts * ROW * SP);
   A_(h->v, ts * ROW * SP);
   A_(h->yf, ts * ROW * SP);
@@ -455,6 +457,7 @@ Layout make_layout(ocp_handle h) {
   L.SegT = h->SegT;
   L.SegU = h->SegU;
   L.SegX = h->SegX;
+  L.FacX = h->FacX;
   for (int k = 0; k < 16; ++k) {
     L.gsel[k] = h->gsel[k];
     L.ginv[k] = h->ginv[k];

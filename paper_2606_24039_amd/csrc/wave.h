@@ -1318,8 +1318,12 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
   for (;;) {
     if (need) {  // the only call site of the factorisation
       constexpr int FORM = sizeof(T) == 4 ? FACTOR_WV : FACTOR_PK;
-      const int bad = factor_instance<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
-                                                                   rho_bar, nullptr, w.row);
+      // long horizons: the chunked factorisation (same blocks, shorter serial depth)
+      const bool chunked = w.N >= st.seg_min_n && w.N >= FAC_CHUNK_MIN_N;
+      const int bad = chunked ? factor_chunked<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
+                                                                            rho_bar, nullptr)
+                              : factor_instance<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
+                                                                             rho_bar, nullptr, w.row);
       wave_sync();
       if (bad) {
         status = 3;
