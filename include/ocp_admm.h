@@ -254,9 +254,14 @@ ocp_status ocp_graph_launch(ocp_handle h, void* stream);
  * (interleaved iteration) for short horizons and, for horizons
  * N >= seg_min_n, segmented: the horizon is cut into four segments whose
  * chains run side by side from a zero start and are joined through the
- * segments' transfer blocks, formed after each factorisation.  Both solve the
- * same system; results agree up to rounding.  The default switch is
- * N >= 128.
+ * segments' transfer blocks, formed after each factorisation.  The same
+ * switch selects the chunked block Cholesky (Appendix "ADMM", Schur
+ * complement) for the solve's and the adjoint's factorisations: five chunks,
+ * three of them first reduced to their map from the entering Schur state
+ * (Woodbury identity), so that every chunk is factored from its true entering
+ * state in two passes whose serial depth is two fifths of the horizon.  Both
+ * launch shapes solve the same system with the same blocks; results agree up
+ * to rounding.  The default switch is N >= 128.
  *
  * ocp_set_segmented: set the switch for later solves on this handle (values
  * below 15 are raised to 15: segments of at least four stages; INT32_MAX

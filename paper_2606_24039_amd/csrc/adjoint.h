@@ -36,6 +36,7 @@ struct AdjArgs {
   const double* dLdx;  // [S][n]
   double sigma_b, rho_b, eps_active;
   int sweeps;
+  int chunk_min_n;  // horizons from which the factorisation runs chunked
   // scratch, FP64 padded [S][ROW] (v carries STAGE_PAD padding stages)
   double* w;    // inequality-row weights (rho_b on active rows)
   double* ex;   // eta_x
@@ -361,8 +362,14 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   LF.SubB = a.P;
   LF.ChF = a.K;
   LF.ChB = a.Kb;
-  const int bad = L.ti ? factor_instance<double, NX, NU, NG, true, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q)
-                       : factor_instance<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
+  const bool chunked = g.N >= a.chunk_min_n && g.N >= FAC_CHUNK_MIN_N;
+  int bad;
+  if (L.ti)
+    bad = chunked ? factor_chunked<double, NX, NU, NG, true, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w)
+                  : factor_instance<double, NX, NU, NG, true, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
+  else
+    bad = chunked ? factor_chunked<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w)
+                  : factor_instance<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
   wave_sync();
 
   // ---- refinement sweeps ----

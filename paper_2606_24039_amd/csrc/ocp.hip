@@ -882,6 +882,7 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   a.rho_b = s->adj_rho;
   a.eps_active = s->eps_active;
   a.sweeps = s->refine_sweeps;
+  a.chunk_min_n = h->seg_min_n;
   a.w = h->adj_rhog;
   a.ex = h->adj_ex;
   a.ef = h->adj_ey;

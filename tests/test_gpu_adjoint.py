@@ -37,10 +37,14 @@ def _loss_grad(solver, x, nx):
     return g
 
 
+@pytest.mark.parametrize("seg", [None, 15], ids=["stagewise", "chunked"])
 @pytest.mark.parametrize("precision", [FP64, MIXED])
-def test_adjoint_matches_oracle_dense_solve(precision):
+def test_adjoint_matches_oracle_dense_solve(precision, seg):
+    """seg = 15: the solve and the adjoint factor N = 64 in chunks (segmented substitutions)."""
     b = random_lti(8, N=64, seed=4)
     s = lti_solver(b, precision)
+    if seg is not None:
+        s.set_segmented(seg)
     eps = 1e-9 if precision == FP64 else 1e-6
     out = s.solve(_settings(eps_abs=eps, eps_rel=eps, max_admm=5000))
     g = s.adjoint(_loss_grad(s, out["x"], b.nx), _settings(eps_active=1e-6))
