@@ -722,6 +722,16 @@ __device__ __forceinline__ T seg_link(T pe, int dir, gptr<T> X, gptr<const T> TU
   return in;
 }
 
+// Prefetch distance of the segmented sweeps, in steps.  FP32 iterations of
+// small stages (n <= 8) keep four steps in flight (measured: 9-11 % off the
+// long and ragged bicycle solves against two); deeper buffers, or four in
+// FP64, overflow the register budget into scratch memory and run slower.
+// Loads reach at most SEG_AHEAD + 1 stages past either end of the horizon,
+// inside the STAGE_PAD padding stages.
+template <typename T, int n>
+constexpr int SEG_AHEAD = (sizeof(T) == 4 && n <= 8) ? 4 : 2;
+static_assert(SEG_AHEAD<float, 6> + 1 <= STAGE_PAD, "segmented prefetch beyond the padding stages");
+
 // inputs of one stage of the segmented forward sweep
 template <typename T, int NX, int NU, int NG, bool TI>
 struct SegFwdIn {
@@ -783,7 +793,7 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
       sto(P.v, ov(t), r);
       p = r - dotb<n>(d.Cr, p, T(0));  // p = 0 before the quarter's first stage
     };
-    seg_walk<2, In>(steps, load, comp);
+    seg_walk<SEG_AHEAD<T, n>, In>(steps, load, comp);
     pe = p;
   }
   const T vin = seg_link<T, n>(pe, 0, X, Tq, q, i);
@@ -807,7 +817,7 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
       v = d.r - dotb<n>(d.Cr, v, T(0));
       sto(P.v, ov(t), dotb<n>(d.Br, v, T(0)));
     };
-    seg_walk<2, In>(steps, load, comp);
+    seg_walk<SEG_AHEAD<T, n>, In>(steps, load, comp);
   }
   wave_sync();
 
@@ -827,7 +837,7 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
       if (k >= sg.len) return;
       p = d.s - dotb<n>(d.Cr, p, T(0));  // p = 0 past the quarter's last stage
     };
-    seg_walk<2, In>(steps, load, comp);
+    seg_walk<SEG_AHEAD<T, n>, In>(steps, load, comp);
     pe = p;
   }
   const T xin = seg_link<T, n>(pe, 1, X, Uq, q, i);
@@ -870,7 +880,7 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
       if (t == 0 && i < NX) sto(P.yf, ov(N), c.yinit + c.rfa * (xt - c.xinit));
       xn = xt;
     };
-    seg_walk<2, In>(steps, load, comp);
+    seg_walk<SEG_AHEAD<T, n>, In>(steps, load, comp);
   }
   wave_sync();
 }
