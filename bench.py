@@ -34,7 +34,7 @@ PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E (published)
 # reads 0.500 of the copied bytes, WRITE_SIZE 1.000).  Summary and commands:
 # profiles/admm_solve_wave_lti1024_n50.md.  Keyed by (workload, precision);
 # valid for the kernel as profiled -- set to None when the kernel changes.
-TRAFFIC_BYTES = {("c2", "mixed"): (23622934.1 * 1.99994 + 2114126.3 * 1.0) * 1024}
+TRAFFIC_BYTES = {("c2", "mixed"): (23642190.2 * 1.99994 + 2015575.9 * 1.0) * 1024}
 
 
 def log(*a):
