@@ -199,12 +199,87 @@ def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True):
     return res
 
 
+def run_bicycle(batch, precision, steps, warmup, settings_kw, grad=True):
+    """Timed SQP solves (+ the adjoint of the last QP) of a kinematic-bicycle batch."""
+    import torch
+
+    from paper_2606_24039_amd import _abi as A
+    from paper_2606_24039_amd.solver import OCPSolver
+
+    s = OCPSolver(4, 2, 3, batch.horizons, model=A.MODEL_BICYCLE, precision=precision)
+    s.set_bicycle(batch)
+    st = A.default_settings(**settings_kw)
+    out = s.alloc_solution()
+    grads = s.alloc_grads()
+    gstruct = s.grads_struct(grads)
+    dl = torch.as_tensor(np.random.default_rng(11).standard_normal((s.S, 6)), dtype=torch.float64, device="cuda")
+
+    def step():
+        s.solve(st, out=out, sync=False)
+        if grad:
+            s.adjoint_raw(st, dl, gstruct)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    s.profile(True)
+    s.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = s.profile_read()
+    s.profile(False)
+    kkt = out["sqp_kkt"].cpu().numpy()
+    res = {"ms_per_step": wall / steps * 1e3,
+           "kernel_ms_per_step": {k: round(ms / steps, 4) for k, (ms, c) in kt.items()},
+           "sqp_kkt_max": [float(v) for v in np.nanmax(kkt, axis=0)],
+           "grad_finite": bool(torch.isfinite(grads["eta_x"]).all().item()) if grad else None}
+    s.close()
+    return res
+
+
+def bench_bicycle(args):
+    """Long-horizon workloads (kinematic bicycle, implicit midpoint, 10 SQP x
+    50 ADMM iterations with fixed counts, forward + adjoint): `c5a` one
+    instance of N = 8192, `c5b` 256 instances of N ~ U{32..2048}."""
+    from workloads import bicycle_long_and_ragged
+
+    lng, rag = bicycle_long_and_ragged(seed=5)
+    batch = lng if args.workload == "c5a" else rag
+    desc = ("kinematic bicycle, one instance N=8192" if args.workload == "c5a"
+            else "kinematic bicycle, 256 instances N~U{32..2048}")
+    kw = dict(max_sqp=10, max_admm=50, k_check=0, k_rho=25, fixed_sqp=1)
+    steps, warmup = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
+    log(f"[bench] workload: {desc}")
+    mixed = run_bicycle(batch, 1, steps, warmup, kw, grad=not args.no_grad)
+    out = {"metric": "SQP solves/s (10 SQP x 50 ADMM iterations, fixed counts), FP32 ADMM iterations + FP64 "
+                     "factorisation" + ("" if args.no_grad else ", + adjoint of the last QP"),
+           "value": round(batch.batch / (mixed["ms_per_step"] * 1e-3), 4), "unit": "SQP solves/s", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": round(mixed["ms_per_step"], 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": desc, "batch": int(batch.batch), "stages": int(np.sum(batch.horizons + 1)),
+                      "nx": 4, "nu": 2, "ng": 3, "grad": not args.no_grad,
+                      "parallelism": "single GPU, one wavefront per instance"},
+           "kernel_ms_per_step": mixed["kernel_ms_per_step"], "sqp_kkt_max": mixed["sqp_kkt_max"],
+           "roofline": None, "cpu_baseline": None}
+    if not args.no_fp64:
+        fp64 = run_bicycle(batch, 0, steps, 1, kw, grad=not args.no_grad)
+        out["fp64"] = {"ms_per_step": round(fp64["ms_per_step"], 3), "kernel_ms_per_step": fp64["kernel_ms_per_step"],
+                       "sqp_kkt_max": fp64["sqp_kkt_max"]}
+        out["speedup_vs_fp64"] = round(fp64["ms_per_step"] / mixed["ms_per_step"], 3)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c5a", "c5b"],
+                    help="c2: the batched linear MPC benchmark; c5a / c5b: the long / ragged bicycle horizons")
     ap.add_argument("--cpu-sample", type=int, default=256, help="instances timed on the oracle (0 = skip)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison")
     ap.add_argument("--no-grad", action="store_true", help="forward solves only (no adjoint in the step)")
@@ -228,6 +303,9 @@ def main():
                                    "cross-GPU exchange; run one process per GPU on disjoint instance shards"}))
         sys.exit(2)
 
+    if args.workload in ("c5a", "c5b"):
+        bench_bicycle(args)
+        return
     batch, desc = make_workload(args.workload)
     settings_kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_admm=1000, k_check=25, k_rho=25)
     f_it, f_fac = lti_flops_per_stage(batch.nx, batch.nu, batch.ng)
