@@ -333,17 +333,23 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
       }
     }
   }
-  // take the step (lane k updates component k of every stage)
-  for (int t = 0; t <= N; ++t) {
-    const int64_t s = s0 + t;
-    const size_t sv = (size_t)s * ROW + lane;
-    if (lane < 6) a.xbar[sv] += alpha * (double(XS[sv]) - a.xbar[sv]);
-    if (lane < 3) {
-      a.xibar[sv] += alpha * (double(XIS[sv]) - a.xibar[sv]);
-      a.ygbar[sv] += alpha * (double(YGS[sv]) - a.ygbar[sv]);
+  // take the step (lane i updates the stages t = i, i+16, ...)
+  for (int t = lane; t <= N; t += ROW) {
+    const size_t sv = (size_t)(s0 + t) * ROW;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.xbar[sv + k] += alpha * (double(XS[sv + k]) - a.xbar[sv + k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a.xibar[sv + k] += alpha * (double(XIS[sv + k]) - a.xibar[sv + k]);
+      a.ygbar[sv + k] += alpha * (double(YGS[sv + k]) - a.ygbar[sv + k]);
     }
-    if (lane < 4) a.yfbar[sv] += alpha * (double(YFS[sv]) - a.yfbar[sv]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.yfbar[sv + k] += alpha * (double(YFS[sv + k]) - a.yfbar[sv + k]);
   }
+  // the stopping quantities read the neighbouring stages other lanes wrote
+  // (one wavefront per workgroup: rows that returned early are masked lanes
+  // of the same wave, which still reaches the barrier)
+  __syncthreads();
   // stopping quantities (eq. sqp_stop) at the new iterate
   double st = 0.0, fe = 0.0, gi = 0.0;
   for (int t = lane; t <= N; t += ROW) {
