@@ -228,13 +228,29 @@ __device__ __forceinline__ void bike_point(const BikeArgs& a, const double* xb, 
   for (int k = 0; k < 6; ++k) z[k] = xb[k] + al * dx[k];
 }
 
-// Line search and SQP bookkeeping for one instance per 16-lane row.  Lane i
-// handles the stages t = i, i+16, ...; per-candidate sums use row reductions.
+// sum / max over the wavefront (every lane receives the result; fixed order)
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row_sum(v);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  v = row_max(v);
+  v = fmax(v, __shfl_xor(v, 16));
+  v = fmax(v, __shfl_xor(v, 32));
+  return v;
+}
+
+// Line search and SQP bookkeeping, one wavefront per instance.  Lane i
+// handles the stages t = i, i+64, ...; per-candidate sums are wavefront
+// reductions.
 template <typename T>
 __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs a) {
   constexpr int NA = 8;  // alpha in {1, 1/2, ..., 1/128}
-  const int lane = threadIdx.x & (ROW - 1);
-  const int slot = row_slot();
+  constexpr int WL = 64;  // lanes per instance
+  const int lane = threadIdx.x;
+  const int slot = blockIdx.x;
   if (slot >= L.B) return;
   const int b = L.order ? L.order[slot] : slot;
   if (a.frozen[b]) return;
@@ -250,7 +266,7 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
 #pragma unroll
   for (int j = 0; j <= NA; ++j) cost[j] = viol[j] = 0.0;
   double gdir = 0.0;
-  for (int t = lane; t <= N; t += ROW) {
+  for (int t = lane; t <= N; t += WL) {
     const int64_t s = s0 + t;
     double xb[6], dx[6], xbn[6], dxn[6];
     const double xib = a.xibar[s * ROW + 2];
@@ -305,11 +321,11 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
       viol[j] += v;
     }
   }
-  gdir = row_sum(gdir);
+  gdir = wave_sum(gdir);
 #pragma unroll
   for (int j = 0; j <= NA; ++j) {
-    cost[j] = row_sum(cost[j]);
-    viol[j] = row_sum(viol[j]);
+    cost[j] = wave_sum(cost[j]);
+    viol[j] = wave_sum(viol[j]);
   }
   const double mu = fmax(fmax(a.mu[b], fabs(gdir) / (0.5 * fmax(viol[0], a.eps_c))), 1.0);
   const double dmu = gdir - mu * viol[0];
@@ -333,8 +349,8 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
       }
     }
   }
-  // take the step (lane i updates the stages t = i, i+16, ...)
-  for (int t = lane; t <= N; t += ROW) {
+  // take the step (lane i updates the stages t = i, i+64, ...)
+  for (int t = lane; t <= N; t += WL) {
     const size_t sv = (size_t)(s0 + t) * ROW;
 #pragma unroll
     for (int k = 0; k < 6; ++k) a.xbar[sv + k] += alpha * (double(XS[sv + k]) - a.xbar[sv + k]);
@@ -347,12 +363,10 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     for (int k = 0; k < 4; ++k) a.yfbar[sv + k] += alpha * (double(YFS[sv + k]) - a.yfbar[sv + k]);
   }
   // the stopping quantities read the neighbouring stages other lanes wrote
-  // (one wavefront per workgroup: rows that returned early are masked lanes
-  // of the same wave, which still reaches the barrier)
   __syncthreads();
   // stopping quantities (eq. sqp_stop) at the new iterate
   double st = 0.0, fe = 0.0, gi = 0.0;
-  for (int t = lane; t <= N; t += ROW) {
+  for (int t = lane; t <= N; t += WL) {
     const int64_t s = s0 + t;
     const double* xb = a.xbar + s * ROW;
     const double* W = (t == N) ? a.Qfd : a.Qd;
@@ -403,9 +417,9 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     gi = fmax(gi, fmax(fmax(g1 - a.d_b, -a.d_b - g1), 0.0));
     gi = fmax(gi, fmax(fmax(g2 - a.lat_b, -a.lat_b - g2), 0.0));
   }
-  st = row_max(st);
-  fe = row_max(fe);
-  gi = row_max(gi);
+  st = wave_max(st);
+  fe = wave_max(fe);
+  gi = wave_max(gi);
   if (lane == 0) {
     a.mu[b] = mu;
     a.kkt[(size_t)b * 3 + 0] = st;

@@ -617,7 +617,6 @@ ocp_status bicycle_sqp(ocp_handle h, const ocp_settings* s, hipStream_t st) {
   const Layout L = make_layout(h);
   const int64_t S = h->S;
   const unsigned gs = (unsigned)((std::max<int64_t>(S, h->B) + 255) / 256);
-  const int grid = (h->B + kRowsPerWave - 1) / kRowsPerWave;
   Prof* pf = &h->prof;
   if (!(s->warm_start && h->solved))
     timed(pf, OCP_K_OTHER, st,
@@ -633,9 +632,9 @@ ocp_status bicycle_sqp(ocp_handle h, const ocp_settings* s, hipStream_t st) {
     run_admm(h, ad, st);
     timed(pf, OCP_K_SQP, st, [&] {
       if (h->mixed)
-        hipLaunchKernelGGL(bike_linesearch_kernel<float>, dim3(grid), dim3(16 * kRowsPerWave), 0, st, L, a);
+        hipLaunchKernelGGL(bike_linesearch_kernel<float>, dim3(h->B), dim3(64), 0, st, L, a);
       else
-        hipLaunchKernelGGL(bike_linesearch_kernel<double>, dim3(grid), dim3(16 * kRowsPerWave), 0, st, L, a);
+        hipLaunchKernelGGL(bike_linesearch_kernel<double>, dim3(h->B), dim3(64), 0, st, L, a);
     });
   }
   return hip_ok(hipGetLastError());
