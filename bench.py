@@ -241,15 +241,22 @@ def run_bicycle(batch, precision, steps, warmup, settings_kw, grad=True):
 
 
 def bench_bicycle(args):
-    """Long-horizon workloads (kinematic bicycle, implicit midpoint, 10 SQP x
-    50 ADMM iterations with fixed counts, forward + adjoint): `c5a` one
-    instance of N = 8192, `c5b` 256 instances of N ~ U{32..2048}."""
+    """Kinematic-bicycle workloads (implicit midpoint, 10 SQP x 50 ADMM
+    iterations with fixed counts, forward + adjoint): `c3` 4096 instances of
+    N = 100, `c5a` one instance of N = 8192, `c5b` 256 instances of
+    N ~ U{32..2048}."""
     from workloads import bicycle_long_and_ragged
 
-    lng, rag = bicycle_long_and_ragged(seed=5)
-    batch = lng if args.workload == "c5a" else rag
-    desc = ("kinematic bicycle, one instance N=8192" if args.workload == "c5a"
-            else "kinematic bicycle, 256 instances N~U{32..2048}")
+    if args.workload == "c3":
+        from workloads import bicycle_batch
+
+        batch = bicycle_batch(4096, N=100, seed=3)
+        desc = "kinematic bicycle, 4096 instances N=100"
+    else:
+        lng, rag = bicycle_long_and_ragged(seed=5)
+        batch = lng if args.workload == "c5a" else rag
+        desc = ("kinematic bicycle, one instance N=8192" if args.workload == "c5a"
+                else "kinematic bicycle, 256 instances N~U{32..2048}")
     kw = dict(max_sqp=10, max_admm=50, k_check=0, k_rho=25, fixed_sqp=1)
     steps, warmup = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
     log(f"[bench] workload: {desc}")
@@ -278,8 +285,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c5a", "c5b"],
-                    help="c2: the batched linear MPC benchmark; c5a / c5b: the long / ragged bicycle horizons")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5a", "c5b"],
+                    help="c2: the batched linear MPC benchmark; c3: 4096 bicycle instances, N = 100; "
+                         "c5a / c5b: the long / ragged bicycle horizons")
     ap.add_argument("--cpu-sample", type=int, default=256, help="instances timed on the oracle (0 = skip)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison")
     ap.add_argument("--no-grad", action="store_true", help="forward solves only (no adjoint in the step)")
@@ -303,7 +311,7 @@ def main():
                                    "cross-GPU exchange; run one process per GPU on disjoint instance shards"}))
         sys.exit(2)
 
-    if args.workload in ("c5a", "c5b"):
+    if args.workload in ("c3", "c5a", "c5b"):
         bench_bicycle(args)
         return
     batch, desc = make_workload(args.workload)
