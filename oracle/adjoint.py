@@ -20,8 +20,14 @@ returns  dL/dtheta = -(dF/dtheta)' eta  (eq. loss_gradient):
 
 Soft rows: an L1 row whose slack is nonzero has the fixed multiplier
 -gamma1 sign(xi) and drops out of the system; an L1 row with xi = 0 is treated
-as a hard row.  L2-slack rows (eq. bwd:slack_reduced_system) are not handled
-here and raise.
+as a hard row.  An active L2-slack row (penalty gamma2/2 xi^2) keeps its slack
+through the eliminated slack stationarity gamma2 xi + y = 0, so its active
+equation reads G_i x - y_i / gamma2 = b_i (eq. bwd:kkt_active with the slack
+toggle on): K carries -1/gamma2 on that row's diagonal.  Eliminating those
+rows gives the reduced system of eq. bwd:slack_reduced_system,
+[[H + gamma2 G_S'G_S, J'], [J, 0]] with J = [C; hard active rows] and
+eta_y = gamma2 G_S eta_x on the slack rows (no loss term on xi), which is the
+form the regularised refinement below (the GPU scheme) solves.
 
 Parity: the dense direct solve is the definition; pinned by central finite
 differences of polished solutions and by the closed-form LQR gradient
@@ -60,8 +66,6 @@ def active_set(qp: StageQP, x, y_g, xi=None, eps_g=None, eps_solve=1e-4):
         drop = (kind == SOFT_L1) & (np.asarray(xi) != 0.0)
         lower &= ~drop
         upper &= ~drop
-    if np.any(kind == SOFT_L2):
-        raise NotImplementedError("L2-slack rows need the reduced slack adjoint system")
     return lower, upper
 
 
@@ -69,8 +73,12 @@ def _kkt(qp: StageQP, lower, upper, H=None):
     P, C, G, q, c, lo, hi = qp.matrices()
     H = P if H is None else H
     act = lower | upper
-    GA = G[np.flatnonzero(act)]
-    K = sp.bmat([[H, C.T, GA.T], [C, None, None], [GA, None, None]], format="csc")
+    idx = np.flatnonzero(act)
+    GA = G[idx]
+    # active L2-slack rows: G_i x - y_i / gamma2 = b_i
+    dA = np.where(qp.soft_rows()[idx] == SOFT_L2, 1.0 / qp.gamma2, 0.0)
+    D = -sp.diags(dA) if np.any(dA) else None
+    K = sp.bmat([[H, C.T, GA.T], [C, None, None], [GA, None, D]], format="csc")
     bA = np.where(lower, lo, hi)[act]
     return K, P, C, G, q, c, GA, bA, act
 
@@ -101,6 +109,8 @@ def polish(qp: StageQP, x, y_g, xi=None, eps_solve=1e-4, tol=1e-9):
     if xi is not None:
         sel = (kind == SOFT_L1) & (np.asarray(xi) != 0.0)
         xis[sel] = np.clip(g[sel], lo[sel], hi[sel]) - g[sel]
+    l2 = (kind == SOFT_L2) & act
+    xis[l2] = -yg[l2] / qp.gamma2  # slack stationarity gamma2 xi + y = 0
     gx = g + xis
     feas = np.all(gx >= lo - tol * np.maximum(1, np.abs(lo))) and np.all(gx <= hi + tol * np.maximum(1, np.abs(hi)))
     signs = np.all(yg[lower] <= tol) and np.all(yg[upper] >= -tol)
@@ -121,7 +131,9 @@ def adjoint_dense(qp: StageQP, x, dL_dx, lower, upper, H=None):
 
 def adjoint_refined(qp: StageQP, x, dL_dx, lower, upper, sigma_b=1e-9, rho_b=1e6, sweeps=4, H=None):
     """Same eta by iterative refinement on K with the regularised matrix
-    K_reg = [[H + sigma_b I, J'], [J, -rho_b^{-1} I]], J = [C; G_A]:
+    K_reg = [[H + sigma_b I, J'], [J, -rho_b^{-1} I]], J = [C; G_A] (active
+    L2-slack rows leave J and add gamma2 G_S'G_S to H, their eta_y recovered
+    as gamma2 G_S eta_x: eq. bwd:slack_reduced_system):
     e <- e + K_reg^{-1} (r - K e).  Each K_reg solve is one Schur step
     (H + sigma_b I + rho_b J'J) e_x = r_x + rho_b J' r_y, e_y = rho_b (J e_x - r_y).
     Written with dense NumPy algebra (the oracle's plain form of the GPU scheme).
@@ -129,9 +141,12 @@ def adjoint_refined(qp: StageQP, x, dL_dx, lower, upper, sigma_b=1e-9, rho_b=1e6
     P, C, G, q, c, lo, hi = qp.matrices()
     H = P if H is None else H
     act = lower | upper
-    J = sp.vstack([C, G[np.flatnonzero(act)]]).tocsr()
+    l2 = act & (qp.soft_rows() == SOFT_L2)  # slack rows: in H (eq. bwd:slack_reduced_system)
+    hard = act & ~l2
+    J = sp.vstack([C, G[np.flatnonzero(hard)]]).tocsr()
     nv = qp.nvar
-    Hd = H.toarray()
+    Gs = G[np.flatnonzero(l2)].toarray() if sp.issparse(G) else np.asarray(G)[np.flatnonzero(l2)]
+    Hd = H.toarray() + qp.gamma2 * Gs.T @ Gs
     Jd = J.toarray()
     S = Hd + sigma_b * np.eye(nv) + rho_b * Jd.T @ Jd
     Lc = np.linalg.cholesky(S)
@@ -151,7 +166,8 @@ def adjoint_refined(qp: StageQP, x, dL_dx, lower, upper, sigma_b=1e-9, rho_b=1e6
         ex, ey = ex + dx, ey + dy
     ne = qp.neq
     eta_g = np.zeros(qp.nineq)
-    eta_g[act] = ey[ne:]
+    eta_g[hard] = ey[ne:]
+    eta_g[l2] = qp.gamma2 * (Gs @ ex)
     return ex, ey[:ne], eta_g
 
 

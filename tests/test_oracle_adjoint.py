@@ -53,3 +53,91 @@ def test_refinement_equals_dense_adjoint():
     e2 = adjoint_refined(qp, sol["x"], gx, sol["lower"], sol["upper"], sweeps=6)
     for a, c in zip(e1, e2):
         np.testing.assert_allclose(c, a, rtol=1e-10, atol=1e-12 * max(1.0, np.abs(a).max()))
+
+
+def _l2_slack_qp():
+    """Double integrator whose position rows carry an L2 slack and bind: the
+    start lies outside the tightened position box, so the first stages hold
+    nonzero slack."""
+    from oracle.qp import SOFT_L2, lti_batch_qp
+    from workloads import double_integrator
+
+    b = double_integrator(1, N=12, seed=3)
+    b.x0[0, :2] = [1.8, -1.6]
+    qp = lti_batch_qp(b, 0)
+    kinds = np.zeros(qp.ng, dtype=np.int64)
+    kinds[:2] = SOFT_L2
+    qp.soft = kinds
+    qp.gamma2 = 4.0
+    qp.lo[:, :2] = -1.0
+    qp.hi[:, :2] = 1.0
+    return qp
+
+
+def _admm_exact(qp, warm=None):
+    from oracle.admm import ADMMSettings, admm_solve
+
+    return admm_solve(qp, ADMMSettings(eps_abs=1e-13, eps_rel=1e-13, max_iter=400000), warm=warm)
+
+
+def test_l2_slack_adjoint_matches_central_fd_of_admm_solutions():
+    """eq. bwd:slack_reduced_system: eta on a QP with active L2-slack rows,
+    against central differences of the ADMM solutions (the smoothed slack
+    projection, an independent route to the optimum), h = 1e-5."""
+    from oracle.adjoint import polish, qp_vjp
+    from oracle.qp import SOFT_L2
+
+    qp = _l2_slack_qp()
+    r = _admm_exact(qp)
+    ok, sol = polish(qp, r.x, r.y_g, xi=r.xi, eps_solve=1e-8)
+    assert ok
+    lower, upper = sol["lower"], sol["upper"]
+    l2 = (lower | upper) & (qp.soft_rows() == SOFT_L2)
+    assert l2.sum() >= 2 and np.all(np.abs(sol["xi"][l2]) > 1e-3)
+    np.testing.assert_allclose(sol["xi"], r.xi, atol=1e-8)
+    g = np.random.default_rng(5).standard_normal(qp.nvar)
+    ex, ef, eg = adjoint_dense(qp, sol["x"], g, lower, upper)
+    grads = qp_vjp(qp, sol["x"], ex, ef, eg, lower, upper)
+    warm = {"x": r.x, "z_g": r.z_g, "y_f": r.y_f, "y_g": r.y_g, "rho_bar": r.rho_bar}
+    h = 1e-5
+
+    def fd(field, idx):
+        vals = []
+        for sgn in (1.0, -1.0):
+            arr = getattr(qp, field)
+            old = arr[idx]
+            arr[idx] = old + sgn * h
+            vals.append(g @ _admm_exact(qp, warm).x)
+            arr[idx] = old
+        return (vals[0] - vals[1]) / (2 * h)
+
+    rows = np.flatnonzero(l2)
+    t0, r0 = divmod(int(rows[0]), qp.ng)
+    checks = [("q", (0, 4), grads["d_q"][0, 4]), ("q", (5, 1), grads["d_q"][5, 1]),
+              ("x_init", (0,), grads["d_x_init"][0]), ("x_init", (3,), grads["d_x_init"][3])]
+    bound = "lo" if lower[rows[0]] else "hi"
+    checks.append((bound, (t0, r0), grads["d_" + bound][t0, r0]))
+    for field, idx, want in checks:
+        got = fd(field, idx)
+        assert abs(got - want) <= 1e-4 * max(1.0, abs(want)), (field, idx, got, want)
+    # the slack rows' adjoint multipliers satisfy their row of the dense
+    # system, G_S eta_x - eta_y / gamma2 = 0, and are not all zero
+    G = qp.matrices()[2]
+    np.testing.assert_allclose(eg[l2], qp.gamma2 * (G @ ex)[l2], atol=1e-10)
+    assert np.any(np.abs(eg[l2]) > 1e-3)
+
+
+def test_l2_slack_refinement_equals_dense_adjoint():
+    """The reduced system of the GPU scheme (slack rows in H, eta_y recovered)
+    equals the full active-set KKT solve with its -1/gamma2 slack diagonal."""
+    from oracle.adjoint import polish
+
+    qp = _l2_slack_qp()
+    r = _admm_exact(qp)
+    ok, sol = polish(qp, r.x, r.y_g, xi=r.xi, eps_solve=1e-8)
+    assert ok
+    g = np.random.default_rng(6).standard_normal(qp.nvar)
+    e1 = adjoint_dense(qp, sol["x"], g, sol["lower"], sol["upper"])
+    e2 = adjoint_refined(qp, sol["x"], g, sol["lower"], sol["upper"], sweeps=6)
+    for a, c in zip(e1, e2):
+        np.testing.assert_allclose(c, a, rtol=1e-9, atol=1e-11 * max(1.0, np.abs(a).max()))
