@@ -196,7 +196,11 @@ ocp_status ocp_get_solution(ocp_handle h, const ocp_solution* out, void* stream)
  * bwd:noslack_kkt_matrix / loss_gradient): identify the active set, factor
  * the regularised active-set Schur matrix in FP64, refine against the exact
  * KKT system and map eta to QP-data gradients.  dL_dx [S,n] device.
- * Errors: OCP_E_ORDER before a solve; OCP_E_UNSUPPORTED for L2-slack rows. */
+ * Active L2-slack rows follow the reduced system of eq.
+ * bwd:slack_reduced_system (their penalty gamma2 G_i'G_i joins H, their
+ * eta_y = gamma2 G_i eta_x; no loss term on the slacks); L1 rows with a
+ * nonzero slack carry a fixed multiplier and leave the active set.
+ * Errors: OCP_E_ORDER before a solve. */
 ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const ocp_qp_grads* out,
                        void* stream);
 
@@ -240,8 +244,7 @@ ocp_status ocp_profile_read(ocp_handle h, ocp_kernel_times* out);
  * bicycle model: a cold SQP start unless warm_start was set and a solve had
  * run).  Kernel timing is suspended while capturing.  Errors: OCP_E_ARG
  * (null handle / settings / stream, dL_dx without grads or vice versa),
- * OCP_E_ORDER (no problem data), OCP_E_UNSUPPORTED (adjoint of L2-slack
- * rows), OCP_E_HIP. */
+ * OCP_E_ORDER (no problem data), OCP_E_HIP. */
 ocp_status ocp_graph_capture(ocp_handle h, const ocp_settings* s, const ocp_solution* out, const double* dL_dx,
                              const ocp_qp_grads* grads, void* stream);
 

@@ -122,6 +122,9 @@ __device__ __forceinline__ void adjoint_sweeps_ti(const Layout& L, const AdjArgs
   const bool hasE = L.E != nullptr;
   const int gsel = L.gsel[i < NG ? i : 0], ginv = L.ginv[i];
   const bool gid = __ballot(i < NG && gsel != i) == 0;
+  // L2-slack row (eq. bwd:slack_reduced_system): when active it sits in H as
+  // gamma2 G_i'G_i (its weight in w is gamma2) instead of in J
+  const bool slr = i < NG && L.soft[i] == 1;
   auto gather_t = [&](double u) { return gid ? u : row_gather(u, ginv < 0 ? 0 : ginv); };  // G' u (lane i)
   auto gather = [&](double u) { return gid ? u : row_gather(u, gsel); };                    // G u (row i)
   // instance bases (uniform) and lane offsets
@@ -181,7 +184,14 @@ __device__ __forceinline__ void adjoint_sweeps_ti(const Layout& L, const AdjArgs
           jte = dotb<NX>(tb.Apc, efm, jte);
         jte += (t == 0 && xr) ? d.efr : 0.0;  // initial-state rows
         const double wc = (i < NG) ? d.wc : 0.0;
-        const double egv = (i < NG && wc != 0.0) ? d.eg : 0.0;
+        const bool slk = slr && wc != 0.0;
+        double gx;
+        if constexpr (ST::GSEL)
+          gx = gather(ec);
+        else
+          gx = dotb<n>(tb.Gr, ec, 0.0);
+        // J' e_y over the hard active rows, plus the active slack rows' H term G_i'(gamma2 G_i e_x)
+        const double egv = (i < NG && wc != 0.0) ? (slk ? wc * gx : d.eg) : 0.0;
         if constexpr (ST::GSEL) {
           const double gt = gather_t(egv);
           jte += (ginv >= 0) ? gt : 0.0;
@@ -202,12 +212,7 @@ __device__ __forceinline__ void adjoint_sweeps_ti(const Layout& L, const AdjArgs
         const double rfc = (thi && xr) ? -cx : 0.0;   // dynamics row t
         const double rfm = (tlo && xr) ? -cxm : 0.0;  // dynamics row t-1
         const double rf0 = (t == 0 && xr) ? -ec : 0.0;  // initial-state rows
-        double gx;
-        if constexpr (ST::GSEL)
-          gx = gather(ec);
-        else
-          gx = dotb<n>(tb.Gr, ec, 0.0);
-        const double rgc = (wc != 0.0) ? -gx : 0.0;
+        const double rgc = (wc != 0.0 && !slk) ? -gx : 0.0;
         double tc = dotb<NX>(tb.Amc, rfc, 0.0);
         if constexpr (ST::APNEG)
           tc -= rfm;
@@ -287,7 +292,7 @@ __device__ __forceinline__ void adjoint_sweeps_ti(const Layout& L, const AdjArgs
         if (FULL || t <= N) {
           const uint32_t o = ov(t);
           if (thi && xr) sto(ef, o + VS, d.efn + rb * (jd - d.rfn));
-          if (i < NG && d.wc != 0.0) sto(eg, o, d.eg + rb * (gd - d.rg));
+          if (i < NG && d.wc != 0.0 && !slr) sto(eg, o, d.eg + rb * (gd - d.rg));
           if (t == 0 && xr) sto(ef, o, d.ef0 + rb * (dx - d.rf0));
           if (i < n) sto(ex, o, d.ex + dx);
         }
@@ -314,6 +319,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   const gptr<double> ex = as_global(a.ex), ef = as_global(a.ef), eg = as_global(a.eg);
   const gptr<double> rf = as_global(a.rf), rg = as_global(a.rg), wv = as_global(a.w);
   const int kind = (i < NG) ? (int)L.soft[i] : 0;
+  const bool slr = kind == 1;  // L2-slack row (in H when active)
   const double rb = a.rho_b;
 
   // ---- 1. active set ----
@@ -350,7 +356,8 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
       act = lower ? -1 : (upper ? 1 : 0);
     }
     a.act[sv] = (int8_t)act;
-    wv[sv] = act ? rb : 0.0;
+    // active slack rows enter the Schur matrix with their penalty gamma2
+    wv[sv] = act ? (kind == 1 ? L.gamma2 : rb) : 0.0;
     ex[sv] = 0.0;
     ef[sv] = 0.0;
     eg[sv] = 0.0;
@@ -409,7 +416,10 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
         jte = dotb<NX>(B.Apcm, efm, jte);
         if (t == 0 && i < NX) jte += ef[sv];  // initial-state rows
         const double wc = (i < NG) ? wv[sv] : 0.0;
-        const double egv = (i < NG && wc != 0.0) ? eg[sv] : 0.0;
+        const bool slk = slr && wc != 0.0;
+        const double gx = dotb<n>(B.Gr, ec, 0.0);
+        // J' e_y over the hard active rows, plus the active slack rows' H term G_i'(gamma2 G_i e_x)
+        const double egv = (i < NG && wc != 0.0) ? (slk ? wc * gx : eg[sv]) : 0.0;
         jte = dotb<NG>(B.Gc, egv, jte);
         const double rx = ((i < n) ? a.dLdx[(size_t)s * n + i] : 0.0) - (he + jte);
         // equality-row residuals -J e_x of the rows touching stage t
@@ -420,8 +430,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
         cxm = dotb<n>(B.Aprm, ec, cxm);
         const double rfm = (t > 0 && i < NX) ? -cxm : 0.0;  // dynamics row t-1
         const double rf0 = (t == 0 && i < NX) ? -ec : 0.0;  // initial-state rows
-        const double gx = dotb<n>(B.Gr, ec, 0.0);
-        const double rgc = (wc != 0.0) ? -gx : 0.0;
+        const double rgc = (wc != 0.0 && !slk) ? -gx : 0.0;
         double tc = dotb<NX>(B.Amc, rfc, 0.0);
         tc = dotb<NX>(B.Apcm, rfm, tc);
         tc += rf0;
@@ -463,7 +472,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
         jd = dotb<n>(Apr, dn, jd);
         if (t < N && i < NX) ef[sv + ROW] += rb * (jd - rf[sv + ROW]);
         const double gd = dotb<n>(Gr, dx, 0.0);
-        if (i < NG && wv[sv] != 0.0) eg[sv] += rb * (gd - rg[sv]);
+        if (i < NG && wv[sv] != 0.0 && !slr) eg[sv] += rb * (gd - rg[sv]);
         if (t == 0 && i < NX) ef[sv] += rb * (dx - rf[sv]);
         if (i < n) ex[sv] += dx;
       }
@@ -484,9 +493,13 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
       if (a.d_q) a.d_q[(size_t)s * n + i] = -e;
       if (a.d_Ddiag) a.d_Ddiag[(size_t)s * n + i] = -e * double(X[sv]);
     }
+    // eta_y of an active slack row: gamma2 G_i eta_x (its row of the reduced system)
+    double Gr[n];
+    load_row<n>(Gr, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (size_t)(i < NG ? i : NG - 1) * n, true);
+    const double gex = dotb<n>(Gr, (i < n) ? ex[sv] : 0.0, 0.0);
     if (i < NG) {
       const int act = a.act[sv];
-      const double e = eg[sv] + nanv;
+      const double e = ((kind == 1 && act != 0) ? L.gamma2 * gex : eg[sv]) + nanv;
       if (a.d_lo) a.d_lo[(size_t)s * NG + i] = (act < 0) ? e : 0.0;
       if (a.d_hi) a.d_hi[(size_t)s * NG + i] = (act > 0) ? e : 0.0;
       if (a.active) a.active[(size_t)s * NG + i] = (int8_t)act;

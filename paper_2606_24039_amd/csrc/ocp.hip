@@ -871,8 +871,6 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
                        void* stream) {
   if (!h || !s || !dL_dx || !out) return OCP_E_ARG;
   if (!h->solved) return OCP_E_ORDER;
-  for (int r = 0; r < h->d.ng; ++r)
-    if (h->soft_host[r] == OCP_ROW_L2) return OCP_E_UNSUPPORTED;
   if (!(s->adj_sigma > 0) || !(s->adj_rho > 0) || !(s->eps_active > 0) || s->refine_sweeps < 1) return OCP_E_ARG;
   hipStream_t st = (hipStream_t)stream;
   AdjArgs a{};
