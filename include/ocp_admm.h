@@ -147,10 +147,13 @@ typedef struct {
 /* Gradients of a loss w.r.t. the QP data at the last solution (device, FP64,
  * caller-owned, NULL to skip): d_q [S,n], d_Ddiag [S,n] (diagonal of D_t),
  * d_x_init [B,nx], d_lo, d_hi [S,ng], eta_x [S,n], active [S,ng] (int8:
- * -1 lower, +1 upper, 0 inactive). */
+ * -1 lower, +1 upper, 0 inactive), d_gamma2 [B] (w.r.t. the L2 slack
+ * weight: sum over the active L2-slack rows of xi_i (G eta_x)_i, Sec.
+ * "Backward pass" with slack variables; 0 without such rows). */
 typedef struct {
   double *d_q, *d_Ddiag, *d_x_init, *d_lo, *d_hi, *eta_x;
   int8_t* active;
+  double* d_gamma2;
 } ocp_qp_grads;
 
 /* Fill `s` with the defaults listed above.  Never fails. */

@@ -171,12 +171,23 @@ def adjoint_refined(qp: StageQP, x, dL_dx, lower, upper, sigma_b=1e-9, rho_b=1e6
     return ex, ey[:ne], eta_g
 
 
-def qp_vjp(qp: StageQP, x, eta_x, eta_f, eta_g, lower, upper):
-    """Map eta to gradients of the QP data (eq. loss_gradient)."""
+def qp_vjp(qp: StageQP, x, eta_x, eta_f, eta_g, lower, upper, xi=None):
+    """Map eta to gradients of the QP data (eq. loss_gradient).  With the
+    slacks `xi` given, also the gradient w.r.t. the L2 slack weight: gamma2
+    enters only the active slack rows' equation G_i x - y_i / gamma2 = b_i,
+    whose derivative y_i / gamma2^2 = -xi_i / gamma2 (slack stationarity)
+    with eta_y,i = gamma2 G_i eta_x gives dL/dgamma2 = sum_i xi_i (G eta_x)_i
+    over those rows (the paper's xi_A' S grad g_A eta_x)."""
     n = qp.n
     xs = np.asarray(x).reshape(qp.N + 1, n)
     ex = np.asarray(eta_x).reshape(qp.N + 1, n)
+    d_gamma2 = None
+    if xi is not None:
+        G = qp.matrices()[2]
+        l2 = (lower | upper) & (qp.soft_rows() == SOFT_L2)
+        d_gamma2 = float(np.sum(np.asarray(xi)[l2] * (G @ np.asarray(eta_x))[l2]))
     return {
+        "d_gamma2": d_gamma2,
         "d_q": -ex,
         "d_c": np.asarray(eta_f).copy(),
         "d_x_init": np.asarray(eta_f)[: qp.nx].copy(),

@@ -54,7 +54,8 @@ class ocp_solution(C.Structure):
 
 
 class ocp_qp_grads(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in ("d_q", "d_Ddiag", "d_x_init", "d_lo", "d_hi", "eta_x", "active")]
+    _fields_ = [(k, C.c_void_p) for k in ("d_q", "d_Ddiag", "d_x_init", "d_lo", "d_hi", "eta_x", "active",
+                                          "d_gamma2")]
 
 
 # (name, restype, argtypes) for every symbol declared in include/ocp_admm.h

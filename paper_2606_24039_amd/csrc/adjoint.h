@@ -49,7 +49,7 @@ struct AdjArgs {
   // factor of the regularised Schur matrix, FP64 P/K form (factor.h), padded
   double *P, *K, *Kb;
   // outputs (FP64, may be null)
-  double *d_q, *d_Ddiag, *d_x_init, *d_lo, *d_hi, *eta_x;
+  double *d_q, *d_Ddiag, *d_x_init, *d_lo, *d_hi, *eta_x, *d_gamma2;
   int8_t* active;
 };
 
@@ -482,6 +482,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
 
   // ---- 3. VJP outputs ----
   const double nanv = bad ? NAN : 0.0;
+  double dgam = 0.0;  // this lane's part of dL/dgamma2
   for (int blk = 0; blk < nbl; ++blk) {
     const int t = 4 * blk + q;
     if (t > N) break;
@@ -500,12 +501,17 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     if (i < NG) {
       const int act = a.act[sv];
       const double e = ((kind == 1 && act != 0) ? L.gamma2 * gex : eg[sv]) + nanv;
+      if (kind == 1 && act != 0) dgam += double(XI[sv]) * gex;
       if (a.d_lo) a.d_lo[(size_t)s * NG + i] = (act < 0) ? e : 0.0;
       if (a.d_hi) a.d_hi[(size_t)s * NG + i] = (act > 0) ? e : 0.0;
       if (a.active) a.active[(size_t)s * NG + i] = (int8_t)act;
     }
     if (t == 0 && i < NX && a.d_x_init) a.d_x_init[(size_t)b * NX + i] = ef[sv] + nanv;
   }
+  dgam = row_sum(dgam);
+  dgam += __shfl_xor(dgam, 16);
+  dgam += __shfl_xor(dgam, 32);
+  if (threadIdx.x == 0 && a.d_gamma2) a.d_gamma2[b] = dgam + nanv;
 }
 
 }  // namespace ocpk

@@ -894,6 +894,7 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   a.d_q = out->d_q;
   a.d_Ddiag = out->d_Ddiag;
   a.d_x_init = out->d_x_init;
+  a.d_gamma2 = out->d_gamma2;
   a.d_lo = out->d_lo;
   a.d_hi = out->d_hi;
   a.eta_x = out->eta_x;

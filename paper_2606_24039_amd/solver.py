@@ -163,7 +163,8 @@ class OCPSolver:
         return {"d_q": torch.empty(self.S, self.n, **f64), "d_Ddiag": torch.empty(self.S, self.n, **f64),
                 "d_x_init": torch.empty(self.B, self.nx, **f64), "d_lo": torch.empty(self.S, self.ng, **f64),
                 "d_hi": torch.empty(self.S, self.ng, **f64), "eta_x": torch.empty(self.S, self.n, **f64),
-                "active": torch.empty(self.S, self.ng, dtype=torch.int8, device=self.device)}
+                "active": torch.empty(self.S, self.ng, dtype=torch.int8, device=self.device),
+                "d_gamma2": torch.empty(self.B, **f64)}
 
     def grads_struct(self, g):
         return A.ocp_qp_grads(*[g[k].data_ptr() for k, _ in A.ocp_qp_grads._fields_])

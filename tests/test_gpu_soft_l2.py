@@ -11,7 +11,7 @@ slack on the active rows.
 * Adjoint at a tight FP64 solve: the active set equals the oracle's at its
   polished optimum (same rule and tolerance), eta and the QP-data gradients
   match the oracle's dense KKT solve with the -1/gamma2 slack diagonal (1e-6),
-  under both launch shapes.
+  and so does the gradient w.r.t. the slack weight, under both launch shapes.
 """
 import numpy as np
 import pytest
@@ -108,7 +108,8 @@ def test_l2_slack_adjoint_matches_oracle_dense_solve(seg):
         dli = s.split(dl, i).cpu().numpy().reshape(-1)
         ex, ef, eg = adjoint_dense(qp, sol["x"], dli, lower, upper)
         assert rel(s.split(g["eta_x"], i).cpu().numpy().reshape(-1), ex) < 1e-6, i
-        qg = qp_vjp(qp, sol["x"], ex, ef, eg, lower, upper)
+        qg = qp_vjp(qp, sol["x"], ex, ef, eg, lower, upper, xi=sol["xi"])
+        assert abs(float(g["d_gamma2"][i]) - qg["d_gamma2"]) <= 1e-6 * max(1.0, abs(qg["d_gamma2"])), i
         flat = lambda a: np.asarray(a).reshape(-1)
         assert rel(flat(g["d_x_init"][i].cpu().numpy()), flat(qg["d_x_init"])) < 1e-6, i
         for k in ("d_q", "d_lo", "d_hi"):

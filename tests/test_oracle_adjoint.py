@@ -97,7 +97,7 @@ def test_l2_slack_adjoint_matches_central_fd_of_admm_solutions():
     np.testing.assert_allclose(sol["xi"], r.xi, atol=1e-8)
     g = np.random.default_rng(5).standard_normal(qp.nvar)
     ex, ef, eg = adjoint_dense(qp, sol["x"], g, lower, upper)
-    grads = qp_vjp(qp, sol["x"], ex, ef, eg, lower, upper)
+    grads = qp_vjp(qp, sol["x"], ex, ef, eg, lower, upper, xi=sol["xi"])
     warm = {"x": r.x, "z_g": r.z_g, "y_f": r.y_f, "y_g": r.y_g, "rho_bar": r.rho_bar}
     h = 1e-5
 
@@ -120,6 +120,15 @@ def test_l2_slack_adjoint_matches_central_fd_of_admm_solutions():
     for field, idx, want in checks:
         got = fd(field, idx)
         assert abs(got - want) <= 1e-4 * max(1.0, abs(want)), (field, idx, got, want)
+    # the slack weight itself (Sec. "Backward pass", slack variables)
+    vals = []
+    for sgn in (1.0, -1.0):
+        qp.gamma2 = 4.0 + sgn * h
+        vals.append(g @ _admm_exact(qp, warm).x)
+    qp.gamma2 = 4.0
+    got = (vals[0] - vals[1]) / (2 * h)
+    assert abs(got - grads["d_gamma2"]) <= 1e-4 * max(1.0, abs(got)), (got, grads["d_gamma2"])
+    assert abs(grads["d_gamma2"]) > 1e-4
     # the slack rows' adjoint multipliers satisfy their row of the dense
     # system, G_S eta_x - eta_y / gamma2 = 0, and are not all zero
     G = qp.matrices()[2]
