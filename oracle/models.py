@@ -8,6 +8,10 @@ writes the trapezoidal rule in Remark A1; the midpoint rule has the same
 block structure):
     f_t = x_t + dt * fc((x_t + x_{t+1}) / 2, u_t) - x_{t+1} = 0.
 Jacobians:  A_t^- = [I + dt/2 Jx, dt Ju],  A_t^+ = [-I + dt/2 Jx, 0].
+The trapezoidal rule of Remark A1 (batch.integrator = 1), same hold on u:
+    f_t = x_t + dt/2 (fc(x_t, u_t) + fc(x_{t+1}, u_t)) - x_{t+1} = 0,
+    A_t^- = [I + dt/2 Jx(x_t), dt/2 (Ju(x_t) + Ju(x_{t+1}))],
+    A_t^+ = [-I + dt/2 Jx(x_{t+1}), 0].
 
 Cost 1/2 (x_t - r_t)'Q(x_t - r_t) + 1/2 u_t'R u_t (t < N), with Q_f at t = N.
 Inequalities g_t = (a_t, delta_t, n_t'(p_t - p_ref_t)): hard boxes on a and
@@ -18,7 +22,8 @@ c and the shifted bounds for the absolute variable), so the linear cost term
 is q_t = grad l_t(xbar_t) - D_t xbar_t.
 
 Parity: Jacobians pinned by central differences, midpoint residual by a
-Newton-solved rollout (tests/test_oracle_sqp.py).
+Newton-solved rollout, both rules by their order of accuracy on a circle
+(tests/test_oracle_sqp.py).
 """
 from __future__ import annotations
 
@@ -62,6 +67,21 @@ def midpoint_jacobians(xt, ut, xn, dt, L):
     return Am, Ap
 
 
+def trapezoid_residual(xt, ut, xn, dt, L):
+    """f_t(x_t, u_t, x_{t+1}) of the trapezoidal rule (zero-order hold on u)."""
+    return xt + 0.5 * dt * (fc(xt, ut, L) + fc(xn, ut, L)) - xn
+
+
+def trapezoid_jacobians(xt, ut, xn, dt, L):
+    """(A^- [4x6], A^+ [4x6]) of the trapezoidal f_t."""
+    Jx0, Ju0 = fc_jac(xt, ut, L)
+    Jx1, Ju1 = fc_jac(xn, ut, L)
+    I = np.eye(4)
+    Am = np.hstack([I + 0.5 * dt * Jx0, 0.5 * dt * (Ju0 + Ju1)])
+    Ap = np.hstack([-I + 0.5 * dt * Jx1, np.zeros((4, 2))])
+    return Am, Ap
+
+
 class BicycleOCP:
     """One instance of a workloads.BicycleBatch as an OCP."""
 
@@ -81,6 +101,9 @@ class BicycleOCP:
         self.soft = np.array([HARD, HARD, SOFT_L1])
         self.gamma1 = batch.gamma_l1
         self.nx, self.nu, self.ng = 4, 2, 3
+        trap = getattr(batch, "integrator", 0) == 1
+        self._res = trapezoid_residual if trap else midpoint_residual
+        self._jac = trapezoid_jacobians if trap else midpoint_jacobians
 
     @property
     def n(self):
@@ -118,7 +141,7 @@ class BicycleOCP:
         """(x_0 - x_init, f_0, ..., f_{N-1}) stacked."""
         r = [z[0, :4] - self.x_init]
         for t in range(self.N):
-            r.append(midpoint_residual(z[t, :4], z[t, 4:], z[t + 1, :4], self.dt, self.L))
+            r.append(self._res(z[t, :4], z[t, 4:], z[t + 1, :4], self.dt, self.L))
         return np.concatenate(r)
 
     def eq_jac_T_times(self, z, y):
@@ -127,7 +150,7 @@ class BicycleOCP:
         out[0, :4] += y[:4]
         for t in range(self.N):
             yt = y[4 + 4 * t: 8 + 4 * t]
-            Am, Ap = midpoint_jacobians(z[t, :4], z[t, 4:], z[t + 1, :4], self.dt, self.L)
+            Am, Ap = self._jac(z[t, :4], z[t, 4:], z[t + 1, :4], self.dt, self.L)
             out[t] += Am.T @ yt
             out[t + 1] += Ap.T @ yt
         return out
@@ -158,8 +181,8 @@ class BicycleOCP:
         Ap = np.zeros((N, 4, 6))
         b = np.zeros((N, 4))
         for t in range(N):
-            Am[t], Ap[t] = midpoint_jacobians(z[t, :4], z[t, 4:], z[t + 1, :4], self.dt, self.L)
-            f = midpoint_residual(z[t, :4], z[t, 4:], z[t + 1, :4], self.dt, self.L)
+            Am[t], Ap[t] = self._jac(z[t, :4], z[t, 4:], z[t + 1, :4], self.dt, self.L)
+            f = self._res(z[t, :4], z[t, 4:], z[t + 1, :4], self.dt, self.L)
             b[t] = Am[t] @ z[t] + Ap[t] @ z[t + 1] - f
         G = np.stack([self.G_block(t) for t in range(N + 1)])
         gz = self.ineq(z)

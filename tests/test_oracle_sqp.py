@@ -11,47 +11,81 @@
 * At SQP convergence the NLP stopping quantities (eq. sqp_stop) are small.
 """
 import numpy as np
+import pytest
 
 from oracle.admm import ADMMSettings
-from oracle.models import BicycleOCP, midpoint_jacobians, midpoint_residual
+from oracle.models import (BicycleOCP, midpoint_jacobians, midpoint_residual, trapezoid_jacobians,
+                           trapezoid_residual)
 from oracle.sqp import SQPSettings, line_search, sqp_solve, stop_test
 from workloads import bicycle_batch
 
 
-def _newton_step(xt, ut, dt, L):
+def _newton_step(xt, ut, dt, L, res=midpoint_residual):
     xn = xt.copy()
     for _ in range(50):
-        r = midpoint_residual(xt, ut, xn, dt, L)
+        r = res(xt, ut, xn, dt, L)
         J = np.zeros((4, 4))
         for k in range(4):
             e = np.zeros(4)
             e[k] = 1e-7
-            J[:, k] = (midpoint_residual(xt, ut, xn + e, dt, L) - midpoint_residual(xt, ut, xn - e, dt, L)) / 2e-7
+            J[:, k] = (res(xt, ut, xn + e, dt, L) - res(xt, ut, xn - e, dt, L)) / 2e-7
         xn = xn - np.linalg.solve(J, r)
         if np.max(np.abs(r)) < 1e-15:
             break
     return xn
 
 
-def test_jacobians_match_central_differences(rng):
+@pytest.mark.parametrize("rule", ["midpoint", "trapezoid"])
+def test_jacobians_match_central_differences(rng, rule):
+    res, jac = ((midpoint_residual, midpoint_jacobians) if rule == "midpoint"
+                else (trapezoid_residual, trapezoid_jacobians))
     for _ in range(20):
         xt = rng.normal(size=4) + np.array([0, 0, 0, 6.0])
         xn = xt + 0.1 * rng.normal(size=4)
         ut = rng.uniform(-0.3, 0.3, size=2)
-        Am, Ap = midpoint_jacobians(xt, ut, xn, 0.05, 2.5)
+        Am, Ap = jac(xt, ut, xn, 0.05, 2.5)
         h = 1e-6
         for k in range(6):
             e = np.zeros(6)
             e[k] = h
             zp, zm = np.concatenate([xt, ut]) + e, np.concatenate([xt, ut]) - e
-            d = (midpoint_residual(zp[:4], zp[4:], xn, 0.05, 2.5) - midpoint_residual(zm[:4], zm[4:], xn, 0.05, 2.5)) / (2 * h)
+            d = (res(zp[:4], zp[4:], xn, 0.05, 2.5) - res(zm[:4], zm[4:], xn, 0.05, 2.5)) / (2 * h)
             np.testing.assert_allclose(Am[:, k], d, atol=1e-8)
         for k in range(4):
             e = np.zeros(4)
             e[k] = h
-            d = (midpoint_residual(xt, ut, xn + e, 0.05, 2.5) - midpoint_residual(xt, ut, xn - e, 0.05, 2.5)) / (2 * h)
+            d = (res(xt, ut, xn + e, 0.05, 2.5) - res(xt, ut, xn - e, 0.05, 2.5)) / (2 * h)
             np.testing.assert_allclose(Ap[:, k], d, atol=1e-8)
         np.testing.assert_allclose(Ap[:, 4:], 0.0)
+
+
+def test_trapezoid_exact_for_constant_acceleration_line_and_second_order_on_circle():
+    """The trapezoidal rule integrates v' = a exactly along a straight line
+    (the position is quadratic in time) and is second-order on a circle;
+    it differs from the midpoint rule once the heading turns."""
+    dt, L, yaw, v0, a = 0.05, 2.5, 0.3, 5.0, 1.7
+    x = np.array([1.0, -2.0, yaw, v0])
+    for t in range(1, 40):
+        x = _newton_step(x, np.array([a, 0.0]), dt, L, trapezoid_residual)
+        tt = t * dt
+        s = v0 * tt + 0.5 * a * tt ** 2
+        np.testing.assert_allclose(x, [1.0 + s * np.cos(yaw), -2.0 + s * np.sin(yaw), yaw, v0 + a * tt], atol=1e-11)
+    Lw, v, d = 2.5, 8.0, 0.2
+    w = v * np.tan(d) / Lw
+    errs, last = [], None
+    for dt in (0.05, 0.025):
+        x = np.array([0.0, 0.0, 0.0, v])
+        T = 2.0
+        for _ in range(int(round(T / dt))):
+            x = _newton_step(x, np.array([0.0, d]), dt, Lw, trapezoid_residual)
+        exact = np.array([v / w * np.sin(w * T), v / w * (1 - np.cos(w * T)), w * T, v])
+        errs.append(np.max(np.abs(x - exact)))
+        last = x
+    assert errs[0] < 1e-2 and 3.5 < errs[0] / errs[1] < 4.5
+    xm = np.array([0.0, 0.0, 0.0, v])
+    for _ in range(80):
+        xm = _newton_step(xm, np.array([0.0, d]), 0.025, Lw)
+    assert np.max(np.abs(xm - last)) > 1e-6
 
 
 def test_midpoint_exact_for_constant_acceleration_line():
@@ -183,8 +217,10 @@ def test_linear_problem_converges_in_one_sqp_step():
     assert np.any(np.abs(r.z[:, 3:]) >= 0.2 - 1e-9)  # bounds are active
 
 
-def test_bicycle_sqp_reaches_nlp_kkt_point():
+@pytest.mark.parametrize("integrator", [0, 1], ids=["midpoint", "trapezoid"])
+def test_bicycle_sqp_reaches_nlp_kkt_point(integrator):
     b = bicycle_batch(1, N=20, seed=92)
+    b.integrator = integrator
     ocp = BicycleOCP(b, 0)
     tight = ADMMSettings(eps_abs=1e-11, eps_rel=1e-11, max_iter=20000)
     r = sqp_solve(ocp, SQPSettings(max_sqp=25, fixed_iters=False, eps_c=1e-7), admm=tight)

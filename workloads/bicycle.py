@@ -47,6 +47,7 @@ class BicycleBatch:
     Rd: np.ndarray = field(default_factory=lambda: np.array(R_DIAG))
     Qfd: np.ndarray = field(default_factory=lambda: np.array(Q_DIAG))
     meta: dict = field(default_factory=dict)
+    integrator: int = 0  # 0: implicit midpoint, 1: trapezoidal rule
 
     nx: int = 4
     nu: int = 2
