@@ -60,6 +60,10 @@ enum { OCP_PREC_FP64 = 0, OCP_PREC_MIXED = 1 };
 /* inequality-row kinds: hard, L2-penalised slack (Sec. "Slack update"),
  * L1-penalised slack */
 enum { OCP_ROW_HARD = 0, OCP_ROW_L2 = 1, OCP_ROW_L1 = 2 };
+/* bicycle discretisation (zero-order hold on u): implicit midpoint
+ * x_t + dt fc((x_t + x_{t+1})/2, u_t) - x_{t+1}, or the trapezoidal rule of
+ * Remark A1, x_t + dt/2 (fc(x_t, u_t) + fc(x_{t+1}, u_t)) - x_{t+1} */
+enum { OCP_INTEG_MIDPOINT = 0, OCP_INTEG_TRAPEZOID = 1 };
 /* per-instance status */
 enum { OCP_SOLVED = 0, OCP_MAX_ITER = 1, OCP_NON_FINITE = 2, OCP_FACTOR_BREAKDOWN = 3 };
 
@@ -129,6 +133,7 @@ typedef struct {
   const double *ref, *normal, *x0;
   double dt, wheelbase, a_bound, steer_bound, lat_bound, gamma1;
   double Qd[4], Rd[2], Qfd[4];
+  int32_t integrator; /* OCP_INTEG_MIDPOINT or OCP_INTEG_TRAPEZOID */
 } ocp_bicycle;
 
 /* Solution buffers (device, FP64, caller-owned).  Any pointer may be NULL

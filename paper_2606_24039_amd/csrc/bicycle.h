@@ -29,6 +29,7 @@ struct BikeArgs {
   const int32_t* stage_inst;  // [S] instance of each global stage
   double dt, Lw, a_b, d_b, lat_b, gamma1;
   double Qd[4], Rd[2], Qfd[4];
+  int integ;  // 0 implicit midpoint, 1 trapezoidal rule
   // SQP state (FP64, padded [S][ROW])
   double* xbar;
   double* xibar;
@@ -56,30 +57,67 @@ __device__ __forceinline__ void bike_fc(const double* x, const double* u, double
 }
 
 // midpoint residual f_t and its Jacobian blocks at (xt, ut, xn)
-__device__ __forceinline__ void bike_midpoint(const double* xt, const double* ut, const double* xn, double dt,
-                                              double Lw, double* f, double (*Am)[6], double (*Ap)[6]) {
-  double m[4];
+// Discrete dynamics f_t(x_t, u_t, x_{t+1}) and its Jacobians A^- (w.r.t.
+// (x_t, u_t)) and A^+ (w.r.t. (x_{t+1}, u_{t+1})), zero-order hold on u:
+//   integ 0, implicit midpoint: x_t + dt fc((x_t + x_{t+1})/2, u_t) - x_{t+1}
+//   integ 1, trapezoidal rule (Remark A1):
+//            x_t + dt/2 (fc(x_t, u_t) + fc(x_{t+1}, u_t)) - x_{t+1}
+__device__ __forceinline__ void bike_fc(const double* x, const double* u, double Lw, double* fc, double (*Jx)[4],
+                                        double* ju) {
+  const double c = cos(x[2]), s = sin(x[2]), tn = tan(u[1]), cd = cos(u[1]);
+  fc[0] = x[3] * c;
+  fc[1] = x[3] * s;
+  fc[2] = x[3] * tn / Lw;
+  fc[3] = u[0];
+  if (!Jx) return;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) m[k] = 0.5 * (xt[k] + xn[k]);
-  const double c = cos(m[2]), s = sin(m[2]), tn = tan(ut[1]), cd = cos(ut[1]);
-  const double fc[4] = {m[3] * c, m[3] * s, m[3] * tn / Lw, ut[0]};
+  for (int r = 0; r < 4; ++r)
 #pragma unroll
-  for (int k = 0; k < 4; ++k) f[k] = xt[k] + dt * fc[k] - xn[k];
-  if (!Am) return;
-  double Jx[4][4] = {{0, 0, -m[3] * s, c}, {0, 0, m[3] * c, s}, {0, 0, 0, tn / Lw}, {0, 0, 0, 0}};
-  double Ju[4][2] = {{0, 0}, {0, 0}, {0, m[3] / (Lw * cd * cd)}, {1, 0}};
+    for (int k = 0; k < 4; ++k) Jx[r][k] = 0.0;
+  Jx[0][2] = -x[3] * s;
+  Jx[0][3] = c;
+  Jx[1][2] = x[3] * c;
+  Jx[1][3] = s;
+  Jx[2][3] = tn / Lw;
+  ju[0] = x[3] / (Lw * cd * cd);  // d yaw' / d delta (the only nonzero entry besides d v' / d a = 1)
+}
+
+__device__ __forceinline__ void bike_dynamics(const double* xt, const double* ut, const double* xn, double dt,
+                                              double Lw, int integ, double* f, double (*Am)[6], double (*Ap)[6]) {
+  double J0[4][4], J1[4][4], ju0 = 0.0, ju1 = 0.0;
+  const bool jac = Am != nullptr;
+  double f0[4];
+  if (integ == 1) {
+    double f1[4];
+    bike_fc(xt, ut, Lw, f0, jac ? J0 : nullptr, &ju0);
+    bike_fc(xn, ut, Lw, f1, jac ? J1 : nullptr, &ju1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) f[k] = xt[k] + 0.5 * dt * (f0[k] + f1[k]) - xn[k];
+  } else {
+    double m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = 0.5 * (xt[k] + xn[k]);
+    bike_fc(m, ut, Lw, f0, jac ? J0 : nullptr, &ju0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) f[k] = xt[k] + dt * f0[k] - xn[k];
+  }
+  if (!jac) return;
+  const bool tr = integ == 1;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      Am[r][k] = (r == k ? 1.0 : 0.0) + 0.5 * dt * Jx[r][k];
-      Ap[r][k] = (r == k ? -1.0 : 0.0) + 0.5 * dt * Jx[r][k];
+      Am[r][k] = (r == k ? 1.0 : 0.0) + 0.5 * dt * J0[r][k];
+      Ap[r][k] = (r == k ? -1.0 : 0.0) + 0.5 * dt * (tr ? J1[r][k] : J0[r][k]);
     }
-    Am[r][4] = dt * Ju[r][0];
-    Am[r][5] = dt * Ju[r][1];
+    Am[r][4] = 0.0;
+    Am[r][5] = 0.0;
     Ap[r][4] = 0.0;
     Ap[r][5] = 0.0;
   }
+  // control columns: d v' / d a = 1, d yaw' / d delta = ju
+  Am[3][4] = dt;
+  Am[2][5] = tr ? 0.5 * dt * (ju0 + ju1) : dt * ju0;
 }
 
 // SQP initial guess: the reference with zero controls.
@@ -133,7 +171,7 @@ __global__ void bike_linearize_kernel(Layout L, BikeArgs a) {
   if (t < N) {
     const double* xn = a.xbar + (s + 1) * ROW;
     double f[4], Ml[4][6], Mr[4][6];
-    bike_midpoint(xb, xb + 4, xn, a.dt, a.Lw, f, Ml, Mr);
+    bike_dynamics(xb, xb + 4, xn, a.dt, a.Lw, a.integ, f, Ml, Mr);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       double acc = -f[r];
@@ -306,7 +344,7 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
       if (t < N) {
         bike_point(a, xbn, dxn, al, zn);
         double f[4];
-        bike_midpoint(z, z + 4, zn, a.dt, a.Lw, f, nullptr, nullptr);
+        bike_dynamics(z, z + 4, zn, a.dt, a.Lw, a.integ, f, nullptr, nullptr);
 #pragma unroll
         for (int k = 0; k < 4; ++k) v += fabs(f[k]);
       }
@@ -385,7 +423,7 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     double f[4], Ml[4][6], Mr[4][6];
     if (t < N) {  // dynamics row t (slot t): A_t^-' y
       const double* yf = a.yfbar + s * ROW;
-      bike_midpoint(xb, xb + 4, xb + ROW, a.dt, a.Lw, f, Ml, Mr);
+      bike_dynamics(xb, xb + 4, xb + ROW, a.dt, a.Lw, a.integ, f, Ml, Mr);
 #pragma unroll
       for (int k = 0; k < 6; ++k)
 #pragma unroll
@@ -396,7 +434,7 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     if (t > 0) {  // dynamics row t-1 (slot t-1): A_{t-1}^+' y
       const double* yf = a.yfbar + (s - 1) * ROW;
       const double* xp = xb - ROW;
-      bike_midpoint(xp, xp + 4, xb, a.dt, a.Lw, f, Ml, Mr);
+      bike_dynamics(xp, xp + 4, xb, a.dt, a.Lw, a.integ, f, Ml, Mr);
 #pragma unroll
       for (int k = 0; k < 6; ++k)
 #pragma unroll

@@ -589,6 +589,7 @@ BikeArgs make_bike(ocp_handle h, const ocp_settings* s) {
   a.d_b = h->bike.steer_bound;
   a.lat_b = h->bike.lat_bound;
   a.gamma1 = h->bike.gamma1;
+  a.integ = h->bike.integrator;
   for (int k = 0; k < 4; ++k) {
     a.Qd[k] = h->bike.Qd[k];
     a.Qfd[k] = h->bike.Qfd[k];
@@ -819,7 +820,7 @@ ocp_status ocp_set_bicycle(ocp_handle h, const ocp_bicycle* p, void* stream) {
   if (!h || !p || !p->ref || !p->normal || !p->x0) return OCP_E_ARG;
   if (h->d.model != OCP_MODEL_BICYCLE) return OCP_E_ORDER;
   if (!(p->dt > 0) || !(p->wheelbase > 0) || !(p->gamma1 > 0) || !(p->a_bound > 0) || !(p->steer_bound > 0) ||
-      !(p->lat_bound > 0))
+      !(p->lat_bound > 0) || (p->integrator != OCP_INTEG_MIDPOINT && p->integrator != OCP_INTEG_TRAPEZOID))
     return OCP_E_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t S = h->S;

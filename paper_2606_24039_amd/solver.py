@@ -87,7 +87,8 @@ class OCPSolver:
         t = [_dev(batch.ref), _dev(batch.normal), _dev(batch.x0)]
         p = A.ocp_bicycle(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(), batch.dt, batch.wheelbase,
                           batch.a_bound, batch.steer_bound, batch.lat_bound, batch.gamma_l1,
-                          (C.c_double * 4)(*batch.Qd), (C.c_double * 2)(*batch.Rd), (C.c_double * 4)(*batch.Qfd))
+                          (C.c_double * 4)(*batch.Qd), (C.c_double * 2)(*batch.Rd), (C.c_double * 4)(*batch.Qfd),
+                          int(getattr(batch, "integrator", 0)))
         A.check(self.lib.ocp_set_bicycle(self.h, C.byref(p), _stream()), "ocp_set_bicycle")
         self._keep = t
         torch.cuda.current_stream().synchronize()

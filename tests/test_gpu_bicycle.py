@@ -89,3 +89,24 @@ def test_ragged_bicycle_batch():
         z = s.split(out["x"], i).cpu().numpy()
         assert z.shape == (rag.horizons[i] + 1, 6)
         assert rel(z, ref.z) < 1e-8
+
+
+@pytest.mark.parametrize("seg", [None, 15], ids=["stagewise", "chunked"])
+def test_trapezoidal_rule_follows_the_oracle_fp64(seg):
+    """The trapezoidal discretisation (Remark A1): linearisation, line-search
+    merit and stopping quantities all evaluate the same rule as the oracle."""
+    b = bicycle_batch(3, N=40, seed=3, first=20)
+    b.integrator = 1
+    s = _solver(b, FP64)
+    if seg is not None:
+        s.set_segmented(seg)
+    out = s.solve(_settings(max_sqp=8, max_admm=50, k_check=0, k_rho=25, fixed_sqp=1))
+    for i in range(b.batch):
+        ref = sqp_solve(BicycleOCP(b, i), SQPSettings(max_sqp=8, fixed_iters=True),
+                        admm=ADMMSettings(max_iter=50, k_check=0, k_rho=25))
+        z = s.split(out["x"], i).cpu().numpy()
+        assert rel(z, ref.z) < 1e-8, rel(z, ref.z)
+        kkt = out["sqp_kkt"][i].cpu().numpy()
+        assert abs(kkt[0] - ref.stop["stationarity"]) < 1e-7 * max(1, ref.stop["stationarity"])
+        assert abs(kkt[1] - ref.stop["eq"]) < 1e-9 + 1e-7 * ref.stop["eq"]
+    s.close()
