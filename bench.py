@@ -42,7 +42,7 @@ def log(*a):
 
 
 # ---------------------------------------------------------------------------
-# algorithmic work per unit ("Measurement")
+# algorithmic work per unit (flops per stage per iteration / factorisation)
 # ---------------------------------------------------------------------------
 def lti_flops_per_stage(nx, nu, ng):
     """(FP32-path flops per stage per ADMM iteration, FP64 flops per stage per
