@@ -303,6 +303,172 @@ __device__ __forceinline__ void adjoint_sweeps_ti(const Layout& L, const AdjArgs
   }
 }
 
+// Refinement sweeps, time-varying blocks: the same passes as the
+// time-invariant form with every stage's blocks read where they are used.
+// Stage-parallel passes walk 4-stage blocks with their inputs loaded ahead
+// (two blocks ahead for small stages, whose block rows fit the registers;
+// inputs are read at stages clamped to 0..N).
+template <int n>
+constexpr int ADJ_TV_DEPTH = n <= 8 ? STAGE_BLOCK_DEPTH : 1;
+
+template <int NX, int NU, int NG>
+struct AdjInTV1 {
+  AdjBlocks<NX, NU, NG> B;
+  double ec, em, en, efc, efm, ef0, wc, eg, dl;
+};
+template <int NX, int NU, int NG>
+struct AdjInTV5 {
+  static constexpr int n = NX + NU;
+  double Amr[n], Apr[n], Gr[n];
+  double dx, dn, efn, rfn, wc, eg, rg, ef0, rf0, ex;
+};
+
+template <int NX, int NU, int NG>
+__device__ __forceinline__ void adjoint_sweeps_tv(const Layout& L, const AdjArgs& a, const WaveGroup& w, int bad,
+                                                  bool slr) {
+  constexpr int n = NX + NU;
+  constexpr int D = ADJ_TV_DEPTH<n>;
+  const int i = w.lane, q = w.row, N = w.N, b = w.b;
+  const int64_t s0 = w.s0;
+  const int ic = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
+  const int nfull = N / 4;
+  const size_t nn = (size_t)n * n;
+  const double rb = a.rho_b;
+  const gptr<double> ex = as_global(a.ex), ef = as_global(a.ef), eg = as_global(a.eg);
+  const gptr<double> rf = as_global(a.rf), rg = as_global(a.rg), wv = as_global(a.w);
+  const gptr<double> R = as_global(a.v) + (size_t)s0 * ROW + i;
+  const gptr<const double> Pr = as_global((const double*)a.P) + (size_t)s0 * nn + (size_t)ic * n;
+  // the chains take bases STAGE_PAD stages before stage 0 and lane offsets
+  const int64_t sp = s0 - STAGE_PAD;
+  const gptr<double> Rb = as_global(a.v) + sp * ROW;
+  const gptr<const double> Kb0 = as_global((const double*)a.K) + sp * (int64_t)nn;
+  const gptr<const double> Kbb0 = as_global((const double*)a.Kb) + sp * (int64_t)nn;
+  const uint32_t orow = (uint32_t)((STAGE_PAD * ROW + i) * (int)sizeof(double));
+  const uint32_t oblk = (uint32_t)((STAGE_PAD * (int)nn + ic * n) * (int)sizeof(double));
+  auto tcl = [&](int blk) { return min(4 * blk + q, N); };
+
+  for (int sweep = 0; sweep < a.sweeps && !bad; ++sweep) {
+    // pass 1: residual r - K e and the Schur right-hand side
+    //   rhs_t = r_x,t + rho_b (C' r_f)_t + G_t'(w .* r_g,t)
+    {
+      using In = AdjInTV1<NX, NU, NG>;
+      auto load = [&](In& d, int blk) {
+        const int t = tcl(blk);
+        const int64_t s = s0 + t;
+        const size_t sv = (size_t)s * ROW + i;
+        load_adj_blocks(d.B, L, b, s0, t, N, i);
+        d.ec = (i < n) ? ex[sv] : 0.0;
+        d.em = (t > 0 && i < n) ? ex[sv - ROW] : 0.0;
+        d.en = (t < N && i < n) ? ex[sv + ROW] : 0.0;
+        d.efc = (t < N && i < NX) ? ef[sv + ROW] : 0.0;  // dynamics row t
+        d.efm = (t > 0 && i < NX) ? ef[sv] : 0.0;        // dynamics row t-1
+        d.ef0 = (t == 0 && i < NX) ? ef[sv] : 0.0;       // initial-state rows
+        d.wc = (i < NG) ? wv[sv] : 0.0;
+        d.eg = (i < NG) ? eg[sv] : 0.0;
+        d.dl = (i < n) ? a.dLdx[(size_t)s * n + i] : 0.0;
+      };
+      auto comp = [&](const In& d, int blk, auto) {
+        const int t = 4 * blk + q;
+        if (t > N) return;  // the same on all lanes of a row
+        const int64_t s = s0 + t;
+        const size_t sv = (size_t)s * ROW + i;
+        const auto& B = d.B;
+        // H e_x
+        double he = dotb<n>(B.Dr, d.ec, 0.0);
+        he = dotb<n>(B.Er, d.em, he);
+        he = dotb<n>(B.Ec, d.en, he);
+        // J' e_y
+        double jte = dotb<NX>(B.Amc, d.efc, 0.0);
+        jte = dotb<NX>(B.Apcm, d.efm, jte);
+        jte += d.ef0;
+        const double wc = d.wc;
+        const bool slk = slr && wc != 0.0;
+        const double gx = dotb<n>(B.Gr, d.ec, 0.0);
+        // J' e_y over the hard active rows, plus the active slack rows' H term G_i'(gamma2 G_i e_x)
+        const double egv = (i < NG && wc != 0.0) ? (slk ? wc * gx : d.eg) : 0.0;
+        jte = dotb<NG>(B.Gc, egv, jte);
+        const double rx = d.dl - (he + jte);
+        // equality-row residuals -J e_x of the rows touching stage t
+        double cx = dotb<n>(B.Amr, d.ec, 0.0);
+        cx = dotb<n>(B.Apr, d.en, cx);
+        const double rfc = (t < N && i < NX) ? -cx : 0.0;  // dynamics row t
+        double cxm = dotb<n>(B.Amrm, d.em, 0.0);
+        cxm = dotb<n>(B.Aprm, d.ec, cxm);
+        const double rfm = (t > 0 && i < NX) ? -cxm : 0.0;  // dynamics row t-1
+        const double rf0 = (t == 0 && i < NX) ? -d.ec : 0.0;  // initial-state rows
+        const double rgc = (wc != 0.0 && !slk) ? -gx : 0.0;
+        double tc = dotb<NX>(B.Amc, rfc, 0.0);
+        tc = dotb<NX>(B.Apcm, rfm, tc);
+        tc += rf0;
+        double rhs = rx + rb * tc;
+        rhs = dotb<NG>(B.Gc, wc * rgc, rhs);
+        if (t == 0 && i < NX) rf[sv] = rf0;
+        if (t < N && i < NX) rf[sv + ROW] = rfc;
+        if (i < NG) rg[sv] = rgc;
+        R[(size_t)t * ROW] = rhs;
+      };
+      stage_blocks<D, In>(nfull, load, comp);
+    }
+    wave_sync();
+    // passes 2-4: d_x = S^{-1} rhs
+    if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
+    wave_sync();
+    {
+      auto load = [&](TrIn<double, n>& d, int blk) {
+        const int t = tcl(blk);
+        load_row<n>(d.Br, Pr + (size_t)t * nn, true);
+        d.v = R[(size_t)t * ROW];
+      };
+      auto comp = [&](const TrIn<double, n>& d, int blk, auto) {
+        const int t = 4 * blk + q;
+        if (t > N) return;
+        R[(size_t)t * ROW] = dotb<n>(d.Br, d.v, 0.0);
+      };
+      stage_blocks<D, TrIn<double, n>>(nfull, load, comp);
+    }
+    wave_sync();
+    if (q == 0) chain<double, n, -1>(Rb, Kbb0, orow, oblk, N);
+    wave_sync();
+    // pass 5: d_y = rho_b (J d_x - r_y), e += d
+    {
+      using In = AdjInTV5<NX, NU, NG>;
+      auto load = [&](In& d, int blk) {
+        const int t = tcl(blk);
+        const int64_t s = s0 + t;
+        const size_t sv = (size_t)s * ROW + i;
+        const size_t oa = ti_or_tv(L.ti, b, s, (size_t)NX * n);
+        load_row<n>(d.Amr, L.Am + oa + (size_t)ix * n, t < N);
+        load_row<n>(d.Apr, L.Ap + oa + (size_t)ix * n, t < N);
+        load_row<n>(d.Gr, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (size_t)ig * n, true);
+        d.dx = R[(size_t)t * ROW];
+        d.dn = (t < N) ? R[(size_t)(t + 1) * ROW] : 0.0;
+        d.efn = (t < N && i < NX) ? ef[sv + ROW] : 0.0;
+        d.rfn = (t < N && i < NX) ? rf[sv + ROW] : 0.0;
+        d.wc = (i < NG) ? wv[sv] : 0.0;
+        d.eg = (i < NG) ? eg[sv] : 0.0;
+        d.rg = (i < NG) ? rg[sv] : 0.0;
+        d.ef0 = (t == 0 && i < NX) ? ef[sv] : 0.0;
+        d.rf0 = (t == 0 && i < NX) ? rf[sv] : 0.0;
+        d.ex = (i < n) ? ex[sv] : 0.0;
+      };
+      auto comp = [&](const In& d, int blk, auto) {
+        const int t = 4 * blk + q;
+        if (t > N) return;
+        const size_t sv = (size_t)(s0 + t) * ROW + i;
+        double jd = dotb<n>(d.Amr, d.dx, 0.0);
+        jd = dotb<n>(d.Apr, d.dn, jd);
+        if (t < N && i < NX) ef[sv + ROW] = d.efn + rb * (jd - d.rfn);
+        const double gd = dotb<n>(d.Gr, d.dx, 0.0);
+        if (i < NG && d.wc != 0.0 && !slr) eg[sv] = d.eg + rb * (gd - d.rg);
+        if (t == 0 && i < NX) ef[sv] = d.ef0 + rb * (d.dx - d.rf0);
+        if (i < n) ex[sv] = d.ex + d.dx;
+      };
+      stage_blocks<D, In>(nfull, load, comp);
+    }
+    wave_sync();
+  }
+}
+
 template <typename T, int NX, int NU, int NG, typename ST>
 __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   constexpr int n = NX + NU;
@@ -380,104 +546,10 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   wave_sync();
 
   // ---- refinement sweeps ----
-  const gptr<double> R = as_global(a.v) + (size_t)s0 * ROW + i;
-  const gptr<const double> Pr = as_global((const double*)a.P) + (size_t)s0 * nn + (size_t)(i < n ? i : n - 1) * n;
-  // the chains take bases STAGE_PAD stages before stage 0 and lane offsets
-  const int64_t sp = s0 - STAGE_PAD;
-  const gptr<double> Rb = as_global(a.v) + sp * ROW;
-  const gptr<const double> Kb0 = as_global((const double*)a.K) + sp * (int64_t)nn;
-  const gptr<const double> Kbb0 = as_global((const double*)a.Kb) + sp * (int64_t)nn;
-  const uint32_t orow = (uint32_t)((STAGE_PAD * ROW + i) * (int)sizeof(double));
-  const uint32_t oblk = (uint32_t)((STAGE_PAD * (int)nn + (i < n ? i : n - 1) * n) * (int)sizeof(double));
   if constexpr (ST::TI) {
     adjoint_sweeps_ti<NX, NU, NG, ST>(L, a, w, bad);
   } else {
-    for (int sweep = 0; sweep < a.sweeps && !bad; ++sweep) {
-      // pass 1: residual r - K e and the Schur right-hand side
-      //   rhs_t = r_x,t + rho_b (C' r_f)_t + G_t'(w .* r_g,t)
-      for (int blk = 0; blk < nbl; ++blk) {
-        const int t = 4 * blk + q;
-        if (t > N) break;
-        const int64_t s = s0 + t;
-        const size_t sv = (size_t)s * ROW + i;
-        AdjBlocks<NX, NU, NG> B;
-        load_adj_blocks(B, L, b, s0, t, N, i);
-        const double ec = (i < n) ? ex[sv] : 0.0;
-        const double em = (t > 0 && i < n) ? ex[sv - ROW] : 0.0;
-        const double en = (t < N && i < n) ? ex[sv + ROW] : 0.0;
-        // H e_x
-        double he = dotb<n>(B.Dr, ec, 0.0);
-        he = dotb<n>(B.Er, em, he);
-        he = dotb<n>(B.Ec, en, he);
-        // J' e_y
-        const double efc = (t < N && i < NX) ? ef[sv + ROW] : 0.0;  // dynamics row t
-        const double efm = (t > 0 && i < NX) ? ef[sv] : 0.0;        // dynamics row t-1
-        double jte = dotb<NX>(B.Amc, efc, 0.0);
-        jte = dotb<NX>(B.Apcm, efm, jte);
-        if (t == 0 && i < NX) jte += ef[sv];  // initial-state rows
-        const double wc = (i < NG) ? wv[sv] : 0.0;
-        const bool slk = slr && wc != 0.0;
-        const double gx = dotb<n>(B.Gr, ec, 0.0);
-        // J' e_y over the hard active rows, plus the active slack rows' H term G_i'(gamma2 G_i e_x)
-        const double egv = (i < NG && wc != 0.0) ? (slk ? wc * gx : eg[sv]) : 0.0;
-        jte = dotb<NG>(B.Gc, egv, jte);
-        const double rx = ((i < n) ? a.dLdx[(size_t)s * n + i] : 0.0) - (he + jte);
-        // equality-row residuals -J e_x of the rows touching stage t
-        double cx = dotb<n>(B.Amr, ec, 0.0);
-        cx = dotb<n>(B.Apr, en, cx);
-        const double rfc = (t < N && i < NX) ? -cx : 0.0;  // dynamics row t
-        double cxm = dotb<n>(B.Amrm, em, 0.0);
-        cxm = dotb<n>(B.Aprm, ec, cxm);
-        const double rfm = (t > 0 && i < NX) ? -cxm : 0.0;  // dynamics row t-1
-        const double rf0 = (t == 0 && i < NX) ? -ec : 0.0;  // initial-state rows
-        const double rgc = (wc != 0.0 && !slk) ? -gx : 0.0;
-        double tc = dotb<NX>(B.Amc, rfc, 0.0);
-        tc = dotb<NX>(B.Apcm, rfm, tc);
-        tc += rf0;
-        double rhs = rx + rb * tc;
-        rhs = dotb<NG>(B.Gc, wc * rgc, rhs);
-        if (t == 0 && i < NX) rf[sv] = rf0;
-        if (t < N && i < NX) rf[sv + ROW] = rfc;
-        if (i < NG) rg[sv] = rgc;
-        R[(size_t)t * ROW] = rhs;
-      }
-      wave_sync();
-      // passes 2-4: d_x = S^{-1} rhs
-      if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
-      wave_sync();
-      for (int blk = 0; blk < nbl; ++blk) {
-        const int t = 4 * blk + q;
-        if (t > N) break;
-        double Prow[n];
-        load_row<n>(Prow, Pr + (size_t)t * nn, true);
-        R[(size_t)t * ROW] = dotb<n>(Prow, R[(size_t)t * ROW], 0.0);
-      }
-      wave_sync();
-      if (q == 0) chain<double, n, -1>(Rb, Kbb0, orow, oblk, N);
-      wave_sync();
-      // pass 5: d_y = rho_b (J d_x - r_y), e += d
-      for (int blk = 0; blk < nbl; ++blk) {
-        const int t = 4 * blk + q;
-        if (t > N) break;
-        const int64_t s = s0 + t;
-        const size_t sv = (size_t)s * ROW + i;
-        const double dx = R[(size_t)t * ROW];
-        const double dn = (t < N) ? R[(size_t)(t + 1) * ROW] : 0.0;
-        const size_t oa = ti_or_tv(L.ti, b, s, (size_t)NX * n);
-        double Amr[n], Apr[n], Gr[n];
-        load_row<n>(Amr, L.Am + oa + (size_t)(i < NX ? i : NX - 1) * n, t < N);
-        load_row<n>(Apr, L.Ap + oa + (size_t)(i < NX ? i : NX - 1) * n, t < N);
-        load_row<n>(Gr, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (size_t)(i < NG ? i : NG - 1) * n, true);
-        double jd = dotb<n>(Amr, dx, 0.0);
-        jd = dotb<n>(Apr, dn, jd);
-        if (t < N && i < NX) ef[sv + ROW] += rb * (jd - rf[sv + ROW]);
-        const double gd = dotb<n>(Gr, dx, 0.0);
-        if (i < NG && wv[sv] != 0.0 && !slr) eg[sv] += rb * (gd - rg[sv]);
-        if (t == 0 && i < NX) ef[sv] += rb * (dx - rf[sv]);
-        if (i < n) ex[sv] += dx;
-      }
-      wave_sync();
-    }
+    adjoint_sweeps_tv<NX, NU, NG>(L, a, w, bad, slr);
   }
 
   // ---- 3. VJP outputs ----
