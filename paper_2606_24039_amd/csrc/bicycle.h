@@ -82,12 +82,14 @@ __device__ __forceinline__ void bike_fc(const double* x, const double* u, double
   ju[0] = x[3] / (Lw * cd * cd);  // d yaw' / d delta (the only nonzero entry besides d v' / d a = 1)
 }
 
+template <int INTEG>
 __device__ __forceinline__ void bike_dynamics(const double* xt, const double* ut, const double* xn, double dt,
-                                              double Lw, int integ, double* f, double (*Am)[6], double (*Ap)[6]) {
+                                              double Lw, double* f, double (*Am)[6], double (*Ap)[6]) {
+  constexpr bool tr = INTEG == 1;
   double J0[4][4], J1[4][4], ju0 = 0.0, ju1 = 0.0;
   const bool jac = Am != nullptr;
   double f0[4];
-  if (integ == 1) {
+  if constexpr (tr) {
     double f1[4];
     bike_fc(xt, ut, Lw, f0, jac ? J0 : nullptr, &ju0);
     bike_fc(xn, ut, Lw, f1, jac ? J1 : nullptr, &ju1);
@@ -102,13 +104,15 @@ __device__ __forceinline__ void bike_dynamics(const double* xt, const double* ut
     for (int k = 0; k < 4; ++k) f[k] = xt[k] + dt * f0[k] - xn[k];
   }
   if (!jac) return;
-  const bool tr = integ == 1;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       Am[r][k] = (r == k ? 1.0 : 0.0) + 0.5 * dt * J0[r][k];
-      Ap[r][k] = (r == k ? -1.0 : 0.0) + 0.5 * dt * (tr ? J1[r][k] : J0[r][k]);
+      if constexpr (tr)
+        Ap[r][k] = (r == k ? -1.0 : 0.0) + 0.5 * dt * J1[r][k];
+      else
+        Ap[r][k] = (r == k ? -1.0 : 0.0) + 0.5 * dt * J0[r][k];
     }
     Am[r][4] = 0.0;
     Am[r][5] = 0.0;
@@ -118,6 +122,7 @@ __device__ __forceinline__ void bike_dynamics(const double* xt, const double* ut
   // control columns: d v' / d a = 1, d yaw' / d delta = ju
   Am[3][4] = dt;
   Am[2][5] = tr ? 0.5 * dt * (ju0 + ju1) : dt * ju0;
+  (void)ju1;
 }
 
 // SQP initial guess: the reference with zero controls.
@@ -142,7 +147,9 @@ __global__ void bike_init_kernel(Layout L, BikeArgs a, double rho0) {
 
 // Convexify at xbar (one thread per global stage) and warm-start the ADMM
 // state from the SQP iterate: x = xbar, y = ybar, z_g = G xbar.
-template <typename T>
+// INTEG: the discretisation (0 implicit midpoint, 1 trapezoidal rule), a
+// compile-time choice so that each kernel holds one rule's code.
+template <typename T, int INTEG>
 __global__ void bike_linearize_kernel(Layout L, BikeArgs a) {
   const int64_t S = L.stage_off[L.B];
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -171,7 +178,7 @@ __global__ void bike_linearize_kernel(Layout L, BikeArgs a) {
   if (t < N) {
     const double* xn = a.xbar + (s + 1) * ROW;
     double f[4], Ml[4][6], Mr[4][6];
-    bike_dynamics(xb, xb + 4, xn, a.dt, a.Lw, a.integ, f, Ml, Mr);
+    bike_dynamics<INTEG>(xb, xb + 4, xn, a.dt, a.Lw, f, Ml, Mr);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       double acc = -f[r];
@@ -283,7 +290,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // Line search and SQP bookkeeping, one wavefront per instance.  Lane i
 // handles the stages t = i, i+64, ...; per-candidate sums are wavefront
 // reductions.
-template <typename T>
+template <typename T, int INTEG>
 __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs a) {
   constexpr int NA = 8;  // alpha in {1, 1/2, ..., 1/128}
   constexpr int WL = 64;  // lanes per instance
@@ -344,7 +351,7 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
       if (t < N) {
         bike_point(a, xbn, dxn, al, zn);
         double f[4];
-        bike_dynamics(z, z + 4, zn, a.dt, a.Lw, a.integ, f, nullptr, nullptr);
+        bike_dynamics<INTEG>(z, z + 4, zn, a.dt, a.Lw, f, nullptr, nullptr);
 #pragma unroll
         for (int k = 0; k < 4; ++k) v += fabs(f[k]);
       }
@@ -423,7 +430,7 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     double f[4], Ml[4][6], Mr[4][6];
     if (t < N) {  // dynamics row t (slot t): A_t^-' y
       const double* yf = a.yfbar + s * ROW;
-      bike_dynamics(xb, xb + 4, xb + ROW, a.dt, a.Lw, a.integ, f, Ml, Mr);
+      bike_dynamics<INTEG>(xb, xb + 4, xb + ROW, a.dt, a.Lw, f, Ml, Mr);
 #pragma unroll
       for (int k = 0; k < 6; ++k)
 #pragma unroll
@@ -434,7 +441,7 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     if (t > 0) {  // dynamics row t-1 (slot t-1): A_{t-1}^+' y
       const double* yf = a.yfbar + (s - 1) * ROW;
       const double* xp = xb - ROW;
-      bike_dynamics(xp, xp + 4, xb, a.dt, a.Lw, a.integ, f, Ml, Mr);
+      bike_dynamics<INTEG>(xp, xp + 4, xb, a.dt, a.Lw, f, Ml, Mr);
 #pragma unroll
       for (int k = 0; k < 6; ++k)
 #pragma unroll

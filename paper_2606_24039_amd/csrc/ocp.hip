@@ -626,16 +626,20 @@ ocp_status bicycle_sqp(ocp_handle h, const ocp_settings* s, hipStream_t st) {
   for (int k = 0; k < s->max_sqp; ++k) {
     timed(pf, OCP_K_SQP, st, [&] {
       if (h->mixed)
-        hipLaunchKernelGGL(bike_linearize_kernel<float>, dim3(gs), dim3(256), 0, st, L, a);
+        hipLaunchKernelGGL((a.integ ? bike_linearize_kernel<float, 1> : bike_linearize_kernel<float, 0>), dim3(gs),
+                           dim3(256), 0, st, L, a);
       else
-        hipLaunchKernelGGL(bike_linearize_kernel<double>, dim3(gs), dim3(256), 0, st, L, a);
+        hipLaunchKernelGGL((a.integ ? bike_linearize_kernel<double, 1> : bike_linearize_kernel<double, 0>), dim3(gs),
+                           dim3(256), 0, st, L, a);
     });
     run_admm(h, ad, st);
     timed(pf, OCP_K_SQP, st, [&] {
       if (h->mixed)
-        hipLaunchKernelGGL(bike_linesearch_kernel<float>, dim3(h->B), dim3(64), 0, st, L, a);
+        hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<float, 1> : bike_linesearch_kernel<float, 0>), dim3(h->B),
+                           dim3(64), 0, st, L, a);
       else
-        hipLaunchKernelGGL(bike_linesearch_kernel<double>, dim3(h->B), dim3(64), 0, st, L, a);
+        hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<double, 1> : bike_linesearch_kernel<double, 0>),
+                           dim3(h->B), dim3(64), 0, st, L, a);
     });
   }
   return hip_ok(hipGetLastError());
