@@ -110,3 +110,16 @@ def test_trapezoidal_rule_follows_the_oracle_fp64(seg):
         assert abs(kkt[0] - ref.stop["stationarity"]) < 1e-7 * max(1, ref.stop["stationarity"])
         assert abs(kkt[1] - ref.stop["eq"]) < 1e-9 + 1e-7 * ref.stop["eq"]
     s.close()
+
+
+def test_unknown_discretisation_rule_is_rejected():
+    from paper_2606_24039_amd import _abi as A
+    from paper_2606_24039_amd.solver import OCPSolver
+
+    b = bicycle_batch(1, N=10, seed=3)
+    b.integrator = 2
+    s = OCPSolver(4, 2, 3, b.horizons, model=A.MODEL_BICYCLE, precision=FP64)
+    with pytest.raises(A.OCPError) as e:
+        s.set_bicycle(b)
+    assert e.value.code == A.OCP_E_ARG
+    s.close()
