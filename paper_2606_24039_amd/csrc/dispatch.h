@@ -1,0 +1,113 @@
+// Dispatch of the compiled stage shapes: kernel timing, the launch
+// functions of the persistent solve and the adjoint, and the table entry of
+// one (nx, nu, ng, iteration precision).  Each entry is instantiated in its
+// own translation unit (inst.hip, compiled once per shape and precision).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "adjoint.h"
+#include "ocp_admm.h"
+#include "wave.h"
+
+namespace ocpk {
+
+// ---------------------------------------------------------------------------
+// kernel timing: optional HIP-event pairs around the solver's launches, by
+// kernel class (ocp_kernel_class).  Off by default; events are created on
+// first use and recycled after each read.
+// ---------------------------------------------------------------------------
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // 2 per recorded launch
+  std::vector<int> cls;
+  size_t used = 0;
+  double ms[OCP_K_COUNT] = {0};
+  int64_t launches[OCP_K_COUNT] = {0};
+
+  bool begin(int c, hipStream_t st) {
+    if (!on) return false;
+    if (2 * used + 2 > ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return false;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return false;
+      }
+      ev.push_back(a);
+      ev.push_back(b);
+      cls.push_back(c);
+    }
+    cls[used] = c;
+    (void)hipEventRecord(ev[2 * used], st);
+    return true;
+  }
+  void end(hipStream_t st) { (void)hipEventRecord(ev[2 * used++ + 1], st); }
+  hipError_t collect() {
+    for (size_t k = 0; k < used; ++k) {
+      hipError_t e = hipEventSynchronize(ev[2 * k + 1]);
+      if (e != hipSuccess) return e;
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
+      if (e != hipSuccess) return e;
+      ms[cls[k]] += t;
+      launches[cls[k]] += 1;
+    }
+    used = 0;
+    return hipSuccess;
+  }
+  void release() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    cls.clear();
+    used = 0;
+  }
+};
+
+// launch `f` bracketed by a timing pair of class `c` when timing is on
+template <typename F>
+void timed(Prof* p, int c, hipStream_t st, F&& f) {
+  const bool t = p && p->begin(c, st);
+  f();
+  if (t) p->end(st);
+}
+
+// ---------------------------------------------------------------------------
+// dispatch table: one instantiation per compiled (nx, nu, ng)
+// ---------------------------------------------------------------------------
+using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, hipStream_t, Prof*);
+using AdjFn = void (*)(const Layout&, const AdjArgs&, hipStream_t, Prof*);
+
+// One ADMM solve: per-solve initialisation, then one wavefront per instance
+// runs the whole of Algorithm 3 (factorisation, iterations, FP64 checks, rho
+// adaptation and refactorisation) without waiting for other instances.
+template <typename T, int NX, int NU, int NG, typename ST>
+void launch_solve(const Layout& L, const Settings& s, int32_t* need, hipStream_t st, Prof* pf) {
+  timed(pf, OCP_K_OTHER, st,
+        [&] { hipLaunchKernelGGL((admm_init_kernel<T>), dim3(L.init_blocks), dim3(256), 0, st, L, s, need); });
+  timed(pf, OCP_K_SOLVE, st,
+        [&] { hipLaunchKernelGGL((admm_solve_wave_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, s); });
+}
+
+// one instance per wavefront
+template <typename T, int NX, int NU, int NG, typename ST>
+void launch_adjoint(const Layout& L, const AdjArgs& a, hipStream_t st, Prof* pf) {
+  timed(pf, OCP_K_ADJOINT, st,
+        [&] { hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, a); });
+}
+
+// structure variants of the iteration kernel
+enum { VAR_TV = 0, VAR_TI = 1, VAR_LTI_BOX = 2 };
+using StTV = Structure<false, false, false>;
+using StTI = Structure<true, false, false>;
+using StBox = Structure<true, true, true>;
+
+// launch functions of one shape and iteration precision, by structure variant
+struct PrecEntry {
+  SolveFn solve[3];
+  AdjFn adj[3];
+};
+
+}  // namespace ocpk

@@ -10,135 +10,39 @@
 #include <numeric>
 #include <vector>
 
-#include "admm.h"
-#include "adjoint.h"
 #include "bicycle.h"
+#include "dispatch.h"
 #include "ocp_admm.h"
 #include "setup.h"
-#include "wave.h"
 
 using namespace ocpk;
 
 namespace {
 
-// instances per workgroup (one 16-lane row each)
-constexpr int kRowsPerWave = 4;
-
-// ---------------------------------------------------------------------------
-// kernel timing: optional HIP-event pairs around the solver's launches, by
-// kernel class (ocp_kernel_class).  Off by default; events are created on
-// first use and recycled after each read.
-// ---------------------------------------------------------------------------
-struct Prof {
-  bool on = false;
-  std::vector<hipEvent_t> ev;  // 2 per recorded launch
-  std::vector<int> cls;
-  size_t used = 0;
-  double ms[OCP_K_COUNT] = {0};
-  int64_t launches[OCP_K_COUNT] = {0};
-
-  bool begin(int c, hipStream_t st) {
-    if (!on) return false;
-    if (2 * used + 2 > ev.size()) {
-      hipEvent_t a, b;
-      if (hipEventCreate(&a) != hipSuccess) return false;
-      if (hipEventCreate(&b) != hipSuccess) {
-        (void)hipEventDestroy(a);
-        return false;
-      }
-      ev.push_back(a);
-      ev.push_back(b);
-      cls.push_back(c);
-    }
-    cls[used] = c;
-    (void)hipEventRecord(ev[2 * used], st);
-    return true;
-  }
-  void end(hipStream_t st) { (void)hipEventRecord(ev[2 * used++ + 1], st); }
-  hipError_t collect() {
-    for (size_t k = 0; k < used; ++k) {
-      hipError_t e = hipEventSynchronize(ev[2 * k + 1]);
-      if (e != hipSuccess) return e;
-      float t = 0.f;
-      e = hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
-      if (e != hipSuccess) return e;
-      ms[cls[k]] += t;
-      launches[cls[k]] += 1;
-    }
-    used = 0;
-    return hipSuccess;
-  }
-  void release() {
-    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-    ev.clear();
-    cls.clear();
-    used = 0;
-  }
-};
-
-// launch `f` bracketed by a timing pair of class `c` when timing is on
-template <typename F>
-void timed(Prof* p, int c, hipStream_t st, F&& f) {
-  const bool t = p && p->begin(c, st);
-  f();
-  if (t) p->end(st);
-}
-
-// ---------------------------------------------------------------------------
-// dispatch table: one instantiation per compiled (nx, nu, ng)
-// ---------------------------------------------------------------------------
-using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, hipStream_t, Prof*);
-using AdjFn = void (*)(const Layout&, const AdjArgs&, hipStream_t, Prof*);
-
-// One ADMM solve: per-solve initialisation, then one wavefront per instance
-// runs the whole of Algorithm 3 (factorisation, iterations, FP64 checks, rho
-// adaptation and refactorisation) without waiting for other instances.
-template <typename T, int NX, int NU, int NG, typename ST>
-void launch_solve(const Layout& L, const Settings& s, int32_t* need, hipStream_t st, Prof* pf) {
-  timed(pf, OCP_K_OTHER, st,
-        [&] { hipLaunchKernelGGL((admm_init_kernel<T>), dim3(L.init_blocks), dim3(256), 0, st, L, s, need); });
-  timed(pf, OCP_K_SOLVE, st,
-        [&] { hipLaunchKernelGGL((admm_solve_wave_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, s); });
-}
-
-// one instance per wavefront
-template <typename T, int NX, int NU, int NG, typename ST>
-void launch_adjoint(const Layout& L, const AdjArgs& a, hipStream_t st, Prof* pf) {
-  timed(pf, OCP_K_ADJOINT, st,
-        [&] { hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, a); });
-}
-
-// structure variants of the iteration kernel
-enum { VAR_TV = 0, VAR_TI = 1, VAR_LTI_BOX = 2 };
-using StTV = Structure<false, false, false>;
-using StTI = Structure<true, false, false>;
-using StBox = Structure<true, true, true>;
-
 struct Entry {
   int nx, nu, ng;
-  SolveFn f64[3];  // [variant]
-  SolveFn f32[3];
-  AdjFn adj64[3];  // [variant]
-  AdjFn adj32[3];
+  const PrecEntry* (*p64)();  // FP64 iterations
+  const PrecEntry* (*p32)();  // FP32 iterations over the FP64 factorisation
 };
 
-#define OCP_ENTRY(NX, NU, NG)                                                                       \
-  Entry {                                                                                           \
-    NX, NU, NG,                                                                                     \
-        {launch_solve<double, NX, NU, NG, StTV>, launch_solve<double, NX, NU, NG, StTI>,            \
-         launch_solve<double, NX, NU, NG, StBox>},                                                  \
-        {launch_solve<float, NX, NU, NG, StTV>, launch_solve<float, NX, NU, NG, StTI>,              \
-         launch_solve<float, NX, NU, NG, StBox>},                                                   \
-        {launch_adjoint<double, NX, NU, NG, StTV>, launch_adjoint<double, NX, NU, NG, StTI>,        \
-         launch_adjoint<double, NX, NU, NG, StBox>},                                                \
-        {launch_adjoint<float, NX, NU, NG, StTV>, launch_adjoint<float, NX, NU, NG, StTI>,          \
-         launch_adjoint<float, NX, NU, NG, StBox>},                                                 \
-  }
+}  // namespace
+
+// one translation unit per compiled shape and precision (inst.hip)
+namespace ocpk {
+const PrecEntry* ocp_entry_4_2_4_f64();  // 2-D double integrator
+const PrecEntry* ocp_entry_4_2_4_f32();
+const PrecEntry* ocp_entry_12_4_16_f64();  // random LTI, all variables boxed
+const PrecEntry* ocp_entry_12_4_16_f32();
+const PrecEntry* ocp_entry_4_2_3_f64();  // kinematic bicycle
+const PrecEntry* ocp_entry_4_2_3_f32();
+}  // namespace ocpk
+
+namespace {
 
 const Entry kTable[] = {
-    OCP_ENTRY(4, 2, 4),    // 2-D double integrator, positions and controls boxed
-    OCP_ENTRY(12, 4, 16),  // random LTI, all stage variables boxed
-    OCP_ENTRY(4, 2, 3),    // kinematic bicycle: a, delta, lateral offset
+    {4, 2, 4, ocp_entry_4_2_4_f64, ocp_entry_4_2_4_f32},
+    {12, 4, 16, ocp_entry_12_4_16_f64, ocp_entry_12_4_16_f32},
+    {4, 2, 3, ocp_entry_4_2_3_f64, ocp_entry_4_2_3_f32},
 };
 
 const Entry* find_entry(int nx, int nu, int ng) {
@@ -572,9 +476,9 @@ void run_admm(ocp_handle h, const Settings& s_, hipStream_t st) {
   const int ti = h->ti ? 1 : 0;
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (ti ? VAR_TI : VAR_TV);
   if (h->mixed)
-    h->entry->f32[var](L, s, h->need, st, &h->prof);
+    h->entry->p32()->solve[var](L, s, h->need, st, &h->prof);
   else
-    h->entry->f64[var](L, s, h->need, st, &h->prof);
+    h->entry->p64()->solve[var](L, s, h->need, st, &h->prof);
 }
 
 BikeArgs make_bike(ocp_handle h, const ocp_settings* s) {
@@ -907,9 +811,9 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   const Layout L = make_layout(h);
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (h->ti ? VAR_TI : VAR_TV);
   if (h->mixed)
-    h->entry->adj32[var](L, a, st, &h->prof);
+    h->entry->p32()->adj[var](L, a, st, &h->prof);
   else
-    h->entry->adj64[var](L, a, st, &h->prof);
+    h->entry->p64()->adj[var](L, a, st, &h->prof);
   return hip_ok(hipGetLastError());
 }
 
