@@ -37,6 +37,7 @@ against the dense solve.
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
@@ -46,8 +47,10 @@ from .qp import HARD, SOFT_L1, SOFT_L2, StageQP
 def active_set(qp: StageQP, x, y_g, xi=None, eps_g=None, eps_solve=1e-4):
     """Lower/upper active masks by the rule of Appendix "Active constraints
     identification": the dual sign decides; closeness to a bound only when the
-    dual is ambiguous (|y| < eps_g).  eps_g = 10 eps_solve max(1, ||y_g||_inf)
-    for the dual test; the proximity test uses eps_g max(1, |bound|).
+    dual is ambiguous (|y| < eps_g).  The tolerance combines an absolute and a
+    relative part on each side: eps_g = 10 eps_solve max(1, ||y_g||_inf) for
+    the dual test (relative to the multipliers), 10 eps_solve max(1, |bound|)
+    for the proximity test (relative to the bound, as the paper's eps_g |g_i|).
     Rows whose L1 slack is nonzero are returned in neither mask.
     """
     _, _, G, _, _, lo, hi = qp.matrices()
@@ -55,9 +58,10 @@ def active_set(qp: StageQP, x, y_g, xi=None, eps_g=None, eps_solve=1e-4):
     y_g = np.asarray(y_g, float)
     if eps_g is None:
         eps_g = 10.0 * eps_solve * max(1.0, float(np.max(np.abs(y_g))) if y_g.size else 1.0)
+    eps_p = 10.0 * eps_solve
     amb = np.abs(y_g) < eps_g
-    lower = (y_g < -eps_g) | (amb & (g - lo <= eps_g * np.maximum(1.0, np.abs(lo))))
-    upper = (y_g > eps_g) | (amb & (hi - g <= eps_g * np.maximum(1.0, np.abs(hi))))
+    lower = (y_g < -eps_g) | (amb & (g - lo <= eps_p * np.maximum(1.0, np.abs(lo))))
+    upper = (y_g > eps_g) | (amb & (hi - g <= eps_p * np.maximum(1.0, np.abs(hi))))
     both = lower & upper
     lower = lower & ~(both & (y_g > 0))
     upper = upper & ~(both & ~(y_g > 0))
@@ -118,12 +122,47 @@ def polish(qp: StageQP, x, y_g, xi=None, eps_solve=1e-4, tol=1e-9):
     return ok, {"x": xs, "y_f": yf, "y_g": yg, "z_g": g, "xi": xis, "lower": lower, "upper": upper}
 
 
+DENSE_LIMIT = 4e7  # entries of the largest J given to the dense rank test (about 320 MB)
+
+
+def independent_rows(qp: StageQP, lower, upper, rtol=1e-9) -> bool:
+    """True if the rows of J = [C; G_A] (hard active rows; active L2-slack
+    rows carry their own diagonal and never make K singular) are linearly
+    independent (LICQ), by the pivoted QR of J' (rank = number of diagonal
+    entries of R above rtol times the largest).  Problems whose J has more
+    than DENSE_LIMIT entries (the long horizons) are not tested and taken as
+    independent."""
+    _, C, G, *_ = qp.matrices()
+    act = (lower | upper) & (qp.soft_rows() != SOFT_L2)
+    J = sp.vstack([C, G[np.flatnonzero(act)]])
+    if J.shape[0] > J.shape[1]:
+        return False
+    if J.shape[0] * J.shape[1] > DENSE_LIMIT:
+        return True  # too large for a dense rank test: taken as independent
+    R = sla.qr(J.toarray().T, mode="r", pivoting=True)[0]
+    d = np.abs(np.diag(R))
+    return bool(d.size == 0 or d.min() > rtol * d.max())
+
+
 def adjoint_dense(qp: StageQP, x, dL_dx, lower, upper, H=None):
-    """eta = K^{-1} (dL/dx, 0, 0) by a direct sparse LU (the definition)."""
+    """eta = K^{-1} (dL/dx, 0, 0) by a direct sparse LU (the definition).
+
+    When the active rows are linearly dependent (LICQ fails; at eps 1e-4 this
+    happens on unconverged instances), K is singular but the system stays
+    consistent: eta_x is unique (H is positive definite) and eta_y is
+    determined up to the null space of J'.  The result is then the
+    minimum-norm solution K^+ (dL/dx, 0, 0) by a dense least-squares solve
+    (singular values below 1e-12 of the largest taken as zero),
+    whose eta_y lies in the range of J -- the limit of the regularised
+    refinement started from zero (its eta_y updates are rho_b (J e_x - r_y)).
+    """
     K, *_ , act = _kkt(qp, lower, upper, H)
     nv, ne = qp.nvar, qp.neq
     rhs = np.concatenate([dL_dx, np.zeros(ne + int(act.sum()))])
-    eta = spla.spsolve(K, rhs)
+    if independent_rows(qp, lower, upper):
+        eta = spla.spsolve(K, rhs)
+    else:
+        eta = sla.lstsq(K.toarray(), rhs, cond=1e-12, lapack_driver="gelsd")[0]
     eta_g = np.zeros(qp.nineq)
     eta_g[act] = eta[nv + ne:]
     return eta[:nv], eta[nv:nv + ne], eta_g

@@ -73,6 +73,7 @@ class ADMMResult:
     r_dual: float
     n_factor: int
     history: list = field(default_factory=list)
+    rho_changes: list = field(default_factory=list)  # (iteration, accepted rho-bar)
 
 
 def project(v, lo, hi, kind, rho_g, gamma2, gamma1):
@@ -123,6 +124,25 @@ def slack_dual_terms(xi, y_g, kind, gamma2, gamma1):
         res = np.concatenate([res, r1])
         scale = np.concatenate([scale, gamma1 * (x1 != 0.0), np.abs(y1)])
     return res, scale
+
+
+def rho_update(rho_bar, r_prim, r_dual, prim_scale, dual_scale, st: ADMMSettings):
+    """Step-size candidate of eq. rho:update and its acceptance rule.
+
+    The candidate scales rho-bar by the square root of the ratio of the
+    normalised primal residual r_prim / prim_scale to the normalised dual
+    residual r_dual / dual_scale, clipped to [rho_min, rho_max]; every
+    normaliser is floored at 1e-30 (reading R7).  It is accepted only when it
+    differs from the current value by more than the factor k_ratio in either
+    direction.  The caller asks only when the iterate is not converged.
+    Returns (candidate, accepted).  Pinned by hand-derived cases in
+    tests/golden/rho_update.json.
+    """
+    num = r_prim / max(prim_scale, 1e-30)
+    den = r_dual / max(dual_scale, 1e-30)
+    cand = rho_bar * np.sqrt(num / max(den, 1e-30))
+    cand = float(np.clip(cand, st.rho_min, st.rho_max))
+    return cand, bool(max(cand / rho_bar, rho_bar / cand) > st.k_ratio)
 
 
 def _inf(v) -> float:
@@ -195,6 +215,7 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
         return M.factor(st.sigma, st.rho_f_scale * rb, rb)
 
     history = []
+    rho_changes = []
     n_factor = 0
     try:
         cf = factor(rho_bar)
@@ -233,19 +254,17 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
                 status = CONVERGED
                 break
             if adapt and not conv:
-                num = r_prim / max(ps, 1e-30)
-                den = r_dual / max(ds, 1e-30)
-                cand = rho_bar * np.sqrt(num / max(den, 1e-30))
-                cand = float(np.clip(cand, st.rho_min, st.rho_max))
-                if max(cand / rho_bar, rho_bar / cand) > st.k_ratio:
+                cand, accept = rho_update(rho_bar, r_prim, r_dual, ps, ds, st)
+                if accept:
                     rho_bar = cand
+                    rho_changes.append((k, rho_bar))
                     try:
                         cf = factor(rho_bar)
                         n_factor += 1
                     except np.linalg.LinAlgError:
                         status = FACTOR_BREAKDOWN
                         break
-    return ADMMResult(x, z_g, xi, y_f, y_g, rho_bar, k, status, r_prim, r_dual, n_factor, history)
+    return ADMMResult(x, z_g, xi, y_f, y_g, rho_bar, k, status, r_prim, r_dual, n_factor, history, rho_changes)
 
 
 def kkt_residuals(qp: StageQP, x, z_g, xi, y_f, y_g):

@@ -7,8 +7,9 @@
 // 1. Active set (Appendix, "Active constraints identification"): the dual
 //    sign decides (y < -eps_g lower, y > eps_g upper); closeness to a bound is
 //    used only when |y| < eps_g.  eps_g = 10 eps_active max(1, ||y_g||_inf);
-//    proximity tolerance eps_g max(1, |bound|).  L1-slack rows with nonzero
-//    slack keep their fixed multiplier and are not active.
+//    proximity tolerance 10 eps_active max(1, |bound|) (relative to the bound,
+//    not to the multipliers).  L1-slack rows with nonzero slack keep their
+//    fixed multiplier and are not active.
 // 2. The KKT matrix of the active-set conditions (eq. bwd:noslack_kkt_matrix)
 //      K = [[H, J'], [J, 0]],  J = [C; G_A]
 //    has a zero (2,2) block and no Schur form.  Its regularisation
@@ -495,7 +496,8 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     if (t <= N && i < NG) ymax = fmax(ymax, fabs(double(YG[(size_t)(s0 + t) * ROW + i])));
   }
   ymax = rows_max(row_max(ymax));
-  const double epsg = 10.0 * a.eps_active * fmax(1.0, ymax);
+  const double epsg = 10.0 * a.eps_active * fmax(1.0, ymax);  // dual test, relative to the multipliers
+  const double epsp = 10.0 * a.eps_active;                     // proximity test, relative to the bound
   for (int blk = 0; blk < nbl; ++blk) {
     const int t = 4 * blk + q;
     if (t > N) break;
@@ -510,8 +512,8 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
       const size_t sb = ti_or_tv(L.ti, b, s, NG) + i;
       const double lo = L.lo[sb], hi = L.hi[sb], y = double(YG[sv]);
       const bool amb = fabs(y) < epsg;
-      bool lower = (y < -epsg) || (amb && (gx - lo <= epsg * fmax(1.0, fabs(lo))));
-      bool upper = (y > epsg) || (amb && (hi - gx <= epsg * fmax(1.0, fabs(hi))));
+      bool lower = (y < -epsg) || (amb && (gx - lo <= epsp * fmax(1.0, fabs(lo))));
+      bool upper = (y > epsg) || (amb && (hi - gx <= epsp * fmax(1.0, fabs(hi))));
       if (lower && upper) {
         if (y > 0)
           lower = false;

@@ -150,3 +150,61 @@ def test_l2_slack_refinement_equals_dense_adjoint():
     e2 = adjoint_refined(qp, sol["x"], g, sol["lower"], sol["upper"], sweeps=6)
     for a, c in zip(e1, e2):
         np.testing.assert_allclose(c, a, rtol=1e-9, atol=1e-11 * max(1.0, np.abs(a).max()))
+
+
+def _dependent_active_set():
+    """Random LTI QP solved exactly, with the stage-0 state rows added to the
+    active set: x_0 is already fixed by the initial-state rows, so each added
+    row duplicates one of them (LICQ fails, K is singular)."""
+    b = random_lti(1, N=8, seed=45)
+    L, g, sol = implicit_theta_grad(b, 0)
+    qp = qp_of_theta(b, 0, theta_of(b, 0))
+    _, gx = loss_and_grad_x(qp, sol["x"])
+    lower, upper = sol["lower"].copy(), sol["upper"].copy()
+    ng = qp.ng
+    extra = np.zeros_like(lower)
+    extra[:b.nx] = True  # rows 0..nx-1 of stage 0 select x_0 (G = I on the box rows)
+    assert not np.any((lower | upper) & extra)
+    return qp, sol, gx, lower, upper, lower | extra
+
+
+def test_dependent_active_rows_give_the_minimum_norm_adjoint():
+    from oracle.adjoint import independent_rows
+
+    qp, sol, gx, lower, upper, lower_dep = _dependent_active_set()
+    assert independent_rows(qp, lower, upper)
+    assert not independent_rows(qp, lower_dep, upper)
+    ex0, ef0, eg0 = adjoint_dense(qp, sol["x"], gx, lower, upper)
+    ex, ef, eg = adjoint_dense(qp, sol["x"], gx, lower_dep, upper)
+    nx = qp.nx
+    # eta_x is unique: a duplicated row changes nothing
+    np.testing.assert_allclose(ex, ex0, rtol=1e-9, atol=1e-11)
+    # two identical rows share the multiplier evenly in the minimum-norm
+    # solution: each gets half of what the single row carried
+    np.testing.assert_allclose(ef[:nx], 0.5 * ef0[:nx], rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(eg[:nx], 0.5 * ef0[:nx], rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(ef[nx:], ef0[nx:], rtol=1e-9, atol=1e-11)
+    # and the regularised refinement from zero (the GPU scheme) reaches it
+    rx, rf, rg = adjoint_refined(qp, sol["x"], gx, lower_dep, upper, sweeps=8)
+    for a, c in ((ex, rx), (ef, rf), (eg, rg)):
+        np.testing.assert_allclose(c, a, rtol=1e-7, atol=1e-9 * max(1.0, np.abs(a).max()))
+
+
+def test_proximity_tolerance_does_not_scale_with_the_multipliers():
+    """Appendix "Active constraints identification": closeness to a bound is
+    measured relative to the bound.  With ||y_g||_inf = 1e4 the dual threshold
+    is 10 * 1e-4 * 1e4 = 10, but a row with y = 0 sitting 5 below its upper
+    bound 10 is not near it (proximity tolerance 10 * 1e-4 * 10 = 1e-2)."""
+    from oracle.adjoint import active_set
+
+    b = random_lti(1, N=2, seed=46)
+    qp = qp_of_theta(b, 0, theta_of(b, 0))
+    x = np.zeros(qp.nvar)
+    n = qp.n
+    x[n + 0] = 5.0          # stage 1, state 0: 5 from the bound 10
+    x[n + 1] = 10.0 - 5e-3  # stage 1, state 1: within 1e-2 of the bound
+    y = np.zeros(qp.nineq)
+    y[2 * qp.ng + 3] = 1e4  # a large multiplier elsewhere
+    lower, upper = active_set(qp, x, y, eps_solve=1e-4)
+    assert not upper[qp.ng + 0] and upper[qp.ng + 1]
+    assert upper[2 * qp.ng + 3] and not lower[2 * qp.ng + 3]
