@@ -29,12 +29,25 @@ PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E (published)
 
 # HBM traffic of the persistent solve launch, per launch, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) of `bench.py --steps 1 --warmup 0
-# --cpu-sample 0 --no-fp64`, each scaled by the same counter's reading for a
-# plain 1 GiB device copy (`bench.py --copy-calibration 1024`: FETCH_SIZE
-# reads 0.500 of the copied bytes, WRITE_SIZE 1.000).  Summary and commands:
-# profiles/admm_solve_wave_lti1024_n50.md.  Keyed by (workload, precision);
-# valid for the kernel as profiled -- set to None when the kernel changes.
-TRAFFIC_BYTES = {("c2", "mixed"): (23642190.2 * 1.99994 + 2015575.9 * 1.0) * 1024}
+# --cpu-sample 0 --no-fp64 --no-sub`, each scaled by the same counter's reading
+# for a plain 1 GiB device copy (`bench.py --copy-calibration 1024`).  Keyed by
+# (workload, precision, hash of the kernel sources): a changed kernel reports
+# null until it is profiled again.  Summary and commands:
+# profiles/admm_solve_wave_lti1024_n50.md.
+TRAFFIC_BYTES = {}
+
+
+def kernel_source_hash() -> str:
+    """sha256 (16 hex digits) over the HIP sources of the library."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2606_24039_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -82,21 +95,24 @@ def make_workload(name):
 
 def cpu_baseline(batch, sample, settings_kw, grad):
     """The FP64 oracle on the host cores, one instance per task: the ADMM
-    solve and (with grad) the dense-LU adjoint of the same instance."""
+    solve and (with grad) the active-set adjoint of the same instance.  Uses
+    every core of the affinity mask up to 16, the CPU share of one GPU on the
+    benchmark hosts."""
     import multiprocessing as mp
 
     global _CPU_BATCH
     _CPU_BATCH = batch
-    cores = min(len(os.sched_getaffinity(0)), 16, sample)
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16, sample))
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores, initializer=_worker_init) as pool:
-        res = pool.map(_oracle_one, [(i, settings_kw, grad) for i in range(sample)])
+        res = pool.map(_oracle_one, [(i, settings_kw, grad) for i in range(sample)], chunksize=1)
     wall = time.perf_counter() - t0
     solved = sum(1 for ok, _ in res if ok)
     iters = sum(it for _, it in res)
     return {"value": solved / wall, "unit": "QP solves/s", "cores": cores, "kind": "oracle",
             "sample": (f"first {sample} of {batch.batch} instances, FP64 NumPy/SciPy oracle, eps 1e-4"
-                       + (", ADMM solve + sparse-LU adjoint" if grad else ", ADMM solve")),
+                       + (", ADMM solve + active-set adjoint (sparse LU; minimum-norm where the active rows "
+                          "are dependent)" if grad else ", ADMM solve")),
             "solved": solved, "wall_s": round(wall, 3), "admm_iters_per_s": iters / wall}
 
 
@@ -121,23 +137,12 @@ def _oracle_one(args):
     qp = lti_batch_qp(batch, i)
     r = admm_solve(qp, ADMMSettings(**kw))
     if grad:
-        from oracle.adjoint import active_set, adjoint_dense, adjoint_refined, qp_vjp
+        from oracle.adjoint import active_set, adjoint_dense, qp_vjp
 
         S = batch.N + 1
         dl = upstream_gradient(batch)[i * S:(i + 1) * S].reshape(-1)
         lower, upper = active_set(qp, r.x, r.y_g, r.xi)
-        import warnings
-
-        with warnings.catch_warnings():
-            warnings.simplefilter("ignore")
-            try:  # sparse LU of the KKT matrix (the definition)
-                ex, ef, eg = adjoint_dense(qp, r.x, dl, lower, upper)
-            except RuntimeError:
-                ex = None
-        if ex is None or not np.all(np.isfinite(ex)):
-            # dependent active rows make K singular: the regularised
-            # refinement (the GPU's scheme) is still defined
-            ex, ef, eg = adjoint_refined(qp, r.x, dl, lower, upper, sigma_b=1e-9, rho_b=1e6, sweeps=6)
+        ex, ef, eg = adjoint_dense(qp, r.x, dl, lower, upper)
         qp_vjp(qp, r.x, ex, ef, eg, lower, upper)
     return r.status == 0, r.iters
 
@@ -187,14 +192,22 @@ def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True):
     status = out["status"].cpu().numpy()
     iters = out["admm_iters"].cpu().numpy()
     nfact = out["n_factor"].cpu().numpy()
-    solved = int((status == 0).sum())
-    finite_grad = bool(torch.isfinite(grads["d_q"]).all().item()) if grad else None
+    ok = status == 0
+    if grad:  # "+grad": the instance's gradient must be refined to the tolerance too
+        ok &= grads["adj_status"].cpu().numpy() == 0
+    solved = int(ok.sum())
     res = {"wall_s": wall, "ms_per_step": wall / steps * 1e3, "solved": solved, "batch": batch.batch,
            "iters_mean": float(iters.mean()), "iters_max": int(iters.max()), "iters_sum": int(iters.sum()),
+           "iters_pct": {p: int(np.percentile(iters, p)) for p in (50, 90, 99)},
+           "iters_capped": int((iters >= settings_kw.get("max_admm", 1000)).sum()),
            "nfact_sum": int(nfact.sum()),
            "status_counts": {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
-           "kernels": {k: {"ms_per_step": ms / steps, "launches_per_step": c / steps} for k, (ms, c) in kt.items()},
-           "grad_finite": finite_grad}
+           "kernels": {k: {"ms_per_step": ms / steps, "launches_per_step": c / steps} for k, (ms, c) in kt.items()}}
+    if grad:
+        ast = grads["adj_status"].cpu().numpy()
+        res["adjoint"] = {"status_counts": {int(k): int(v) for k, v in zip(*np.unique(ast, return_counts=True))},
+                          "ok_on_solved": int(((ast == 0) & (status == 0)).sum()),
+                          "resid_max_ok": float(grads["adj_resid"].cpu().numpy()[ast == 0].max(initial=0.0))}
     s.close()
     return res
 
@@ -235,7 +248,9 @@ def run_bicycle(batch, precision, steps, warmup, settings_kw, grad=True):
     res = {"ms_per_step": wall / steps * 1e3,
            "kernel_ms_per_step": {k: round(ms / steps, 4) for k, (ms, c) in kt.items()},
            "sqp_kkt_max": [float(v) for v in np.nanmax(kkt, axis=0)],
-           "grad_finite": bool(torch.isfinite(grads["eta_x"]).all().item()) if grad else None}
+           "adj_status_counts": ({int(k): int(v) for k, v in zip(*np.unique(grads["adj_status"].cpu().numpy(),
+                                                                             return_counts=True))}
+                                 if grad else None)}
     s.close()
     return res
 
@@ -288,7 +303,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5a", "c5b"],
                     help="c2: the batched linear MPC benchmark; c3: 4096 bicycle instances, N = 100; "
                          "c5a / c5b: the long / ragged bicycle horizons")
-    ap.add_argument("--cpu-sample", type=int, default=256, help="instances timed on the oracle (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=1024, help="instances timed on the oracle (0 = skip)")
+    ap.add_argument("--no-sub", action="store_true", help="skip the differentiation and double-integrator sub-results")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison")
     ap.add_argument("--no-grad", action="store_true", help="forward solves only (no adjoint in the step)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -315,10 +331,7 @@ def main():
         bench_bicycle(args)
         return
     batch, desc = make_workload(args.workload)
-    settings_kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_admm=1000, k_check=25, k_rho=25)
-    f_it, f_fac = lti_flops_per_stage(batch.nx, batch.nu, batch.ng)
-    stages = batch.N + 1
-
+    settings_kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_admm=1000, k_check=25, k_rho=25, eps_active=1e-4)
     log(f"[bench] workload: {desc}")
     mixed = run_gpu(batch, 1, args.steps, args.warmup, settings_kw, grad=not args.no_grad)
     log(f"[bench] mixed: {json.dumps(mixed)}")
@@ -328,31 +341,7 @@ def main():
         log(f"[bench] fp64: {json.dumps(fp64)}")
 
     value = mixed["solved"] / (mixed["ms_per_step"] * 1e-3)
-    # roofline of the dominant kernel (the persistent ADMM solve).  It streams
-    # the factor blocks of every running instance once per iteration (the
-    # stage vectors stay in LDS between boundary checks) and is bound by
-    # memory traffic while the batch is full (the FP32 factor copies of 1024
-    # instances, 213 MB, exceed the L2), so the bound is HBM: achieved
-    # = algorithmic bytes of all its launches in a step / its GPU time in a
-    # step (= average bytes per launch / average launch duration).
-    kit = mixed["kernels"]["solve"]
-    n = batch.nx + batch.nu
-    b_it = lti_bytes_per_stage(n, 4, 4, min(k for k in (settings_kw.get("k_check", 25), settings_kw.get("k_rho", 25)) if k > 0))
-    bytes_launch = mixed["iters_sum"] * stages * b_it / max(kit["launches_per_step"], 1)
-    t_launch = kit["ms_per_step"] * 1e-3 / max(kit["launches_per_step"], 1)
-    achieved = bytes_launch / t_launch / 1e9
-    F32 = mixed["iters_sum"] * stages * f_it
-    F64 = mixed["nfact_sum"] * stages * f_fac
-    traffic = TRAFFIC_BYTES.get((args.workload, "mixed"))
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM, 5), "traffic": traffic,
-            "kernel": f"admm_solve_wave_kernel<float,{batch.nx},{batch.nu},{batch.ng},box>",
-            "avg_launch_us": round(t_launch * 1e6, 2), "launches_per_step": kit["launches_per_step"],
-            "bytes_per_launch": bytes_launch, "bytes_per_stage_iteration": b_it,
-            "alu_tflops": round((F32 + F64 * PEAK_FP32 / PEAK_FP64) / (t_launch * kit["launches_per_step"]) / 1e12,
-                                4),
-            "alu_frac_fp32_peak": round((F32 + F64 * PEAK_FP32 / PEAK_FP64) / (t_launch * kit["launches_per_step"])
-                                        / 1e12 / PEAK_FP32, 6)}
+    roof, hbm = roofline(batch, mixed, "mixed", args.workload)
     out = {
         "metric": "QP solves/s at 1e-4 KKT residual, FP32+grad vs plain FP64, 1 MI355X",
         "value": round(value, 2), "unit": "QP solves/s", "n_gpus": 1, "steps": args.steps,
@@ -360,24 +349,105 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": desc, "batch": batch.batch, "horizon": batch.N, "nx": batch.nx, "nu": batch.nu,
                    "ng": batch.ng, "precision": "fp32 ADMM iterations, fp64 factorisation, gate and adjoint",
-                   "eps": 1e-4, "max_admm": 1000, "grad": not args.no_grad,
-                   "parallelism": "single GPU, one instance per 16-lane row"},
+                   "eps": 1e-4, "eps_active": 1e-4, "max_admm": 1000, "grad": not args.no_grad,
+                   "parallelism": "single GPU, one instance per wavefront"},
         "admm_iters_per_s": round(mixed["iters_sum"] / (mixed["ms_per_step"] * 1e-3), 1),
         "kernel_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in mixed["kernels"].items()},
         "solved_fraction": mixed["solved"] / batch.batch,
+        "iters": {"mean": round(mixed["iters_mean"], 1), **{f"p{k}": v for k, v in mixed["iters_pct"].items()},
+                  "max": mixed["iters_max"], "capped": mixed["iters_capped"]},
         "roofline": roof,
+        "hbm_view": hbm,
     }
+    if "adjoint" in mixed:
+        out["adjoint_status"] = mixed["adjoint"]
     if fp64 is not None:
         out["fp64"] = {"value": round(fp64["solved"] / (fp64["ms_per_step"] * 1e-3), 2),
                        "ms_per_step": round(fp64["ms_per_step"], 4),
                        "kernel_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in fp64["kernels"].items()},
-                       "solved_fraction": fp64["solved"] / batch.batch, "iters_mean": fp64["iters_mean"]}
+                       "solved_fraction": fp64["solved"] / batch.batch, "iters_mean": fp64["iters_mean"],
+                       "iters_capped": fp64["iters_capped"]}
         out["speedup_vs_fp64"] = round(value / max(out["fp64"]["value"], 1e-9), 3)
+    if not args.no_sub:
+        out["sub_results"] = sub_results(args)
     if args.cpu_sample > 0:
         cb_kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_iter=1000, k_check=25, k_rho=25)
         out["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_sample, batch.batch), cb_kw, not args.no_grad)
         log(f"[bench] cpu: {json.dumps(out['cpu_baseline'])}")
     print(json.dumps(out), flush=True)
+
+
+def roofline(batch, res, prec, workload):
+    """Roofline of the dominant kernel (the persistent ADMM solve launch) by
+    the algorithmic work of one launch: F32 = instance-iterations x stages x
+    the flops of one stage-iteration, F64 = factorisations x stages x the
+    flops of one stage factorisation, bytes = problem data in plus solution
+    out.  Roofline time max(bytes / BW, F32 / peak32 + F64 / peak64); the
+    kernel is bound by the plain vector ALUs (no contraction is dense enough
+    for MFMA), so `achieved` is the FP32-equivalent rate against the FP32
+    vector peak and frac = roofline time / measured launch time.  The HBM
+    view (the design's factor stream) is reported beside it."""
+    f_it, f_fac = lti_flops_per_stage(batch.nx, batch.nu, batch.ng)
+    stages = batch.N + 1
+    kit = res["kernels"]["solve"]
+    launches = max(kit["launches_per_step"], 1)
+    t_launch = kit["ms_per_step"] * 1e-3 / launches
+    F32 = res["iters_sum"] * stages * f_it / launches
+    F64 = res["nfact_sum"] * stages * f_fac / launches
+    n = batch.nx + batch.nu
+    # FP64 problem data in (A, B, diag Q, diag R, diag Q_f, bounds, x0) and the
+    # FP64 solution out (x, y_f, y_g, z_g) per instance
+    b_in = 8 * (batch.nx * batch.nx + batch.nx * batch.nu + 2 * batch.nx + batch.nu + 2 * batch.ng + batch.nx)
+    b_out = 8 * stages * (n + batch.nx + 2 * batch.ng)
+    bytes_alg = batch.batch * (b_in + b_out)
+    t_roof = max(bytes_alg / (PEAK_HBM * 1e9), F32 / (PEAK_FP32 * 1e12) + F64 / (PEAK_FP64 * 1e12))
+    achieved = (F32 + F64 * PEAK_FP32 / PEAK_FP64) / t_launch / 1e12
+    src = kernel_source_hash()
+    traffic = TRAFFIC_BYTES.get((workload, prec, src))
+    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32, "unit": "TFLOP/s",
+            "frac": round(t_roof / t_launch, 5), "traffic": traffic,
+            "kernel": f"admm_solve_wave_kernel<float,{batch.nx},{batch.nu},{batch.ng},box>",
+            "avg_launch_us": round(t_launch * 1e6, 2), "launches_per_step": kit["launches_per_step"],
+            "flops_fp32_per_launch": F32, "flops_fp64_per_launch": F64, "bytes_per_launch": bytes_alg,
+            "flops_per_stage_iteration": f_it, "flops_per_stage_factorisation": f_fac,
+            "roofline_time_us": round(t_roof * 1e6, 2), "kernel_source": src}
+    b_it = lti_bytes_per_stage(n, 4, 4)
+    design_bytes = res["iters_sum"] * stages * b_it / launches
+    hbm = {"design_bytes_per_launch": design_bytes, "bytes_per_stage_iteration": b_it,
+           "achieved_GBps": round(design_bytes / t_launch / 1e9, 1), "peak_GBps": PEAK_HBM,
+           "frac": round(design_bytes / t_launch / 1e9 / PEAK_HBM, 4), "measured_traffic": traffic}
+    return roof, hbm
+
+
+def sub_results(args):
+    """The other linear workloads, each at a few steps: the differentiation
+    batch (512 random LTI instances, N = 64, +grad, gated at 1e-4; FP32
+    iterations and plain FP64) and the single double integrator (N = 20, FP64,
+    200 iterations at fixed rho: per-solve latency, and 64 copies)."""
+    from workloads import double_integrator, random_lti
+
+    sub = {}
+    b4 = random_lti(512, N=64, seed=4)
+    kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_admm=1000, k_check=25, k_rho=25, eps_active=1e-4)
+    steps = max(3, min(args.steps, 10))
+    m = run_gpu(b4, 1, steps, 2, kw, grad=True)
+    f = run_gpu(b4, 0, steps, 1, kw, grad=True)
+    sub["c4_lti512_n64_grad"] = {
+        "value": round(m["solved"] / (m["ms_per_step"] * 1e-3), 1), "unit": "QP solves/s (gated, +grad)",
+        "ms_per_step": round(m["ms_per_step"], 4), "solved_fraction": m["solved"] / b4.batch,
+        "iters_mean": round(m["iters_mean"], 1), "iters_capped": m["iters_capped"],
+        "fp64_value": round(f["solved"] / (f["ms_per_step"] * 1e-3), 1), "fp64_ms_per_step": round(f["ms_per_step"], 4),
+        "fp64_solved_fraction": f["solved"] / b4.batch, "steps": steps}
+    kw1 = dict(max_admm=200, k_check=0, adapt_rho=0)
+    for B in (1, 64):
+        b1 = double_integrator(B, N=20, seed=1)
+        r = run_gpu(b1, 0, max(10, steps), 3, kw1, grad=False)
+        sub[f"c1_double_integrator_b{B}"] = {
+            "ms_per_step": round(r["ms_per_step"], 4), "solves_per_s": round(B / (r["ms_per_step"] * 1e-3), 1),
+            "unit": "QP solves/s (200 fixed-rho FP64 iterations)", "solve_kernel_ms": round(
+                r["kernels"]["solve"]["ms_per_step"], 4)}
+    log(f"[bench] sub-results: {json.dumps(sub)}")
+    return sub
 
 
 if __name__ == "__main__":

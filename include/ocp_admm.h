@@ -66,6 +66,12 @@ enum { OCP_ROW_HARD = 0, OCP_ROW_L2 = 1, OCP_ROW_L1 = 2 };
 enum { OCP_INTEG_MIDPOINT = 0, OCP_INTEG_TRAPEZOID = 1 };
 /* per-instance status */
 enum { OCP_SOLVED = 0, OCP_MAX_ITER = 1, OCP_NON_FINITE = 2, OCP_FACTOR_BREAKDOWN = 3 };
+/* per-instance adjoint status (ocp_qp_grads.adj_status): the relative FP64
+ * residual ||r - K eta||_inf / ||dL/dx||_inf of the active-set KKT system after
+ * the refinement sweeps is at most adj_tol (OK) or above it (RESIDUAL: the
+ * sweeps did not converge, e.g. nearly dependent active rows), the result is
+ * not finite, or the factorisation of the regularised Schur matrix broke down */
+enum { OCP_ADJ_OK = 0, OCP_ADJ_RESIDUAL = 1, OCP_ADJ_NON_FINITE = 2, OCP_ADJ_BREAKDOWN = 3 };
 
 typedef struct {
   int32_t batch;          /* B >= 1 */
@@ -88,6 +94,8 @@ typedef struct {
   double armijo_eta;
   double eps_active;       /* active-set tolerance scale for the adjoint */
   double adj_sigma, adj_rho; /* regularisation of the adjoint refinement */
+  double adj_tol;          /* relative KKT residual after the sweeps accepted as refined
+                              (adj_status OK); default 1e-10 */
   int32_t max_admm;        /* ADMM iterations per QP */
   int32_t k_rho;           /* rho adaptation interval (0 = never) */
   int32_t k_check;         /* convergence test interval (0 = run exactly max_admm) */
@@ -95,7 +103,7 @@ typedef struct {
   int32_t warm_start;      /* 1: start from the handle's current state and rho */
   int32_t max_sqp;         /* SQP iterations (bicycle model) */
   int32_t fixed_sqp;       /* 1: run exactly max_sqp iterations */
-  int32_t refine_sweeps;   /* adjoint iterative-refinement sweeps */
+  int32_t refine_sweeps;   /* adjoint iterative-refinement sweeps (default 8) */
 } ocp_settings;
 
 /* Linear time-invariant model (OCP_MODEL_LTI): x_{t+1} = A x_t + B u_t,
@@ -154,11 +162,19 @@ typedef struct {
  * d_x_init [B,nx], d_lo, d_hi [S,ng], eta_x [S,n], active [S,ng] (int8:
  * -1 lower, +1 upper, 0 inactive), d_gamma2 [B] (w.r.t. the L2 slack
  * weight: sum over the active L2-slack rows of xi_i (G eta_x)_i, Sec.
- * "Backward pass" with slack variables; 0 without such rows). */
+ * "Backward pass" with slack variables; 0 without such rows);
+ * eta_f [S,nx] (adjoint of the equality multipliers, in the slot convention
+ * of ocp_solution.y_f: dL/dc = eta_f) and eta_g [S,ng] (of the inequality
+ * multipliers, 0 on inactive rows); per instance [B]: adj_resid (relative
+ * FP64 KKT residual after the sweeps) and adj_status (OCP_ADJ_*).  When the
+ * active rows are linearly dependent the multiplier part is the one the
+ * refinement reaches from zero, the minimum-norm solution. */
 typedef struct {
   double *d_q, *d_Ddiag, *d_x_init, *d_lo, *d_hi, *eta_x;
   int8_t* active;
   double* d_gamma2;
+  double *eta_f, *eta_g, *adj_resid;
+  int32_t* adj_status;
 } ocp_qp_grads;
 
 /* Fill `s` with the defaults listed above.  Never fails. */
@@ -208,7 +224,13 @@ ocp_status ocp_get_solution(ocp_handle h, const ocp_solution* out, void* stream)
  * bwd:slack_reduced_system (their penalty gamma2 G_i'G_i joins H, their
  * eta_y = gamma2 G_i eta_x; no loss term on the slacks); L1 rows with a
  * nonzero slack carry a fixed multiplier and leave the active set.
- * Errors: OCP_E_ORDER before a solve. */
+ * Bicycle model: the VJP is that of the last SQP iteration's QP at that QP's
+ * own ADMM solution (x, y_g, xi before the line-search step), which is the
+ * returned iterate once the SQP has converged with unit steps; d_Ddiag uses
+ * that QP solution.  Per-instance adj_status / adj_resid report whether the
+ * refinement reached settings.adj_tol.  Errors: OCP_E_ORDER before a solve,
+ * OCP_E_ARG (null pointers, non-positive adj_sigma / adj_rho / eps_active /
+ * adj_tol, refine_sweeps < 1). */
 ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const ocp_qp_grads* out,
                        void* stream);
 

@@ -148,7 +148,8 @@ def adjoint_dense(qp: StageQP, x, dL_dx, lower, upper, H=None):
     """eta = K^{-1} (dL/dx, 0, 0) by a direct sparse LU (the definition).
 
     When the active rows are linearly dependent (LICQ fails; at eps 1e-4 this
-    happens on unconverged instances), K is singular but the system stays
+    happens on unconverged instances; the LU then shows a pivot below 1e-12 of
+    the largest, or none at all), K is singular but the system stays
     consistent: eta_x is unique (H is positive definite) and eta_y is
     determined up to the null space of J'.  The result is then the
     minimum-norm solution K^+ (dL/dx, 0, 0) by a dense least-squares solve
@@ -159,8 +160,16 @@ def adjoint_dense(qp: StageQP, x, dL_dx, lower, upper, H=None):
     K, *_ , act = _kkt(qp, lower, upper, H)
     nv, ne = qp.nvar, qp.neq
     rhs = np.concatenate([dL_dx, np.zeros(ne + int(act.sum()))])
-    if independent_rows(qp, lower, upper):
-        eta = spla.spsolve(K, rhs)
+    lu = None
+    try:
+        lu = spla.splu(K)
+        piv = np.abs(lu.U.diagonal())
+        if not (piv.min() > 1e-12 * piv.max()):  # a pivot at rounding level: K is singular
+            lu = None
+    except RuntimeError:  # exactly singular
+        lu = None
+    if lu is not None:
+        eta = lu.solve(rhs)
     else:
         eta = sla.lstsq(K.toarray(), rhs, cond=1e-12, lapack_driver="gelsd")[0]
     eta_g = np.zeros(qp.nineq)

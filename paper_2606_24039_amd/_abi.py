@@ -15,6 +15,7 @@ MODEL_QP, MODEL_LTI, MODEL_BICYCLE = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 ROW_HARD, ROW_L2, ROW_L1 = 0, 1, 2
 SOLVED, MAX_ITER, NON_FINITE, FACTOR_BREAKDOWN = 0, 1, 2, 3
+ADJ_OK, ADJ_RESIDUAL, ADJ_NON_FINITE, ADJ_BREAKDOWN = 0, 1, 2, 3
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -28,7 +29,7 @@ class ocp_dims(C.Structure):
 class ocp_settings(C.Structure):
     _fields_ = [(k, C.c_double) for k in (
         "sigma", "rho0", "rho_f_scale", "rho_min", "rho_max", "k_ratio", "alpha", "eps_abs", "eps_rel",
-        "eps_c", "armijo_eta", "eps_active", "adj_sigma", "adj_rho")] + [(k, C.c_int32) for k in (
+        "eps_c", "armijo_eta", "eps_active", "adj_sigma", "adj_rho", "adj_tol")] + [(k, C.c_int32) for k in (
             "max_admm", "k_rho", "k_check", "adapt_rho", "warm_start", "max_sqp", "fixed_sqp", "refine_sweeps")]
 
 
@@ -55,7 +56,7 @@ class ocp_solution(C.Structure):
 
 class ocp_qp_grads(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("d_q", "d_Ddiag", "d_x_init", "d_lo", "d_hi", "eta_x", "active",
-                                          "d_gamma2")]
+                                          "d_gamma2", "eta_f", "eta_g", "adj_resid", "adj_status")]
 
 
 # (name, restype, argtypes) for every symbol declared in include/ocp_admm.h

@@ -20,7 +20,9 @@
 //    with rho_f = rho_b and per-row inequality weights rho_b [row active].
 //    Iterative refinement e <- e + K_reg^{-1}(r - K e) with the residual in
 //    FP64 converges to K^{-1} r (the regularisation is a perturbation of
-//    size max(sigma_b, 1/rho_b)).
+//    size max(sigma_b, 1/rho_b)); refine_sweeps corrections, then the final
+//    residual ||r - K e||_inf / ||dL/dx||_inf is compared with adj_tol for
+//    the per-instance status.
 // 3. VJP (eq. loss_gradient): dL/dq = -eta_x, dL/dx_init = eta_f(initial
 //    rows), dL/dD_t[i,i] = -eta_x,t,i x_t,i, dL/dlo = eta_g on lower-active
 //    rows, dL/dhi = eta_g on upper-active rows.
@@ -29,6 +31,7 @@
 // initial-state rows at stage 0, dynamics row t at stage t + 1.
 #pragma once
 
+#include "ocp_admm.h"
 #include "wave.h"
 
 namespace ocpk {
@@ -52,6 +55,9 @@ struct AdjArgs {
   // outputs (FP64, may be null)
   double *d_q, *d_Ddiag, *d_x_init, *d_lo, *d_hi, *eta_x, *d_gamma2;
   int8_t* active;
+  double *eta_f, *eta_g, *adj_resid;
+  int32_t* adj_status;
+  double adj_tol;  // relative KKT residual accepted as refined
 };
 
 // Blocks of stage t a row needs for the products with H, C and G (FP64).
@@ -110,7 +116,7 @@ struct AdjIn5 {
 // unpadded FP64 scratch vectors are read at stages clamped to 0..N (the
 // clamped values are never used).
 template <int NX, int NU, int NG, typename ST>
-__device__ __forceinline__ void adjoint_sweeps_ti(const Layout& L, const AdjArgs& a, const WaveGroup& w, int bad) {
+__device__ __forceinline__ double adjoint_sweeps_ti(const Layout& L, const AdjArgs& a, const WaveGroup& w, int bad) {
   constexpr int n = NX + NU;
   constexpr uint32_t VS = ROW * sizeof(double);
   const int i = w.lane, q = w.row, N = w.N;
@@ -145,7 +151,11 @@ __device__ __forceinline__ void adjoint_sweeps_ti(const Layout& L, const AdjArgs
   // of the padded exchange buffer (no clamping needed within the padding)
   auto oR = [&](int t) { return (uint32_t)(((STAGE_PAD + t) * ROW + i) * (int)sizeof(double)); };
 
-  for (int sweep = 0; sweep < a.sweeps && !bad; ++sweep) {
+  // this lane's part of ||r - K e||_inf; the pass after the last sweep only
+  // evaluates it
+  double rres = 0.0;
+  for (int sweep = 0; sweep <= a.sweeps && !bad; ++sweep) {
+    rres = 0.0;
     // pass 1: residual r - K e and the Schur right-hand side
     //   rhs_t = r_x,t + rho_b (C' r_f)_t + G'(w .* r_g,t)
     {
@@ -233,11 +243,14 @@ __device__ __forceinline__ void adjoint_sweeps_ti(const Layout& L, const AdjArgs
           if (thi && xr) sto(rf, o + VS, rfc);
           if (i < NG) sto(rg, o, rgc);
           sto(Rb, oR(t), rhs);
+          rres = fmax(rres, fmax(i < n ? fabs(rx) : 0.0, i < NG ? fabs(rgc) : 0.0));
+          if (xr) rres = fmax(rres, fmax(fabs(rfc), fabs(rf0)));
         }
       };
       stage_blocks<STAGE_BLOCK_DEPTH, AdjIn1>(nfull, load, comp);
     }
     wave_sync();
+    if (sweep == a.sweeps) break;
     // passes 2-4: d_x = S^{-1} rhs
     if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
     wave_sync();
@@ -302,6 +315,7 @@ __device__ __forceinline__ void adjoint_sweeps_ti(const Layout& L, const AdjArgs
     }
     wave_sync();
   }
+  return rres;
 }
 
 // Refinement sweeps, time-varying blocks: the same passes as the
@@ -325,8 +339,8 @@ struct AdjInTV5 {
 };
 
 template <int NX, int NU, int NG>
-__device__ __forceinline__ void adjoint_sweeps_tv(const Layout& L, const AdjArgs& a, const WaveGroup& w, int bad,
-                                                  bool slr) {
+__device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjArgs& a, const WaveGroup& w, int bad,
+                                                    bool slr) {
   constexpr int n = NX + NU;
   constexpr int D = ADJ_TV_DEPTH<n>;
   const int i = w.lane, q = w.row, N = w.N, b = w.b;
@@ -348,7 +362,9 @@ __device__ __forceinline__ void adjoint_sweeps_tv(const Layout& L, const AdjArgs
   const uint32_t oblk = (uint32_t)((STAGE_PAD * (int)nn + ic * n) * (int)sizeof(double));
   auto tcl = [&](int blk) { return min(4 * blk + q, N); };
 
-  for (int sweep = 0; sweep < a.sweeps && !bad; ++sweep) {
+  double rres = 0.0;  // this lane's part of ||r - K e||_inf (the pass after the last sweep only evaluates it)
+  for (int sweep = 0; sweep <= a.sweeps && !bad; ++sweep) {
+    rres = 0.0;
     // pass 1: residual r - K e and the Schur right-hand side
     //   rhs_t = r_x,t + rho_b (C' r_f)_t + G_t'(w .* r_g,t)
     {
@@ -407,10 +423,13 @@ __device__ __forceinline__ void adjoint_sweeps_tv(const Layout& L, const AdjArgs
         if (t < N && i < NX) rf[sv + ROW] = rfc;
         if (i < NG) rg[sv] = rgc;
         R[(size_t)t * ROW] = rhs;
+        rres = fmax(rres, fmax(i < n ? fabs(rx) : 0.0, i < NG ? fabs(rgc) : 0.0));
+        if (i < NX) rres = fmax(rres, fmax(fabs(rfc), fabs(rf0)));
       };
       stage_blocks<D, In>(nfull, load, comp);
     }
     wave_sync();
+    if (sweep == a.sweeps) break;
     // passes 2-4: d_x = S^{-1} rhs
     if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
     wave_sync();
@@ -468,6 +487,7 @@ __device__ __forceinline__ void adjoint_sweeps_tv(const Layout& L, const AdjArgs
     }
     wave_sync();
   }
+  return rres;
 }
 
 template <typename T, int NX, int NU, int NG, typename ST>
@@ -490,12 +510,14 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   const double rb = a.rho_b;
 
   // ---- 1. active set ----
-  double ymax = 0.0;
+  double ymax = 0.0, dlmax = 0.0;
   for (int blk = 0; blk < nbl; ++blk) {
     const int t = 4 * blk + q;
     if (t <= N && i < NG) ymax = fmax(ymax, fabs(double(YG[(size_t)(s0 + t) * ROW + i])));
+    if (t <= N && i < n) dlmax = fmax(dlmax, fabs(a.dLdx[(size_t)(s0 + t) * n + i]));
   }
   ymax = rows_max(row_max(ymax));
+  dlmax = rows_max(row_max(dlmax));
   const double epsg = 10.0 * a.eps_active * fmax(1.0, ymax);  // dual test, relative to the multipliers
   const double epsp = 10.0 * a.eps_active;                     // proximity test, relative to the bound
   for (int blk = 0; blk < nbl; ++blk) {
@@ -547,16 +569,19 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
                   : factor_instance<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
   wave_sync();
 
-  // ---- refinement sweeps ----
+  // ---- refinement sweeps, then the final FP64 residual ||r - K e||_inf ----
+  double rres;
   if constexpr (ST::TI) {
-    adjoint_sweeps_ti<NX, NU, NG, ST>(L, a, w, bad);
+    rres = adjoint_sweeps_ti<NX, NU, NG, ST>(L, a, w, bad);
   } else {
-    adjoint_sweeps_tv<NX, NU, NG>(L, a, w, bad, slr);
+    rres = adjoint_sweeps_tv<NX, NU, NG>(L, a, w, bad, slr);
   }
+  rres = rows_max(row_max(rres));
 
   // ---- 3. VJP outputs ----
   const double nanv = bad ? NAN : 0.0;
   double dgam = 0.0;  // this lane's part of dL/dgamma2
+  bool nonfin = false;
   for (int blk = 0; blk < nbl; ++blk) {
     const int t = 4 * blk + q;
     if (t > N) break;
@@ -564,6 +589,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     const size_t sv = (size_t)s * ROW + i;
     if (i < n) {
       const double e = ex[sv] + nanv;
+      nonfin |= !isfinite(e);
       if (a.eta_x) a.eta_x[(size_t)s * n + i] = e;
       if (a.d_q) a.d_q[(size_t)s * n + i] = -e;
       if (a.d_Ddiag) a.d_Ddiag[(size_t)s * n + i] = -e * double(X[sv]);
@@ -576,16 +602,33 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
       const int act = a.act[sv];
       const double e = ((kind == 1 && act != 0) ? L.gamma2 * gex : eg[sv]) + nanv;
       if (kind == 1 && act != 0) dgam += double(XI[sv]) * gex;
+      if (act != 0) nonfin |= !isfinite(e);
       if (a.d_lo) a.d_lo[(size_t)s * NG + i] = (act < 0) ? e : 0.0;
       if (a.d_hi) a.d_hi[(size_t)s * NG + i] = (act > 0) ? e : 0.0;
+      if (a.eta_g) a.eta_g[(size_t)s * NG + i] = (act != 0) ? e : 0.0;
       if (a.active) a.active[(size_t)s * NG + i] = (int8_t)act;
     }
-    if (t == 0 && i < NX && a.d_x_init) a.d_x_init[(size_t)b * NX + i] = ef[sv] + nanv;
+    if (i < NX) {
+      // equality rows in the slot convention of y_f: the initial-state rows
+      // at stage 0, dynamics row t - 1 at stage t
+      const double e = ef[sv] + nanv;
+      nonfin |= !isfinite(e);
+      if (a.eta_f) a.eta_f[(size_t)s * NX + i] = e;
+      if (t == 0 && a.d_x_init) a.d_x_init[(size_t)b * NX + i] = e;
+    }
   }
   dgam = row_sum(dgam);
   dgam += __shfl_xor(dgam, 16);
   dgam += __shfl_xor(dgam, 32);
-  if (threadIdx.x == 0 && a.d_gamma2) a.d_gamma2[b] = dgam + nanv;
+  const bool anynf = __ballot(nonfin) != 0;
+  if (threadIdx.x == 0) {
+    if (a.d_gamma2) a.d_gamma2[b] = dgam + nanv;
+    // relative FP64 residual of the active-set KKT system after the sweeps
+    const double rel = rres / fmax(dlmax, 1e-300);
+    if (a.adj_resid) a.adj_resid[b] = bad ? NAN : rel;
+    if (a.adj_status)
+      a.adj_status[b] = bad ? OCP_ADJ_BREAKDOWN : (anynf ? OCP_ADJ_NON_FINITE : (rel <= a.adj_tol ? OCP_ADJ_OK : OCP_ADJ_RESIDUAL));
+  }
 }
 
 }  // namespace ocpk

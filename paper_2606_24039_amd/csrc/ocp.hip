@@ -569,7 +569,8 @@ void ocp_default_settings(ocp_settings* s) {
   s->armijo_eta = 0.4;
   s->eps_active = 1e-4;
   s->adj_sigma = 1e-9;
-  s->adj_rho = 1e6;
+  s->adj_rho = 1e8;
+  s->adj_tol = 1e-10;
   s->max_admm = 1000;
   s->k_rho = 25;
   s->k_check = 25;
@@ -577,7 +578,7 @@ void ocp_default_settings(ocp_settings* s) {
   s->warm_start = 0;
   s->max_sqp = 10;
   s->fixed_sqp = 1;
-  s->refine_sweeps = 6;
+  s->refine_sweeps = 8;
 }
 
 const char* ocp_status_string(ocp_status st) {
@@ -780,7 +781,9 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
                        void* stream) {
   if (!h || !s || !dL_dx || !out) return OCP_E_ARG;
   if (!h->solved) return OCP_E_ORDER;
-  if (!(s->adj_sigma > 0) || !(s->adj_rho > 0) || !(s->eps_active > 0) || s->refine_sweeps < 1) return OCP_E_ARG;
+  if (!(s->adj_sigma > 0) || !(s->adj_rho > 0) || !(s->eps_active > 0) || !(s->adj_tol > 0) ||
+      s->refine_sweeps < 1)
+    return OCP_E_ARG;
   hipStream_t st = (hipStream_t)stream;
   AdjArgs a{};
   a.dLdx = dL_dx;
@@ -808,6 +811,11 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   a.d_hi = out->d_hi;
   a.eta_x = out->eta_x;
   a.active = out->active;
+  a.eta_f = out->eta_f;
+  a.eta_g = out->eta_g;
+  a.adj_resid = out->adj_resid;
+  a.adj_status = out->adj_status;
+  a.adj_tol = s->adj_tol;
   const Layout L = make_layout(h);
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (h->ti ? VAR_TI : VAR_TV);
   if (h->mixed)

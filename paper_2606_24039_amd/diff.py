@@ -16,19 +16,26 @@ from . import _abi as A
 class LTIMPC(torch.autograd.Function):
     @staticmethod
     def forward(ctx, solver, settings, Amat, Bm, G, Qd, Rd, Qfd, lo, hi, x0):
-        solver.set_lti(Amat.detach(), Bm.detach(), Qd.detach(), Rd.detach(), Qfd.detach(), G.detach(),
-                       lo.detach(), hi.detach(), x0.detach())
+        data = tuple(t.detach() for t in (Amat, Bm, Qd, Rd, Qfd, G, lo, hi, x0))
+        solver.set_lti(*data)
         out = solver.solve(settings)
         ctx.solver = solver
         ctx.settings = settings
-        ctx.save_for_backward(out["x"])
+        ctx.generation = solver.generation  # the handle's state this backward differentiates
+        ctx.save_for_backward(out["x"], *data)
         ctx.mark_non_differentiable(out["status"])
         return out["x"].clone(), out["status"]
 
     @staticmethod
     def backward(ctx, dx, _dstatus):
         s = ctx.solver
-        (x,) = ctx.saved_tensors
+        x, *data = ctx.saved_tensors
+        if s.generation != ctx.generation:
+            # the handle was reused for another problem since this forward: restore
+            # this forward's data and solve again (the solve is deterministic, so
+            # the handle holds the same solution the forward returned)
+            s.set_lti(*data)
+            s.solve(ctx.settings)
         g = s.adjoint(dx.contiguous().to(torch.float64), ctx.settings)
         dev = x.device
         inst = torch.repeat_interleave(torch.arange(s.B, device=dev),

@@ -45,6 +45,7 @@ class OCPSolver:
         A.check(self.lib.ocp_create(C.byref(self.dims), hz.ctypes.data_as(A._ip), C.byref(h)), "ocp_create")
         self.h = h
         self._keep = []
+        self.generation = 0  # bumped by every call that changes the handle's problem data or solution
 
     def workspace_bytes(self) -> int:
         out = C.c_size_t()
@@ -65,6 +66,7 @@ class OCPSolver:
 
     # ------------------------------------------------------------------ setters
     def set_lti(self, A_, Bm, Qd, Rd, Qfd, G, lo, hi, x0):
+        self.generation += 1
         t = [_dev(v) for v in (A_, Bm, Qd, Rd, Qfd, G, lo, hi, x0)]
         p = A.ocp_lti(*[tt.data_ptr() for tt in t])
         A.check(self.lib.ocp_set_lti(self.h, C.byref(p), _stream()), "ocp_set_lti")
@@ -72,6 +74,7 @@ class OCPSolver:
         torch.cuda.current_stream().synchronize()
 
     def set_qp(self, D, Am, Ap, x_init, G, lo, hi, E=None, q=None, b=None, soft=None, gamma2=1.0, gamma1=1.0):
+        self.generation += 1
         t = {k: (_dev(v) if v is not None else None) for k, v in dict(D=D, E=E, q=q, Am=Am, Ap=Ap, b=b, G=G, lo=lo,
                                                                          hi=hi, x_init=x_init).items()}
         st = _dev(soft, dtype=torch.uint8) if soft is not None else None
@@ -83,6 +86,7 @@ class OCPSolver:
         torch.cuda.current_stream().synchronize()
 
     def set_bicycle(self, batch):
+        self.generation += 1
         """Load a workloads.BicycleBatch."""
         t = [_dev(batch.ref), _dev(batch.normal), _dev(batch.x0)]
         p = A.ocp_bicycle(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(), batch.dt, batch.wheelbase,
@@ -110,6 +114,7 @@ class OCPSolver:
     def solve(self, settings=None, out=None, sync=True, **overrides):
         s = settings if settings is not None else A.default_settings(**overrides)
         out = out if out is not None else self.alloc_solution()
+        self.generation += 1
         sol = A.ocp_solution(*[(out[k].data_ptr() if out.get(k) is not None else None) for k, _ in
                                A.ocp_solution._fields_])
         A.check(self.lib.ocp_solve(self.h, C.byref(s), C.byref(sol), _stream()), "ocp_solve")
@@ -131,6 +136,7 @@ class OCPSolver:
 
     def solve_raw(self, settings, sol_struct):
         """Launch a solve with a prebuilt ocp_solution (no allocation, no sync)."""
+        self.generation += 1
         A.check(self.lib.ocp_solve(self.h, C.byref(settings), C.byref(sol_struct) if sol_struct is not None else None,
                                    _stream()), "ocp_solve")
 
@@ -165,7 +171,9 @@ class OCPSolver:
                 "d_x_init": torch.empty(self.B, self.nx, **f64), "d_lo": torch.empty(self.S, self.ng, **f64),
                 "d_hi": torch.empty(self.S, self.ng, **f64), "eta_x": torch.empty(self.S, self.n, **f64),
                 "active": torch.empty(self.S, self.ng, dtype=torch.int8, device=self.device),
-                "d_gamma2": torch.empty(self.B, **f64)}
+                "d_gamma2": torch.empty(self.B, **f64), "eta_f": torch.empty(self.S, self.nx, **f64),
+                "eta_g": torch.empty(self.S, self.ng, **f64), "adj_resid": torch.empty(self.B, **f64),
+                "adj_status": torch.empty(self.B, dtype=torch.int32, device=self.device)}
 
     def grads_struct(self, g):
         return A.ocp_qp_grads(*[g[k].data_ptr() for k, _ in A.ocp_qp_grads._fields_])
@@ -183,6 +191,7 @@ class OCPSolver:
                 "ocp_graph_capture")
 
     def graph_launch(self):
+        self.generation += 1
         A.check(self.lib.ocp_graph_launch(self.h, _stream()), "ocp_graph_launch")
 
     def set_segmented(self, seg_min_n: int):
@@ -194,6 +203,7 @@ class OCPSolver:
         (ocp_autotune); returns the chosen switch horizon."""
         s = settings if settings is not None else A.default_settings(**overrides)
         chosen = C.c_int32(0)
+        self.generation += 1
         A.check(self.lib.ocp_autotune(self.h, C.byref(s), int(reps), _stream(), C.byref(chosen)), "ocp_autotune")
         return int(chosen.value)
 

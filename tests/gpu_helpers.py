@@ -24,3 +24,16 @@ def per_instance(solver, out, i):
     """(x [(N+1)*n], z_g, xi, y_f, y_g) of instance i as flat numpy arrays in the oracle's ordering."""
     g = lambda k: solver.split(out[k], i).detach().cpu().numpy().reshape(-1)
     return {"x": g("x"), "z_g": g("z_g"), "xi": g("xi"), "y_f": g("y_f"), "y_g": g("y_g")}
+
+
+def oracle_map(fn, arglist):
+    """Run an oracle function over a list of argument tuples in fresh worker
+    processes (spawned: they never touch the GPU), one BLAS thread each."""
+    import multiprocessing as mp
+    import os
+
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), len(arglist)))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.starmap(fn, arglist)

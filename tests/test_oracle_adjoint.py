@@ -208,3 +208,22 @@ def test_proximity_tolerance_does_not_scale_with_the_multipliers():
     lower, upper = active_set(qp, x, y, eps_solve=1e-4)
     assert not upper[qp.ng + 0] and upper[qp.ng + 1]
     assert upper[2 * qp.ng + 3] and not lower[2 * qp.ng + 3]
+
+
+def test_singularity_detection_agrees_with_the_rank_test():
+    """adjoint_dense switches to the minimum-norm solve exactly when the
+    active rows are dependent: on the converged C2-shaped instances of the
+    sample (independent rows) the sparse LU result is kept, on the
+    constructed dependent set the minimum-norm one is returned."""
+    import scipy.linalg as sla
+
+    from oracle.adjoint import _kkt, independent_rows
+
+    qp, sol, gx, lower, upper, lower_dep = _dependent_active_set()
+    for lo_, dep in ((lower, False), (lower_dep, True)):
+        assert independent_rows(qp, lo_, upper) == (not dep)
+        K = _kkt(qp, lo_, upper)[0]
+        rhs = np.concatenate([gx, np.zeros(K.shape[0] - gx.size)])
+        ex, ef, eg = adjoint_dense(qp, sol["x"], gx, lo_, upper)
+        mn = sla.lstsq(K.toarray(), rhs, cond=1e-12)[0]
+        np.testing.assert_allclose(np.concatenate([ex, ef]), mn[:ex.size + ef.size], rtol=1e-8, atol=1e-10)
