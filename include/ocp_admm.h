@@ -50,7 +50,8 @@ typedef enum {
   OCP_E_HIP = 3,         /* a HIP runtime call failed */
   OCP_E_NOMEM = 4,       /* workspace allocation failed */
   OCP_E_ORDER = 5,       /* call order violated (e.g. solve before set, adjoint before solve) */
-  OCP_E_UNSUPPORTED = 6  /* feature not available for this model / row kind */
+  OCP_E_UNSUPPORTED = 6, /* feature not available for this model / row kind */
+  OCP_E_SCRATCH = 7      /* problem larger than the no-allocation scratch (ocp_solve_noalloc) */
 } ocp_status;
 
 /* models */
@@ -312,6 +313,29 @@ ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n);
  * runs.  Errors: OCP_E_ARG (null handle / settings, reps < 1, invalid
  * settings), OCP_E_ORDER (no problem data), OCP_E_HIP. */
 ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void* stream, int32_t* seg_min_n);
+
+/* Bytes of device memory the library holds on every GPU it runs on, for the
+ * life of the process, as the workspace of ocp_solve_noalloc. */
+#define OCP_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* One solve that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same work as ocp_create + ocp_set_lti / ocp_set_qp /
+ * ocp_set_bicycle + ocp_solve (cold start) on `stream`, with the workspace
+ * taken from a file-scope device array of OCP_NOALLOC_SCRATCH_BYTES instead of
+ * allocated.  `problem` points to the ocp_lti, ocp_qp or ocp_bicycle struct
+ * that dims->model selects; horizons is a HOST array of B horizons; the
+ * caller owns `problem`'s and `out`'s device buffers as for ocp_solve.
+ * Every call on a GPU shares that GPU's scratch and overwrites what the
+ * previous call left there: calls that overlap on one GPU (different
+ * streams or threads) race, and nothing of a call survives the next one (no
+ * ocp_get_solution / ocp_adjoint afterwards; use a handle for those).  The
+ * call synchronises `stream` once (after laying out the stages).  Errors:
+ * those of ocp_create / ocp_set_* / ocp_solve, and OCP_E_SCRATCH when the
+ * workspace ocp_workspace_bytes reports plus the horizons exceeds
+ * OCP_NOALLOC_SCRATCH_BYTES. */
+ocp_status ocp_solve_noalloc(const ocp_dims* dims, const int32_t* horizons, const void* problem,
+                             const ocp_settings* s, const ocp_solution* out, void* stream);
 
 #ifdef __cplusplus
 }

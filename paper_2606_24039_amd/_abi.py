@@ -10,7 +10,8 @@ import os
 
 from .build import LIB_PATH
 
-OCP_OK, OCP_E_ARG, OCP_E_SHAPE, OCP_E_HIP, OCP_E_NOMEM, OCP_E_ORDER, OCP_E_UNSUPPORTED = range(7)
+OCP_OK, OCP_E_ARG, OCP_E_SHAPE, OCP_E_HIP, OCP_E_NOMEM, OCP_E_ORDER, OCP_E_UNSUPPORTED, OCP_E_SCRATCH = range(8)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 MODEL_QP, MODEL_LTI, MODEL_BICYCLE = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 ROW_HARD, ROW_L2, ROW_L1 = 0, 1, 2
@@ -89,6 +90,8 @@ SIGNATURES = [
     ("ocp_set_segmented", C.c_int, [C.c_void_p, C.c_int32]),
     ("ocp_autotune", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     ("ocp_profile_read", C.c_int, [C.c_void_p, C.POINTER(ocp_kernel_times)]),
+    ("ocp_solve_noalloc", C.c_int, [C.POINTER(ocp_dims), _ip, C.c_void_p, C.POINTER(ocp_settings),
+                                    C.POINTER(ocp_solution), C.c_void_p]),
 ]
 
 _LIB = None

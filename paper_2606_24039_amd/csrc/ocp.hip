@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -64,6 +65,7 @@ struct ocp_handle_s {
   const Entry* entry = nullptr;
   std::vector<void*> allocs;
   size_t bytes = 0;
+  char* carve = nullptr;  // when set, the workspace is carved from here instead of allocated
 
   int64_t* stage_off = nullptr;
   int32_t* order = nullptr;
@@ -118,8 +120,13 @@ template <typename P>
 ocp_status halloc(ocp_handle h, P** p, size_t bytes, bool count_only) {
   bytes = std::max<size_t>(bytes, 8);
   bytes = (bytes + 255) & ~size_t(255);
+  const size_t at = h->bytes;
   h->bytes += bytes;
   if (count_only) return OCP_OK;
+  if (h->carve) {  // the caller has checked that the whole workspace fits
+    *p = (P*)(h->carve + at);
+    return OCP_OK;
+  }
   void* ptr = nullptr;
   if (hipMalloc(&ptr, bytes) != hipSuccess) return OCP_E_NOMEM;
   h->allocs.push_back(ptr);
@@ -259,6 +266,20 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
     h->xinitT = h->xinit;
     h->qT = h->q;
     h->bdT = h->bd;
+  }
+  if (h->carve) {
+    // carved workspace: the caller clears it and lays out the stages on the
+    // device (no host buffers); only the padding offsets are applied here
+    const size_t tsz = h->tsz();
+    void** padded[] = {&h->SubA, &h->SubB, &h->ChF, &h->ChB, &h->x, &h->v, &h->yf, &h->zg, &h->yg, &h->xi,
+                       (void**)&h->adj_v, (void**)&h->adj_P, (void**)&h->adj_K, (void**)&h->adj_Kb};
+    const size_t stage_bytes[] = {tsz * nn,  tsz * nn,  tsz * nn,  tsz * nn,  tsz * ROW,
+                                  tsz * ROW, tsz * ROW, tsz * ROW, tsz * ROW, tsz * ROW,
+                                  sizeof(double) * ROW, sizeof(double) * nn, sizeof(double) * nn,
+                                  sizeof(double) * nn};
+    for (int k = 0; k < 14; ++k)
+      if (*padded[k]) *padded[k] = (char*)*padded[k] + stage_bytes[k] * STAGE_PAD;
+    return OCP_OK;
   }
   // stage offsets and longest-first processing order (host -> device, once)
   std::vector<int64_t> off(B + 1, 0);
@@ -549,6 +570,31 @@ ocp_status bicycle_sqp(ocp_handle h, const ocp_settings* s, hipStream_t st) {
   return hip_ok(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of the no-allocation entry point: a file-scope device array, one
+// copy per GPU for the life of the process.  Host code reaches it only through
+// the address hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[OCP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's scratch (looked up once per device)
+ocp_status scratch_base(char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return OCP_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return OCP_E_HIP;
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return OCP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -583,6 +629,7 @@ void ocp_default_settings(ocp_settings* s) {
 
 const char* ocp_status_string(ocp_status st) {
   switch (st) {
+    case OCP_E_SCRATCH: return "problem exceeds the no-allocation scratch (OCP_NOALLOC_SCRATCH_BYTES)";
     case OCP_OK: return "ok";
     case OCP_E_ARG: return "invalid argument";
     case OCP_E_SHAPE: return "unsupported or inconsistent shape";
@@ -647,8 +694,8 @@ ocp_status ocp_set_lti(ocp_handle h, const ocp_lti* p, void* stream) {
   // a G whose rows each select one distinct variable takes the box-bound kernel variant
   {
     const int ng = h->d.ng, n = h->n;
-    std::vector<double> Gh((size_t)std::max(ng, 1) * n, 0.0);
-    if (ng > 0 && (hipMemcpyAsync(Gh.data(), p->G, sizeof(double) * ng * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+    double Gh[ROW * ROW] = {0.0};  // ng, n <= ROW (checked at creation)
+    if (ng > 0 && (hipMemcpyAsync(Gh, p->G, sizeof(double) * ng * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
                    hipStreamSynchronize(st) != hipSuccess))
       return OCP_E_HIP;
     bool sel = true;
@@ -668,7 +715,7 @@ ocp_status ocp_set_lti(ocp_handle h, const ocp_lti* p, void* stream) {
     std::memcpy(h->ginv, gi, 16);
   }
   std::memset(h->soft_host, 0, sizeof(h->soft_host));
-  if (hipMemsetAsync(h->soft, 0, 16, st) != hipSuccess) return OCP_E_HIP;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, (uint64_t*)h->soft, (size_t)2);
   refresh_copies(h, st);
   h->data_set = true;
   h->solved = false;
@@ -707,7 +754,7 @@ ocp_status ocp_set_qp(ocp_handle h, const ocp_qp* p, void* stream) {
     for (int r = 0; r < ng && ok; ++r)
       if (h->soft_host[r] > OCP_ROW_L1) return OCP_E_ARG;
   } else {
-    ok = ok && hipMemsetAsync(h->soft, 0, 16, st) == hipSuccess;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, (uint64_t*)h->soft, (size_t)2);
   }
   if (!ok) return OCP_E_HIP;
   if (!h->ti) {
@@ -942,6 +989,52 @@ ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void*
   const ocp_status r = ocp_set_segmented(h, pick);
   if (seg_min_n) *seg_min_n = h->seg_min_n;
   return r;
+}
+
+ocp_status ocp_solve_noalloc(const ocp_dims* d, const int32_t* horizons, const void* problem, const ocp_settings* s,
+                             const ocp_solution* out, void* stream) {
+  ocp_status st = check_dims(d, horizons);
+  if (st != OCP_OK) return st;
+  if (!problem) return OCP_E_ARG;
+  st = check_settings(s);
+  if (st != OCP_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  // host bookkeeping lives on the stack for this call (its vectors stay empty)
+  ocp_handle_s h;
+  st = build(&h, d, horizons, true);
+  if (st != OCP_OK) return st;
+  const size_t ws = h.bytes;
+  const size_t hz_bytes = ((size_t)d->batch * sizeof(int32_t) + 255) & ~size_t(255);
+  if (ws + hz_bytes > (size_t)OCP_NOALLOC_SCRATCH_BYTES) return OCP_E_SCRATCH;
+  char* base = nullptr;
+  st = scratch_base(&base);
+  if (st != OCP_OK) return st;
+  h = ocp_handle_s();
+  h.carve = base;
+  st = build(&h, d, horizons, false);
+  if (st != OCP_OK) return st;
+  // the scratch keeps the previous call's contents: clear the workspace (the
+  // zero padding stages and blocks the factorisations never write), then lay
+  // out the stages from a device copy of the horizons
+  int32_t* hz_dev = (int32_t*)(base + ws);
+  const size_t words = ws / sizeof(uint64_t);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::min<size_t>((words + 255) / 256, 4096)), dim3(256), 0, hs,
+                     (uint64_t*)base, words);
+  if (hipMemcpyAsync(hz_dev, horizons, sizeof(int32_t) * d->batch, hipMemcpyHostToDevice, hs) != hipSuccess)
+    return OCP_E_HIP;
+  hipLaunchKernelGGL(stage_layout_kernel, dim3(1), dim3(1024), 0, hs, hz_dev, d->batch, h.stage_off, h.order,
+                     h.stage_inst);
+  // the caller's horizons array may be released once this returns
+  if (hipStreamSynchronize(hs) != hipSuccess || hipGetLastError() != hipSuccess) return OCP_E_HIP;
+  switch (d->model) {
+    case OCP_MODEL_LTI: st = ocp_set_lti(&h, (const ocp_lti*)problem, stream); break;
+    case OCP_MODEL_QP: st = ocp_set_qp(&h, (const ocp_qp*)problem, stream); break;
+    default: st = ocp_set_bicycle(&h, (const ocp_bicycle*)problem, stream); break;
+  }
+  if (st != OCP_OK) return st;
+  ocp_settings cold = *s;
+  cold.warm_start = 0;
+  return ocp_solve(&h, &cold, out, stream);
 }
 
 }  // extern "C"

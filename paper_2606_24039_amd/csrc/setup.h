@@ -95,6 +95,34 @@ __global__ void zero_last_stage_kernel(double* __restrict__ p, const int64_t* __
   for (int k = threadIdx.x; k < sz; k += blockDim.x) q[k] = 0.0;
 }
 
+// clear n 64-bit words (a kernel rather than a memset node, so the clearing
+// also replays correctly inside a captured graph)
+__global__ void zero_u64_kernel(uint64_t* __restrict__ p, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    p[k] = 0;
+}
+
+// Stage layout of a ragged batch on the device (one workgroup): stage
+// offsets (prefix sums of N_b + 1), the longest-first processing order (a
+// stable descending rank: instance b goes after every longer one and after
+// the equal ones before it) and the instance of every stage.
+__global__ void stage_layout_kernel(const int32_t* __restrict__ hz, int B, int64_t* __restrict__ off,
+                                    int32_t* __restrict__ order, int32_t* __restrict__ stage_inst) {
+  if (threadIdx.x == 0) {
+    int64_t acc = 0;
+    off[0] = 0;
+    for (int b = 0; b < B; ++b) off[b + 1] = (acc += hz[b] + 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    const int hb = hz[b];
+    int rank = 0;
+    for (int c = 0; c < B; ++c) rank += (hz[c] > hb) || (hz[c] == hb && c < b);
+    order[rank] = b;
+    for (int64_t k = off[b]; k < off[b + 1]; ++k) stage_inst[k] = b;
+  }
+}
+
 // compact FP64 [S][w] -> padded [S][ROW] state
 template <typename T>
 __global__ void pad_kernel(const double* __restrict__ src, T* __restrict__ dst, int64_t S, int w) {
