@@ -192,14 +192,28 @@ def _speye(m):
 
 
 def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record=False,
-               mats: _QPMats | None = None) -> ADMMResult:
+               mats: _QPMats | None = None, scaling=None) -> ADMMResult:
     """Run Algorithm 3 on one QP.
 
     warm: optional dict with any of x, z_g, y_f, y_g, rho_bar (cold start is
     x = 0, z_g = 0, y = 0, rho_bar = rho0).
     record: keep (x, z_g, xi, y_f, y_g) after every iteration in `history`.
+    scaling: an oracle.scaling.Scaling (Remark 4): the iterations run on the
+    rescaled QP and the step-size update uses its residuals, while the
+    stopping test, the reported residuals, the warm start, the history and
+    the result are in the original variables.
     """
-    M = mats or _QPMats(qp)
+    if scaling is not None:
+        from .scaling import scale_qp, to_scaled, to_unscaled
+
+        Mg = mats or _QPMats(qp)  # the original problem: stopping test and reported residuals
+        qp = scale_qp(qp, scaling)
+        M = _QPMats(qp)
+        fwd = lambda *v: to_scaled(Mg.qp, scaling, *v)  # noqa: E731
+        back = lambda *v: to_unscaled(Mg.qp, scaling, *v)  # noqa: E731
+    else:
+        M = Mg = mats or _QPMats(qp)
+        fwd = back = lambda *v: v  # noqa: E731
     nvar, neq, nin = qp.nvar, qp.neq, qp.nineq
     warm = warm or {}
     x = np.array(warm.get("x", np.zeros(nvar)), dtype=float)
@@ -207,6 +221,8 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
     y_f = np.array(warm.get("y_f", np.zeros(neq)), dtype=float)
     y_g = np.array(warm.get("y_g", np.zeros(nin)), dtype=float)
     xi = np.zeros(nin)
+    if scaling is not None:
+        x, z_g, xi, y_f, y_g = fwd(x, z_g, xi, y_f, y_g)
     rho_bar = float(warm.get("rho_bar", st.rho0))
     a = st.alpha
     kind = M.kind
@@ -221,7 +237,7 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
         cf = factor(rho_bar)
         n_factor += 1
     except np.linalg.LinAlgError:
-        return ADMMResult(x, z_g, xi, y_f, y_g, rho_bar, 0, FACTOR_BREAKDOWN,
+        return ADMMResult(*back(x, z_g, xi, y_f, y_g), rho_bar, 0, FACTOR_BREAKDOWN,
                           np.inf, np.inf, n_factor, history)
 
     status = MAX_ITER
@@ -240,12 +256,12 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
         y_f = y_f + rho_f * (zh_f - M.c)
         y_g = y_g + rho_g * (zh_g - z_g)
         if record:
-            history.append((x.copy(), z_g.copy(), xi.copy(), y_f.copy(), y_g.copy()))
+            history.append(tuple(v.copy() for v in back(x, z_g, xi, y_f, y_g)))
 
         check = st.k_check > 0 and k % st.k_check == 0
         adapt = st.adapt_rho and st.k_rho > 0 and k % st.k_rho == 0
         if check or adapt or k == st.max_iter:
-            r_prim, r_dual, ps, ds = M.residuals(x, z_g, xi, y_f, y_g)
+            r_prim, r_dual, ps, ds = Mg.residuals(*back(x, z_g, xi, y_f, y_g))
             if not (np.isfinite(r_prim) and np.isfinite(r_dual)):
                 status = NON_FINITE
                 break
@@ -254,7 +270,9 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
                 status = CONVERGED
                 break
             if adapt and not conv:
-                cand, accept = rho_update(rho_bar, r_prim, r_dual, ps, ds, st)
+                # the step size balances the residuals of the problem the iterations run on
+                rp_i, rd_i, ps_i, ds_i = (r_prim, r_dual, ps, ds) if M is Mg else M.residuals(x, z_g, xi, y_f, y_g)
+                cand, accept = rho_update(rho_bar, rp_i, rd_i, ps_i, ds_i, st)
                 if accept:
                     rho_bar = cand
                     rho_changes.append((k, rho_bar))
@@ -264,7 +282,8 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
                     except np.linalg.LinAlgError:
                         status = FACTOR_BREAKDOWN
                         break
-    return ADMMResult(x, z_g, xi, y_f, y_g, rho_bar, k, status, r_prim, r_dual, n_factor, history, rho_changes)
+    return ADMMResult(*back(x, z_g, xi, y_f, y_g), rho_bar, k, status, r_prim, r_dual, n_factor, history,
+                      rho_changes)
 
 
 def kkt_residuals(qp: StageQP, x, z_g, xi, y_f, y_g):
