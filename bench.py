@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32 = 157.3  # TFLOP/s, MI355X vector FP32 (published)
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X vector FP64 (published)
 PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E (published)
+SCALE_P = 0.6  # exponent of the box normalisation (ocp_set_scaling_box) on the FP32 path
 
 # HBM traffic of the persistent solve launch, per launch, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) of `bench.py --steps 1 --warmup 0
@@ -154,7 +155,7 @@ def upstream_gradient(batch, seed=11):
     return rng.standard_normal((batch.batch * (batch.N + 1), batch.nx + batch.nu))
 
 
-def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True):
+def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=None):
     import torch
 
     from paper_2606_24039_amd import _abi as A
@@ -162,6 +163,8 @@ def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True):
 
     hz = np.full(batch.batch, batch.N)
     s = OCPSolver(batch.nx, batch.nu, batch.ng, hz, model=A.MODEL_LTI, precision=precision)
+    if scale_p is not None:
+        s.set_scaling_box(scale_p)
     s.set_lti(batch.A, batch.B, batch.Qd, batch.Rd, batch.Qfd, batch.G, batch.lo, batch.hi, batch.x0)
     st = A.default_settings(**settings_kw)
     out = s.alloc_solution()
@@ -305,6 +308,8 @@ def main():
                          "c5a / c5b: the long / ragged bicycle horizons")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="instances timed on the oracle (0 = skip)")
     ap.add_argument("--no-sub", action="store_true", help="skip the differentiation and double-integrator sub-results")
+    ap.add_argument("--no-scaling", action="store_true",
+                    help="FP32 path without the problem rescaling (Remark 4) the headline uses")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison")
     ap.add_argument("--no-grad", action="store_true", help="forward solves only (no adjoint in the step)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -332,13 +337,24 @@ def main():
         return
     batch, desc = make_workload(args.workload)
     settings_kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_admm=1000, k_check=25, k_rho=25, eps_active=1e-4)
+    scale_p = None if args.no_scaling else SCALE_P
     log(f"[bench] workload: {desc}")
-    mixed = run_gpu(batch, 1, args.steps, args.warmup, settings_kw, grad=not args.no_grad)
+    mixed = run_gpu(batch, 1, args.steps, args.warmup, settings_kw, grad=not args.no_grad, scale_p=scale_p)
     log(f"[bench] mixed: {json.dumps(mixed)}")
     fp64 = None
+    variants = {}
     if not args.no_fp64:
         fp64 = run_gpu(batch, 0, max(3, args.steps // 4), 1, settings_kw, grad=not args.no_grad)
         log(f"[bench] fp64: {json.dumps(fp64)}")
+        # the other two combinations of precision and rescaling, for context
+        for name, prec, sp in (("fp32_unscaled", 1, None), ("fp64_rescaled", 0, SCALE_P)):
+            if (sp is None) == (scale_p is None) and prec == 1:
+                continue
+            r = run_gpu(batch, prec, max(3, args.steps // 4), 1, settings_kw, grad=not args.no_grad, scale_p=sp)
+            variants[name] = {"value": round(r["solved"] / (r["ms_per_step"] * 1e-3), 2),
+                              "ms_per_step": round(r["ms_per_step"], 4), "solved_fraction": r["solved"] / batch.batch,
+                              "iters_mean": round(r["iters_mean"], 1), "iters_capped": r["iters_capped"]}
+            log(f"[bench] {name}: {json.dumps(r)}")
 
     value = mixed["solved"] / (mixed["ms_per_step"] * 1e-3)
     roof, hbm = roofline(batch, mixed, "mixed", args.workload)
@@ -349,6 +365,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": desc, "batch": batch.batch, "horizon": batch.N, "nx": batch.nx, "nu": batch.nu,
                    "ng": batch.ng, "precision": "fp32 ADMM iterations, fp64 factorisation, gate and adjoint",
+                   "rescaling": (f"box normalisation, power-of-two factors, exponent {scale_p}" if scale_p is not None
+                                 else "none"),
                    "eps": 1e-4, "eps_active": 1e-4, "max_admm": 1000, "grad": not args.no_grad,
                    "parallelism": "single GPU, one instance per wavefront"},
         "admm_iters_per_s": round(mixed["iters_sum"] / (mixed["ms_per_step"] * 1e-3), 1),
@@ -368,6 +386,7 @@ def main():
                        "solved_fraction": fp64["solved"] / batch.batch, "iters_mean": fp64["iters_mean"],
                        "iters_capped": fp64["iters_capped"]}
         out["speedup_vs_fp64"] = round(value / max(out["fp64"]["value"], 1e-9), 3)
+        out["variants"] = variants
     if not args.no_sub:
         out["sub_results"] = sub_results(args)
     if args.cpu_sample > 0:
@@ -430,7 +449,7 @@ def sub_results(args):
     b4 = random_lti(512, N=64, seed=4)
     kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_admm=1000, k_check=25, k_rho=25, eps_active=1e-4)
     steps = max(3, min(args.steps, 10))
-    m = run_gpu(b4, 1, steps, 2, kw, grad=True)
+    m = run_gpu(b4, 1, steps, 2, kw, grad=True, scale_p=None if args.no_scaling else SCALE_P)
     f = run_gpu(b4, 0, steps, 1, kw, grad=True)
     sub["c4_lti512_n64_grad"] = {
         "value": round(m["solved"] / (m["ms_per_step"] * 1e-3), 1), "unit": "QP solves/s (gated, +grad)",

@@ -303,6 +303,43 @@ ocp_status ocp_graph_launch(ocp_handle h, void* stream);
  * OCP_E_ARG (null handle). */
 ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n);
 
+/* Problem rescaling (Remark 4: states and controls normalised inside the
+ * solver, transparently to the caller).  Per instance b: variable factors
+ * d [B,n] (x_t = d * xh_t at every stage), inequality-row factors e_g [B,ng]
+ * and a cost factor c [B] (DEVICE pointers, FP64, all > 0 and finite).  The
+ * next ocp_set_lti / ocp_set_qp loads the rescaled QP
+ *   D_t, E_t -> c diag(d) D_t diag(d), c diag(d) E_t diag(d);  q_t -> c d * q_t;
+ *   Am_t, Ap_t -> diag(1/d_x) Am_t diag(d), diag(1/d_x) Ap_t diag(d);
+ *   b_t -> b_t / d_x;  x_init -> x_init / d_x;
+ *   G_t -> diag(e_g) G_t diag(d);  lo, hi -> e_g * lo, e_g * hi
+ * (A_init = [I 0], A+ = [-I 0] and unit selection rows keep their form when
+ * e_g = 1/d_j on a row selecting variable j; power-of-two factors make the
+ * transform exact).  ADMM (Algorithm 3) iterates on it and adapts the step
+ * size (eq. rho:update) from its residuals; the stopping test, the reported
+ * residuals, the returned solution (x = d xh, z_g = zh/e_g, xi = xih/e_g,
+ * y_f = yh_f/(c d_x), y_g = e_g yh_g/c) and the adjoint's inputs and outputs
+ * are in the original variables.  d = NULL removes the rescaling.  Either way
+ * the loaded data and solution are invalidated (call ocp_set_* again) and a
+ * captured graph is dropped.  Models OCP_MODEL_LTI and OCP_MODEL_QP with hard
+ * rows only.  Synchronises `stream` (to check the factors).  Errors:
+ * OCP_E_ARG (null handle, missing e_g / c, a factor not positive and finite),
+ * OCP_E_UNSUPPORTED (bicycle model; ocp_set_qp returns it for soft rows),
+ * OCP_E_HIP. */
+ocp_status ocp_set_scaling(ocp_handle h, const double* d, const double* e_g, const double* c, void* stream);
+
+/* Box normalisation (Remark 4) derived on the device from every problem
+ * loaded afterwards, per instance, in powers of two (the transform is exact):
+ * a variable j bounded by a hard selection row of G (read at stage 0) gets
+ * d_j = 2^rint(p log2 h_j), h_j the half width of its bounds, others 1;
+ * e_g = 1/d_j on selection rows, 2^-rint(log2 max_j |G_rj d_j|) on other hard
+ * rows; c = 2^-rint(log2 m), m the largest diagonal entry of diag(d) D_t
+ * diag(d) over the instance's stages.  Then as ocp_set_scaling.  p = 0.6 is
+ * the default the benchmark uses (FP32 iterations converge on the random-LTI
+ * workload as often as unscaled FP64 ones).  ocp_set_scaling(h, NULL, ...)
+ * removes it.  Errors: OCP_E_ARG (null handle, p negative or not finite),
+ * OCP_E_UNSUPPORTED (bicycle model). */
+ocp_status ocp_set_scaling_box(ocp_handle h, double p);
+
 /* Autotuner over the launch shape: times `reps` cold-start ocp_solve calls
  * with settings `s` on the handle's own batch for each switch point --
  * 15 (every instance segmented), 128 (the default) and INT32_MAX (none) --

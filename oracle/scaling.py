@@ -48,12 +48,19 @@ def identity_scaling(qp: StageQP) -> Scaling:
     return Scaling(np.ones(qp.n), np.ones(qp.ng), 1.0)
 
 
+def _pow2(v):
+    """The power of two nearest to v > 0 in the logarithm (2^rint(log2 v)):
+    factors that scale exactly in floating point."""
+    return float(np.exp2(np.rint(np.log2(v))))
+
+
 def box_scaling(qp: StageQP, p: float = 0.6) -> Scaling:
-    """Normalisation by the box widths: d_j = (half width of the bound on
-    variable j) ** p for variables boxed by a selection row of G (the same rows
-    at every stage are assumed), 1 for the others; e_g = 1/d_j on selection
-    rows, 1/max_j |G_rj d_j| on other hard rows, 1 on soft rows; c = 1 / the
-    largest diagonal entry of diag(d) D_t diag(d) over the stages."""
+    """Normalisation by the box widths, in powers of two: d_j = 2^rint(p
+    log2 h_j) with h_j the half width of the bound on variable j for
+    variables boxed by a selection row of G (read at stage 0), 1 for the
+    others; e_g = 1/d_j on selection rows, 2^-rint(log2 max_j |G_rj d_j|) on
+    other hard rows, 1 on soft rows; c = 2^-rint(log2 m) with m the largest
+    diagonal entry of diag(d) D_t diag(d) over the stages."""
     n, ng = qp.n, qp.ng
     d = np.ones(n)
     G0 = qp.G[0]
@@ -64,14 +71,18 @@ def box_scaling(qp: StageQP, p: float = 0.6) -> Scaling:
             sel[r] = nz[0]
             half = 0.5 * (qp.hi[0, r] - qp.lo[0, r])
             if np.isfinite(half) and half > 0:
-                d[nz[0]] = half ** p
+                d[nz[0]] = float(np.exp2(np.rint(p * np.log2(half))))
     e_g = np.ones(ng)
     for r in range(ng):
         if qp.soft[r] != HARD:
             continue
-        e_g[r] = 1.0 / d[sel[r]] if sel[r] >= 0 else 1.0 / max(np.max(np.abs(G0[r] * d)), 1e-300)
-    dd = np.array([np.max(np.diag(qp.D[t]) * d * d) for t in range(qp.N + 1)])
-    c = 1.0 / max(float(np.max(dd)), 1e-300)
+        if sel[r] >= 0:
+            e_g[r] = 1.0 / d[sel[r]]
+        else:
+            m = float(np.max(np.abs(G0[r] * d)))
+            e_g[r] = 1.0 / _pow2(m) if m > 0 else 1.0
+    dd = max(float(np.max(np.diag(qp.D[t]) * d * d)) for t in range(qp.N + 1))
+    c = 1.0 / _pow2(dd) if dd > 0 else 1.0
     return Scaling(d, e_g, c)
 
 

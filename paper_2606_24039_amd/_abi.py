@@ -90,6 +90,8 @@ SIGNATURES = [
     ("ocp_set_segmented", C.c_int, [C.c_void_p, C.c_int32]),
     ("ocp_autotune", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     ("ocp_profile_read", C.c_int, [C.c_void_p, C.POINTER(ocp_kernel_times)]),
+    ("ocp_set_scaling", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ocp_set_scaling_box", C.c_int, [C.c_void_p, C.c_double]),
     ("ocp_solve_noalloc", C.c_int, [C.POINTER(ocp_dims), _ip, C.c_void_p, C.POINTER(ocp_settings),
                                     C.POINTER(ocp_solution), C.c_void_p]),
 ]

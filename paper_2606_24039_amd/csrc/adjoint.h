@@ -124,6 +124,8 @@ __device__ __forceinline__ double adjoint_sweeps_ti(const Layout& L, const AdjAr
   const int ic = i < n ? i : n - 1;
   const int nfull = N / 4;
   const double rb = a.rho_b;
+  // rescaled QP: the loss gradient w.r.t. xh = x / d is d * dL/dx
+  const double dls = L.sc ? L.sc[(size_t)w.b * 3 * ROW + i] : 1.0;
   TIBlocks64<NX, NU, NG, ST> tb;
   tb.load(L, w.b, i);
   const bool hasE = L.E != nullptr;
@@ -169,7 +171,7 @@ __device__ __forceinline__ double adjoint_sweeps_ti(const Layout& L, const AdjAr
         d.efr = ldo(ef, o);          // dynamics row t-1, or the initial-state rows at t = 0
         d.wc = ldo(wv, o);
         d.eg = ldo(eg, o);
-        d.dl = ldo(dL, (uint32_t)((min(t, N) * n + ic) * (int)sizeof(double)));
+        d.dl = ldo(dL, (uint32_t)((min(t, N) * n + ic) * (int)sizeof(double))) * dls;
       };
       auto comp = [&](const AdjIn1& d, int blk, auto full) {
         constexpr bool FULL = decltype(full)::value;
@@ -349,6 +351,7 @@ __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjAr
   const int nfull = N / 4;
   const size_t nn = (size_t)n * n;
   const double rb = a.rho_b;
+  const double dls = L.sc ? L.sc[(size_t)b * 3 * ROW + i] : 1.0;  // rescaled QP: d * dL/dx
   const gptr<double> ex = as_global(a.ex), ef = as_global(a.ef), eg = as_global(a.eg);
   const gptr<double> rf = as_global(a.rf), rg = as_global(a.rg), wv = as_global(a.w);
   const gptr<double> R = as_global(a.v) + (size_t)s0 * ROW + i;
@@ -382,7 +385,7 @@ __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjAr
         d.ef0 = (t == 0 && i < NX) ? ef[sv] : 0.0;       // initial-state rows
         d.wc = (i < NG) ? wv[sv] : 0.0;
         d.eg = (i < NG) ? eg[sv] : 0.0;
-        d.dl = (i < n) ? a.dLdx[(size_t)s * n + i] : 0.0;
+        d.dl = (i < n) ? a.dLdx[(size_t)s * n + i] * dls : 0.0;
       };
       auto comp = [&](const In& d, int blk, auto) {
         const int t = 4 * blk + q;
@@ -508,13 +511,21 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   const int kind = (i < NG) ? (int)L.soft[i] : 0;
   const bool slr = kind == 1;  // L2-slack row (in H when active)
   const double rb = a.rho_b;
+  // rescaled QP (Remark 4): the active set is judged and the results are
+  // returned in the original variables.  Lane factors: d_i (variable), e_i
+  // (inequality row), c; all 1 without rescaling.
+  const double* scb = L.sc ? L.sc + (size_t)b * 3 * ROW : nullptr;
+  const double sd = scb ? scb[i] : 1.0, se = scb ? scb[ROW + i] : 1.0, scc = scb ? scb[2 * ROW] : 1.0;
+  const double yw = se / scc;       // y_g = e yh_g / c
+  const double exw = scc * sd;      // eta_x = c d etah_x
+  const double efw = 1.0 / sd;      // eta_f = etah_f / d_x (lane = state component)
 
   // ---- 1. active set ----
   double ymax = 0.0, dlmax = 0.0;
   for (int blk = 0; blk < nbl; ++blk) {
     const int t = 4 * blk + q;
-    if (t <= N && i < NG) ymax = fmax(ymax, fabs(double(YG[(size_t)(s0 + t) * ROW + i])));
-    if (t <= N && i < n) dlmax = fmax(dlmax, fabs(a.dLdx[(size_t)(s0 + t) * n + i]));
+    if (t <= N && i < NG) ymax = fmax(ymax, fabs(double(YG[(size_t)(s0 + t) * ROW + i]) * yw));
+    if (t <= N && i < n) dlmax = fmax(dlmax, fabs(a.dLdx[(size_t)(s0 + t) * n + i] * sd));
   }
   ymax = rows_max(row_max(ymax));
   dlmax = rows_max(row_max(dlmax));
@@ -528,11 +539,12 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     const double xc = (i < n) ? double(X[sv]) : 0.0;
     double Gr[n];
     load_row<n>(Gr, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (size_t)(i < NG ? i : NG - 1) * n, true);
-    const double gx = dotb<n>(Gr, xc, 0.0);
+    const double gx = dotb<n>(Gr, xc, 0.0) / se;
     int act = 0;
     if (i < NG) {
       const size_t sb = ti_or_tv(L.ti, b, s, NG) + i;
-      const double lo = L.lo[sb], hi = L.hi[sb], y = double(YG[sv]);
+      // original-variable row value, bounds and multiplier
+      const double lo = L.lo[sb] / se, hi = L.hi[sb] / se, y = double(YG[sv]) * yw;
       const bool amb = fabs(y) < epsg;
       bool lower = (y < -epsg) || (amb && (gx - lo <= epsp * fmax(1.0, fabs(lo))));
       bool upper = (y > epsg) || (amb && (hi - gx <= epsp * fmax(1.0, fabs(hi))));
@@ -588,11 +600,11 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     const int64_t s = s0 + t;
     const size_t sv = (size_t)s * ROW + i;
     if (i < n) {
-      const double e = ex[sv] + nanv;
+      const double e = ex[sv] * exw + nanv;
       nonfin |= !isfinite(e);
       if (a.eta_x) a.eta_x[(size_t)s * n + i] = e;
       if (a.d_q) a.d_q[(size_t)s * n + i] = -e;
-      if (a.d_Ddiag) a.d_Ddiag[(size_t)s * n + i] = -e * double(X[sv]);
+      if (a.d_Ddiag) a.d_Ddiag[(size_t)s * n + i] = -e * double(X[sv]) * sd;
     }
     // eta_y of an active slack row: gamma2 G_i eta_x (its row of the reduced system)
     double Gr[n];
@@ -600,7 +612,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     const double gex = dotb<n>(Gr, (i < n) ? ex[sv] : 0.0, 0.0);
     if (i < NG) {
       const int act = a.act[sv];
-      const double e = ((kind == 1 && act != 0) ? L.gamma2 * gex : eg[sv]) + nanv;
+      const double e = ((kind == 1 && act != 0) ? L.gamma2 * gex : eg[sv]) * se + nanv;
       if (kind == 1 && act != 0) dgam += double(XI[sv]) * gex;
       if (act != 0) nonfin |= !isfinite(e);
       if (a.d_lo) a.d_lo[(size_t)s * NG + i] = (act < 0) ? e : 0.0;
@@ -611,7 +623,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     if (i < NX) {
       // equality rows in the slot convention of y_f: the initial-state rows
       // at stage 0, dynamics row t - 1 at stage t
-      const double e = ef[sv] + nanv;
+      const double e = ef[sv] * efw + nanv;
       nonfin |= !isfinite(e);
       if (a.eta_f) a.eta_f[(size_t)s * NX + i] = e;
       if (t == 0 && a.d_x_init) a.d_x_init[(size_t)b * NX + i] = e;

@@ -124,9 +124,33 @@ constexpr int chain_prefetch() {
   return (sizeof(T) == 8 && n > 8) ? 4 : 8;
 }
 
+// residuals and scales of the QP the iterations run on (rp, rd, ps, ds: the
+// step-size update), and of the original problem (the _u fields, equal without
+// rescaling: the stopping test and the reported residuals)
 struct Resid {
   double rp, rd, ps, ds;
+  double rp_u, rd_u, ps_u, ds_u;
   int nonfinite;
+};
+
+// Per-lane weights that take a residual entry of the rescaled QP to the
+// original problem: equality rows (lane = state component) d_x, inequality
+// rows 1/e_g, stationarity rows (lane = variable component) 1/(c d), slack
+// terms 1/c.  All 1 without rescaling.
+struct ResW {
+  double f, g, d, s;
+  __device__ __forceinline__ void load(const Layout& L, int b, int i) {
+    if (!L.sc) {
+      f = g = d = s = 1.0;
+      return;
+    }
+    const double* p = L.sc + (size_t)b * 3 * ROW;
+    const double di = p[i], ei = p[ROW + i], c = p[2 * ROW + i];
+    f = di;
+    g = 1.0 / ei;
+    d = 1.0 / (c * di);
+    s = 1.0 / c;
+  }
 };
 
 constexpr int32_t ST_RUNNING = -1;

@@ -166,6 +166,10 @@ struct Layout {
   const double* x_init;  // [B][nx]
   const uint8_t* soft;   // [ng]
   double gamma2, gamma1;
+  // problem rescaling (Remark 4), [B][3][ROW]: variable factors d (x = d xh),
+  // inequality-row factors e_g, and the cost factor c in every lane of the
+  // third row; the data above are those of the rescaled QP.  Null: none.
+  const double* sc;
 
   // iteration-precision copies of the data read every ADMM iteration
   const void* AmT;

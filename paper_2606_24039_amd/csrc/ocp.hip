@@ -86,6 +86,9 @@ struct ocp_handle_s {
   int32_t *status = nullptr, *iters = nullptr, *nfact = nullptr, *need = nullptr;
   double gamma2 = 1.0, gamma1 = 1.0;
   bool has_E = false, has_q = false, has_bd = false;
+  double* sc = nullptr;  // rescaling factors [B][3][ROW] (Remark 4)
+  bool scaled = false;   // the loaded data are rescaled by sc
+  double box_p = -1.0;   // >= 0: derive sc from each loaded problem (box normalisation, exponent box_p)
   bool data_set = false, solved = false;
 
   // bicycle model state
@@ -244,6 +247,7 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
     A_(h->sqp_frozen, sizeof(int32_t) * B);
   }
   A_(h->stage_inst, sizeof(int32_t) * S);
+  A_(h->sc, sizeof(double) * 3 * ROW * B);
   A_(h->adj_rhog, sizeof(double) * ROW * S);
   A_(h->adj_ex, sizeof(double) * ROW * S);
   A_(h->adj_ey, sizeof(double) * ROW * S);
@@ -365,6 +369,7 @@ Layout make_layout(ocp_handle h) {
   L.soft = h->soft;
   L.gamma2 = h->gamma2;
   L.gamma1 = h->gamma1;
+  L.sc = h->scaled ? h->sc : nullptr;
   L.AmT = h->AmT;
   L.ApT = h->ApT;
   L.GT = h->GT;
@@ -431,12 +436,14 @@ ocp_status check_settings(const ocp_settings* s) {
   return OCP_OK;
 }
 
+// padded state -> caller's FP64 array; on a rescaled QP times the factor
+// `code` that maps the entry back to the original variables
 template <typename T>
-void unpad(const void* src, double* dst, int64_t S, int w, hipStream_t st) {
+void unpad(ocp_handle h, const void* src, double* dst, int w, int code, hipStream_t st) {
   if (!dst || w == 0) return;
-  const size_t len = (size_t)S * w;
-  hipLaunchKernelGGL(unpad_kernel<T>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, (const T*)src, dst, S,
-                     w);
+  const size_t len = (size_t)h->S * w;
+  hipLaunchKernelGGL(unpad_kernel<T>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, (const T*)src, dst,
+                     h->S, w, h->stage_inst, h->scaled ? (const double*)h->sc : nullptr, code);
 }
 
 template <typename T>
@@ -444,7 +451,43 @@ void unpad_yf(ocp_handle h, const void* src, double* dst, hipStream_t st) {
   if (!dst) return;
   const size_t len = (size_t)h->S * h->d.nx;
   hipLaunchKernelGGL(unpad_yf_kernel<T>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, (const T*)src, dst,
-                     h->stage_off, h->stage_inst, h->S, h->d.nx);
+                     h->stage_off, h->stage_inst, h->S, h->d.nx, h->scaled ? (const double*)h->sc : nullptr);
+}
+
+// Rescale the loaded FP64 QP data in place by the handle's factors (Remark
+// 4; the transform is listed in the header at ocp_set_scaling).
+void apply_scaling(ocp_handle h, hipStream_t st) {
+  if (!h->scaled) return;
+  const int n = h->n, nx = h->d.nx, ng = h->d.ng, B = h->B;
+  const int64_t S = h->S, blkI = h->ti ? (int64_t)B : S;
+  const int per = h->ti ? 1 : 0;
+  if (h->box_p >= 0.0)
+    hipLaunchKernelGGL(box_scaling_kernel, dim3((B + 63) / 64), dim3(64), 0, st, B, n, ng, h->ti ? 1 : 0,
+                       (const int64_t*)h->stage_off, (const double*)h->D, (const double*)h->G, (const double*)h->lo,
+                       (const double*)h->hi, (const uint8_t*)h->soft, h->box_p, h->sc);
+  auto run = [&](double* p, int64_t nblk, int R, int Cc, int per_, int rowf, int colf) {
+    const int64_t len = nblk * R * Cc;
+    if (!p || len == 0) return;
+    hipLaunchKernelGGL(scale_blocks_kernel, dim3((unsigned)std::min<int64_t>((len + 255) / 256, 8192)), dim3(256), 0,
+                       st, p, nblk, R, Cc, per_, h->stage_inst, (const double*)h->sc, rowf, colf);
+  };
+  run(h->D, h->ti ? 2 * (int64_t)B : S, n, n, h->ti ? 2 : 0, SF_CD, SF_D);
+  if (h->has_E) run(h->E, blkI, n, n, per, SF_CD, SF_D);
+  if (h->has_q) run(h->q, S, 1, n, 0, SF_C, SF_D);
+  run(h->Am, blkI, nx, n, per, SF_INV_D, SF_D);
+  run(h->Ap, blkI, nx, n, per, SF_INV_D, SF_D);
+  if (h->has_bd) run(h->bd, blkI, 1, nx, per, SF_ONE, SF_INV_D);
+  run(h->G, blkI, ng, n, per, SF_E, SF_D);
+  run(h->lo, blkI, 1, ng, per, SF_ONE, SF_E);
+  run(h->hi, blkI, 1, ng, per, SF_ONE, SF_E);
+  run(h->xinit, B, 1, nx, 1, SF_ONE, SF_INV_D);
+}
+
+void drop_graph(ocp_handle h) {
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->graph_exec = nullptr;
+  h->graph = nullptr;
 }
 
 ocp_status copy_out(ocp_handle h, const ocp_solution* o, hipStream_t st) {
@@ -452,23 +495,23 @@ ocp_status copy_out(ocp_handle h, const ocp_solution* o, hipStream_t st) {
   const int64_t S = h->S;
   const int B = h->B;
   if (h->mixed) {
-    unpad<float>(h->x, o->x, S, h->n, st);
-    unpad<float>(h->xi, o->xi, S, h->d.ng, st);
-    unpad<float>(h->zg, o->z_g, S, h->d.ng, st);
+    unpad<float>(h, h->x, o->x, h->n, SF_D, st);
+    unpad<float>(h, h->xi, o->xi, h->d.ng, SF_INV_E, st);
+    unpad<float>(h, h->zg, o->z_g, h->d.ng, SF_INV_E, st);
     unpad_yf<float>(h, h->yf, o->y_f, st);
-    unpad<float>(h->yg, o->y_g, S, h->d.ng, st);
+    unpad<float>(h, h->yg, o->y_g, h->d.ng, SF_E_OVER_C, st);
   } else {
-    unpad<double>(h->x, o->x, S, h->n, st);
-    unpad<double>(h->xi, o->xi, S, h->d.ng, st);
-    unpad<double>(h->zg, o->z_g, S, h->d.ng, st);
+    unpad<double>(h, h->x, o->x, h->n, SF_D, st);
+    unpad<double>(h, h->xi, o->xi, h->d.ng, SF_INV_E, st);
+    unpad<double>(h, h->zg, o->z_g, h->d.ng, SF_INV_E, st);
     unpad_yf<double>(h, h->yf, o->y_f, st);
-    unpad<double>(h->yg, o->y_g, S, h->d.ng, st);
+    unpad<double>(h, h->yg, o->y_g, h->d.ng, SF_E_OVER_C, st);
   }
-  if (h->d.model == OCP_MODEL_BICYCLE) {  // the SQP iterate is the solution
-    unpad<double>(h->xbar, o->x, S, h->n, st);
-    unpad<double>(h->xibar, o->xi, S, h->d.ng, st);
+  if (h->d.model == OCP_MODEL_BICYCLE) {  // the SQP iterate is the solution (never rescaled)
+    unpad<double>(h, h->xbar, o->x, h->n, SF_ONE, st);
+    unpad<double>(h, h->xibar, o->xi, h->d.ng, SF_ONE, st);
     unpad_yf<double>(h, h->yfbar, o->y_f, st);
-    unpad<double>(h->ygbar, o->y_g, S, h->d.ng, st);
+    unpad<double>(h, h->ygbar, o->y_g, h->d.ng, SF_ONE, st);
     if (o->sqp_kkt && hipMemcpyAsync(o->sqp_kkt, h->kkt, sizeof(double) * 3 * B, hipMemcpyDeviceToDevice, st) != hipSuccess)
       return OCP_E_HIP;
     if (o->sqp_iters &&
@@ -716,6 +759,7 @@ ocp_status ocp_set_lti(ocp_handle h, const ocp_lti* p, void* stream) {
   }
   std::memset(h->soft_host, 0, sizeof(h->soft_host));
   hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, (uint64_t*)h->soft, (size_t)2);
+  apply_scaling(h, st);
   refresh_copies(h, st);
   h->data_set = true;
   h->solved = false;
@@ -766,6 +810,10 @@ ocp_status ocp_set_qp(ocp_handle h, const ocp_qp* p, void* stream) {
   h->gamma2 = p->gamma2;
   h->gamma1 = p->gamma1;
   h->variant = h->ti ? VAR_TI : VAR_TV;
+  if (h->scaled)
+    for (int r = 0; r < ng; ++r)
+      if (h->soft_host[r] != OCP_ROW_HARD) return OCP_E_UNSUPPORTED;  // soft rows are not rescaled
+  apply_scaling(h, st);
   refresh_copies(h, st);
   h->data_set = true;
   h->solved = false;
@@ -949,6 +997,45 @@ ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n) {
     h->graph = nullptr;
   }
   h->seg_min_n = std::max<int32_t>(seg_min_n, SEG_FLOOR_N);
+  return OCP_OK;
+}
+
+ocp_status ocp_set_scaling(ocp_handle h, const double* d, const double* e_g, const double* c, void* stream) {
+  if (!h) return OCP_E_ARG;
+  drop_graph(h);  // a captured graph keeps the data layout it was recorded with
+  h->data_set = false;
+  h->solved = false;
+  h->box_p = -1.0;
+  if (!d) {
+    h->scaled = false;
+    return OCP_OK;
+  }
+  if ((h->d.ng > 0 && !e_g) || !c) return OCP_E_ARG;
+  if (h->d.model == OCP_MODEL_BICYCLE) return OCP_E_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  const int B = h->B, n = h->n, ng = h->d.ng;
+  hipLaunchKernelGGL(pack_scaling_kernel, dim3((unsigned)std::min<int64_t>(((int64_t)B * 3 * ROW + 255) / 256, 4096)),
+                     dim3(256), 0, st, d, ng > 0 ? e_g : d, c, B, n, ng, h->sc);
+  // the factors must be positive and finite
+  std::vector<double> hs((size_t)B * 3 * ROW);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(hs.data(), h->sc, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return OCP_E_HIP;
+  for (double v : hs)
+    if (!(v > 0.0) || !std::isfinite(v)) return OCP_E_ARG;
+  h->scaled = true;
+  return OCP_OK;
+}
+
+ocp_status ocp_set_scaling_box(ocp_handle h, double p) {
+  if (!h || !(p >= 0.0) || !std::isfinite(p)) return OCP_E_ARG;
+  if (h->d.model == OCP_MODEL_BICYCLE) return OCP_E_UNSUPPORTED;
+  drop_graph(h);
+  h->data_set = false;
+  h->solved = false;
+  h->scaled = true;
+  h->box_p = p;
   return OCP_OK;
 }
 

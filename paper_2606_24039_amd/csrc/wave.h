@@ -916,10 +916,16 @@ __device__ __forceinline__ Resid residuals_gen(const Layout& L, const WaveGroup&
   const gptr<const T> XI = as_global((const T*)L.xi);
   double m_cxc = 0, m_cx = 0, m_c = 0, m_gxz = 0, m_gx = 0, m_z = 0;
   double m_dual = 0, m_px = 0, m_aty = 0, m_q = 0, m_sres = 0, m_sscale = 0;
+  // the same maxima for the original problem (rescaling weights rw)
+  double u_cxc = 0, u_cx = 0, u_c = 0, u_gxz = 0, u_gx = 0, u_z = 0;
+  double u_dual = 0, u_px = 0, u_aty = 0, u_q = 0, u_sres = 0, u_sscale = 0;
+  ResW rw;
+  rw.load(L, b, i);
   int nf = 0;
-  auto upd = [&](double& m, double v) {
+  auto upd = [&](double& m, double& mu, double v, double wgt) {
     if (!isfinite(v)) nf = 1;
     m = fmax(m, fabs(v));
+    mu = fmax(mu, fabs(v) * wgt);
   };
   // blocks of stage t (TI: read once, the terminal D_N separately)
   double Dr[n], DrN[TI ? n : 1], Ec[n], Er[n], Amc[NX], Apc[NX], Amr[n], Apr[n], Gc[NG], Gr[n], cv = 0.0;
@@ -997,41 +1003,41 @@ __device__ __forceinline__ Resid residuals_gen(const Layout& L, const WaveGroup&
     aty = dotb<NG>(Gc, ygv, aty);
     const double qv = (L.q && i < n) ? as_global(L.q)[(size_t)s * n + i] : 0.0;
     if (i < n) {
-      upd(m_dual, px + qv + aty);
-      upd(m_px, px);
-      upd(m_aty, aty);
-      upd(m_q, qv);
+      upd(m_dual, u_dual, px + qv + aty, rw.d);
+      upd(m_px, u_px, px, rw.d);
+      upd(m_aty, u_aty, aty, rw.d);
+      upd(m_q, u_q, qv, rw.d);
     }
     // equality rows touching stage t
     if (t == 0 && i < NX) {
-      upd(m_cxc, xc - xi0);
-      upd(m_cx, xc);
-      upd(m_c, xi0);
+      upd(m_cxc, u_cxc, xc - xi0, rw.f);
+      upd(m_cx, u_cx, xc, rw.f);
+      upd(m_c, u_c, xi0, rw.f);
     }
     double cx = dotb<n>(Amr, xc, 0.0);
     cx = dotb<n>(Apr, xn, cx);
     if (t < N && i < NX) {
-      upd(m_cxc, cx - cv);
-      upd(m_cx, cx);
-      upd(m_c, cv);
+      upd(m_cxc, u_cxc, cx - cv, rw.f);
+      upd(m_cx, u_cx, cx, rw.f);
+      upd(m_c, u_c, cv, rw.f);
     }
     // inequality rows of stage t
     const double gx = dotb<n>(Gr, xc, 0.0);
     if (i < NG) {
       const double zv = double(ZG[sv]);
-      upd(m_gxz, gx - zv);
-      upd(m_gx, gx);
-      upd(m_z, zv);
+      upd(m_gxz, u_gxz, gx - zv, rw.g);
+      upd(m_gx, u_gx, gx, rw.g);
+      upd(m_z, u_z, zv, rw.g);
       const double xiv = double(XI[sv]);
       if (kind == 1) {
-        upd(m_sres, gamma2 * xiv + ygv);
-        upd(m_sscale, gamma2 * xiv);
-        upd(m_sscale, ygv);
+        upd(m_sres, u_sres, gamma2 * xiv + ygv, rw.s);
+        upd(m_sscale, u_sscale, gamma2 * xiv, rw.s);
+        upd(m_sscale, u_sscale, ygv, rw.s);
       } else if (kind == 2) {
         const double r1 = (xiv != 0.0) ? fabs(ygv + gamma1 * (xiv > 0 ? 1.0 : -1.0)) : fmax(fabs(ygv) - gamma1, 0.0);
-        upd(m_sres, r1);
-        upd(m_sscale, xiv != 0.0 ? gamma1 : 0.0);
-        upd(m_sscale, ygv);
+        upd(m_sres, u_sres, r1, rw.s);
+        upd(m_sscale, u_sscale, xiv != 0.0 ? gamma1 : 0.0, rw.s);
+        upd(m_sscale, u_sscale, ygv, rw.s);
       }
     }
   }
@@ -1040,6 +1046,14 @@ __device__ __forceinline__ Resid residuals_gen(const Layout& L, const WaveGroup&
   R.ps = rows_max(row_max(fmax(fmax(m_cx, m_gx), fmax(m_c, m_z))));
   R.rd = rows_max(row_max(fmax(m_dual, m_sres)));
   R.ds = rows_max(row_max(fmax(fmax(m_px, m_aty), fmax(m_q, m_sscale))));
+  if (L.sc) {
+    R.rp_u = rows_max(row_max(fmax(u_cxc, u_gxz)));
+    R.ps_u = rows_max(row_max(fmax(fmax(u_cx, u_gx), fmax(u_c, u_z))));
+    R.rd_u = rows_max(row_max(fmax(u_dual, u_sres)));
+    R.ds_u = rows_max(row_max(fmax(fmax(u_px, u_aty), fmax(u_q, u_sscale))));
+  } else {
+    R.rp_u = R.rp, R.ps_u = R.ps, R.rd_u = R.rd, R.ds_u = R.ds;
+  }
   R.nonfinite = rows_max(row_max(nf));
   return R;
 }
@@ -1076,10 +1090,16 @@ __device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& 
   const bool gid = __ballot(i < NG && gsel != i) == 0;
   double m_cxc = 0, m_cx = 0, m_c = 0, m_gxz = 0, m_gx = 0, m_z = 0;
   double m_dual = 0, m_px = 0, m_aty = 0, m_q = 0, m_sres = 0, m_sscale = 0;
+  // the same maxima for the original problem (rescaling weights rw)
+  double u_cxc = 0, u_cx = 0, u_c = 0, u_gxz = 0, u_gx = 0, u_z = 0;
+  double u_dual = 0, u_px = 0, u_aty = 0, u_q = 0, u_sres = 0, u_sscale = 0;
+  ResW rw;
+  rw.load(L, b, i);
   int nf = 0;
-  auto upd = [&](double& m, double v) {
+  auto upd = [&](double& m, double& mu, double v, double wgt) {
     if (!isfinite(v)) nf = 1;
     m = fmax(m, fabs(v));
+    mu = fmax(mu, fabs(v) * wgt);
   };
   auto load = [&](ResIn<T>& d, int blk) {
     const int t = 4 * blk + q;
@@ -1127,16 +1147,16 @@ __device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& 
     }
     const double qv = (i < n) ? d.q : 0.0;
     if (i < n) {
-      upd(m_dual, px + qv + aty);
-      upd(m_px, px);
-      upd(m_aty, aty);
-      upd(m_q, qv);
+      upd(m_dual, u_dual, px + qv + aty, rw.d);
+      upd(m_px, u_px, px, rw.d);
+      upd(m_aty, u_aty, aty, rw.d);
+      upd(m_q, u_q, qv, rw.d);
     }
     // equality rows touching stage t
     if (t == 0 && xr) {
-      upd(m_cxc, xc - xi0);
-      upd(m_cx, xc);
-      upd(m_c, xi0);
+      upd(m_cxc, u_cxc, xc - xi0, rw.f);
+      upd(m_cx, u_cx, xc, rw.f);
+      upd(m_c, u_c, xi0, rw.f);
     }
     double cx = dotb<n>(tb.Amr, xc, 0.0);
     if constexpr (ST::APNEG)
@@ -1144,9 +1164,9 @@ __device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& 
     else
       cx = dotb<n>(tb.Apr, xn, cx);
     if (thi && xr) {
-      upd(m_cxc, cx - cv);
-      upd(m_cx, cx);
-      upd(m_c, cv);
+      upd(m_cxc, u_cxc, cx - cv, rw.f);
+      upd(m_cx, u_cx, cx, rw.f);
+      upd(m_c, u_c, cv, rw.f);
     }
     // inequality rows of stage t
     double gx;
@@ -1156,19 +1176,19 @@ __device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& 
       gx = dotb<n>(tb.Gr, xc, 0.0);
     if (i < NG) {
       const double zv = double(d.zg);
-      upd(m_gxz, gx - zv);
-      upd(m_gx, gx);
-      upd(m_z, zv);
+      upd(m_gxz, u_gxz, gx - zv, rw.g);
+      upd(m_gx, u_gx, gx, rw.g);
+      upd(m_z, u_z, zv, rw.g);
       const double xiv = double(d.xi);
       if (kind == 1) {
-        upd(m_sres, gamma2 * xiv + ygv);
-        upd(m_sscale, gamma2 * xiv);
-        upd(m_sscale, ygv);
+        upd(m_sres, u_sres, gamma2 * xiv + ygv, rw.s);
+        upd(m_sscale, u_sscale, gamma2 * xiv, rw.s);
+        upd(m_sscale, u_sscale, ygv, rw.s);
       } else if (kind == 2) {
         const double r1 = (xiv != 0.0) ? fabs(ygv + gamma1 * (xiv > 0 ? 1.0 : -1.0)) : fmax(fabs(ygv) - gamma1, 0.0);
-        upd(m_sres, r1);
-        upd(m_sscale, xiv != 0.0 ? gamma1 : 0.0);
-        upd(m_sscale, ygv);
+        upd(m_sres, u_sres, r1, rw.s);
+        upd(m_sscale, u_sscale, xiv != 0.0 ? gamma1 : 0.0, rw.s);
+        upd(m_sscale, u_sscale, ygv, rw.s);
       }
     }
   };
@@ -1178,6 +1198,14 @@ __device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& 
   R.ps = rows_max(row_max(fmax(fmax(m_cx, m_gx), fmax(m_c, m_z))));
   R.rd = rows_max(row_max(fmax(m_dual, m_sres)));
   R.ds = rows_max(row_max(fmax(fmax(m_px, m_aty), fmax(m_q, m_sscale))));
+  if (L.sc) {
+    R.rp_u = rows_max(row_max(fmax(u_cxc, u_gxz)));
+    R.ps_u = rows_max(row_max(fmax(fmax(u_cx, u_gx), fmax(u_c, u_z))));
+    R.rd_u = rows_max(row_max(fmax(u_dual, u_sres)));
+    R.ds_u = rows_max(row_max(fmax(fmax(u_px, u_aty), fmax(u_q, u_sscale))));
+  } else {
+    R.rp_u = R.rp, R.ps_u = R.ps, R.rd_u = R.rd, R.ds_u = R.ds;
+  }
   R.nonfinite = rows_max(row_max(nf));
   return R;
 }
@@ -1201,7 +1229,9 @@ __device__ __forceinline__ int boundary_decision(const Resid& R, const Settings&
                                                  double& rho_bar, bool& refactor) {
   refactor = false;
   if (R.nonfinite) return 2;
-  const bool conv = R.rp <= st.eps_abs + st.eps_rel * R.ps && R.rd <= st.eps_abs + st.eps_rel * R.ds;
+  // stopping test on the original problem, step size from the residuals of
+  // the QP the iterations run on
+  const bool conv = R.rp_u <= st.eps_abs + st.eps_rel * R.ps_u && R.rd_u <= st.eps_abs + st.eps_rel * R.ds_u;
   if ((check || (st.k_check > 0 && last)) && conv) return 0;
   if (last) return 1;
   if (adapt && !conv) {
@@ -1366,8 +1396,8 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
     L.nfact[w.b] = nfact;
     L.rho[w.b] = rho_bar;
     L.status[w.b] = status;
-    L.rprim[w.b] = R.rp;
-    L.rdual[w.b] = R.rd;
+    L.rprim[w.b] = R.rp_u;
+    L.rdual[w.b] = R.rd_u;
   }
 }
 

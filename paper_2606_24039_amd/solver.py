@@ -194,6 +194,24 @@ class OCPSolver:
         self.generation += 1
         A.check(self.lib.ocp_graph_launch(self.h, _stream()), "ocp_graph_launch")
 
+    def set_scaling(self, d=None, e_g=None, c=None):
+        """Rescale later problems by per-instance factors d [B, n], e_g [B, ng],
+        c [B] (ocp_set_scaling); d = None removes the rescaling.  Load the
+        problem again afterwards."""
+        self.generation += 1
+        if d is None:
+            A.check(self.lib.ocp_set_scaling(self.h, None, None, None, _stream()), "ocp_set_scaling")
+            return
+        t = [_dev(d), _dev(e_g), _dev(c)]
+        A.check(self.lib.ocp_set_scaling(self.h, *[C.c_void_p(v.data_ptr()) for v in t], _stream()),
+                "ocp_set_scaling")
+
+    def set_scaling_box(self, p: float = 0.6):
+        """Box normalisation of later problems, derived on the device
+        (ocp_set_scaling_box).  Load the problem again afterwards."""
+        self.generation += 1
+        A.check(self.lib.ocp_set_scaling_box(self.h, float(p)), "ocp_set_scaling_box")
+
     def set_segmented(self, seg_min_n: int):
         """Horizons N >= seg_min_n solve with segmented substitutions (ocp_set_segmented)."""
         A.check(self.lib.ocp_set_segmented(self.h, int(seg_min_n)), "ocp_set_segmented")

@@ -108,15 +108,19 @@ def test_point_maps_are_inverse_and_carry_the_kkt_residuals(rng):
 
 
 def test_box_scaling_closed_form():
+    """Random LTI: x in [-10, 10], u in [-1, 1], Q = diag(U[0.5, 2]), R = 0.1 I:
+    10^0.6 = 3.98 rounds to d_x = 4, 1^0.6 = 1 gives d_u = 1; the largest
+    diagonal entry of diag(d) D diag(d) is 16 max Q_jj in [8, 32], so c is
+    1/8, 1/16 or 1/32 by where 16 max Q_jj falls against 8 sqrt 2 and 16 sqrt 2."""
     b = random_lti(2, N=5, seed=2)
-    qp = lti_batch_qp(b, 1)
-    p = 0.6
-    sc = box_scaling(qp, p)
-    half = 0.5 * (b.hi[1] - b.lo[1])
-    np.testing.assert_allclose(sc.d, half ** p)
-    np.testing.assert_allclose(sc.e_g, 1.0 / half ** p)
-    Pd = np.concatenate([np.maximum(b.Qd[1], b.Qfd[1]), b.Rd[1]])
-    assert sc.c == pytest.approx(1.0 / np.max(Pd * sc.d ** 2))
+    for i in range(2):
+        qp = lti_batch_qp(b, i)
+        sc = box_scaling(qp, 0.6)
+        np.testing.assert_array_equal(sc.d, np.concatenate([np.full(b.nx, 4.0), np.ones(b.nu)]))
+        np.testing.assert_array_equal(sc.e_g, 1.0 / sc.d)
+        m = 16.0 * max(np.max(b.Qd[i]), np.max(b.Qfd[i]))
+        expect = 1 / 8 if m < 8 * np.sqrt(2) else (1 / 16 if m < 16 * np.sqrt(2) else 1 / 32)
+        assert sc.c == expect
 
 
 def test_stopping_test_and_residuals_are_the_original_problems():
