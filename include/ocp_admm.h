@@ -65,8 +65,14 @@ enum { OCP_ROW_HARD = 0, OCP_ROW_L2 = 1, OCP_ROW_L1 = 2 };
  * x_t + dt fc((x_t + x_{t+1})/2, u_t) - x_{t+1}, or the trapezoidal rule of
  * Remark A1, x_t + dt/2 (fc(x_t, u_t) + fc(x_{t+1}, u_t)) - x_{t+1} */
 enum { OCP_INTEG_MIDPOINT = 0, OCP_INTEG_TRAPEZOID = 1 };
-/* per-instance status */
-enum { OCP_SOLVED = 0, OCP_MAX_ITER = 1, OCP_NON_FINITE = 2, OCP_FACTOR_BREAKDOWN = 3 };
+/* per-instance status; OCP_INFEASIBLE: at a convergence check the change of
+ * the multipliers since the previous check certifies that {Cx = c, lo <= Gx
+ * <= hi} is empty (Farkas: ||A'dy||_inf <= eps_pinf ||dy||_inf and
+ * c'dy_f + hi'max(dy_g,0) + lo'min(dy_g,0) < -eps_pinf ||dy||_inf, the ADMM
+ * infeasibility test of Banjac, Goulart, Stellato and Boyd), evaluated in
+ * the original variables; problems with soft rows are never declared
+ * infeasible */
+enum { OCP_SOLVED = 0, OCP_MAX_ITER = 1, OCP_NON_FINITE = 2, OCP_FACTOR_BREAKDOWN = 3, OCP_INFEASIBLE = 4 };
 /* per-instance adjoint status (ocp_qp_grads.adj_status): the relative FP64
  * residual ||r - K eta||_inf / ||dL/dx||_inf of the active-set KKT system after
  * the refinement sweeps is at most adj_tol (OK) or above it (RESIDUAL: the
@@ -97,6 +103,8 @@ typedef struct {
   double adj_sigma, adj_rho; /* regularisation of the adjoint refinement */
   double adj_tol;          /* relative KKT residual after the sweeps accepted as refined
                               (adj_status OK); default 1e-10 */
+  double eps_pinf;         /* infeasibility-certificate tolerance (OCP_INFEASIBLE); 0 = no test;
+                              default 1e-4 */
   int32_t max_admm;        /* ADMM iterations per QP */
   int32_t k_rho;           /* rho adaptation interval (0 = never) */
   int32_t k_check;         /* convergence test interval (0 = run exactly max_admm) */

@@ -16,7 +16,9 @@ One iteration, in the paper's order:
   4. dual update y_f += rho_f (z^_f - c), y_g += rho_g (z^_g - z_g);
   5. residuals (eq. admm:residuals), stop test (eq. admm:termination:slack)
      and the rho-bar adaptation (eq. rho:update), rho_f = 1e3 rho-bar,
-     rho_g = rho-bar.
+     rho_g = rho-bar; at convergence checks that do not stop, the change of
+     the multipliers since the previous check is tested as a primal
+     infeasibility certificate (status 4; see infeasibility_certificate).
 
 The Schur system is solved with SciPy's banded Cholesky (LAPACK pbtrf/pbtrs)
 on the (2n-1)-band storage of S; a failed factorisation is reported as a
@@ -36,7 +38,7 @@ import scipy.linalg as sla
 
 from .qp import HARD, SOFT_L1, SOFT_L2, StageQP
 
-CONVERGED, MAX_ITER, NON_FINITE, FACTOR_BREAKDOWN = 0, 1, 2, 3
+CONVERGED, MAX_ITER, NON_FINITE, FACTOR_BREAKDOWN, PRIMAL_INFEASIBLE = 0, 1, 2, 3, 4
 
 
 @dataclass
@@ -54,6 +56,7 @@ class ADMMSettings:
     max_iter: int = 1000
     k_check: int = 25  # 0 = never test for convergence (fixed iteration count)
     adapt_rho: bool = True
+    eps_pinf: float = 1e-4  # primal-infeasibility certificate tolerance (0 = no test)
 
     def with_(self, **kw) -> "ADMMSettings":
         return replace(self, **kw)
@@ -143,6 +146,29 @@ def rho_update(rho_bar, r_prim, r_dual, prim_scale, dual_scale, st: ADMMSettings
     cand = rho_bar * np.sqrt(num / max(den, 1e-30))
     cand = float(np.clip(cand, st.rho_min, st.rho_max))
     return cand, bool(max(cand / rho_bar, rho_bar / cand) > st.k_ratio)
+
+
+def infeasibility_certificate(M, dy_f, dy_g, eps) -> bool:
+    """Primal-infeasibility test of an ADMM multiplier increment (the
+    certificate of Banjac, Goulart, Stellato and Boyd for ADMM on convex QPs,
+    written from its definition): the constraint set {Cx = c, lo <= Gx <= hi}
+    is empty if some dy = (dy_f, dy_g) has A'dy = 0 and a negative support
+    value c'dy_f + hi'max(dy_g, 0) + lo'min(dy_g, 0) < 0 (Farkas).  dy is the
+    change of the multipliers between two convergence checks: on an infeasible
+    problem the multipliers grow along such a direction.  Accepted when
+    ||A'dy||_inf <= eps ||dy||_inf and the support value < -eps ||dy||_inf.
+    Soft rows never bound the slacked constraint set: any nonzero dy on them
+    fails the test."""
+    nrm = max(_inf(dy_f), _inf(dy_g))
+    if not nrm > 0:
+        return False
+    if _inf(M.C.T @ dy_f + M.G.T @ dy_g) > eps * nrm:
+        return False
+    if np.any(dy_g[M.kind != HARD] != 0.0):
+        return False
+    hi_t = np.where(dy_g > 0, M.hi * dy_g, 0.0)
+    lo_t = np.where(dy_g < 0, M.lo * dy_g, 0.0)
+    return bool(M.c @ dy_f + np.sum(hi_t) + np.sum(lo_t) < -eps * nrm)
 
 
 def _inf(v) -> float:
@@ -243,6 +269,7 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
     status = MAX_ITER
     r_prim = r_dual = np.inf
     k = 0
+    y_prev = None  # multipliers at the previous convergence check (original variables)
     for k in range(1, st.max_iter + 1):
         rho_f, rho_g = st.rho_f_scale * rho_bar, rho_bar
         eta = st.sigma * x - M.q + M.C.T @ (rho_f * M.c - y_f) + M.G.T @ (rho_g * z_g - y_g)
@@ -269,6 +296,13 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
             if (check or (st.k_check > 0 and k == st.max_iter)) and conv:
                 status = CONVERGED
                 break
+            if check and st.eps_pinf > 0:
+                yo = back(x, z_g, xi, y_f, y_g)
+                if y_prev is not None and infeasibility_certificate(Mg, yo[3] - y_prev[0], yo[4] - y_prev[1],
+                                                                    st.eps_pinf):
+                    status = PRIMAL_INFEASIBLE
+                    break
+                y_prev = (yo[3].copy(), yo[4].copy())
             if adapt and not conv:
                 # the step size balances the residuals of the problem the iterations run on
                 rp_i, rd_i, ps_i, ds_i = (r_prim, r_dual, ps, ds) if M is Mg else M.residuals(x, z_g, xi, y_f, y_g)

@@ -15,7 +15,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 MODEL_QP, MODEL_LTI, MODEL_BICYCLE = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 ROW_HARD, ROW_L2, ROW_L1 = 0, 1, 2
-SOLVED, MAX_ITER, NON_FINITE, FACTOR_BREAKDOWN = 0, 1, 2, 3
+SOLVED, MAX_ITER, NON_FINITE, FACTOR_BREAKDOWN, INFEASIBLE = 0, 1, 2, 3, 4
 ADJ_OK, ADJ_RESIDUAL, ADJ_NON_FINITE, ADJ_BREAKDOWN = 0, 1, 2, 3
 
 _dp = C.POINTER(C.c_double)
@@ -30,7 +30,7 @@ class ocp_dims(C.Structure):
 class ocp_settings(C.Structure):
     _fields_ = [(k, C.c_double) for k in (
         "sigma", "rho0", "rho_f_scale", "rho_min", "rho_max", "k_ratio", "alpha", "eps_abs", "eps_rel",
-        "eps_c", "armijo_eta", "eps_active", "adj_sigma", "adj_rho", "adj_tol")] + [(k, C.c_int32) for k in (
+        "eps_c", "armijo_eta", "eps_active", "adj_sigma", "adj_rho", "adj_tol", "eps_pinf")] + [(k, C.c_int32) for k in (
             "max_admm", "k_rho", "k_check", "adapt_rho", "warm_start", "max_sqp", "fixed_sqp", "refine_sweeps")]
 
 

@@ -206,10 +206,12 @@ struct Layout {
   // ADMM state in iteration precision; stage vectors padded to ROW
   void* x;   // [S][ROW]
   void* v;   // [S][ROW] forward-substitution scratch
-  void* yf;  // [S][ROW] slot s0: initial-state rows, slot s0+t+1: dynamics row t
+  void* yf;  // [S][ROW] slot of stage t: dynamics row t; slot of stage N: the initial-state rows
   void* zg;  // [S][ROW]
   void* yg;  // [S][ROW]
   void* xi;  // [S][ROW]
+  void* ypf;  // [S][ROW] y_f and y_g at the previous convergence check (infeasibility test)
+  void* ypg;
 
   // per instance
   double* rho;
@@ -223,6 +225,7 @@ struct Layout {
 
 struct Settings {
   double sigma, rho0, rho_f_scale, rho_min, rho_max, k_ratio, alpha, eps_abs, eps_rel;
+  double eps_pinf;  // primal-infeasibility certificate tolerance (0: no test)
   int max_iter, k_rho, k_check, adapt_rho, warm;
   int seg_min_n;  // horizons N >= seg_min_n run the segmented substitutions
 };

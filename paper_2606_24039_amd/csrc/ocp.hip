@@ -82,6 +82,7 @@ struct ocp_handle_s {
   int seg_min_n = SEG_MIN_N;  // launch shape: horizons from which the substitutions run segmented
   int8_t gsel[16] = {0}, ginv[16] = {0};
   void *x = nullptr, *v = nullptr, *yf = nullptr, *zg = nullptr, *yg = nullptr, *xi = nullptr;
+  void *ypf = nullptr, *ypg = nullptr;  // multipliers at the previous convergence check
   double *rho = nullptr, *rprim = nullptr, *rdual = nullptr;
   int32_t *status = nullptr, *iters = nullptr, *nfact = nullptr, *need = nullptr;
   double gamma2 = 1.0, gamma1 = 1.0;
@@ -226,6 +227,8 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   A_(h->zg, ts * ROW * SP);
   A_(h->yg, ts * ROW * SP);
   A_(h->xi, ts * ROW * SP);
+  A_(h->ypf, ts * ROW * (size_t)S);
+  A_(h->ypg, ts * ROW * (size_t)S);
   A_(h->rho, sizeof(double) * B);
   A_(h->rprim, sizeof(double) * B);
   A_(h->rdual, sizeof(double) * B);
@@ -398,6 +401,8 @@ Layout make_layout(ocp_handle h) {
   L.zg = h->zg;
   L.yg = h->yg;
   L.xi = h->xi;
+  L.ypf = h->ypf;
+  L.ypg = h->ypg;
   L.rho = h->rho;
   L.status = h->status;
   L.iters = h->iters;
@@ -419,6 +424,7 @@ Settings make_settings(const ocp_settings* s, int warm) {
   o.alpha = s->alpha;
   o.eps_abs = s->eps_abs;
   o.eps_rel = s->eps_rel;
+  o.eps_pinf = s->eps_pinf;
   o.max_iter = s->max_admm;
   o.k_rho = s->k_rho;
   o.k_check = s->k_check;
@@ -431,7 +437,7 @@ ocp_status check_settings(const ocp_settings* s) {
   if (!s) return OCP_E_ARG;
   if (!(s->sigma > 0) || !(s->rho0 > 0) || !(s->rho_f_scale > 0) || !(s->rho_min > 0) ||
       !(s->rho_max >= s->rho_min) || !(s->alpha > 0 && s->alpha < 2) || s->max_admm < 1 || s->k_check < 0 ||
-      s->k_rho < 0 || !(s->eps_abs >= 0) || !(s->eps_rel >= 0))
+      s->k_rho < 0 || !(s->eps_abs >= 0) || !(s->eps_rel >= 0) || !(s->eps_pinf >= 0))
     return OCP_E_ARG;
   return OCP_OK;
 }
@@ -660,6 +666,7 @@ void ocp_default_settings(ocp_settings* s) {
   s->adj_sigma = 1e-9;
   s->adj_rho = 1e8;
   s->adj_tol = 1e-10;
+  s->eps_pinf = 1e-4;
   s->max_admm = 1000;
   s->k_rho = 25;
   s->k_check = 25;

@@ -1223,16 +1223,101 @@ __device__ __noinline__ Resid residuals_wave(const Layout& Lm, const WaveGroup& 
     return residuals_gen<T, NX, NU, NG, false>(L, w, kind, gamma2, gamma1);
 }
 
+// Primal-infeasibility certificate at a convergence check (the test of
+// Banjac, Goulart, Stellato and Boyd for ADMM on convex QPs, written from its
+// definition): with dy the change of the multipliers since the previous
+// check, the constraint set {Cx = c, lo <= Gx <= hi} is empty when
+// ||A'dy||_inf <= eps ||dy||_inf and c'dy_f + hi'max(dy_g, 0) + lo'min(dy_g, 0)
+// < -eps ||dy||_inf (Farkas).  Evaluated in the original variables of a
+// rescaled QP; a nonzero dy on a soft row fails it.  Stages spread over the
+// four rows as in the residuals; blocks read from the FP64 master data.
+template <typename T, int NX, int NU, int NG>
+__device__ __noinline__ int pinf_wave(const Layout& Lm, const WaveGroup& wm, double eps_) {
+  const Layout L = uni(Lm);
+  const int b = uni(wm.b), N = uni(wm.N);
+  const int64_t s0 = uni(wm.s0);
+  const double eps = uni(eps_);
+  constexpr int n = NX + NU;
+  const int i = wm.lane, q = wm.row;
+  const int ic = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
+  const bool ti = L.ti != 0;
+  const gptr<const T> YF = as_global((const T*)L.yf), YG = as_global((const T*)L.yg);
+  const gptr<const T> PF = as_global((const T*)L.ypf), PG = as_global((const T*)L.ypg);
+  ResW rw;
+  rw.load(L, b, i);
+  const int kind = (i < NG) ? (int)L.soft[i] : 0;
+  const size_t vi = (size_t)(s0 + N) * ROW + i;  // initial-state slot
+  const double dyinit = (i < NX) ? double(YF[vi]) - double(PF[vi]) : 0.0;
+  const double xi0 = L.x_init[(size_t)b * NX + ix];
+  double m_aty = 0.0, m_dy = 0.0, sup = 0.0;
+  int soft_bad = 0;
+  for (int t = q; t <= N; t += 4) {
+    const int64_t s = s0 + t;
+    const size_t sv = (size_t)s * ROW + i;
+    const double dyfc = (t < N && i < NX) ? double(YF[sv]) - double(PF[sv]) : 0.0;
+    const double dyfm = (t > 0 && i < NX) ? double(YF[sv - ROW]) - double(PF[sv - ROW]) : 0.0;
+    const double dyg = (i < NG) ? double(YG[sv]) - double(PG[sv]) : 0.0;
+    double Amc[NX], Apc[NX], Gc[NG];
+    load_col<NX>(Amc, L.Am + ti_or_tv(ti, b, s, (size_t)NX * n) + ic, n, t < N);
+    load_col<NX>(Apc, L.Ap + ti_or_tv(ti, b, t > 0 ? s - 1 : s, (size_t)NX * n) + ic, n, t > 0);
+    load_col<NG>(Gc, L.G + ti_or_tv(ti, b, s, (size_t)NG * n) + ic, n, true);
+    double aty = dotb<NX>(Amc, dyfc, 0.0);
+    aty = dotb<NX>(Apc, dyfm, aty);
+    if (t == 0 && i < NX) aty += dyinit;
+    aty = dotb<NG>(Gc, dyg, aty);
+    if (i < n) m_aty = fmax(m_aty, fabs(aty) * rw.d);
+    if (i < NX) {
+      m_dy = fmax(m_dy, fabs(dyfc) * rw.d);  // y_f = yh_f / (c d_x): the stationarity weight
+      const double cv = (t < N && L.bd) ? L.bd[ti_or_tv(ti, b, s, NX) + ix] : 0.0;
+      sup += cv * dyfc;
+      if (t == 0) {
+        m_dy = fmax(m_dy, fabs(dyinit) * rw.d);
+        sup += xi0 * dyinit;
+      }
+    }
+    if (i < NG) {
+      m_dy = fmax(m_dy, fabs(dyg) * rw.s / rw.g);  // y_g = e yh_g / c
+      const size_t sb = ti_or_tv(ti, b, s, NG) + i;
+      if (dyg > 0.0) sup += L.hi[sb] * dyg;
+      if (dyg < 0.0) sup += L.lo[sb] * dyg;
+      if (kind != 0 && dyg != 0.0) soft_bad = 1;
+    }
+  }
+  m_aty = rows_max(row_max(m_aty));
+  m_dy = rows_max(row_max(m_dy));
+  sup = row_sum(sup);
+  sup += __shfl_xor(sup, 16);
+  sup += __shfl_xor(sup, 32);
+  sup *= rw.s;  // original variables: the support value of the rescaled QP over c
+  soft_bad = rows_max(row_max(soft_bad));
+  return (m_dy > 0.0 && !soft_bad && m_aty <= eps * m_dy && sup < -eps * m_dy) ? 1 : 0;
+}
+
+// y_f, y_g -> the previous-check copies (every stage of the instance)
+template <typename T>
+__device__ __forceinline__ void keep_multipliers(const Layout& L, const WaveGroup& w) {
+  T* yf = (T*)L.yf;
+  T* yg = (T*)L.yg;
+  T* pf = (T*)L.ypf;
+  T* pg = (T*)L.ypg;
+  for (int e = threadIdx.x; e < (w.N + 1) * ROW; e += 64) {
+    const size_t k = (size_t)w.s0 * ROW + e;
+    pf[k] = yf[k];
+    pg[k] = yg[k];
+  }
+}
+
 // Boundary decision of the schedule (eq. admm:termination:slack, rho:update):
 // returns the new status (ST_RUNNING to continue) and may change rho_bar.
 __device__ __forceinline__ int boundary_decision(const Resid& R, const Settings& st, int check, int adapt, int last,
-                                                 double& rho_bar, bool& refactor) {
+                                                 int infeasible, double& rho_bar, bool& refactor) {
   refactor = false;
   if (R.nonfinite) return 2;
   // stopping test on the original problem, step size from the residuals of
   // the QP the iterations run on
   const bool conv = R.rp_u <= st.eps_abs + st.eps_rel * R.ps_u && R.rd_u <= st.eps_abs + st.eps_rel * R.ds_u;
   if ((check || (st.k_check > 0 && last)) && conv) return 0;
+  if (check && infeasible) return 4;  // certificate of the multiplier change (pinf_wave)
   if (last) return 1;
   if (adapt && !conv) {
     const double num = R.rp / fmax(R.ps, 1e-30);
@@ -1355,6 +1440,7 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
   const bool adapt_on = st.adapt_rho && st.k_rho > 0;
   int k = L.iters[w.b];
   bool need = true;
+  bool have_prev = false;  // multipliers of an earlier check are kept (ypf, ypg)
   for (;;) {
     if (need) {  // the only call site of the factorisation
       constexpr int FORM = sizeof(T) == 4 ? FACTOR_WV : FACTOR_PK;
@@ -1387,8 +1473,16 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
     const int last = (nb == st.max_iter) ? 1 : 0;
     if (check || adapt || last) {
       R = residuals_wave<T, NX, NU, NG, ST>(Lc, w, kind, L.gamma2, L.gamma1);
-      status = boundary_decision(R, st, check, adapt, last, rho_bar, need);
+      // infeasibility test from the second check on (the first has no earlier multipliers)
+      const int pinf = (check && have_prev && st.eps_pinf > 0.0) ? pinf_wave<T, NX, NU, NG>(Lc, w, st.eps_pinf) : 0;
+      status = boundary_decision(R, st, check, adapt, last, pinf, rho_bar, need);
       if (status != ST_RUNNING) break;
+      if (check && st.eps_pinf > 0.0) {
+        wave_sync();
+        keep_multipliers<T>(Lc, w);
+        wave_sync();
+        have_prev = true;
+      }
     }
   }
   if (threadIdx.x == 0) {
