@@ -155,7 +155,7 @@ def upstream_gradient(batch, seed=11):
     return rng.standard_normal((batch.batch * (batch.N + 1), batch.nx + batch.nu))
 
 
-def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=None):
+def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=None, tune=False):
     import torch
 
     from paper_2606_24039_amd import _abi as A
@@ -167,6 +167,7 @@ def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=Non
         s.set_scaling_box(scale_p)
     s.set_lti(batch.A, batch.B, batch.Qd, batch.Rd, batch.Qfd, batch.G, batch.lo, batch.hi, batch.x0)
     st = A.default_settings(**settings_kw)
+    shape = s.autotune(st, reps=2) if tune else None  # launch shape picked on this batch (not timed)
     out = s.alloc_solution()
     sol = s.solution_struct(out)
     grads = s.alloc_grads()
@@ -205,7 +206,9 @@ def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=Non
            "iters_capped": int((iters >= settings_kw.get("max_admm", 1000)).sum()),
            "nfact_sum": int(nfact.sum()),
            "status_counts": {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
-           "kernels": {k: {"ms_per_step": ms / steps, "launches_per_step": c / steps} for k, (ms, c) in kt.items()}}
+           "kernels": {k: {"ms_per_step": ms / steps, "launches_per_step": c / steps} for k, (ms, c) in kt.items()},
+           "launch_shape": ({"segmented_from_horizon": shape[0], "segmented_from_iteration": shape[1]}
+                            if shape else None)}
     if grad:
         ast = grads["adj_status"].cpu().numpy()
         res["adjoint"] = {"status_counts": {int(k): int(v) for k, v in zip(*np.unique(ast, return_counts=True))},
@@ -308,6 +311,7 @@ def main():
                          "c5a / c5b: the long / ragged bicycle horizons")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="instances timed on the oracle (0 = skip)")
     ap.add_argument("--no-sub", action="store_true", help="skip the differentiation and double-integrator sub-results")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no ocp_autotune)")
     ap.add_argument("--no-scaling", action="store_true",
                     help="FP32 path without the problem rescaling (Remark 4) the headline uses")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison")
@@ -339,7 +343,8 @@ def main():
     settings_kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_admm=1000, k_check=25, k_rho=25, eps_active=1e-4)
     scale_p = None if args.no_scaling else SCALE_P
     log(f"[bench] workload: {desc}")
-    mixed = run_gpu(batch, 1, args.steps, args.warmup, settings_kw, grad=not args.no_grad, scale_p=scale_p)
+    mixed = run_gpu(batch, 1, args.steps, args.warmup, settings_kw, grad=not args.no_grad, scale_p=scale_p,
+                    tune=not args.no_tune)
     log(f"[bench] mixed: {json.dumps(mixed)}")
     fp64 = None
     variants = {}
@@ -376,6 +381,7 @@ def main():
                   "max": mixed["iters_max"], "capped": mixed["iters_capped"]},
         "roofline": roof,
         "hbm_view": hbm,
+        "launch_shape": mixed["launch_shape"],
     }
     if "adjoint" in mixed:
         out["adjoint_status"] = mixed["adjoint"]

@@ -348,16 +348,30 @@ ocp_status ocp_set_scaling(ocp_handle h, const double* d, const double* e_g, con
  * OCP_E_UNSUPPORTED (bicycle model). */
 ocp_status ocp_set_scaling_box(ocp_handle h, double p);
 
+/* Launch shape of a batch's tail: from ADMM iteration `iteration` on, every
+ * instance still running (N >= 15) takes the segmented substitutions
+ * described at ocp_set_segmented, whatever its horizon.  While the batch is
+ * full the interleaved sweeps read each chain block once, which is what the
+ * memory system favours; once few instances remain, each is bound by the
+ * serial depth of its chains, which the segments shorten.  INT32_MAX (the
+ * default) keeps the switch off.  Drops a captured graph.  Errors: OCP_E_ARG
+ * (null handle, negative iteration). */
+ocp_status ocp_set_segmented_after(ocp_handle h, int32_t iteration);
+
 /* Autotuner over the launch shape: times `reps` cold-start ocp_solve calls
- * with settings `s` on the handle's own batch for each switch point --
- * 15 (every instance segmented), 128 (the default) and INT32_MAX (none) --
- * on `stream` (one warm-up solve each; synchronises the stream), keeps the
- * fastest for later solves and returns it in *seg_min_n (HOST int32; may be
- * NULL).  The solution state afterwards is that of the last timed solve:
- * solve again before reading results.  Kernel timing is suspended while it
- * runs.  Errors: OCP_E_ARG (null handle / settings, reps < 1, invalid
- * settings), OCP_E_ORDER (no problem data), OCP_E_HIP. */
-ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void* stream, int32_t* seg_min_n);
+ * with settings `s` on the handle's own batch for each candidate pair
+ * (segmented from horizon, every running instance segmented from iteration):
+ * (15, never), (128, never), (never, never), (128, 150), (128, 300),
+ * (128, 500) -- see ocp_set_segmented and ocp_set_segmented_after -- on
+ * `stream` (one warm-up solve each; synchronises the stream), keeps the
+ * fastest pair for later solves and returns it in *seg_min_n and *seg_after
+ * (HOST int32; either may be NULL; never = INT32_MAX).  The solution state
+ * afterwards is that of the last timed solve: solve again before reading
+ * results.  Kernel timing is suspended while it runs.  Errors: OCP_E_ARG
+ * (null handle / settings, reps < 1, invalid settings), OCP_E_ORDER (no
+ * problem data), OCP_E_HIP. */
+ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void* stream, int32_t* seg_min_n,
+                        int32_t* seg_after);
 
 /* Bytes of device memory the library holds on every GPU it runs on, for the
  * life of the process, as the workspace of ocp_solve_noalloc. */

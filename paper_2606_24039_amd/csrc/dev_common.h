@@ -228,6 +228,7 @@ struct Settings {
   double eps_pinf;  // primal-infeasibility certificate tolerance (0: no test)
   int max_iter, k_rho, k_check, adapt_rho, warm;
   int seg_min_n;  // horizons N >= seg_min_n run the segmented substitutions
+  int seg_after;  // from this iteration on every instance (N >= 15) runs them (the batch's tail)
 };
 
 struct Group {

@@ -80,6 +80,7 @@ struct ocp_handle_s {
   double* FacX = nullptr;
   int variant = 0;
   int seg_min_n = SEG_MIN_N;  // launch shape: horizons from which the substitutions run segmented
+  int seg_after = INT32_MAX;  // iteration from which every running instance does (the batch's tail)
   int8_t gsel[16] = {0}, ginv[16] = {0};
   void *x = nullptr, *v = nullptr, *yf = nullptr, *zg = nullptr, *yg = nullptr, *xi = nullptr;
   void *ypf = nullptr, *ypg = nullptr;  // multipliers at the previous convergence check
@@ -543,6 +544,7 @@ void run_admm(ocp_handle h, const Settings& s_, hipStream_t st) {
   const Layout L = make_layout(h);
   Settings s = s_;
   s.seg_min_n = h->seg_min_n;
+  s.seg_after = h->seg_after;
   const int ti = h->ti ? 1 : 0;
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (ti ? VAR_TI : VAR_TV);
   if (h->mixed)
@@ -1007,6 +1009,13 @@ ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n) {
   return OCP_OK;
 }
 
+ocp_status ocp_set_segmented_after(ocp_handle h, int32_t iteration) {
+  if (!h || iteration < 0) return OCP_E_ARG;
+  drop_graph(h);  // a captured graph keeps the launch shape it was recorded with
+  h->seg_after = iteration;
+  return OCP_OK;
+}
+
 ocp_status ocp_set_scaling(ocp_handle h, const double* d, const double* e_g, const double* c, void* stream) {
   if (!h) return OCP_E_ARG;
   drop_graph(h);  // a captured graph keeps the data layout it was recorded with
@@ -1046,7 +1055,8 @@ ocp_status ocp_set_scaling_box(ocp_handle h, double p) {
   return OCP_OK;
 }
 
-ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void* stream, int32_t* seg_min_n) {
+ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void* stream, int32_t* seg_min_n,
+                        int32_t* seg_after) {
   if (!h || !s || reps < 1) return OCP_E_ARG;
   ocp_status st = check_settings(s);
   if (st != OCP_OK) return st;
@@ -1054,7 +1064,10 @@ ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void*
   hipStream_t stream_ = (hipStream_t)stream;
   ocp_settings cold = *s;
   cold.warm_start = 0;
-  const int32_t cand[3] = {SEG_FLOOR_N, SEG_MIN_N, INT32_MAX};
+  // (segmented from horizon, every running instance segmented from iteration)
+  constexpr int NC = 6;
+  const int32_t cand[NC][2] = {{SEG_FLOOR_N, INT32_MAX}, {SEG_MIN_N, INT32_MAX}, {INT32_MAX, INT32_MAX},
+                               {SEG_MIN_N, 150},         {SEG_MIN_N, 300},       {SEG_MIN_N, 500}};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -1063,9 +1076,10 @@ ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void*
   const bool prof_on = h->prof.on;
   h->prof.on = false;
   float best = INFINITY;
-  int32_t pick = h->seg_min_n;
-  for (int c = 0; c < 3 && st == OCP_OK; ++c) {
-    h->seg_min_n = cand[c];
+  int32_t pick = h->seg_min_n, pick_after = h->seg_after;
+  for (int c = 0; c < NC && st == OCP_OK; ++c) {
+    h->seg_min_n = cand[c][0];
+    h->seg_after = cand[c][1];
     st = ocp_solve(h, &cold, nullptr, stream);  // warm-up (and first touch of the transfer blocks)
     if (st != OCP_OK) break;
     if (hipEventRecord(e0, stream_) != hipSuccess) st = OCP_E_HIP;
@@ -1074,14 +1088,16 @@ ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void*
     if (st == OCP_OK && (hipEventRecord(e1, stream_) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
       st = OCP_E_HIP;
-    if (st == OCP_OK && ms < best) best = ms, pick = cand[c];
+    if (st == OCP_OK && ms < best) best = ms, pick = cand[c][0], pick_after = cand[c][1];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->prof.on = prof_on;
   if (st != OCP_OK) return st;
-  const ocp_status r = ocp_set_segmented(h, pick);
+  ocp_status r = ocp_set_segmented(h, pick);
+  if (r == OCP_OK) r = ocp_set_segmented_after(h, pick_after);
   if (seg_min_n) *seg_min_n = h->seg_min_n;
+  if (seg_after) *seg_after = h->seg_after;
   return r;
 }
 

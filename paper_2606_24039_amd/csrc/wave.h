@@ -1441,6 +1441,11 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
   int k = L.iters[w.b];
   bool need = true;
   bool have_prev = false;  // multipliers of an earlier check are kept (ypf, ypg)
+  bool seg_ready = false;  // transfer blocks of the current factorisation are formed
+  // launch shape of the next iterations: long horizons always segmented; the
+  // rest switch to it at iteration seg_after (few instances are left running
+  // by then, and the shorter serial depth beats the extra block reads)
+  auto segmented = [&](int kk) { return w.N >= st.seg_min_n || (kk >= st.seg_after && w.N >= SEG_FLOOR_N); };
   for (;;) {
     if (need) {  // the only call site of the factorisation
       constexpr int FORM = sizeof(T) == 4 ? FACTOR_WV : FACTOR_PK;
@@ -1457,17 +1462,21 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
       }
       ++nfact;
       need = false;
-      if (w.N >= st.seg_min_n) {
-        prepare_segments<T, NX, NU, NG>(Lc, w.b, w.s0, w.N);
-        wave_sync();
-      }
+      seg_ready = false;
     }
     if (k >= st.max_iter) break;
     int nb = st.max_iter;
     if (st.k_check > 0) nb = min(nb, (k / st.k_check + 1) * st.k_check);
     if (adapt_on) nb = min(nb, (k / st.k_rho + 1) * st.k_rho);
-    k = (w.N >= st.seg_min_n) ? run_segment<T, NX, NU, NG, ST, true>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar)
-                           : run_segment<T, NX, NU, NG, ST, false>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
+    if (st.seg_after > k && st.seg_after < nb) nb = st.seg_after;  // the shape changes at a segment start
+    const bool seg = segmented(k);
+    if (seg && !seg_ready) {
+      prepare_segments<T, NX, NU, NG>(Lc, w.b, w.s0, w.N);
+      wave_sync();
+      seg_ready = true;
+    }
+    k = seg ? run_segment<T, NX, NU, NG, ST, true>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar)
+            : run_segment<T, NX, NU, NG, ST, false>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
     const int check = (st.k_check > 0 && nb % st.k_check == 0) ? 1 : 0;
     const int adapt = (adapt_on && nb % st.k_rho == 0 && nb < st.max_iter) ? 1 : 0;
     const int last = (nb == st.max_iter) ? 1 : 0;

@@ -212,18 +212,24 @@ class OCPSolver:
         self.generation += 1
         A.check(self.lib.ocp_set_scaling_box(self.h, float(p)), "ocp_set_scaling_box")
 
+    def set_segmented_after(self, iteration: int):
+        """Instances still running at ADMM iteration `iteration` take the
+        segmented substitutions (ocp_set_segmented_after)."""
+        A.check(self.lib.ocp_set_segmented_after(self.h, int(iteration)), "ocp_set_segmented_after")
+
     def set_segmented(self, seg_min_n: int):
         """Horizons N >= seg_min_n solve with segmented substitutions (ocp_set_segmented)."""
         A.check(self.lib.ocp_set_segmented(self.h, int(seg_min_n)), "ocp_set_segmented")
 
-    def autotune(self, settings=None, reps: int = 1, **overrides) -> int:
+    def autotune(self, settings=None, reps: int = 1, **overrides):
         """Time the launch-shape candidates on this batch and keep the fastest
-        (ocp_autotune); returns the chosen switch horizon."""
+        (ocp_autotune); returns (segmented-from horizon, segmented-from iteration)."""
         s = settings if settings is not None else A.default_settings(**overrides)
-        chosen = C.c_int32(0)
+        n_min, after = C.c_int32(0), C.c_int32(0)
         self.generation += 1
-        A.check(self.lib.ocp_autotune(self.h, C.byref(s), int(reps), _stream(), C.byref(chosen)), "ocp_autotune")
-        return int(chosen.value)
+        A.check(self.lib.ocp_autotune(self.h, C.byref(s), int(reps), _stream(), C.byref(n_min), C.byref(after)),
+                "ocp_autotune")
+        return int(n_min.value), int(after.value)
 
     def split(self, arr, i):
         """Rows of a stage-concatenated array that belong to instance i."""

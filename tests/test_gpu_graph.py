@@ -59,3 +59,87 @@ def test_captured_step_replays_match_the_eager_step(precision):
             s.solve(default_settings(eps_abs=1e-3, eps_rel=1e-3, max_admm=50))
             stream.synchronize()
         s.close()
+
+
+@pytest.mark.parametrize("precision", [MIXED, FP64])
+def test_captured_bicycle_sqp_step(precision):
+    """A kinematic-bicycle step (3 SQP iterations of linearisation, ADMM and
+    line search, then the adjoint of the last QP) captured once: every replay
+    equals the eager step bit for bit, and in FP64 the trajectory equals the
+    oracle's SQP run (1e-8)."""
+    import torch
+
+    from oracle.admm import ADMMSettings
+    from oracle.models import BicycleOCP
+    from oracle.sqp import SQPSettings, sqp_solve
+    from paper_2606_24039_amd import _abi as A
+    from paper_2606_24039_amd import default_settings
+    from paper_2606_24039_amd.solver import OCPSolver
+    from workloads import bicycle_batch
+
+    b = bicycle_batch(6, N=40, seed=3)
+    stream = torch.cuda.Stream()
+    keys = ("x", "xi", "y_f", "y_g", "sqp_kkt", "sqp_iters", "status")
+    gkeys = ("d_q", "d_Ddiag", "d_x_init", "eta_x", "eta_f", "active", "adj_status")
+    with torch.cuda.stream(stream):
+        s = OCPSolver(4, 2, 3, b.horizons, model=A.MODEL_BICYCLE, precision=precision)
+        s.set_bicycle(b)
+        st = default_settings(max_sqp=3, max_admm=50, k_check=0, k_rho=25, fixed_sqp=1)
+        dl = torch.as_tensor(np.random.default_rng(5).standard_normal((s.S, 6)), dtype=torch.float64, device="cuda")
+        ref = _snapshot(s.solve(st), keys)
+        refg = _snapshot(s.adjoint(dl, st), gkeys)
+        out = s.alloc_solution()
+        grads = s.alloc_grads()
+        s.graph_capture(st, out, dl, grads)
+        for rep in range(3):
+            for v in list(out.values()) + list(grads.values()):
+                v.fill_(-7)
+            s.graph_launch()
+            stream.synchronize()
+            got, gotg = _snapshot(out, keys), _snapshot(grads, gkeys)
+            for k in keys:
+                assert np.array_equal(got[k], ref[k]), (rep, k)
+            for k in gkeys:
+                assert np.array_equal(gotg[k], refg[k]), (rep, k)
+            s.solve(default_settings(max_sqp=1, max_admm=20, k_check=0, fixed_sqp=1))  # eager work between replays
+            stream.synchronize()
+        if precision == FP64:
+            for i in range(b.batch):
+                r = sqp_solve(BicycleOCP(b, i), SQPSettings(max_sqp=3, fixed_iters=True),
+                              admm=ADMMSettings(max_iter=50, k_check=0, k_rho=25))
+                z = s.split(torch.as_tensor(got["x"]), i).numpy()
+                assert np.max(np.abs(z - r.z)) / max(np.max(np.abs(r.z)), 1.0) < 1e-8, i
+        s.close()
+
+
+def test_captured_rescaled_lti_step():
+    """The same for a rescaled random-LTI step (box normalisation): the graph
+    keeps the rescaled data and the unscaling of the outputs."""
+    import torch
+
+    from paper_2606_24039_amd import default_settings
+
+    b = random_lti(16, N=30, seed=2)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = lti_solver(b, MIXED)
+        s.set_scaling_box(0.6)
+        s.set_lti(b.A, b.B, b.Qd, b.Rd, b.Qfd, b.G, b.lo, b.hi, b.x0)
+        st = default_settings(eps_abs=1e-4, eps_rel=1e-4, max_admm=400)
+        dl = torch.as_tensor(np.random.default_rng(7).standard_normal((s.S, s.n)), dtype=torch.float64, device="cuda")
+        ref = _snapshot(s.solve(st), KEYS)
+        refg = _snapshot(s.adjoint(dl, st), GKEYS)
+        out = s.alloc_solution()
+        grads = s.alloc_grads()
+        s.graph_capture(st, out, dl, grads)
+        for rep in range(2):
+            for v in list(out.values()) + list(grads.values()):
+                v.fill_(-7)
+            s.graph_launch()
+            stream.synchronize()
+            got, gotg = _snapshot(out, KEYS), _snapshot(grads, GKEYS)
+            for k in KEYS:
+                assert np.array_equal(got[k], ref[k]), (rep, k)
+            for k in GKEYS:
+                assert np.array_equal(gotg[k], refg[k]), (rep, k)
+        s.close()

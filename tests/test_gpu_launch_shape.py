@@ -28,12 +28,15 @@ def _sub(b, i, N):
     return bi
 
 
-@pytest.mark.parametrize("seg_min_n,horizons", [(15, [15, 16, 17, 18, 50]), (NEVER, [130, 203])])
-def test_forced_launch_shape_fixed_rho_iterates_fp64(seg_min_n, horizons):
+@pytest.mark.parametrize("seg_min_n,after,horizons", [(15, NEVER, [15, 16, 17, 18, 50]), (NEVER, NEVER, [130, 203]),
+                                                     (NEVER, 30, [15, 16, 17, 18, 50, 130])])
+def test_forced_launch_shape_fixed_rho_iterates_fp64(seg_min_n, after, horizons):
+    """after = 30: every instance switches to the segmented sweeps at iteration 30 (the tail switch)."""
     hz = np.array(horizons)
     b = random_lti(len(hz), N=int(hz.max()), seed=31)
     s = lti_solver(b, FP64, horizons=hz)
     s.set_segmented(seg_min_n)
+    s.set_segmented_after(after)
     out = s.solve(_settings(max_admm=60, k_check=0, adapt_rho=0))
     for i, N in enumerate(hz):
         ref = admm_solve(lti_batch_qp(_sub(b, i, N), 0), ADMMSettings(max_iter=60, k_check=0, adapt_rho=False))
@@ -48,7 +51,7 @@ def test_autotune_picks_a_candidate_and_solves_stay_correct():
     for precision in (MIXED, FP64):
         s = lti_solver(b, precision)
         chosen = s.autotune(_settings(), reps=1)
-        assert chosen in (15, 128, NEVER)
+        assert chosen in ((15, NEVER), (128, NEVER), (NEVER, NEVER), (128, 150), (128, 300), (128, 500))
         out = s.solve(_settings())
         st = out["status"].cpu().numpy()
         assert (st == 0).mean() >= 0.85
