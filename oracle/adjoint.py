@@ -144,8 +144,38 @@ def independent_rows(qp: StageQP, lower, upper, rtol=1e-9) -> bool:
     return bool(d.size == 0 or d.min() > rtol * d.max())
 
 
-def adjoint_dense(qp: StageQP, x, dL_dx, lower, upper, H=None):
+def _slack_rows(qp: StageQP, lower, upper, xi):
+    """Rows whose slack is a function of x at the solution: active L2-slack
+    rows, and L1-slack rows with nonzero slack (xi_i = bound - G_i x there)."""
+    kind = qp.soft_rows()
+    l2 = (lower | upper) & (kind == SOFT_L2)
+    l1 = np.zeros_like(l2) if xi is None else (kind == SOFT_L1) & (np.asarray(xi) != 0.0)
+    return l2, l1
+
+
+def slack_rhs(qp: StageQP, dL_dx, dL_dxi, lower, upper, xi=None):
+    """x-part of the reduced right-hand side with a loss on the slacks
+    (eq. bwd:slack_reduced_system): dL/dx - G_S' dL/dxi over the rows whose
+    slack moves with x (active L2 rows; L1 rows with nonzero slack, whose
+    xi = bound - G x gives the same term)."""
+    if dL_dxi is None:
+        return np.asarray(dL_dx, float)
+    l2, l1 = _slack_rows(qp, lower, upper, xi)
+    G = qp.matrices()[2]
+    w = np.where(l2 | l1, np.asarray(dL_dxi, float).reshape(-1), 0.0)
+    return np.asarray(dL_dx, float) - G.T @ w
+
+
+def adjoint_dense(qp: StageQP, x, dL_dx, lower, upper, H=None, dL_dxi=None, xi=None):
     """eta = K^{-1} (dL/dx, 0, 0) by a direct sparse LU (the definition).
+
+    With a loss on the slacks (dL_dxi [nineq], `xi` the solution's slacks):
+    eq. loss_gradient's right-hand side (dL/dx, dL/dxi, 0) of the slack
+    system eq. bwd:slack_adjoint, written on K (slacks of the active L2 rows
+    eliminated through their stationarity gamma2 xi + y = 0): the active L2
+    row of K reads G_i e_x - e_y,i / gamma2 = -dL/dxi_i / gamma2; an L1 row
+    with nonzero slack is not in K and its loss enters through
+    xi_i = bound - G_i x as -G_i' dL/dxi_i in the x-part.
 
     When the active rows are linearly dependent (LICQ fails; at eps 1e-4 this
     happens on unconverged instances; the LU then shows a pivot below 1e-12 of
@@ -160,6 +190,13 @@ def adjoint_dense(qp: StageQP, x, dL_dx, lower, upper, H=None):
     K, *_ , act = _kkt(qp, lower, upper, H)
     nv, ne = qp.nvar, qp.neq
     rhs = np.concatenate([dL_dx, np.zeros(ne + int(act.sum()))])
+    if dL_dxi is not None:
+        l2, l1 = _slack_rows(qp, lower, upper, xi)
+        dxi = np.asarray(dL_dxi, float).reshape(-1)
+        G = qp.matrices()[2]
+        rhs[:nv] -= G.T @ np.where(l1, dxi, 0.0)
+        ry = np.where(l2, -dxi / qp.gamma2, 0.0)
+        rhs[nv + ne:] = ry[act]
     lu = None
     try:
         lu = spla.splu(K)
@@ -177,7 +214,8 @@ def adjoint_dense(qp: StageQP, x, dL_dx, lower, upper, H=None):
     return eta[:nv], eta[nv:nv + ne], eta_g
 
 
-def adjoint_refined(qp: StageQP, x, dL_dx, lower, upper, sigma_b=1e-9, rho_b=1e6, sweeps=4, H=None):
+def adjoint_refined(qp: StageQP, x, dL_dx, lower, upper, sigma_b=1e-9, rho_b=1e6, sweeps=4, H=None,
+                    dL_dxi=None, xi=None):
     """Same eta by iterative refinement on K with the regularised matrix
     K_reg = [[H + sigma_b I, J'], [J, -rho_b^{-1} I]], J = [C; G_A] (active
     L2-slack rows leave J and add gamma2 G_S'G_S to H, their eta_y recovered
@@ -204,7 +242,7 @@ def adjoint_refined(qp: StageQP, x, dL_dx, lower, upper, sigma_b=1e-9, rho_b=1e6
         ey = rho_b * (Jd @ ex - ry)
         return ex, ey
 
-    rx0 = np.asarray(dL_dx, float)
+    rx0 = slack_rhs(qp, dL_dx, dL_dxi, lower, upper, xi)  # eq. bwd:slack_reduced_system
     ry0 = np.zeros(Jd.shape[0])
     ex, ey = kreg_solve(rx0, ry0)
     for _ in range(sweeps - 1):
@@ -215,31 +253,57 @@ def adjoint_refined(qp: StageQP, x, dL_dx, lower, upper, sigma_b=1e-9, rho_b=1e6
     ne = qp.neq
     eta_g = np.zeros(qp.nineq)
     eta_g[hard] = ey[ne:]
-    eta_g[l2] = qp.gamma2 * (Gs @ ex)
+    eta_g[l2] = qp.gamma2 * (Gs @ ex)  # eq. bwd:slack:eta_xi_yg
+    if dL_dxi is not None:
+        eta_g[l2] += np.asarray(dL_dxi, float).reshape(-1)[l2]
     return ex, ey[:ne], eta_g
 
 
-def qp_vjp(qp: StageQP, x, eta_x, eta_f, eta_g, lower, upper, xi=None):
+def qp_vjp(qp: StageQP, x, eta_x, eta_f, eta_g, lower, upper, xi=None, dL_dxi=None):
     """Map eta to gradients of the QP data (eq. loss_gradient).  With the
-    slacks `xi` given, also the gradient w.r.t. the L2 slack weight: gamma2
-    enters only the active slack rows' equation G_i x - y_i / gamma2 = b_i,
-    whose derivative y_i / gamma2^2 = -xi_i / gamma2 (slack stationarity)
-    with eta_y,i = gamma2 G_i eta_x gives dL/dgamma2 = sum_i xi_i (G eta_x)_i
-    over those rows (the paper's xi_A' S grad g_A eta_x)."""
+    slacks `xi` given, also:
+
+    * dL/dgamma2: gamma2 enters only the active slack rows' equation
+      G_i x - y_i / gamma2 = b_i, whose derivative y_i / gamma2^2 =
+      -xi_i / gamma2 (slack stationarity) with eta_y,i = gamma2 G_i eta_x +
+      dL/dxi_i gives dL/dgamma2 = -xi_A' eta_xi = sum_i xi_i (G eta_x)_i over
+      those rows (the paper's xi_A' S grad g_A eta_x);
+    * dL/dgamma1: an L1 row with nonzero slack carries the fixed multiplier
+      -gamma1 sign(xi_i) in the stationarity, so dL/dgamma1 =
+      sum_i sign(xi_i) (G eta_x)_i over those rows;
+    * eta_xi = -G_i eta_x on the rows whose slack moves with x (eq.
+      bwd:slack:eta_xi_yg; active L2 rows, L1 rows with nonzero slack), 0
+      elsewhere.
+
+    With a loss on the slacks (dL_dxi), an L1 row with nonzero slack
+    xi_i = bound_i - G_i x also passes dL/dxi_i to that bound (lower when
+    xi_i > 0, upper when xi_i < 0)."""
     n = qp.n
     xs = np.asarray(x).reshape(qp.N + 1, n)
     ex = np.asarray(eta_x).reshape(qp.N + 1, n)
-    d_gamma2 = None
+    d_lo = np.where(lower, eta_g, 0.0)
+    d_hi = np.where(upper, eta_g, 0.0)
+    d_gamma2 = d_gamma1 = eta_xi = None
     if xi is not None:
         G = qp.matrices()[2]
-        l2 = (lower | upper) & (qp.soft_rows() == SOFT_L2)
-        d_gamma2 = float(np.sum(np.asarray(xi)[l2] * (G @ np.asarray(eta_x))[l2]))
+        gex = G @ np.asarray(eta_x)
+        xi = np.asarray(xi, float).reshape(-1)
+        l2, l1 = _slack_rows(qp, lower, upper, xi)
+        d_gamma2 = float(np.sum(xi[l2] * gex[l2]))
+        d_gamma1 = float(np.sum(np.sign(xi[l1]) * gex[l1]))
+        eta_xi = np.where(l2 | l1, -gex, 0.0).reshape(qp.N + 1, qp.ng)
+        if dL_dxi is not None:
+            dxi = np.asarray(dL_dxi, float).reshape(-1)
+            d_lo = d_lo + np.where(l1 & (xi > 0), dxi, 0.0)
+            d_hi = d_hi + np.where(l1 & (xi < 0), dxi, 0.0)
     return {
         "d_gamma2": d_gamma2,
+        "d_gamma1": d_gamma1,
+        "eta_xi": eta_xi,
         "d_q": -ex,
         "d_c": np.asarray(eta_f).copy(),
         "d_x_init": np.asarray(eta_f)[: qp.nx].copy(),
         "d_Ddiag": -ex * xs,
-        "d_lo": np.where(lower, eta_g, 0.0).reshape(qp.N + 1, qp.ng),
-        "d_hi": np.where(upper, eta_g, 0.0).reshape(qp.N + 1, qp.ng),
+        "d_lo": d_lo.reshape(qp.N + 1, qp.ng),
+        "d_hi": d_hi.reshape(qp.N + 1, qp.ng),
     }

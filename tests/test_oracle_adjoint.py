@@ -7,6 +7,7 @@
 * The regularised iterative-refinement adjoint equals the dense solve.
 """
 import numpy as np
+import pytest
 
 from oracle.adjoint import adjoint_dense, adjoint_refined
 from oracle.lti import (fd_theta_grad, implicit_theta_grad, loss_and_grad_x, qp_of_theta,
@@ -227,3 +228,88 @@ def test_singularity_detection_agrees_with_the_rank_test():
         ex, ef, eg = adjoint_dense(qp, sol["x"], gx, lo_, upper)
         mn = sla.lstsq(K.toarray(), rhs, cond=1e-12)[0]
         np.testing.assert_allclose(np.concatenate([ex, ef]), mn[:ex.size + ef.size], rtol=1e-8, atol=1e-10)
+
+
+def _slack_qp(kind, gamma):
+    """Double integrator with slack position rows (L2 or L1) and a start
+    outside the tightened box: the first stages hold nonzero slack."""
+    from workloads import double_integrator
+    from oracle.qp import lti_batch_qp
+
+    b = double_integrator(1, N=12, seed=3)
+    b.x0[0, :2] = [1.8, -1.6]
+    qp = lti_batch_qp(b, 0)
+    kinds = np.zeros(qp.ng, dtype=np.int64)
+    kinds[:2] = kind
+    qp.soft = kinds
+    if kind == 1:
+        qp.gamma2 = gamma
+    else:
+        qp.gamma1 = gamma
+    qp.lo[:, :2] = -1.0
+    qp.hi[:, :2] = 1.0
+    return qp
+
+
+@pytest.mark.parametrize("kind,gamma", [(1, 4.0), (2, 0.7)], ids=["L2", "L1"])
+def test_slack_loss_gradients_match_central_fd(kind, gamma):
+    """A loss on the slacks, L = g'x + h'xi (eq. loss_gradient with the
+    slack block of eq. bwd:slack_adjoint): the VJP w.r.t. q, x_init, the
+    bound of a slacked row and the slack weight against central differences
+    (h = 1e-5) of ADMM solutions; the refinement form gives the dense one."""
+    from oracle.adjoint import adjoint_refined, polish, qp_vjp
+
+    qp = _slack_qp(kind, gamma)
+    r = _admm_exact(qp)
+    ok, sol = polish(qp, r.x, r.y_g, xi=r.xi, eps_solve=1e-8)
+    assert ok
+    xi0 = sol["xi"] if kind == 1 else r.xi
+    lower, upper = sol["lower"], sol["upper"]
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal(qp.nvar)
+    hx = np.zeros(qp.nineq)
+    slack = np.flatnonzero(np.abs(xi0) > 1e-3)
+    assert slack.size >= 2
+    hx[slack] = rng.standard_normal(slack.size)
+    ex, ef, eg = adjoint_dense(qp, sol["x"], g, lower, upper, dL_dxi=hx, xi=xi0)
+    e2 = adjoint_refined(qp, sol["x"], g, lower, upper, sweeps=8, dL_dxi=hx, xi=xi0)
+    for a, c in zip((ex, ef, eg), e2):
+        np.testing.assert_allclose(c, a, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(a).max()))
+    gr = qp_vjp(qp, sol["x"], ex, ef, eg, lower, upper, xi=xi0, dL_dxi=hx)
+    warm = {"x": r.x, "z_g": r.z_g, "y_f": r.y_f, "y_g": r.y_g, "rho_bar": r.rho_bar}
+    h = 1e-5
+
+    def loss(res):
+        return g @ res.x + hx @ res.xi
+
+    def fd(set_, base):
+        vals = []
+        for sgn in (1.0, -1.0):
+            set_(base + sgn * h)
+            vals.append(loss(_admm_exact(qp, warm)))
+        set_(base)
+        return (vals[0] - vals[1]) / (2 * h)
+
+    def setter(arr, idx):
+        def f(v):
+            arr[idx] = v
+        return f
+
+    t0, r0 = divmod(int(slack[0]), qp.ng)
+    side = "lo" if xi0[slack[0]] > 0 else "hi"
+    if kind == 1:
+        side = "lo" if lower[slack[0]] else "hi"
+    checks = [("q", (0, 4), gr["d_q"][0, 4]), ("q", (5, 1), gr["d_q"][5, 1]),
+              ("x_init", (0,), gr["d_x_init"][0]), (side, (t0, r0), gr["d_" + side][t0, r0])]
+    for field, idx, want in checks:
+        arr = getattr(qp, field)
+        got = fd(setter(arr, idx), arr[idx])
+        assert abs(got - want) <= 1e-4 * max(1.0, abs(want)), (field, idx, got, want)
+    wname = "gamma2" if kind == 1 else "gamma1"
+    got = fd(lambda v: setattr(qp, wname, v), gamma)
+    want = gr["d_" + wname]
+    assert abs(got - want) <= 1e-4 * max(1.0, abs(got)), (wname, got, want)
+    assert abs(want) > 1e-4
+    # eta_xi = -G eta_x on the slacked rows (eq. bwd:slack:eta_xi_yg)
+    G = qp.matrices()[2]
+    np.testing.assert_allclose(gr["eta_xi"].reshape(-1)[slack], -(G @ ex)[slack], atol=1e-12)
