@@ -184,6 +184,7 @@ typedef struct {
   double* d_gamma2;
   double *eta_f, *eta_g, *adj_resid;
   int32_t* adj_status;
+  double *eta_xi, *d_gamma1; /* [S,ng], [B]: see ocp_adjoint */
 } ocp_qp_grads;
 
 /* Fill `s` with the defaults listed above.  Never fails. */
@@ -228,11 +229,17 @@ ocp_status ocp_get_solution(ocp_handle h, const ocp_solution* out, void* stream)
 /* Implicit-differentiation VJP at the last solution (Algorithm 2, eq.
  * bwd:noslack_kkt_matrix / loss_gradient): identify the active set, factor
  * the regularised active-set Schur matrix in FP64, refine against the exact
- * KKT system and map eta to QP-data gradients.  dL_dx [S,n] device.
- * Active L2-slack rows follow the reduced system of eq.
- * bwd:slack_reduced_system (their penalty gamma2 G_i'G_i joins H, their
- * eta_y = gamma2 G_i eta_x; no loss term on the slacks); L1 rows with a
- * nonzero slack carry a fixed multiplier and leave the active set.
+ * KKT system and map eta to QP-data gradients.  dL_dx [S,n] device; dL_dxi
+ * [S,ng] device, the loss gradient w.r.t. the slacks, may be NULL (zero).
+ * Slack rows (eq. bwd:slack_adjoint): active L2-slack rows follow the reduced
+ * system of eq. bwd:slack_reduced_system -- their penalty gamma2 G_i'G_i
+ * joins H, the right-hand side gets -G_i' dL/dxi_i, their eta_y = dL/dxi_i +
+ * gamma2 G_i eta_x and eta_xi = -G_i eta_x (eq. bwd:slack:eta_xi_yg); L1 rows
+ * with a nonzero slack carry the fixed multiplier -gamma1 sign(xi) and leave
+ * the active set, their slack xi = bound - G_i x contributes -G_i' dL/dxi_i
+ * to the right-hand side and dL/dxi_i to that bound (d_lo when xi > 0, d_hi
+ * when xi < 0), eta_xi = -G_i eta_x, and d_gamma1 [B] = sum over them of
+ * sign(xi_i) (G eta_x)_i; eta_xi is 0 on the other rows.
  * Bicycle model: the VJP is that of the last SQP iteration's QP at that QP's
  * own ADMM solution (x, y_g, xi before the line-search step), which is the
  * returned iterate once the SQP has converged with unit steps; d_Ddiag uses
@@ -240,8 +247,8 @@ ocp_status ocp_get_solution(ocp_handle h, const ocp_solution* out, void* stream)
  * refinement reached settings.adj_tol.  Errors: OCP_E_ORDER before a solve,
  * OCP_E_ARG (null pointers, non-positive adj_sigma / adj_rho / eps_active /
  * adj_tol, refine_sweeps < 1). */
-ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const ocp_qp_grads* out,
-                       void* stream);
+ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const double* dL_dxi,
+                       const ocp_qp_grads* out, void* stream);
 
 /* Kernel timing (observability).  Classes of the library's launches: */
 enum {
@@ -275,7 +282,7 @@ ocp_status ocp_profile_read(ocp_handle h, ocp_kernel_times* out);
  * of one solve, and optionally the adjoint after it, recorded once and
  * replayed without per-launch host work).  Records, on `stream` (not NULL),
  * exactly the launches ocp_solve(h, s, out, stream) and -- when dL_dx and
- * grads are both given -- ocp_adjoint(h, s, dL_dx, grads, stream) would issue
+ * grads are both given -- ocp_adjoint(h, s, dL_dx, dL_dxi, grads, stream) would issue
  * now, into a HIP graph owned by the handle (replacing any earlier one).
  * Nothing runs during capture.  The graph keeps the given device pointers:
  * the caller keeps `out`, `dL_dx` and the `grads` buffers alive and in place
@@ -285,7 +292,7 @@ ocp_status ocp_profile_read(ocp_handle h, ocp_kernel_times* out);
  * (null handle / settings / stream, dL_dx without grads or vice versa),
  * OCP_E_ORDER (no problem data), OCP_E_HIP. */
 ocp_status ocp_graph_capture(ocp_handle h, const ocp_settings* s, const ocp_solution* out, const double* dL_dx,
-                             const ocp_qp_grads* grads, void* stream);
+                             const double* dL_dxi, const ocp_qp_grads* grads, void* stream);
 
 /* Replay the captured graph on `stream`.  Errors: OCP_E_ARG, OCP_E_ORDER
  * (nothing captured), OCP_E_HIP. */

@@ -57,7 +57,8 @@ class ocp_solution(C.Structure):
 
 class ocp_qp_grads(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("d_q", "d_Ddiag", "d_x_init", "d_lo", "d_hi", "eta_x", "active",
-                                          "d_gamma2", "eta_f", "eta_g", "adj_resid", "adj_status")]
+                                          "d_gamma2", "eta_f", "eta_g", "adj_resid", "adj_status", "eta_xi",
+                                          "d_gamma1")]
 
 
 # (name, restype, argtypes) for every symbol declared in include/ocp_admm.h
@@ -81,10 +82,11 @@ SIGNATURES = [
     ("ocp_set_bicycle", C.c_int, [C.c_void_p, C.POINTER(ocp_bicycle), C.c_void_p]),
     ("ocp_solve", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.POINTER(ocp_solution), C.c_void_p]),
     ("ocp_get_solution", C.c_int, [C.c_void_p, C.POINTER(ocp_solution), C.c_void_p]),
-    ("ocp_adjoint", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_void_p, C.POINTER(ocp_qp_grads),
+    ("ocp_adjoint", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_void_p, C.c_void_p, C.POINTER(ocp_qp_grads),
                               C.c_void_p]),
     ("ocp_profile", C.c_int, [C.c_void_p, C.c_int32]),
     ("ocp_graph_capture", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.POINTER(ocp_solution), C.c_void_p,
+                                    C.c_void_p,
                                     C.POINTER(ocp_qp_grads), C.c_void_p]),
     ("ocp_graph_launch", C.c_int, [C.c_void_p, C.c_void_p]),
     ("ocp_set_segmented", C.c_int, [C.c_void_p, C.c_int32]),

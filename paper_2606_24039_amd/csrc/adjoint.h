@@ -37,7 +37,9 @@
 namespace ocpk {
 
 struct AdjArgs {
-  const double* dLdx;  // [S][n]
+  const double* dLdx;   // [S][n] (the effective right-hand side dl below when dLdxi is given)
+  const double* dLdxi;  // [S][ng] loss gradient w.r.t. the slacks; may be null
+  double* dl;           // [S][n] scratch: dL/dx - G_S' dL/dxi (eq. bwd:slack_reduced_system)
   double sigma_b, rho_b, eps_active;
   int sweeps;
   int chunk_min_n;  // horizons from which the factorisation runs chunked
@@ -57,6 +59,7 @@ struct AdjArgs {
   int8_t* active;
   double *eta_f, *eta_g, *adj_resid;
   int32_t* adj_status;
+  double *eta_xi, *d_gamma1;
   double adj_tol;  // relative KKT residual accepted as refined
 };
 
@@ -565,6 +568,31 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     eg[sv] = 0.0;
   }
   wave_sync();
+  // loss on the slacks: the rows whose slack moves with x (active L2 rows,
+  // L1 rows with nonzero slack xi = bound - G x) contribute -G_i' dL/dxi_i to
+  // the right-hand side of the reduced system (eq. bwd:slack_reduced_system)
+  AdjArgs ar = a;
+  if (a.dLdxi) {
+    dlmax = 0.0;
+    for (int blk = 0; blk < nbl; ++blk) {
+      const int t = 4 * blk + q;
+      if (t > N) break;
+      const int64_t s = s0 + t;
+      const size_t sv = (size_t)s * ROW + i;
+      const bool moves = i < NG && ((kind == 1 && a.act[sv] != 0) || (kind == 2 && double(XI[sv]) != 0.0));
+      const double wr = moves ? a.dLdxi[(size_t)s * NG + i] : 0.0;
+      double Gc[NG];
+      load_col<NG>(Gc, L.G + ti_or_tv(L.ti, b, s, (size_t)NG * n) + (i < n ? i : n - 1), n, true);
+      const double e = (i < n ? a.dLdx[(size_t)s * n + i] : 0.0) - dotb<NG>(Gc, wr, 0.0);
+      if (i < n) {
+        a.dl[(size_t)s * n + i] = e;
+        dlmax = fmax(dlmax, fabs(e * sd));
+      }
+    }
+    dlmax = rows_max(row_max(dlmax));
+    wave_sync();
+    ar.dLdx = a.dl;
+  }
 
   // ---- 2. factor H + sigma_b I + rho_b (C'C + G_A'G_A) (FP64, P/K form) ----
   Layout LF = L;
@@ -584,15 +612,15 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   // ---- refinement sweeps, then the final FP64 residual ||r - K e||_inf ----
   double rres;
   if constexpr (ST::TI) {
-    rres = adjoint_sweeps_ti<NX, NU, NG, ST>(L, a, w, bad);
+    rres = adjoint_sweeps_ti<NX, NU, NG, ST>(L, ar, w, bad);
   } else {
-    rres = adjoint_sweeps_tv<NX, NU, NG>(L, a, w, bad, slr);
+    rres = adjoint_sweeps_tv<NX, NU, NG>(L, ar, w, bad, slr);
   }
   rres = rows_max(row_max(rres));
 
   // ---- 3. VJP outputs ----
   const double nanv = bad ? NAN : 0.0;
-  double dgam = 0.0;  // this lane's part of dL/dgamma2
+  double dgam = 0.0, dgam1 = 0.0;  // this lane's parts of dL/dgamma2, dL/dgamma1
   bool nonfin = false;
   for (int blk = 0; blk < nbl; ++blk) {
     const int t = 4 * blk + q;
@@ -612,12 +640,22 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     const double gex = dotb<n>(Gr, (i < n) ? ex[sv] : 0.0, 0.0);
     if (i < NG) {
       const int act = a.act[sv];
-      const double e = ((kind == 1 && act != 0) ? L.gamma2 * gex : eg[sv]) * se + nanv;
-      if (kind == 1 && act != 0) dgam += double(XI[sv]) * gex;
+      const double xiv = double(XI[sv]);
+      const double dxi = a.dLdxi ? a.dLdxi[(size_t)s * NG + i] : 0.0;
+      const bool l2a = kind == 1 && act != 0;     // active L2-slack row
+      const bool l1s = kind == 2 && xiv != 0.0;   // L1 row with nonzero slack
+      // eta_y of an active L2 row: dL/dxi + gamma2 G_i eta_x (eq. bwd:slack:eta_xi_yg)
+      const double e = (l2a ? L.gamma2 * gex + dxi : eg[sv]) * se + nanv;
+      if (l2a) dgam += xiv * gex;
+      if (l1s) dgam1 += (xiv > 0.0 ? 1.0 : -1.0) * gex;
       if (act != 0) nonfin |= !isfinite(e);
-      if (a.d_lo) a.d_lo[(size_t)s * NG + i] = (act < 0) ? e : 0.0;
-      if (a.d_hi) a.d_hi[(size_t)s * NG + i] = (act > 0) ? e : 0.0;
+      // an L1 row with nonzero slack passes dL/dxi to its bound (xi = bound - G x)
+      const double blo = (act < 0) ? e : ((l1s && xiv > 0.0) ? dxi : 0.0);
+      const double bhi = (act > 0) ? e : ((l1s && xiv < 0.0) ? dxi : 0.0);
+      if (a.d_lo) a.d_lo[(size_t)s * NG + i] = blo;
+      if (a.d_hi) a.d_hi[(size_t)s * NG + i] = bhi;
       if (a.eta_g) a.eta_g[(size_t)s * NG + i] = (act != 0) ? e : 0.0;
+      if (a.eta_xi) a.eta_xi[(size_t)s * NG + i] = (l2a || l1s) ? -gex + nanv : 0.0;
       if (a.active) a.active[(size_t)s * NG + i] = (int8_t)act;
     }
     if (i < NX) {
@@ -632,9 +670,13 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   dgam = row_sum(dgam);
   dgam += __shfl_xor(dgam, 16);
   dgam += __shfl_xor(dgam, 32);
+  dgam1 = row_sum(dgam1);
+  dgam1 += __shfl_xor(dgam1, 16);
+  dgam1 += __shfl_xor(dgam1, 32);
   const bool anynf = __ballot(nonfin) != 0;
   if (threadIdx.x == 0) {
     if (a.d_gamma2) a.d_gamma2[b] = dgam + nanv;
+    if (a.d_gamma1) a.d_gamma1[b] = dgam1 + nanv;
     // relative FP64 residual of the active-set KKT system after the sweeps
     const double rel = rres / fmax(dlmax, 1e-300);
     if (a.adj_resid) a.adj_resid[b] = bad ? NAN : rel;

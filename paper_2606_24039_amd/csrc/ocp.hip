@@ -107,6 +107,7 @@ struct ocp_handle_s {
   double *adj_rhog = nullptr, *adj_ex = nullptr, *adj_ey = nullptr, *adj_eg = nullptr, *adj_r = nullptr;
   double *adj_v = nullptr, *adj_rg = nullptr;
   double *adj_P = nullptr, *adj_K = nullptr, *adj_Kb = nullptr;  // adjoint factor, FP64 P/K form
+  double* adj_dl = nullptr;  // [S][n] right-hand side with a loss on the slacks
   uint8_t soft_host[16] = {0};
   int8_t* adj_act = nullptr;
 
@@ -263,6 +264,7 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   A_(h->adj_Kb, sizeof(double) * nn * SP);
   A_(h->adj_rg, sizeof(double) * ROW * S);
   A_(h->adj_act, sizeof(int8_t) * ROW * S);
+  A_(h->adj_dl, sizeof(double) * n * S);
 #undef A_
   if (count_only) return OCP_OK;
   if (!h->mixed) {  // iteration-precision copies alias the FP64 data
@@ -881,8 +883,8 @@ ocp_status ocp_get_solution(ocp_handle h, const ocp_solution* out, void* stream)
   return copy_out(h, out, (hipStream_t)stream);
 }
 
-ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const ocp_qp_grads* out,
-                       void* stream) {
+ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const double* dL_dxi,
+                       const ocp_qp_grads* out, void* stream) {
   if (!h || !s || !dL_dx || !out) return OCP_E_ARG;
   if (!h->solved) return OCP_E_ORDER;
   if (!(s->adj_sigma > 0) || !(s->adj_rho > 0) || !(s->eps_active > 0) || !(s->adj_tol > 0) ||
@@ -891,6 +893,8 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   hipStream_t st = (hipStream_t)stream;
   AdjArgs a{};
   a.dLdx = dL_dx;
+  a.dLdxi = dL_dxi;
+  a.dl = h->adj_dl;
   a.sigma_b = s->adj_sigma;
   a.rho_b = s->adj_rho;
   a.eps_active = s->eps_active;
@@ -919,6 +923,8 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   a.eta_g = out->eta_g;
   a.adj_resid = out->adj_resid;
   a.adj_status = out->adj_status;
+  a.eta_xi = out->eta_xi;
+  a.d_gamma1 = out->d_gamma1;
   a.adj_tol = s->adj_tol;
   const Layout L = make_layout(h);
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (h->ti ? VAR_TI : VAR_TV);
@@ -948,7 +954,7 @@ ocp_status ocp_profile_read(ocp_handle h, ocp_kernel_times* out) {
 }
 
 ocp_status ocp_graph_capture(ocp_handle h, const ocp_settings* s, const ocp_solution* out, const double* dL_dx,
-                             const ocp_qp_grads* grads, void* stream) {
+                             const double* dL_dxi, const ocp_qp_grads* grads, void* stream) {
   if (!h || !s || !stream) return OCP_E_ARG;
   if ((dL_dx == nullptr) != (grads == nullptr)) return OCP_E_ARG;
   ocp_status st = check_settings(s);
@@ -970,7 +976,7 @@ ocp_status ocp_graph_capture(ocp_handle h, const ocp_settings* s, const ocp_solu
     return OCP_E_HIP;
   }
   st = ocp_solve(h, s, out, stream);
-  if (st == OCP_OK && dL_dx) st = ocp_adjoint(h, s, dL_dx, grads, stream);
+  if (st == OCP_OK && dL_dx) st = ocp_adjoint(h, s, dL_dx, dL_dxi, grads, stream);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(cs, &g);
   h->prof.on = prof_on;

@@ -140,13 +140,14 @@ class OCPSolver:
         A.check(self.lib.ocp_solve(self.h, C.byref(settings), C.byref(sol_struct) if sol_struct is not None else None,
                                    _stream()), "ocp_solve")
 
-    def adjoint(self, dL_dx, settings=None, **overrides):
+    def adjoint(self, dL_dx, settings=None, dL_dxi=None, **overrides):
         s = settings if settings is not None else A.default_settings(**overrides)
         g = self.alloc_grads()
         gs = self.grads_struct(g)
         dl = _dev(dL_dx)
-        A.check(self.lib.ocp_adjoint(self.h, C.byref(s), C.c_void_p(dl.data_ptr()), C.byref(gs), _stream()),
-                "ocp_adjoint")
+        dxi = _dev(dL_dxi) if dL_dxi is not None else None
+        A.check(self.lib.ocp_adjoint(self.h, C.byref(s), C.c_void_p(dl.data_ptr()), _ptr(dxi), C.byref(gs),
+                                     _stream()), "ocp_adjoint")
         torch.cuda.current_stream().synchronize()
         return g
 
@@ -160,10 +161,10 @@ class OCPSolver:
         A.check(self.lib.ocp_profile_read(self.h, C.byref(t)), "ocp_profile_read")
         return {name: (t.ms[k], int(t.launches[k])) for k, name in enumerate(A.K_NAMES)}
 
-    def adjoint_raw(self, settings, dl, grads_struct):
+    def adjoint_raw(self, settings, dl, grads_struct, dxi=None):
         """Launch an adjoint with prebuilt arguments (no allocation, no sync)."""
-        A.check(self.lib.ocp_adjoint(self.h, C.byref(settings), C.c_void_p(dl.data_ptr()), C.byref(grads_struct),
-                                     _stream()), "ocp_adjoint")
+        A.check(self.lib.ocp_adjoint(self.h, C.byref(settings), C.c_void_p(dl.data_ptr()), _ptr(dxi),
+                                     C.byref(grads_struct), _stream()), "ocp_adjoint")
 
     def alloc_grads(self):
         f64 = dict(dtype=torch.float64, device=self.device)
@@ -173,20 +174,21 @@ class OCPSolver:
                 "active": torch.empty(self.S, self.ng, dtype=torch.int8, device=self.device),
                 "d_gamma2": torch.empty(self.B, **f64), "eta_f": torch.empty(self.S, self.nx, **f64),
                 "eta_g": torch.empty(self.S, self.ng, **f64), "adj_resid": torch.empty(self.B, **f64),
-                "adj_status": torch.empty(self.B, dtype=torch.int32, device=self.device)}
+                "adj_status": torch.empty(self.B, dtype=torch.int32, device=self.device),
+                "eta_xi": torch.empty(self.S, self.ng, **f64), "d_gamma1": torch.empty(self.B, **f64)}
 
     def grads_struct(self, g):
         return A.ocp_qp_grads(*[g[k].data_ptr() for k, _ in A.ocp_qp_grads._fields_])
 
-    def graph_capture(self, settings, out, dl=None, grads=None):
+    def graph_capture(self, settings, out, dl=None, grads=None, dxi=None):
         """Record one solve (and the adjoint for dl, grads) into the handle's
         HIP graph on the current stream; `out`, `dl` and `grads` must stay
         alive and in place while the graph is replayed."""
         sol = self.solution_struct(out)
         gs = self.grads_struct(grads) if grads is not None else None
-        self._graph_keep = (out, dl, grads, sol, gs)
+        self._graph_keep = (out, dl, grads, sol, gs, dxi)
         A.check(self.lib.ocp_graph_capture(self.h, C.byref(settings), C.byref(sol),
-                                           C.c_void_p(dl.data_ptr()) if dl is not None else None,
+                                           C.c_void_p(dl.data_ptr()) if dl is not None else None, _ptr(dxi),
                                            C.byref(gs) if gs is not None else None, _stream()),
                 "ocp_graph_capture")
 

@@ -66,7 +66,7 @@ def test_defaults_and_host_side_errors():
     assert lib.ocp_status_string(_abi.OCP_E_ORDER) == b"call order violated"
     assert lib.ocp_destroy(None) == _abi.OCP_OK
     # entry points that need a handle reject a null one before any device work
-    assert lib.ocp_graph_capture(None, C.byref(s), None, None, None, None) == _abi.OCP_E_ARG
+    assert lib.ocp_graph_capture(None, C.byref(s), None, None, None, None, None) == _abi.OCP_E_ARG
     assert lib.ocp_graph_launch(None, None) == _abi.OCP_E_ARG
     assert lib.ocp_profile(None, 1) == _abi.OCP_E_ARG
     assert lib.ocp_profile_read(None, None) == _abi.OCP_E_ARG

@@ -33,9 +33,16 @@ def _settings(**kw):
     return default_settings(**kw)
 
 
+@pytest.mark.parametrize("slack_loss", [False, True], ids=["x_loss", "x_and_slack_loss"])
 @pytest.mark.parametrize("seg", [None, 15], ids=["stagewise", "chunked"])
 @pytest.mark.parametrize("precision", [FP64, MIXED])
-def test_bicycle_adjoint_matches_oracle_dense_solve(precision, seg):
+def test_bicycle_adjoint_matches_oracle_dense_solve(precision, seg, slack_loss):
+    """slack_loss: the loss also has a term on the slacks (dL/dxi, eq.
+    loss_gradient with the slack block): the L1 rows with nonzero slack pass
+    it to the right-hand side and to their bound; eta_xi and dL/dgamma1 are
+    compared too.  The adjoint runs in FP64 in both precisions and the
+    linearisation point is the shared initial guess, so the oracle's dense
+    solve at the GPU's active set is matched to 1e-6 in both."""
     from paper_2606_24039_amd import _abi as A
     from paper_2606_24039_amd.solver import OCPSolver
 
@@ -51,7 +58,9 @@ def test_bicycle_adjoint_matches_oracle_dense_solve(precision, seg):
     eps = 1e-10 if precision == FP64 else 1e-6
     s.solve(_settings(max_sqp=1, fixed_sqp=1, eps_abs=eps, eps_rel=eps, max_admm=20000))
     dl = torch.as_tensor(np.random.default_rng(7).standard_normal((s.S, 6)), dtype=torch.float64, device="cuda")
-    g = s.adjoint(dl, _settings(eps_active=1e-6))
+    dxi = (torch.as_tensor(np.random.default_rng(9).standard_normal((s.S, 3)), dtype=torch.float64, device="cuda")
+           if slack_loss else None)
+    g = s.adjoint(dl, _settings(eps_active=1e-6), dL_dxi=dxi)
     for i in range(b.batch):
         ocp = BicycleOCP(b, i)
         qp = ocp.convexify(ocp.initial_guess())
@@ -69,13 +78,20 @@ def test_bicycle_adjoint_matches_oracle_dense_solve(precision, seg):
             ref_lo, ref_up = active_set(qp, sol["x"], sol["y_g"], xi=r.xi, eps_solve=1e-6)
             assert np.array_equal(lower, ref_lo) and np.array_equal(upper, ref_up), i
         dli = s.split(dl, i).cpu().numpy().reshape(-1)
-        ex, ef, eg = adjoint_dense(qp, sol["x"], dli, lower, upper)
-        tol = 1e-6 if precision == FP64 else 2e-3
+        # which L1 rows hold a nonzero slack (they leave the active set): the
+        # oracle's converged ADMM slacks of the same QP
+        xi_gpu = r.xi
+        dxii = s.split(dxi, i).cpu().numpy().reshape(-1) if slack_loss else None
+        ex, ef, eg = adjoint_dense(qp, sol["x"], dli, lower, upper, dL_dxi=dxii, xi=xi_gpu)
+        tol = 1e-6
         assert rel(s.split(g["eta_x"], i).cpu().numpy().reshape(-1), ex) < tol, i
-        if precision == FP64:
-            qg = qp_vjp(qp, sol["x"], ex, ef, eg, lower, upper)
-            flat = lambda a: np.asarray(a).reshape(-1)
-            assert rel(flat(g["d_x_init"][i].cpu().numpy()), flat(qg["d_x_init"])) < tol, i
-            for k in ("d_q", "d_lo", "d_hi"):
-                assert rel(flat(s.split(g[k], i).cpu().numpy()), flat(qg[k])) < tol, (i, k)
+        qg = qp_vjp(qp, sol["x"], ex, ef, eg, lower, upper, xi=xi_gpu, dL_dxi=dxii)
+        flat = lambda a: np.asarray(a).reshape(-1)
+        assert rel(flat(g["d_x_init"][i].cpu().numpy()), flat(qg["d_x_init"])) < tol, i
+        for k in ("d_q", "d_lo", "d_hi", "eta_xi"):
+            assert rel(flat(s.split(g[k], i).cpu().numpy()), flat(qg[k])) < tol, (i, k)
+        assert rel(flat(s.split(g["eta_g"], i).cpu().numpy()), flat(eg)) < tol, i
+        assert abs(float(g["d_gamma1"][i]) - qg["d_gamma1"]) <= tol * max(1.0, abs(qg["d_gamma1"])), i
+        if i == 1:
+            assert abs(qg["d_gamma1"]) > 1e-6
     s.close()

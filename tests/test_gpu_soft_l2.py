@@ -88,15 +88,20 @@ def test_l2_slack_fixed_rho_iterates_fp64():
     s.close()
 
 
+@pytest.mark.parametrize("slack_loss", [False, True], ids=["x_loss", "x_and_slack_loss"])
 @pytest.mark.parametrize("seg", [None, 15], ids=["stagewise", "chunked"])
-def test_l2_slack_adjoint_matches_oracle_dense_solve(seg):
+def test_l2_slack_adjoint_matches_oracle_dense_solve(seg, slack_loss):
+    """slack_loss: a loss term on the slacks too (eq. bwd:slack_reduced_system
+    right-hand side, eta_y and eta_xi of eq. bwd:slack:eta_xi_yg)."""
     qps = _qps()
     s = _solver(qps)
     if seg is not None:
         s.set_segmented(seg)
     s.solve(_settings(eps_abs=1e-10, eps_rel=1e-10, max_admm=40000))
     dl = torch.as_tensor(np.random.default_rng(8).standard_normal((s.S, 6)), dtype=torch.float64, device="cuda")
-    g = s.adjoint(dl, _settings(eps_active=1e-6))
+    dxi = (torch.as_tensor(np.random.default_rng(10).standard_normal((s.S, s.ng)), dtype=torch.float64,
+                           device="cuda") if slack_loss else None)
+    g = s.adjoint(dl, _settings(eps_active=1e-6), dL_dxi=dxi)
     for i, qp in enumerate(qps):
         r = admm_solve(qp, ADMMSettings(eps_abs=1e-12, eps_rel=1e-12, max_iter=400000))
         ok, sol = polish(qp, r.x, r.y_g, xi=r.xi, eps_solve=1e-8)
@@ -106,9 +111,12 @@ def test_l2_slack_adjoint_matches_oracle_dense_solve(seg):
         assert np.array_equal(act < 0, lower) and np.array_equal(act > 0, upper), i
         assert np.any(((lower | upper) & (qp.soft_rows() == SOFT_L2)))
         dli = s.split(dl, i).cpu().numpy().reshape(-1)
-        ex, ef, eg = adjoint_dense(qp, sol["x"], dli, lower, upper)
+        dxii = s.split(dxi, i).cpu().numpy().reshape(-1) if slack_loss else None
+        ex, ef, eg = adjoint_dense(qp, sol["x"], dli, lower, upper, dL_dxi=dxii, xi=sol["xi"])
         assert rel(s.split(g["eta_x"], i).cpu().numpy().reshape(-1), ex) < 1e-6, i
-        qg = qp_vjp(qp, sol["x"], ex, ef, eg, lower, upper, xi=sol["xi"])
+        assert rel(s.split(g["eta_g"], i).cpu().numpy().reshape(-1), eg) < 1e-6, i
+        qg = qp_vjp(qp, sol["x"], ex, ef, eg, lower, upper, xi=sol["xi"], dL_dxi=dxii)
+        assert rel(s.split(g["eta_xi"], i).cpu().numpy().reshape(-1), qg["eta_xi"].reshape(-1)) < 1e-6, i
         assert abs(float(g["d_gamma2"][i]) - qg["d_gamma2"]) <= 1e-6 * max(1.0, abs(qg["d_gamma2"])), i
         flat = lambda a: np.asarray(a).reshape(-1)
         assert rel(flat(g["d_x_init"][i].cpu().numpy()), flat(qg["d_x_init"])) < 1e-6, i
