@@ -113,7 +113,18 @@ typedef struct {
   int32_t max_sqp;         /* SQP iterations (bicycle model) */
   int32_t fixed_sqp;       /* 1: run exactly max_sqp iterations */
   int32_t refine_sweeps;   /* adjoint iterative-refinement sweeps (default 8) */
+  int32_t adj_mode;        /* bicycle model: what ocp_adjoint differentiates (OCP_ADJ_LAST_QP,
+                              OCP_ADJ_SQP_GN, OCP_ADJ_SQP_EXACT); ignored for linear models */
 } ocp_settings;
+
+/* ocp_settings.adj_mode.  LAST_QP: the last SQP iteration's QP at its own
+ * ADMM solution.  SQP_GN / SQP_EXACT: the SQP solution itself -- the KKT
+ * conditions of the OCP at the handle's SQP iterate (the last solve's, or one
+ * restored by ocp_set_iterate), i.e. the QP convexified there with the Hessian
+ * of the cost alone (Gauss-Newton, the paper's approximate second-order
+ * option) or of the Lagrangian, grad^2 l + sum_t y_f,t' grad^2 f_t (exact; the
+ * dynamics curvature fills D_t and the cross-stage blocks E_t). */
+enum { OCP_ADJ_LAST_QP = 0, OCP_ADJ_SQP_GN = 1, OCP_ADJ_SQP_EXACT = 2 };
 
 /* Linear time-invariant model (OCP_MODEL_LTI): x_{t+1} = A x_t + B u_t,
  * cost 1/2(x'Qx + u'Ru) for t < N and 1/2(x'Q_f x + u'Ru) at t = N, bounds
@@ -249,6 +260,18 @@ ocp_status ocp_get_solution(ocp_handle h, const ocp_solution* out, void* stream)
  * adj_tol, refine_sweeps < 1). */
 ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx, const double* dL_dxi,
                        const ocp_qp_grads* out, void* stream);
+
+/* Checkpoint restore for the SQP layer (bicycle model): load an SQP iterate
+ * -- x [S,n], xi [S,ng], y_f [S,nx] (slot convention of ocp_solution.y_f), y_g
+ * [S,ng], DEVICE, FP64, as ocp_solve returned it -- into the handle, so that
+ * ocp_adjoint with adj_mode SQP_GN / SQP_EXACT differentiates at it even after
+ * the handle solved other problems (the problem data must be those of that
+ * solve: call ocp_set_bicycle again first if they changed).  Only the iterate
+ * is kept between a forward and its backward; the factorisation is redone
+ * there.  Errors: OCP_E_ARG (null pointers), OCP_E_UNSUPPORTED (other
+ * models), OCP_E_ORDER (no problem data). */
+ocp_status ocp_set_iterate(ocp_handle h, const double* x, const double* xi, const double* y_f, const double* y_g,
+                           void* stream);
 
 /* Kernel timing (observability).  Classes of the library's launches: */
 enum {

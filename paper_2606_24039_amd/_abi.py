@@ -17,6 +17,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 ROW_HARD, ROW_L2, ROW_L1 = 0, 1, 2
 SOLVED, MAX_ITER, NON_FINITE, FACTOR_BREAKDOWN, INFEASIBLE = 0, 1, 2, 3, 4
 ADJ_OK, ADJ_RESIDUAL, ADJ_NON_FINITE, ADJ_BREAKDOWN = 0, 1, 2, 3
+ADJ_LAST_QP, ADJ_SQP_GN, ADJ_SQP_EXACT = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -31,7 +32,8 @@ class ocp_settings(C.Structure):
     _fields_ = [(k, C.c_double) for k in (
         "sigma", "rho0", "rho_f_scale", "rho_min", "rho_max", "k_ratio", "alpha", "eps_abs", "eps_rel",
         "eps_c", "armijo_eta", "eps_active", "adj_sigma", "adj_rho", "adj_tol", "eps_pinf")] + [(k, C.c_int32) for k in (
-            "max_admm", "k_rho", "k_check", "adapt_rho", "warm_start", "max_sqp", "fixed_sqp", "refine_sweeps")]
+            "max_admm", "k_rho", "k_check", "adapt_rho", "warm_start", "max_sqp", "fixed_sqp", "refine_sweeps",
+            "adj_mode")]
 
 
 class ocp_lti(C.Structure):
@@ -91,6 +93,7 @@ SIGNATURES = [
     ("ocp_graph_launch", C.c_int, [C.c_void_p, C.c_void_p]),
     ("ocp_set_segmented", C.c_int, [C.c_void_p, C.c_int32]),
     ("ocp_set_segmented_after", C.c_int, [C.c_void_p, C.c_int32]),
+    ("ocp_set_iterate", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ocp_autotune", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_int32, C.c_void_p, C.POINTER(C.c_int32),
                                C.POINTER(C.c_int32)]),
     ("ocp_profile_read", C.c_int, [C.c_void_p, C.POINTER(ocp_kernel_times)]),

@@ -475,4 +475,134 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
   }
 }
 
+// sum_k y_k grad^2 fc_k at (x, u) over w = (px, py, yaw, v, a, delta): the
+// nonzero second derivatives of v cos(yaw), v sin(yaw), v tan(delta) / L
+__device__ __forceinline__ void bike_fc_hessian(const double* x, const double* u, const double* y, double Lw,
+                                                double (*A)[6]) {
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) A[r][c] = 0.0;
+  const double cy = cos(x[2]), sy = sin(x[2]), v = x[3];
+  const double cd = cos(u[1]), c2 = cd * cd, td = tan(u[1]);
+  A[2][2] = -y[0] * v * cy - y[1] * v * sy;
+  A[2][3] = A[3][2] = -y[0] * sy + y[1] * cy;
+  A[3][5] = A[5][3] = y[2] / (Lw * c2);
+  A[5][5] = y[2] * 2.0 * v * td / (Lw * c2);
+}
+
+// Curvature blocks of dynamics row t (multiplier y) over the stage variables
+// z_t = (x_t, u_t) and x_{t+1}: left [6][6] (z_t, z_t), right [4][4]
+// (x_{t+1}, x_{t+1}), cross [4][6] (x_{t+1}, z_t), all of y' grad^2 f_t.
+//   midpoint:  dt M' A((x_t + x_{t+1})/2, u_t) M,  M = [[I/2, 0, I/2], [0, I, 0]]
+//   trapezoid: dt/2 (A(x_t, u_t) on (x_t, u_t) + A(x_{t+1}, u_t) on (x_{t+1}, u_t))
+template <int INTEG>
+__device__ __forceinline__ void bike_row_hessian(const double* xt, const double* ut, const double* xn,
+                                                 const double* y, double dt, double Lw, double (*left)[6],
+                                                 double (*right)[4], double (*cross)[6]) {
+  double A[6][6];
+  if constexpr (INTEG == 0) {
+    double m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = 0.5 * (xt[k] + xn[k]);
+    bike_fc_hessian(m, ut, y, Lw, A);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) left[r][c] = dt * A[r][c] * (r < 4 ? 0.5 : 1.0) * (c < 4 ? 0.5 : 1.0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) right[r][c] = 0.25 * dt * A[r][c];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) cross[r][c] = dt * A[r][c] * 0.5 * (c < 4 ? 0.5 : 1.0);
+    }
+  } else {
+    double B[6][6];
+    bike_fc_hessian(xt, ut, y, Lw, A);
+    bike_fc_hessian(xn, ut, y, Lw, B);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) left[r][c] = 0.5 * dt * (A[r][c] + ((r >= 4 && c >= 4) ? B[r][c] : 0.0));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) right[r][c] = 0.5 * dt * B[r][c];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) cross[r][c] = (c >= 4) ? 0.5 * dt * B[r][c] : 0.0;
+    }
+  }
+}
+
+// Exact Hessian of the Lagrangian at the SQP iterate (one thread per stage):
+// D_t gains the curvature of dynamics row t (left block) and of row t-1
+// (right block), E_t (block (t+1, t)) is the cross block of row t.  Runs
+// after bike_linearize_kernel, which leaves D_t = diag(Q or Q_f, R).
+template <int INTEG>
+__global__ void bike_hessian_kernel(Layout L, BikeArgs a) {
+  const int64_t S = L.stage_off[L.B];
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const int b = a.stage_inst[s];
+  const int64_t s0 = L.stage_off[b];
+  const int t = (int)(s - s0);
+  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+  double* D = const_cast<double*>(L.D) + s * 36;
+  double* E = const_cast<double*>(L.E) + s * 36;
+  double left[6][6], right[4][4], cross[4][6];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) E[k] = 0.0;
+  if (t < N) {  // row t: this stage on the left
+    const double* xt = a.xbar + s * ROW;
+    bike_row_hessian<INTEG>(xt, xt + 4, xt + ROW, a.yfbar + s * ROW, a.dt, a.Lw, left, right, cross);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) D[r * 6 + c] += left[r][c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) E[r * 6 + c] = cross[r][c];
+  }
+  if (t > 0) {  // row t-1: this stage's state on the right
+    const double* xp = a.xbar + (s - 1) * ROW;
+    bike_row_hessian<INTEG>(xp, xp + 4, xp + ROW, a.yfbar + (s - 1) * ROW, a.dt, a.Lw, left, right, cross);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) D[r * 6 + c] += right[r][c];
+  }
+}
+
+// The QP state of the adjoint set to the SQP iterate: slacks (the
+// linearisation has put x and the multipliers in place)
+template <typename T>
+__global__ void iterate_slacks_kernel(const double* __restrict__ xibar, T* __restrict__ xi, int64_t S) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < S * ROW) xi[k] = T(xibar[k]);
+}
+
+// checkpointed iterate (output layout) -> the SQP state (padded [S][ROW]);
+// y_f from the output slot convention (initial rows at the first stage,
+// dynamics row t at stage t + 1) to the internal one (dynamics row t at
+// stage t, initial rows at the last stage)
+__global__ void load_iterate_kernel(const double* __restrict__ x, const double* __restrict__ xi,
+                                    const double* __restrict__ yf, const double* __restrict__ yg,
+                                    const int64_t* __restrict__ off, const int32_t* __restrict__ inst, int64_t S,
+                                    int n, int nx, int ng, double* __restrict__ xbar, double* __restrict__ xibar,
+                                    double* __restrict__ yfbar, double* __restrict__ ygbar) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= S * ROW) return;
+  const int64_t s = k / ROW;
+  const int j = (int)(k % ROW);
+  xbar[k] = j < n ? x[s * n + j] : 0.0;
+  xibar[k] = j < ng ? xi[s * ng + j] : 0.0;
+  ygbar[k] = j < ng ? yg[s * ng + j] : 0.0;
+  const int b = inst[s];
+  const int64_t to = (s == off[b]) ? off[b + 1] - 1 : s - 1;
+  if (j < nx) yfbar[to * ROW + j] = yf[s * nx + j];
+  else yfbar[to * ROW + j] = 0.0;
+}
+
 }  // namespace ocpk

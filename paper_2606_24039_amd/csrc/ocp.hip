@@ -186,7 +186,7 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   A_(h->stage_off, sizeof(int64_t) * (B + 1));
   A_(h->order, sizeof(int32_t) * B);
   A_(h->D, sizeof(double) * nn * (h->ti ? 2 * (size_t)B : (size_t)S));
-  if (d->model == OCP_MODEL_QP) A_(h->E, sizeof(double) * nn * blkI);
+  if (d->model != OCP_MODEL_LTI) A_(h->E, sizeof(double) * nn * blkI);  // bicycle: the Lagrangian Hessian
   if (d->model != OCP_MODEL_LTI) A_(h->bd, sizeof(double) * nx * blkI);
   if (d->model != OCP_MODEL_LTI) A_(h->q, sizeof(double) * n * (size_t)S);
   A_(h->Am, sizeof(double) * nx * n * blkI);
@@ -679,6 +679,7 @@ void ocp_default_settings(ocp_settings* s) {
   s->max_sqp = 10;
   s->fixed_sqp = 1;
   s->refine_sweeps = 8;
+  s->adj_mode = OCP_ADJ_LAST_QP;
 }
 
 const char* ocp_status_string(ocp_status st) {
@@ -888,9 +889,41 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   if (!h || !s || !dL_dx || !out) return OCP_E_ARG;
   if (!h->solved) return OCP_E_ORDER;
   if (!(s->adj_sigma > 0) || !(s->adj_rho > 0) || !(s->eps_active > 0) || !(s->adj_tol > 0) ||
-      s->refine_sweeps < 1)
+      s->refine_sweeps < 1 || s->adj_mode < OCP_ADJ_LAST_QP || s->adj_mode > OCP_ADJ_SQP_EXACT)
     return OCP_E_ARG;
   hipStream_t st = (hipStream_t)stream;
+  const bool at_iterate = h->d.model == OCP_MODEL_BICYCLE && s->adj_mode != OCP_ADJ_LAST_QP;
+  if (at_iterate) {
+    // differentiate the SQP solution: the QP convexified at the iterate, its
+    // state set to the iterate, and for OCP_ADJ_SQP_EXACT the Hessian of the
+    // Lagrangian in D_t, E_t
+    const BikeArgs ba = make_bike(h, s);
+    const Layout L0 = make_layout(h);
+    const unsigned gs = (unsigned)((std::max<int64_t>(h->S, h->B) + 255) / 256);
+    const int integ = ba.integ;
+    timed(&h->prof, OCP_K_SQP, st, [&] {
+      if (h->mixed)
+        hipLaunchKernelGGL((integ ? bike_linearize_kernel<float, 1> : bike_linearize_kernel<float, 0>), dim3(gs),
+                           dim3(256), 0, st, L0, ba);
+      else
+        hipLaunchKernelGGL((integ ? bike_linearize_kernel<double, 1> : bike_linearize_kernel<double, 0>), dim3(gs),
+                           dim3(256), 0, st, L0, ba);
+      const unsigned gv = (unsigned)((h->S * ROW + 255) / 256);
+      if (h->mixed)
+        hipLaunchKernelGGL(iterate_slacks_kernel<float>, dim3(gv), dim3(256), 0, st, (const double*)h->xibar,
+                           (float*)h->xi, h->S);
+      else
+        hipLaunchKernelGGL(iterate_slacks_kernel<double>, dim3(gv), dim3(256), 0, st, (const double*)h->xibar,
+                           (double*)h->xi, h->S);
+      if (s->adj_mode == OCP_ADJ_SQP_EXACT) {
+        Layout LE = L0;
+        LE.E = h->E;
+        hipLaunchKernelGGL((integ ? bike_hessian_kernel<1> : bike_hessian_kernel<0>), dim3(gs), dim3(256), 0, st,
+                           LE, ba);
+      }
+    });
+    h->has_E = s->adj_mode == OCP_ADJ_SQP_EXACT;
+  }
   AdjArgs a{};
   a.dLdx = dL_dx;
   a.dLdxi = dL_dxi;
@@ -932,6 +965,20 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
     h->entry->p32()->adj[var](L, a, st, &h->prof);
   else
     h->entry->p64()->adj[var](L, a, st, &h->prof);
+  if (at_iterate) h->has_E = false;  // the SQP's own QPs carry no cross-stage Hessian blocks
+  return hip_ok(hipGetLastError());
+}
+
+ocp_status ocp_set_iterate(ocp_handle h, const double* x, const double* xi, const double* y_f, const double* y_g,
+                           void* stream) {
+  if (!h || !x || !xi || !y_f || !y_g) return OCP_E_ARG;
+  if (h->d.model != OCP_MODEL_BICYCLE) return OCP_E_UNSUPPORTED;
+  if (!h->data_set) return OCP_E_ORDER;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(load_iterate_kernel, dim3((unsigned)((h->S * ROW + 255) / 256)), dim3(256), 0, st, x, xi, y_f,
+                     y_g, (const int64_t*)h->stage_off, (const int32_t*)h->stage_inst, h->S, h->n, h->d.nx, h->d.ng,
+                     h->xbar, h->xibar, h->yfbar, h->ygbar);
+  h->solved = true;  // the adjoint may differentiate at this iterate
   return hip_ok(hipGetLastError());
 }
 

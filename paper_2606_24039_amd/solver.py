@@ -85,14 +85,16 @@ class OCPSolver:
         self._keep = list(t.values()) + [st]
         torch.cuda.current_stream().synchronize()
 
-    def set_bicycle(self, batch):
+    def set_bicycle(self, batch, x0=None, ref=None, Qd=None, Rd=None, Qfd=None):
+        """Load a workloads.BicycleBatch; x0 [B,4], ref [S,4] and the weight
+        diagonals Qd [4], Rd [2], Qfd [4] override the batch's when given."""
         self.generation += 1
-        """Load a workloads.BicycleBatch."""
-        t = [_dev(batch.ref), _dev(batch.normal), _dev(batch.x0)]
+        t = [_dev(batch.ref if ref is None else ref), _dev(batch.normal), _dev(batch.x0 if x0 is None else x0)]
+        w = lambda v, dflt: [float(e) for e in (dflt if v is None else v)]  # noqa: E731
         p = A.ocp_bicycle(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(), batch.dt, batch.wheelbase,
                           batch.a_bound, batch.steer_bound, batch.lat_bound, batch.gamma_l1,
-                          (C.c_double * 4)(*batch.Qd), (C.c_double * 2)(*batch.Rd), (C.c_double * 4)(*batch.Qfd),
-                          int(getattr(batch, "integrator", 0)))
+                          (C.c_double * 4)(*w(Qd, batch.Qd)), (C.c_double * 2)(*w(Rd, batch.Rd)),
+                          (C.c_double * 4)(*w(Qfd, batch.Qfd)), int(getattr(batch, "integrator", 0)))
         A.check(self.lib.ocp_set_bicycle(self.h, C.byref(p), _stream()), "ocp_set_bicycle")
         self._keep = t
         torch.cuda.current_stream().synchronize()
@@ -213,6 +215,14 @@ class OCPSolver:
         (ocp_set_scaling_box).  Load the problem again afterwards."""
         self.generation += 1
         A.check(self.lib.ocp_set_scaling_box(self.h, float(p)), "ocp_set_scaling_box")
+
+    def set_iterate(self, x, xi, y_f, y_g):
+        """Restore a checkpointed SQP iterate (ocp_set_iterate), in the layout
+        of the solution buffers."""
+        t = [_dev(v) for v in (x, xi, y_f, y_g)]
+        A.check(self.lib.ocp_set_iterate(self.h, *[C.c_void_p(v.data_ptr()) for v in t], _stream()),
+                "ocp_set_iterate")
+        torch.cuda.current_stream().synchronize()
 
     def set_segmented_after(self, iteration: int):
         """Instances still running at ADMM iteration `iteration` take the
