@@ -35,19 +35,36 @@ SCALE_P = 0.6  # exponent of the box normalisation (ocp_set_scaling_box) on the 
 # (workload, precision, hash of the kernel sources): a changed kernel reports
 # null until it is profiled again.  Summary and commands:
 # profiles/admm_solve_wave_lti1024_n50.md.
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {
+    # FETCH_SIZE 17,221,750 KiB x 1.99994 + WRITE_SIZE 1,970,336 KiB x 1.000
+    ("c2", "mixed", "22b3f3cefd50c467"): 37_286_624_469,
+}
 
 
 def kernel_source_hash() -> str:
-    """sha256 (16 hex digits) over the HIP sources of the library."""
+    """sha256 (16 hex digits) over the sources the kernels are compiled from:
+    csrc/inst.hip and every header it includes, transitively (the host code
+    and the SQP-only kernels do not enter it)."""
     import hashlib
+    import re
 
+    dirs = [os.path.join(ROOT, "paper_2606_24039_amd", "csrc"), os.path.join(ROOT, "include")]
+    seen, todo = [], ["inst.hip"]
+    while todo:
+        name = todo.pop()
+        if name in seen:
+            continue
+        path = next((os.path.join(d, name) for d in dirs if os.path.exists(os.path.join(d, name))), None)
+        if path is None:
+            continue  # a system header
+        seen.append(name)
+        with open(path, encoding="utf-8") as f:
+            todo += re.findall(r'^\s*#\s*include\s+"([^"]+)"', f.read(), re.M)
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2606_24039_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in sorted(seen):
+        path = next(os.path.join(d, name) for d in dirs if os.path.exists(os.path.join(d, name)))
+        with open(path, "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
@@ -290,7 +307,8 @@ def bench_bicycle(args):
            "data": "synthetic",
            "config": {"workload": desc, "batch": int(batch.batch), "stages": int(np.sum(batch.horizons + 1)),
                       "nx": 4, "nu": 2, "ng": 3, "grad": not args.no_grad,
-                      "parallelism": "single GPU, one wavefront per instance"},
+                      "parallelism": "single GPU; one wavefront per instance, one 8-wavefront workgroup per "
+                                     "instance with N >= 255"},
            "kernel_ms_per_step": mixed["kernel_ms_per_step"], "sqp_kkt_max": mixed["sqp_kkt_max"],
            "roofline": None, "cpu_baseline": None}
     if not args.no_fp64:

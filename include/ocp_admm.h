@@ -341,6 +341,19 @@ ocp_status ocp_graph_launch(ocp_handle h, void* stream);
  * OCP_E_ARG (null handle). */
 ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n);
 
+/* Multi-wavefront instances (Sec. "Scalability to longer planning
+ * horizons"): an instance with horizon N >= mw_min_n is solved by one
+ * workgroup of W wavefronts (W = 8 for stage width n <= 8, else 4) instead
+ * of one wavefront.  Its chunked factorisation runs 4 W + 1 chunks and its
+ * segmented substitutions 4 W segments, one per 16-lane row of the
+ * workgroup, so their serial depth is about 2 / (4 W) of the horizon;
+ * wavefront 0 keeps the schedule (convergence checks, rho adaptation)
+ * described at ocp_solve.  Results agree with the one-wavefront shapes up to
+ * rounding.  Default 255 (horizons of 256 stages and more); 0 turns it off.
+ * Drops a captured graph.  Errors: OCP_E_ARG (null handle, or 0 < mw_min_n
+ * < 16 W - 1: segments of fewer than four stages), OCP_E_HIP. */
+ocp_status ocp_set_multiwave(ocp_handle h, int32_t mw_min_n);
+
 /* Problem rescaling (Remark 4: states and controls normalised inside the
  * solver, transparently to the caller).  Per instance b: variable factors
  * d [B,n] (x_t = d * xh_t at every stage), inequality-row factors e_g [B,ng]

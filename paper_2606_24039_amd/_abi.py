@@ -92,6 +92,7 @@ SIGNATURES = [
                                     C.POINTER(ocp_qp_grads), C.c_void_p]),
     ("ocp_graph_launch", C.c_int, [C.c_void_p, C.c_void_p]),
     ("ocp_set_segmented", C.c_int, [C.c_void_p, C.c_int32]),
+    ("ocp_set_multiwave", C.c_int, [C.c_void_p, C.c_int32]),
     ("ocp_set_segmented_after", C.c_int, [C.c_void_p, C.c_int32]),
     ("ocp_set_iterate", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ocp_autotune", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_int32, C.c_void_p, C.POINTER(C.c_int32),

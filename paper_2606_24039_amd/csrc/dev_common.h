@@ -199,6 +199,12 @@ struct Layout {
   void* SegX;
   // chunked factorisation: per instance [FX_SLOTS][n][n] FP64 exchange blocks
   double* FacX;
+  // instances solved by a multi-wavefront workgroup (horizon N >= mw_min_n):
+  // their list [n_mw] and per list slot the chunked factorisation's exchange
+  // blocks of the workgroup's rows
+  const int32_t* mw_list;
+  int n_mw, mw_min_n;
+  double* FacXmw;
   // structure of time-invariant LTI data: G rows are unit selectors
   int8_t gsel[16];  // variable selected by inequality row r
   int8_t ginv[16];  // inequality row selecting variable i, or -1
@@ -265,6 +271,7 @@ __device__ __forceinline__ Layout uni(const Layout& L) {
   u.Linv64 = uni(L.Linv64), u.M64 = uni(L.M64);
   u.SubA = uni(L.SubA), u.SubB = uni(L.SubB), u.ChF = uni(L.ChF), u.ChB = uni(L.ChB);
   u.SegT = uni(L.SegT), u.SegU = uni(L.SegU), u.SegX = uni(L.SegX), u.FacX = uni(L.FacX);
+  u.mw_list = uni(L.mw_list), u.n_mw = uni(L.n_mw), u.mw_min_n = uni(L.mw_min_n), u.FacXmw = uni(L.FacXmw);
   u.x = uni(L.x), u.v = uni(L.v), u.yf = uni(L.yf), u.zg = uni(L.zg), u.yg = uni(L.yg), u.xi = uni(L.xi);
   u.rho = uni(L.rho), u.status = uni(L.status), u.iters = uni(L.iters), u.nfact = uni(L.nfact);
   u.rprim = uni(L.rprim), u.rdual = uni(L.rdual);

@@ -80,15 +80,23 @@ void timed(Prof* p, int c, hipStream_t st, F&& f) {
 using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, hipStream_t, Prof*);
 using AdjFn = void (*)(const Layout&, const AdjArgs&, hipStream_t, Prof*);
 
-// One ADMM solve: per-solve initialisation, then one wavefront per instance
-// runs the whole of Algorithm 3 (factorisation, iterations, FP64 checks, rho
-// adaptation and refactorisation) without waiting for other instances.
+// One ADMM solve: per-solve initialisation, then one workgroup of
+// mw_waves() wavefronts per long instance (N >= L.mw_min_n) and one
+// wavefront per other instance run the whole of Algorithm 3 (factorisation,
+// iterations, FP64 checks, rho adaptation and refactorisation) without
+// waiting for other instances.
 template <typename T, int NX, int NU, int NG, typename ST>
 void launch_solve(const Layout& L, const Settings& s, int32_t* need, hipStream_t st, Prof* pf) {
   timed(pf, OCP_K_OTHER, st,
         [&] { hipLaunchKernelGGL((admm_init_kernel<T>), dim3(L.init_blocks), dim3(256), 0, st, L, s, need); });
-  timed(pf, OCP_K_SOLVE, st,
-        [&] { hipLaunchKernelGGL((admm_solve_wave_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, s); });
+  if (L.n_mw > 0)
+    timed(pf, OCP_K_SOLVE, st, [&] {
+      hipLaunchKernelGGL((admm_solve_mw_kernel<T, NX, NU, NG, ST>), dim3(L.n_mw), dim3(64 * mw_waves<NX + NU>()), 0,
+                         st, L, s);
+    });
+  if (L.n_mw < L.B)
+    timed(pf, OCP_K_SOLVE, st,
+          [&] { hipLaunchKernelGGL((admm_solve_wave_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, s); });
 }
 
 // one instance per wavefront

@@ -361,14 +361,16 @@ __device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, d
 
 // ---------------------------------------------------------------------------
 // Chunked factorisation of long horizons (same outputs as factor_instance up
-// to rounding, two fifths of its serial depth).
+// to rounding, 2 / (R + 1) of its serial depth with R 16-lane rows).
 //
 // The recurrence above carries one n x n state from stage to stage: what
 // enters stage t is M_t (S_t = Theta_t - M_t M_t').  The horizon is cut into
-// five contiguous chunks c = 0..4, chunk c covering stages a_c .. b_c.
+// R + 1 contiguous chunks c = 0..R, chunk c covering stages a_c .. b_c (R = 4:
+// the four rows of one wavefront; R = 4 W: the rows of a W-wavefront
+// workgroup, all of which call this function).
 //
 // Phase 1, one chunk per 16-lane row: row 0 factors chunk 0 exactly and
-// stores its blocks.  Row c = 1..3 summarises chunk c as a function of its
+// stores its blocks.  Row c = 1..R-1 summarises chunk c as a function of its
 // entering state.  With T the block-tridiagonal matrix of the chunk's
 // interior a_c .. b_c - 1 (no entering term), factored by the same recurrence
 // started from M = 0 (T = L0 L0'), the entering state Z = M M' (M = M_{a_c})
@@ -380,32 +382,39 @@ __device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, d
 // block as U_a = L0_a^{-1}, U_t = -W0_t U_{t-1} (W0_t = L0_t^{-1} M0_t), these
 // are K_aa = sum_t U_t' U_t and K_ba = M0_b U_{b-1}.  I - M' K_aa M is SPD
 // because T - E Z E' is (a Schur complement of the SPD Schur matrix).
-// Phase 2, on every row, serially over c = 1..3: from M_{a_1} (row 0's exit)
-// the summaries give M_{a_2}, M_{a_3}, M_{a_4}, and L_{b_c}^{-1}, which the
+// Phase 2, on every row, serially over c = 1..R-1: from M_{a_1} (row 0's
+// exit) the summaries give M_{a_2} .. M_{a_R}, and L_{b_c}^{-1}, which the
 // first stage of the next chunk needs for its V block.
-// Phase 3, one chunk per row: rows 1..3 re-run chunks 1..3 and row 0 runs
-// chunk 4, each from its true entering state, storing their blocks.  Every
+// Phase 3, one chunk per row: rows 1..R-1 re-run chunks 1..R-1 and row 0 runs
+// chunk R, each from its true entering state, storing their blocks.  Every
 // row forms and stores all n columns of its outputs.
 //
-// Scratch: L.FacX, [B][FX_SLOTS][n][n] FP64 per instance.
+// Scratch: fx_slots(R) FP64 n x n exchange blocks per instance (L.FacX for
+// R = 4, [B][FX_SLOTS][n][n]).
 // ---------------------------------------------------------------------------
 struct FacChunk {
   int a, len;  // first stage and stage count
 };
+template <int R = 4>
 __device__ __forceinline__ FacChunk fac_chunk(int c, int N) {
-  const int S = N + 1, base = S / 5, rem = S % 5;
+  const int S = N + 1, base = S / (R + 1), rem = S % (R + 1);
   return FacChunk{c * base + min(c, rem), base + (c < rem ? 1 : 0)};
 }
-// shortest horizon factored in chunks (every chunk then holds at least three
-// stages, so every summarised chunk has an interior)
+// shortest horizon factored in chunks by one wavefront (every chunk then
+// holds at least three stages, so every summarised chunk has an interior);
+// R rows need N + 1 >= 3 (R + 1)
 constexpr int FAC_CHUNK_MIN_N = 15;
-// FacX slots: M_{a_1} and L_{b_0}^{-1} from row 0; per summarised chunk
-// c = 1..3 the four blocks S0_b, K_aa, K_ba, Phi_b at FX_SUM + 4 (c - 1)
-enum { FX_M1 = 0, FX_X0 = 1, FX_SUM = 2, FX_SLOTS = 14 };
+__host__ __device__ constexpr int fac_chunk_min_n(int R) { return 3 * (R + 1) - 1; }
+// exchange slots: M_{a_1} and L_{b_0}^{-1} from row 0; per summarised chunk
+// c = 1..R-1 the four blocks S0_b, K_aa, K_ba, Phi_b at FX_SUM + 4 (c - 1)
+enum { FX_M1 = 0, FX_X0 = 1, FX_SUM = 2 };
+__host__ __device__ constexpr int fx_slots(int R) { return FX_SUM + 4 * (R - 1); }
+constexpr int FX_SLOTS = fx_slots(4);
 
-template <typename T, int NX, int NU, int NG, bool HOIST, int FORM, int TAG = 0>
+template <typename T, int NX, int NU, int NG, bool HOIST, int FORM, int TAG = 0, int NR = 4>
 __device__ __noinline__ int factor_chunked(const Layout& Lm, const Group& gm, double sigma_, double rho_f_,
-                                           double rho_g_, const double* __restrict__ rhog_rows_) {
+                                           double rho_g_, const double* __restrict__ rhog_rows_,
+                                           double* FX_ = nullptr) {
   const Layout L = uni(Lm);
   const Group g{gm.lane, uni(gm.b), uni(gm.s0), uni(gm.N)};
   const double sigma = uni(sigma_), rho_f = uni(rho_f_), rho_g = uni(rho_g_);
@@ -419,7 +428,8 @@ __device__ __noinline__ int factor_chunked(const Layout& Lm, const Group& gm, do
   const int ic = vi ? i : n - 1;
   const int N = g.N;
   const size_t nn = (size_t)n * n;
-  double* const FX = L.FacX + (size_t)g.b * FX_SLOTS * nn;
+  // exchange blocks: the caller's (multi-wavefront instances), else the instance's slots of L.FacX
+  double* const FX = FX_ ? uni(FX_) : L.FacX + (size_t)g.b * FX_SLOTS * nn;
 
   // rho-independent products (row i), formed once when the blocks do not vary
   double PAm[HOIST ? n : 1], PAp[HOIST ? n : 1], PG[HOIST ? n : 1], PPhi[HOIST ? n : 1];
@@ -662,14 +672,14 @@ __device__ __noinline__ int factor_chunked(const Layout& Lm, const Group& gm, do
     UT[j] = (i == j) ? 1.0 : 0.0;
     Kaa[j] = 0.0;
   }
-  sweep(std::true_type{}, fac_chunk(q, N), q == 0, fac_chunk(0, N).len);
+  sweep(std::true_type{}, fac_chunk<NR>(q, N), q == 0, fac_chunk<NR>(0, N).len);
   if (q == 0) {
     store_row(FX_M1, Mrow);
     store_row(FX_X0, Xprev);
   }
-  __syncthreads();
+  __syncthreads();  // every wavefront of the caller's workgroup
 
-  // phase 2: entering states of chunks 2, 3, 4 (every row computes them all)
+  // phase 2: entering states of chunks 2..R (every row computes them all)
   double M[n], Xb[n];
   load_row<n>(M, FX + FX_M1 * nn + (size_t)ic * n, true);
   load_row<n>(Xb, FX + FX_X0 * nn + (size_t)ic * n, true);
@@ -678,7 +688,7 @@ __device__ __noinline__ int factor_chunked(const Layout& Lm, const Group& gm, do
     Mrow[j] = M[j];
     Xprev[j] = Xb[j];
   }
-  for (int c = 1; c <= 3; ++c) {
+  for (int c = 1; c <= NR - 1; ++c) {
     double S0[n], Ka[n], Kb[n], Ph[n];
     const size_t base = (size_t)(FX_SUM + 4 * (c - 1)) * nn + (size_t)ic * n;
     load_row<n>(S0, FX + base, true);
@@ -717,7 +727,7 @@ __device__ __noinline__ int factor_chunked(const Layout& Lm, const Group& gm, do
 #pragma unroll
     for (int j = 0; j < n; ++j) M[j] = 0.0;
     cross_row<n, n>(Ph, Xb, M, 1.0);
-    const bool take = (q == c + 1) || (c == 3 && q == 0);
+    const bool take = (q == c + 1) || (c == NR - 1 && q == 0);
     if (take) {
 #pragma unroll
       for (int j = 0; j < n; ++j) {
@@ -728,7 +738,7 @@ __device__ __noinline__ int factor_chunked(const Layout& Lm, const Group& gm, do
   }
 
   // phase 3
-  sweep(std::false_type{}, fac_chunk(q == 0 ? 4 : q, N), true, fac_chunk(1, N).len);
+  sweep(std::false_type{}, fac_chunk<NR>(q == 0 ? NR : q, N), true, fac_chunk<NR>(1, N).len);
   return __ballot(bad != 0) != 0ull ? 1 : 0;
 }
 

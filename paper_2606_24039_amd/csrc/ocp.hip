@@ -78,6 +78,15 @@ struct ocp_handle_s {
   void *SubA = nullptr, *SubB = nullptr, *ChF = nullptr, *ChB = nullptr;
   void *SegT = nullptr, *SegU = nullptr, *SegX = nullptr;
   double* FacX = nullptr;
+  // multi-wavefront instances: N >= mw_min_n (0: none), their device list,
+  // the exchange blocks of their chunked factorisation (mw_cap slots: the
+  // instances at or above the smallest admissible threshold)
+  int mw_min_n = MW_MIN_N;
+  int n_mw = 0, mw_cap = 0;
+  bool mw_off = false;  // no multi-wavefront workgroups (workspace carved by ocp_solve_noalloc)
+  int32_t* mw_list = nullptr;
+  double* FacXmw = nullptr;
+  std::vector<int32_t> horizons_host;
   int variant = 0;
   int seg_min_n = SEG_MIN_N;  // launch shape: horizons from which the substitutions run segmented
   int seg_after = INT32_MAX;  // iteration from which every running instance does (the batch's tail)
@@ -157,6 +166,23 @@ ocp_status check_dims(const ocp_dims* d, const int32_t* horizons) {
   return OCP_OK;
 }
 
+// the list of multi-wavefront instances for the current threshold (longest
+// first), host -> device
+ocp_status upload_mw_list(ocp_handle h) {
+  h->n_mw = 0;
+  if (h->mw_off || h->mw_min_n <= 0 || h->mw_cap == 0) return OCP_OK;
+  std::vector<int32_t> lst;
+  for (int b = 0; b < h->B; ++b)
+    if (h->horizons_host[(size_t)b] >= h->mw_min_n) lst.push_back(b);
+  std::stable_sort(lst.begin(), lst.end(),
+                   [&](int a, int c) { return h->horizons_host[(size_t)a] > h->horizons_host[(size_t)c]; });
+  if (lst.empty()) return OCP_OK;
+  if (hipMemcpy(h->mw_list, lst.data(), sizeof(int32_t) * lst.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return OCP_E_HIP;
+  h->n_mw = (int)lst.size();
+  return OCP_OK;
+}
+
 // allocate (or only count) the workspace
 ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool count_only) {
   h->d = *d;
@@ -223,6 +249,14 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   A_(h->SegU, ts * nn * 4 * (size_t)B);
   A_(h->SegX, ts * ROW * 8 * (size_t)B);
   A_(h->FacX, sizeof(double) * nn * FX_SLOTS * (size_t)B);
+  {
+    const int W = mw_waves_of(n);
+    h->mw_cap = 0;
+    if (!h->mw_off)
+      for (int b = 0; b < B; ++b) h->mw_cap += horizons[b] >= mw_floor_n(W) ? 1 : 0;
+    A_(h->mw_list, sizeof(int32_t) * (size_t)B);
+    if (h->mw_cap > 0) A_(h->FacXmw, sizeof(double) * nn * fx_slots(4 * W) * (size_t)h->mw_cap);
+  }
   A_(h->x, ts * ROW * SP);
   A_(h->v, ts * ROW * SP);
   A_(h->yf, ts * ROW * SP);
@@ -290,6 +324,11 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
     for (int k = 0; k < 14; ++k)
       if (*padded[k]) *padded[k] = (char*)*padded[k] + stage_bytes[k] * STAGE_PAD;
     return OCP_OK;
+  }
+  h->horizons_host.assign(horizons, horizons + B);
+  {
+    const ocp_status ms = upload_mw_list(h);
+    if (ms != OCP_OK) return ms;
   }
   // stage offsets and longest-first processing order (host -> device, once)
   std::vector<int64_t> off(B + 1, 0);
@@ -394,6 +433,10 @@ Layout make_layout(ocp_handle h) {
   L.SegU = h->SegU;
   L.SegX = h->SegX;
   L.FacX = h->FacX;
+  L.mw_list = h->mw_list;
+  L.n_mw = h->n_mw;
+  L.mw_min_n = h->mw_min_n;
+  L.FacXmw = h->FacXmw;
   for (int k = 0; k < 16; ++k) {
     L.gsel[k] = h->gsel[k];
     L.ginv[k] = h->ginv[k];
@@ -1048,6 +1091,15 @@ ocp_status ocp_graph_launch(ocp_handle h, void* stream) {
   return OCP_OK;
 }
 
+ocp_status ocp_set_multiwave(ocp_handle h, int32_t mw_min_n) {
+  if (!h) return OCP_E_ARG;
+  const int floor_n = mw_floor_n(mw_waves_of(h->n));
+  if (mw_min_n > 0 && mw_min_n < floor_n) return OCP_E_ARG;
+  drop_graph(h);  // a captured graph keeps the launch shape it was recorded with
+  h->mw_min_n = mw_min_n > 0 ? mw_min_n : 0;
+  return upload_mw_list(h);
+}
+
 ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n) {
   if (!h) return OCP_E_ARG;
   if (h->graph_exec) {  // a captured graph keeps the launch shape it was recorded with
@@ -1164,6 +1216,7 @@ ocp_status ocp_solve_noalloc(const ocp_dims* d, const int32_t* horizons, const v
   hipStream_t hs = (hipStream_t)stream;
   // host bookkeeping lives on the stack for this call (its vectors stay empty)
   ocp_handle_s h;
+  h.mw_off = true;  // one wavefront per instance: no per-workgroup exchange blocks in the scratch
   st = build(&h, d, horizons, true);
   if (st != OCP_OK) return st;
   const size_t ws = h.bytes;
@@ -1174,6 +1227,7 @@ ocp_status ocp_solve_noalloc(const ocp_dims* d, const int32_t* horizons, const v
   if (st != OCP_OK) return st;
   h = ocp_handle_s();
   h.carve = base;
+  h.mw_off = true;
   st = build(&h, d, horizons, false);
   if (st != OCP_OK) return st;
   // the scratch keeps the previous call's contents: clear the workspace (the

@@ -108,6 +108,13 @@ __device__ __forceinline__ void ldo_n(T (&d)[K], gptr<const T> base, uint32_t of
   }
 }
 
+template <int K, typename T>
+__device__ __forceinline__ void ldo_n(T (&d)[K], lptr<const T> base, uint32_t off) {
+  const lptr<const T> p = (lptr<const T>)((lptr<const char>)base + off);
+#pragma unroll
+  for (int k = 0; k < K; ++k) d[k] = p[k];
+}
+
 // Uniform base pointers of one instance.
 template <typename T, int NX, int NU, int NG, bool LV = false>
 struct IterPtrs {
@@ -618,44 +625,47 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST, 
 }
 
 // ---------------------------------------------------------------------------
-// Segmented substitutions.  The horizon is cut into four contiguous
-// quarters, quarter q on row q.  A chain over a quarter from a zero start
-// gives a particular solution; the true value at the quarter's end differs by
-// the quarter's transfer block applied to the value entering it:
+// Segmented substitutions.  The horizon is cut into R contiguous segments,
+// segment q on 16-lane row q (R = 4: the rows of one wavefront; R = 4 W: the
+// rows of a W-wavefront workgroup).  A chain over a segment from a zero start
+// gives a particular solution; the true value at the segment's end differs by
+// the segment's transfer block applied to the value entering it:
 //   forward   v_b = p_b + T_q v_{a-1},   T_q = (-B_b) ... (-B_a),  B = ChF
 //   backward  x_a = p_a + U_q x_{b+1},   U_q = (-B_a) ... (-B_b),  B = ChB
-// (quarter q covers stages a..b).  One iteration: every row runs its
-// quarter's forward chain from zero (with the eta_t / r_t work of each stage),
-// a short serial pass over the four quarter ends finds each quarter's true
-// entering value, every row re-runs its quarter from that value (with the
-// SubB_t product), and the same for the backward chain (with the constraint
-// updates of each stage).  Serial depth per chain: two quarter lengths plus
-// three block products, in place of the whole horizon.  T_q and U_q depend
+// (segment q covers stages a..b).  One iteration: every row runs its
+// segment's forward chain from zero (with the eta_t / r_t work of each stage),
+// a serial pass over the R segment ends finds each segment's true entering
+// value, every row re-runs its segment from that value (with the SubB_t
+// product), and the same for the backward chain (with the constraint updates
+// of each stage).  Serial depth per chain: two segment lengths plus up to
+// R - 1 block products, in place of the whole horizon.  T_q and U_q depend
 // only on the factorisation and are formed after it by pushing the identity
-// through each quarter's chain (prepare_segments).
+// through each segment's chain (prepare_segments).
 // ---------------------------------------------------------------------------
 constexpr int SEG_MIN_N = 128;  // default switch: shorter horizons keep the interleaved iteration
 constexpr int SEG_FLOOR_N = 15;  // segments of at least four stages
 
 struct SegRange {
-  int a, len;  // first stage and stage count of this row's quarter
+  int a, len;  // first stage and stage count of this row's segment
 };
+template <int R = 4>
 __device__ __forceinline__ SegRange seg_range(int q, int N) {
-  const int S = N + 1, base = S / 4, rem = S % 4;
+  const int S = N + 1, base = S / R, rem = S % R;
   return SegRange{q * base + min(q, rem), base + (q < rem ? 1 : 0)};
 }
 
-// T_q and U_q of every quarter of one instance (all rows; row q forms its own
-// quarter's blocks): lane i keeps row i of the running product in H[0..n).
-template <typename T, int NX, int NU, int NG>
-__device__ __noinline__ void prepare_segments(const Layout& Lm, int b_, int64_t s0_, int N_) {
+// T_q and U_q of every segment of one instance (all rows; row q forms its own
+// segment's blocks into Tout / Uout + q n n): lane i keeps row i of the
+// running product in H[0..n).
+template <typename T, int NX, int NU, int NG, int R = 4, typename OP = T*>
+__device__ __noinline__ void prepare_segments(const Layout& Lm, int b_, int64_t s0_, int N_, OP Tout, OP Uout) {
   constexpr int n = NX + NU;
   const Layout L = uni(Lm);
-  const int b = uni(b_), N = uni(N_);
+  const int N = uni(N_);
   const int64_t s0 = uni(s0_);
   const int i = threadIdx.x & (ROW - 1), q = threadIdx.x >> 4;
   const int ir = i < n ? i : n - 1;
-  const SegRange sg = seg_range(q, N);
+  const SegRange sg = seg_range<R>(q, N);
   const int64_t nn = (int64_t)n * n;
   const uint32_t orow = (uint32_t)(ir * n * (int)sizeof(T));
   for (int dir = 0; dir < 2; ++dir) {
@@ -674,48 +684,46 @@ __device__ __noinline__ void prepare_segments(const Layout& Lm, int b_, int64_t 
       for (int j = 0; j < n; ++j) H[j] = Hn[j];
     }
     if (i < n) {
-      T* out = (T*)(dir == 0 ? L.SegT : L.SegU) + ((int64_t)b * 4 + q) * nn + (int64_t)i * n;
+      const OP out = (dir == 0 ? Tout : Uout) + q * nn + i * n;
 #pragma unroll
       for (int j = 0; j < n; ++j) out[j] = H[j];
     }
   }
+  (void)b_;
 }
 
-// The serial pass over the quarter ends.  Every row stores its particular
-// value pe (lane i: entry i) into slot `dir * 4 + q`, then every row forms the
-// true values in sweep order and returns the value entering its own quarter.
-// dir 0 (forward): v_0 = pe_0, v_q = pe_q + T_q v_{q-1}; row q gets v_{q-1}
-// (zero on row 0).  dir 1 (backward): x_3 = pe_3, x_q = pe_q + U_q x_{q+1};
-// row q gets x_{q+1} (zero on row 3).
-template <typename T, int n>
-__device__ __forceinline__ T seg_link(T pe, int dir, gptr<T> X, gptr<const T> TU, int q, int i) {
+// The serial pass over the segment ends.  Every row stores its particular
+// value pe (lane i: entry i) into slot `dir * R + q`, then forms the true
+// values in sweep order as far as its wavefront's rows need them and returns
+// the value entering its own segment.  dir 0 (forward): v_0 = pe_0, v_k =
+// pe_k + T_k v_{k-1}; row q gets v_{q-1} (zero on row 0).  dir 1 (backward):
+// x_{R-1} = pe_{R-1}, x_k = pe_k + U_k x_{k+1}; row q gets x_{q+1} (zero on
+// row R - 1).  X: [2 R][ROW] slots; TU: the R transfer blocks of the sweep.
+template <typename T, int n, int R, typename XP, typename TP>
+__device__ __forceinline__ T seg_link(T pe, int dir, XP X, TP TU, int q, int i) {
   const int ir = i < n ? i : n - 1;
   const uint32_t ol = (uint32_t)(i * (int)sizeof(T));
-  sto(X + (dir * 4 + q) * ROW, ol, pe);
-  wave_sync();
-  T p[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) p[k] = ldo(X + (dir * 4 + k) * ROW, ol);
+  sto(X + (dir * R + q) * ROW, ol, pe);
+  __syncthreads();  // every row of the workgroup has stored its end value
   const uint32_t orow = (uint32_t)(ir * n * (int)sizeof(T));
+  const int q_lo = (int)(threadIdx.x >> 6) * 4, q_hi = q_lo + 3;  // this wavefront's rows
   T in = T(0);
   if (dir == 0) {
-    T v = p[0];  // true end value of quarter 0
+    T v = ldo(X + 0 * ROW, ol);  // true end value of segment 0
     in = (q == 1) ? v : in;
-#pragma unroll
-    for (int k = 1; k < 3; ++k) {
+    for (int k = 1; k < q_hi; ++k) {
       T Br[n];
       ldo_n<n>(Br, TU + k * n * n, orow);
-      v = dotb<n>(Br, v, p[k]);
+      v = dotb<n>(Br, v, ldo(X + k * ROW, ol));
       in = (q == k + 1) ? v : in;
     }
   } else {
-    T x = p[3];  // true start value of quarter 3
-    in = (q == 2) ? x : in;
-#pragma unroll
-    for (int k = 2; k > 0; --k) {
+    T x = ldo(X + (2 * R - 1) * ROW, ol);  // true start value of segment R - 1
+    in = (q == R - 2) ? x : in;
+    for (int k = R - 2; k > q_lo; --k) {
       T Br[n];
       ldo_n<n>(Br, TU + k * n * n, orow);
-      x = dotb<n>(Br, x, p[k]);
+      x = dotb<n>(Br, x, ldo(X + (R + k) * ROW, ol));
       in = (q == k - 1) ? x : in;
     }
   }
@@ -728,8 +736,16 @@ __device__ __forceinline__ T seg_link(T pe, int dir, gptr<T> X, gptr<const T> TU
 // FP64, overflow the register budget into scratch memory and run slower.
 // Loads reach at most SEG_AHEAD + 1 stages past either end of the horizon,
 // inside the STAGE_PAD padding stages.
-template <typename T, int n>
-constexpr int SEG_AHEAD = (sizeof(T) == 4 && n <= 8) ? 4 : 2;
+// Multi-wavefront workgroups (R > 4) run two wavefronts per SIMD, which
+// hide part of the load latency; their register budget (256) holds two steps
+// in flight (measured on one N = 8192 bicycle instance, FP32: 0.49 ms per
+// ADMM iteration with two, 0.50 with one; 16 wavefronts per workgroup with
+// one or none: 0.52).
+#ifndef OCP_MW_AHEAD
+#define OCP_MW_AHEAD 2
+#endif
+template <typename T, int n, int R = 4>
+constexpr int SEG_AHEAD = R > 4 ? OCP_MW_AHEAD : (sizeof(T) == 4 && n <= 8) ? 4 : 2;
 static_assert(SEG_AHEAD<float, 6> + 1 <= STAGE_PAD, "segmented prefetch beyond the padding stages");
 
 // inputs of one stage of the segmented forward sweep
@@ -741,9 +757,8 @@ struct SegFwdIn {
 
 // One ADMM iteration with segmented substitutions (see above).  X: the
 // instance's exchange slots; Tq / Uq: its transfer blocks.
-template <typename T, int NX, int NU, int NG, typename ST>
-__device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, ST>& c, gptr<T> X, gptr<const T> Tq,
-                                                   gptr<const T> Uq) {
+template <typename T, int NX, int NU, int NG, typename ST, int R, typename XP, typename TP>
+__device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, ST>& c, XP X, TP Tq, TP Uq) {
   constexpr int n = NX + NU;
   constexpr bool TI = ST::TI;
   constexpr int VS = ROW * (int)sizeof(T);
@@ -751,8 +766,8 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
   const auto& P = c.P;
   const int ir = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
   const T init = (i < NX) ? c.rho_f * c.xinit - c.yinit : T(0);
-  const SegRange sg = seg_range(q, N);
-  const int steps = (N + 4) / 4;  // the longest quarter
+  const SegRange sg = seg_range<R>(q, N);
+  const int steps = (N + R) / R;  // the longest segment
   // offsets of stage t on this lane (vector entry, factor row)
   auto ov = [&](int t) { return (uint32_t)(((STAGE_PAD + t) * ROW + i) * (int)sizeof(T)); };
   auto of = [&](int t) { return (uint32_t)(((STAGE_PAD + t) * n * n + ir * n) * (int)sizeof(T)); };
@@ -793,10 +808,10 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
       sto(P.v, ov(t), r);
       p = r - dotb<n>(d.Cr, p, T(0));  // p = 0 before the quarter's first stage
     };
-    seg_walk<SEG_AHEAD<T, n>, In>(steps, load, comp);
+    seg_walk<SEG_AHEAD<T, n, R>, In>(steps, load, comp);
     pe = p;
   }
-  const T vin = seg_link<T, n>(pe, 0, X, Tq, q, i);
+  const T vin = seg_link<T, n, R>(pe, 0, X, Tq, q, i);
 
   // ---- forward, true values from vin, then s_t = SubB_t v_t ----
   {
@@ -817,7 +832,7 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
       v = d.r - dotb<n>(d.Cr, v, T(0));
       sto(P.v, ov(t), dotb<n>(d.Br, v, T(0)));
     };
-    seg_walk<SEG_AHEAD<T, n>, In>(steps, load, comp);
+    seg_walk<SEG_AHEAD<T, n, R>, In>(steps, load, comp);
   }
   wave_sync();
 
@@ -837,10 +852,10 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
       if (k >= sg.len) return;
       p = d.s - dotb<n>(d.Cr, p, T(0));  // p = 0 past the quarter's last stage
     };
-    seg_walk<SEG_AHEAD<T, n>, In>(steps, load, comp);
+    seg_walk<SEG_AHEAD<T, n, R>, In>(steps, load, comp);
     pe = p;
   }
-  const T xin = seg_link<T, n>(pe, 1, X, Uq, q, i);
+  const T xin = seg_link<T, n, R>(pe, 1, X, Uq, q, i);
 
   // ---- backward, true values from xin, with the constraint-row updates ----
   {
@@ -880,7 +895,7 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
       if (t == 0 && i < NX) sto(P.yf, ov(N), c.yinit + c.rfa * (xt - c.xinit));
       xn = xt;
     };
-    seg_walk<SEG_AHEAD<T, n>, In>(steps, load, comp);
+    seg_walk<SEG_AHEAD<T, n, R>, In>(steps, load, comp);
   }
   wave_sync();
 }
@@ -1231,7 +1246,7 @@ __device__ __noinline__ Resid residuals_wave(const Layout& Lm, const WaveGroup& 
 // < -eps ||dy||_inf (Farkas).  Evaluated in the original variables of a
 // rescaled QP; a nonzero dy on a soft row fails it.  Stages spread over the
 // four rows as in the residuals; blocks read from the FP64 master data.
-template <typename T, int NX, int NU, int NG>
+template <typename T, int NX, int NU, int NG, int TAG = 0>
 __device__ __noinline__ int pinf_wave(const Layout& Lm, const WaveGroup& wm, double eps_) {
   const Layout L = uni(Lm);
   const int b = uni(wm.b), N = uni(wm.N);
@@ -1336,9 +1351,9 @@ __device__ __forceinline__ int boundary_decision(const Resid& R, const Settings&
 // schedule between two boundaries).  Not inlined: the loop gets the register
 // file to itself, the solve-level state of the caller stays out of it.
 // Returns the iteration count reached.
-template <typename T, int NX, int NU, int NG, typename ST, bool SEG>
+template <typename T, int NX, int NU, int NG, typename ST, bool SEG, int R = 4>
 __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, int b_, int64_t s0_, int N_, int k0_,
-                                        int nb_, double rho_bar_) {
+                                        int nb_, double rho_bar_, lptr<T> mw_ = nullptr) {
   const Layout L = uni(Lm);
   const int b = uni(b_), N = uni(N_), nb = uni(nb_);
   const int64_t s0 = uni(s0_);
@@ -1359,9 +1374,20 @@ __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, in
   const IterCtx<T, NX, NU, NG, ST> c{tb,   P,    T(uni(st.sigma)), rho_f, T(rho_bar), alpha, T(1) - alpha,
                                      rho_f * alpha, kind, pc, xinit, T(0), gsel, ginv, i, q, N, gid, hard};
   constexpr int64_t nn = (int64_t)(NX + NU) * (NX + NU);
-  const gptr<T> X = as_global((T*)L.SegX + (int64_t)b * 8 * ROW);
-  const gptr<const T> Tq = as_global((const T*)L.SegT + (int64_t)b * 4 * nn);
-  const gptr<const T> Uq = as_global((const T*)L.SegU + (int64_t)b * 4 * nn);
+  // exchange slots and transfer blocks: the instance's in global memory (one
+  // wavefront), or the workgroup's LDS ([R][nn] T, [R][nn] U, [2R][ROW] X)
+  const auto X = [&] {
+    if constexpr (R == 4) return as_global((T*)L.SegX + (int64_t)b * 8 * ROW);
+    else return mw_ + 2 * R * nn;
+  }();
+  const auto Tq = [&] {
+    if constexpr (R == 4) return as_global((const T*)L.SegT + (int64_t)b * 4 * nn);
+    else return (lptr<const T>)mw_;
+  }();
+  const auto Uq = [&] {
+    if constexpr (R == 4) return as_global((const T*)L.SegU + (int64_t)b * 4 * nn);
+    else return (lptr<const T>)(mw_ + R * nn);
+  }();
   // LDS of the interleaved iteration: FP32 horizons up to STATE_LDS_STAGES
   // keep all six stage vectors there for the segment (copied in here and out
   // before the boundary's residuals); longer ones, and FP64, the exchange
@@ -1407,7 +1433,7 @@ __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, in
     IterCtx<T, NX, NU, NG, ST> ck = c;
     ck.yinit = ldo(P.yf, o_yinit);  // initial-state multipliers (slot N)
     if constexpr (SEG)
-      wave_iteration_seg<T, NX, NU, NG, ST>(ck, X, Tq, Uq);
+      wave_iteration_seg<T, NX, NU, NG, ST, R>(ck, X, Tq, Uq);
     else if (xv_lds)
       wave_iteration<T, NX, NU, NG, ST>(ck, lo, XVl);
     else
@@ -1416,19 +1442,89 @@ __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, in
   return k;
 }
 
-// One complete ADMM solve per wavefront (Algorithm 3 with the stopping test
-// and rho adaptation): FP64 factorisation, iterations up to each boundary,
-// FP64 residuals and decisions at the boundary, refactorisation after an
-// accepted rho change.  Instances never wait for each other.
-template <typename T, int NX, int NU, int NG, typename ST>
-__global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings st) {
-  WaveGroup w;
-  if (!wave_group(L, w)) return;
-  if (L.status[w.b] != ST_RUNNING) return;
+// Multi-wavefront instances: one workgroup of W wavefronts per instance.
+// Wavefront 0 runs the schedule below (checks, rho decisions); the
+// factorisation, the transfer blocks and the iterations between two
+// boundaries are workgroup operations in which every 16-lane row of the W
+// wavefronts takes one chunk / segment (R = 4 W of them).  Wavefront 0 posts
+// each operation in LDS and meets the others at a barrier; the others loop
+// on posted operations until MW_EXIT.  Every operation ends with a barrier,
+// so between operations wavefront 0 alone runs, with wavefront-local syncs.
+enum { MW_EXIT = 0, MW_FACTOR = 1, MW_PREP = 2, MW_ITERS = 3 };
+struct MwCmd {
+  int op, k, nb;
+  double rho_bar;
+};
+// wavefronts per workgroup: 8 for stages up to 8 wide (32 rows; two
+// wavefronts per SIMD leave each 256 registers, which the segmented sweeps
+// need), 4 for wider stages (the LDS transfer blocks grow as n^2)
+#ifndef OCP_MW_WAVES
+#define OCP_MW_WAVES 8
+#endif
+__host__ __device__ constexpr int mw_waves_of(int n) { return n <= 8 ? OCP_MW_WAVES : 4; }
+template <int n>
+constexpr int mw_waves() { return mw_waves_of(n); }
+// shortest horizon taken by a W-wavefront workgroup: four stages per segment
+// (and at least three per factorisation chunk)
+__host__ __device__ constexpr int mw_floor_n(int W) { return 16 * W - 1; }
+static_assert(mw_floor_n(4) >= fac_chunk_min_n(16) && mw_floor_n(16) >= fac_chunk_min_n(64), "chunk floor");
+// default: horizons from 256 stages take a workgroup
+constexpr int MW_MIN_N = 255;
+
+__device__ __forceinline__ void wave_local_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One workgroup operation (all W wavefronts; ends with a barrier).  buf: the
+// LDS transfer blocks and exchange slots; FX: the chunked factorisation's
+// exchange blocks; bad: one flag per wavefront.
+template <typename T, int NX, int NU, int NG, typename ST, int W>
+__device__ __noinline__ void mw_op(const Layout& Lm, const Settings& st, int b_, int64_t s0_, int N_, MwCmd c,
+                                   lptr<T> buf, double* FX, lptr<int> bad) {
+  constexpr int R = 4 * W;
+  constexpr int nn = (NX + NU) * (NX + NU);
+  const int b = uni(b_), N = uni(N_), op = uni(c.op);
+  const int64_t s0 = uni(s0_);
+  const double rho_bar = uni(c.rho_bar);
+  if (op == MW_FACTOR) {
+    constexpr int FORM = sizeof(T) == 4 ? FACTOR_WV : FACTOR_PK;
+    const Group g{(int)(threadIdx.x & (ROW - 1)), b, s0, N};
+    const int bd = factor_chunked<T, NX, NU, NG, ST::TI, FORM, 1, R>(Lm, g, st.sigma, st.rho_f_scale * rho_bar,
+                                                                      rho_bar, nullptr, FX);
+    if ((threadIdx.x & 63) == 0) bad[threadIdx.x >> 6] = bd;
+  } else if (op == MW_PREP) {
+    prepare_segments<T, NX, NU, NG, R>(Lm, b, s0, N, buf, buf + R * nn);
+  } else if (op == MW_ITERS) {
+    run_segment<T, NX, NU, NG, ST, true, R>(Lm, st, b, s0, N, uni(c.k), uni(c.nb), rho_bar, buf);
+  }
+  __syncthreads();
+}
+
+// LDS of a multi-wavefront instance
+template <typename T, int NX, int NU, int NG, int W>
+struct MwShared {
+  static constexpr int R = 4 * W, nn = (NX + NU) * (NX + NU);
+  T buf[2 * R * nn + 2 * R * ROW];  // T blocks, U blocks, exchange slots
+  MwCmd cmd;
+  int bad[W];
+};
+
+// One complete ADMM solve of one instance (Algorithm 3 with the stopping
+// test and rho adaptation): FP64 factorisation, iterations up to each
+// boundary, FP64 residuals and decisions at the boundary, refactorisation
+// after an accepted rho change.  W = 1: the whole solve on one wavefront;
+// W > 1: wavefront 0 of a W-wavefront workgroup, the heavy parts posted as
+// workgroup operations.
+template <typename T, int NX, int NU, int NG, typename ST, int W>
+__device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings& st, const WaveGroup& w,
+                                                MwShared<T, NX, NU, NG, W>* sh, double* FX) {
   // the non-inlined callees get copies in memory: the kernel arguments
   // themselves never have their address taken
   const Layout Lc = L;
   const Settings sc = st;
+  constexpr int64_t nn = (int64_t)(NX + NU) * (NX + NU);
+  constexpr int TAG = W > 1 ? 1 : 0;
   const int i = w.lane;
   const Group g{w.lane, w.b, w.s0, w.N};
   const int kind = (i < NG) ? (int)L.soft[i] : 0;
@@ -1436,6 +1532,21 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
   int nfact = L.nfact[w.b];
   int status = ST_RUNNING;
   Resid R{INFINITY, INFINITY, 0.0, 0.0, 0};
+  // post a workgroup operation and take part in it
+  auto post = [&](int op, int k, int nb) {
+    if constexpr (W > 1) {
+      if (threadIdx.x == 0) sh->cmd = MwCmd{op, k, nb, rho_bar};
+      __syncthreads();
+      mw_op<T, NX, NU, NG, ST, W>(Lc, sc, w.b, w.s0, w.N, MwCmd{op, k, nb, rho_bar}, (lptr<T>)sh->buf, FX,
+                                  (lptr<int>)sh->bad);
+    }
+  };
+  auto local_sync = [&] {
+    if constexpr (W > 1)
+      wave_local_sync();
+    else
+      wave_sync();
+  };
 
   const bool adapt_on = st.adapt_rho && st.k_rho > 0;
   int k = L.iters[w.b];
@@ -1445,17 +1556,26 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
   // launch shape of the next iterations: long horizons always segmented; the
   // rest switch to it at iteration seg_after (few instances are left running
   // by then, and the shorter serial depth beats the extra block reads)
-  auto segmented = [&](int kk) { return w.N >= st.seg_min_n || (kk >= st.seg_after && w.N >= SEG_FLOOR_N); };
+  auto segmented = [&](int kk) {
+    return W > 1 || w.N >= st.seg_min_n || (kk >= st.seg_after && w.N >= SEG_FLOOR_N);
+  };
   for (;;) {
     if (need) {  // the only call site of the factorisation
-      constexpr int FORM = sizeof(T) == 4 ? FACTOR_WV : FACTOR_PK;
-      // long horizons: the chunked factorisation (same blocks, shorter serial depth)
-      const bool chunked = w.N >= st.seg_min_n && w.N >= FAC_CHUNK_MIN_N;
-      const int bad = chunked ? factor_chunked<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
-                                                                            rho_bar, nullptr)
-                              : factor_instance<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
-                                                                             rho_bar, nullptr, w.row);
-      wave_sync();
+      int bad = 0;
+      if constexpr (W > 1) {
+        post(MW_FACTOR, 0, 0);
+#pragma unroll
+        for (int v = 0; v < W; ++v) bad |= sh->bad[v];
+      } else {
+        constexpr int FORM = sizeof(T) == 4 ? FACTOR_WV : FACTOR_PK;
+        // long horizons: the chunked factorisation (same blocks, shorter serial depth)
+        const bool chunked = w.N >= st.seg_min_n && w.N >= FAC_CHUNK_MIN_N;
+        bad = chunked ? factor_chunked<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar, rho_bar,
+                                                                    nullptr)
+                      : factor_instance<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
+                                                                     rho_bar, nullptr, w.row);
+        wave_sync();
+      }
       if (bad) {
         status = 3;
         break;
@@ -1471,28 +1591,43 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
     if (st.seg_after > k && st.seg_after < nb) nb = st.seg_after;  // the shape changes at a segment start
     const bool seg = segmented(k);
     if (seg && !seg_ready) {
-      prepare_segments<T, NX, NU, NG>(Lc, w.b, w.s0, w.N);
-      wave_sync();
+      if constexpr (W > 1) {
+        post(MW_PREP, 0, 0);
+      } else {
+        prepare_segments<T, NX, NU, NG>(Lc, w.b, w.s0, w.N, (T*)L.SegT + (int64_t)w.b * 4 * nn,
+                                        (T*)L.SegU + (int64_t)w.b * 4 * nn);
+        wave_sync();
+      }
       seg_ready = true;
     }
-    k = seg ? run_segment<T, NX, NU, NG, ST, true>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar)
-            : run_segment<T, NX, NU, NG, ST, false>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
+    if constexpr (W > 1) {
+      post(MW_ITERS, k, nb);
+      k = nb;
+    } else {
+      k = seg ? run_segment<T, NX, NU, NG, ST, true>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar)
+              : run_segment<T, NX, NU, NG, ST, false>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
+    }
     const int check = (st.k_check > 0 && nb % st.k_check == 0) ? 1 : 0;
     const int adapt = (adapt_on && nb % st.k_rho == 0 && nb < st.max_iter) ? 1 : 0;
     const int last = (nb == st.max_iter) ? 1 : 0;
     if (check || adapt || last) {
-      R = residuals_wave<T, NX, NU, NG, ST>(Lc, w, kind, L.gamma2, L.gamma1);
+      R = residuals_wave<T, NX, NU, NG, ST, TAG>(Lc, w, kind, L.gamma2, L.gamma1);
       // infeasibility test from the second check on (the first has no earlier multipliers)
-      const int pinf = (check && have_prev && st.eps_pinf > 0.0) ? pinf_wave<T, NX, NU, NG>(Lc, w, st.eps_pinf) : 0;
+      const int pinf =
+          (check && have_prev && st.eps_pinf > 0.0) ? pinf_wave<T, NX, NU, NG, TAG>(Lc, w, st.eps_pinf) : 0;
       status = boundary_decision(R, st, check, adapt, last, pinf, rho_bar, need);
       if (status != ST_RUNNING) break;
       if (check && st.eps_pinf > 0.0) {
-        wave_sync();
+        local_sync();
         keep_multipliers<T>(Lc, w);
-        wave_sync();
+        local_sync();
         have_prev = true;
       }
     }
+  }
+  if constexpr (W > 1) {
+    if (threadIdx.x == 0) sh->cmd = MwCmd{MW_EXIT, 0, 0, 0.0};
+    __syncthreads();  // releases the other wavefronts
   }
   if (threadIdx.x == 0) {
     L.iters[w.b] = k;
@@ -1501,6 +1636,50 @@ __global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings 
     L.status[w.b] = status;
     L.rprim[w.b] = R.rp_u;
     L.rdual[w.b] = R.rd_u;
+  }
+}
+
+// One instance per wavefront; instances with a multi-wavefront workgroup
+// (horizon N >= L.mw_min_n) are left to admm_solve_mw_kernel.  Instances
+// never wait for each other.
+template <typename T, int NX, int NU, int NG, typename ST>
+__global__ __launch_bounds__(64) void admm_solve_wave_kernel(Layout L, Settings st) {
+  WaveGroup w;
+  if (!wave_group(L, w)) return;
+  if (L.status[w.b] != ST_RUNNING) return;
+  if (L.n_mw > 0 && w.N >= L.mw_min_n) return;
+  admm_solve_body<T, NX, NU, NG, ST, 1>(L, st, w, nullptr, nullptr);
+}
+
+// One instance per workgroup of W wavefronts: the instances L.mw_list[0 ..
+// L.n_mw), each with its own exchange blocks for the chunked factorisation
+// (L.FacXmw, fx_slots(4 W) n x n blocks per workgroup).
+template <typename T, int NX, int NU, int NG, typename ST>
+__global__ __launch_bounds__(64 * mw_waves<NX + NU>()) void admm_solve_mw_kernel(Layout L, Settings st) {
+  constexpr int W = mw_waves<NX + NU>();
+  constexpr int nn = (NX + NU) * (NX + NU);
+  __shared__ MwShared<T, NX, NU, NG, W> sh;
+  const int slot = blockIdx.x;
+  if (slot >= L.n_mw) return;
+  WaveGroup w;
+  w.lane = threadIdx.x & (ROW - 1);
+  w.row = (threadIdx.x >> 4) & 3;
+  w.b = L.mw_list[slot];
+  w.s0 = L.stage_off[w.b];
+  w.N = (int)(L.stage_off[w.b + 1] - w.s0) - 1;
+  if (L.status[w.b] != ST_RUNNING) return;  // the whole workgroup
+  double* FX = L.FacXmw + (size_t)slot * fx_slots(4 * W) * nn;
+  if (threadIdx.x < 64) {
+    admm_solve_body<T, NX, NU, NG, ST, W>(L, st, w, &sh, FX);
+    return;
+  }
+  const Layout Lc = L;
+  const Settings sc = st;
+  for (;;) {
+    __syncthreads();  // an operation has been posted
+    const MwCmd c = sh.cmd;
+    if (c.op == MW_EXIT) break;
+    mw_op<T, NX, NU, NG, ST, W>(Lc, sc, w.b, w.s0, w.N, c, (lptr<T>)sh.buf, FX, (lptr<int>)sh.bad);
   }
 }
 

@@ -229,6 +229,11 @@ class OCPSolver:
         segmented substitutions (ocp_set_segmented_after)."""
         A.check(self.lib.ocp_set_segmented_after(self.h, int(iteration)), "ocp_set_segmented_after")
 
+    def set_multiwave(self, mw_min_n: int):
+        """Horizons N >= mw_min_n solve on a multi-wavefront workgroup
+        (ocp_set_multiwave; 0 turns it off)."""
+        A.check(self.lib.ocp_set_multiwave(self.h, int(mw_min_n)), "ocp_set_multiwave")
+
     def set_segmented(self, seg_min_n: int):
         """Horizons N >= seg_min_n solve with segmented substitutions (ocp_set_segmented)."""
         A.check(self.lib.ocp_set_segmented(self.h, int(seg_min_n)), "ocp_set_segmented")
