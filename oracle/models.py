@@ -13,9 +13,16 @@ The trapezoidal rule of Remark A1 (batch.integrator = 1), same hold on u:
     A_t^- = [I + dt/2 Jx(x_t), dt/2 (Ju(x_t) + Ju(x_{t+1}))],
     A_t^+ = [-I + dt/2 Jx(x_{t+1}), 0].
 
-Cost 1/2 (x_t - r_t)'Q(x_t - r_t) + 1/2 u_t'R u_t (t < N), with Q_f at t = N.
+Cost 1/2 (x_t - r_t)'Q(x_t - r_t) + 1/2 u_t'R u_t (t < N), with Q_f at t = N,
+plus the control-rate cost of the racing problem (Sec. "Hardware
+Deployment: Autonomous Racing", eq. cost), 1/2 (u_t - u_{t+1})'W(u_t -
+u_{t+1}) for t < N (W diagonal, zero by default; the same 1/2 as the other
+terms).  It couples neighbouring stages: D_t gets W once at t = 0 and t = N
+and twice in between, and E_t (block (t+1, t)) gets -W on the control rows.
 Inequalities g_t = (a_t, delta_t, n_t'(p_t - p_ref_t)): hard boxes on a and
-delta, the lateral offset soft (L1) within +-lat_bound.
+delta, the lateral offset soft (L1) within +-lat_bound.  With u_init given,
+the first control is fixed, (x_0, u_0) = (x_init, u_init) as in the racing
+problem: the two control rows of stage 0 get lo = hi = u_init.
 
 The QP is written in absolute coordinates (Appendix "QP Approximation" gives
 c and the shifted bounds for the absolute variable), so the linear cost term
@@ -96,8 +103,16 @@ class BicycleOCP:
         self.Q = np.diag(batch.Qd)
         self.R = np.diag(batch.Rd)
         self.Qf = np.diag(batch.Qfd)
-        self.g_lo = np.array([-batch.a_bound, -batch.steer_bound, -batch.lat_bound])
-        self.g_hi = -self.g_lo
+        # per-stage bounds [(N+1), 3]; stage 0's control rows fixed at u_init
+        lo = np.array([-batch.a_bound, -batch.steer_bound, -batch.lat_bound])
+        self.g_lo = np.tile(lo, (self.N + 1, 1))
+        self.g_hi = np.tile(-lo, (self.N + 1, 1))
+        u_init = getattr(batch, "u_init", None)
+        self.u_init = None if u_init is None else np.asarray(u_init, float)[i].copy()
+        if self.u_init is not None:
+            self.g_lo[0, :2] = self.u_init
+            self.g_hi[0, :2] = self.u_init
+        self.W = np.diag(np.asarray(getattr(batch, "Wd", np.zeros(2)), float))
         self.soft = np.array([HARD, HARD, SOFT_L1])
         self.gamma1 = batch.gamma_l1
         self.nx, self.nu, self.ng = 4, 2, 3
@@ -110,9 +125,11 @@ class BicycleOCP:
         return 6
 
     def initial_guess(self):
-        """The reference trajectory with zero controls."""
+        """The reference trajectory with zero controls (u_0 = u_init when fixed)."""
         z = np.zeros((self.N + 1, 6))
         z[:, :4] = self.ref
+        if self.u_init is not None:
+            z[0, 4:] = self.u_init
         return z
 
     # --- cost --------------------------------------------------------------
@@ -127,6 +144,9 @@ class BicycleOCP:
         for t in range(self.N + 1):
             e = np.concatenate([z[t, :4] - self.ref[t], z[t, 4:]])
             tot += 0.5 * e @ self.stage_weights(t) @ e
+        for t in range(self.N):
+            du = z[t, 4:] - z[t + 1, 4:]
+            tot += 0.5 * du @ self.W @ du
         return tot
 
     def cost_grad(self, z):
@@ -134,7 +154,22 @@ class BicycleOCP:
         for t in range(self.N + 1):
             e = np.concatenate([z[t, :4] - self.ref[t], z[t, 4:]])
             g[t] = self.stage_weights(t) @ e
+        for t in range(self.N):
+            wdu = self.W @ (z[t, 4:] - z[t + 1, 4:])
+            g[t, 4:] += wdu
+            g[t + 1, 4:] -= wdu
         return g
+
+    def cost_hessian_blocks(self):
+        """(D [(N+1),6,6], E [N,6,6]) of the cost's Hessian, E_t = block (t+1, t)."""
+        N = self.N
+        D = np.stack([self.stage_weights(t) for t in range(N + 1)])
+        E = np.zeros((N, 6, 6))
+        for t in range(N):
+            D[t, 4:, 4:] += self.W
+            D[t + 1, 4:, 4:] += self.W
+            E[t, 4:, 4:] = -self.W
+        return D, E
 
     # --- equality constraints (init + dynamics) -----------------------------
     def eq_residual(self, z):
@@ -174,9 +209,13 @@ class BicycleOCP:
     def convexify(self, z) -> StageQP:
         """QP approximation at the trajectory z [(N+1), 6] (Appendix "QP Approximation")."""
         N = self.N
-        D = np.stack([self.stage_weights(t) for t in range(N + 1)])
+        D, E = self.cost_hessian_blocks()
         grad = self.cost_grad(z)
+        # q_t = grad_t - (H z)_t with (H z)_t = D_t z_t + E_{t-1} z_{t-1} + E_t' z_{t+1}
         q = np.stack([grad[t] - D[t] @ z[t] for t in range(N + 1)])
+        for t in range(N):
+            q[t + 1] -= E[t] @ z[t]
+            q[t] -= E[t].T @ z[t + 1]
         Am = np.zeros((N, 4, 6))
         Ap = np.zeros((N, 4, 6))
         b = np.zeros((N, 4))
@@ -187,8 +226,8 @@ class BicycleOCP:
         G = np.stack([self.G_block(t) for t in range(N + 1)])
         gz = self.ineq(z)
         Gz = np.einsum("tij,tj->ti", G, z)
-        lo = self.g_lo[None, :] - gz + Gz
-        hi = self.g_hi[None, :] - gz + Gz
-        return StageQP(nx=4, nu=2, N=N, D=D, E=np.zeros((N, 6, 6)), q=q, Am=Am, Ap=Ap, b=b,
+        lo = self.g_lo - gz + Gz
+        hi = self.g_hi - gz + Gz
+        return StageQP(nx=4, nu=2, N=N, D=D, E=E, q=q, Am=Am, Ap=Ap, b=b,
                        x_init=self.x_init.copy(), G=G, lo=lo, hi=hi, soft=self.soft.copy(),
                        gamma2=1.0, gamma1=self.gamma1)

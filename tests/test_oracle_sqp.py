@@ -112,8 +112,13 @@ def test_midpoint_second_order_on_circle():
     assert errs[0] < 1e-2 and 3.5 < errs[0] / errs[1] < 4.5
 
 
-def test_convexification_pins(rng):
+@pytest.mark.parametrize("racing", [False, True], ids=["tracking", "rate_cost_and_u_init"])
+def test_convexification_pins(rng, racing):
+    """racing: the control-rate cost (cross-stage E_t) and u_0 = u_init."""
     b = bicycle_batch(2, N=12, seed=91)
+    if racing:
+        b.Wd = np.array([3.0, 40.0])
+        b.u_init = np.array([[0.4, -0.05], [-0.7, 0.1]])
     ocp = BicycleOCP(b, 1)
     zbar = ocp.initial_guess() + 0.05 * rng.normal(size=(ocp.N + 1, 6))
     qp = ocp.convexify(zbar)
@@ -136,8 +141,12 @@ def test_convexification_pins(rng):
     z = zbar + rng.normal(size=zbar.shape)
     g = ocp.ineq(z).reshape(-1)
     Gx = G @ z.reshape(-1)
-    np.testing.assert_allclose(Gx - lo, g - np.tile(ocp.g_lo, ocp.N + 1), atol=1e-12)
-    np.testing.assert_allclose(hi - Gx, np.tile(ocp.g_hi, ocp.N + 1) - g, atol=1e-12)
+    np.testing.assert_allclose(Gx - lo, g - ocp.g_lo.reshape(-1), atol=1e-12)
+    np.testing.assert_allclose(hi - Gx, ocp.g_hi.reshape(-1) - g, atol=1e-12)
+    if racing:
+        # the two control rows of stage 0 are the equality u_0 = u_init
+        np.testing.assert_array_equal(lo[:2], b.u_init[1])
+        np.testing.assert_array_equal(hi[:2], b.u_init[1])
 
 
 class _LinearOCP:

@@ -15,6 +15,7 @@ the same shape (nx=4, nu=2, horizons 100 .. 8192, ragged batches).
 from __future__ import annotations
 
 from dataclasses import dataclass, field
+from typing import Optional
 
 import numpy as np
 
@@ -48,6 +49,11 @@ class BicycleBatch:
     Qfd: np.ndarray = field(default_factory=lambda: np.array(Q_DIAG))
     meta: dict = field(default_factory=dict)
     integrator: int = 0  # 0: implicit midpoint, 1: trapezoidal rule
+    # racing features (Sec. "Hardware Deployment: Autonomous Racing"): the
+    # control-rate weight diagonal W (1/2 (u_t - u_{t+1})'W(u_t - u_{t+1}))
+    # and the fixed first control u_0 = u_init [B, 2] (None: free)
+    Wd: np.ndarray = field(default_factory=lambda: np.zeros(2))
+    u_init: Optional[np.ndarray] = None
 
     nx: int = 4
     nu: int = 2
@@ -78,6 +84,8 @@ class BicycleBatch:
             x0=self.x0[idx].copy(), dt=self.dt, wheelbase=self.wheelbase, a_bound=self.a_bound,
             steer_bound=self.steer_bound, lat_bound=self.lat_bound, gamma_l1=self.gamma_l1,
             Qd=self.Qd.copy(), Rd=self.Rd.copy(), Qfd=self.Qfd.copy(), meta=dict(self.meta),
+            integrator=self.integrator, Wd=np.array(self.Wd, dtype=float).copy(),
+            u_init=None if self.u_init is None else np.asarray(self.u_init)[idx].copy(),
         )
 
 
