@@ -308,14 +308,17 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
                 rp_i, rd_i, ps_i, ds_i = (r_prim, r_dual, ps, ds) if M is Mg else M.residuals(x, z_g, xi, y_f, y_g)
                 cand, accept = rho_update(rho_bar, rp_i, rd_i, ps_i, ds_i, st)
                 if accept:
+                    # also at the last iteration: the returned rho_bar is the
+                    # step size an SQP iteration hands to its next QP
                     rho_bar = cand
                     rho_changes.append((k, rho_bar))
-                    try:
-                        cf = factor(rho_bar)
-                        n_factor += 1
-                    except np.linalg.LinAlgError:
-                        status = FACTOR_BREAKDOWN
-                        break
+                    if k < st.max_iter:  # the factorisation serves the iterations that follow
+                        try:
+                            cf = factor(rho_bar)
+                            n_factor += 1
+                        except np.linalg.LinAlgError:
+                            status = FACTOR_BREAKDOWN
+                            break
     return ADMMResult(*back(x, z_g, xi, y_f, y_g), rho_bar, k, status, r_prim, r_dual, n_factor, history,
                       rho_changes)
 

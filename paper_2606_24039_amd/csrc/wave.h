@@ -1333,17 +1333,19 @@ __device__ __forceinline__ int boundary_decision(const Resid& R, const Settings&
   const bool conv = R.rp_u <= st.eps_abs + st.eps_rel * R.ps_u && R.rd_u <= st.eps_abs + st.eps_rel * R.ds_u;
   if ((check || (st.k_check > 0 && last)) && conv) return 0;
   if (check && infeasible) return 4;  // certificate of the multiplier change (pinf_wave)
-  if (last) return 1;
   if (adapt && !conv) {
+    // also at the last boundary: the final rho_bar is the step size an SQP
+    // iteration hands to its next QP (no refactorisation follows it there)
     const double num = R.rp / fmax(R.ps, 1e-30);
     const double den = R.rd / fmax(R.ds, 1e-30);
     double cand = rho_bar * sqrt(num / fmax(den, 1e-30));
     cand = fmin(fmax(cand, st.rho_min), st.rho_max);
     if (fmax(cand / rho_bar, rho_bar / cand) > st.k_ratio) {
       rho_bar = cand;
-      refactor = true;
+      refactor = !last;
     }
   }
+  if (last) return 1;
   return ST_RUNNING;
 }
 
@@ -1608,7 +1610,7 @@ __device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings&
               : run_segment<T, NX, NU, NG, ST, false>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
     }
     const int check = (st.k_check > 0 && nb % st.k_check == 0) ? 1 : 0;
-    const int adapt = (adapt_on && nb % st.k_rho == 0 && nb < st.max_iter) ? 1 : 0;
+    const int adapt = (adapt_on && nb % st.k_rho == 0) ? 1 : 0;
     const int last = (nb == st.max_iter) ? 1 : 0;
     if (check || adapt || last) {
       R = residuals_wave<T, NX, NU, NG, ST, TAG>(Lc, w, kind, L.gamma2, L.gamma1);
