@@ -156,12 +156,20 @@ typedef struct {
  * 1/2 (x_t - r_t)'Q(x_t - r_t) + 1/2 u_t'R u_t (Q_f at t = N); rows
  * a in [-a_bound, a_bound], delta in [-steer_bound, steer_bound] (hard) and
  * the lateral offset n_t'(p_t - p_ref,t) in [-lat_bound, lat_bound] (L1 slack,
- * weight gamma1).  ref [S,4], normal [S,2], x0 [B,4] device; scalars host. */
+ * weight gamma1).  ref [S,4], normal [S,2], x0 [B,4] device; scalars host.
+ * Racing features (Sec. "Hardware Deployment: Autonomous Racing"): the
+ * control-rate cost of eq. cost, 1/2 (u_t - u_{t+1})'diag(Wd)(u_t - u_{t+1})
+ * for t < N (Wd = 0: none; it couples neighbouring stages through E_t), and
+ * the fixed first control (x_0, u_0) = (x_init, u_init): u_init [B,2]
+ * (device, may be NULL: u_0 free) makes the two control rows of stage 0
+ * equalities, and the SQP starts from u_0 = u_init. */
 typedef struct {
   const double *ref, *normal, *x0;
   double dt, wheelbase, a_bound, steer_bound, lat_bound, gamma1;
   double Qd[4], Rd[2], Qfd[4];
   int32_t integrator; /* OCP_INTEG_MIDPOINT or OCP_INTEG_TRAPEZOID */
+  double Wd[2];
+  const double* u_init;
 } ocp_bicycle;
 
 /* Solution buffers (device, FP64, caller-owned).  Any pointer may be NULL

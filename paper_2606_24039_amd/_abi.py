@@ -48,7 +48,8 @@ class ocp_qp(C.Structure):
 class ocp_bicycle(C.Structure):
     _fields_ = [("ref", C.c_void_p), ("normal", C.c_void_p), ("x0", C.c_void_p)] + [
         (k, C.c_double) for k in ("dt", "wheelbase", "a_bound", "steer_bound", "lat_bound", "gamma1")] + [
-        ("Qd", C.c_double * 4), ("Rd", C.c_double * 2), ("Qfd", C.c_double * 4), ("integrator", C.c_int32)]
+        ("Qd", C.c_double * 4), ("Rd", C.c_double * 2), ("Qfd", C.c_double * 4), ("integrator", C.c_int32),
+        ("Wd", C.c_double * 2), ("u_init", C.c_void_p)]
 
 
 class ocp_solution(C.Structure):

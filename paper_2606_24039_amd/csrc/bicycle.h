@@ -29,6 +29,10 @@ struct BikeArgs {
   const int32_t* stage_inst;  // [S] instance of each global stage
   double dt, Lw, a_b, d_b, lat_b, gamma1;
   double Qd[4], Rd[2], Qfd[4];
+  // control-rate cost 1/2 (u_t - u_{t+1})'diag(Wd)(u_t - u_{t+1}) (rate: Wd != 0)
+  double Wd[2];
+  int rate;
+  const double* u_init;  // [B][2]: u_0 fixed (equality rows), or null
   int integ;  // 0 implicit midpoint, 1 trapezoidal rule
   // SQP state (FP64, padded [S][ROW])
   double* xbar;
@@ -125,7 +129,7 @@ __device__ __forceinline__ void bike_dynamics(const double* xt, const double* ut
   (void)ju1;
 }
 
-// SQP initial guess: the reference with zero controls.
+// SQP initial guess: the reference with zero controls (u_0 = u_init when fixed).
 __global__ void bike_init_kernel(Layout L, BikeArgs a, double rho0) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s < (int64_t)L.B) {
@@ -142,6 +146,13 @@ __global__ void bike_init_kernel(Layout L, BikeArgs a, double rho0) {
     a.xibar[s * ROW + k] = 0.0;
     a.yfbar[s * ROW + k] = 0.0;
     a.ygbar[s * ROW + k] = 0.0;
+  }
+  if (a.u_init) {
+    const int b = a.stage_inst[s];
+    if (s == L.stage_off[b]) {
+      a.xbar[s * ROW + 4] = a.u_init[(size_t)b * 2];
+      a.xbar[s * ROW + 5] = a.u_init[(size_t)b * 2 + 1];
+    }
   }
 }
 
@@ -172,6 +183,20 @@ __global__ void bike_linearize_kernel(Layout L, BikeArgs a) {
   D[4 * 6 + 4] = a.Rd[0];
   D[5 * 6 + 5] = a.Rd[1];
   q[4] = q[5] = 0.0;
+  if (a.rate) {
+    // rate cost: W on the controls of the one or two differences touching
+    // stage t, -W in E_t = block (t+1, t); a pure quadratic form, so q is unchanged
+    const double cnt = (t < N ? 1.0 : 0.0) + (t > 0 ? 1.0 : 0.0);
+    D[4 * 6 + 4] += cnt * a.Wd[0];
+    D[5 * 6 + 5] += cnt * a.Wd[1];
+    if (t < N) {
+      double* E = const_cast<double*>(L.E) + s * 36;
+#pragma unroll
+      for (int k = 0; k < 36; ++k) E[k] = 0.0;
+      E[4 * 6 + 4] = -a.Wd[0];
+      E[5 * 6 + 5] = -a.Wd[1];
+    }
+  }
   double* Am = const_cast<double*>(L.Am) + s * 24;
   double* Ap = const_cast<double*>(L.Ap) + s * 24;
   double* bd = const_cast<double*>(L.bd) + s * 4;
@@ -213,6 +238,10 @@ __global__ void bike_linearize_kernel(Layout L, BikeArgs a) {
   hi[1] = a.d_b;
   lo[2] = -a.lat_b + np;
   hi[2] = a.lat_b + np;
+  if (t == 0 && a.u_init) {  // (x_0, u_0) = (x_init, u_init): equality rows on u_0
+    lo[0] = hi[0] = a.u_init[(size_t)b * 2];
+    lo[1] = hi[1] = a.u_init[(size_t)b * 2 + 1];
+  }
   if (t == 0) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) const_cast<double*>(L.x_init)[(size_t)b * 4 + k] = a.x0[(size_t)b * 4 + k];
@@ -337,6 +366,13 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     for (int k = 0; k < 4; ++k) gdir += W[k] * (xb[k] - r[k]) * dx[k];
     gdir += a.Rd[0] * xb[4] * dx[4] + a.Rd[1] * xb[5] * dx[5];
     gdir += a.gamma1 * ((xib != 0.0) ? (xib > 0 ? dxi : -dxi) : fabs(dxi));
+    if (a.rate && t < N)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) gdir += a.Wd[k] * (xb[4 + k] - xbn[4 + k]) * (dx[4 + k] - dxn[4 + k]);
+    // bounds of the control rows (u_0 fixed when u_init is given)
+    const bool fix0 = t == 0 && a.u_init;
+    const double alo = fix0 ? a.u_init[(size_t)b * 2] : -a.a_b, ahi = fix0 ? alo : a.a_b;
+    const double dlo = fix0 ? a.u_init[(size_t)b * 2 + 1] : -a.d_b, dhi = fix0 ? dlo : a.d_b;
 #pragma unroll
     for (int j = 0; j <= NA; ++j) {
       const double al = (j == 0) ? 0.0 : ldexp(1.0, -(j - 1));
@@ -354,13 +390,16 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
         bike_dynamics<INTEG>(z, z + 4, zn, a.dt, a.Lw, f, nullptr, nullptr);
 #pragma unroll
         for (int k = 0; k < 4; ++k) v += fabs(f[k]);
+        if (a.rate)
+#pragma unroll
+          for (int k = 0; k < 2; ++k) c += 0.5 * a.Wd[k] * (z[4 + k] - zn[4 + k]) * (z[4 + k] - zn[4 + k]);
       }
       if (t == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) v += fabs(z[k] - x0[k]);
       }
       const double g0 = z[4], g1 = z[5], g2 = nx_ * z[0] + ny_ * z[1] + gconst + xi;
-      v += fmax(g0 - a.a_b, 0.0) + fmax(-a.a_b - g0, 0.0) + fmax(g1 - a.d_b, 0.0) + fmax(-a.d_b - g1, 0.0) +
+      v += fmax(g0 - ahi, 0.0) + fmax(alo - g0, 0.0) + fmax(g1 - dhi, 0.0) + fmax(dlo - g1, 0.0) +
            fmax(g2 - a.lat_b, 0.0) + fmax(-a.lat_b - g2, 0.0);
       cost[j] += c;
       viol[j] += v;
@@ -421,6 +460,13 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     for (int k = 0; k < 4; ++k) grad[k] = W[k] * (xb[k] - r[k]);
     grad[4] = a.Rd[0] * xb[4];
     grad[5] = a.Rd[1] * xb[5];
+    if (a.rate) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (t < N) grad[4 + k] += a.Wd[k] * (xb[4 + k] - xb[ROW + 4 + k]);
+        if (t > 0) grad[4 + k] += a.Wd[k] * (xb[4 + k] - xb[-ROW + 4 + k]);
+      }
+    }
     const double* yg = a.ygbar + s * ROW;
     const double nx_ = a.normal[s * 2], ny_ = a.normal[s * 2 + 1];
     grad[4] += yg[0];
@@ -458,8 +504,11 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     for (int k = 0; k < 6; ++k) st = fmax(st, fabs(grad[k]));
     const double xi = a.xibar[s * ROW + 2];
     const double g0 = xb[4], g1 = xb[5], g2 = nx_ * (xb[0] - r[0]) + ny_ * (xb[1] - r[1]) + xi;
-    gi = fmax(gi, fmax(fmax(g0 - a.a_b, -a.a_b - g0), 0.0));
-    gi = fmax(gi, fmax(fmax(g1 - a.d_b, -a.d_b - g1), 0.0));
+    const bool fix0 = t == 0 && a.u_init;
+    const double alo = fix0 ? a.u_init[(size_t)b * 2] : -a.a_b, ahi = fix0 ? alo : a.a_b;
+    const double dlo = fix0 ? a.u_init[(size_t)b * 2 + 1] : -a.d_b, dhi = fix0 ? dlo : a.d_b;
+    gi = fmax(gi, fmax(fmax(g0 - ahi, alo - g0), 0.0));
+    gi = fmax(gi, fmax(fmax(g1 - dhi, dlo - g1), 0.0));
     gi = fmax(gi, fmax(fmax(g2 - a.lat_b, -a.lat_b - g2), 0.0));
   }
   st = wave_max(st);
@@ -537,8 +586,9 @@ __device__ __forceinline__ void bike_row_hessian(const double* xt, const double*
 
 // Exact Hessian of the Lagrangian at the SQP iterate (one thread per stage):
 // D_t gains the curvature of dynamics row t (left block) and of row t-1
-// (right block), E_t (block (t+1, t)) is the cross block of row t.  Runs
-// after bike_linearize_kernel, which leaves D_t = diag(Q or Q_f, R).
+// (right block), E_t (block (t+1, t)) the cross block of row t.  Runs after
+// bike_linearize_kernel, which leaves the cost's Hessian in D_t and, with a
+// rate cost, E_t.
 template <int INTEG>
 __global__ void bike_hessian_kernel(Layout L, BikeArgs a) {
   const int64_t S = L.stage_off[L.B];
@@ -551,8 +601,9 @@ __global__ void bike_hessian_kernel(Layout L, BikeArgs a) {
   double* D = const_cast<double*>(L.D) + s * 36;
   double* E = const_cast<double*>(L.E) + s * 36;
   double left[6][6], right[4][4], cross[4][6];
+  if (!a.rate)  // with a rate cost the linearisation has written E_t = -W (t < N)
 #pragma unroll
-  for (int k = 0; k < 36; ++k) E[k] = 0.0;
+    for (int k = 0; k < 36; ++k) E[k] = 0.0;
   if (t < N) {  // row t: this stage on the left
     const double* xt = a.xbar + s * ROW;
     bike_row_hessian<INTEG>(xt, xt + 4, xt + ROW, a.yfbar + s * ROW, a.dt, a.Lw, left, right, cross);
@@ -563,7 +614,7 @@ __global__ void bike_hessian_kernel(Layout L, BikeArgs a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int c = 0; c < 6; ++c) E[r * 6 + c] = cross[r][c];
+      for (int c = 0; c < 6; ++c) E[r * 6 + c] += cross[r][c];
   }
   if (t > 0) {  // row t-1: this stage's state on the right
     const double* xp = a.xbar + (s - 1) * ROW;

@@ -106,6 +106,8 @@ struct ocp_handle_s {
   double* bike_ref = nullptr;
   double* bike_normal = nullptr;
   double* bike_x0 = nullptr;
+  double* bike_uinit = nullptr;  // [B][2] (u_0 fixed when bike.u_init is set)
+  bool bike_rate = false;        // a control-rate cost: the QPs carry E_t
   ocp_bicycle bike{};
   double *xbar = nullptr, *xibar = nullptr, *yfbar = nullptr, *ygbar = nullptr, *mu = nullptr, *kkt = nullptr;
   int32_t* sqp_done = nullptr;
@@ -276,6 +278,7 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
     A_(h->bike_ref, sizeof(double) * 4 * S);
     A_(h->bike_normal, sizeof(double) * 2 * S);
     A_(h->bike_x0, sizeof(double) * 4 * B);
+    A_(h->bike_uinit, sizeof(double) * 2 * B);
     A_(h->xbar, sizeof(double) * ROW * S);
     A_(h->xibar, sizeof(double) * ROW * S);
     A_(h->yfbar, sizeof(double) * ROW * S);
@@ -617,6 +620,10 @@ BikeArgs make_bike(ocp_handle h, const ocp_settings* s) {
   }
   a.Rd[0] = h->bike.Rd[0];
   a.Rd[1] = h->bike.Rd[1];
+  a.Wd[0] = h->bike.Wd[0];
+  a.Wd[1] = h->bike.Wd[1];
+  a.rate = h->bike_rate ? 1 : 0;
+  a.u_init = h->bike.u_init ? h->bike_uinit : nullptr;
   a.xbar = h->xbar;
   a.xibar = h->xibar;
   a.yfbar = h->yfbar;
@@ -879,7 +886,8 @@ ocp_status ocp_set_bicycle(ocp_handle h, const ocp_bicycle* p, void* stream) {
   if (!h || !p || !p->ref || !p->normal || !p->x0) return OCP_E_ARG;
   if (h->d.model != OCP_MODEL_BICYCLE) return OCP_E_ORDER;
   if (!(p->dt > 0) || !(p->wheelbase > 0) || !(p->gamma1 > 0) || !(p->a_bound > 0) || !(p->steer_bound > 0) ||
-      !(p->lat_bound > 0) || (p->integrator != OCP_INTEG_MIDPOINT && p->integrator != OCP_INTEG_TRAPEZOID))
+      !(p->lat_bound > 0) || (p->integrator != OCP_INTEG_MIDPOINT && p->integrator != OCP_INTEG_TRAPEZOID) ||
+      !(p->Wd[0] >= 0) || !(p->Wd[1] >= 0) || !std::isfinite(p->Wd[0]) || !std::isfinite(p->Wd[1]))
     return OCP_E_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t S = h->S;
@@ -887,11 +895,15 @@ ocp_status ocp_set_bicycle(ocp_handle h, const ocp_bicycle* p, void* stream) {
       hipMemcpyAsync(h->bike_normal, p->normal, sizeof(double) * 2 * S, hipMemcpyDeviceToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h->bike_x0, p->x0, sizeof(double) * 4 * h->B, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return OCP_E_HIP;
+  if (p->u_init &&
+      hipMemcpyAsync(h->bike_uinit, p->u_init, sizeof(double) * 2 * h->B, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return OCP_E_HIP;
   h->bike = *p;
   h->variant = VAR_TV;
   h->gamma1 = p->gamma1;
   h->gamma2 = 1.0;
-  h->has_E = false;
+  h->bike_rate = p->Wd[0] != 0.0 || p->Wd[1] != 0.0;
+  h->has_E = h->bike_rate;
   h->has_q = true;
   h->has_bd = true;
   const uint8_t kinds[16] = {OCP_ROW_HARD, OCP_ROW_HARD, OCP_ROW_L1};
@@ -965,7 +977,7 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
                            LE, ba);
       }
     });
-    h->has_E = s->adj_mode == OCP_ADJ_SQP_EXACT;
+    h->has_E = h->bike_rate || s->adj_mode == OCP_ADJ_SQP_EXACT;
   }
   AdjArgs a{};
   a.dLdx = dL_dx;
@@ -1008,7 +1020,7 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
     h->entry->p32()->adj[var](L, a, st, &h->prof);
   else
     h->entry->p64()->adj[var](L, a, st, &h->prof);
-  if (at_iterate) h->has_E = false;  // the SQP's own QPs carry no cross-stage Hessian blocks
+  if (at_iterate) h->has_E = h->bike_rate;  // the SQP's own QPs: cross-stage blocks from a rate cost only
   return hip_ok(hipGetLastError());
 }
 

@@ -91,10 +91,15 @@ class OCPSolver:
         self.generation += 1
         t = [_dev(batch.ref if ref is None else ref), _dev(batch.normal), _dev(batch.x0 if x0 is None else x0)]
         w = lambda v, dflt: [float(e) for e in (dflt if v is None else v)]  # noqa: E731
+        u_init = getattr(batch, "u_init", None)
+        if u_init is not None:
+            t.append(_dev(u_init))
         p = A.ocp_bicycle(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(), batch.dt, batch.wheelbase,
                           batch.a_bound, batch.steer_bound, batch.lat_bound, batch.gamma_l1,
                           (C.c_double * 4)(*w(Qd, batch.Qd)), (C.c_double * 2)(*w(Rd, batch.Rd)),
-                          (C.c_double * 4)(*w(Qfd, batch.Qfd)), int(getattr(batch, "integrator", 0)))
+                          (C.c_double * 4)(*w(Qfd, batch.Qfd)), int(getattr(batch, "integrator", 0)),
+                          (C.c_double * 2)(*w(None, getattr(batch, "Wd", (0.0, 0.0)))),
+                          t[3].data_ptr() if u_init is not None else None)
         A.check(self.lib.ocp_set_bicycle(self.h, C.byref(p), _stream()), "ocp_set_bicycle")
         self._keep = t
         torch.cuda.current_stream().synchronize()
