@@ -57,6 +57,12 @@ class ADMMSettings:
     k_check: int = 25  # 0 = never test for convergence (fixed iteration count)
     adapt_rho: bool = True
     eps_pinf: float = 1e-4  # primal-infeasibility certificate tolerance (0 = no test)
+    # primal-update solver: "direct" (banded Cholesky) or "pcg" (block-Jacobi
+    # preconditioned CG from the current x, oracle.pcg; at most pcg_max_iter
+    # iterations, relative residual pcg_tol)
+    linsolve: str = "direct"
+    pcg_max_iter: int = 50
+    pcg_tol: float = 1e-10
 
     def with_(self, **kw) -> "ADMMSettings":
         return replace(self, **kw)
@@ -77,6 +83,7 @@ class ADMMResult:
     n_factor: int
     history: list = field(default_factory=list)
     rho_changes: list = field(default_factory=list)  # (iteration, accepted rho-bar)
+    pcg_iters: list = field(default_factory=list)  # CG iterations of each primal update (linsolve "pcg")
 
 
 def project(v, lo, hi, kind, rho_g, gamma2, gamma1):
@@ -254,7 +261,14 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
     kind = M.kind
 
     def factor(rb):
+        if st.linsolve == "pcg":
+            from .pcg import diag_block_inverses
+
+            S = M.schur(st.sigma, st.rho_f_scale * rb, rb).tocsr()
+            return S, diag_block_inverses(S, qp.n)
         return M.factor(st.sigma, st.rho_f_scale * rb, rb)
+
+    pcg_iters = []
 
     history = []
     rho_changes = []
@@ -273,7 +287,13 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
     for k in range(1, st.max_iter + 1):
         rho_f, rho_g = st.rho_f_scale * rho_bar, rho_bar
         eta = st.sigma * x - M.q + M.C.T @ (rho_f * M.c - y_f) + M.G.T @ (rho_g * z_g - y_g)
-        xt = sla.cho_solve_banded((cf, True), eta)
+        if st.linsolve == "pcg":
+            from .pcg import pcg
+
+            xt, it = pcg(cf[0], eta, x, cf[1], st.pcg_max_iter, st.pcg_tol)
+            pcg_iters.append(it)
+        else:
+            xt = sla.cho_solve_banded((cf, True), eta)
         zt_f = M.C @ xt
         zt_g = M.G @ xt
         x = a * xt + (1.0 - a) * x
@@ -320,7 +340,7 @@ def admm_solve(qp: StageQP, st: ADMMSettings = ADMMSettings(), warm=None, record
                             status = FACTOR_BREAKDOWN
                             break
     return ADMMResult(*back(x, z_g, xi, y_f, y_g), rho_bar, k, status, r_prim, r_dual, n_factor, history,
-                      rho_changes)
+                      rho_changes, pcg_iters)
 
 
 def kkt_residuals(qp: StageQP, x, z_g, xi, y_f, y_g):
