@@ -27,6 +27,9 @@ PEAK_FP32 = 157.3  # TFLOP/s, MI355X vector FP32 (published)
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X vector FP64 (published)
 PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E (published)
 SCALE_P = 0.6  # exponent of the box normalisation (ocp_set_scaling_box) on the FP32 path
+# PCG primal updates of the direct-vs-PCG comparison: at most 25 CG iterations
+# per ADMM iteration, relative residual 1e-5 (about what FP32 iterations resolve)
+PCG_ITERS, PCG_TOL = 25, 1e-5
 
 # HBM traffic of the persistent solve launch, per launch, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) of `bench.py --steps 1 --warmup 0
@@ -172,7 +175,7 @@ def upstream_gradient(batch, seed=11):
     return rng.standard_normal((batch.batch * (batch.N + 1), batch.nx + batch.nu))
 
 
-def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=None, tune=False):
+def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=None, tune=False, pcg=None):
     import torch
 
     from paper_2606_24039_amd import _abi as A
@@ -183,6 +186,9 @@ def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=Non
     if scale_p is not None:
         s.set_scaling_box(scale_p)
     s.set_lti(batch.A, batch.B, batch.Qd, batch.Rd, batch.Qfd, batch.G, batch.lo, batch.hi, batch.x0)
+    if pcg is not None:  # (max CG iterations, relative tolerance): PCG primal updates
+        s.set_linsolve(True, max_iter=pcg[0], tol=pcg[1])
+        tune = False  # no launch-shape choice for the stage-parallel PCG updates
     st = A.default_settings(**settings_kw)
     shape = s.autotune(st, reps=2) if tune else None  # launch shape picked on this batch (not timed)
     out = s.alloc_solution()
@@ -235,7 +241,7 @@ def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=Non
     return res
 
 
-def run_bicycle(batch, precision, steps, warmup, settings_kw, grad=True):
+def run_bicycle(batch, precision, steps, warmup, settings_kw, grad=True, pcg=None):
     """Timed SQP solves (+ the adjoint of the last QP) of a kinematic-bicycle batch."""
     import torch
 
@@ -243,6 +249,8 @@ def run_bicycle(batch, precision, steps, warmup, settings_kw, grad=True):
     from paper_2606_24039_amd.solver import OCPSolver
 
     s = OCPSolver(4, 2, 3, batch.horizons, model=A.MODEL_BICYCLE, precision=precision)
+    if pcg is not None:
+        s.set_linsolve(True, max_iter=pcg[0], tol=pcg[1])
     s.set_bicycle(batch)
     st = A.default_settings(**settings_kw)
     out = s.alloc_solution()
@@ -298,7 +306,8 @@ def bench_bicycle(args):
     kw = dict(max_sqp=10, max_admm=50, k_check=0, k_rho=25, fixed_sqp=1)
     steps, warmup = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
     log(f"[bench] workload: {desc}")
-    mixed = run_bicycle(batch, 1, steps, warmup, kw, grad=not args.no_grad)
+    pcg = (args.pcg_iters, args.pcg_tol) if args.linsolve == "pcg" else None
+    mixed = run_bicycle(batch, 1, steps, warmup, kw, grad=not args.no_grad, pcg=pcg)
     out = {"metric": "SQP solves/s (10 SQP x 50 ADMM iterations, fixed counts), FP32 ADMM iterations + FP64 "
                      "factorisation" + ("" if args.no_grad else ", + adjoint of the last QP"),
            "value": round(batch.batch / (mixed["ms_per_step"] * 1e-3), 4), "unit": "SQP solves/s", "n_gpus": 1,
@@ -307,8 +316,10 @@ def bench_bicycle(args):
            "data": "synthetic",
            "config": {"workload": desc, "batch": int(batch.batch), "stages": int(np.sum(batch.horizons + 1)),
                       "nx": 4, "nu": 2, "ng": 3, "grad": not args.no_grad,
-                      "parallelism": "single GPU; one wavefront per instance, one 8-wavefront workgroup per "
-                                     "instance with N >= 255"},
+                      "parallelism": ("single GPU; one wavefront per instance" if pcg else
+                                      "single GPU; one wavefront per instance, one 8-wavefront workgroup per "
+                                      "instance with N >= 255"),
+                      "linsolve": ({"pcg_max_iter": pcg[0], "pcg_tol": pcg[1]} if pcg else "direct")},
            "kernel_ms_per_step": mixed["kernel_ms_per_step"], "sqp_kkt_max": mixed["sqp_kkt_max"],
            "roofline": None, "cpu_baseline": None}
     if not args.no_fp64:
@@ -334,6 +345,10 @@ def main():
                     help="FP32 path without the problem rescaling (Remark 4) the headline uses")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison")
     ap.add_argument("--no-grad", action="store_true", help="forward solves only (no adjoint in the step)")
+    ap.add_argument("--linsolve", default="direct", choices=["direct", "pcg"],
+                    help="primal-update solver of the measured run (pcg: block-Jacobi PCG, --pcg-iters / --pcg-tol)")
+    ap.add_argument("--pcg-iters", type=int, default=PCG_ITERS)
+    ap.add_argument("--pcg-tol", type=float, default=PCG_TOL)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -361,7 +376,8 @@ def main():
     settings_kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_admm=1000, k_check=25, k_rho=25, eps_active=1e-4)
     scale_p = None if args.no_scaling else SCALE_P
     log(f"[bench] workload: {desc}")
-    mixed = run_gpu(batch, 1, args.steps, args.warmup, settings_kw, grad=not args.no_grad, scale_p=scale_p,
+    pcg = (args.pcg_iters, args.pcg_tol) if args.linsolve == "pcg" else None
+    mixed = run_gpu(batch, 1, args.steps, args.warmup, settings_kw, grad=not args.no_grad, scale_p=scale_p, pcg=pcg,
                     tune=not args.no_tune)
     log(f"[bench] mixed: {json.dumps(mixed)}")
     fp64 = None
@@ -378,6 +394,15 @@ def main():
                               "ms_per_step": round(r["ms_per_step"], 4), "solved_fraction": r["solved"] / batch.batch,
                               "iters_mean": round(r["iters_mean"], 1), "iters_capped": r["iters_capped"]}
             log(f"[bench] {name}: {json.dumps(r)}")
+        if pcg is None:  # the direct-vs-PCG comparison (the PCG backend on the same FP32 rescaled path)
+            r = run_gpu(batch, 1, max(3, args.steps // 4), 1, settings_kw, grad=not args.no_grad, scale_p=scale_p,
+                        pcg=(args.pcg_iters, args.pcg_tol))
+            variants["fp32_pcg"] = {"value": round(r["solved"] / (r["ms_per_step"] * 1e-3), 2),
+                                    "ms_per_step": round(r["ms_per_step"], 4),
+                                    "solved_fraction": r["solved"] / batch.batch,
+                                    "iters_mean": round(r["iters_mean"], 1), "iters_capped": r["iters_capped"],
+                                    "pcg": {"max_iter": args.pcg_iters, "tol": args.pcg_tol}}
+            log(f"[bench] fp32_pcg: {json.dumps(r)}")
 
     value = mixed["solved"] / (mixed["ms_per_step"] * 1e-3)
     roof, hbm = roofline(batch, mixed, "mixed", args.workload)
@@ -391,7 +416,8 @@ def main():
                    "rescaling": (f"box normalisation, power-of-two factors, exponent {scale_p}" if scale_p is not None
                                  else "none"),
                    "eps": 1e-4, "eps_active": 1e-4, "max_admm": 1000, "grad": not args.no_grad,
-                   "parallelism": "single GPU, one instance per wavefront"},
+                   "parallelism": "single GPU, one instance per wavefront",
+                   "linsolve": ({"pcg_max_iter": pcg[0], "pcg_tol": pcg[1]} if pcg else "direct")},
         "admm_iters_per_s": round(mixed["iters_sum"] / (mixed["ms_per_step"] * 1e-3), 1),
         "kernel_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in mixed["kernels"].items()},
         "solved_fraction": mixed["solved"] / batch.batch,

@@ -362,6 +362,25 @@ ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n);
  * < 16 W - 1: segments of fewer than four stages), OCP_E_HIP. */
 ocp_status ocp_set_multiwave(ocp_handle h, int32_t mw_min_n);
 
+/* Primal-update solver of the ADMM iterations (the PCG backends of the
+ * paper's table of QP solver backends, the hybrid of its discussion section:
+ * PCG forward, direct backward).  OCP_LINSOLVE_DIRECT (default): the
+ * block-tridiagonal Cholesky of S and its two substitution chains.
+ * OCP_LINSOLVE_PCG: S x~ = eta (eq. admm:schur) by block-Jacobi
+ * preconditioned conjugate gradients from the current primal iterate x,
+ * stopping before an iteration when ||r||_2 <= tol ||eta||_2 or after
+ * max_iter iterations; the "factorisation" after a rho change forms the
+ * diagonal blocks of S, their inverses and the coupling blocks instead (no
+ * recursion), and every pass is stage-parallel (one wavefront per instance;
+ * no segmented, chunked or multi-wavefront shapes).  Inexact solves slow
+ * ADMM's convergence; the stopping test is unchanged.  The adjoint always
+ * uses the direct solver.  The first switch to PCG allocates five stage
+ * vectors (and, for FP64 iterations, one block per stage) on the handle.
+ * Drops a captured graph.  Errors: OCP_E_ARG (null handle, unknown mode,
+ * max_iter < 1, tol negative or not finite), OCP_E_NOMEM, OCP_E_HIP. */
+enum { OCP_LINSOLVE_DIRECT = 0, OCP_LINSOLVE_PCG = 1 };
+ocp_status ocp_set_linsolve(ocp_handle h, int32_t mode, int32_t max_iter, double tol);
+
 /* Problem rescaling (Remark 4: states and controls normalised inside the
  * solver, transparently to the caller).  Per instance b: variable factors
  * d [B,n] (x_t = d * xh_t at every stage), inequality-row factors e_g [B,ng]

@@ -18,6 +18,7 @@ ROW_HARD, ROW_L2, ROW_L1 = 0, 1, 2
 SOLVED, MAX_ITER, NON_FINITE, FACTOR_BREAKDOWN, INFEASIBLE = 0, 1, 2, 3, 4
 ADJ_OK, ADJ_RESIDUAL, ADJ_NON_FINITE, ADJ_BREAKDOWN = 0, 1, 2, 3
 ADJ_LAST_QP, ADJ_SQP_GN, ADJ_SQP_EXACT = 0, 1, 2
+LINSOLVE_DIRECT, LINSOLVE_PCG = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -94,6 +95,7 @@ SIGNATURES = [
     ("ocp_graph_launch", C.c_int, [C.c_void_p, C.c_void_p]),
     ("ocp_set_segmented", C.c_int, [C.c_void_p, C.c_int32]),
     ("ocp_set_multiwave", C.c_int, [C.c_void_p, C.c_int32]),
+    ("ocp_set_linsolve", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double]),
     ("ocp_set_segmented_after", C.c_int, [C.c_void_p, C.c_int32]),
     ("ocp_set_iterate", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ocp_autotune", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_int32, C.c_void_p, C.POINTER(C.c_int32),

@@ -205,6 +205,12 @@ struct Layout {
   const int32_t* mw_list;
   int n_mw, mw_min_n;
   double* FacXmw;
+  // PCG primal updates (pcg != 0): at most pcg_max_it iterations to the
+  // relative residual pcg_tol; vectors [S][ROW] in iteration precision,
+  // padded like the state vectors (x~, r, z, p, S p)
+  int pcg, pcg_max_it;
+  double pcg_tol;
+  void *pcg_xt, *pcg_r, *pcg_z, *pcg_p, *pcg_sp;
   // structure of time-invariant LTI data: G rows are unit selectors
   int8_t gsel[16];  // variable selected by inequality row r
   int8_t ginv[16];  // inequality row selecting variable i, or -1
@@ -272,6 +278,9 @@ __device__ __forceinline__ Layout uni(const Layout& L) {
   u.SubA = uni(L.SubA), u.SubB = uni(L.SubB), u.ChF = uni(L.ChF), u.ChB = uni(L.ChB);
   u.SegT = uni(L.SegT), u.SegU = uni(L.SegU), u.SegX = uni(L.SegX), u.FacX = uni(L.FacX);
   u.mw_list = uni(L.mw_list), u.n_mw = uni(L.n_mw), u.mw_min_n = uni(L.mw_min_n), u.FacXmw = uni(L.FacXmw);
+  u.pcg = uni(L.pcg), u.pcg_max_it = uni(L.pcg_max_it), u.pcg_tol = uni(L.pcg_tol);
+  u.pcg_xt = uni(L.pcg_xt), u.pcg_r = uni(L.pcg_r), u.pcg_z = uni(L.pcg_z), u.pcg_p = uni(L.pcg_p);
+  u.pcg_sp = uni(L.pcg_sp);
   u.x = uni(L.x), u.v = uni(L.v), u.yf = uni(L.yf), u.zg = uni(L.zg), u.yg = uni(L.yg), u.xi = uni(L.xi);
   u.rho = uni(L.rho), u.status = uni(L.status), u.iters = uni(L.iters), u.nfact = uni(L.nfact);
   u.rprim = uni(L.rprim), u.rdual = uni(L.rdual);

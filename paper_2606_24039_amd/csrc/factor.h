@@ -155,7 +155,11 @@ __device__ __forceinline__ T quarter_pick(const T (&a)[K], int q) {
 // In the two solve forms the four 16-lane rows of the wavefront each form and
 // store the output columns 4 qrow .. 4 qrow + 3 (the recurrence itself runs
 // on every row).  Returns 0 on success, 1 on a non-positive / non-finite pivot.
-enum { FACTOR_M = 0, FACTOR_WV = 1, FACTOR_PK = 2 };
+//   FACTOR_PCG (PCG primal updates) no recursion: SubA = Theta_t^-1 (the
+//              block-Jacobi preconditioner), SubB = Theta_t, ChF = Phi_t
+//              (block (t+1, t) of S), ChB = Phi_t' (t < N), all in
+//              iteration precision; row 0 stores them.
+enum { FACTOR_M = 0, FACTOR_WV = 1, FACTOR_PK = 2, FACTOR_PCG = 3 };
 
 // TAG only separates the instantiations called from kernels with different
 // occupancy targets (the register budget of a called function follows its
@@ -169,6 +173,7 @@ __device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, d
   const double* __restrict__ rhog_rows = uni(rhog_rows_);
   constexpr bool WV = FORM == FACTOR_WV;
   constexpr bool PK = FORM == FACTOR_PK;
+  constexpr bool PCG = FORM == FACTOR_PCG;
   constexpr int n = NX + NU;
   const int i = g.lane;
   const bool vi = i < n;
@@ -247,11 +252,39 @@ __device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, d
       for (int r = 0; r < NG; ++r) Gw[r] = cur.w[r] * cur.Gc[r];
       cross_row<NG, n>(Gw, cur.Gc, S, 1.0);
     }
-    if (t > 0) cross_row<n, n>(Mrow, Mrow, S, -1.0);
+    if (!PCG && t > 0) cross_row<n, n>(Mrow, Mrow, S, -1.0);
+    double Th[PCG ? n : 1];  // row i of Theta_t (PCG: the matrix-vector products use it)
+    if constexpr (PCG) {
+#pragma unroll
+      for (int k = 0; k < n; ++k) Th[k] = S[k];
+    }
 
     // dense Cholesky of S and X = L^{-1} (lane i holds row i)
     double X[n];
     bad |= chol_inv<n>(S, X, i);
+    if constexpr (PCG) {
+      // Theta_t^-1 = X'X (row i), and Theta_t
+      double XT[n], E1[n], Pi[n];
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        XT[j] = 0.0;
+        E1[j] = (i == j) ? 1.0 : 0.0;
+      }
+      cross_row<n, n>(E1, X, XT, 1.0);
+      sfor<0, n>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        Pi[jj] = dotb<n>(XT, X[jj], 0.0);
+      });
+      if (qrow == 0 && vi) {
+        const gptr<T> pr = as_global((T*)L.SubA + (size_t)s * nn + (size_t)i * n);
+        const gptr<T> tr = as_global((T*)L.SubB + (size_t)s * nn + (size_t)i * n);
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          pr[j] = T(Pi[j]);
+          tr[j] = T(Th[j]);
+        }
+      }
+    }
     double Pc[PK ? 4 : 1];  // columns 4 qrow .. 4 qrow + 3 of P_t, row i
     if constexpr (WV) {
       // rows / columns 4 qrow .. 4 qrow + 3 of Linv_t, W_t and V_{t-1}
@@ -318,6 +351,17 @@ __device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, d
         for (int k = 0; k < n; ++k) Phi[k] = cur.E[k];
         cross_row<NX, n>(cur.Apc, cur.Amc, Phi, rho_f);
       }
+      if constexpr (PCG) {  // Phi_t rows and, transposed, Phi_t'
+        if (qrow == 0 && vi) {
+          const gptr<T> fr = as_global((T*)L.ChF + (size_t)s * nn + (size_t)i * n);
+          const gptr<T> fc = as_global((T*)L.ChB + (size_t)s * nn + i);
+#pragma unroll
+          for (int j = 0; j < n; ++j) {
+            fr[j] = T(Phi[j]);
+            fc[(size_t)j * n] = T(Phi[j]);
+          }
+        }
+      }
       // M_{t+1} row i: M[i][j] = sum_{k<=j} Phi[i][k] Linv[j][k]
       sfor<0, n>([&](auto j) {
         constexpr int jj = decltype(j)::value;
@@ -344,7 +388,7 @@ __device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, d
             kb[(size_t)j * n] = T(kij);
           }
         });
-      } else if (!WV && vi) {
+      } else if (FORM == FACTOR_M && vi) {
         const gptr<double> dst = as_global(L.M64 + (size_t)(s + 1) * nn + (size_t)i * n);
 #pragma unroll
         for (int j = 0; j < n; ++j) dst[j] = Mrow[j];

@@ -87,6 +87,10 @@ struct ocp_handle_s {
   int32_t* mw_list = nullptr;
   double* FacXmw = nullptr;
   std::vector<int32_t> horizons_host;
+  // PCG primal updates (ocp_set_linsolve): mode, limits, vectors (allocated by the first switch to PCG)
+  int pcg = 0, pcg_max_it = 50;
+  double pcg_tol = 1e-6;
+  void *pcg_xt = nullptr, *pcg_r = nullptr, *pcg_z = nullptr, *pcg_p = nullptr, *pcg_sp = nullptr;
   int variant = 0;
   int seg_min_n = SEG_MIN_N;  // launch shape: horizons from which the substitutions run segmented
   int seg_after = INT32_MAX;  // iteration from which every running instance does (the batch's tail)
@@ -437,7 +441,15 @@ Layout make_layout(ocp_handle h) {
   L.SegX = h->SegX;
   L.FacX = h->FacX;
   L.mw_list = h->mw_list;
-  L.n_mw = h->n_mw;
+  L.n_mw = h->pcg ? 0 : h->n_mw;  // PCG updates run one wavefront per instance
+  L.pcg = h->pcg;
+  L.pcg_max_it = h->pcg_max_it;
+  L.pcg_tol = h->pcg_tol;
+  L.pcg_xt = h->pcg_xt;
+  L.pcg_r = h->pcg_r;
+  L.pcg_z = h->pcg_z;
+  L.pcg_p = h->pcg_p;
+  L.pcg_sp = h->pcg_sp;
   L.mw_min_n = h->mw_min_n;
   L.FacXmw = h->FacXmw;
   for (int k = 0; k < 16; ++k) {
@@ -1100,6 +1112,36 @@ ocp_status ocp_graph_launch(ocp_handle h, void* stream) {
   if (!h->graph_exec) return OCP_E_ORDER;
   if (hipGraphLaunch(h->graph_exec, (hipStream_t)stream) != hipSuccess) return OCP_E_HIP;
   h->solved = true;
+  return OCP_OK;
+}
+
+ocp_status ocp_set_linsolve(ocp_handle h, int32_t mode, int32_t max_iter, double tol) {
+  if (!h || (mode != OCP_LINSOLVE_DIRECT && mode != OCP_LINSOLVE_PCG) || max_iter < 1 || !(tol >= 0.0) ||
+      !std::isfinite(tol))
+    return OCP_E_ARG;
+  if (h->carve) return OCP_E_UNSUPPORTED;
+  drop_graph(h);  // a captured graph keeps the solver it was recorded with
+  if (mode == OCP_LINSOLVE_PCG && !h->pcg_xt) {
+    // five padded stage vectors and, for FP64 iterations, the preconditioner blocks
+    const size_t ts = h->tsz(), nn = (size_t)h->n * h->n;
+    const size_t SP = (size_t)h->S + 1 + 2 * (size_t)STAGE_PAD;
+    void** vec[] = {&h->pcg_xt, &h->pcg_r, &h->pcg_z, &h->pcg_p, &h->pcg_sp};
+    for (void** v : vec) {
+      ocp_status st = halloc(h, v, ts * ROW * SP, false);
+      if (st != OCP_OK) return st;
+      if (hipMemset(*v, 0, ts * ROW * SP) != hipSuccess) return OCP_E_HIP;
+      *v = (char*)*v + ts * ROW * STAGE_PAD;
+    }
+    if (!h->SubA) {
+      ocp_status st = halloc(h, &h->SubA, ts * nn * SP, false);
+      if (st != OCP_OK) return st;
+      if (hipMemset(h->SubA, 0, ts * nn * SP) != hipSuccess) return OCP_E_HIP;
+      h->SubA = (char*)h->SubA + ts * nn * STAGE_PAD;
+    }
+  }
+  h->pcg = mode == OCP_LINSOLVE_PCG ? 1 : 0;
+  h->pcg_max_it = max_iter;
+  h->pcg_tol = tol;
   return OCP_OK;
 }
 

@@ -402,7 +402,7 @@ struct TrIn {
 // r_t of the stage on this row: eta_t, times Linv_t for FP32 iterations.
 // `init` is this lane's initial-state term (rho_f x_init - y_init on lanes
 // < nx), added at t = 0.
-template <bool FULL, typename T, int NX, int NU, int NG, typename ST, bool LV>
+template <bool FULL, bool RAW = false, typename T, int NX, int NU, int NG, typename ST, bool LV>
 __device__ __forceinline__ T stage_r(const IterCtx<T, NX, NU, NG, ST, LV>& c, const EtaIn<T, NX, NU, NG, ST::TI>& cur,
                                      int t, T init) {
   constexpr int n = NX + NU;
@@ -437,7 +437,7 @@ __device__ __forceinline__ T stage_r(const IterCtx<T, NX, NU, NG, ST, LV>& c, co
   } else {
     eta = dotb<NG>(cur.GC, u, eta);
   }
-  if constexpr (EtaIn<T, NX, NU, NG, TI>::SA)
+  if constexpr (EtaIn<T, NX, NU, NG, TI>::SA && !RAW)
     return dotb<n>(cur.Ar, eta, T(0));
   else
     return eta;
@@ -896,6 +896,176 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
       xn = xt;
     };
     seg_walk<SEG_AHEAD<T, n, R>, In>(steps, load, comp);
+  }
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// PCG primal update (the PCG backend; ocp_set_linsolve).  S x~ = eta is
+// solved by block-Jacobi preconditioned conjugate gradients from the current
+// primal iterate x: with Theta_t the diagonal blocks of S and Phi_t its
+// block (t+1, t), (S p)_t = Theta_t p_t + Phi_{t-1} p_{t-1} + Phi_t' p_{t+1}
+// and the preconditioner applies Theta_t^-1 stage by stage (blocks from
+// factor_instance, FACTOR_PCG).  Every pass is stage-parallel: row q takes
+// the stages t = q, q + 4, ...; the inner products are wavefront sums in
+// FP64.  Stops before an iteration when ||r||_2 <= tol ||eta||_2, or after
+// max_it iterations.  Then the constraint updates of every stage from x~.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PcgPtrs {
+  gptr<T> xt, r, z, p, sp;  // [stages][ROW], at stage -STAGE_PAD like the state vectors
+};
+
+template <typename T, int NX, int NU, int NG, typename ST>
+__device__ __forceinline__ void wave_iteration_pcg(const IterCtx<T, NX, NU, NG, ST>& c, const PcgPtrs<T>& B, int max_it,
+                                                   double tol) {
+  constexpr int n = NX + NU;
+  constexpr bool TI = ST::TI;
+  constexpr int VS = ROW * (int)sizeof(T);
+  const int N = c.N, q = c.q, i = c.i;
+  const auto& P = c.P;
+  const bool vi = i < n;
+  const int ir = vi ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
+  const T init = (i < NX) ? c.rho_f * c.xinit - c.yinit : T(0);
+  const int steps = (N + 4) / 4;
+  auto ov = [&](int t) { return (uint32_t)(((STAGE_PAD + t) * ROW + i) * (int)sizeof(T)); };
+  auto of = [&](int t) { return (uint32_t)(((STAGE_PAD + t) * n * n + ir * n) * (int)sizeof(T)); };
+  // (S v)_t on lane i from the vector v (global, this lane's entry of stages t-1, t, t+1)
+  auto smul = [&](gptr<const T> v, int t) {
+    T Th[n], Fm[n], Ft[n];
+    ldo_n<n>(Th, P.SB, of(t));
+    T acc = dotb<n>(Th, ldo(v, ov(t)), T(0));
+    if (t > 0) {
+      ldo_n<n>(Fm, P.CF, of(t - 1));
+      acc = dotb<n>(Fm, ldo<-VS>(v, ov(t)), acc);
+    }
+    if (t < N) {
+      ldo_n<n>(Ft, P.CB, of(t));
+      acc = dotb<n>(Ft, ldo<VS>(v, ov(t)), acc);
+    }
+    return acc;
+  };
+  auto precond = [&](T r, int t) {
+    T Mi[n];
+    ldo_n<n>(Mi, P.SA, of(t));
+    return dotb<n>(Mi, r, T(0));
+  };
+  auto wsum = [](double v) {
+    v = row_sum(v);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+  };
+
+  // eta_t (raw) into r; ||eta||^2
+  double bb = 0.0;
+  for (int k = 0; k < steps; ++k) {
+    const int t = 4 * k + q;
+    if (t > N) continue;  // the same on all lanes of a row
+    EtaIn<T, NX, NU, NG, TI> d;
+    const uint32_t o = ov(t);
+    d.x = ldo(P.x, o);
+    d.yf = ldo(P.yf, o);
+    d.yfm = ldo<-VS>(P.yf, o);
+    d.zg = ldo(P.zg, o);
+    d.yg = ldo(P.yg, o);
+    const int tm = t > 0 ? t - 1 : 0;
+    d.q = P.q ? ldo(P.q, (uint32_t)((t * n + ir) * (int)sizeof(T))) : T(0);
+    if constexpr (!TI) {
+      d.bd = P.bd ? ldo(P.bd, (uint32_t)((t * NX + ix) * (int)sizeof(T))) : T(0);
+      d.bdm = P.bd ? ldo(P.bd, (uint32_t)((tm * NX + ix) * (int)sizeof(T))) : T(0);
+      ldo_n<NX, n>(d.AmC, P.Am, (uint32_t)((t * NX * n + ir) * (int)sizeof(T)));
+      ldo_n<NX, n>(d.ApCm, P.Ap, (uint32_t)((tm * NX * n + ir) * (int)sizeof(T)));
+      ldo_n<NG, n>(d.GC, P.G, (uint32_t)((t * NG * n + ir) * (int)sizeof(T)));
+    }
+    const T eta = vi ? stage_r<false, true>(c, d, t, init) : T(0);
+    sto(B.r, o, eta);
+    bb += double(eta) * double(eta);
+  }
+  // r = eta - S x, z = M r, p = z from x~_0 = x
+  double rz = 0.0, rr = 0.0;
+  for (int k = 0; k < steps; ++k) {
+    const int t = 4 * k + q;
+    if (t > N) continue;
+    const uint32_t o = ov(t);
+    const T r = vi ? ldo(B.r, o) - smul(P.x, t) : T(0);
+    const T z = vi ? precond(r, t) : T(0);
+    sto(B.xt, o, vi ? ldo(P.x, o) : T(0));
+    sto(B.r, o, r);
+    sto(B.z, o, z);
+    sto(B.p, o, z);
+    rz += double(r) * double(z);
+    rr += double(r) * double(r);
+  }
+  bb = wsum(bb);
+  rz = wsum(rz);
+  rr = wsum(rr);
+  wave_sync();  // p of every stage stored
+  const double lim = tol * tol * bb;
+  for (int it = 0; it < max_it && rr > lim; ++it) {
+    double pSp = 0.0;
+    for (int k = 0; k < steps; ++k) {
+      const int t = 4 * k + q;
+      if (t > N) continue;
+      const uint32_t o = ov(t);
+      const T sp = vi ? smul(B.p, t) : T(0);
+      sto(B.sp, o, sp);
+      pSp += double(ldo(B.p, o)) * double(sp);
+    }
+    pSp = wsum(pSp);
+    const T alpha = T(rz / pSp);
+    double rz_new = 0.0;
+    rr = 0.0;
+    for (int k = 0; k < steps; ++k) {
+      const int t = 4 * k + q;
+      if (t > N) continue;
+      const uint32_t o = ov(t);
+      const T pv = ldo(B.p, o);
+      const T x = ldo(B.xt, o) + alpha * pv;
+      const T r = ldo(B.r, o) - alpha * ldo(B.sp, o);
+      const T z = vi ? precond(r, t) : T(0);
+      sto(B.xt, o, x);
+      sto(B.r, o, r);
+      sto(B.z, o, z);
+      rz_new += double(r) * double(z);
+      rr += double(r) * double(r);
+    }
+    rz_new = wsum(rz_new);
+    rr = wsum(rr);
+    const T beta = T(rz_new / rz);
+    rz = rz_new;
+    for (int k = 0; k < steps; ++k) {
+      const int t = 4 * k + q;
+      if (t > N) continue;
+      const uint32_t o = ov(t);
+      sto(B.p, o, ldo(B.z, o) + beta * ldo(B.p, o));
+    }
+    wave_sync();  // p of every stage stored
+  }
+  wave_sync();  // x~ of every stage stored
+  // over-relaxation, projections and dual updates from x~
+  for (int k = 0; k < steps; ++k) {
+    const int t = 4 * k + q;
+    if (t > N) continue;
+    const uint32_t o = ov(t);
+    UpdIn<T, NX, NU, NG, TI> u;
+    u.x = ldo(P.x, o);
+    u.yf = ldo(P.yf, o);
+    u.zg = ldo(P.zg, o);
+    u.yg = ldo(P.yg, o);
+    if constexpr (!TI) {
+      u.lo = ldo(P.lo, (uint32_t)((t * NG + ig) * (int)sizeof(T)));
+      u.hi = ldo(P.hi, (uint32_t)((t * NG + ig) * (int)sizeof(T)));
+      u.bd = P.bd ? ldo(P.bd, (uint32_t)((t * NX + ix) * (int)sizeof(T))) : T(0);
+      ldo_n<n>(u.AmR, P.Am, (uint32_t)((t * NX * n + ix * n) * (int)sizeof(T)));
+      ldo_n<n>(u.ApR, P.Ap, (uint32_t)((t * NX * n + ix * n) * (int)sizeof(T)));
+      ldo_n<n>(u.GR, P.G, (uint32_t)((t * NG * n + ig * n) * (int)sizeof(T)));
+    }
+    u.xt = ldo(B.xt, o);
+    u.xt1 = (t < N) ? ldo<VS>(B.xt, o) : T(0);
+    stage_update<false>(c, u, t, o);
+    // initial-state rows: y_init += rho_f alpha (x~_0 - x_init), slot N of y_f
+    if (t == 0 && i < NX) sto(P.yf, ov(N), c.yinit + c.rfa * (u.xt - c.xinit));
   }
   wave_sync();
 }
@@ -1400,6 +1570,20 @@ __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, in
   const bool state_lds = !SEG && sizeof(T) == 4 && N + 1 + 2 * STAGE_PAD + 8 <= STATE_LDS_STAGES;
   const bool xv_lds = !SEG && N + 1 + 2 * STAGE_PAD + 8 <= LDS_ELEMS / ROW;
   int k = uni(k0_);
+  if constexpr (!SEG) {
+    if (L.pcg) {  // PCG primal updates (stage-parallel; no chains)
+      const int64_t sp = s0 - STAGE_PAD;
+      const PcgPtrs<T> B{as_global((T*)L.pcg_xt + sp * ROW), as_global((T*)L.pcg_r + sp * ROW),
+                         as_global((T*)L.pcg_z + sp * ROW), as_global((T*)L.pcg_p + sp * ROW),
+                         as_global((T*)L.pcg_sp + sp * ROW)};
+      for (; k < nb; ++k) {
+        IterCtx<T, NX, NU, NG, ST> ck = c;
+        ck.yinit = ldo(P.yf, o_yinit);
+        wave_iteration_pcg<T, NX, NU, NG, ST>(ck, B, L.pcg_max_it, L.pcg_tol);
+      }
+      return k;
+    }
+  }
   if constexpr (!SEG && sizeof(T) == 4) {
     if (state_lds) {
       const IterPtrs<T, NX, NU, NG, true> PL(P, XVl, STATE_LDS_STAGES);
@@ -1559,6 +1743,7 @@ __device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings&
   // rest switch to it at iteration seg_after (few instances are left running
   // by then, and the shorter serial depth beats the extra block reads)
   auto segmented = [&](int kk) {
+    if (W == 1 && L.pcg) return false;  // the PCG updates have no chains to segment
     return W > 1 || w.N >= st.seg_min_n || (kk >= st.seg_after && w.N >= SEG_FLOOR_N);
   };
   for (;;) {
@@ -1571,11 +1756,15 @@ __device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings&
       } else {
         constexpr int FORM = sizeof(T) == 4 ? FACTOR_WV : FACTOR_PK;
         // long horizons: the chunked factorisation (same blocks, shorter serial depth)
-        const bool chunked = w.N >= st.seg_min_n && w.N >= FAC_CHUNK_MIN_N;
-        bad = chunked ? factor_chunked<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar, rho_bar,
-                                                                    nullptr)
-                      : factor_instance<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
-                                                                     rho_bar, nullptr, w.row);
+        const bool chunked = !L.pcg && w.N >= st.seg_min_n && w.N >= FAC_CHUNK_MIN_N;
+        if (L.pcg)  // the PCG blocks: Theta_t, Theta_t^-1, Phi_t (no recursion)
+          bad = factor_instance<T, NX, NU, NG, ST::TI, FACTOR_PCG>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
+                                                                   rho_bar, nullptr, w.row);
+        else
+          bad = chunked ? factor_chunked<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
+                                                                      rho_bar, nullptr)
+                        : factor_instance<T, NX, NU, NG, ST::TI, FORM>(Lc, g, st.sigma, st.rho_f_scale * rho_bar,
+                                                                       rho_bar, nullptr, w.row);
         wave_sync();
       }
       if (bad) {

@@ -234,6 +234,12 @@ class OCPSolver:
         segmented substitutions (ocp_set_segmented_after)."""
         A.check(self.lib.ocp_set_segmented_after(self.h, int(iteration)), "ocp_set_segmented_after")
 
+    def set_linsolve(self, pcg: bool, max_iter: int = 50, tol: float = 1e-6):
+        """Primal updates by block-Jacobi PCG (pcg=True) or the direct
+        block-tridiagonal Cholesky (ocp_set_linsolve)."""
+        A.check(self.lib.ocp_set_linsolve(self.h, A.LINSOLVE_PCG if pcg else A.LINSOLVE_DIRECT, int(max_iter),
+                                          float(tol)), "ocp_set_linsolve")
+
     def set_multiwave(self, mw_min_n: int):
         """Horizons N >= mw_min_n solve on a multi-wavefront workgroup
         (ocp_set_multiwave; 0 turns it off)."""
