@@ -77,9 +77,11 @@ def test_random_lti_converges_to_the_qp_optimum(precision, tol, eps):
         got = per_instance(s, out, i)
         if precision == FP64:
             assert st[i] == 0
+        # primal and dual solutions at the stated tolerance (1e-6 relative in
+        # FP64, 1e-4 in FP32; measured: 3e-8 and 3e-5)
         assert rel(got["x"], exact["x"]) < tol
-        assert rel(got["y_f"], exact["y_f"]) < 10 * tol
-        assert rel(got["y_g"], exact["y_g"]) < 10 * tol
+        assert rel(got["y_f"], exact["y_f"]) < tol
+        assert rel(got["y_g"], exact["y_g"]) < tol
 
 
 def test_random_lti_gate_at_1e4_matches_oracle_solution():
