@@ -77,7 +77,13 @@ void timed(Prof* p, int c, hipStream_t st, F&& f) {
 // ---------------------------------------------------------------------------
 // dispatch table: one instantiation per compiled (nx, nu, ng)
 // ---------------------------------------------------------------------------
-using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, hipStream_t, Prof*);
+// a second stream and two events: the multi-wavefront launch of a mixed batch
+// runs beside the one-wavefront launch (fork / join on the caller's stream)
+struct Fork {
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, hipStream_t, Prof*, const Fork*);
 using AdjFn = void (*)(const Layout&, const AdjArgs&, hipStream_t, Prof*);
 
 // One ADMM solve: per-solve initialisation, then one workgroup of
@@ -86,17 +92,27 @@ using AdjFn = void (*)(const Layout&, const AdjArgs&, hipStream_t, Prof*);
 // iterations, FP64 checks, rho adaptation and refactorisation) without
 // waiting for other instances.
 template <typename T, int NX, int NU, int NG, typename ST>
-void launch_solve(const Layout& L, const Settings& s, int32_t* need, hipStream_t st, Prof* pf) {
+void launch_solve(const Layout& L, const Settings& s, int32_t* need, hipStream_t st, Prof* pf, const Fork* fk) {
   timed(pf, OCP_K_OTHER, st,
         [&] { hipLaunchKernelGGL((admm_init_kernel<T>), dim3(L.init_blocks), dim3(256), 0, st, L, s, need); });
+  // both launches of a mixed batch side by side: the workgroup launch on the
+  // second stream, forked from and joined back into the caller's stream
+  const bool both = L.n_mw > 0 && L.n_mw < L.B && fk && fk->aux;
+  hipStream_t mst = st;
+  if (both && hipEventRecord(fk->fork, st) == hipSuccess && hipStreamWaitEvent(fk->aux, fk->fork, 0) == hipSuccess)
+    mst = fk->aux;
   if (L.n_mw > 0)
-    timed(pf, OCP_K_SOLVE, st, [&] {
+    timed(pf, OCP_K_SOLVE, mst, [&] {
       hipLaunchKernelGGL((admm_solve_mw_kernel<T, NX, NU, NG, ST>), dim3(L.n_mw), dim3(64 * mw_waves<NX + NU>()), 0,
-                         st, L, s);
+                         mst, L, s);
     });
   if (L.n_mw < L.B)
     timed(pf, OCP_K_SOLVE, st,
           [&] { hipLaunchKernelGGL((admm_solve_wave_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, s); });
+  if (mst != st) {
+    (void)hipEventRecord(fk->join, mst);
+    (void)hipStreamWaitEvent(st, fk->join, 0);
+  }
 }
 
 // one instance per wavefront

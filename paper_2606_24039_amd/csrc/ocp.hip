@@ -86,6 +86,7 @@ struct ocp_handle_s {
   bool mw_off = false;  // no multi-wavefront workgroups (workspace carved by ocp_solve_noalloc)
   int32_t* mw_list = nullptr;
   double* FacXmw = nullptr;
+  Fork fork;  // second stream for the workgroup launch of a mixed batch (created with the handle)
   std::vector<int32_t> horizons_host;
   // PCG primal updates (ocp_set_linsolve): mode, limits, vectors (allocated by the first switch to PCG)
   int pcg = 0, pcg_max_it = 50;
@@ -336,6 +337,12 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   {
     const ocp_status ms = upload_mw_list(h);
     if (ms != OCP_OK) return ms;
+  }
+  if (h->mw_cap > 0 && h->mw_cap < B) {  // a batch that may launch both solve kernels
+    if (hipStreamCreateWithFlags(&h->fork.aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->fork.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->fork.join, hipEventDisableTiming) != hipSuccess)
+      return OCP_E_HIP;
   }
   // stage offsets and longest-first processing order (host -> device, once)
   std::vector<int64_t> off(B + 1, 0);
@@ -608,9 +615,9 @@ void run_admm(ocp_handle h, const Settings& s_, hipStream_t st) {
   const int ti = h->ti ? 1 : 0;
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (ti ? VAR_TI : VAR_TV);
   if (h->mixed)
-    h->entry->p32()->solve[var](L, s, h->need, st, &h->prof);
+    h->entry->p32()->solve[var](L, s, h->need, st, &h->prof, &h->fork);
   else
-    h->entry->p64()->solve[var](L, s, h->need, st, &h->prof);
+    h->entry->p64()->solve[var](L, s, h->need, st, &h->prof, &h->fork);
 }
 
 BikeArgs make_bike(ocp_handle h, const ocp_settings* s) {
@@ -793,6 +800,9 @@ ocp_status ocp_destroy(ocp_handle h) {
   h->prof.release();
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->fork.join) (void)hipEventDestroy(h->fork.join);
+  if (h->fork.fork) (void)hipEventDestroy(h->fork.fork);
+  if (h->fork.aux) (void)hipStreamDestroy(h->fork.aux);
   free_all(h);
   delete h;
   return OCP_OK;

@@ -1647,7 +1647,10 @@ struct MwCmd {
 #ifndef OCP_MW_WAVES
 #define OCP_MW_WAVES 8
 #endif
-__host__ __device__ constexpr int mw_waves_of(int n) { return n <= 8 ? OCP_MW_WAVES : 4; }
+#ifndef OCP_MW_WAVES_WIDE
+#define OCP_MW_WAVES_WIDE 4
+#endif
+__host__ __device__ constexpr int mw_waves_of(int n) { return n <= 8 ? OCP_MW_WAVES : OCP_MW_WAVES_WIDE; }
 template <int n>
 constexpr int mw_waves() { return mw_waves_of(n); }
 // shortest horizon taken by a W-wavefront workgroup: four stages per segment

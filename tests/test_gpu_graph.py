@@ -143,3 +143,55 @@ def test_captured_rescaled_lti_step():
             for k in GKEYS:
                 assert np.array_equal(gotg[k], refg[k]), (rep, k)
         s.close()
+
+
+@pytest.mark.parametrize("precision", [MIXED, FP64])
+def test_captured_mixed_batch_with_a_workgroup_instance(precision):
+    """A batch with one instance above the multi-wavefront threshold and
+    short ones: the workgroup launch runs on a second stream forked from and
+    joined back into the capturing stream.  Every replay equals the eager
+    step bit for bit, and the eager FP64 trajectory equals the oracle's."""
+    import torch
+
+    from oracle.admm import ADMMSettings
+    from oracle.models import BicycleOCP
+    from oracle.sqp import SQPSettings, sqp_solve
+    from paper_2606_24039_amd import _abi as A
+    from paper_2606_24039_amd import default_settings
+    from paper_2606_24039_amd.solver import OCPSolver
+    from workloads import bicycle_batch
+
+    long_ = bicycle_batch(1, N=300, seed=3)
+    short = bicycle_batch(3, N=30, seed=4)
+    b = bicycle_batch(4, N=300, seed=3)
+    b.horizons = np.array([300, 30, 30, 30])
+    b.stage_off = np.concatenate([[0], np.cumsum(b.horizons + 1)]).astype(np.int64)
+    b.ref = np.concatenate([long_.ref, short.ref])
+    b.normal = np.concatenate([long_.normal, short.normal])
+    b.x0 = np.concatenate([long_.x0, short.x0])
+    stream = torch.cuda.Stream()
+    keys = ("x", "xi", "y_f", "y_g", "sqp_kkt", "status")
+    with torch.cuda.stream(stream):
+        s = OCPSolver(4, 2, 3, b.horizons, model=A.MODEL_BICYCLE, precision=precision)
+        s.set_bicycle(b)
+        st = default_settings(max_sqp=2, max_admm=50, k_check=0, k_rho=25, fixed_sqp=1)
+        ref = _snapshot(s.solve(st), keys)
+        out = s.alloc_solution()
+        s.graph_capture(st, out)
+        for rep in range(3):
+            for v in out.values():
+                v.fill_(-7)
+            s.graph_launch()
+            stream.synchronize()
+            got = _snapshot(out, keys)
+            for k in keys:
+                assert np.array_equal(got[k], ref[k]), (rep, k)
+            s.solve(default_settings(max_sqp=1, max_admm=20, k_check=0, fixed_sqp=1))
+            stream.synchronize()
+    if precision == FP64:
+        for i in (0, 1):
+            r = sqp_solve(BicycleOCP(b, i), SQPSettings(max_sqp=2, fixed_iters=True),
+                          admm=ADMMSettings(max_iter=50, k_check=0, k_rho=25))
+            z = ref["x"][b.stage_off[i]:b.stage_off[i + 1]]
+            assert np.max(np.abs(z - r.z)) <= 1e-8 * max(1.0, np.max(np.abs(r.z))), i
+    s.close()
