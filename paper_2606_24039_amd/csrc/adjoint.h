@@ -343,15 +343,57 @@ struct AdjInTV5 {
   double dx, dn, efn, rfn, wc, eg, rg, ef0, rf0, ex;
 };
 
-template <int NX, int NU, int NG>
+// One substitution chain y_t = r_t - B_t y_prev (DIR +1: t = 0..N, B = K;
+// -1: t = N..0, B = Kb; y in place of r in Rv) on R segments, segment q on
+// 16-lane row q of a multi-wavefront workgroup: the particular solution of
+// each segment from a zero start, the serial pass over the segment ends
+// (seg_link, with the segments' transfer blocks TU), then the correction
+// d_t = -B_t d_prev from the entering value added in place.
+template <int n, int R, int DIR>
+__device__ __forceinline__ void adj_seg_chain(gptr<double> Rv, gptr<const double> Bm, lptr<double> X,
+                                              lptr<const double> TU, int N, int q, int i) {
+  const SegRange sg = seg_range<R>(q, N);
+  const int ir = i < n ? i : n - 1;
+  const size_t nn = (size_t)n * n;
+  auto stage = [&](int k) { return DIR > 0 ? sg.a + k : sg.a + sg.len - 1 - k; };
+  double y = 0.0;
+  for (int k = 0; k < sg.len; ++k) {
+    const int t = stage(k);
+    double Br[n];
+    load_row<n>(Br, Bm + (size_t)t * nn + (size_t)ir * n, true);
+    const double r = Rv[(size_t)t * ROW + i];
+    y = (i < n) ? r - dotb<n>(Br, y, 0.0) : 0.0;
+    Rv[(size_t)t * ROW + i] = y;
+  }
+  const double in = seg_link<double, n, R>(y, DIR > 0 ? 0 : 1, X, TU, q, i);
+  double d = in;
+  for (int k = 0; k < sg.len; ++k) {
+    const int t = stage(k);
+    double Br[n];
+    load_row<n>(Br, Bm + (size_t)t * nn + (size_t)ir * n, true);
+    d = (i < n) ? -dotb<n>(Br, d, 0.0) : 0.0;
+    Rv[(size_t)t * ROW + i] += d;
+  }
+}
+
+// LDS of a multi-wavefront adjoint: the chains' transfer blocks (forward,
+// backward) and exchange slots, and one reduction slot per wavefront
+template <int n, int R>
+struct AdjMwLds {
+  double tu[2 * R * n * n];
+  double x[2 * R * ROW];
+  double red[R / 4];
+};
+
+template <int NX, int NU, int NG, int NR = 4>
 __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjArgs& a, const WaveGroup& w, int bad,
-                                                    bool slr) {
+                                                    bool slr, AdjMwLds<NX + NU, NR>* mw = nullptr) {
   constexpr int n = NX + NU;
   constexpr int D = ADJ_TV_DEPTH<n>;
   const int i = w.lane, q = w.row, N = w.N, b = w.b;
   const int64_t s0 = w.s0;
   const int ic = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
-  const int nfull = N / 4;
+  const int nfull = N / NR;
   const size_t nn = (size_t)n * n;
   const double rb = a.rho_b;
   const double dls = L.sc ? L.sc[(size_t)b * 3 * ROW + i] : 1.0;  // rescaled QP: d * dL/dx
@@ -366,7 +408,7 @@ __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjAr
   const gptr<const double> Kbb0 = as_global((const double*)a.Kb) + sp * (int64_t)nn;
   const uint32_t orow = (uint32_t)((STAGE_PAD * ROW + i) * (int)sizeof(double));
   const uint32_t oblk = (uint32_t)((STAGE_PAD * (int)nn + ic * n) * (int)sizeof(double));
-  auto tcl = [&](int blk) { return min(4 * blk + q, N); };
+  auto tcl = [&](int blk) { return min(NR * blk + q, N); };
 
   double rres = 0.0;  // this lane's part of ||r - K e||_inf (the pass after the last sweep only evaluates it)
   for (int sweep = 0; sweep <= a.sweeps && !bad; ++sweep) {
@@ -391,7 +433,7 @@ __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjAr
         d.dl = (i < n) ? a.dLdx[(size_t)s * n + i] * dls : 0.0;
       };
       auto comp = [&](const In& d, int blk, auto) {
-        const int t = 4 * blk + q;
+        const int t = NR * blk + q;
         if (t > N) return;  // the same on all lanes of a row
         const int64_t s = s0 + t;
         const size_t sv = (size_t)s * ROW + i;
@@ -437,7 +479,12 @@ __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjAr
     wave_sync();
     if (sweep == a.sweeps) break;
     // passes 2-4: d_x = S^{-1} rhs
-    if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
+    if constexpr (NR == 4) {
+      if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
+    } else {
+      adj_seg_chain<n, NR, +1>(as_global(a.v) + (size_t)s0 * ROW, as_global((const double*)a.K) + (size_t)s0 * nn,
+                              (lptr<double>)mw->x, (lptr<const double>)mw->tu, N, q, i);
+    }
     wave_sync();
     {
       auto load = [&](TrIn<double, n>& d, int blk) {
@@ -446,14 +493,19 @@ __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjAr
         d.v = R[(size_t)t * ROW];
       };
       auto comp = [&](const TrIn<double, n>& d, int blk, auto) {
-        const int t = 4 * blk + q;
+        const int t = NR * blk + q;
         if (t > N) return;
         R[(size_t)t * ROW] = dotb<n>(d.Br, d.v, 0.0);
       };
       stage_blocks<D, TrIn<double, n>>(nfull, load, comp);
     }
     wave_sync();
-    if (q == 0) chain<double, n, -1>(Rb, Kbb0, orow, oblk, N);
+    if constexpr (NR == 4) {
+      if (q == 0) chain<double, n, -1>(Rb, Kbb0, orow, oblk, N);
+    } else {
+      adj_seg_chain<n, NR, -1>(as_global(a.v) + (size_t)s0 * ROW, as_global((const double*)a.Kb) + (size_t)s0 * nn,
+                              (lptr<double>)mw->x, (lptr<const double>)(mw->tu + NR * nn), N, q, i);
+    }
     wave_sync();
     // pass 5: d_y = rho_b (J d_x - r_y), e += d
     {
@@ -478,7 +530,7 @@ __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjAr
         d.ex = (i < n) ? ex[sv] : 0.0;
       };
       auto comp = [&](const In& d, int blk, auto) {
-        const int t = 4 * blk + q;
+        const int t = NR * blk + q;
         if (t > N) return;
         const size_t sv = (size_t)(s0 + t) * ROW + i;
         double jd = dotb<n>(d.Amr, d.dx, 0.0);
@@ -496,15 +548,39 @@ __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjAr
   return rres;
 }
 
-template <typename T, int NX, int NU, int NG, typename ST>
-__global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
+// cross-wavefront reductions of a multi-wavefront adjoint (R > 4): every
+// lane holds its wavefront's value on entry and the workgroup's on return
+template <int R, typename F>
+__device__ __forceinline__ double adj_block_reduce(double v, double* red, F&& op) {
+  if constexpr (R == 4) {
+    return v;
+  } else {
+    constexpr int W = R / 4;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int k = 1; k < W; ++k) r = op(r, red[k]);
+    __syncthreads();  // the slots are reused by the next reduction
+    return r;
+  }
+}
+
+// The adjoint of one instance on R 16-lane rows: one wavefront (R = 4,
+// time-invariant or time-varying data) or a workgroup of R / 4 wavefronts
+// (time-varying data; chunked factorisation with R + 1 chunks and chains on
+// R segments, FX its exchange blocks, mw its LDS).
+template <typename T, int NX, int NU, int NG, typename ST, int R>
+__device__ __forceinline__ void adjoint_body(const Layout& L, const AdjArgs& a, const WaveGroup& w, double* FX,
+                                             AdjMwLds<NX + NU, R>* mw) {
   constexpr int n = NX + NU;
-  WaveGroup w;
-  if (!wave_group(L, w)) return;
+  static_assert(R == 4 || !ST::TI, "multi-wavefront adjoints take time-varying data");
   const int i = w.lane, q = w.row, b = w.b, N = w.N;
   const int64_t s0 = w.s0;
   const Group g{w.lane, w.b, w.s0, w.N};
-  const int nbl = (N + 4) / 4;
+  const int nbl = (N + R) / R;
+  auto vmax = [](double x, double y) { return fmax(x, y); };
+  auto vsum = [](double x, double y) { return x + y; };
   const size_t nn = (size_t)n * n;
   const gptr<const T> X = as_global((const T*)L.x);
   const gptr<const T> YG = as_global((const T*)L.yg);
@@ -526,16 +602,16 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   // ---- 1. active set ----
   double ymax = 0.0, dlmax = 0.0;
   for (int blk = 0; blk < nbl; ++blk) {
-    const int t = 4 * blk + q;
+    const int t = R * blk + q;
     if (t <= N && i < NG) ymax = fmax(ymax, fabs(double(YG[(size_t)(s0 + t) * ROW + i]) * yw));
     if (t <= N && i < n) dlmax = fmax(dlmax, fabs(a.dLdx[(size_t)(s0 + t) * n + i] * sd));
   }
-  ymax = rows_max(row_max(ymax));
-  dlmax = rows_max(row_max(dlmax));
+  ymax = adj_block_reduce<R>(rows_max(row_max(ymax)), mw ? mw->red : nullptr, vmax);
+  dlmax = adj_block_reduce<R>(rows_max(row_max(dlmax)), mw ? mw->red : nullptr, vmax);
   const double epsg = 10.0 * a.eps_active * fmax(1.0, ymax);  // dual test, relative to the multipliers
   const double epsp = 10.0 * a.eps_active;                     // proximity test, relative to the bound
   for (int blk = 0; blk < nbl; ++blk) {
-    const int t = 4 * blk + q;
+    const int t = R * blk + q;
     if (t > N) break;
     const int64_t s = s0 + t;
     const size_t sv = (size_t)s * ROW + i;
@@ -575,7 +651,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   if (a.dLdxi) {
     dlmax = 0.0;
     for (int blk = 0; blk < nbl; ++blk) {
-      const int t = 4 * blk + q;
+      const int t = R * blk + q;
       if (t > N) break;
       const int64_t s = s0 + t;
       const size_t sv = (size_t)s * ROW + i;
@@ -589,7 +665,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
         dlmax = fmax(dlmax, fabs(e * sd));
       }
     }
-    dlmax = rows_max(row_max(dlmax));
+    dlmax = adj_block_reduce<R>(rows_max(row_max(dlmax)), mw ? mw->red : nullptr, vmax);
     wave_sync();
     ar.dLdx = a.dl;
   }
@@ -599,31 +675,40 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   LF.SubB = a.P;
   LF.ChF = a.K;
   LF.ChB = a.Kb;
-  const bool chunked = g.N >= a.chunk_min_n && g.N >= FAC_CHUNK_MIN_N;
   int bad;
-  if (L.ti)
-    bad = chunked ? factor_chunked<double, NX, NU, NG, true, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w)
-                  : factor_instance<double, NX, NU, NG, true, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
-  else
-    bad = chunked ? factor_chunked<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w)
-                  : factor_instance<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
-  wave_sync();
+  if constexpr (R == 4) {
+    const bool chunked = g.N >= a.chunk_min_n && g.N >= FAC_CHUNK_MIN_N;
+    if (L.ti)
+      bad = chunked ? factor_chunked<double, NX, NU, NG, true, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w)
+                    : factor_instance<double, NX, NU, NG, true, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
+    else
+      bad = chunked ? factor_chunked<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w)
+                    : factor_instance<double, NX, NU, NG, false, FACTOR_PK>(LF, g, a.sigma_b, rb, 0.0, a.w, q);
+    wave_sync();
+  } else {
+    constexpr int nn_ = n * n;
+    bad = factor_chunked<double, NX, NU, NG, false, FACTOR_PK, 1, R>(LF, g, a.sigma_b, rb, 0.0, a.w, FX);
+    bad = (int)adj_block_reduce<R>((double)bad, mw->red, vmax);
+    // transfer blocks of the segmented chains (forward: K, backward: Kb)
+    prepare_segments<double, NX, NU, NG, R>(LF, b, s0, N, (lptr<double>)mw->tu, (lptr<double>)(mw->tu + R * nn_));
+    __syncthreads();
+  }
 
   // ---- refinement sweeps, then the final FP64 residual ||r - K e||_inf ----
   double rres;
   if constexpr (ST::TI) {
     rres = adjoint_sweeps_ti<NX, NU, NG, ST>(L, ar, w, bad);
   } else {
-    rres = adjoint_sweeps_tv<NX, NU, NG>(L, ar, w, bad, slr);
+    rres = adjoint_sweeps_tv<NX, NU, NG, R>(L, ar, w, bad, slr, mw);
   }
-  rres = rows_max(row_max(rres));
+  rres = adj_block_reduce<R>(rows_max(row_max(rres)), mw ? mw->red : nullptr, vmax);
 
   // ---- 3. VJP outputs ----
   const double nanv = bad ? NAN : 0.0;
   double dgam = 0.0, dgam1 = 0.0;  // this lane's parts of dL/dgamma2, dL/dgamma1
   bool nonfin = false;
   for (int blk = 0; blk < nbl; ++blk) {
-    const int t = 4 * blk + q;
+    const int t = R * blk + q;
     if (t > N) break;
     const int64_t s = s0 + t;
     const size_t sv = (size_t)s * ROW + i;
@@ -673,7 +758,9 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
   dgam1 = row_sum(dgam1);
   dgam1 += __shfl_xor(dgam1, 16);
   dgam1 += __shfl_xor(dgam1, 32);
-  const bool anynf = __ballot(nonfin) != 0;
+  dgam = adj_block_reduce<R>(dgam, mw ? mw->red : nullptr, vsum);
+  dgam1 = adj_block_reduce<R>(dgam1, mw ? mw->red : nullptr, vsum);
+  const bool anynf = adj_block_reduce<R>(__ballot(nonfin) != 0 ? 1.0 : 0.0, mw ? mw->red : nullptr, vmax) != 0.0;
   if (threadIdx.x == 0) {
     if (a.d_gamma2) a.d_gamma2[b] = dgam + nanv;
     if (a.d_gamma1) a.d_gamma1[b] = dgam1 + nanv;
@@ -683,6 +770,35 @@ __global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
     if (a.adj_status)
       a.adj_status[b] = bad ? OCP_ADJ_BREAKDOWN : (anynf ? OCP_ADJ_NON_FINITE : (rel <= a.adj_tol ? OCP_ADJ_OK : OCP_ADJ_RESIDUAL));
   }
+}
+
+
+// One instance per wavefront; with multi-wavefront instances (time-varying
+// data) those are left to adjoint_mw_kernel.
+template <typename T, int NX, int NU, int NG, typename ST>
+__global__ __launch_bounds__(64) void adjoint_kernel(Layout L, AdjArgs a) {
+  WaveGroup w;
+  if (!wave_group(L, w)) return;
+  if (!ST::TI && L.n_mw > 0 && w.N >= L.mw_min_n) return;
+  adjoint_body<T, NX, NU, NG, ST, 4>(L, a, w, nullptr, nullptr);
+}
+
+// One instance per workgroup of mw_waves() wavefronts: L.mw_list[0 .. L.n_mw)
+// (time-varying data), with the exchange blocks of the solve's workgroups.
+template <typename T, int NX, int NU, int NG, typename ST>
+__global__ __launch_bounds__(64 * mw_waves<NX + NU>()) void adjoint_mw_kernel(Layout L, AdjArgs a) {
+  constexpr int W = mw_waves<NX + NU>(), R = 4 * W, n = NX + NU;
+  __shared__ AdjMwLds<n, R> lds;
+  const int slot = blockIdx.x;
+  if (slot >= L.n_mw) return;
+  WaveGroup w;
+  w.lane = threadIdx.x & (ROW - 1);
+  w.row = threadIdx.x >> 4;
+  w.b = L.mw_list[slot];
+  w.s0 = L.stage_off[w.b];
+  w.N = (int)(L.stage_off[w.b + 1] - w.s0) - 1;
+  double* FX = L.FacXmw + (size_t)slot * fx_slots(R) * n * n;
+  adjoint_body<T, NX, NU, NG, ST, R>(L, a, w, FX, &lds);
 }
 
 }  // namespace ocpk

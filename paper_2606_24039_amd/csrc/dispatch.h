@@ -84,7 +84,7 @@ struct Fork {
   hipEvent_t fork = nullptr, join = nullptr;
 };
 using SolveFn = void (*)(const Layout&, const Settings&, int32_t*, hipStream_t, Prof*, const Fork*);
-using AdjFn = void (*)(const Layout&, const AdjArgs&, hipStream_t, Prof*);
+using AdjFn = void (*)(const Layout&, const AdjArgs&, hipStream_t, Prof*, const Fork*);
 
 // One ADMM solve: per-solve initialisation, then one workgroup of
 // mw_waves() wavefronts per long instance (N >= L.mw_min_n) and one
@@ -115,11 +115,29 @@ void launch_solve(const Layout& L, const Settings& s, int32_t* need, hipStream_t
   }
 }
 
-// one instance per wavefront
+// one instance per wavefront, and (time-varying data) one workgroup per
+// multi-wavefront instance, side by side as in launch_solve
 template <typename T, int NX, int NU, int NG, typename ST>
-void launch_adjoint(const Layout& L, const AdjArgs& a, hipStream_t st, Prof* pf) {
-  timed(pf, OCP_K_ADJOINT, st,
-        [&] { hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, a); });
+void launch_adjoint(const Layout& L, const AdjArgs& a, hipStream_t st, Prof* pf, const Fork* fk) {
+  const int n_mw = ST::TI ? 0 : L.n_mw;
+  const bool both = n_mw > 0 && n_mw < L.B && fk && fk->aux;
+  hipStream_t mst = st;
+  if (both && hipEventRecord(fk->fork, st) == hipSuccess && hipStreamWaitEvent(fk->aux, fk->fork, 0) == hipSuccess)
+    mst = fk->aux;
+  if constexpr (!ST::TI) {
+    if (n_mw > 0)
+      timed(pf, OCP_K_ADJOINT, mst, [&] {
+        hipLaunchKernelGGL((adjoint_mw_kernel<T, NX, NU, NG, ST>), dim3(n_mw), dim3(64 * mw_waves<NX + NU>()), 0,
+                           mst, L, a);
+      });
+  }
+  if (n_mw < L.B)
+    timed(pf, OCP_K_ADJOINT, st,
+          [&] { hipLaunchKernelGGL((adjoint_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, a); });
+  if (mst != st) {
+    (void)hipEventRecord(fk->join, mst);
+    (void)hipStreamWaitEvent(st, fk->join, 0);
+  }
 }
 
 // structure variants of the iteration kernel

@@ -1039,9 +1039,9 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
   const Layout L = make_layout(h);
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (h->ti ? VAR_TI : VAR_TV);
   if (h->mixed)
-    h->entry->p32()->adj[var](L, a, st, &h->prof);
+    h->entry->p32()->adj[var](L, a, st, &h->prof, &h->fork);
   else
-    h->entry->p64()->adj[var](L, a, st, &h->prof);
+    h->entry->p64()->adj[var](L, a, st, &h->prof, &h->fork);
   if (at_iterate) h->has_E = h->bike_rate;  // the SQP's own QPs: cross-stage blocks from a rate cost only
   return hip_ok(hipGetLastError());
 }

@@ -1523,7 +1523,9 @@ __device__ __forceinline__ int boundary_decision(const Resid& R, const Settings&
 // schedule between two boundaries).  Not inlined: the loop gets the register
 // file to itself, the solve-level state of the caller stays out of it.
 // Returns the iteration count reached.
-template <typename T, int NX, int NU, int NG, typename ST, bool SEG, int R = 4>
+// PCG: the PCG primal updates (its own instantiation, so that the direct
+// path's register allocation does not see them).
+template <typename T, int NX, int NU, int NG, typename ST, bool SEG, int R = 4, bool PCG = false>
 __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, int b_, int64_t s0_, int N_, int k0_,
                                         int nb_, double rho_bar_, lptr<T> mw_ = nullptr) {
   const Layout L = uni(Lm);
@@ -1565,13 +1567,13 @@ __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, in
   // before the boundary's residuals); longer ones, and FP64, the exchange
   // vector only
   constexpr int LDS_ELEMS = sizeof(T) == 4 ? 6 * STATE_LDS_STAGES * ROW : XV_LDS_STAGES * ROW;
-  __shared__ __attribute__((aligned(16))) T lds_buf[SEG ? 1 : LDS_ELEMS];
+  __shared__ __attribute__((aligned(16))) T lds_buf[(SEG || PCG) ? 1 : LDS_ELEMS];
   const lptr<T> XVl = (lptr<T>)lds_buf;
   const bool state_lds = !SEG && sizeof(T) == 4 && N + 1 + 2 * STAGE_PAD + 8 <= STATE_LDS_STAGES;
   const bool xv_lds = !SEG && N + 1 + 2 * STAGE_PAD + 8 <= LDS_ELEMS / ROW;
   int k = uni(k0_);
-  if constexpr (!SEG) {
-    if (L.pcg) {  // PCG primal updates (stage-parallel; no chains)
+  if constexpr (PCG) {
+    {  // PCG primal updates (stage-parallel; no chains)
       const int64_t sp = s0 - STAGE_PAD;
       const PcgPtrs<T> B{as_global((T*)L.pcg_xt + sp * ROW), as_global((T*)L.pcg_r + sp * ROW),
                          as_global((T*)L.pcg_z + sp * ROW), as_global((T*)L.pcg_p + sp * ROW),
@@ -1798,8 +1800,11 @@ __device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings&
       post(MW_ITERS, k, nb);
       k = nb;
     } else {
-      k = seg ? run_segment<T, NX, NU, NG, ST, true>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar)
-              : run_segment<T, NX, NU, NG, ST, false>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
+      if (L.pcg)
+        k = run_segment<T, NX, NU, NG, ST, false, 4, true>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
+      else
+        k = seg ? run_segment<T, NX, NU, NG, ST, true>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar)
+                : run_segment<T, NX, NU, NG, ST, false>(Lc, sc, w.b, w.s0, w.N, k, nb, rho_bar);
     }
     const int check = (st.k_check > 0 && nb % st.k_check == 0) ? 1 : 0;
     const int adapt = (adapt_on && nb % st.k_rho == 0) ? 1 : 0;

@@ -14,6 +14,8 @@ oracle's as closely as the one-wavefront shapes do.
   trajectory in FP64 against the oracle.
 * The threshold's argument checks, and the default (horizons of 256 stages
   and more) on a batch where it applies.
+* The adjoint on a workgroup (time-varying data): equal to the one-wavefront
+  adjoint and to the oracle's dense KKT solve, with a slack loss.
 """
 import numpy as np
 import pytest
@@ -132,3 +134,58 @@ def test_multiwave_threshold_checks_and_default():
         res.append(out["x"].cpu().numpy())
         s.close()
     assert rel(res[0], res[1]) < 1e-10, rel(res[0], res[1])
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_multiwave_adjoint_matches_one_wavefront_and_oracle(precision):
+    """The adjoint of a long time-varying instance on its workgroup
+    (33-chunk FP64 factorisation, refinement chains on 32 segments) equals
+    the one-wavefront adjoint (1e-9) and the oracle's dense KKT solve at the
+    same active set (1e-6), with a loss on x and on the slacks; an instance
+    starts off the track so that L1 rows carry slack."""
+    from oracle.adjoint import adjoint_dense, qp_vjp
+    from paper_2606_24039_amd import _abi as A
+    from paper_2606_24039_amd.solver import OCPSolver
+    import torch
+
+    b = bicycle_batch(2, N=300, seed=6)
+    o = b.stage_off[1]
+    b.x0[1, :2] = b.ref[o, :2] + 2.6 * b.normal[o]
+    eps = 1e-10 if precision == FP64 else 1e-6
+    st = _settings(max_sqp=1, fixed_sqp=1, eps_abs=eps, eps_rel=eps, max_admm=20000)
+    res = {}
+    for mw in (127, 0):
+        s = OCPSolver(4, 2, 3, b.horizons, model=A.MODEL_BICYCLE, precision=precision)
+        s.set_multiwave(mw)
+        s.set_bicycle(b)
+        s.solve(st)
+        dl = torch.as_tensor(np.random.default_rng(7).standard_normal((s.S, 6)), dtype=torch.float64, device="cuda")
+        dxi = torch.as_tensor(np.random.default_rng(9).standard_normal((s.S, 3)), dtype=torch.float64, device="cuda")
+        g = s.adjoint(dl, _settings(eps_active=1e-6), dL_dxi=dxi)
+        out = s.get_solution()
+        res[mw] = ({k: v.clone() for k, v in g.items()}, {k: v.clone() for k, v in out.items()}, s, dl, dxi)
+    gm, om, sm, dl, dxi = res[127]
+    g1, o1, s1, _, _ = res[0]
+    assert (gm["adj_status"] == 0).all(), gm["adj_status"]
+    if precision == FP64:
+        assert rel(gm["eta_x"].cpu().numpy(), g1["eta_x"].cpu().numpy()) < 1e-9
+        assert torch.equal(gm["active"], g1["active"])
+    for i in range(b.batch):
+        ocp = BicycleOCP(b, i)
+        qp = ocp.convexify(ocp.initial_guess())
+        act = sm.split(gm["active"], i).cpu().numpy().reshape(-1)
+        r = admm_solve(qp, ADMMSettings(eps_abs=1e-11, eps_rel=1e-11, max_iter=200000))
+        ok, sol = polish(qp, r.x, r.y_g, xi=r.xi, eps_solve=1e-8)
+        assert ok
+        dli = sm.split(dl, i).cpu().numpy().reshape(-1)
+        dxii = sm.split(dxi, i).cpu().numpy().reshape(-1)
+        ex, ef, eg = adjoint_dense(qp, sol["x"], dli, act < 0, act > 0, dL_dxi=dxii, xi=r.xi)
+        assert rel(sm.split(gm["eta_x"], i).cpu().numpy().reshape(-1), ex) < 1e-6, i
+        qg = qp_vjp(qp, sol["x"], ex, ef, eg, act < 0, act > 0, xi=r.xi, dL_dxi=dxii)
+        flat = lambda a: np.asarray(a).reshape(-1)  # noqa: E731
+        assert rel(flat(gm["d_x_init"][i].cpu().numpy()), flat(qg["d_x_init"])) < 1e-6, i
+        for k in ("d_q", "d_lo", "d_hi", "eta_xi"):
+            assert rel(flat(sm.split(gm[k], i).cpu().numpy()), flat(qg[k])) < 1e-6, (i, k)
+        assert abs(float(gm["d_gamma1"][i]) - qg["d_gamma1"]) <= 1e-6 * max(1.0, abs(qg["d_gamma1"])), i
+    sm.close()
+    s1.close()
