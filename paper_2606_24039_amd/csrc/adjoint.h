@@ -356,21 +356,33 @@ __device__ __forceinline__ void adj_seg_chain(gptr<double> Rv, gptr<const double
   const int ir = i < n ? i : n - 1;
   const size_t nn = (size_t)n * n;
   auto stage = [&](int k) { return DIR > 0 ? sg.a + k : sg.a + sg.len - 1 - k; };
+  // the next step's block row and vector entry are loaded while this one computes
+  double Bn[n], rn;
+  load_row<n>(Bn, Bm + (size_t)stage(0) * nn + (size_t)ir * n, sg.len > 0);
+  rn = sg.len > 0 ? Rv[(size_t)stage(0) * ROW + i] : 0.0;
   double y = 0.0;
   for (int k = 0; k < sg.len; ++k) {
     const int t = stage(k);
     double Br[n];
-    load_row<n>(Br, Bm + (size_t)t * nn + (size_t)ir * n, true);
-    const double r = Rv[(size_t)t * ROW + i];
+#pragma unroll
+    for (int j = 0; j < n; ++j) Br[j] = Bn[j];
+    const double r = rn;
+    if (k + 1 < sg.len) {
+      load_row<n>(Bn, Bm + (size_t)stage(k + 1) * nn + (size_t)ir * n, true);
+      rn = Rv[(size_t)stage(k + 1) * ROW + i];
+    }
     y = (i < n) ? r - dotb<n>(Br, y, 0.0) : 0.0;
     Rv[(size_t)t * ROW + i] = y;
   }
   const double in = seg_link<double, n, R>(y, DIR > 0 ? 0 : 1, X, TU, q, i);
   double d = in;
+  load_row<n>(Bn, Bm + (size_t)stage(0) * nn + (size_t)ir * n, sg.len > 0);
   for (int k = 0; k < sg.len; ++k) {
     const int t = stage(k);
     double Br[n];
-    load_row<n>(Br, Bm + (size_t)t * nn + (size_t)ir * n, true);
+#pragma unroll
+    for (int j = 0; j < n; ++j) Br[j] = Bn[j];
+    if (k + 1 < sg.len) load_row<n>(Bn, Bm + (size_t)stage(k + 1) * nn + (size_t)ir * n, true);
     d = (i < n) ? -dotb<n>(Br, d, 0.0) : 0.0;
     Rv[(size_t)t * ROW + i] += d;
   }
