@@ -96,7 +96,7 @@ def lti_flops_per_stage(nx, nu, ng):
 def lti_bytes_per_stage(n, ts, blocks, k_seg=25):
     """Algorithmic bytes one ADMM iteration moves per stage, for the design
     measured here (FP32 iterations, horizons up to 55 stages): the `blocks`
-    n x n factor blocks (Linv_t, Linv_t', W_t, V_t) stream from memory once per
+    n x n factor blocks (the packed Linv_t, W_t, V_t) stream from memory once per
     iteration; the six padded 16-entry stage vectors stay in LDS for a
     segment of `k_seg` iterations, so five of them (x, y_f, z_g, y_g, xi) move
     in and out once per segment."""
@@ -480,7 +480,7 @@ def roofline(batch, res, prec, workload):
             "flops_fp32_per_launch": F32, "flops_fp64_per_launch": F64, "bytes_per_launch": bytes_alg,
             "flops_per_stage_iteration": f_it, "flops_per_stage_factorisation": f_fac,
             "roofline_time_us": round(t_roof * 1e6, 2), "kernel_source": src}
-    b_it = lti_bytes_per_stage(n, 4, 4)
+    b_it = lti_bytes_per_stage(n, 4, 3)
     design_bytes = res["iters_sum"] * stages * b_it / launches
     hbm = {"design_bytes_per_launch": design_bytes, "bytes_per_stage_iteration": b_it,
            "achieved_GBps": round(design_bytes / t_launch / 1e9, 1), "peak_GBps": PEAK_HBM,

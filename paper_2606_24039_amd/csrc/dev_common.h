@@ -76,6 +76,20 @@ __device__ __forceinline__ T dotb(const T (&a)[K], T v, T acc) {
   return dotb_asm<K>(a, v, acc);
 }
 
+// Products with the packed FP32 inverse factor (factor.h, FACTOR_WV): lane i
+// of a row holds c[e] = Linv[max(i,s)][min(i,s)], s = (i - e) mod K, so
+//   dotl: acc + sum_{j<=i} Linv[i][j] v_j       (row_shr by i - j)
+//   dotu: acc + sum_{j>=i} Linv[j][i] v_j       (row_shl by j - i)
+// (lanes j >= K of v must be zero in dotu)
+template <int K>
+__device__ __forceinline__ float dotl(const float (&c)[K], float v, float acc) {
+  return dotl_asm<K>(c, v, acc);
+}
+template <int K>
+__device__ __forceinline__ float dotu(const float (&c)[K], float v, float acc) {
+  return dotu_asm<K>(c, v, acc);
+}
+
 // value of lane `src` (0..15) of this 16-lane row (ds_bpermute)
 __device__ __forceinline__ float row_gather(float v, int src) {
   const int addr = ((int)(threadIdx.x & ~(ROW - 1)) + src) << 2;
@@ -183,8 +197,9 @@ struct Layout {
 
   // factor, [S][n][n] row-major.  FP64 Linv_t and M_t (adjoint); in
   // iteration precision the blocks the ADMM substitutions read (factor.h,
-  // FACTOR_WV / FACTOR_PK): SubA multiplies eta_t, SubB the forward result,
-  // ChF / ChB carry the forward / backward chains
+  // FACTOR_WV / FACTOR_PK): SubA multiplies eta_t (FP32: the packed Linv_t,
+  // which also gives Linv_t' v), SubB the forward result (FP64: P_t), ChF /
+  // ChB carry the forward / backward chains
   double* Linv64;
   double* M64;
   void* SubA;

@@ -142,9 +142,13 @@ __device__ __forceinline__ T quarter_pick(const T (&a)[K], int q) {
 // FORM selects the outputs (all row-major, [S][n][n]):
 //   FACTOR_M   (adjoint)  FP64 Linv_t and M_t.
 //   FACTOR_WV  (ADMM solve, FP32 iterations) in iteration precision
-//              SubA = Linv_t, SubB = Linv_t', ChF = W_t = Linv_t M_t (W_0 = 0),
+//              SubA = Linv_t packed (below), ChF = W_t = Linv_t M_t (W_0 = 0),
 //              ChB = V_t = Linv_t' M_{t+1}' (V_N = 0):
 //                v_t = Linv_t eta_t - W_t v_{t-1},  x_t = Linv_t' v_t - V_t x_{t+1}.
+//              Packed Linv_t: row i, entry e holds Linv_t[max(i,s)][min(i,s)]
+//              with s = (i - e) mod n, so one n x n block gives both
+//              Linv_t eta (entries with s <= i, dotl) and Linv_t' v (s >= i,
+//              dotu); SubB is not written.
 //   FACTOR_PK  (ADMM solve, FP64 iterations) SubB = P_t = (L_t L_t')^{-1},
 //              ChF = K_t = Phi_{t-1} P_{t-1} (K_0 = 0), ChB = Kb_t = K_{t+1}'
 //              (Kb_N = 0):
@@ -287,9 +291,8 @@ __device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, d
     }
     double Pc[PK ? 4 : 1];  // columns 4 qrow .. 4 qrow + 3 of P_t, row i
     if constexpr (WV) {
-      // rows / columns 4 qrow .. 4 qrow + 3 of Linv_t, W_t and V_{t-1}
-      const gptr<T> lr = as_global((T*)L.SubA + (size_t)s * nn + (size_t)i * n);
-      const gptr<T> lc = as_global((T*)L.SubB + (size_t)s * nn + i);
+      // columns 4 qrow .. 4 qrow + 3 of Linv_t (packed), W_t and V_{t-1}
+      const gptr<T> pk = as_global((T*)L.SubA + (size_t)s * nn);
       const gptr<T> wr = as_global((T*)L.ChF + (size_t)s * nn + (size_t)i * n);
       const gptr<T> vc = as_global((T*)L.ChB + (size_t)(t > 0 ? s - 1 : s) * nn + i);
       sfor<0, 4>([&](auto jj_) {
@@ -304,8 +307,9 @@ __device__ __noinline__ int factor_instance(const Layout& Lm, const Group& gm, d
           uji = dotb<n>(Mrow, quarter_pick<jj>(Xprev, qrow), 0.0);
         }
         if (vi && j < n) {
-          lr[j] = T(xj);
-          lc[(size_t)j * n] = T(xj);
+          // Linv_t[i][j], j <= i: entry i - j of row i and entry j - i + n of row j
+          if (j <= i) pk[i * n + i - j] = T(xj);
+          if (j < i) pk[j * n + j - i + n] = T(xj);
           if (t > 0) {
             wr[j] = T(wij);
             vc[(size_t)j * n] = T(uji);
@@ -615,19 +619,20 @@ __device__ __noinline__ int factor_chunked(const Layout& Lm, const Group& gm, do
       if (t < N) phi(Phi);
       if (store) {
         if constexpr (WV) {
-          // Linv_t (rows and columns), W_t, and V_{t-1} = (M_t Linv_{t-1})'
+          // Linv_t (packed), W_t, and V_{t-1} = (M_t Linv_{t-1})'
           double V[n];
           sfor<0, n>([&](auto j) {
             constexpr int jj = decltype(j)::value;
             V[jj] = dotb<n>(Mrow, Xprev[jj], 0.0);
           });
           if (vi) {
-            const gptr<T> lr = as_global((T*)L.SubA + (size_t)s * nn + (size_t)i * n);
-            const gptr<T> lc = as_global((T*)L.SubB + (size_t)s * nn + i);
+            // Linv_t packed: Linv_t[i][j], j <= i, to entry i - j of row i
+            // and entry j - i + n of row j
+            const gptr<T> pk = as_global((T*)L.SubA + (size_t)s * nn);
 #pragma unroll
             for (int j = 0; j < n; ++j) {
-              lr[j] = T(X[j]);
-              lc[(size_t)j * n] = T(X[j]);
+              if (j <= i) pk[i * n + i - j] = T(X[j]);
+              if (j < i) pk[j * n + j - i + n] = T(X[j]);
             }
             if (t > 0) {
               const gptr<T> wr = as_global((T*)L.ChF + (size_t)s * nn + (size_t)i * n);

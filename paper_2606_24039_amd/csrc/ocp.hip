@@ -248,7 +248,7 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
   const size_t SP = S1 + 2 * (size_t)STAGE_PAD;
   A_(h->Linv64, sizeof(double) * nn * S1);
   A_(h->M64, sizeof(double) * nn * S1);
-  if (h->mixed) A_(h->SubA, ts * nn * SP);  // Linv_t (FP32 iterations only)
+  if (h->mixed) A_(h->SubA, ts * nn * SP);  // packed Linv_t (FP32 iterations only)
   A_(h->SubB, ts * nn * SP);
   A_(h->ChF, ts * nn * SP);
   A_(h->ChB, ts * nn * SP);

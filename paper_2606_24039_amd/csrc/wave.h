@@ -378,7 +378,7 @@ template <typename T, int NX, int NU, int NG, bool TI>
 struct EtaIn {
   static constexpr int n = NX + NU;
   static constexpr bool SA = sizeof(T) == 4;  // FP32 iterations multiply by Linv_t here
-  T Ar[SA ? n : 1];                           // row `lane` of SubA
+  T Ar[SA ? n : 1];                           // row `lane` of SubA (packed Linv_t)
   T x, q, yf, yfm, zg, yg, bd, bdm;
   T AmC[TI ? 1 : NX], ApCm[TI ? 1 : NX], GC[TI ? 1 : NG];
 };
@@ -392,12 +392,31 @@ struct UpdIn {
   T AmR[TI ? 1 : n], ApR[TI ? 1 : n], GR[TI ? 1 : n];
 };
 
-// pass-3 inputs: row `lane` of SubB and v_t
+// pass-3 inputs: row `lane` of SubB (FP32: of the packed Linv_t) and v_t
 template <typename T, int n>
 struct TrIn {
   T Br[n];
   T v;
 };
+
+// the block pass 3 multiplies: FP32 Linv_t' (the packed Linv_t in SubA),
+// FP64 P_t (SubB)
+template <typename T, typename PP>
+__device__ __forceinline__ gptr<const T> sub_b_ptr(const PP& P) {
+  if constexpr (sizeof(T) == 4)
+    return P.SA;
+  else
+    return P.SB;
+}
+// s_t = SubB_t v_t on lane i, from row i of the block sub_b_ptr points to
+// (FP32: entries past n of v are zeroed for the shifted product)
+template <typename T, int n>
+__device__ __forceinline__ T sub_b_mul(const T (&B)[n], T v, int i) {
+  if constexpr (sizeof(T) == 4)
+    return dotu<n>(B, (n < ROW && i >= n) ? 0.f : v, 0.f);
+  else
+    return dotb<n>(B, v, T(0));
+}
 
 // r_t of the stage on this row: eta_t, times Linv_t for FP32 iterations.
 // `init` is this lane's initial-state term (rho_f x_init - y_init on lanes
@@ -438,7 +457,7 @@ __device__ __forceinline__ T stage_r(const IterCtx<T, NX, NU, NG, ST, LV>& c, co
     eta = dotb<NG>(cur.GC, u, eta);
   }
   if constexpr (EtaIn<T, NX, NU, NG, TI>::SA && !RAW)
-    return dotb<n>(cur.Ar, eta, T(0));
+    return dotl<n>(cur.Ar, eta, 0.f);
   else
     return eta;
 }
@@ -565,13 +584,13 @@ __device__ __forceinline__ void wave_iteration(const IterCtx<T, NX, NU, NG, ST, 
   {
     using In = TrIn<T, n>;
     auto load = [&](In& d, int blk) {
-      ldo_n<n>(d.Br, P.SB, lo.f + blk * LO::FB);
+      ldo_n<n>(d.Br, sub_b_ptr<T>(P), lo.f + blk * LO::FB);
       d.v = ldo(XV, lo.v + blk * LO::VB);
     };
     auto comp = [&](const In& d, int blk, auto full) {
       constexpr bool FULL = decltype(full)::value;
       const int t = 4 * blk + q;
-      const T s = dotb<n>(d.Br, d.v, T(0));
+      const T s = sub_b_mul<T, n>(d.Br, d.v, i);
       if (FULL || t <= N) sto(XV, lo.v + blk * LO::VB, s);
     };
     stage_blocks<STAGE_BLOCK_DEPTH, In>(nfull, load, comp);
@@ -822,7 +841,7 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
     auto load = [&](In& d, int k) {
       const int t = sg.a + k;
       ldo_n<n>(d.Cr, P.CF, of(t));
-      ldo_n<n>(d.Br, P.SB, of(t));
+      ldo_n<n>(d.Br, sub_b_ptr<T>(P), of(t));
       d.r = ldo(P.v, ov(t));
     };
     T v = vin;
@@ -830,7 +849,7 @@ __device__ __forceinline__ void wave_iteration_seg(const IterCtx<T, NX, NU, NG, 
       if (k >= sg.len) return;
       const int t = sg.a + k;
       v = d.r - dotb<n>(d.Cr, v, T(0));
-      sto(P.v, ov(t), dotb<n>(d.Br, v, T(0)));
+      sto(P.v, ov(t), sub_b_mul<T, n>(d.Br, v, i));
     };
     seg_walk<SEG_AHEAD<T, n, R>, In>(steps, load, comp);
   }
