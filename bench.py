@@ -230,7 +230,8 @@ def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=Non
            "nfact_sum": int(nfact.sum()),
            "status_counts": {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
            "kernels": {k: {"ms_per_step": ms / steps, "launches_per_step": c / steps} for k, (ms, c) in kt.items()},
-           "launch_shape": ({"segmented_from_horizon": shape[0], "segmented_from_iteration": shape[1]}
+           "launch_shape": ({"segmented_from_horizon": shape[0], "segmented_from_iteration": shape[1],
+                             "two_wavefront_from_iteration": shape[2]}
                             if shape else None)}
     if grad:
         ast = grads["adj_status"].cpu().numpy()
@@ -447,19 +448,25 @@ def main():
 
 
 def roofline(batch, res, prec, workload):
-    """Roofline of the dominant kernel (the persistent ADMM solve launch) by
-    the algorithmic work of one launch: F32 = instance-iterations x stages x
-    the flops of one stage-iteration, F64 = factorisations x stages x the
-    flops of one stage factorisation, bytes = problem data in plus solution
-    out.  Roofline time max(bytes / BW, F32 / peak32 + F64 / peak64); the
-    kernel is bound by the plain vector ALUs (no contraction is dense enough
-    for MFMA), so `achieved` is the FP32-equivalent rate against the FP32
-    vector peak and frac = roofline time / measured launch time.  The HBM
-    view (the design's factor stream) is reported beside it."""
+    """Roofline of the dominant kernel, the ADMM solve: one persistent launch
+    of one wavefront per instance, followed on the same stream, when the
+    two-wavefront continuation is on, by the launch that resumes the
+    instances still running at its iteration (the two launches of one solve
+    are timed together).  Algorithmic work of one solve: F32 =
+    instance-iterations x stages x the flops of one stage-iteration, F64 =
+    factorisations x stages x the flops of one stage factorisation, bytes =
+    problem data in plus solution out.  Roofline time max(bytes / BW, F32 /
+    peak32 + F64 / peak64); the kernels are bound by the plain vector ALUs
+    (no contraction is dense enough for MFMA), so `achieved` is the
+    FP32-equivalent rate against the FP32 vector peak and frac = roofline
+    time / measured solve time.  The HBM view (the design's factor stream)
+    is reported beside it."""
     f_it, f_fac = lti_flops_per_stage(batch.nx, batch.nu, batch.ng)
     stages = batch.N + 1
     kit = res["kernels"]["solve"]
-    launches = max(kit["launches_per_step"], 1)
+    tail = (res.get("launch_shape") or {}).get("two_wavefront_from_iteration", 0)
+    per_solve = 2 if tail else 1
+    launches = max(kit["launches_per_step"] / per_solve, 1)
     t_launch = kit["ms_per_step"] * 1e-3 / launches
     F32 = res["iters_sum"] * stages * f_it / launches
     F64 = res["nfact_sum"] * stages * f_fac / launches
@@ -475,8 +482,11 @@ def roofline(batch, res, prec, workload):
     traffic = TRAFFIC_BYTES.get((workload, prec, src))
     roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32, "unit": "TFLOP/s",
             "frac": round(t_roof / t_launch, 5), "traffic": traffic,
-            "kernel": f"admm_solve_wave_kernel<float,{batch.nx},{batch.nu},{batch.ng},box>",
-            "avg_launch_us": round(t_launch * 1e6, 2), "launches_per_step": kit["launches_per_step"],
+            "kernel": f"admm_solve_wave_kernel<float,{batch.nx},{batch.nu},{batch.ng},box>" + (
+                f" + admm_solve_tail_kernel<float,{batch.nx},{batch.nu},{batch.ng},box> (from iteration {tail})"
+                if tail else ""),
+            "avg_solve_us": round(t_launch * 1e6, 2), "launches_per_step": kit["launches_per_step"],
+            "launches_per_solve": per_solve,
             "flops_fp32_per_launch": F32, "flops_fp64_per_launch": F64, "bytes_per_launch": bytes_alg,
             "flops_per_stage_iteration": f_it, "flops_per_stage_factorisation": f_fac,
             "roofline_time_us": round(t_roof * 1e6, 2), "kernel_source": src}

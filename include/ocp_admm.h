@@ -428,20 +428,44 @@ ocp_status ocp_set_scaling_box(ocp_handle h, double p);
  * (null handle, negative iteration). */
 ocp_status ocp_set_segmented_after(ocp_handle h, int32_t iteration);
 
+/* Continuation of a batch's tail on two-wavefront workgroups (Sec.
+ * "Scalability to longer planning horizons"; FP32 iterations): from ADMM
+ * iteration `iteration` on, every instance solved on one wavefront that is
+ * still running (horizon N >= 31, direct primal updates) continues on a
+ * workgroup of two wavefronts.  The one-wavefront launch stops such an
+ * instance at that iteration with its iterate, rho, factorisation count and
+ * check state in device memory; a second launch on the same stream resumes
+ * it with 8 substitution segments (4 per wavefront) and, after a later rho
+ * change, the 9-chunk factorisation described at ocp_set_multiwave.  The
+ * schedule of checks and rho decisions is the same, so results agree with
+ * the one-wavefront solve up to rounding.  While the batch is full, one
+ * wavefront per instance keeps the memory system busiest; once few instances
+ * remain, each is bound by its own instruction stream, which two wavefronts
+ * split.  0 (the default) turns it off.  Drops a captured graph.  Errors:
+ * OCP_E_ARG (null handle, negative iteration), OCP_E_UNSUPPORTED (iteration
+ * > 0 on an FP64 handle), OCP_E_NOMEM (the continuation's buffers, allocated
+ * when first enabled: 8 B + 30 n^2 * 8 B per instance, plus 4 bytes),
+ * OCP_E_HIP. */
+ocp_status ocp_set_tail_workgroup(ocp_handle h, int32_t iteration);
+
 /* Autotuner over the launch shape: times `reps` cold-start ocp_solve calls
- * with settings `s` on the handle's own batch for each candidate pair
- * (segmented from horizon, every running instance segmented from iteration):
- * (15, never), (128, never), (never, never), (128, 150), (128, 300),
- * (128, 500) -- see ocp_set_segmented and ocp_set_segmented_after -- on
- * `stream` (one warm-up solve each; synchronises the stream), keeps the
- * fastest pair for later solves and returns it in *seg_min_n and *seg_after
- * (HOST int32; either may be NULL; never = INT32_MAX).  The solution state
- * afterwards is that of the last timed solve: solve again before reading
- * results.  Kernel timing is suspended while it runs.  Errors: OCP_E_ARG
- * (null handle / settings, reps < 1, invalid settings), OCP_E_ORDER (no
- * problem data), OCP_E_HIP. */
+ * with settings `s` on the handle's own batch for each candidate triple
+ * (segmented from horizon, every running instance segmented from iteration,
+ * continuation on two-wavefront workgroups from iteration): (15, never, 0),
+ * (128, never, 0), (never, never, 0), (128, 150, 0), (128, 300, 0),
+ * (128, 500, 0), and with FP32 iterations also (128, never, 200),
+ * (128, never, 300), (128, 150, 200) -- see ocp_set_segmented,
+ * ocp_set_segmented_after and ocp_set_tail_workgroup -- on `stream` (one
+ * warm-up solve each; synchronises the stream), keeps the fastest for later
+ * solves and returns it in *seg_min_n, *seg_after and *tail_after (HOST
+ * int32; any may be NULL; never = INT32_MAX, 0 = no continuation).  The
+ * solution state afterwards is that of the last timed solve: solve again
+ * before reading results.  Kernel timing is suspended while it runs.
+ * Errors: OCP_E_ARG (null handle / settings, reps < 1, invalid settings),
+ * OCP_E_ORDER (no problem data), OCP_E_NOMEM (the continuation's buffers),
+ * OCP_E_HIP. */
 ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void* stream, int32_t* seg_min_n,
-                        int32_t* seg_after);
+                        int32_t* seg_after, int32_t* tail_after);
 
 /* Bytes of device memory the library holds on every GPU it runs on, for the
  * life of the process, as the workspace of ocp_solve_noalloc. */

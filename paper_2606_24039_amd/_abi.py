@@ -97,9 +97,10 @@ SIGNATURES = [
     ("ocp_set_multiwave", C.c_int, [C.c_void_p, C.c_int32]),
     ("ocp_set_linsolve", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double]),
     ("ocp_set_segmented_after", C.c_int, [C.c_void_p, C.c_int32]),
+    ("ocp_set_tail_workgroup", C.c_int, [C.c_void_p, C.c_int32]),
     ("ocp_set_iterate", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ocp_autotune", C.c_int, [C.c_void_p, C.POINTER(ocp_settings), C.c_int32, C.c_void_p, C.POINTER(C.c_int32),
-                               C.POINTER(C.c_int32)]),
+                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     ("ocp_profile_read", C.c_int, [C.c_void_p, C.POINTER(ocp_kernel_times)]),
     ("ocp_set_scaling", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ocp_set_scaling_box", C.c_int, [C.c_void_p, C.c_double]),

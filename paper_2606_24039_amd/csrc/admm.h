@@ -160,6 +160,7 @@ constexpr int32_t ST_RUNNING = -1;
 template <typename T>
 __global__ void admm_init_kernel(Layout L, Settings st, int32_t* __restrict__ need) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0 && L.tail_count) *L.tail_count = 0;
   if (k < L.B) {
     L.status[k] = ST_RUNNING;
     L.iters[k] = 0;

@@ -220,6 +220,15 @@ struct Layout {
   const int32_t* mw_list;
   int n_mw, mw_min_n;
   double* FacXmw;
+  // continuation of one-wavefront instances on two-wavefront workgroups
+  // (Settings::tail_after): the instances handed over, their count (cleared
+  // by the per-solve init), per instance the state bits of the hand-over
+  // (bit 0: factorisation due, bit 1: multipliers of a check kept), and per
+  // list slot the chunked factorisation's exchange blocks
+  int32_t* tail_list;
+  int32_t* tail_count;
+  int32_t* tail_flags;
+  double* FacXtail;
   // PCG primal updates (pcg != 0): at most pcg_max_it iterations to the
   // relative residual pcg_tol; vectors [S][ROW] in iteration precision,
   // padded like the state vectors (x~, r, z, p, S p)
@@ -256,6 +265,8 @@ struct Settings {
   int max_iter, k_rho, k_check, adapt_rho, warm;
   int seg_min_n;  // horizons N >= seg_min_n run the segmented substitutions
   int seg_after;  // from this iteration on every instance (N >= 15) runs them (the batch's tail)
+  int tail_after;  // > 0: one-wavefront instances still running at this iteration continue on a
+                   // two-wavefront workgroup (admm_solve_tail_kernel); 0: off
 };
 
 struct Group {
@@ -293,6 +304,8 @@ __device__ __forceinline__ Layout uni(const Layout& L) {
   u.SubA = uni(L.SubA), u.SubB = uni(L.SubB), u.ChF = uni(L.ChF), u.ChB = uni(L.ChB);
   u.SegT = uni(L.SegT), u.SegU = uni(L.SegU), u.SegX = uni(L.SegX), u.FacX = uni(L.FacX);
   u.mw_list = uni(L.mw_list), u.n_mw = uni(L.n_mw), u.mw_min_n = uni(L.mw_min_n), u.FacXmw = uni(L.FacXmw);
+  u.tail_list = uni(L.tail_list), u.tail_count = uni(L.tail_count), u.tail_flags = uni(L.tail_flags);
+  u.FacXtail = uni(L.FacXtail);
   u.pcg = uni(L.pcg), u.pcg_max_it = uni(L.pcg_max_it), u.pcg_tol = uni(L.pcg_tol);
   u.pcg_xt = uni(L.pcg_xt), u.pcg_r = uni(L.pcg_r), u.pcg_z = uni(L.pcg_z), u.pcg_p = uni(L.pcg_p);
   u.pcg_sp = uni(L.pcg_sp);

@@ -106,9 +106,18 @@ void launch_solve(const Layout& L, const Settings& s, int32_t* need, hipStream_t
       hipLaunchKernelGGL((admm_solve_mw_kernel<T, NX, NU, NG, ST>), dim3(L.n_mw), dim3(64 * mw_waves<NX + NU>()), 0,
                          mst, L, s);
     });
-  if (L.n_mw < L.B)
+  if (L.n_mw < L.B) {
     timed(pf, OCP_K_SOLVE, st,
           [&] { hipLaunchKernelGGL((admm_solve_wave_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64), 0, st, L, s); });
+    // instances handed over at s.tail_after continue on two-wavefront
+    // workgroups (FP32 iterations; one block per instance, the unused exit)
+    if constexpr (sizeof(T) == 4) {
+      if (s.tail_after > 0 && L.tail_count)
+        timed(pf, OCP_K_SOLVE, st, [&] {
+          hipLaunchKernelGGL((admm_solve_tail_kernel<T, NX, NU, NG, ST>), dim3(L.B), dim3(64 * TAIL_W), 0, st, L, s);
+        });
+    }
+  }
   if (mst != st) {
     (void)hipEventRecord(fk->join, mst);
     (void)hipStreamWaitEvent(st, fk->join, 0);

@@ -86,6 +86,11 @@ struct ocp_handle_s {
   bool mw_off = false;  // no multi-wavefront workgroups (workspace carved by ocp_solve_noalloc)
   int32_t* mw_list = nullptr;
   double* FacXmw = nullptr;
+  // continuation of one-wavefront instances on two-wavefront workgroups from
+  // ADMM iteration tail_after (0: off); buffers allocated when first enabled
+  int tail_after = 0;
+  int32_t *tail_list = nullptr, *tail_count = nullptr, *tail_flags = nullptr;
+  double* FacXtail = nullptr;
   Fork fork;  // second stream for the workgroup launch of a mixed batch (created with the handle)
   std::vector<int32_t> horizons_host;
   // PCG primal updates (ocp_set_linsolve): mode, limits, vectors (allocated by the first switch to PCG)
@@ -459,6 +464,10 @@ Layout make_layout(ocp_handle h) {
   L.pcg_sp = h->pcg_sp;
   L.mw_min_n = h->mw_min_n;
   L.FacXmw = h->FacXmw;
+  L.tail_list = h->tail_list;
+  L.tail_count = h->tail_count;
+  L.tail_flags = h->tail_flags;
+  L.FacXtail = h->FacXtail;
   for (int k = 0; k < 16; ++k) {
     L.gsel[k] = h->gsel[k];
     L.ginv[k] = h->ginv[k];
@@ -612,6 +621,7 @@ void run_admm(ocp_handle h, const Settings& s_, hipStream_t st) {
   Settings s = s_;
   s.seg_min_n = h->seg_min_n;
   s.seg_after = h->seg_after;
+  s.tail_after = h->tail_after;
   const int ti = h->ti ? 1 : 0;
   const int var = (h->variant == VAR_LTI_BOX) ? VAR_LTI_BOX : (ti ? VAR_TI : VAR_TV);
   if (h->mixed)
@@ -1164,6 +1174,25 @@ ocp_status ocp_set_multiwave(ocp_handle h, int32_t mw_min_n) {
   return upload_mw_list(h);
 }
 
+ocp_status ocp_set_tail_workgroup(ocp_handle h, int32_t iteration) {
+  if (!h || iteration < 0) return OCP_E_ARG;
+  if (iteration > 0 && (!h->mixed || h->carve)) return OCP_E_UNSUPPORTED;
+  drop_graph(h);  // a captured graph keeps the launch shape it was recorded with
+  if (iteration > 0 && !h->tail_count) {
+    const size_t B = (size_t)h->B, nn = (size_t)h->n * h->n;
+    ocp_status st = halloc(h, &h->tail_list, sizeof(int32_t) * B, false);
+    if (st == OCP_OK) st = halloc(h, &h->tail_flags, sizeof(int32_t) * B, false);
+    if (st == OCP_OK) st = halloc(h, &h->FacXtail, sizeof(double) * nn * fx_slots(4 * TAIL_W) * B, false);
+    int32_t* cnt = nullptr;
+    if (st == OCP_OK) st = halloc(h, &cnt, sizeof(int32_t), false);
+    if (st != OCP_OK) return st;
+    if (hipMemset(cnt, 0, sizeof(int32_t)) != hipSuccess) return OCP_E_HIP;
+    h->tail_count = cnt;  // set last: a handle with a count has every tail buffer
+  }
+  h->tail_after = iteration;
+  return OCP_OK;
+}
+
 ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n) {
   if (!h) return OCP_E_ARG;
   if (h->graph_exec) {  // a captured graph keeps the launch shape it was recorded with
@@ -1225,7 +1254,7 @@ ocp_status ocp_set_scaling_box(ocp_handle h, double p) {
 }
 
 ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void* stream, int32_t* seg_min_n,
-                        int32_t* seg_after) {
+                        int32_t* seg_after, int32_t* tail_after) {
   if (!h || !s || reps < 1) return OCP_E_ARG;
   ocp_status st = check_settings(s);
   if (st != OCP_OK) return st;
@@ -1233,10 +1262,14 @@ ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void*
   hipStream_t stream_ = (hipStream_t)stream;
   ocp_settings cold = *s;
   cold.warm_start = 0;
-  // (segmented from horizon, every running instance segmented from iteration)
-  constexpr int NC = 6;
-  const int32_t cand[NC][2] = {{SEG_FLOOR_N, INT32_MAX}, {SEG_MIN_N, INT32_MAX}, {INT32_MAX, INT32_MAX},
-                               {SEG_MIN_N, 150},         {SEG_MIN_N, 300},       {SEG_MIN_N, 500}};
+  // (segmented from horizon, every running instance segmented from
+  // iteration, continuation on two-wavefront workgroups from iteration);
+  // the last three only with FP32 iterations
+  constexpr int NC = 9;
+  const int32_t cand[NC][3] = {{SEG_FLOOR_N, INT32_MAX, 0}, {SEG_MIN_N, INT32_MAX, 0}, {INT32_MAX, INT32_MAX, 0},
+                               {SEG_MIN_N, 150, 0},         {SEG_MIN_N, 300, 0},       {SEG_MIN_N, 500, 0},
+                               {SEG_MIN_N, INT32_MAX, 200}, {SEG_MIN_N, INT32_MAX, 300}, {SEG_MIN_N, 150, 200}};
+  const int nc = h->mixed && !h->carve ? NC : 6;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -1245,10 +1278,12 @@ ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void*
   const bool prof_on = h->prof.on;
   h->prof.on = false;
   float best = INFINITY;
-  int32_t pick = h->seg_min_n, pick_after = h->seg_after;
-  for (int c = 0; c < NC && st == OCP_OK; ++c) {
+  int32_t pick = h->seg_min_n, pick_after = h->seg_after, pick_tail = h->tail_after;
+  for (int c = 0; c < nc && st == OCP_OK; ++c) {
     h->seg_min_n = cand[c][0];
     h->seg_after = cand[c][1];
+    if (cand[c][2] > 0 || h->tail_after > 0) st = ocp_set_tail_workgroup(h, cand[c][2]);
+    if (st != OCP_OK) break;
     st = ocp_solve(h, &cold, nullptr, stream);  // warm-up (and first touch of the transfer blocks)
     if (st != OCP_OK) break;
     if (hipEventRecord(e0, stream_) != hipSuccess) st = OCP_E_HIP;
@@ -1257,7 +1292,7 @@ ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void*
     if (st == OCP_OK && (hipEventRecord(e1, stream_) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
       st = OCP_E_HIP;
-    if (st == OCP_OK && ms < best) best = ms, pick = cand[c][0], pick_after = cand[c][1];
+    if (st == OCP_OK && ms < best) best = ms, pick = cand[c][0], pick_after = cand[c][1], pick_tail = cand[c][2];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1265,8 +1300,10 @@ ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void*
   if (st != OCP_OK) return st;
   ocp_status r = ocp_set_segmented(h, pick);
   if (r == OCP_OK) r = ocp_set_segmented_after(h, pick_after);
+  if (r == OCP_OK) r = ocp_set_tail_workgroup(h, pick_tail);
   if (seg_min_n) *seg_min_n = h->seg_min_n;
   if (seg_after) *seg_after = h->seg_after;
+  if (tail_after) *tail_after = h->tail_after;
   return r;
 }
 

@@ -763,9 +763,13 @@ __device__ __forceinline__ T seg_link(T pe, int dir, XP X, TP TU, int q, int i) 
 #ifndef OCP_MW_AHEAD
 #define OCP_MW_AHEAD 2
 #endif
+#ifndef OCP_SEG_AHEAD_WIDE
+#define OCP_SEG_AHEAD_WIDE 2
+#endif
 template <typename T, int n, int R = 4>
-constexpr int SEG_AHEAD = R > 4 ? OCP_MW_AHEAD : (sizeof(T) == 4 && n <= 8) ? 4 : 2;
+constexpr int SEG_AHEAD = R > 4 ? OCP_MW_AHEAD : (sizeof(T) == 4 && n <= 8) ? 4 : OCP_SEG_AHEAD_WIDE;
 static_assert(SEG_AHEAD<float, 6> + 1 <= STAGE_PAD, "segmented prefetch beyond the padding stages");
+static_assert(SEG_AHEAD<float, 16> + 1 <= STAGE_PAD, "segmented prefetch beyond the padding stages");
 
 // inputs of one stage of the segmented forward sweep
 template <typename T, int NX, int NU, int NG, bool TI>
@@ -1677,7 +1681,9 @@ constexpr int mw_waves() { return mw_waves_of(n); }
 // shortest horizon taken by a W-wavefront workgroup: four stages per segment
 // (and at least three per factorisation chunk)
 __host__ __device__ constexpr int mw_floor_n(int W) { return 16 * W - 1; }
-static_assert(mw_floor_n(4) >= fac_chunk_min_n(16) && mw_floor_n(16) >= fac_chunk_min_n(64), "chunk floor");
+static_assert(mw_floor_n(2) >= fac_chunk_min_n(8) && mw_floor_n(4) >= fac_chunk_min_n(16) &&
+                  mw_floor_n(16) >= fac_chunk_min_n(64),
+              "chunk floor");
 // default: horizons from 256 stages take a workgroup
 constexpr int MW_MIN_N = 255;
 
@@ -1720,13 +1726,20 @@ struct MwShared {
   int bad[W];
 };
 
+// workgroup width of the continuation of a one-wavefront instance
+// (Settings::tail_after)
+constexpr int TAIL_W = 2;
+
 // One complete ADMM solve of one instance (Algorithm 3 with the stopping
 // test and rho adaptation): FP64 factorisation, iterations up to each
 // boundary, FP64 residuals and decisions at the boundary, refactorisation
 // after an accepted rho change.  W = 1: the whole solve on one wavefront;
 // W > 1: wavefront 0 of a W-wavefront workgroup, the heavy parts posted as
-// workgroup operations.
-template <typename T, int NX, int NU, int NG, typename ST, int W>
+// workgroup operations.  The iteration count, rho and the factorisation
+// count start from the instance's entries; RESUME: the solve continues one
+// that a one-wavefront solve handed over at st.tail_after (its factorisation
+// is current unless flagged, its check multipliers kept if flagged).
+template <typename T, int NX, int NU, int NG, typename ST, int W, bool RESUME = false>
 __device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings& st, const WaveGroup& w,
                                                 MwShared<T, NX, NU, NG, W>* sh, double* FX) {
   // the non-inlined callees get copies in memory: the kernel arguments
@@ -1763,6 +1776,13 @@ __device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings&
   bool need = true;
   bool have_prev = false;  // multipliers of an earlier check are kept (ypf, ypg)
   bool seg_ready = false;  // transfer blocks of the current factorisation are formed
+  if constexpr (RESUME) {
+    const int f = L.tail_flags[w.b];
+    need = (f & 1) != 0;
+    have_prev = (f & 2) != 0;
+  }
+  // a one-wavefront instance hands over to a workgroup at st.tail_after
+  const bool hand_over = W == 1 && st.tail_after > 0 && !L.pcg && w.N >= mw_floor_n(TAIL_W);
   // launch shape of the next iterations: long horizons always segmented; the
   // rest switch to it at iteration seg_after (few instances are left running
   // by then, and the shorter serial depth beats the extra block reads)
@@ -1804,6 +1824,7 @@ __device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings&
     if (st.k_check > 0) nb = min(nb, (k / st.k_check + 1) * st.k_check);
     if (adapt_on) nb = min(nb, (k / st.k_rho + 1) * st.k_rho);
     if (st.seg_after > k && st.seg_after < nb) nb = st.seg_after;  // the shape changes at a segment start
+    if (hand_over && st.tail_after > k && st.tail_after < nb) nb = st.tail_after;
     const bool seg = segmented(k);
     if (seg && !seg_ready) {
       if constexpr (W > 1) {
@@ -1841,6 +1862,14 @@ __device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings&
         local_sync();
         have_prev = true;
       }
+    }
+    if (hand_over && k >= st.tail_after) {
+      // the state stays in memory; admm_solve_tail_kernel continues the solve
+      if (threadIdx.x == 0) {
+        L.tail_flags[w.b] = (need ? 1 : 0) | (have_prev ? 2 : 0);
+        L.tail_list[atomicAdd(L.tail_count, 1)] = w.b;
+      }
+      break;
     }
   }
   if constexpr (W > 1) {
@@ -1889,6 +1918,39 @@ __global__ __launch_bounds__(64 * mw_waves<NX + NU>()) void admm_solve_mw_kernel
   double* FX = L.FacXmw + (size_t)slot * fx_slots(4 * W) * nn;
   if (threadIdx.x < 64) {
     admm_solve_body<T, NX, NU, NG, ST, W>(L, st, w, &sh, FX);
+    return;
+  }
+  const Layout Lc = L;
+  const Settings sc = st;
+  for (;;) {
+    __syncthreads();  // an operation has been posted
+    const MwCmd c = sh.cmd;
+    if (c.op == MW_EXIT) break;
+    mw_op<T, NX, NU, NG, ST, W>(Lc, sc, w.b, w.s0, w.N, c, (lptr<T>)sh.buf, FX, (lptr<int>)sh.bad);
+  }
+}
+
+// The continuation: one workgroup of TAIL_W wavefronts per instance that a
+// one-wavefront solve handed over (L.tail_list[0 .. *L.tail_count), list
+// slot = block); launched after admm_solve_wave_kernel on the same stream
+// with one block per instance of the batch, the blocks past the count exit.
+template <typename T, int NX, int NU, int NG, typename ST>
+__global__ __launch_bounds__(64 * TAIL_W) void admm_solve_tail_kernel(Layout L, Settings st) {
+  constexpr int W = TAIL_W;
+  constexpr int nn = (NX + NU) * (NX + NU);
+  __shared__ MwShared<T, NX, NU, NG, W> sh;
+  const int slot = blockIdx.x;
+  if (slot >= *L.tail_count) return;  // the whole workgroup
+  WaveGroup w;
+  w.lane = threadIdx.x & (ROW - 1);
+  w.row = (threadIdx.x >> 4) & 3;
+  w.b = L.tail_list[slot];
+  w.s0 = L.stage_off[w.b];
+  w.N = (int)(L.stage_off[w.b + 1] - w.s0) - 1;
+  if (L.status[w.b] != ST_RUNNING) return;
+  double* FX = L.FacXtail + (size_t)slot * fx_slots(4 * W) * nn;
+  if (threadIdx.x < 64) {
+    admm_solve_body<T, NX, NU, NG, ST, W, true>(L, st, w, &sh, FX);
     return;
   }
   const Layout Lc = L;

@@ -234,6 +234,11 @@ class OCPSolver:
         segmented substitutions (ocp_set_segmented_after)."""
         A.check(self.lib.ocp_set_segmented_after(self.h, int(iteration)), "ocp_set_segmented_after")
 
+    def set_tail_workgroup(self, iteration: int):
+        """One-wavefront instances still running at ADMM iteration `iteration`
+        continue on two-wavefront workgroups (ocp_set_tail_workgroup; 0: off)."""
+        A.check(self.lib.ocp_set_tail_workgroup(self.h, int(iteration)), "ocp_set_tail_workgroup")
+
     def set_linsolve(self, pcg: bool, max_iter: int = 50, tol: float = 1e-6):
         """Primal updates by block-Jacobi PCG (pcg=True) or the direct
         block-tridiagonal Cholesky (ocp_set_linsolve)."""
@@ -251,13 +256,14 @@ class OCPSolver:
 
     def autotune(self, settings=None, reps: int = 1, **overrides):
         """Time the launch-shape candidates on this batch and keep the fastest
-        (ocp_autotune); returns (segmented-from horizon, segmented-from iteration)."""
+        (ocp_autotune); returns (segmented-from horizon, segmented-from iteration,
+        two-wavefront continuation from iteration)."""
         s = settings if settings is not None else A.default_settings(**overrides)
-        n_min, after = C.c_int32(0), C.c_int32(0)
+        n_min, after, tail = C.c_int32(0), C.c_int32(0), C.c_int32(0)
         self.generation += 1
-        A.check(self.lib.ocp_autotune(self.h, C.byref(s), int(reps), _stream(), C.byref(n_min), C.byref(after)),
-                "ocp_autotune")
-        return int(n_min.value), int(after.value)
+        A.check(self.lib.ocp_autotune(self.h, C.byref(s), int(reps), _stream(), C.byref(n_min), C.byref(after),
+                                      C.byref(tail)), "ocp_autotune")
+        return int(n_min.value), int(after.value), int(tail.value)
 
     def split(self, arr, i):
         """Rows of a stage-concatenated array that belong to instance i."""

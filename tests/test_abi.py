@@ -71,7 +71,7 @@ def test_defaults_and_host_side_errors():
     assert lib.ocp_profile(None, 1) == _abi.OCP_E_ARG
     assert lib.ocp_profile_read(None, None) == _abi.OCP_E_ARG
     assert lib.ocp_set_segmented(None, 128) == _abi.OCP_E_ARG
-    assert lib.ocp_autotune(None, C.byref(s), 1, None, None, None) == _abi.OCP_E_ARG
+    assert lib.ocp_autotune(None, C.byref(s), 1, None, None, None, None) == _abi.OCP_E_ARG
 
 
 def test_product_path_has_no_cpu_fallback(monkeypatch):
