@@ -112,7 +112,8 @@ typedef struct {
   int32_t warm_start;      /* 1: start from the handle's current state and rho */
   int32_t max_sqp;         /* SQP iterations (bicycle model) */
   int32_t fixed_sqp;       /* 1: run exactly max_sqp iterations */
-  int32_t refine_sweeps;   /* adjoint iterative-refinement sweeps (default 8) */
+  int32_t refine_sweeps;   /* adjoint iterative-refinement sweeps, at most (default 8; an instance
+                              stops earlier once its relative residual is below adj_tol / 100) */
   int32_t adj_mode;        /* bicycle model: what ocp_adjoint differentiates (OCP_ADJ_LAST_QP,
                               OCP_ADJ_SQP_GN, OCP_ADJ_SQP_EXACT); ignored for linear models */
 } ocp_settings;

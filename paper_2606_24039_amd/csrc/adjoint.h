@@ -20,9 +20,10 @@
 //    with rho_f = rho_b and per-row inequality weights rho_b [row active].
 //    Iterative refinement e <- e + K_reg^{-1}(r - K e) with the residual in
 //    FP64 converges to K^{-1} r (the regularisation is a perturbation of
-//    size max(sigma_b, 1/rho_b)); refine_sweeps corrections, then the final
-//    residual ||r - K e||_inf / ||dL/dx||_inf is compared with adj_tol for
-//    the per-instance status.
+//    size max(sigma_b, 1/rho_b)); at most refine_sweeps corrections (fewer
+//    once ||r - K e||_inf / ||dL/dx||_inf is below adj_tol / 100), then the
+//    final residual ||r - K e||_inf / ||dL/dx||_inf is compared with adj_tol
+//    for the per-instance status.
 // 3. VJP (eq. loss_gradient): dL/dq = -eta_x, dL/dx_init = eta_f(initial
 //    rows), dL/dD_t[i,i] = -eta_x,t,i x_t,i, dL/dlo = eta_g on lower-active
 //    rows, dL/dhi = eta_g on upper-active rows.
@@ -61,6 +62,7 @@ struct AdjArgs {
   int32_t* adj_status;
   double *eta_xi, *d_gamma1;
   double adj_tol;  // relative KKT residual accepted as refined
+  double stop_res;  // the sweeps stop once ||r - K e||_inf <= stop_res (set per instance; 0: all sweeps)
 };
 
 // Blocks of stage t a row needs for the products with H, C and G (FP64).
@@ -256,6 +258,8 @@ __device__ __forceinline__ double adjoint_sweeps_ti(const Layout& L, const AdjAr
     }
     wave_sync();
     if (sweep == a.sweeps) break;
+    // refined before the last sweep: this residual is the final one
+    if (rows_max(row_max(rres)) <= a.stop_res) break;
     // passes 2-4: d_x = S^{-1} rhs
     if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
     wave_sync();
@@ -397,6 +401,24 @@ struct AdjMwLds {
   double red[R / 4];
 };
 
+// cross-wavefront reductions of a multi-wavefront adjoint (R > 4): every
+// lane holds its wavefront's value on entry and the workgroup's on return
+template <int R, typename F>
+__device__ __forceinline__ double adj_block_reduce(double v, double* red, F&& op) {
+  if constexpr (R == 4) {
+    return v;
+  } else {
+    constexpr int W = R / 4;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int k = 1; k < W; ++k) r = op(r, red[k]);
+    __syncthreads();  // the slots are reused by the next reduction
+    return r;
+  }
+}
+
 template <int NX, int NU, int NG, int NR = 4>
 __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjArgs& a, const WaveGroup& w, int bad,
                                                     bool slr, AdjMwLds<NX + NU, NR>* mw = nullptr) {
@@ -490,6 +512,10 @@ __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjAr
     }
     wave_sync();
     if (sweep == a.sweeps) break;
+    // refined before the last sweep: this residual is the final one
+    const double rmax = adj_block_reduce<NR>(rows_max(row_max(rres)), mw ? mw->red : nullptr,
+                                             [](double x, double y) { return fmax(x, y); });
+    if (rmax <= a.stop_res) break;
     // passes 2-4: d_x = S^{-1} rhs
     if constexpr (NR == 4) {
       if (q == 0) chain<double, n, +1>(Rb, Kb0, orow, oblk, N);
@@ -560,23 +586,6 @@ __device__ __forceinline__ double adjoint_sweeps_tv(const Layout& L, const AdjAr
   return rres;
 }
 
-// cross-wavefront reductions of a multi-wavefront adjoint (R > 4): every
-// lane holds its wavefront's value on entry and the workgroup's on return
-template <int R, typename F>
-__device__ __forceinline__ double adj_block_reduce(double v, double* red, F&& op) {
-  if constexpr (R == 4) {
-    return v;
-  } else {
-    constexpr int W = R / 4;
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double r = red[0];
-#pragma unroll
-    for (int k = 1; k < W; ++k) r = op(r, red[k]);
-    __syncthreads();  // the slots are reused by the next reduction
-    return r;
-  }
-}
 
 // The adjoint of one instance on R 16-lane rows: one wavefront (R = 4,
 // time-invariant or time-varying data) or a workgroup of R / 4 wavefronts
@@ -707,6 +716,8 @@ __device__ __forceinline__ void adjoint_body(const Layout& L, const AdjArgs& a, 
   }
 
   // ---- refinement sweeps, then the final FP64 residual ||r - K e||_inf ----
+  // (the sweeps end early once the residual is a hundredth of the accepted one)
+  ar.stop_res = 1e-2 * a.adj_tol * fmax(dlmax, 1e-300);
   double rres;
   if constexpr (ST::TI) {
     rres = adjoint_sweeps_ti<NX, NU, NG, ST>(L, ar, w, bad);
