@@ -31,16 +31,18 @@ SCALE_P = 0.6  # exponent of the box normalisation (ocp_set_scaling_box) on the 
 # per ADMM iteration, relative residual 1e-5 (about what FP32 iterations resolve)
 PCG_ITERS, PCG_TOL = 25, 1e-5
 
-# HBM traffic of the persistent solve launch, per launch, from two rocprofv3
+# HBM traffic of one ADMM solve (its launches: the one-wavefront launch and,
+# with the continuation on, the two-wavefront one), from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) of `bench.py --steps 1 --warmup 0
 # --cpu-sample 0 --no-fp64 --no-sub`, each scaled by the same counter's reading
 # for a plain 1 GiB device copy (`bench.py --copy-calibration 1024`).  Keyed by
 # (workload, precision, hash of the kernel sources): a changed kernel reports
 # null until it is profiled again.  Summary and commands:
-# profiles/admm_solve_wave_lti1024_n50.md.
+# profiles/admm_solve_wave_tail_lti1024_n50.md.
 TRAFFIC_BYTES = {
-    # FETCH_SIZE 17,247,041.8 KiB x 1.99994 + WRITE_SIZE 2,082,401.0 KiB x 1.000
-    ("c2", "mixed", "c7ee386cf4b9c0bc"): 37_453_187_581,
+    # one solve = admm_solve_wave_kernel + admm_solve_tail_kernel (continuation from iteration 200):
+    # FETCH_SIZE (14,691,843.3 + 721,480.8) KiB x 1.99994 + WRITE_SIZE (1,106,986.6 + 694,706.1) KiB x 1.000
+    ("c2", "mixed", "c6851d69a523cb30"): 33_410_403_915,
 }
 
 
@@ -101,6 +103,15 @@ def lti_bytes_per_stage(n, ts, blocks, k_seg=25):
     segment of `k_seg` iterations, so five of them (x, y_f, z_g, y_g, xi) move
     in and out once per segment."""
     return blocks * n * n * ts + (2 * 5 * 16 * ts) / k_seg
+
+
+def seg_bytes_per_stage(n, ts):
+    """The same for the segmented sweeps of the two-wavefront continuation:
+    the packed Linv_t and both chain blocks are read twice per iteration (the
+    particular and the true sweep of each chain), and the sweeps move 16
+    padded stage vectors through global memory (eta inputs, x~, the
+    exchange vector and the constraint-row state)."""
+    return 6 * n * n * ts + 16 * 16 * ts
 
 
 def make_workload(name):
@@ -223,11 +234,15 @@ def run_gpu(batch, precision, steps, warmup, settings_kw, grad=True, scale_p=Non
     if grad:  # "+grad": the instance's gradient must be refined to the tolerance too
         ok &= grads["adj_status"].cpu().numpy() == 0
     solved = int(ok.sum())
+    tail = shape[2] if shape else 0
     res = {"wall_s": wall, "ms_per_step": wall / steps * 1e3, "solved": solved, "batch": batch.batch,
            "iters_mean": float(iters.mean()), "iters_max": int(iters.max()), "iters_sum": int(iters.sum()),
            "iters_pct": {p: int(np.percentile(iters, p)) for p in (50, 90, 99)},
            "iters_capped": int((iters >= settings_kw.get("max_admm", 1000)).sum()),
            "nfact_sum": int(nfact.sum()),
+           # instance-iterations of the one-wavefront launch and of the continuation
+           "iters_split": [int(np.minimum(iters, tail).sum()) if tail else int(iters.sum()),
+                           int(np.maximum(iters - tail, 0).sum()) if tail else 0],
            "status_counts": {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
            "kernels": {k: {"ms_per_step": ms / steps, "launches_per_step": c / steps} for k, (ms, c) in kt.items()},
            "launch_shape": ({"segmented_from_horizon": shape[0], "segmented_from_iteration": shape[1],
@@ -491,8 +506,11 @@ def roofline(batch, res, prec, workload):
             "flops_per_stage_iteration": f_it, "flops_per_stage_factorisation": f_fac,
             "roofline_time_us": round(t_roof * 1e6, 2), "kernel_source": src}
     b_it = lti_bytes_per_stage(n, 4, 3)
-    design_bytes = res["iters_sum"] * stages * b_it / launches
+    b_seg = seg_bytes_per_stage(n, 4)
+    it_one, it_cont = res["iters_split"]
+    design_bytes = (it_one * b_it + it_cont * b_seg) * stages / launches
     hbm = {"design_bytes_per_launch": design_bytes, "bytes_per_stage_iteration": b_it,
+           "bytes_per_stage_iteration_continuation": b_seg, "instance_iterations": [it_one, it_cont],
            "achieved_GBps": round(design_bytes / t_launch / 1e9, 1), "peak_GBps": PEAK_HBM,
            "frac": round(design_bytes / t_launch / 1e9 / PEAK_HBM, 4), "measured_traffic": traffic}
     return roof, hbm
