@@ -517,10 +517,12 @@ def roofline(batch, res, prec, workload):
 
 
 def sub_results(args):
-    """The other linear workloads, each at a few steps: the differentiation
-    batch (512 random LTI instances, N = 64, +grad, gated at 1e-4; FP32
-    iterations and plain FP64) and the single double integrator (N = 20, FP64,
-    200 iterations at fixed rho: per-solve latency, and 64 copies)."""
+    """The other workloads, each at a few steps: the differentiation batch
+    (512 random LTI instances, N = 64, +grad, gated at 1e-4; FP32 iterations
+    and plain FP64), the single double integrator (N = 20, FP64, 200
+    iterations at fixed rho: per-solve latency, and 64 copies) and the
+    kinematic-bicycle SQP workloads (4096 x N = 100, one N = 8192 instance,
+    256 ragged horizons)."""
     from workloads import double_integrator, random_lti
 
     sub = {}
@@ -543,6 +545,19 @@ def sub_results(args):
             "ms_per_step": round(r["ms_per_step"], 4), "solves_per_s": round(B / (r["ms_per_step"] * 1e-3), 1),
             "unit": "QP solves/s (200 fixed-rho FP64 iterations)", "solve_kernel_ms": round(
                 r["kernels"]["solve"]["ms_per_step"], 4)}
+    # the bicycle workloads (10 SQP x 50 ADMM iterations, fixed counts, FP32
+    # iterations + the adjoint of the last QP), two timed steps each
+    from workloads import bicycle_batch, bicycle_long_and_ragged
+
+    lng, rag = bicycle_long_and_ragged(seed=5)
+    kwb = dict(max_sqp=10, max_admm=50, k_check=0, k_rho=25, fixed_sqp=1)
+    for name, bb in (("c3_bicycle4096_n100", bicycle_batch(4096, N=100, seed=3)),
+                     ("c5a_bicycle1_n8192", lng), ("c5b_bicycle256_ragged", rag)):
+        r = run_bicycle(bb, 1, 2, 1, kwb, grad=True)
+        sub[name] = {"value": round(bb.batch / (r["ms_per_step"] * 1e-3), 2),
+                     "unit": "SQP solves/s (10 SQP x 50 ADMM iterations, + adjoint)",
+                     "ms_per_step": round(r["ms_per_step"], 3), "kernel_ms_per_step": r["kernel_ms_per_step"],
+                     "sqp_kkt_max": r["sqp_kkt_max"], "steps": 2}
     log(f"[bench] sub-results: {json.dumps(sub)}")
     return sub
 
