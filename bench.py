@@ -97,9 +97,10 @@ def lti_flops_per_stage(nx, nu, ng):
 
 def lti_bytes_per_stage(n, ts, blocks, k_seg=25):
     """Algorithmic bytes one ADMM iteration moves per stage, for the design
-    measured here (FP32 iterations, horizons up to 55 stages): the `blocks`
-    n x n factor blocks (the packed Linv_t, W_t, V_t) stream from memory once per
-    iteration; the six padded 16-entry stage vectors stay in LDS for a
+    measured here (FP32 iterations, horizons up to 55 stages): `blocks` n x n
+    factor blocks stream from memory per iteration (W_t and V_t once each, the
+    packed Linv_t twice: pass 1 and pass 3 read it, and an instance's blocks do
+    not stay in the L2 between them); the six padded 16-entry stage vectors stay in LDS for a
     segment of `k_seg` iterations, so five of them (x, y_f, z_g, y_g, xi) move
     in and out once per segment."""
     return blocks * n * n * ts + (2 * 5 * 16 * ts) / k_seg
@@ -505,7 +506,7 @@ def roofline(batch, res, prec, workload):
             "flops_fp32_per_launch": F32, "flops_fp64_per_launch": F64, "bytes_per_launch": bytes_alg,
             "flops_per_stage_iteration": f_it, "flops_per_stage_factorisation": f_fac,
             "roofline_time_us": round(t_roof * 1e6, 2), "kernel_source": src}
-    b_it = lti_bytes_per_stage(n, 4, 3)
+    b_it = lti_bytes_per_stage(n, 4, 4)
     b_seg = seg_bytes_per_stage(n, 4)
     it_one, it_cont = res["iters_split"]
     design_bytes = (it_one * b_it + it_cont * b_seg) * stages / launches
