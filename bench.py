@@ -530,14 +530,14 @@ def sub_results(args):
     b4 = random_lti(512, N=64, seed=4)
     kw = dict(eps_abs=1e-4, eps_rel=1e-4, max_admm=1000, k_check=25, k_rho=25, eps_active=1e-4)
     steps = max(3, min(args.steps, 10))
-    m = run_gpu(b4, 1, steps, 2, kw, grad=True, scale_p=None if args.no_scaling else SCALE_P)
+    m = run_gpu(b4, 1, steps, 2, kw, grad=True, scale_p=None if args.no_scaling else SCALE_P, tune=not args.no_tune)
     f = run_gpu(b4, 0, steps, 1, kw, grad=True)
     sub["c4_lti512_n64_grad"] = {
         "value": round(m["solved"] / (m["ms_per_step"] * 1e-3), 1), "unit": "QP solves/s (gated, +grad)",
         "ms_per_step": round(m["ms_per_step"], 4), "solved_fraction": m["solved"] / b4.batch,
         "iters_mean": round(m["iters_mean"], 1), "iters_capped": m["iters_capped"],
         "fp64_value": round(f["solved"] / (f["ms_per_step"] * 1e-3), 1), "fp64_ms_per_step": round(f["ms_per_step"], 4),
-        "fp64_solved_fraction": f["solved"] / b4.batch, "steps": steps}
+        "fp64_solved_fraction": f["solved"] / b4.batch, "steps": steps, "launch_shape": m["launch_shape"]}
     kw1 = dict(max_admm=200, k_check=0, adapt_rho=0)
     for B in (1, 64):
         b1 = double_integrator(B, N=20, seed=1)
