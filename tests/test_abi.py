@@ -71,6 +71,9 @@ def test_defaults_and_host_side_errors():
     assert lib.ocp_profile(None, 1) == _abi.OCP_E_ARG
     assert lib.ocp_profile_read(None, None) == _abi.OCP_E_ARG
     assert lib.ocp_set_segmented(None, 128) == _abi.OCP_E_ARG
+    assert lib.ocp_set_segmented_after(None, 150) == _abi.OCP_E_ARG
+    assert lib.ocp_set_tail_workgroup(None, 200) == _abi.OCP_E_ARG
+    assert lib.ocp_set_multiwave(None, 255) == _abi.OCP_E_ARG
     assert lib.ocp_autotune(None, C.byref(s), 1, None, None, None, None) == _abi.OCP_E_ARG
 
 
