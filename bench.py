@@ -41,8 +41,8 @@ PCG_ITERS, PCG_TOL = 25, 1e-5
 # profiles/admm_solve_wave_tail_lti1024_n50.md.
 TRAFFIC_BYTES = {
     # one solve = admm_solve_wave_kernel + admm_solve_tail_kernel (continuation from iteration 200):
-    # FETCH_SIZE (14,691,843.3 + 721,480.8) KiB x 1.99994 + WRITE_SIZE (1,106,986.6 + 694,706.1) KiB x 1.000
-    ("c2", "mixed", "c6851d69a523cb30"): 33_410_403_915,
+    # FETCH_SIZE (14,708,718.4 + 699,035.4) KiB x 1.99994 + WRITE_SIZE (1,097,993.8 + 773,955.6) KiB x 1.000
+    ("c2", "mixed", "d82b077f4e32754a"): 33_470_944_306,
 }
 
 

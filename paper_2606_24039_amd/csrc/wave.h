@@ -1110,7 +1110,7 @@ __device__ __forceinline__ T rows_max(T v) {
 // admm:termination:slack with the stages spread over the four rows (stage t
 // on row t mod 4); every row reads the neighbouring stages it needs directly.
 // General form: the blocks of every stage are read where they are used.
-template <typename T, int NX, int NU, int NG, bool TI>
+template <typename T, int NX, int NU, int NG, bool TI, int RR = 4>
 __device__ __forceinline__ Resid residuals_gen(const Layout& L, const WaveGroup& w, int kind, double gamma2,
                                                double gamma1) {
   constexpr int n = NX + NU;
@@ -1161,9 +1161,9 @@ __device__ __forceinline__ Resid residuals_gen(const Layout& L, const WaveGroup&
   }
   const double yinit = double(YF[(size_t)(w.s0 + N) * ROW + i]);
   const double xi0 = as_global(L.x_init)[(size_t)b * NX + ix];
-  const int nbl = (N + 4) / 4;
+  const int nbl = (N + RR) / RR;
   for (int blk = 0; blk < nbl; ++blk) {
-    const int t = 4 * blk + q;
+    const int t = RR * blk + q;
     if (t > N) break;
     const int64_t s = w.s0 + t;
     const size_t sv = (size_t)s * ROW + i;
@@ -1276,7 +1276,7 @@ struct ResIn {
 // The same residuals for time-invariant data: blocks read once (FP64), the
 // explicit-dynamics and selection structure of ST used, stage inputs loaded
 // two blocks ahead.
-template <typename T, int NX, int NU, int NG, typename ST>
+template <typename T, int NX, int NU, int NG, typename ST, int RR = 4>
 __device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& w, int kind, double gamma2,
                                               double gamma1) {
   constexpr int n = NX + NU;
@@ -1310,7 +1310,7 @@ __device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& 
     mu = fmax(mu, fabs(v) * wgt);
   };
   auto load = [&](ResIn<T>& d, int blk) {
-    const int t = 4 * blk + q;
+    const int t = RR == 4 ? 4 * blk + q : min(RR * blk + q, N + 1);  // loads stay within the padding
     const uint32_t o = (uint32_t)(((STAGE_PAD + t) * ROW + i) * (int)sizeof(T));
     d.xc = ldo(X, o);
     d.xm = ldo<-VS>(X, o);
@@ -1324,7 +1324,7 @@ __device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& 
   };
   auto comp = [&](const ResIn<T>& d, int blk, auto full) {
     constexpr bool FULL = decltype(full)::value;
-    const int t = 4 * blk + q;
+    const int t = RR * blk + q;
     if (!FULL && t > N) return;
     const bool thi = FULL || t < N, xr = i < NX;
     const double xc = double(d.xc);
@@ -1400,7 +1400,7 @@ __device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& 
       }
     }
   };
-  stage_blocks<STAGE_BLOCK_DEPTH, ResIn<T>>(N / 4, load, comp);
+  stage_blocks<STAGE_BLOCK_DEPTH, ResIn<T>>(N / RR, load, comp);
   Resid R;
   R.rp = rows_max(row_max(fmax(m_cxc, m_gxz)));
   R.ps = rows_max(row_max(fmax(fmax(m_cx, m_gx), fmax(m_c, m_z))));
@@ -1418,7 +1418,10 @@ __device__ __forceinline__ Resid residuals_ti(const Layout& L, const WaveGroup& 
   return R;
 }
 
-template <typename T, int NX, int NU, int NG, typename ST, int TAG = 0>
+// RR: rows the stages are spread over (4: one wavefront; 4 W: the rows of a
+// W-wavefront workgroup, wm.row the row in the workgroup, each wavefront's
+// maxima then combined by the caller)
+template <typename T, int NX, int NU, int NG, typename ST, int TAG = 0, int RR = 4>
 __device__ __noinline__ Resid residuals_wave(const Layout& Lm, const WaveGroup& wm, int kind, double gamma2_,
                                              double gamma1_) {
   const Layout L = uni(Lm);
@@ -1426,9 +1429,9 @@ __device__ __noinline__ Resid residuals_wave(const Layout& Lm, const WaveGroup& 
   w.b = uni(wm.b), w.s0 = uni(wm.s0), w.N = uni(wm.N);
   const double gamma2 = uni(gamma2_), gamma1 = uni(gamma1_);
   if constexpr (ST::TI)
-    return residuals_ti<T, NX, NU, NG, ST>(L, w, kind, gamma2, gamma1);
+    return residuals_ti<T, NX, NU, NG, ST, RR>(L, w, kind, gamma2, gamma1);
   else
-    return residuals_gen<T, NX, NU, NG, false>(L, w, kind, gamma2, gamma1);
+    return residuals_gen<T, NX, NU, NG, false, RR>(L, w, kind, gamma2, gamma1);
 }
 
 // Primal-infeasibility certificate at a convergence check (the test of
@@ -1439,12 +1442,20 @@ __device__ __noinline__ Resid residuals_wave(const Layout& Lm, const WaveGroup& 
 // < -eps ||dy||_inf (Farkas).  Evaluated in the original variables of a
 // rescaled QP; a nonzero dy on a soft row fails it.  Stages spread over the
 // four rows as in the residuals; blocks read from the FP64 master data.
-template <typename T, int NX, int NU, int NG, int TAG = 0>
-__device__ __noinline__ int pinf_wave(const Layout& Lm, const WaveGroup& wm, double eps_) {
+// parts of the test (maxima of |A'dy| and |dy|, the support value, a soft
+// row with a change), reduced over the rows of one wavefront
+struct PinfPart {
+  double m_aty, m_dy, sup;
+  int soft_bad;
+};
+__device__ __forceinline__ int pinf_decide(const PinfPart& p, double eps) {
+  return (p.m_dy > 0.0 && !p.soft_bad && p.m_aty <= eps * p.m_dy && p.sup < -eps * p.m_dy) ? 1 : 0;
+}
+template <typename T, int NX, int NU, int NG, int TAG = 0, int RR = 4>
+__device__ __noinline__ PinfPart pinf_parts(const Layout& Lm, const WaveGroup& wm) {
   const Layout L = uni(Lm);
   const int b = uni(wm.b), N = uni(wm.N);
   const int64_t s0 = uni(wm.s0);
-  const double eps = uni(eps_);
   constexpr int n = NX + NU;
   const int i = wm.lane, q = wm.row;
   const int ic = i < n ? i : n - 1, ix = i < NX ? i : NX - 1, ig = i < NG ? i : NG - 1;
@@ -1459,7 +1470,7 @@ __device__ __noinline__ int pinf_wave(const Layout& Lm, const WaveGroup& wm, dou
   const double xi0 = L.x_init[(size_t)b * NX + ix];
   double m_aty = 0.0, m_dy = 0.0, sup = 0.0;
   int soft_bad = 0;
-  for (int t = q; t <= N; t += 4) {
+  for (int t = q; t <= N; t += RR) {
     const int64_t s = s0 + t;
     const size_t sv = (size_t)s * ROW + i;
     const double dyfc = (t < N && i < NX) ? double(YF[sv]) - double(PF[sv]) : 0.0;
@@ -1498,7 +1509,11 @@ __device__ __noinline__ int pinf_wave(const Layout& Lm, const WaveGroup& wm, dou
   sup += __shfl_xor(sup, 32);
   sup *= rw.s;  // original variables: the support value of the rescaled QP over c
   soft_bad = rows_max(row_max(soft_bad));
-  return (m_dy > 0.0 && !soft_bad && m_aty <= eps * m_dy && sup < -eps * m_dy) ? 1 : 0;
+  return PinfPart{m_aty, m_dy, sup, soft_bad};
+}
+template <typename T, int NX, int NU, int NG, int TAG = 0>
+__device__ __forceinline__ int pinf_wave(const Layout& Lm, const WaveGroup& wm, double eps) {
+  return pinf_decide(pinf_parts<T, NX, NU, NG, TAG>(Lm, wm), eps);
 }
 
 // y_f, y_g -> the previous-check copies (every stage of the instance)
@@ -1661,7 +1676,14 @@ __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, in
 // each operation in LDS and meets the others at a barrier; the others loop
 // on posted operations until MW_EXIT.  Every operation ends with a barrier,
 // so between operations wavefront 0 alone runs, with wavefront-local syncs.
-enum { MW_EXIT = 0, MW_FACTOR = 1, MW_PREP = 2, MW_ITERS = 3 };
+enum { MW_EXIT = 0, MW_FACTOR = 1, MW_PREP = 2, MW_ITERS = 3, MW_CHECK = 4 };
+// MW_CHECK parts (MwCmd::k): FP64 residuals, infeasibility certificate,
+// keep the multipliers for the next certificate
+enum { MW_CHECK_RESID = 1, MW_CHECK_PINF = 2, MW_CHECK_KEEP = 4 };
+// LDS slots of the cross-wavefront reductions of MW_CHECK: per wavefront
+// MW_RED_F doubles (the eight residual maxima, non-finite flag, the three
+// certificate parts, its soft-row flag), then the combined values
+constexpr int MW_RED_F = 16;
 struct MwCmd {
   int op, k, nb;
   double rho_bar;
@@ -1694,10 +1716,10 @@ __device__ __forceinline__ void wave_local_sync() {
 
 // One workgroup operation (all W wavefronts; ends with a barrier).  buf: the
 // LDS transfer blocks and exchange slots; FX: the chunked factorisation's
-// exchange blocks; bad: one flag per wavefront.
+// exchange blocks; bad: one flag per wavefront; red: the MW_CHECK reductions.
 template <typename T, int NX, int NU, int NG, typename ST, int W>
 __device__ __noinline__ void mw_op(const Layout& Lm, const Settings& st, int b_, int64_t s0_, int N_, MwCmd c,
-                                   lptr<T> buf, double* FX, lptr<int> bad) {
+                                   lptr<T> buf, double* FX, lptr<int> bad, lptr<double> red) {
   constexpr int R = 4 * W;
   constexpr int nn = (NX + NU) * (NX + NU);
   const int b = uni(b_), N = uni(N_), op = uni(c.op);
@@ -1713,6 +1735,53 @@ __device__ __noinline__ void mw_op(const Layout& Lm, const Settings& st, int b_,
     prepare_segments<T, NX, NU, NG, R>(Lm, b, s0, N, buf, buf + R * nn);
   } else if (op == MW_ITERS) {
     run_segment<T, NX, NU, NG, ST, true, R>(Lm, st, b, s0, N, uni(c.k), uni(c.nb), rho_bar, buf);
+  } else if (op == MW_CHECK) {
+    // the boundary's FP64 work with the stages over all R rows; each
+    // wavefront's maxima / sums into LDS, combined by thread 0
+    const int parts = uni(c.k);
+    WaveGroup wg;
+    wg.lane = (int)(threadIdx.x & (ROW - 1));
+    wg.row = (int)(threadIdx.x >> 4);
+    wg.b = b, wg.s0 = s0, wg.N = N;
+    const int i = wg.lane, wv = (int)(threadIdx.x >> 6);
+    const bool lead = (threadIdx.x & 63) == 0;
+    if (parts & MW_CHECK_RESID) {
+      const int kind = (i < NG) ? (int)Lm.soft[i] : 0;
+      const Resid P = residuals_wave<T, NX, NU, NG, ST, 1, R>(Lm, wg, kind, Lm.gamma2, Lm.gamma1);
+      if (lead) {
+        lptr<double> r = red + wv * MW_RED_F;
+        r[0] = P.rp, r[1] = P.rd, r[2] = P.ps, r[3] = P.ds;
+        r[4] = P.rp_u, r[5] = P.rd_u, r[6] = P.ps_u, r[7] = P.ds_u;
+        r[8] = (double)P.nonfinite;
+      }
+    }
+    if (parts & MW_CHECK_PINF) {
+      const PinfPart P = pinf_parts<T, NX, NU, NG, 1, R>(Lm, wg);
+      if (lead) {
+        lptr<double> r = red + wv * MW_RED_F;
+        r[9] = P.m_aty, r[10] = P.m_dy, r[11] = P.sup, r[12] = (double)P.soft_bad;
+      }
+    }
+    if (parts & MW_CHECK_KEEP) {
+      T* yf = (T*)Lm.yf;
+      T* yg = (T*)Lm.yg;
+      T* pf = (T*)Lm.ypf;
+      T* pg = (T*)Lm.ypg;
+      for (int e = (int)threadIdx.x; e < (N + 1) * ROW; e += 64 * W) {
+        const size_t k = (size_t)s0 * ROW + e;
+        pf[k] = yf[k];
+        pg[k] = yg[k];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      lptr<double> o = red + W * MW_RED_F;
+      for (int f = 0; f < MW_RED_F; ++f) {
+        double v = red[f];
+        for (int k = 1; k < W; ++k) v = (f == 11) ? v + red[k * MW_RED_F + f] : fmax(v, red[k * MW_RED_F + f]);
+        o[f] = v;
+      }
+    }
   }
   __syncthreads();
 }
@@ -1724,6 +1793,7 @@ struct MwShared {
   T buf[2 * R * nn + 2 * R * ROW];  // T blocks, U blocks, exchange slots
   MwCmd cmd;
   int bad[W];
+  double red[(W + 1) * MW_RED_F];  // MW_CHECK reductions
 };
 
 // workgroup width of the continuation of a one-wavefront instance
@@ -1761,7 +1831,7 @@ __device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings&
       if (threadIdx.x == 0) sh->cmd = MwCmd{op, k, nb, rho_bar};
       __syncthreads();
       mw_op<T, NX, NU, NG, ST, W>(Lc, sc, w.b, w.s0, w.N, MwCmd{op, k, nb, rho_bar}, (lptr<T>)sh->buf, FX,
-                                  (lptr<int>)sh->bad);
+                                  (lptr<int>)sh->bad, (lptr<double>)sh->red);
     }
   };
   auto local_sync = [&] {
@@ -1850,16 +1920,29 @@ __device__ __forceinline__ void admm_solve_body(const Layout& L, const Settings&
     const int adapt = (adapt_on && nb % st.k_rho == 0) ? 1 : 0;
     const int last = (nb == st.max_iter) ? 1 : 0;
     if (check || adapt || last) {
-      R = residuals_wave<T, NX, NU, NG, ST, TAG>(Lc, w, kind, L.gamma2, L.gamma1);
       // infeasibility test from the second check on (the first has no earlier multipliers)
-      const int pinf =
-          (check && have_prev && st.eps_pinf > 0.0) ? pinf_wave<T, NX, NU, NG, TAG>(Lc, w, st.eps_pinf) : 0;
+      const bool want_pinf = check && have_prev && st.eps_pinf > 0.0;
+      int pinf = 0;
+      if constexpr (W > 1) {
+        // on every row of the workgroup (MW_CHECK), the combined values in sh->red
+        post(MW_CHECK, MW_CHECK_RESID | (want_pinf ? MW_CHECK_PINF : 0), 0);
+        const double* o = sh->red + W * MW_RED_F;
+        R = Resid{o[0], o[1], o[2], o[3], o[4], o[5], o[6], o[7], (int)o[8]};
+        if (want_pinf) pinf = pinf_decide(PinfPart{o[9], o[10], o[11], (int)o[12]}, st.eps_pinf);
+      } else {
+        R = residuals_wave<T, NX, NU, NG, ST, TAG>(Lc, w, kind, L.gamma2, L.gamma1);
+        if (want_pinf) pinf = pinf_wave<T, NX, NU, NG, TAG>(Lc, w, st.eps_pinf);
+      }
       status = boundary_decision(R, st, check, adapt, last, pinf, rho_bar, need);
       if (status != ST_RUNNING) break;
       if (check && st.eps_pinf > 0.0) {
-        local_sync();
-        keep_multipliers<T>(Lc, w);
-        local_sync();
+        if constexpr (W > 1) {
+          post(MW_CHECK, MW_CHECK_KEEP, 0);
+        } else {
+          local_sync();
+          keep_multipliers<T>(Lc, w);
+          local_sync();
+        }
         have_prev = true;
       }
     }
@@ -1926,7 +2009,8 @@ __global__ __launch_bounds__(64 * mw_waves<NX + NU>()) void admm_solve_mw_kernel
     __syncthreads();  // an operation has been posted
     const MwCmd c = sh.cmd;
     if (c.op == MW_EXIT) break;
-    mw_op<T, NX, NU, NG, ST, W>(Lc, sc, w.b, w.s0, w.N, c, (lptr<T>)sh.buf, FX, (lptr<int>)sh.bad);
+    mw_op<T, NX, NU, NG, ST, W>(Lc, sc, w.b, w.s0, w.N, c, (lptr<T>)sh.buf, FX, (lptr<int>)sh.bad,
+                                (lptr<double>)sh.red);
   }
 }
 
@@ -1959,7 +2043,8 @@ __global__ __launch_bounds__(64 * TAIL_W) void admm_solve_tail_kernel(Layout L, 
     __syncthreads();  // an operation has been posted
     const MwCmd c = sh.cmd;
     if (c.op == MW_EXIT) break;
-    mw_op<T, NX, NU, NG, ST, W>(Lc, sc, w.b, w.s0, w.N, c, (lptr<T>)sh.buf, FX, (lptr<int>)sh.bad);
+    mw_op<T, NX, NU, NG, ST, W>(Lc, sc, w.b, w.s0, w.N, c, (lptr<T>)sh.buf, FX, (lptr<int>)sh.bad,
+                                (lptr<double>)sh.red);
   }
 }
 
