@@ -36,20 +36,46 @@ PCG_ITERS, PCG_TOL = 25, 1e-5
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) of `bench.py --steps 1 --warmup 0
 # --cpu-sample 0 --no-fp64 --no-sub`, each scaled by the same counter's reading
 # for a plain 1 GiB device copy (`bench.py --copy-calibration 1024`).  Keyed by
-# (workload, precision, hash of the kernel sources): a changed kernel reports
-# null until it is profiled again.  Summary and commands:
+# (workload, precision, hash of the kernel code, comments and layout left
+# out): a changed kernel reports null until it is profiled again.  Summary and commands:
 # profiles/admm_solve_wave_tail_lti1024_n50.md.
 TRAFFIC_BYTES = {
     # one solve = admm_solve_wave_kernel + admm_solve_tail_kernel (continuation from iteration 200):
     # FETCH_SIZE (14,708,718.4 + 699,035.4) KiB x 1.99994 + WRITE_SIZE (1,097,993.8 + 773,955.6) KiB x 1.000
-    ("c2", "mixed", "d82b077f4e32754a"): 33_470_944_306,
+    ("c2", "mixed", "439f73a5bfd54c19"): 33_470_944_306,
 }
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without its comments, whitespace runs collapsed (string
+    and character literals kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
-    """sha256 (16 hex digits) over the sources the kernels are compiled from:
+    """sha256 (16 hex digits) over the code the kernels are compiled from:
     csrc/inst.hip and every header it includes, transitively (the host code
-    and the SQP-only kernels do not enter it)."""
+    and the SQP-only kernels do not enter it), comments and layout left out,
+    so that only a change of the code itself invalidates a measurement."""
     import hashlib
     import re
 
@@ -68,8 +94,8 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for name in sorted(seen):
         path = next(os.path.join(d, name) for d in dirs if os.path.exists(os.path.join(d, name)))
-        with open(path, "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+        with open(path, encoding="utf-8") as f:
+            h.update(name.encode() + b"\0" + _code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

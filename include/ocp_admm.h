@@ -355,9 +355,10 @@ ocp_status ocp_set_segmented(ocp_handle h, int32_t seg_min_n);
  * workgroup of W wavefronts (W = 8 for stage width n <= 8, else 4) instead
  * of one wavefront.  Its chunked factorisation runs 4 W + 1 chunks and its
  * segmented substitutions 4 W segments, one per 16-lane row of the
- * workgroup, so their serial depth is about 2 / (4 W) of the horizon;
- * wavefront 0 keeps the schedule (convergence checks, rho adaptation)
- * described at ocp_solve.  Results agree with the one-wavefront shapes up to
+ * workgroup, so their serial depth is about 2 / (4 W) of the horizon; the
+ * FP64 convergence checks spread the stages over the same rows, and
+ * wavefront 0 keeps the schedule (stopping and rho decisions) described at
+ * ocp_solve.  Results agree with the one-wavefront shapes up to
  * rounding.  Default 255 (horizons of 256 stages and more); 0 turns it off.
  * Drops a captured graph.  Errors: OCP_E_ARG (null handle, or 0 < mw_min_n
  * < 16 W - 1: segments of fewer than four stages), OCP_E_HIP. */

@@ -1669,10 +1669,11 @@ __device__ __noinline__ int run_segment(const Layout& Lm, const Settings& st, in
 }
 
 // Multi-wavefront instances: one workgroup of W wavefronts per instance.
-// Wavefront 0 runs the schedule below (checks, rho decisions); the
-// factorisation, the transfer blocks and the iterations between two
-// boundaries are workgroup operations in which every 16-lane row of the W
-// wavefronts takes one chunk / segment (R = 4 W of them).  Wavefront 0 posts
+// Wavefront 0 runs the schedule below (stopping and rho decisions); the
+// factorisation, the transfer blocks, the iterations between two boundaries
+// and the boundary's FP64 evaluation are workgroup operations in which every
+// 16-lane row of the W wavefronts takes one chunk / segment / set of stages
+// (R = 4 W of them).  Wavefront 0 posts
 // each operation in LDS and meets the others at a barrier; the others loop
 // on posted operations until MW_EXIT.  Every operation ends with a barrier,
 // so between operations wavefront 0 alone runs, with wavefront-local syncs.
