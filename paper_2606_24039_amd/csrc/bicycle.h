@@ -45,6 +45,12 @@ struct BikeArgs {
   int32_t* frozen;  // [B] 1 once converged (only when not running a fixed count)
   double eps_c, armijo_eta;
   int fixed;
+  // line search: chunks of LS_CHUNK stages (chunk -> instance, first stage;
+  // instance -> first chunk, [B+1]); null: one chunk per instance
+  const int32_t* chunk_inst;
+  const int32_t* chunk_t0;
+  const int32_t* chunk_off;
+  double* parts;  // [chunks][LS_NF] merit parts; null: every horizon fits one chunk (no parts kernel)
 };
 
 struct BikeDeriv {
@@ -316,31 +322,19 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Line search and SQP bookkeeping, one wavefront per instance.  Lane i
-// handles the stages t = i, i+64, ...; per-candidate sums are wavefront
-// reductions.
+// Merit pieces of the stages t_begin .. t_end - 1 of instance b (lane
+// stride 64): cost and constraint violation at z = xbar + alpha (x* - xbar)
+// for alpha = 0, 1, 1/2, ..., 1/128 (entries 0..8), and the directional
+// derivative of cost + slack penalty at xbar.
 template <typename T, int INTEG>
-__global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs a) {
-  constexpr int NA = 8;  // alpha in {1, 1/2, ..., 1/128}
-  constexpr int WL = 64;  // lanes per instance
-  const int lane = threadIdx.x;
-  const int slot = blockIdx.x;
-  if (slot >= L.B) return;
-  const int b = L.order ? L.order[slot] : slot;
-  if (a.frozen[b]) return;
-  const int64_t s0 = L.stage_off[b];
-  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+__device__ __forceinline__ void bike_merit_stages(const Layout& L, const BikeArgs& a, int b, int64_t s0, int N,
+                                                  int t_begin, int t_end, int lane, double (&cost)[9],
+                                                  double (&viol)[9], double& gdir) {
+  constexpr int NA = 8;
   const T* XS = (const T*)L.x;
   const T* XIS = (const T*)L.xi;
-  const T* YFS = (const T*)L.yf;
-  const T* YGS = (const T*)L.yg;
   const double* x0 = a.x0 + (size_t)b * 4;
-
-  double cost[NA + 1], viol[NA + 1];
-#pragma unroll
-  for (int j = 0; j <= NA; ++j) cost[j] = viol[j] = 0.0;
-  double gdir = 0.0;
-  for (int t = lane; t <= N; t += WL) {
+  for (int t = t_begin + lane; t < t_end; t += 64) {
     const int64_t s = s0 + t;
     double xb[6], dx[6], xbn[6], dxn[6];
     const double xib = a.xibar[s * ROW + 2];
@@ -405,11 +399,92 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
       viol[j] += v;
     }
   }
+}
+
+// stages per block of bike_merit_parts_kernel, and the merit parts of a block
+constexpr int LS_CHUNK = 512;
+constexpr int LS_NF = 19;  // cost[0..8], viol[0..8], gdir
+
+// Merit parts of the line search, one wavefront per chunk of LS_CHUNK stages
+// of an instance (a.chunk_inst / a.chunk_t0; without them one chunk per
+// instance), written to a.parts[chunk][LS_NF]; bike_linesearch_kernel adds
+// an instance's chunks in order.  Long horizons spread over many wavefronts.
+template <typename T, int INTEG>
+__global__ __launch_bounds__(64) void bike_merit_parts_kernel(Layout L, BikeArgs a, int nchunks) {
+  const int c = blockIdx.x;
+  if (c >= nchunks) return;
+  const int b = a.chunk_inst ? a.chunk_inst[c] : c;
+  if (a.frozen[b]) return;
+  const int64_t s0 = L.stage_off[b];
+  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+  const int t0 = a.chunk_inst ? a.chunk_t0[c] : 0;
+  const int t1 = a.chunk_inst ? min(t0 + LS_CHUNK, N + 1) : N + 1;
+  double cost[9], viol[9], gdir = 0.0;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) cost[j] = viol[j] = 0.0;
+  bike_merit_stages<T, INTEG>(L, a, b, s0, N, t0, t1, (int)threadIdx.x, cost, viol, gdir);
   gdir = wave_sum(gdir);
 #pragma unroll
-  for (int j = 0; j <= NA; ++j) {
+  for (int j = 0; j < 9; ++j) {
     cost[j] = wave_sum(cost[j]);
     viol[j] = wave_sum(viol[j]);
+  }
+  if (threadIdx.x == 0) {
+    double* o = a.parts + (size_t)c * LS_NF;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      o[j] = cost[j];
+      o[9 + j] = viol[j];
+    }
+    o[18] = gdir;
+  }
+}
+
+// Line search and SQP bookkeeping, one wavefront per instance.  Lane i
+// handles the stages t = i, i+64, ...; per-candidate sums are wavefront
+// reductions.
+template <typename T, int INTEG>
+__global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs a) {
+  constexpr int NA = 8;  // alpha in {1, 1/2, ..., 1/128}
+  constexpr int WL = 64;  // lanes per instance
+  const int lane = threadIdx.x;
+  const int slot = blockIdx.x;
+  if (slot >= L.B) return;
+  const int b = L.order ? L.order[slot] : slot;
+  if (a.frozen[b]) return;
+  const int64_t s0 = L.stage_off[b];
+  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+  const T* XS = (const T*)L.x;
+  const T* XIS = (const T*)L.xi;
+  const T* YFS = (const T*)L.yf;
+  const T* YGS = (const T*)L.yg;
+  const double* x0 = a.x0 + (size_t)b * 4;
+
+  // merit pieces over the whole horizon: from the parts of this instance's
+  // chunks (bike_merit_parts_kernel, added in chunk order: lane f sums part
+  // f) when the batch has horizons longer than a chunk, else here
+  double cost[NA + 1], viol[NA + 1], gdir = 0.0;
+  if (a.parts) {
+    const int c0 = a.chunk_off ? a.chunk_off[b] : b, c1 = a.chunk_off ? a.chunk_off[b + 1] : b + 1;
+    double acc = 0.0;
+    if (lane < LS_NF)
+      for (int c = c0; c < c1; ++c) acc += a.parts[(size_t)c * LS_NF + lane];
+#pragma unroll
+    for (int j = 0; j <= NA; ++j) {
+      cost[j] = __shfl(acc, j);
+      viol[j] = __shfl(acc, 9 + j);
+    }
+    gdir = __shfl(acc, 18);
+  } else {
+#pragma unroll
+    for (int j = 0; j <= NA; ++j) cost[j] = viol[j] = 0.0;
+    bike_merit_stages<T, INTEG>(L, a, b, s0, N, 0, N + 1, lane, cost, viol, gdir);
+    gdir = wave_sum(gdir);
+#pragma unroll
+    for (int j = 0; j <= NA; ++j) {
+      cost[j] = wave_sum(cost[j]);
+      viol[j] = wave_sum(viol[j]);
+    }
   }
   const double mu = fmax(fmax(a.mu[b], fabs(gdir) / (0.5 * fmax(viol[0], a.eps_c))), 1.0);
   const double dmu = gdir - mu * viol[0];

@@ -123,6 +123,10 @@ struct ocp_handle_s {
   int32_t* sqp_done = nullptr;
   int32_t* sqp_frozen = nullptr;
   int32_t* stage_inst = nullptr;
+  // line-search chunks (LS_CHUNK stages; a carved workspace keeps one per instance)
+  int ls_nchunks = 0;
+  int32_t *ls_chunk_inst = nullptr, *ls_chunk_t0 = nullptr, *ls_chunk_off = nullptr;
+  double* ls_parts = nullptr;
 
   // adjoint scratch (FP64, padded [S][ROW])
   double *adj_rhog = nullptr, *adj_ex = nullptr, *adj_ey = nullptr, *adj_eg = nullptr, *adj_r = nullptr;
@@ -297,6 +301,16 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
     A_(h->kkt, sizeof(double) * 3 * B);
     A_(h->sqp_done, sizeof(int32_t) * B);
     A_(h->sqp_frozen, sizeof(int32_t) * B);
+    size_t nch = (size_t)B;
+    if (!h->carve) {
+      nch = 0;
+      for (int b = 0; b < B; ++b) nch += (size_t)(horizons[b] + LS_CHUNK) / LS_CHUNK;
+      A_(h->ls_chunk_inst, sizeof(int32_t) * nch);
+      A_(h->ls_chunk_t0, sizeof(int32_t) * nch);
+      A_(h->ls_chunk_off, sizeof(int32_t) * (B + 1));
+    }
+    h->ls_nchunks = (int)nch;
+    A_(h->ls_parts, sizeof(double) * LS_NF * nch);
   }
   A_(h->stage_inst, sizeof(int32_t) * S);
   A_(h->sc, sizeof(double) * 3 * ROW * B);
@@ -347,6 +361,23 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
     if (hipStreamCreateWithFlags(&h->fork.aux, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&h->fork.fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->fork.join, hipEventDisableTiming) != hipSuccess)
+      return OCP_E_HIP;
+  }
+  // line-search chunks of the bicycle model (host -> device, once)
+  if (h->ls_chunk_inst) {
+    std::vector<int32_t> ci, ct, co((size_t)B + 1, 0);
+    for (int b = 0; b < B; ++b) {
+      co[(size_t)b] = (int32_t)ci.size();
+      for (int t = 0; t <= horizons[b]; t += LS_CHUNK) {
+        ci.push_back(b);
+        ct.push_back(t);
+      }
+    }
+    co[(size_t)B] = (int32_t)ci.size();
+    if ((int)ci.size() != h->ls_nchunks ||
+        hipMemcpy(h->ls_chunk_inst, ci.data(), sizeof(int32_t) * ci.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->ls_chunk_t0, ct.data(), sizeof(int32_t) * ct.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->ls_chunk_off, co.data(), sizeof(int32_t) * co.size(), hipMemcpyHostToDevice) != hipSuccess)
       return OCP_E_HIP;
   }
   // stage offsets and longest-first processing order (host -> device, once)
@@ -664,6 +695,10 @@ BikeArgs make_bike(ocp_handle h, const ocp_settings* s) {
   a.eps_c = s->eps_c;
   a.armijo_eta = s->armijo_eta;
   a.fixed = s->fixed_sqp;
+  a.chunk_inst = h->ls_chunk_inst;
+  a.chunk_t0 = h->ls_chunk_t0;
+  a.chunk_off = h->ls_chunk_off;
+  a.parts = h->ls_nchunks > h->B ? h->ls_parts : nullptr;
   return a;
 }
 
@@ -691,12 +726,25 @@ ocp_status bicycle_sqp(ocp_handle h, const ocp_settings* s, hipStream_t st) {
     });
     run_admm(h, ad, st);
     timed(pf, OCP_K_SQP, st, [&] {
-      if (h->mixed)
+      const int nch = h->ls_nchunks;
+      if (!a.parts) {  // every horizon within one chunk: the line-search kernel sums itself
+        if (h->mixed)
+          hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<float, 1> : bike_linesearch_kernel<float, 0>),
+                             dim3(h->B), dim3(64), 0, st, L, a);
+        else
+          hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<double, 1> : bike_linesearch_kernel<double, 0>),
+                             dim3(h->B), dim3(64), 0, st, L, a);
+      } else if (h->mixed) {
+        hipLaunchKernelGGL((a.integ ? bike_merit_parts_kernel<float, 1> : bike_merit_parts_kernel<float, 0>),
+                           dim3(nch), dim3(64), 0, st, L, a, nch);
         hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<float, 1> : bike_linesearch_kernel<float, 0>), dim3(h->B),
                            dim3(64), 0, st, L, a);
-      else
+      } else {
+        hipLaunchKernelGGL((a.integ ? bike_merit_parts_kernel<double, 1> : bike_merit_parts_kernel<double, 0>),
+                           dim3(nch), dim3(64), 0, st, L, a, nch);
         hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<double, 1> : bike_linesearch_kernel<double, 0>),
                            dim3(h->B), dim3(64), 0, st, L, a);
+      }
     });
   }
   return hip_ok(hipGetLastError());
