@@ -51,6 +51,7 @@ struct BikeArgs {
   const int32_t* chunk_t0;
   const int32_t* chunk_off;
   double* parts;  // [chunks][LS_NF] merit parts; null: every horizon fits one chunk (no parts kernel)
+  double* alpha;  // [B] step length the line search took (chunked step update), with parts
 };
 
 struct BikeDeriv {
@@ -401,115 +402,17 @@ __device__ __forceinline__ void bike_merit_stages(const Layout& L, const BikeArg
   }
 }
 
-// stages per block of bike_merit_parts_kernel, and the merit parts of a block
-constexpr int LS_CHUNK = 512;
-constexpr int LS_NF = 19;  // cost[0..8], viol[0..8], gdir
-
-// Merit parts of the line search, one wavefront per chunk of LS_CHUNK stages
-// of an instance (a.chunk_inst / a.chunk_t0; without them one chunk per
-// instance), written to a.parts[chunk][LS_NF]; bike_linesearch_kernel adds
-// an instance's chunks in order.  Long horizons spread over many wavefronts.
-template <typename T, int INTEG>
-__global__ __launch_bounds__(64) void bike_merit_parts_kernel(Layout L, BikeArgs a, int nchunks) {
-  const int c = blockIdx.x;
-  if (c >= nchunks) return;
-  const int b = a.chunk_inst ? a.chunk_inst[c] : c;
-  if (a.frozen[b]) return;
-  const int64_t s0 = L.stage_off[b];
-  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
-  const int t0 = a.chunk_inst ? a.chunk_t0[c] : 0;
-  const int t1 = a.chunk_inst ? min(t0 + LS_CHUNK, N + 1) : N + 1;
-  double cost[9], viol[9], gdir = 0.0;
-#pragma unroll
-  for (int j = 0; j < 9; ++j) cost[j] = viol[j] = 0.0;
-  bike_merit_stages<T, INTEG>(L, a, b, s0, N, t0, t1, (int)threadIdx.x, cost, viol, gdir);
-  gdir = wave_sum(gdir);
-#pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    cost[j] = wave_sum(cost[j]);
-    viol[j] = wave_sum(viol[j]);
-  }
-  if (threadIdx.x == 0) {
-    double* o = a.parts + (size_t)c * LS_NF;
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      o[j] = cost[j];
-      o[9 + j] = viol[j];
-    }
-    o[18] = gdir;
-  }
-}
-
-// Line search and SQP bookkeeping, one wavefront per instance.  Lane i
-// handles the stages t = i, i+64, ...; per-candidate sums are wavefront
-// reductions.
-template <typename T, int INTEG>
-__global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs a) {
-  constexpr int NA = 8;  // alpha in {1, 1/2, ..., 1/128}
-  constexpr int WL = 64;  // lanes per instance
-  const int lane = threadIdx.x;
-  const int slot = blockIdx.x;
-  if (slot >= L.B) return;
-  const int b = L.order ? L.order[slot] : slot;
-  if (a.frozen[b]) return;
-  const int64_t s0 = L.stage_off[b];
-  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+// SQP step with the line search's length alpha: the iterate moves towards the
+// QP solution, stages t_begin .. t_end - 1 of the instance starting at stage
+// s0 (lane stride 64).
+template <typename T>
+__device__ __forceinline__ void bike_take_step(const Layout& L, const BikeArgs& a, int64_t s0, int t_begin, int t_end,
+                                               int lane, double alpha) {
   const T* XS = (const T*)L.x;
   const T* XIS = (const T*)L.xi;
   const T* YFS = (const T*)L.yf;
   const T* YGS = (const T*)L.yg;
-  const double* x0 = a.x0 + (size_t)b * 4;
-
-  // merit pieces over the whole horizon: from the parts of this instance's
-  // chunks (bike_merit_parts_kernel, added in chunk order: lane f sums part
-  // f) when the batch has horizons longer than a chunk, else here
-  double cost[NA + 1], viol[NA + 1], gdir = 0.0;
-  if (a.parts) {
-    const int c0 = a.chunk_off ? a.chunk_off[b] : b, c1 = a.chunk_off ? a.chunk_off[b + 1] : b + 1;
-    double acc = 0.0;
-    if (lane < LS_NF)
-      for (int c = c0; c < c1; ++c) acc += a.parts[(size_t)c * LS_NF + lane];
-#pragma unroll
-    for (int j = 0; j <= NA; ++j) {
-      cost[j] = __shfl(acc, j);
-      viol[j] = __shfl(acc, 9 + j);
-    }
-    gdir = __shfl(acc, 18);
-  } else {
-#pragma unroll
-    for (int j = 0; j <= NA; ++j) cost[j] = viol[j] = 0.0;
-    bike_merit_stages<T, INTEG>(L, a, b, s0, N, 0, N + 1, lane, cost, viol, gdir);
-    gdir = wave_sum(gdir);
-#pragma unroll
-    for (int j = 0; j <= NA; ++j) {
-      cost[j] = wave_sum(cost[j]);
-      viol[j] = wave_sum(viol[j]);
-    }
-  }
-  const double mu = fmax(fmax(a.mu[b], fabs(gdir) / (0.5 * fmax(viol[0], a.eps_c))), 1.0);
-  const double dmu = gdir - mu * viol[0];
-  const double phi0 = cost[0] + mu * viol[0];
-  double alpha = -1.0;
-#pragma unroll
-  for (int j = 1; j <= NA; ++j) {
-    const double al = ldexp(1.0, -(j - 1));
-    const double ph = cost[j] + mu * viol[j];
-    if (alpha < 0.0 && isfinite(ph) && ph <= phi0 + a.armijo_eta * al * dmu) alpha = al;
-  }
-  if (alpha < 0.0) {  // fallback: the finite candidate with the smallest merit (ties: larger alpha)
-    double best = INFINITY;
-    alpha = 0.0;
-#pragma unroll
-    for (int j = 1; j <= NA; ++j) {
-      const double ph = cost[j] + mu * viol[j];
-      if (isfinite(ph) && ph < best) {
-        best = ph;
-        alpha = ldexp(1.0, -(j - 1));
-      }
-    }
-  }
-  // take the step (lane i updates the stages t = i, i+64, ...)
-  for (int t = lane; t <= N; t += WL) {
+  for (int t = t_begin + lane; t < t_end; t += 64) {
     const size_t sv = (size_t)(s0 + t) * ROW;
 #pragma unroll
     for (int k = 0; k < 6; ++k) a.xbar[sv + k] += alpha * (double(XS[sv + k]) - a.xbar[sv + k]);
@@ -521,11 +424,17 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
 #pragma unroll
     for (int k = 0; k < 4; ++k) a.yfbar[sv + k] += alpha * (double(YFS[sv + k]) - a.yfbar[sv + k]);
   }
-  // the stopping quantities read the neighbouring stages other lanes wrote
-  __syncthreads();
-  // stopping quantities (eq. sqp_stop) at the new iterate
-  double st = 0.0, fe = 0.0, gi = 0.0;
-  for (int t = lane; t <= N; t += WL) {
+}
+
+// Stopping-quantity pieces (eq. sqp_stop) at the SQP iterate, stages
+// t_begin .. t_end - 1 of instance b (lane stride 64): maxima of the
+// stationarity residual, the equality residuals and the inequality
+// violations.
+template <int INTEG>
+__device__ __forceinline__ void bike_stop_stages(const BikeArgs& a, int b, int64_t s0, int N, int t_begin, int t_end,
+                                                 int lane, double& st, double& fe, double& gi) {
+  const double* x0 = a.x0 + (size_t)b * 4;
+  for (int t = t_begin + lane; t < t_end; t += 64) {
     const int64_t s = s0 + t;
     const double* xb = a.xbar + s * ROW;
     const double* W = (t == N) ? a.Qfd : a.Qd;
@@ -586,6 +495,123 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     gi = fmax(gi, fmax(fmax(g1 - dhi, dlo - g1), 0.0));
     gi = fmax(gi, fmax(fmax(g2 - a.lat_b, -a.lat_b - g2), 0.0));
   }
+}
+
+// stages per block of bike_merit_parts_kernel, and the merit parts of a block
+constexpr int LS_CHUNK = 512;
+constexpr int LS_NF = 19;  // cost[0..8], viol[0..8], gdir
+
+// Merit parts of the line search, one wavefront per chunk of LS_CHUNK stages
+// of an instance (a.chunk_inst / a.chunk_t0; without them one chunk per
+// instance), written to a.parts[chunk][LS_NF]; bike_linesearch_kernel adds
+// an instance's chunks in order.  Long horizons spread over many wavefronts.
+template <typename T, int INTEG>
+__global__ __launch_bounds__(64) void bike_merit_parts_kernel(Layout L, BikeArgs a, int nchunks) {
+  const int c = blockIdx.x;
+  if (c >= nchunks) return;
+  const int b = a.chunk_inst ? a.chunk_inst[c] : c;
+  if (a.frozen[b]) return;
+  const int64_t s0 = L.stage_off[b];
+  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+  const int t0 = a.chunk_inst ? a.chunk_t0[c] : 0;
+  const int t1 = a.chunk_inst ? min(t0 + LS_CHUNK, N + 1) : N + 1;
+  double cost[9], viol[9], gdir = 0.0;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) cost[j] = viol[j] = 0.0;
+  bike_merit_stages<T, INTEG>(L, a, b, s0, N, t0, t1, (int)threadIdx.x, cost, viol, gdir);
+  gdir = wave_sum(gdir);
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    cost[j] = wave_sum(cost[j]);
+    viol[j] = wave_sum(viol[j]);
+  }
+  if (threadIdx.x == 0) {
+    double* o = a.parts + (size_t)c * LS_NF;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      o[j] = cost[j];
+      o[9 + j] = viol[j];
+    }
+    o[18] = gdir;
+  }
+}
+
+// Line search and SQP bookkeeping, one wavefront per instance.  Lane i
+// handles the stages t = i, i+64, ...; per-candidate sums are wavefront
+// reductions.
+template <typename T, int INTEG>
+__global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs a) {
+  constexpr int NA = 8;  // alpha in {1, 1/2, ..., 1/128}
+  const int lane = threadIdx.x;
+  const int slot = blockIdx.x;
+  if (slot >= L.B) return;
+  const int b = L.order ? L.order[slot] : slot;
+  if (a.frozen[b]) return;
+  const int64_t s0 = L.stage_off[b];
+  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+
+  // merit pieces over the whole horizon: from the parts of this instance's
+  // chunks (bike_merit_parts_kernel, added in chunk order: lane f sums part
+  // f) when the batch has horizons longer than a chunk, else here
+  double cost[NA + 1], viol[NA + 1], gdir = 0.0;
+  if (a.parts) {
+    const int c0 = a.chunk_off ? a.chunk_off[b] : b, c1 = a.chunk_off ? a.chunk_off[b + 1] : b + 1;
+    double acc = 0.0;
+    if (lane < LS_NF)
+      for (int c = c0; c < c1; ++c) acc += a.parts[(size_t)c * LS_NF + lane];
+#pragma unroll
+    for (int j = 0; j <= NA; ++j) {
+      cost[j] = __shfl(acc, j);
+      viol[j] = __shfl(acc, 9 + j);
+    }
+    gdir = __shfl(acc, 18);
+  } else {
+#pragma unroll
+    for (int j = 0; j <= NA; ++j) cost[j] = viol[j] = 0.0;
+    bike_merit_stages<T, INTEG>(L, a, b, s0, N, 0, N + 1, lane, cost, viol, gdir);
+    gdir = wave_sum(gdir);
+#pragma unroll
+    for (int j = 0; j <= NA; ++j) {
+      cost[j] = wave_sum(cost[j]);
+      viol[j] = wave_sum(viol[j]);
+    }
+  }
+  const double mu = fmax(fmax(a.mu[b], fabs(gdir) / (0.5 * fmax(viol[0], a.eps_c))), 1.0);
+  const double dmu = gdir - mu * viol[0];
+  const double phi0 = cost[0] + mu * viol[0];
+  double alpha = -1.0;
+#pragma unroll
+  for (int j = 1; j <= NA; ++j) {
+    const double al = ldexp(1.0, -(j - 1));
+    const double ph = cost[j] + mu * viol[j];
+    if (alpha < 0.0 && isfinite(ph) && ph <= phi0 + a.armijo_eta * al * dmu) alpha = al;
+  }
+  if (alpha < 0.0) {  // fallback: the finite candidate with the smallest merit (ties: larger alpha)
+    double best = INFINITY;
+    alpha = 0.0;
+#pragma unroll
+    for (int j = 1; j <= NA; ++j) {
+      const double ph = cost[j] + mu * viol[j];
+      if (isfinite(ph) && ph < best) {
+        best = ph;
+        alpha = ldexp(1.0, -(j - 1));
+      }
+    }
+  }
+  if (a.parts) {  // the step and the stopping quantities follow in bike_stop_parts_kernel / bike_stop_combine_kernel
+    if (lane == 0) {
+      a.mu[b] = mu;
+      a.alpha[b] = alpha;
+    }
+    return;
+  }
+  // take the step (lane i updates the stages t = i, i+64, ...)
+  bike_take_step<T>(L, a, s0, 0, N + 1, lane, alpha);
+  // the stopping quantities read the neighbouring stages other lanes wrote
+  __syncthreads();
+  // stopping quantities (eq. sqp_stop) at the new iterate
+  double st = 0.0, fe = 0.0, gi = 0.0;
+  bike_stop_stages<INTEG>(a, b, s0, N, 0, N + 1, lane, st, fe, gi);
   st = wave_max(st);
   fe = wave_max(fe);
   gi = wave_max(gi);
@@ -597,6 +623,63 @@ __global__ __launch_bounds__(64) void bike_linesearch_kernel(Layout L, BikeArgs 
     a.done[b] += 1;
     if (!a.fixed && st <= a.eps_c && fe <= a.eps_c && gi <= a.eps_c) a.frozen[b] = 1;
   }
+}
+
+// The step of a batch with horizons past one chunk, one wavefront per chunk,
+// with the length bike_linesearch_kernel chose for the instance.
+template <typename T>
+__global__ __launch_bounds__(64) void bike_step_parts_kernel(Layout L, BikeArgs a, int nchunks) {
+  const int c = blockIdx.x;
+  if (c >= nchunks) return;
+  const int b = a.chunk_inst ? a.chunk_inst[c] : c;
+  if (a.frozen[b]) return;
+  const int64_t s0 = L.stage_off[b];
+  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+  const int t0 = a.chunk_inst ? a.chunk_t0[c] : 0;
+  const int t1 = a.chunk_inst ? min(t0 + LS_CHUNK, N + 1) : N + 1;
+  bike_take_step<T>(L, a, s0, t0, t1, (int)threadIdx.x, a.alpha[b]);
+}
+
+// Stopping quantities of a batch with horizons past one chunk: their maxima
+// over each chunk of LS_CHUNK stages (parts 0..2 of the chunk), after
+// bike_step_parts_kernel took the step of every chunk.
+template <typename T, int INTEG>
+__global__ __launch_bounds__(64) void bike_stop_parts_kernel(Layout L, BikeArgs a, int nchunks) {
+  const int c = blockIdx.x;
+  if (c >= nchunks) return;
+  const int b = a.chunk_inst ? a.chunk_inst[c] : c;
+  if (a.frozen[b]) return;
+  const int64_t s0 = L.stage_off[b];
+  const int N = (int)(L.stage_off[b + 1] - s0) - 1;
+  const int t0 = a.chunk_inst ? a.chunk_t0[c] : 0;
+  const int t1 = a.chunk_inst ? min(t0 + LS_CHUNK, N + 1) : N + 1;
+  double st = 0.0, fe = 0.0, gi = 0.0;
+  bike_stop_stages<INTEG>(a, b, s0, N, t0, t1, (int)threadIdx.x, st, fe, gi);
+  st = wave_max(st);
+  fe = wave_max(fe);
+  gi = wave_max(gi);
+  if (threadIdx.x == 0) {
+    double* o = a.parts + (size_t)c * LS_NF;
+    o[0] = st, o[1] = fe, o[2] = gi;
+  }
+}
+
+// The instance's stopping quantities from its chunks' maxima; the SQP
+// iteration count and the convergence flag (one thread per instance).
+__global__ void bike_stop_combine_kernel(Layout L, BikeArgs a) {
+  const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (b >= L.B || a.frozen[b]) return;
+  const int c0 = a.chunk_off ? a.chunk_off[b] : b, c1 = a.chunk_off ? a.chunk_off[b + 1] : b + 1;
+  double st = 0.0, fe = 0.0, gi = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    const double* p = a.parts + (size_t)c * LS_NF;
+    st = fmax(st, p[0]), fe = fmax(fe, p[1]), gi = fmax(gi, p[2]);
+  }
+  a.kkt[(size_t)b * 3 + 0] = st;
+  a.kkt[(size_t)b * 3 + 1] = fe;
+  a.kkt[(size_t)b * 3 + 2] = gi;
+  a.done[b] += 1;
+  if (!a.fixed && st <= a.eps_c && fe <= a.eps_c && gi <= a.eps_c) a.frozen[b] = 1;
 }
 
 // sum_k y_k grad^2 fc_k at (x, u) over w = (px, py, yaw, v, a, delta): the

@@ -126,7 +126,7 @@ struct ocp_handle_s {
   // line-search chunks (LS_CHUNK stages; a carved workspace keeps one per instance)
   int ls_nchunks = 0;
   int32_t *ls_chunk_inst = nullptr, *ls_chunk_t0 = nullptr, *ls_chunk_off = nullptr;
-  double* ls_parts = nullptr;
+  double *ls_parts = nullptr, *ls_alpha = nullptr;
 
   // adjoint scratch (FP64, padded [S][ROW])
   double *adj_rhog = nullptr, *adj_ex = nullptr, *adj_ey = nullptr, *adj_eg = nullptr, *adj_r = nullptr;
@@ -308,6 +308,7 @@ ocp_status build(ocp_handle h, const ocp_dims* d, const int32_t* horizons, bool 
       A_(h->ls_chunk_inst, sizeof(int32_t) * nch);
       A_(h->ls_chunk_t0, sizeof(int32_t) * nch);
       A_(h->ls_chunk_off, sizeof(int32_t) * (B + 1));
+      A_(h->ls_alpha, sizeof(double) * B);
     }
     h->ls_nchunks = (int)nch;
     A_(h->ls_parts, sizeof(double) * LS_NF * nch);
@@ -699,6 +700,7 @@ BikeArgs make_bike(ocp_handle h, const ocp_settings* s) {
   a.chunk_t0 = h->ls_chunk_t0;
   a.chunk_off = h->ls_chunk_off;
   a.parts = h->ls_nchunks > h->B ? h->ls_parts : nullptr;
+  a.alpha = h->ls_alpha;
   return a;
 }
 
@@ -734,16 +736,25 @@ ocp_status bicycle_sqp(ocp_handle h, const ocp_settings* s, hipStream_t st) {
         else
           hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<double, 1> : bike_linesearch_kernel<double, 0>),
                              dim3(h->B), dim3(64), 0, st, L, a);
-      } else if (h->mixed) {
-        hipLaunchKernelGGL((a.integ ? bike_merit_parts_kernel<float, 1> : bike_merit_parts_kernel<float, 0>),
-                           dim3(nch), dim3(64), 0, st, L, a, nch);
-        hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<float, 1> : bike_linesearch_kernel<float, 0>), dim3(h->B),
-                           dim3(64), 0, st, L, a);
-      } else {
-        hipLaunchKernelGGL((a.integ ? bike_merit_parts_kernel<double, 1> : bike_merit_parts_kernel<double, 0>),
-                           dim3(nch), dim3(64), 0, st, L, a, nch);
-        hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<double, 1> : bike_linesearch_kernel<double, 0>),
-                           dim3(h->B), dim3(64), 0, st, L, a);
+      } else {  // merit parts per chunk, the decision per instance, then the step and the stopping maxima per chunk
+        if (h->mixed) {
+          hipLaunchKernelGGL((a.integ ? bike_merit_parts_kernel<float, 1> : bike_merit_parts_kernel<float, 0>),
+                             dim3(nch), dim3(64), 0, st, L, a, nch);
+          hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<float, 1> : bike_linesearch_kernel<float, 0>),
+                             dim3(h->B), dim3(64), 0, st, L, a);
+          hipLaunchKernelGGL(bike_step_parts_kernel<float>, dim3(nch), dim3(64), 0, st, L, a, nch);
+          hipLaunchKernelGGL((a.integ ? bike_stop_parts_kernel<float, 1> : bike_stop_parts_kernel<float, 0>),
+                             dim3(nch), dim3(64), 0, st, L, a, nch);
+        } else {
+          hipLaunchKernelGGL((a.integ ? bike_merit_parts_kernel<double, 1> : bike_merit_parts_kernel<double, 0>),
+                             dim3(nch), dim3(64), 0, st, L, a, nch);
+          hipLaunchKernelGGL((a.integ ? bike_linesearch_kernel<double, 1> : bike_linesearch_kernel<double, 0>),
+                             dim3(h->B), dim3(64), 0, st, L, a);
+          hipLaunchKernelGGL(bike_step_parts_kernel<double>, dim3(nch), dim3(64), 0, st, L, a, nch);
+          hipLaunchKernelGGL((a.integ ? bike_stop_parts_kernel<double, 1> : bike_stop_parts_kernel<double, 0>),
+                             dim3(nch), dim3(64), 0, st, L, a, nch);
+        }
+        hipLaunchKernelGGL(bike_stop_combine_kernel, dim3((h->B + 255) / 256), dim3(256), 0, st, L, a);
       }
     });
   }

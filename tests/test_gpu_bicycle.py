@@ -8,6 +8,9 @@ line search, stopping quantities of eq. sqp_stop.
 * FP32 ADMM iterations: the final iterate stays within the FP32 tolerance of
   the oracle's and its NLP KKT residuals are reported.
 * Ragged horizons in one batch.
+* Horizons past the line search's 512-stage chunks (merit sums, step and
+  stopping quantities spread over one wavefront per chunk) follow the
+  oracle's trajectory in FP64.
 """
 import numpy as np
 import pytest
@@ -51,6 +54,24 @@ def test_fixed_iterations_follow_the_oracle_fp64():
         assert abs(kkt[0] - ref.stop["stationarity"]) < 1e-7 * max(1, ref.stop["stationarity"])
         assert abs(kkt[1] - ref.stop["eq"]) < 1e-9 + 1e-7 * ref.stop["eq"]
         assert int(out["sqp_iters"][i]) == 10
+
+
+def test_chunked_line_search_follows_the_oracle_fp64():
+    """Horizons 1183, 610 and 505: three, two and one 512-stage chunks."""
+    _, rag = bicycle_long_and_ragged(seed=13, long_N=16, ragged=3, n_lo=480, n_hi=1200)
+    assert list(rag.horizons) == [1183, 610, 505]
+    s = _solver(rag, FP64)
+    out = s.solve(_settings(max_sqp=3, max_admm=25, k_check=0, k_rho=25, fixed_sqp=1))
+    for i in range(rag.batch):
+        ref = sqp_solve(BicycleOCP(rag, i), SQPSettings(max_sqp=3, fixed_iters=True),
+                        admm=ADMMSettings(max_iter=25, k_check=0, k_rho=25))
+        z = s.split(out["x"], i).cpu().numpy()
+        assert rel(z, ref.z) < 1e-8, (i, rel(z, ref.z))
+        kkt = out["sqp_kkt"][i].cpu().numpy()
+        assert abs(kkt[0] - ref.stop["stationarity"]) < 1e-7 * max(1, ref.stop["stationarity"]), (i, kkt, ref.stop)
+        assert abs(kkt[1] - ref.stop["eq"]) < 1e-9 + 1e-7 * ref.stop["eq"], (i, kkt, ref.stop)
+        assert abs(kkt[2] - ref.stop["ineq"]) < 1e-9 + 1e-7 * ref.stop["ineq"], (i, kkt, ref.stop)
+        assert int(out["sqp_iters"][i]) == 3
 
 
 def test_converged_sqp_reaches_the_oracle_kkt_point():
