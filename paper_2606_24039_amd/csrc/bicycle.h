@@ -163,40 +163,69 @@ __global__ void bike_init_kernel(Layout L, BikeArgs a, double rho0) {
   }
 }
 
-// Convexify at xbar (one thread per global stage) and warm-start the ADMM
-// state from the SQP iterate: x = xbar, y = ybar, z_g = G xbar.
+// Convexify at xbar and warm-start the ADMM state from the SQP iterate:
+// x = xbar, y = ybar, z_g = G xbar.  One thread per global stage, blocks of
+// LIN_BLOCK consecutive stages: each thread forms its stage's blocks in
+// registers, and every output array (stage-major, so a block's stages are
+// one contiguous range of it) is staged in LDS and written with consecutive
+// lanes on consecutive elements.
 // INTEG: the discretisation (0 implicit midpoint, 1 trapezoidal rule), a
 // compile-time choice so that each kernel holds one rule's code.
+constexpr int LIN_BLOCK = 64;
 template <typename T, int INTEG>
-__global__ void bike_linearize_kernel(Layout L, BikeArgs a) {
+__global__ __launch_bounds__(LIN_BLOCK) void bike_linearize_kernel(Layout L, BikeArgs a) {
+  __shared__ double stg[LIN_BLOCK * 36];
   const int64_t S = L.stage_off[L.B];
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const int b = a.stage_inst[s];
+  const int64_t sb = (int64_t)blockIdx.x * LIN_BLOCK;
+  if (sb >= S) return;  // the whole block
+  const int tid = threadIdx.x;
+  const int64_t s = sb + tid;
+  const int nst = (int)min<int64_t>(LIN_BLOCK, S - sb);
+  const bool live = s < S;
+  const int64_t sl = live ? s : S - 1;  // the idle threads read a valid stage and store nothing
+  const int b = a.stage_inst[sl];
   const int64_t s0 = L.stage_off[b];
-  const int t = (int)(s - s0);
+  const int t = (int)(sl - s0);
   const int N = (int)(L.stage_off[b + 1] - s0) - 1;
-  const double* xb = a.xbar + s * ROW;
-  double* D = const_cast<double*>(L.D) + s * 36;
-  double* q = const_cast<double*>(L.q) + s * 6;
+  const double* xb = a.xbar + sl * ROW;
   const double* Wq = (t == N) ? a.Qfd : a.Qd;
-#pragma unroll
-  for (int k = 0; k < 36; ++k) D[k] = 0.0;
+  // stage this thread's M values val(0..M-1), then store the block's range
+  // of the array with consecutive lanes on consecutive elements
+  auto put = [&](auto* dst, auto mc, auto&& val) {
+    constexpr int M = decltype(mc)::value;
+    using V = std::remove_pointer_t<decltype(dst)>;
+    V* st = reinterpret_cast<V*>(stg);
+    if (live) sfor<0, M>([&](auto k) { st[tid * M + decltype(k)::value] = val(decltype(k)::value); });
+    __syncthreads();
+    V* d = dst + sb * M;
+    for (int e = tid; e < nst * M; e += LIN_BLOCK) d[e] = st[e];
+    __syncthreads();
+  };
+  using I4 = std::integral_constant<int, 4>;
+  using I3 = std::integral_constant<int, 3>;
+  using I6 = std::integral_constant<int, 6>;
+  using I18 = std::integral_constant<int, 18>;
+  using I24 = std::integral_constant<int, 24>;
+  using I36 = std::integral_constant<int, 36>;
+  using IR = std::integral_constant<int, ROW>;
+
+  // cost: D_t = diag(Q or Q_f, R) (+ the rate weights), q_t = -Q ref_t
+  double dg[6], q[6];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    D[k * 6 + k] = Wq[k];
-    q[k] = -Wq[k] * a.ref[s * 4 + k];
+    dg[k] = Wq[k];
+    q[k] = -Wq[k] * a.ref[sl * 4 + k];
   }
-  D[4 * 6 + 4] = a.Rd[0];
-  D[5 * 6 + 5] = a.Rd[1];
+  dg[4] = a.Rd[0];
+  dg[5] = a.Rd[1];
   q[4] = q[5] = 0.0;
   if (a.rate) {
     // rate cost: W on the controls of the one or two differences touching
     // stage t, -W in E_t = block (t+1, t); a pure quadratic form, so q is unchanged
     const double cnt = (t < N ? 1.0 : 0.0) + (t > 0 ? 1.0 : 0.0);
-    D[4 * 6 + 4] += cnt * a.Wd[0];
-    D[5 * 6 + 5] += cnt * a.Wd[1];
-    if (t < N) {
+    dg[4] += cnt * a.Wd[0];
+    dg[5] += cnt * a.Wd[1];
+    if (live && t < N) {
       double* E = const_cast<double*>(L.E) + s * 36;
 #pragma unroll
       for (int k = 0; k < 36; ++k) E[k] = 0.0;
@@ -204,98 +233,71 @@ __global__ void bike_linearize_kernel(Layout L, BikeArgs a) {
       E[5 * 6 + 5] = -a.Wd[1];
     }
   }
-  double* Am = const_cast<double*>(L.Am) + s * 24;
-  double* Ap = const_cast<double*>(L.Ap) + s * 24;
-  double* bd = const_cast<double*>(L.bd) + s * 4;
+  // dynamics row t linearised at (xbar_t, xbar_{t+1}): A_t^- z_t + A_t^+ z_{t+1} = bd_t
+  double Ml[4][6], Mr[4][6], bd[4];
   if (t < N) {
-    const double* xn = a.xbar + (s + 1) * ROW;
-    double f[4], Ml[4][6], Mr[4][6];
+    const double* xn = xb + ROW;
+    double f[4];
     bike_dynamics<INTEG>(xb, xb + 4, xn, a.dt, a.Lw, f, Ml, Mr);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       double acc = -f[r];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        Am[r * 6 + k] = Ml[r][k];
-        Ap[r * 6 + k] = Mr[r][k];
-        acc += Ml[r][k] * xb[k] + Mr[r][k] * xn[k];
-      }
+      for (int k = 0; k < 6; ++k) acc += Ml[r][k] * xb[k] + Mr[r][k] * xn[k];
       bd[r] = acc;
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < 24; ++k) Am[k] = Ap[k] = 0.0;
+    for (int r = 0; r < 4; ++r) {
+      bd[r] = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) bd[r] = 0.0;
+      for (int k = 0; k < 6; ++k) Ml[r][k] = Mr[r][k] = 0.0;
+    }
   }
-  double* G = const_cast<double*>(L.G) + s * 18;
-  double* lo = const_cast<double*>(L.lo) + s * 3;
-  double* hi = const_cast<double*>(L.hi) + s * 3;
-  const double nx_ = a.normal[s * 2], ny_ = a.normal[s * 2 + 1];
-#pragma unroll
-  for (int k = 0; k < 18; ++k) G[k] = 0.0;
-  G[0 * 6 + 4] = 1.0;
-  G[1 * 6 + 5] = 1.0;
-  G[2 * 6 + 0] = nx_;
-  G[2 * 6 + 1] = ny_;
-  const double np = nx_ * a.ref[s * 4] + ny_ * a.ref[s * 4 + 1];
-  lo[0] = -a.a_b;
-  hi[0] = a.a_b;
-  lo[1] = -a.d_b;
-  hi[1] = a.d_b;
-  lo[2] = -a.lat_b + np;
-  hi[2] = a.lat_b + np;
+  // constraint rows: a, delta and the lateral deviation n'(p - p_ref) + xi
+  const double nx_ = a.normal[sl * 2], ny_ = a.normal[sl * 2 + 1];
+  const double np = nx_ * a.ref[sl * 4] + ny_ * a.ref[sl * 4 + 1];
+  double lo[3] = {-a.a_b, -a.d_b, -a.lat_b + np}, hi[3] = {a.a_b, a.d_b, a.lat_b + np};
   if (t == 0 && a.u_init) {  // (x_0, u_0) = (x_init, u_init): equality rows on u_0
     lo[0] = hi[0] = a.u_init[(size_t)b * 2];
     lo[1] = hi[1] = a.u_init[(size_t)b * 2 + 1];
   }
-  if (t == 0) {
+  auto Gv = [&](int k) { return k == 4 || k == 11 ? 1.0 : k == 12 ? nx_ : k == 13 ? ny_ : 0.0; };
+  if (live && t == 0) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) const_cast<double*>(L.x_init)[(size_t)b * 4 + k] = a.x0[(size_t)b * 4 + k];
   }
+  put(const_cast<double*>(L.D), I36{}, [&](int k) { return (k % 7 == 0) ? dg[k / 7] : 0.0; });
+  put(const_cast<double*>(L.q), I6{}, [&](int k) { return q[k]; });
+  put(const_cast<double*>(L.Am), I24{}, [&](int k) { return Ml[k / 6][k % 6]; });
+  put(const_cast<double*>(L.Ap), I24{}, [&](int k) { return Mr[k / 6][k % 6]; });
+  put(const_cast<double*>(L.bd), I4{}, [&](int k) { return bd[k]; });
+  put(const_cast<double*>(L.G), I18{}, Gv);
+  put(const_cast<double*>(L.lo), I3{}, [&](int k) { return lo[k]; });
+  put(const_cast<double*>(L.hi), I3{}, [&](int k) { return hi[k]; });
   // iteration-precision copies
   if constexpr (!std::is_same<T, double>::value) {
-    T* AmT = (T*)L.AmT + s * 24;
-    T* ApT = (T*)L.ApT + s * 24;
-    T* GT = (T*)L.GT + s * 18;
-#pragma unroll
-    for (int k = 0; k < 24; ++k) {
-      AmT[k] = T(Am[k]);
-      ApT[k] = T(Ap[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < 18; ++k) GT[k] = T(G[k]);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) ((T*)L.qT)[s * 6 + k] = T(q[k]);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) ((T*)L.bdT)[s * 4 + k] = T(bd[k]);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      ((T*)L.loT)[s * 3 + k] = T(lo[k]);
-      ((T*)L.hiT)[s * 3 + k] = T(hi[k]);
-    }
-    if (t == 0) {
+    put((T*)L.AmT, I24{}, [&](int k) { return T(Ml[k / 6][k % 6]); });
+    put((T*)L.ApT, I24{}, [&](int k) { return T(Mr[k / 6][k % 6]); });
+    put((T*)L.GT, I18{}, [&](int k) { return T(Gv(k)); });
+    put((T*)L.qT, I6{}, [&](int k) { return T(q[k]); });
+    put((T*)L.bdT, I4{}, [&](int k) { return T(bd[k]); });
+    put((T*)L.loT, I3{}, [&](int k) { return T(lo[k]); });
+    put((T*)L.hiT, I3{}, [&](int k) { return T(hi[k]); });
+    if (live && t == 0) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) ((T*)L.xinitT)[(size_t)b * 4 + k] = T(a.x0[(size_t)b * 4 + k]);
     }
   }
   // warm start of the ADMM state
-  T* X = (T*)L.x + s * ROW;
-  T* YF = (T*)L.yf + s * ROW;
-  T* YG = (T*)L.yg + s * ROW;
-  T* ZG = (T*)L.zg + s * ROW;
-  T* XI = (T*)L.xi + s * ROW;
-#pragma unroll
-  for (int k = 0; k < ROW; ++k) {
-    X[k] = T(xb[k]);
-    YF[k] = T(a.yfbar[s * ROW + k]);
-    YG[k] = T(a.ygbar[s * ROW + k]);
-    XI[k] = T(0);
-    ZG[k] = T(0);
-  }
-  ZG[0] = T(xb[4]);
-  ZG[1] = T(xb[5]);
-  ZG[2] = T(nx_ * xb[0] + ny_ * xb[1]);
+  const double* yfb = a.yfbar + sl * ROW;
+  const double* ygb = a.ygbar + sl * ROW;
+  const double zg2 = nx_ * xb[0] + ny_ * xb[1];
+  put((T*)L.x, IR{}, [&](int k) { return T(xb[k]); });
+  put((T*)L.yf, IR{}, [&](int k) { return T(yfb[k]); });
+  put((T*)L.yg, IR{}, [&](int k) { return T(ygb[k]); });
+  put((T*)L.xi, IR{}, [&](int k) { return T(0); });
+  put((T*)L.zg, IR{}, [&](int k) { return k == 0 ? T(xb[4]) : k == 1 ? T(xb[5]) : k == 2 ? T(zg2) : T(0); });
 }
 
 // Per-stage pieces of the merit at z = xbar + alpha (x* - xbar).

@@ -712,6 +712,7 @@ ocp_status bicycle_sqp(ocp_handle h, const ocp_settings* s, hipStream_t st) {
   const Layout L = make_layout(h);
   const int64_t S = h->S;
   const unsigned gs = (unsigned)((std::max<int64_t>(S, h->B) + 255) / 256);
+  const unsigned gl = (unsigned)((S + LIN_BLOCK - 1) / LIN_BLOCK);
   Prof* pf = &h->prof;
   if (!(s->warm_start && h->solved))
     timed(pf, OCP_K_OTHER, st,
@@ -720,11 +721,11 @@ ocp_status bicycle_sqp(ocp_handle h, const ocp_settings* s, hipStream_t st) {
   for (int k = 0; k < s->max_sqp; ++k) {
     timed(pf, OCP_K_SQP, st, [&] {
       if (h->mixed)
-        hipLaunchKernelGGL((a.integ ? bike_linearize_kernel<float, 1> : bike_linearize_kernel<float, 0>), dim3(gs),
-                           dim3(256), 0, st, L, a);
+        hipLaunchKernelGGL((a.integ ? bike_linearize_kernel<float, 1> : bike_linearize_kernel<float, 0>), dim3(gl),
+                           dim3(LIN_BLOCK), 0, st, L, a);
       else
-        hipLaunchKernelGGL((a.integ ? bike_linearize_kernel<double, 1> : bike_linearize_kernel<double, 0>), dim3(gs),
-                           dim3(256), 0, st, L, a);
+        hipLaunchKernelGGL((a.integ ? bike_linearize_kernel<double, 1> : bike_linearize_kernel<double, 0>), dim3(gl),
+                           dim3(LIN_BLOCK), 0, st, L, a);
     });
     run_admm(h, ad, st);
     timed(pf, OCP_K_SQP, st, [&] {
@@ -1046,14 +1047,15 @@ ocp_status ocp_adjoint(ocp_handle h, const ocp_settings* s, const double* dL_dx,
     const BikeArgs ba = make_bike(h, s);
     const Layout L0 = make_layout(h);
     const unsigned gs = (unsigned)((std::max<int64_t>(h->S, h->B) + 255) / 256);
+    const unsigned gl = (unsigned)((h->S + LIN_BLOCK - 1) / LIN_BLOCK);
     const int integ = ba.integ;
     timed(&h->prof, OCP_K_SQP, st, [&] {
       if (h->mixed)
-        hipLaunchKernelGGL((integ ? bike_linearize_kernel<float, 1> : bike_linearize_kernel<float, 0>), dim3(gs),
-                           dim3(256), 0, st, L0, ba);
+        hipLaunchKernelGGL((integ ? bike_linearize_kernel<float, 1> : bike_linearize_kernel<float, 0>), dim3(gl),
+                           dim3(LIN_BLOCK), 0, st, L0, ba);
       else
-        hipLaunchKernelGGL((integ ? bike_linearize_kernel<double, 1> : bike_linearize_kernel<double, 0>), dim3(gs),
-                           dim3(256), 0, st, L0, ba);
+        hipLaunchKernelGGL((integ ? bike_linearize_kernel<double, 1> : bike_linearize_kernel<double, 0>), dim3(gl),
+                           dim3(LIN_BLOCK), 0, st, L0, ba);
       const unsigned gv = (unsigned)((h->S * ROW + 255) / 256);
       if (h->mixed)
         hipLaunchKernelGGL(iterate_slacks_kernel<float>, dim3(gv), dim3(256), 0, st, (const double*)h->xibar,
