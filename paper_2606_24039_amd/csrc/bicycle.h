@@ -50,7 +50,8 @@ struct BikeArgs {
   const int32_t* chunk_inst;
   const int32_t* chunk_t0;
   const int32_t* chunk_off;
-  double* parts;  // [chunks][LS_NF] merit parts; null: every horizon fits one chunk (no parts kernel)
+  double* parts;  // [chunks][LS_NF] merit parts, then (entries 0..2) the stopping maxima of the chunk;
+                  // null: every horizon fits one chunk (the line-search kernel does all of it)
   double* alpha;  // [B] step length the line search took (chunked step update), with parts
 };
 
