@@ -112,6 +112,50 @@ def test_captured_bicycle_sqp_step(precision):
         s.close()
 
 
+@pytest.mark.parametrize("precision", [MIXED, FP64])
+def test_captured_bicycle_step_with_long_horizons(precision):
+    """A bicycle step over horizons 1172, 244, 74 and 1042: the two long ones
+    on multi-wavefront workgroups beside the one-wavefront launch (two
+    streams), and the line search spread over 512-stage chunks (merit parts,
+    decision, step, stopping maxima, combination).  Every replay equals the
+    eager step bit for bit."""
+    import torch
+
+    from paper_2606_24039_amd import _abi as A
+    from paper_2606_24039_amd import default_settings
+    from paper_2606_24039_amd.solver import OCPSolver
+    from workloads import bicycle_long_and_ragged
+
+    _, b = bicycle_long_and_ragged(seed=13, long_N=16, ragged=4, n_lo=32, n_hi=1200)
+    assert list(b.horizons) == [1172, 244, 74, 1042]
+    stream = torch.cuda.Stream()
+    keys = ("x", "xi", "y_f", "y_g", "sqp_kkt", "sqp_iters", "status", "rho")
+    gkeys = ("d_q", "d_Ddiag", "d_x_init", "eta_x", "adj_status")
+    with torch.cuda.stream(stream):
+        s = OCPSolver(4, 2, 3, b.horizons, model=A.MODEL_BICYCLE, precision=precision)
+        s.set_bicycle(b)
+        st = default_settings(max_sqp=2, max_admm=30, k_check=0, k_rho=25, fixed_sqp=1)
+        dl = torch.as_tensor(np.random.default_rng(7).standard_normal((s.S, 6)), dtype=torch.float64, device="cuda")
+        ref = _snapshot(s.solve(st), keys)
+        refg = _snapshot(s.adjoint(dl, st), gkeys)
+        out = s.alloc_solution()
+        grads = s.alloc_grads()
+        s.graph_capture(st, out, dl, grads)
+        for rep in range(3):
+            for v in list(out.values()) + list(grads.values()):
+                v.fill_(-7)
+            s.graph_launch()
+            stream.synchronize()
+            got, gotg = _snapshot(out, keys), _snapshot(grads, gkeys)
+            for k in keys:
+                assert np.array_equal(got[k], ref[k]), (rep, k)
+            for k in gkeys:
+                assert np.array_equal(gotg[k], refg[k]), (rep, k)
+            s.solve(default_settings(max_sqp=1, max_admm=10, k_check=0, fixed_sqp=1))  # eager work between replays
+            stream.synchronize()
+        s.close()
+
+
 def test_captured_rescaled_lti_step():
     """The same for a rescaled random-LTI step (box normalisation): the graph
     keeps the rescaled data and the unscaling of the outputs."""
