@@ -485,7 +485,12 @@ ocp_status ocp_autotune(ocp_handle h, const ocp_settings* s, int32_t reps, void*
  * previous call left there: calls that overlap on one GPU (different
  * streams or threads) race, and nothing of a call survives the next one (no
  * ocp_get_solution / ocp_adjoint afterwards; use a handle for those).  The
- * call synchronises `stream` once (after laying out the stages).  Errors:
+ * call synchronises `stream` once (after laying out the stages).  Every
+ * instance runs on one wavefront and the bicycle line search in one pass per
+ * instance, so for horizons from 255 stages on (which a handle gives a
+ * multi-wavefront workgroup) and past 511 (whose line search a handle splits
+ * into chunks) results agree with the handle path's up to rounding; below
+ * both, bit for bit.  Errors:
  * those of ocp_create / ocp_set_* / ocp_solve, and OCP_E_SCRATCH when the
  * workspace ocp_workspace_bytes reports plus the horizons exceeds
  * OCP_NOALLOC_SCRATCH_BYTES. */
