@@ -449,6 +449,7 @@ def main():
 
     value = mixed["solved"] / (mixed["ms_per_step"] * 1e-3)
     roof, hbm = roofline(batch, mixed, "mixed", args.workload)
+    tail_it = (mixed.get("launch_shape") or {}).get("two_wavefront_from_iteration", 0)
     out = {
         "metric": "QP solves/s at 1e-4 KKT residual, FP32+grad vs plain FP64, 1 MI355X",
         "value": round(value, 2), "unit": "QP solves/s", "n_gpus": 1, "steps": args.steps,
@@ -459,7 +460,9 @@ def main():
                    "rescaling": (f"box normalisation, power-of-two factors, exponent {scale_p}" if scale_p is not None
                                  else "none"),
                    "eps": 1e-4, "eps_active": 1e-4, "max_admm": 1000, "grad": not args.no_grad,
-                   "parallelism": "single GPU, one instance per wavefront",
+                   "parallelism": ("single GPU, one instance per wavefront" +
+                                   (f"; instances still running at ADMM iteration {tail_it} continue on "
+                                    "two-wavefront workgroups" if tail_it else "")),
                    "linsolve": ({"pcg_max_iter": pcg[0], "pcg_tol": pcg[1]} if pcg else "direct")},
         "admm_iters_per_s": round(mixed["iters_sum"] / (mixed["ms_per_step"] * 1e-3), 1),
         "kernel_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in mixed["kernels"].items()},
